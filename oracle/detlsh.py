@@ -1,0 +1,366 @@
+"""CPU oracle for DET-LSH (arxiv 2603.24920). TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, FP64 restatement of the method, written from the paper's text.
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+it; the library never calls it, and it shares no code with the GPU path.
+
+Every function names the passage it follows. Readings of points where the paper
+is silent or ambiguous are stated where they are used:
+
+* Encoding ties (Algorithm 1, the binary-search step): a value equal to a
+  breakpoint goes to the higher region (upper-bound rule). Region symbols are
+  the 0-based region index; the first-layer bit of a dimension is the most
+  significant of its log2(Nr) bits.
+* Outer breakpoints (encoding phase, breakpoint formula): interior breakpoints
+  come from the sample at the paper's 1-based ranks floor(ns/Nr)*(z-1); the two
+  outer ones are the min and max over all n points, so every point lies inside
+  its node's box.
+* Tree creation (Algorithm 2 and the node-split rule of the indexing phase): a
+  bulk, insertion-order-free build. A node is split iff its full point set has
+  more than max_leaf points and some dimension still has an unrefined bit. The
+  split dimension minimises |#bit0 - #bit1|, ties to the smallest dimension.
+  Nodes with no points are not leaves. Leaves are numbered in depth-first order
+  (first-layer nodes by ascending key, bit-0 child first); inside a leaf,
+  points are in ascending id order.
+* Node bounds (the bound-distance example of the parallel query section): per
+  dimension, the distance from q' to the node's breakpoint interval (zero
+  inside), combined as a Euclidean norm; the upper bound takes the far edge.
+* Query (Algorithm 5 with the two optimisations of the query-phase
+  self-evaluation): a leaf is admitted whole when its lower bound does not
+  exceed eps*r; admitted leaves of one tree and round go in ascending
+  (lower bound, leaf ordinal) order; stop rule A (|S| >= ceil(beta*n)+k) is
+  checked after every admitted leaf; stop rule B (at least k points of S within
+  c*r) after all L trees of a round. Leaves admitted in an earlier round are
+  not admitted again. Bounds are compared squared: LB^2 <= (eps*r)^2.
+* Top-k: smallest (distance, id), returned in ascending order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+# ---------------------------------------------------------------- projection
+def project(X: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """Hash values h_ij(o) = a_ij . o for every point (Eq. 1, the Euclidean LSH family).
+
+    X: [n][d] (float32 promoted), A: [d][L*K] with column i*K+j = a_ij.
+    Returns FP64 [n][L*K].
+    """
+    return np.asarray(X, dtype=np.float64) @ np.asarray(A, dtype=np.float64)
+
+
+# --------------------------------------------------------------- breakpoints
+def breakpoints(H_sample: np.ndarray, Nr: int, col_min: np.ndarray, col_max: np.ndarray) -> np.ndarray:
+    """Dynamic breakpoints (encoding phase, dynamic encoding scheme; Algorithm 1 step 2).
+
+    For each column, sort the sampled hash values ascending (C-up, 1-based) and
+    take B(z) = C-up(m*(z-1)) for z = 2..Nr with m = floor(ns/Nr). B(1) and
+    B(Nr+1) are the column min and max over all points.
+
+    Returns FP64 [L*K][Nr+1]; entry [col][u] is B(u+1).
+    """
+    ns, LK = H_sample.shape
+    m = ns // Nr
+    if m < 1:
+        raise ValueError("sample smaller than the number of regions")
+    B = np.empty((LK, Nr + 1), dtype=np.float64)
+    for col in range(LK):
+        srt = np.sort(H_sample[:, col])
+        B[col, 0] = col_min[col]
+        for z in range(2, Nr + 1):
+            B[col, z - 1] = srt[m * (z - 1) - 1]     # 1-based rank m*(z-1)
+        B[col, Nr] = col_max[col]
+    return B
+
+
+def encode(H: np.ndarray, B: np.ndarray, L: int, K: int) -> np.ndarray:
+    """Region symbols (Algorithm 1, encoding loop): code = #{z in 2..Nr : B(z) <= h}.
+
+    Returns uint8 [L][n][K].
+    """
+    n = H.shape[0]
+    codes = np.empty((L, n, K), dtype=np.uint8)
+    for i in range(L):
+        for j in range(K):
+            col = i * K + j
+            interior = B[col, 1:-1]
+            codes[i, :, j] = np.searchsorted(interior, H[:, col], side="right")
+    return codes
+
+
+# ---------------------------------------------------------------- DE-Tree
+@dataclasses.dataclass
+class Tree:
+    """One DE-Tree, flattened: leaves in depth-first order over a point permutation."""
+    perm: np.ndarray          # int64 [n]: point ids, leaf by leaf
+    leaf_start: np.ndarray    # int64 [nl]
+    leaf_count: np.ndarray    # int64 [nl]
+    leaf_depth: np.ndarray    # int64 [nl][K]: refined bits per dimension (t_j)
+    leaf_prefix: np.ndarray   # int64 [nl][K]: the t_j leading bits of the codes
+
+    @property
+    def nl(self) -> int:
+        return len(self.leaf_start)
+
+    def hidx(self) -> np.ndarray:
+        """Node id per dimension: (1 << t_j) | prefix_j."""
+        return (np.left_shift(1, self.leaf_depth) | self.leaf_prefix).astype(np.int64)
+
+
+def first_layer_key(codes_i: np.ndarray, bits: int) -> np.ndarray:
+    """First-layer node of each point (Algorithm 2 step 2): the leading code bit of every
+    dimension, dimension 0 most significant."""
+    n, K = codes_i.shape
+    msb = (codes_i.astype(np.int64) >> (bits - 1)) & 1
+    key = np.zeros(n, dtype=np.int64)
+    for j in range(K):
+        key |= msb[:, j] << (K - 1 - j)
+    return key
+
+
+def choose_split(codes_node: np.ndarray, depth: np.ndarray, bits: int) -> int:
+    """Node split rule (indexing phase): the dimension whose next bit divides the node's
+    points most evenly. Returns -1 when every dimension is fully refined."""
+    m, K = codes_node.shape
+    best, best_score = -1, None
+    for j in range(K):
+        t = int(depth[j])
+        if t >= bits:
+            continue
+        cnt1 = int(((codes_node[:, j].astype(np.int64) >> (bits - 1 - t)) & 1).sum())
+        score = abs(2 * cnt1 - m)
+        if best_score is None or score < best_score:
+            best, best_score = j, score
+    return best
+
+
+def build_tree(codes_i: np.ndarray, Nr: int, max_leaf: int) -> Tree:
+    """Create one DE-Tree from the codes of one projected space (Algorithm 2, bulk form).
+
+    codes_i: uint8 [n][K]. The root has 2^K first-layer children keyed by the leading
+    bits; a node with more than ``max_leaf`` points is split in two on one dimension by
+    one more bit (binary refinement).
+    """
+    n, K = codes_i.shape
+    bits = int(round(math.log2(Nr)))
+    key = first_layer_key(codes_i, bits)
+    order = np.lexsort((np.arange(n), key))            # by key, then id
+    keys_sorted = key[order]
+    uniq, first = np.unique(keys_sorted, return_index=True)
+    bounds = list(first) + [n]
+
+    perm, starts, counts, depths, prefixes = [], [], [], [], []
+    pos = 0
+    for u in range(len(uniq)):
+        ids = order[bounds[u]:bounds[u + 1]]           # ascending id inside the node
+        k0 = int(uniq[u])
+        depth = np.ones(K, dtype=np.int64)
+        prefix = np.array([(k0 >> (K - 1 - j)) & 1 for j in range(K)], dtype=np.int64)
+        stack = [(ids, depth, prefix)]
+        while stack:
+            pts, dep, pre = stack.pop()
+            if len(pts) == 0:
+                continue
+            j = -1 if len(pts) <= max_leaf else choose_split(codes_i[pts], dep, bits)
+            if j < 0:
+                perm.append(pts)
+                starts.append(pos)
+                counts.append(len(pts))
+                depths.append(dep.copy())
+                prefixes.append(pre.copy())
+                pos += len(pts)
+                continue
+            bit = (codes_i[pts, j].astype(np.int64) >> (bits - 1 - dep[j])) & 1
+            d1 = dep.copy(); d1[j] += 1
+            p0 = pre.copy(); p0[j] = pre[j] * 2
+            p1 = pre.copy(); p1[j] = pre[j] * 2 + 1
+            stack.append((pts[bit == 1], d1, p1))      # popped second
+            stack.append((pts[bit == 0], d1, p0))      # bit-0 child first
+    return Tree(np.concatenate(perm).astype(np.int64), np.array(starts, dtype=np.int64),
+                np.array(counts, dtype=np.int64), np.array(depths, dtype=np.int64).reshape(-1, K),
+                np.array(prefixes, dtype=np.int64).reshape(-1, K))
+
+
+# ---------------------------------------------------------------- bounds
+def leaf_boxes(tree: Tree, B_tree: np.ndarray, Nr: int):
+    """Breakpoint interval of every leaf in every dimension (bound-distance example).
+
+    A node fixing the t_j leading bits p_j of dimension j covers regions
+    lo = p_j << (b - t_j) .. hi = ((p_j + 1) << (b - t_j)) - 1, i.e. the interval
+    [B(lo+1), B(hi+2)]. B_tree: [K][Nr+1] (0-based, entry u is B(u+1)).
+    Returns (lo, hi) FP64 [nl][K].
+    """
+    bits = int(round(math.log2(Nr)))
+    sh = bits - tree.leaf_depth
+    lo_code = tree.leaf_prefix << sh
+    hi_code = ((tree.leaf_prefix + 1) << sh) - 1
+    K = B_tree.shape[0]
+    cols = np.arange(K)[None, :]
+    return B_tree[cols, lo_code], B_tree[cols, hi_code + 1]
+
+
+def lower_bound_sq(qp: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """Squared lower-bound distance from projected query q' to each node box."""
+    gap = np.maximum(0.0, np.maximum(lo - qp[None, :], qp[None, :] - hi))
+    return (gap * gap).sum(axis=1)
+
+
+def upper_bound_sq(qp: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """Squared upper-bound distance (far edge per dimension)."""
+    far = np.maximum(np.abs(qp[None, :] - lo), np.abs(qp[None, :] - hi))
+    return (far * far).sum(axis=1)
+
+
+# ---------------------------------------------------------------- parameters
+def epsilon(K: int, L: int) -> float:
+    """Projected-radius factor from Eq. 2 and Lemma 3: eps^2 = chi2 upper alpha1 quantile
+    with K degrees of freedom, alpha1 = exp(-1/L)."""
+    from scipy.stats import chi2
+    return float(math.sqrt(chi2.isf(math.exp(-1.0 / L), K)))
+
+
+def theoretical_beta(K: int, L: int, c: float) -> float:
+    """beta = 2 - 2 alpha2^L with c^2 chi2_{alpha2}(K) = eps^2 (Lemma 3, Eq. 2)."""
+    from scipy.stats import chi2
+    eps2 = chi2.isf(math.exp(-1.0 / L), K)
+    alpha2 = float(chi2.sf(eps2 / (c * c), K))
+    return 2.0 - 2.0 * alpha2 ** L
+
+
+# ---------------------------------------------------------------- index
+@dataclasses.dataclass
+class Index:
+    n: int
+    d: int
+    L: int
+    K: int
+    Nr: int
+    A: np.ndarray             # FP64 [d][L*K]
+    B: np.ndarray             # FP64 [L*K][Nr+1]
+    codes: np.ndarray         # uint8 [L][n][K]
+    trees: list
+    boxes: list               # per tree (lo, hi)
+
+
+def build_index(X, A, sample_ids, L, K, Nr, max_leaf, B=None, codes=None) -> Index:
+    """Encoding and indexing phases (Algorithms 1 and 2).
+
+    ``B`` / ``codes`` may be given to rebuild later steps from supplied earlier ones
+    (used to check the GPU step by step)."""
+    X = np.asarray(X)
+    n, d = X.shape
+    A64 = np.asarray(A, dtype=np.float64)
+    if codes is None or B is None:
+        H = project(X, A64)
+        if B is None:
+            B = breakpoints(H[np.asarray(sample_ids)], Nr, H.min(axis=0), H.max(axis=0))
+        if codes is None:
+            codes = encode(H, B, L, K)
+    trees, boxes = [], []
+    for i in range(L):
+        t = build_tree(codes[i], Nr, max_leaf)
+        trees.append(t)
+        boxes.append(leaf_boxes(t, B[i * K:(i + 1) * K], Nr))
+    return Index(n, d, L, K, Nr, A64, np.asarray(B, dtype=np.float64), codes, trees, boxes)
+
+
+# ---------------------------------------------------------------- query
+@dataclasses.dataclass
+class QueryResult:
+    ids: np.ndarray           # int64 [k]
+    dists: np.ndarray         # FP64 [k]
+    rounds: int               # radius rounds started
+    n_cand: int               # |S| at termination
+    stop: str                 # "A" (|S| >= T) or "B" (k points within c*r)
+    leaves: int               # admitted leaves
+    cand: np.ndarray          # int64 [|S|]: S in insertion order
+    radius: float             # r of the last round
+
+
+def radius_ladder(r_min: float, c: float, rounds: int):
+    """r = r_min, r_min*c, r_min*c^2, ... (preliminaries, c^2-ANN by growing radius)."""
+    r = r_min
+    for _ in range(rounds):
+        yield r
+        r = c * r
+
+
+def query(index: Index, X, q, k: int, c: float, beta: float, r_min: float, eps: float,
+          max_rounds: int = 255) -> QueryResult:
+    """c^2-k-ANN query (Algorithm 5 with relaxed leaf admission and lower-bound order)."""
+    X = np.asarray(X)
+    n = index.n
+    T = math.ceil(beta * n) + k
+    q64 = np.asarray(q, dtype=np.float64)
+    qp = q64 @ index.A
+    inS = np.zeros(n, dtype=bool)
+    cand, cdist = [], []
+    n_s = 0
+    leaves = 0
+    prev_t2 = -1.0
+    rho = 0
+    for rho, r in enumerate(radius_ladder(r_min, c, max_rounds)):
+        t = eps * r
+        t2 = t * t
+        for i in range(index.L):
+            tr = index.trees[i]
+            lo, hi = index.boxes[i]
+            lb2 = lower_bound_sq(qp[i * index.K:(i + 1) * index.K], lo, hi)
+            adm = np.nonzero((lb2 <= t2) & (lb2 > prev_t2))[0]
+            adm = adm[np.lexsort((adm, lb2[adm]))]
+            for leaf in adm:
+                leaves += 1
+                ids = tr.perm[tr.leaf_start[leaf]:tr.leaf_start[leaf] + tr.leaf_count[leaf]]
+                new = ids[~inS[ids]]
+                if len(new):
+                    inS[new] = True
+                    n_s += len(new)
+                    cand.append(new)
+                    cdist.append(np.sqrt(((X[new].astype(np.float64) - q64) ** 2).sum(axis=1)))
+                if n_s >= T:
+                    return _finish(cand, cdist, k, rho + 1, "A", leaves, r)
+        if n_s >= k:
+            alld = np.concatenate(cdist)
+            if np.partition(alld, k - 1)[k - 1] <= c * r:
+                return _finish(cand, cdist, k, rho + 1, "B", leaves, r)
+        prev_t2 = t2
+    raise RuntimeError("radius ladder exhausted")
+
+
+def _finish(cand, cdist, k, rounds, stop, leaves, r) -> QueryResult:
+    allc, alld = np.concatenate(cand), np.concatenate(cdist)
+    o = np.lexsort((allc, alld))[:k]
+    return QueryResult(allc[o], alld[o], rounds, len(allc), stop, leaves, allc, r)
+
+
+# ---------------------------------------------------------------- brute force
+def knn_exact(X, Q, k: int, block: int = 4096):
+    """Exact k nearest neighbours by FP64 brute force (difference form), ties by id."""
+    X64 = np.asarray(X, dtype=np.float64)
+    ids_out = np.empty((len(Q), k), dtype=np.int64)
+    d_out = np.empty((len(Q), k), dtype=np.float64)
+    for qi, q in enumerate(np.asarray(Q, dtype=np.float64)):
+        dist = np.empty(len(X64))
+        for s in range(0, len(X64), block):
+            dist[s:s + block] = np.sqrt(((X64[s:s + block] - q) ** 2).sum(axis=1))
+        o = np.lexsort((np.arange(len(X64)), dist))[:k]
+        ids_out[qi], d_out[qi] = o, dist[o]
+    return ids_out, d_out
+
+
+def recall(ids, exact_ids) -> float:
+    """|R intersect R*| / k averaged over queries (evaluation measures)."""
+    ids, exact_ids = np.asarray(ids), np.asarray(exact_ids)
+    k = exact_ids.shape[1]
+    return float(np.mean([len(np.intersect1d(a[:k], b)) / k for a, b in zip(ids, exact_ids)]))
+
+
+def overall_ratio(dists, exact_dists) -> float:
+    """(1/k) sum_i ||q,o_i|| / ||q,o*_i||, averaged over queries (evaluation measures)."""
+    d, e = np.asarray(dists, dtype=np.float64), np.asarray(exact_dists, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(e > 0, d / e, 1.0)
+    return float(r.mean())
