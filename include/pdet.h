@@ -1,0 +1,183 @@
+/*
+ * pdet.h - DET-LSH index build and c^2-k-ANN search on AMD Instinct MI355X (gfx950).
+ *
+ * Method: arxiv 2603.24920 (DET-LSH / PDET-LSH). Section 3 defines the problem
+ * (dataset D of n points in R^d, query q, approximation ratio c > 1, k); Section 4
+ * defines the encoding phase (Eq. 1 projections, dynamic breakpoints, Algorithm 1),
+ * the indexing phase (DE-Trees, Algorithm 2) and the query phase (Algorithms 3-5,
+ * with the optimisations of the query-phase self-evaluation in Section 6).
+ *
+ * Conventions for every entry point:
+ *  - Plain C types only. "device" pointers are HIP device allocations on the
+ *    current device; "host" pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).
+ *    Calls are stream-ordered: device outputs are valid once the stream reaches
+ *    the call's end. Host outputs are valid when the call returns.
+ *  - Every call returns a pdet_status. On failure nothing is leaked, output
+ *    handles are set to NULL, and pdet_last_error() describes the failure
+ *    (thread-local, valid until the next call on the same thread).
+ *  - No exception crosses this boundary.
+ */
+#ifndef PDET_H
+#define PDET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdet_index pdet_index; /* opaque; owned by the library */
+
+typedef enum {
+  PDET_OK = 0,
+  PDET_EINVAL = -1,       /* an argument is out of range or inconsistent          */
+  PDET_ENOMEM = -2,       /* a device allocation failed                            */
+  PDET_EDEVICE = -3,      /* a HIP runtime call failed                             */
+  PDET_EUNSUPPORTED = -4  /* valid in the method but beyond this build's limits    */
+} pdet_status;
+
+typedef enum { PDET_FP32 = 0, PDET_BF16 = 1, PDET_FP8_E4M3 = 2 } pdet_precision;
+
+/* Limits of this build. */
+#define PDET_MAX_K 16          /* projections per space: first-layer keys fit 16 bits   */
+#define PDET_MAX_L 16          /* projected spaces (trees)                               */
+#define PDET_MAX_TOPK 1024     /* k * rescore per query                                  */
+#define PDET_MAX_ROUNDS 255    /* radius rounds r_min * c^rho, rho < 255                 */
+
+/*
+ * Index build parameters (encoding phase and indexing phase, Section 4.1-4.2).
+ *   K, L        projections per space and number of spaces (Eq. 1: K*L Gaussian vectors).
+ *   Nr          regions per dimension, a power of two in [2, 256] (8-bit symbols).
+ *   max_leaf    leaf capacity ("max_size" of Algorithm 2), >= 1.
+ *   proj        host, float32 [d][L*K] row-major; column i*K+j is the hash vector a_ij.
+ *               The caller draws it (entries i.i.d. N(0,1)); it is copied.
+ *   sample_ids  host, int64 [n_sample], distinct ids in [0,n): the points whose
+ *               projections give the interior breakpoints. floor(n_sample/Nr) >= 1.
+ *   lowp_copies bit mask: (1u<<PDET_BF16) and/or (1u<<PDET_FP8_E4M3) build the
+ *               low-precision copies of the data used by those verification forms.
+ */
+typedef struct {
+  int32_t K, L, Nr, max_leaf;
+  const float* proj;
+  const int64_t* sample_ids;
+  int64_t n_sample;
+  uint32_t lowp_copies;
+} pdet_build_params;
+
+/*
+ * Build an index over `data` (device, float32 [n][d] row-major, n < 2^31).
+ * The data pointer is BORROWED: it must stay allocated and unchanged until
+ * pdet_free(), because verification reads it. Everything derived from it
+ * (breakpoints, codes, trees, low-precision copies) is owned by the index.
+ * Errors: EINVAL for n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power
+ * of two in [2,256], max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range;
+ * ENOMEM/EDEVICE from the runtime. On error *out is NULL.
+ * Synchronises `stream` once (to size the leaf tables).
+ */
+pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build_params* p,
+                       void* stream, pdet_index** out);
+
+/* Release an index and all device memory it owns. NULL is a no-op. */
+void pdet_free(pdet_index* idx);
+
+/*
+ * Query parameters (c^2-k-ANN query, Algorithm 5, Section 4.3).
+ *   k, c          uniform k >= 1 and c > 1, used when the per-query arrays are NULL.
+ *   k_per_query   host int32 [nq] or NULL; c_per_query host double [nq] or NULL.
+ *   beta          stop rule A fires once |S| >= ceil(beta*n) + k (beta >= 0).
+ *   r_min         first search radius (> 0); radii r_min*c^rho for rho < 255.
+ *   eps           projected-radius factor; <= 0 selects sqrt(chi2 upper quantile of
+ *                 exp(-1/L) with K degrees of freedom) (Eq. 2 and Lemma 3).
+ *   precision     pdet_precision of candidate verification. FP32 reads the float32
+ *                 data; BF16 / FP8_E4M3 read the index's low-precision copy and
+ *                 re-rank the best rescore*k candidates from the float32 data.
+ *   rescore       >= 1; ignored for FP32.
+ */
+typedef struct {
+  int32_t k;
+  double c;
+  const int32_t* k_per_query;
+  const double* c_per_query;
+  double beta;
+  double r_min;
+  double eps;
+  int32_t precision;
+  int32_t rescore;
+} pdet_query_params;
+
+/* Per-query statistics words written to `qstats` (int32 [nq][PDET_QSTAT_WORDS]). */
+#define PDET_QSTAT_WORDS 8
+#define PDET_QSTAT_ROUNDS 0   /* radius rounds started                                      */
+#define PDET_QSTAT_NCAND 1    /* |S| at termination                                         */
+#define PDET_QSTAT_STOP 2     /* 1: stop rule A (|S| >= T), 2: stop rule B, <0: error       */
+#define PDET_QSTAT_LEAVES 3   /* leaves admitted                                            */
+#define PDET_QSTAT_HSUM 4     /* sum of candidate ids mod 2^32                               */
+#define PDET_QSTAT_HMIX 5     /* sum of mix32(id) mod 2^32, mix32 = murmur3 finaliser        */
+
+/*
+ * Answer nq queries (device float32 [nq][d]).
+ * Outputs (device, caller-owned) are laid out CSR in query order: query q owns
+ * entries [off_q, off_q + k_q) with off_q = sum of k over earlier queries.
+ *   ids    int64: neighbour ids sorted by (distance, id) ascending.
+ *   dists  float32: Euclidean distances (not squared) of those neighbours.
+ *   qstats int32 [nq][PDET_QSTAT_WORDS] or NULL.
+ * Errors: EINVAL for k < 1, k > n, c <= 1, beta < 0, r_min <= 0, a low-precision form
+ * whose copy the index lacks, rescore < 1; EUNSUPPORTED for k*rescore > PDET_MAX_TOPK.
+ * A query whose radius ladder runs out before a stop rule fires gets stop = -1.
+ * Concurrent calls on one index are allowed on different streams (the index is
+ * read-only after build).
+ */
+pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
+                       const pdet_query_params* p, int64_t* ids, float* dists,
+                       int32_t* qstats, void* stream);
+
+/* Description of a built index. */
+typedef struct {
+  int64_t n, n_sample;
+  int32_t d, K, L, Nr, max_leaf;
+  uint32_t lowp_copies;
+  int64_t leaves[PDET_MAX_L];   /* non-empty leaves per tree                          */
+  int64_t device_bytes;         /* device memory owned by the index                   */
+} pdet_index_info;
+
+pdet_status pdet_info(const pdet_index* idx, pdet_index_info* out);
+
+/*
+ * Copy index contents to host memory (introspection and step-by-step checking).
+ *   PDET_X_BREAKPOINTS float32 [L*K][Nr+1]; entry [i*K+j][u] is B_ij(u+1): u=0 the
+ *                      column min over all points, u=Nr the max, interior from the sample.
+ *   PDET_X_CODES       uint8 [L][n][16]: region index of dimension j in column j (j<K).
+ *   PDET_X_PERM        int32 [n] for `tree`: point ids leaf by leaf (depth-first leaf
+ *                      order; order inside a leaf unspecified).
+ *   PDET_X_LEAF_START  int32 [leaves] for `tree`; PDET_X_LEAF_COUNT likewise.
+ *   PDET_X_LEAF_HIDX   uint16 [leaves][16] for `tree`: (1 << t_j) | prefix_j, where the
+ *                      leaf fixes the t_j leading bits prefix_j of dimension j's code.
+ * `bytes` must equal the exact size; otherwise EINVAL. Synchronises the device.
+ */
+enum {
+  PDET_X_BREAKPOINTS = 0, PDET_X_CODES = 1, PDET_X_PERM = 2,
+  PDET_X_LEAF_START = 3, PDET_X_LEAF_COUNT = 4, PDET_X_LEAF_HIDX = 5
+};
+pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void* host,
+                        size_t bytes);
+
+/*
+ * Hash values of m points (device float32 [m][d]) with the index's projection
+ * (Eq. 1): out device float32 [m][L*K], column i*K+j = a_ij . x. Same arithmetic
+ * as the build's encoder and the query projection.
+ */
+pdet_status pdet_project(const pdet_index* idx, const float* x, int64_t m, float* out,
+                         void* stream);
+
+/* eps = sqrt(chi2 upper exp(-1/L) quantile, K dof) from Eq. 2 / Lemma 3; NaN if invalid. */
+double pdet_epsilon(int32_t K, int32_t L);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* pdet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDET_H */

@@ -1,0 +1,276 @@
+// C ABI of libpdet (declared in include/pdet.h): argument checks, the build pipeline
+// (encoding phase then indexing phase) and the query entry point.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "internal.h"
+
+namespace pdet {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class F>
+pdet_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return PDET_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return PDET_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected failure";
+    return PDET_EDEVICE;
+  }
+}
+
+// Regularised lower incomplete gamma P(a, x): power series for x < a + 1, otherwise
+// 1 - Q from the continued fraction of Q (modified Lentz).
+double gamma_p(double a, double x) {
+  if (x <= 0.0) return 0.0;
+  const double lg = std::lgamma(a);
+  if (x < a + 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int i = 1; i < 10000; ++i) {
+      term *= x / (a + i);
+      sum += term;
+      if (std::fabs(term) < std::fabs(sum) * 1e-17) break;
+    }
+    return sum * std::exp(-x + a * std::log(x) - lg);
+  }
+  const double tiny = 1e-300;
+  double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 10000; ++i) {
+    const double an = -i * (i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (std::fabs(del - 1.0) < 1e-17) break;
+  }
+  return 1.0 - std::exp(-x + a * std::log(x) - lg) * h;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// eps^2 is the upper alpha1 quantile of chi2(K), alpha1 = exp(-1/L) (Eq. 2, Lemma 3):
+// solve 1 - P(K/2, x/2) = alpha1 by bisection.
+double epsilon(int K, int L) {
+  const double alpha = std::exp(-1.0 / L);
+  double lo = 0.0, hi = 1.0;
+  while (1.0 - gamma_p(0.5 * K, 0.5 * hi) > alpha) hi *= 2.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (1.0 - gamma_p(0.5 * K, 0.5 * mid) > alpha) lo = mid; else hi = mid;
+  }
+  return std::sqrt(0.5 * (lo + hi));
+}
+
+}  // namespace pdet
+
+int64_t pdet_index::device_bytes() const {
+  int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + perm.bytes + xbf16.bytes +
+              xfp8.bytes + xscale.bytes;
+  for (int i = 0; i < PDET_MAX_L; ++i)
+    b += leaf_start[i].bytes + leaf_count[i].bytes + leaf_hidx[i].bytes + box[i].bytes;
+  return b;
+}
+
+using namespace pdet;
+
+extern "C" {
+
+const char* pdet_last_error(void) { return g_last_error.c_str(); }
+
+double pdet_epsilon(int32_t K, int32_t L) {
+  if (K < 1 || L < 1) return std::numeric_limits<double>::quiet_NaN();
+  return pdet::epsilon(K, L);
+}
+
+pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build_params* p,
+                       void* stream, pdet_index** out) {
+  if (out) *out = nullptr;
+  pdet_index* ix = nullptr;
+  const pdet_status st = guarded([&] {
+    PDET_REQUIRE(out && p && data, PDET_EINVAL, "NULL argument");
+    PDET_REQUIRE(n >= 1 && n < (int64_t(1) << 31), PDET_EINVAL, "n must be in [1, 2^31)");
+    PDET_REQUIRE(d >= 1, PDET_EINVAL, "d must be >= 1");
+    PDET_REQUIRE(p->K >= 1 && p->K <= PDET_MAX_K, PDET_EINVAL, "K must be in [1, 16]");
+    PDET_REQUIRE(p->L >= 1 && p->L <= PDET_MAX_L, PDET_EINVAL, "L must be in [1, 16]");
+    PDET_REQUIRE(p->Nr >= 2 && p->Nr <= 256 && (p->Nr & (p->Nr - 1)) == 0, PDET_EINVAL,
+                 "Nr must be a power of two in [2, 256]");
+    PDET_REQUIRE(p->max_leaf >= 1, PDET_EINVAL, "max_leaf must be >= 1");
+    PDET_REQUIRE(p->proj && p->sample_ids, PDET_EINVAL, "proj and sample_ids are required");
+    PDET_REQUIRE(p->n_sample >= p->Nr && p->n_sample <= n, PDET_EINVAL,
+                 "n_sample must be in [Nr, n]");
+    PDET_REQUIRE((p->lowp_copies & ~((1u << PDET_BF16) | (1u << PDET_FP8_E4M3))) == 0,
+                 PDET_EINVAL, "unknown lowp_copies bit");
+    for (int64_t i = 0; i < p->n_sample; ++i)
+      PDET_REQUIRE(p->sample_ids[i] >= 0 && p->sample_ids[i] < n, PDET_EINVAL,
+                   "sample id out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    ix = new pdet_index();
+    ix->n = n; ix->d = d; ix->K = p->K; ix->L = p->L; ix->Nr = p->Nr;
+    ix->bits = ilog2(p->Nr);
+    ix->max_leaf = p->max_leaf;
+    ix->n_sample = p->n_sample;
+    ix->lowp = p->lowp_copies;
+    ix->X = data;
+    ix->dpad = ((d + 15) / 16) * 16;
+    PDET_HIP(hipGetDevice(&ix->device));
+    PDET_HIP(hipDeviceGetAttribute(&ix->num_cus, hipDeviceAttributeMultiprocessorCount,
+                                   ix->device));
+    const int LK = ix->L * ix->K;
+
+    // projection matrix and sampled projections
+    const std::vector<float> Ap = pad_projection(p->proj, d, ix->L, ix->K);
+    ix->A.alloc(Ap.size() * 4);
+    PDET_HIP(hipMemcpyAsync(ix->A.p, Ap.data(), Ap.size() * 4, hipMemcpyHostToDevice, s));
+    DevBuf sid((size_t)p->n_sample * 8);
+    PDET_HIP(hipMemcpyAsync(sid.p, p->sample_ids, sid.bytes, hipMemcpyHostToDevice, s));
+    int64_t npad = 1;
+    while (npad < p->n_sample) npad <<= 1;
+    DevBuf ps((size_t)LK * npad * 4);
+    fill_f32(ps.as<float>(), (int64_t)LK * npad, INFINITY, s);
+    project_sample(*ix, sid.as<int64_t>(), p->n_sample, ps.as<float>(), npad, s);
+    sort_columns(ps.as<float>(), LK, npad, s);
+    ix->B.alloc((size_t)LK * (ix->Nr + 1) * 4);
+    pick_breakpoints(ps.as<float>(), LK, npad, p->n_sample, ix->Nr, ix->B.as<float>(), s);
+
+    // encode every point; column extremes give the outer breakpoints
+    ix->colmm.alloc((size_t)2 * LK * 4);
+    PDET_HIP(hipMemsetAsync(ix->colmm.p, 0xff, (size_t)LK * 4, s));
+    PDET_HIP(hipMemsetAsync(ix->colmm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));
+    ix->codes.alloc((size_t)ix->L * n * KP);
+    encode_points(*ix, s);
+    set_outer_breakpoints(ix->B.as<float>(), ix->colmm.as<uint32_t>(), LK, ix->Nr, s);
+
+    ix->perm.alloc((size_t)ix->L * n * 4);
+    build_trees(*ix, s);
+    build_lowp_copies(*ix, s);
+    PDET_HIP(hipStreamSynchronize(s));
+    *out = ix;
+    ix = nullptr;
+  });
+  delete ix;
+  return st;
+}
+
+void pdet_free(pdet_index* idx) { delete idx; }
+
+pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
+                       const pdet_query_params* p, int64_t* ids, float* dists, int32_t* qstats,
+                       void* stream) {
+  return guarded([&] {
+    PDET_REQUIRE(idx && p, PDET_EINVAL, "NULL argument");
+    PDET_REQUIRE(nq >= 0, PDET_EINVAL, "nq must be >= 0");
+    if (nq == 0) return;
+    PDET_REQUIRE(queries && ids && dists, PDET_EINVAL, "NULL queries or outputs");
+    PDET_REQUIRE(p->beta >= 0.0 && std::isfinite(p->beta), PDET_EINVAL, "beta must be >= 0");
+    PDET_REQUIRE(p->r_min > 0.0 && std::isfinite(p->r_min), PDET_EINVAL, "r_min must be > 0");
+    PDET_REQUIRE(p->precision >= PDET_FP32 && p->precision <= PDET_FP8_E4M3, PDET_EINVAL,
+                 "unknown precision");
+    if (p->precision != PDET_FP32) {
+      PDET_REQUIRE(idx->lowp & (1u << p->precision), PDET_EINVAL,
+                   "index was built without this low-precision copy");
+      PDET_REQUIRE(p->rescore >= 1, PDET_EINVAL, "rescore must be >= 1");
+    }
+    std::vector<int32_t> k(nq);
+    std::vector<double> c(nq);
+    for (int64_t q = 0; q < nq; ++q) {
+      k[q] = p->k_per_query ? p->k_per_query[q] : p->k;
+      c[q] = p->c_per_query ? p->c_per_query[q] : p->c;
+      PDET_REQUIRE(k[q] >= 1 && k[q] <= idx->n, PDET_EINVAL, "k must be in [1, n]");
+      PDET_REQUIRE(c[q] > 1.0 && std::isfinite(c[q]), PDET_EINVAL, "c must be > 1");
+      const int64_t kl = (p->precision == PDET_FP32) ? k[q] : (int64_t)k[q] * p->rescore;
+      PDET_REQUIRE(kl <= PDET_MAX_TOPK, PDET_EUNSUPPORTED, "k * rescore exceeds 1024");
+    }
+    QueryConfig qc{};
+    qc.Q = queries;
+    qc.nq = nq;
+    qc.k_host = k.data();
+    qc.c_host = c.data();
+    qc.beta = p->beta;
+    qc.r_min = p->r_min;
+    qc.eps = (p->eps > 0.0) ? p->eps : pdet::epsilon(idx->K, idx->L);
+    qc.precision = p->precision;
+    qc.rescore = p->precision == PDET_FP32 ? 1 : p->rescore;
+    qc.ids = ids;
+    qc.dists = dists;
+    qc.qstats = qstats;
+    run_query(*idx, qc, static_cast<hipStream_t>(stream));
+  });
+}
+
+pdet_status pdet_info(const pdet_index* idx, pdet_index_info* out) {
+  return guarded([&] {
+    PDET_REQUIRE(idx && out, PDET_EINVAL, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->n = idx->n;
+    out->n_sample = idx->n_sample;
+    out->d = idx->d;
+    out->K = idx->K;
+    out->L = idx->L;
+    out->Nr = idx->Nr;
+    out->max_leaf = idx->max_leaf;
+    out->lowp_copies = idx->lowp;
+    for (int i = 0; i < idx->L; ++i) out->leaves[i] = idx->nl[i];
+    out->device_bytes = idx->device_bytes();
+  });
+}
+
+pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void* host,
+                        size_t bytes) {
+  return guarded([&] {
+    PDET_REQUIRE(idx && host, PDET_EINVAL, "NULL argument");
+    const void* src = nullptr;
+    size_t want = 0;
+    const bool per_tree = what >= PDET_X_PERM;
+    if (per_tree) PDET_REQUIRE(tree >= 0 && tree < idx->L, PDET_EINVAL, "tree out of range");
+    switch (what) {
+      case PDET_X_BREAKPOINTS:
+        src = idx->B.p; want = (size_t)idx->L * idx->K * (idx->Nr + 1) * 4; break;
+      case PDET_X_CODES:
+        src = idx->codes.p; want = (size_t)idx->L * idx->n * KP; break;
+      case PDET_X_PERM:
+        src = idx->perm.as<int32_t>() + (int64_t)tree * idx->n; want = (size_t)idx->n * 4; break;
+      case PDET_X_LEAF_START:
+        src = idx->leaf_start[tree].p; want = (size_t)idx->nl[tree] * 4; break;
+      case PDET_X_LEAF_COUNT:
+        src = idx->leaf_count[tree].p; want = (size_t)idx->nl[tree] * 4; break;
+      case PDET_X_LEAF_HIDX:
+        src = idx->leaf_hidx[tree].p; want = (size_t)idx->nl[tree] * KP * 2; break;
+      default:
+        throw Error{PDET_EINVAL, "unknown export item"};
+    }
+    PDET_REQUIRE(bytes == want, PDET_EINVAL,
+                 "export size mismatch: expected " + std::to_string(want) + " bytes");
+    PDET_HIP(hipDeviceSynchronize());
+    if (want) PDET_HIP(hipMemcpy(host, src, want, hipMemcpyDeviceToHost));
+  });
+}
+
+pdet_status pdet_project(const pdet_index* idx, const float* x, int64_t m, float* out,
+                         void* stream) {
+  return guarded([&] {
+    PDET_REQUIRE(idx && x && out, PDET_EINVAL, "NULL argument");
+    PDET_REQUIRE(m >= 0, PDET_EINVAL, "m must be >= 0");
+    if (m == 0) return;
+    project_points(*idx, x, m, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+}  // extern "C"

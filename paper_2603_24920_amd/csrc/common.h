@@ -1,0 +1,92 @@
+// Internal definitions shared by the HIP translation units of libpdet.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "pdet.h"
+
+namespace pdet {
+
+// Code rows are padded to 16 bytes (one 128-bit load per point per tree).
+constexpr int KP = 16;
+// Segments up to this many points finish their subtree inside one workgroup's LDS.
+constexpr int LDS_SEG_CAP = 2048;
+
+// Failure carrying a status; thrown only inside the library, caught at the ABI.
+struct Error {
+  pdet_status status;
+  std::string msg;
+};
+
+void set_error(const std::string& msg);
+
+#define PDET_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      throw ::pdet::Error{e_ == hipErrorOutOfMemory ? PDET_ENOMEM : PDET_EDEVICE,      \
+                          std::string(#call) + ": " + hipGetErrorString(e_)};          \
+    }                                                                                  \
+  } while (0)
+
+#define PDET_REQUIRE(cond, status, msg)                     \
+  do {                                                      \
+    if (!(cond)) throw ::pdet::Error{(status), (msg)};      \
+  } while (0)
+
+// Device buffer owned by RAII; freed with hipFree.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{PDET_ENOMEM, "hipMalloc(" + std::to_string(b) + " bytes) failed: " +
+                                   hipGetErrorString(e)};
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Total-order mapping float -> uint32 (for atomic min/max on floats).
+__host__ __device__ inline uint32_t float_to_ordered(float f) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float ordered_to_float(uint32_t u) {
+  return __builtin_bit_cast(float, (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__host__ __device__ inline uint32_t mix32(uint32_t h) {
+  h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+  return h;
+}
+
+inline int ilog2(int x) { int b = 0; while ((1 << b) < x) ++b; return b; }
+
+inline unsigned cdiv(int64_t a, int64_t b) { return static_cast<unsigned>((a + b - 1) / b); }
+
+}  // namespace pdet

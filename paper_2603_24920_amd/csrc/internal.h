@@ -1,0 +1,78 @@
+// Index layout and the host-side entry points of each kernel family.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+struct pdet_index {
+  int64_t n = 0, n_sample = 0;
+  int d = 0, K = 0, L = 0, Nr = 0, bits = 0, max_leaf = 0;
+  uint32_t lowp = 0;
+  int num_cus = 256;
+  int device = 0;
+  const float* X = nullptr;        // borrowed float32 [n][d]
+
+  pdet::DevBuf A;                  // float32 padded projection, see pad_projection()
+  pdet::DevBuf B;                  // float32 [L*K][Nr+1] breakpoints
+  pdet::DevBuf colmm;              // uint32 [2][L*K] ordered min / max of every column
+  pdet::DevBuf codes;              // uint8 [L][n][KP]
+  pdet::DevBuf perm;               // int32 [L][n]
+  // per tree, leaves in depth-first order
+  pdet::DevBuf leaf_start[PDET_MAX_L];   // int32 [nl]
+  pdet::DevBuf leaf_count[PDET_MAX_L];   // int32 [nl]
+  pdet::DevBuf leaf_hidx[PDET_MAX_L];    // uint16 [nl][KP]
+  pdet::DevBuf box[PDET_MAX_L];          // float32 [2][K][nl]: lower / upper edge per dim
+  int64_t nl[PDET_MAX_L] = {};
+  int64_t nl_max = 0;
+  // low-precision copies for verification
+  int dpad = 0;                    // row length of the copies (multiple of 16)
+  pdet::DevBuf xbf16;              // bf16 [n][dpad]
+  pdet::DevBuf xfp8;               // fp8 e4m3 [n][dpad]
+  pdet::DevBuf xscale;             // float32 [n]: fp8 row scale (power of two)
+
+  int64_t device_bytes() const;
+};
+
+namespace pdet {
+using Index = pdet_index;
+
+// project.hip
+std::vector<float> pad_projection(const float* proj, int d, int L, int K);
+void project_points(const Index& ix, const float* X, int64_t m, float* out, hipStream_t s);
+void project_sample(const Index& ix, const int64_t* rows, int64_t m, float* out, int64_t ld,
+                    hipStream_t s);
+void encode_points(const Index& ix, hipStream_t s);
+
+// sort.hip
+void sort_columns(float* keys, int ncols, int64_t npad, hipStream_t s);
+void fill_f32(float* p, int64_t count, float v, hipStream_t s);
+void pick_breakpoints(const float* sorted, int ncols, int64_t npad, int64_t ns, int Nr,
+                      float* B, hipStream_t s);
+void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, hipStream_t s);
+void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,
+               DevBuf& tmp, hipStream_t s);
+
+// tree.hip
+void build_trees(Index& ix, hipStream_t s);
+
+// lowp.hip
+void build_lowp_copies(Index& ix, hipStream_t s);
+
+// query.hip
+struct QueryConfig {
+  const float* Q;
+  int64_t nq;
+  const int32_t* k_host;   // [nq]
+  const double* c_host;    // [nq]
+  double beta, r_min, eps;
+  int precision, rescore;
+  int64_t* ids;
+  float* dists;
+  int32_t* qstats;
+};
+void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s);
+
+}  // namespace pdet

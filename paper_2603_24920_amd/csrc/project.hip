@@ -1,0 +1,290 @@
+// Projection (Eq. 1) and dynamic encoding (Algorithm 1) for gfx950.
+//
+// P = X . A is a thin contraction (m x d) . (d x 16L). Each wave computes a 16-point
+// tile against all 16-column tiles of A with v_mfma_f32_16x16x4_f32 (FP32 inputs,
+// FP32 accumulate), which runs at twice the rate of non-packed FP32 FMAs. The same
+// routine serves the sampled projection, the full encode pass and the query
+// projection, so a point gets bit-identical hash values in all three.
+//
+// MFMA 16x16x4 f32 lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element i of lane l is D[4*(l/16)+i][l%16].
+#include "internal.h"
+
+namespace pdet {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+enum Mode { MODE_PROJECT = 0, MODE_SAMPLE = 1, MODE_ENCODE = 2 };
+
+constexpr int PROJ_THREADS = 1024;
+constexpr int PROJ_WAVES = PROJ_THREADS / 64;
+
+struct ProjArgs {
+  const float* X;          // [rows of X][d]
+  int64_t m;               // points in this launch
+  int d;
+  const int64_t* rows;     // MODE_SAMPLE: X row of point p; else nullptr (p itself)
+  const float* A;          // [d][NC] padded columns for the trees of this launch
+  int tree0;               // first tree of this launch
+  int ntrees;              // trees of this launch (<= NT)
+  int L, K, Nr, bits;
+  int dk;                  // rows of A staged per chunk
+  // MODE_PROJECT: out[p][L*K]; MODE_SAMPLE: out[col][ld] (column-major)
+  float* out;
+  int64_t ld;
+  // MODE_ENCODE
+  const float* Btab;       // [L*K][Nr+1]
+  uint8_t* codes;          // [L][n][KP]
+  int64_t n;
+  uint32_t* colmin;        // [L*K] ordered-uint min / max
+  uint32_t* colmax;
+};
+
+template <int NT, bool VEC4, int MODE>
+__global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
+  constexpr int NC = NT * 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* As = reinterpret_cast<float*>(smem_raw);                 // [dk][NC]
+  float* Bs = As + a.dk * NC;                                      // [NT*K][Nr] interior + inf
+  uint8_t* stage = reinterpret_cast<uint8_t*>(Bs + (MODE == MODE_ENCODE ? NT * a.K * a.Nr : 0));
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col16 = lane & 15;
+  const int grp = lane >> 4;
+  const int nchunks = (a.d + a.dk - 1) / a.dk;
+
+  if constexpr (MODE == MODE_ENCODE) {
+    // interior breakpoints B(2..Nr) of every column of this launch, padded with +inf
+    const int tot = NT * a.K * a.Nr;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int c = e / a.Nr, u = e % a.Nr;
+      const int gcol = (a.tree0 + c / a.K) * a.K + c % a.K;
+      Bs[e] = (u < a.Nr - 1 && c / a.K < a.ntrees) ? a.Btab[(int64_t)gcol * (a.Nr + 1) + 1 + u]
+                                                   : INFINITY;
+    }
+  }
+
+  auto load_A = [&](int chunk) {
+    const int k0 = chunk * a.dk;
+    const int tot = a.dk * NC;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int r = e / NC, c = e % NC;
+      As[e] = (k0 + r < a.d) ? a.A[(int64_t)(k0 + r) * NC + c] : 0.0f;
+    }
+  };
+  if (nchunks == 1) load_A(0);
+  __syncthreads();
+
+  float vmin[NT], vmax[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) { vmin[t] = INFINITY; vmax[t] = -INFINITY; }
+
+  const int64_t ntiles = (a.m + 15) / 16;
+  const int64_t tiles_per_iter = (int64_t)gridDim.x * PROJ_WAVES;
+  const int64_t iters = (ntiles + tiles_per_iter - 1) / tiles_per_iter;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t tile = it * tiles_per_iter + (int64_t)blockIdx.x * PROJ_WAVES + wave;
+    const int64_t p_load = tile * 16 + col16;           // point whose X row this lane reads
+    const bool load_ok = p_load < a.m;
+    int64_t xrow = 0;
+    if (load_ok) xrow = (MODE == MODE_SAMPLE) ? a.rows[p_load] : p_load;
+    const float* xr = a.X + xrow * (int64_t)a.d;
+
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int chunk = 0; chunk < nchunks; ++chunk) {
+      if (nchunks > 1) {
+        __syncthreads();
+        load_A(chunk);
+        __syncthreads();
+      }
+      const int k0 = chunk * a.dk;
+      const int kend = min(a.dk, a.d - k0);
+      for (int kb = 0; kb < kend; kb += 16) {
+        const int kk = k0 + kb + 4 * grp;                 // first of this lane's 4 columns
+        float xv[4];
+        if (VEC4 && load_ok && kk + 3 < a.d) {
+          const float4 v = *reinterpret_cast<const float4*>(xr + kk);
+          xv[0] = v.x; xv[1] = v.y; xv[2] = v.z; xv[3] = v.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) xv[e] = (load_ok && kk + e < a.d) ? xr[kk + e] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float* brow = As + (kb + 4 * grp + e) * NC + col16;
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[e], brow[t * 16], acc[t], 0, 0, 0);
+        }
+      }
+    }
+
+    // acc[t][i] = P[tile*16 + 4*grp + i][t*16 + col16]
+    const int64_t pbase = tile * 16 + 4 * grp;
+    if constexpr (MODE == MODE_PROJECT || MODE == MODE_SAMPLE) {
+      if (col16 < a.K) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if (t >= a.ntrees) break;
+          const int gcol = (a.tree0 + t) * a.K + col16;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t p = pbase + i;
+            if (p < a.m) {
+              if (MODE == MODE_PROJECT) a.out[p * (int64_t)(a.L * a.K) + gcol] = acc[t][i];
+              else a.out[(int64_t)gcol * a.ld + p] = acc[t][i];
+            }
+          }
+        }
+      }
+    } else {
+      uint8_t* st = stage + wave * (16 * NT * KP);          // [16 points][NT][KP]
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pl = 4 * grp + i;
+          uint8_t code = 0;
+          if (col16 < a.K && t < a.ntrees) {
+            const float h = acc[t][i];
+            const float* tab = Bs + (t * a.K + col16) * a.Nr;
+            int pos = 0;
+            for (int s = a.Nr >> 1; s > 0; s >>= 1)
+              if (tab[pos + s - 1] <= h) pos += s;
+            code = static_cast<uint8_t>(pos);
+            if (pbase + i < a.m) { vmin[t] = fminf(vmin[t], h); vmax[t] = fmaxf(vmax[t], h); }
+          }
+          st[(pl * NT + t) * KP + col16] = code;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      // lane e < 16*NT writes the 16-byte code row of point e%16 in tree e/16
+      if (lane < 16 * a.ntrees) {
+        const int pl = lane & 15, t = lane >> 4;
+        const int64_t p = tile * 16 + pl;
+        if (p < a.m) {
+          const uint4 v = *reinterpret_cast<const uint4*>(st + (pl * NT + t) * KP);
+          *reinterpret_cast<uint4*>(a.codes + ((int64_t)(a.tree0 + t) * a.n + p) * KP) = v;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+
+  if constexpr (MODE == MODE_ENCODE) {
+    // column min / max over all points (outer breakpoints B(1), B(Nr+1))
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float lo = vmin[t], hi = vmax[t];
+      lo = fminf(lo, __shfl_xor(lo, 16)); hi = fmaxf(hi, __shfl_xor(hi, 16));
+      lo = fminf(lo, __shfl_xor(lo, 32)); hi = fmaxf(hi, __shfl_xor(hi, 32));
+      if (lane < a.K && t < a.ntrees && lo <= hi) {
+        const int gcol = (a.tree0 + t) * a.K + lane;
+        atomicMin(&a.colmin[gcol], float_to_ordered(lo));
+        atomicMax(&a.colmax[gcol], float_to_ordered(hi));
+      }
+    }
+  }
+}
+
+template <int NT, bool VEC4, int MODE>
+void launch_t(const ProjArgs& a, hipStream_t s, size_t smem, int grid) {
+  auto k = project_kernel<NT, VEC4, MODE>;
+  PDET_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(PROJ_THREADS), smem, s, a);
+  PDET_HIP(hipGetLastError());
+}
+
+template <int MODE>
+void launch_mode(int nt, bool vec4, const ProjArgs& a, hipStream_t s, size_t smem, int grid) {
+#define PDET_CASE(N)                                                   \
+  case N:                                                              \
+    if (vec4) launch_t<N, true, MODE>(a, s, smem, grid);               \
+    else launch_t<N, false, MODE>(a, s, smem, grid);                   \
+    break;
+  switch (nt) {
+    PDET_CASE(1) PDET_CASE(2) PDET_CASE(4)
+    default: throw Error{PDET_EUNSUPPORTED, "projection tile count"};
+  }
+#undef PDET_CASE
+}
+
+int grid_for(int64_t m, int dev_cus) {
+  const int64_t tiles = (m + 15) / 16;
+  const int64_t wg = (tiles + PROJ_WAVES - 1) / PROJ_WAVES;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(wg, (int64_t)dev_cus * 2));
+}
+
+}  // namespace
+
+// Trees per launch: 4 (64 columns), the LDS budget of the encode tables.
+constexpr int TREES_PER_LAUNCH = 4;
+
+static int group_nt(int trees) { return trees <= 1 ? 1 : (trees <= 2 ? 2 : 4); }
+
+void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* rows, int mode,
+                    float* out, int64_t ld, hipStream_t s) {
+  for (int t0 = 0; t0 < ix.L; t0 += TREES_PER_LAUNCH) {
+    const int trees = std::min(TREES_PER_LAUNCH, ix.L - t0);
+    const int nt = group_nt(trees);
+    ProjArgs a{};
+    a.X = X; a.m = m; a.d = ix.d; a.rows = rows;
+    a.tree0 = t0; a.ntrees = trees; a.L = ix.L; a.K = ix.K; a.Nr = ix.Nr; a.bits = ix.bits;
+    a.n = ix.n;
+    a.out = out; a.ld = ld;
+    a.Btab = ix.B.as<float>();
+    a.codes = ix.codes.as<uint8_t>();
+    a.colmin = ix.colmm.as<uint32_t>();
+    a.colmax = ix.colmm.as<uint32_t>() + ix.L * ix.K;
+    // A is stored per launch group: [group][d][NC]
+    a.A = ix.A.as<float>() + (int64_t)(t0 / TREES_PER_LAUNCH) * ix.d * (TREES_PER_LAUNCH * 16);
+    const int NC = nt * 16;
+    a.dk = std::min(((ix.d + 15) / 16) * 16, 128);
+    size_t smem = (size_t)a.dk * NC * 4;
+    if (mode == MODE_ENCODE) smem += (size_t)nt * ix.K * ix.Nr * 4 + (size_t)PROJ_WAVES * 16 * nt * KP;
+    const bool vec4 = (ix.d % 4) == 0;
+    const int grid = grid_for(m, ix.num_cus);
+    if (mode == MODE_PROJECT) launch_mode<MODE_PROJECT>(nt, vec4, a, s, smem, grid);
+    else if (mode == MODE_SAMPLE) launch_mode<MODE_SAMPLE>(nt, vec4, a, s, smem, grid);
+    else launch_mode<MODE_ENCODE>(nt, vec4, a, s, smem, grid);
+  }
+}
+
+void project_points(const Index& ix, const float* X, int64_t m, float* out, hipStream_t s) {
+  run_projection(ix, X, m, nullptr, MODE_PROJECT, out, 0, s);
+}
+void project_sample(const Index& ix, const int64_t* rows, int64_t m, float* out, int64_t ld,
+                    hipStream_t s) {
+  run_projection(ix, ix.X, m, rows, MODE_SAMPLE, out, ld, s);
+}
+void encode_points(const Index& ix, hipStream_t s) {
+  run_projection(ix, ix.X, ix.n, nullptr, MODE_ENCODE, nullptr, 0, s);
+}
+
+// Padded device layout of A: for each group of 4 trees, [d][64] with column
+// 16*t + j = a_{(g*4+t), j} for j < K and zeros elsewhere.
+std::vector<float> pad_projection(const float* proj, int d, int L, int K) {
+  const int groups = (L + TREES_PER_LAUNCH - 1) / TREES_PER_LAUNCH;
+  const int NCg = TREES_PER_LAUNCH * 16;
+  std::vector<float> out((size_t)groups * d * NCg, 0.0f);
+  for (int g = 0; g < groups; ++g) {
+    const int trees = std::min(TREES_PER_LAUNCH, L - g * TREES_PER_LAUNCH);
+    const int nc = group_nt(trees) * 16;   // the launch reads NC = nt*16 columns per row
+    for (int r = 0; r < d; ++r)
+      for (int t = 0; t < trees; ++t)
+        for (int j = 0; j < K; ++j)
+          out[(size_t)g * d * NCg + (size_t)r * nc + t * 16 + j] =
+              proj[(size_t)r * L * K + (g * TREES_PER_LAUNCH + t) * K + j];
+  }
+  return out;
+}
+
+}  // namespace pdet

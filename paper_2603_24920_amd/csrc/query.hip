@@ -1,0 +1,619 @@
+// c^2-k-ANN query (Algorithm 5) with the optimised range query of Section 6
+// (relaxed whole-leaf admission when the leaf's lower bound is within eps*r, and
+// admission in ascending lower-bound order), batched on gfx950.
+//
+// Kernels:
+//  q_setup  per query: radius ladder r_rho = r_min*c^rho, thresholds (eps*r_rho)^2
+//           and c*r_rho, computed with the same double operations as the definition.
+//  q_rho    batched over (leaf block, tree, query tile): squared lower bound of every
+//           leaf box to q' and the first round whose threshold admits it (uint8,
+//           255 = never). Leaf boxes are read once per query tile.
+//  q_main   one workgroup per query: rounds outermost, trees in order; per (round,
+//           tree) the admitted leaves are compacted; if stop rule A may fire inside
+//           the step, the exact number of new points per leaf is counted and a
+//           weighted radix select over the (LB^2, leaf ordinal) keys finds the leaf
+//           at which |S| first reaches T; admitted points are deduplicated with a
+//           per-query bitmap (atomic test-and-set), verified by exact distance and
+//           offered to a top-k list in LDS; stop rule B checks the k-th distance
+//           against c*r after each round.
+#include "devutil.h"
+#include "internal.h"
+
+namespace pdet {
+namespace {
+
+constexpr int QM = 256;          // threads of q_main
+constexpr int CB = 512;          // top-k candidate buffer
+constexpr int QT = 16;           // queries per q_rho block
+constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
+
+struct QArgs {
+  int64_t n;
+  int d, L, K, dpad;
+  const float* X;
+  const uint16_t* xbf;
+  const uint8_t* xf8;
+  const float* xscale;
+  const int32_t* perm;
+  const int32_t* lstart[PDET_MAX_L];
+  const int32_t* lcount[PDET_MAX_L];
+  const float* box[PDET_MAX_L];
+  int64_t nl[PDET_MAX_L];
+  int64_t nlpad;
+  const float* Q;
+  const float* qp;           // [nq][L*K]
+  const int32_t* qk;
+  const int64_t* qT;
+  const int64_t* qoff;
+  const double* qc;
+  const float* t2;           // [slots][NRHO]
+  const double* crr;         // [slots][NRHO]
+  uint8_t* rho;              // [slots][L][nlpad]
+  uint32_t* bitmap;          // [slots][nwords]
+  int64_t nwords;
+  uint32_t* adm_leaf;        // [slots][admcap]
+  uint32_t* adm_w;
+  float* adm_lb;
+  uint32_t* adm2_leaf;       // [slots][admcap + 1]
+  uint32_t* adm2_pre;
+  int64_t admcap;
+  int64_t* ids;
+  float* dists;
+  int32_t* qstats;
+  int rescore, NM;
+  int64_t q0;
+  int nslots;
+  double r_min, eps;
+};
+
+__global__ void q_setup(QArgs a) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= a.nslots) return;
+  const double c = a.qc[a.q0 + slot];
+  float* t2 = const_cast<float*>(a.t2) + (int64_t)slot * NRHO;
+  double* crr = const_cast<double*>(a.crr) + (int64_t)slot * NRHO;
+  double r = a.r_min;
+  for (int rho = 0; rho < NRHO - 1; ++rho) {
+    const double t = a.eps * r;
+    const double tt = t * t;
+    t2[rho] = (float)tt;
+    crr[rho] = c * r;
+    r = c * r;
+  }
+  t2[NRHO - 1] = INFINITY;
+  crr[NRHO - 1] = INFINITY;
+}
+
+// Squared lower-bound distance from q' to a leaf box; explicit fma keeps it identical
+// wherever it is evaluated.
+__device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, const float* q,
+                                 int K) {
+  float acc = 0.0f;
+  for (int j = 0; j < K; ++j) {
+    const float lo = box[(int64_t)j * nl + leaf];
+    const float hi = box[(int64_t)(K + j) * nl + leaf];
+    const float g = fmaxf(0.0f, fmaxf(lo - q[j], q[j] - hi));
+    acc = __fmaf_rn(g, g, acc);
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void q_rho(QArgs a) {
+  __shared__ float sq[QT][PDET_MAX_K];
+  __shared__ float st[QT][NRHO];
+  const int tree = blockIdx.y;
+  const int slot0 = blockIdx.z * QT;
+  const int64_t nl = a.nl[tree];
+  for (int e = threadIdx.x; e < QT * NRHO; e += blockDim.x) {
+    const int qi = e / NRHO, r = e % NRHO;
+    st[qi][r] = (slot0 + qi < a.nslots) ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
+  }
+  for (int e = threadIdx.x; e < QT * a.K; e += blockDim.x) {
+    const int qi = e / a.K, j = e % a.K;
+    sq[qi][j] = (slot0 + qi < a.nslots)
+                    ? a.qp[(a.q0 + slot0 + qi) * (int64_t)(a.L * a.K) + tree * a.K + j]
+                    : 0.0f;
+  }
+  __syncthreads();
+  const int64_t leaf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (leaf >= nl) return;
+  float lo[PDET_MAX_K], hi[PDET_MAX_K];
+  const float* box = a.box[tree];
+#pragma unroll
+  for (int j = 0; j < PDET_MAX_K; ++j) {
+    lo[j] = (j < a.K) ? box[(int64_t)j * nl + leaf] : 0.0f;
+    hi[j] = (j < a.K) ? box[(int64_t)(a.K + j) * nl + leaf] : 0.0f;
+  }
+  for (int qi = 0; qi < QT; ++qi) {
+    const int slot = slot0 + qi;
+    if (slot >= a.nslots) break;
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < PDET_MAX_K; ++j) {
+      if (j < a.K) {
+        const float g = fmaxf(0.0f, fmaxf(lo[j] - sq[qi][j], sq[qi][j] - hi[j]));
+        acc = __fmaf_rn(g, g, acc);
+      }
+    }
+    int pos = 0;   // first round whose threshold admits the leaf = #thresholds < lb2
+#pragma unroll
+    for (int s = NRHO / 2; s > 0; s >>= 1)
+      if (st[qi][pos + s - 1] < acc) pos += s;
+    a.rho[((int64_t)slot * a.L + tree) * a.nlpad + leaf] = (uint8_t)pos;
+  }
+}
+
+__device__ inline bool lex_less(double a, int32_t ia, double b, int32_t ib) {
+  return a < b || (a == b && ia < ib);
+}
+
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// Euclidean distance of candidate `id` to the query, computed by a group of 16 lanes
+// (every lane of the group must call it). PREC 0: float32 data, FP64 accumulation;
+// 1: bf16 copy; 2: fp8 e4m3 copy with a per-row scale (FP32 accumulation).
+template <int PREC>
+__device__ inline double cand_dist(const QArgs& a, int32_t id, const float* qv, int l16) {
+  if constexpr (PREC == PDET_FP32) {
+    const float* xr = a.X + (int64_t)id * a.d;
+    double acc = 0.0;
+    if ((a.d & 3) == 0) {
+      const float4* x4 = reinterpret_cast<const float4*>(xr);
+      const float4* q4 = reinterpret_cast<const float4*>(qv);
+      for (int c = l16; c < (a.d >> 2); c += 16) {
+        const float4 x = x4[c], q = q4[c];
+        const double d0 = (double)x.x - (double)q.x, d1 = (double)x.y - (double)q.y;
+        const double d2 = (double)x.z - (double)q.z, d3 = (double)x.w - (double)q.w;
+        acc = fma(d0, d0, acc); acc = fma(d1, d1, acc);
+        acc = fma(d2, d2, acc); acc = fma(d3, d3, acc);
+      }
+    } else {
+      for (int t = l16; t < a.d; t += 16) {
+        const double df = (double)xr[t] - (double)qv[t];
+        acc = fma(df, df, acc);
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    return sqrt(acc);
+  } else if constexpr (PREC == PDET_BF16) {
+    const uint4* xr = reinterpret_cast<const uint4*>(a.xbf + (int64_t)id * a.dpad);
+    float acc = 0.0f;
+    for (int c = l16; c < (a.dpad >> 3); c += 16) {
+      const uint4 v = xr[c];
+      const float* q = qv + c * 8;
+      float df;
+      df = bf16_lo(v.x) - q[0]; acc = fmaf(df, df, acc);
+      df = bf16_hi(v.x) - q[1]; acc = fmaf(df, df, acc);
+      df = bf16_lo(v.y) - q[2]; acc = fmaf(df, df, acc);
+      df = bf16_hi(v.y) - q[3]; acc = fmaf(df, df, acc);
+      df = bf16_lo(v.z) - q[4]; acc = fmaf(df, df, acc);
+      df = bf16_hi(v.z) - q[5]; acc = fmaf(df, df, acc);
+      df = bf16_lo(v.w) - q[6]; acc = fmaf(df, df, acc);
+      df = bf16_hi(v.w) - q[7]; acc = fmaf(df, df, acc);
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    return sqrt((double)acc);
+  } else {
+    const uint4* xr = reinterpret_cast<const uint4*>(a.xf8 + (int64_t)id * a.dpad);
+    const float sc = a.xscale[id];
+    float acc = 0.0f;
+    for (int c = l16; c < (a.dpad >> 4); c += 16) {
+      const uint4 v = xr[c];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      const float* q = qv + c * 16;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int wi = (int)w[u];
+        const float x0 = __builtin_amdgcn_cvt_f32_fp8(wi, 0) * sc - q[u * 4 + 0];
+        const float x1 = __builtin_amdgcn_cvt_f32_fp8(wi, 1) * sc - q[u * 4 + 1];
+        const float x2 = __builtin_amdgcn_cvt_f32_fp8(wi, 2) * sc - q[u * 4 + 2];
+        const float x3 = __builtin_amdgcn_cvt_f32_fp8(wi, 3) * sc - q[u * 4 + 3];
+        acc = fmaf(x0, x0, acc); acc = fmaf(x1, x1, acc);
+        acc = fmaf(x2, x2, acc); acc = fmaf(x3, x3, acc);
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    return sqrt((double)acc);
+  }
+}
+
+// Bitonic sort of (distance, id) pairs, ascending, over `len` (a power of two) entries.
+__device__ void sort_pairs(double* ld, int32_t* li, int len) {
+  for (int k = 2; k <= len; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < (len >> 1); t += QM) {
+        const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const int p = i | j;
+        const bool asc = (i & k) == 0;
+        const double di = ld[i], dp = ld[p];
+        const int32_t ii = li[i], ip = li[p];
+        if (lex_less(dp, ip, di, ii) == asc) {
+          ld[i] = dp; li[i] = ip; ld[p] = di; li[p] = ii;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(QM) void q_main(QArgs a) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  double* ld = reinterpret_cast<double*>(sm);
+  int32_t* li = reinterpret_cast<int32_t*>(ld + a.NM);
+  float* qv = reinterpret_cast<float*>(li + a.NM);
+  const int dq = (PREC == PDET_FP32) ? ((a.d + 3) & ~3) : a.dpad;
+  float* qps = qv + dq;
+
+  __shared__ uint32_t w_pre[QM + 1];
+  __shared__ int32_t w_start[QM];
+  __shared__ int32_t idbuf[QM];
+  __shared__ uint32_t sh_scan[QM / 64 + 1];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t s_m, s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix;
+  __shared__ unsigned long long s_pts, s_cut;
+
+  const int slot = blockIdx.x;
+  const int64_t q = a.q0 + slot;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = tid & 15, grp = tid >> 4;
+  const int k = a.qk[q];
+  const int64_t T = a.qT[q];
+  const int KL = (PREC == PDET_FP32) ? k : k * a.rescore;
+  const int LK = a.L * a.K;
+
+  for (int e = tid; e < a.NM; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
+  for (int t = tid; t < dq; t += QM) qv[t] = (t < a.d) ? a.Q[q * a.d + t] : 0.0f;
+  for (int t = tid; t < LK; t += QM) qps[t] = a.qp[q * LK + t];
+  uint32_t* bm = a.bitmap + (int64_t)slot * a.nwords;
+  for (int64_t w = tid; w < a.nwords; w += QM) bm[w] = 0u;
+  if (tid == 0) { s_ncb = 0; s_hsum = 0; s_hmix = 0; }
+  __threadfence_block();
+  __syncthreads();
+
+  uint32_t* adm = a.adm_leaf + (int64_t)slot * a.admcap;
+  uint32_t* admw = a.adm_w + (int64_t)slot * a.admcap;
+  float* admlb = a.adm_lb + (int64_t)slot * a.admcap;
+  uint32_t* adm2 = a.adm2_leaf + (int64_t)slot * (a.admcap + 1);
+  uint32_t* pre2 = a.adm2_pre + (int64_t)slot * (a.admcap + 1);
+
+  int64_t nS = 0, leaves = 0;
+  uint32_t hsum = 0, hmix = 0;
+  int stop = -1, rounds = 0;
+
+  auto merge = [&]() {
+    const int used = KL + (int)s_ncb;
+    for (int e = used + tid; e < a.NM; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
+    __syncthreads();
+    sort_pairs(ld, li, a.NM);
+    if (tid == 0) s_ncb = 0;
+    __syncthreads();
+  };
+
+  for (int rho = 0; rho < NRHO - 1 && stop < 0; ++rho) {
+    rounds = rho + 1;
+    for (int i = 0; i < a.L; ++i) {
+      const int64_t nl = a.nl[i];
+      const int32_t* lst = a.lstart[i];
+      const int32_t* lct = a.lcount[i];
+      const int32_t* perm = a.perm + (int64_t)i * a.n;
+      if (tid == 0) { s_m = 0; s_pts = 0; }
+      __syncthreads();
+      const uint8_t* rr = a.rho + ((int64_t)slot * a.L + i) * a.nlpad;
+      for (int64_t b = (int64_t)tid * 16; b < nl; b += QM * 16) {
+        const uint4 v = *reinterpret_cast<const uint4*>(rr + b);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          if (((w[e >> 2] >> (8 * (e & 3))) & 255u) == (uint32_t)rho && b + e < nl) {
+            const uint32_t pos = atomicAdd(&s_m, 1u);
+            adm[pos] = (uint32_t)(b + e);
+            atomicAdd(&s_pts, (unsigned long long)lct[b + e]);
+          }
+        }
+      }
+      __syncthreads();
+      const uint32_t m = s_m;
+      const int64_t pts = (int64_t)s_pts;
+      __syncthreads();   // all threads hold m before thread 0 resets the counters again
+      if (m == 0) continue;
+
+      unsigned long long cut = ~0ull;
+      if (nS + pts >= T) {
+        // exact new-point counts: stop rule A may fire inside this step
+        if (tid == 0) s_newtot = 0;
+        __syncthreads();
+        for (uint32_t e = wave; e < m; e += QM / 64) {
+          const uint32_t leaf = adm[e];
+          const int32_t st = lst[leaf], cnt = lct[leaf];
+          uint32_t cn = 0;
+          for (int p0 = 0; p0 < cnt; p0 += 64) {
+            const int p = p0 + lane;
+            bool nw = false;
+            if (p < cnt) {
+              const int32_t id = perm[st + p];
+              const uint32_t wv = __hip_atomic_load(&bm[id >> 5], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+              nw = !((wv >> (id & 31)) & 1u);
+            }
+            cn += (uint32_t)__popcll(__ballot(nw));
+          }
+          if (lane == 0) {
+            admw[e] = cn;
+            admlb[e] = leaf_lb2(a.box[i], nl, leaf, qps + i * a.K, a.K);
+            atomicAdd(&s_newtot, cn);
+          }
+        }
+        __syncthreads();
+        if (nS + (int64_t)s_newtot >= T) {
+          // weighted radix select: smallest key whose inclusive weight prefix reaches R
+          unsigned long long prefix = 0;
+          uint32_t R = (uint32_t)(T - nS);
+          for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            hist[tid] = 0;
+            __syncthreads();
+            for (uint32_t e = tid; e < m; e += QM) {
+              const unsigned long long key =
+                  ((unsigned long long)__float_as_uint(admlb[e]) << 32) | adm[e];
+              if (pass == 0 || (key >> (shift + 8)) == prefix)
+                atomicAdd(&hist[(key >> shift) & 255], admw[e]);
+            }
+            __syncthreads();
+            if (tid == 0) {
+              uint32_t acc = 0;
+              int dg = 0;
+              for (; dg < 255; ++dg) {
+                if (acc + hist[dg] >= R) break;
+                acc += hist[dg];
+              }
+              s_cut = (prefix << 8) | (unsigned long long)dg;
+              s_newtot = R - acc;
+            }
+            __syncthreads();
+            prefix = s_cut;
+            R = s_newtot;
+            __syncthreads();
+          }
+          cut = prefix;
+        }
+      }
+
+      // included leaves, compacted, with exclusive prefix of their sizes
+      uint32_t m2 = 0, P = 0;
+      for (uint32_t b = 0; b < m; b += QM) {
+        const uint32_t e = b + tid;
+        bool inc = false;
+        uint32_t cnt = 0, leaf = 0;
+        if (e < m) {
+          leaf = adm[e];
+          inc = (cut == ~0ull) ||
+                ((((unsigned long long)__float_as_uint(admlb[e]) << 32) | leaf) <= cut);
+          if (inc) cnt = (uint32_t)lct[leaf];
+        }
+        uint32_t t1, t2;
+        const uint32_t pos = block_excl_scan<QM>(inc ? 1u : 0u, sh_scan, &t1);
+        const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &t2);
+        if (inc) { adm2[m2 + pos] = leaf; pre2[m2 + pos] = P + pre; }
+        m2 += t1;
+        P += t2;
+      }
+      if (tid == 0) { pre2[m2] = P; s_ef = 0; }
+      leaves += m2;
+      __syncthreads();
+
+      int64_t newS = 0;
+      for (uint32_t base = 0; base < P; base += QM) {
+        const uint32_t ef = s_ef;
+        {
+          const uint32_t e = ef + tid;
+          w_pre[tid] = (e <= m2) ? pre2[e] : 0xffffffffu;
+          w_start[tid] = (e < m2) ? lst[adm2[e]] : 0;
+          if (tid == 0) w_pre[QM] = (ef + QM <= m2) ? pre2[ef + QM] : 0xffffffffu;
+          if (tid == 0) s_nb = 0;
+        }
+        __syncthreads();
+        const uint32_t p = base + tid;
+        if (p < P) {
+          int lo = 0, hi = QM;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (w_pre[mid] <= p) lo = mid; else hi = mid;
+          }
+          const int32_t id = perm[w_start[lo] + (p - w_pre[lo])];
+          const uint32_t bit = 1u << (id & 31);
+          const uint32_t old = atomicOr(&bm[id >> 5], bit);
+          if (!(old & bit)) {
+            idbuf[atomicAdd(&s_nb, 1u)] = id;
+            hsum += (uint32_t)id;
+            hmix += mix32((uint32_t)id);
+          }
+        }
+        __syncthreads();
+        const uint32_t nb = s_nb;
+        newS += nb;
+        if (tid == 0) {
+          // first window entry of the next chunk: last e with pre <= base + QM
+          const uint32_t nbase = base + QM;
+          int lo = 0, hi = QM + 1;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (w_pre[mid] <= nbase) lo = mid; else hi = mid;
+          }
+          s_ef = ef + lo;
+        }
+        for (uint32_t c0 = 0; c0 < nb; c0 += QM / 16) {
+          const uint32_t c = c0 + grp;
+          const bool valid = c < nb;
+          const int32_t id = valid ? idbuf[c] : 0;
+          const double dd = cand_dist<PREC>(a, id, qv, l16);
+          if (valid && l16 == 0 && lex_less(dd, id, ld[KL - 1], li[KL - 1])) {
+            const uint32_t pos = atomicAdd(&s_ncb, 1u);
+            ld[KL + pos] = dd;
+            li[KL + pos] = id;
+          }
+        }
+        __syncthreads();
+        if (s_ncb > (uint32_t)(CB - QM)) merge();
+      }
+      nS += newS;
+      if (cut != ~0ull) { stop = 1; break; }
+    }
+    if (stop >= 0) break;
+    if (s_ncb > 0) merge();
+    if (nS >= k && ld[k - 1] <= a.crr[(int64_t)slot * NRHO + rho]) stop = 2;
+    __syncthreads();
+  }
+  if (s_ncb > 0) merge();
+
+  if constexpr (PREC != PDET_FP32) {
+    // re-rank the kept low-precision candidates with exact float32 distances
+    for (int t0 = 0; t0 < KL; t0 += QM / 16) {
+      const int t = t0 + grp;
+      const bool valid = t < KL && li[t] != INT32_MAX;
+      const int32_t id = valid ? li[t] : 0;
+      const double dd = cand_dist<PDET_FP32>(a, id, qv, l16);
+      if (valid && l16 == 0) ld[t] = dd;
+    }
+    __syncthreads();
+    int len = 1;
+    while (len < KL) len <<= 1;
+    for (int e = KL + tid; e < len; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
+    __syncthreads();
+    sort_pairs(ld, li, len);
+  }
+
+  const int64_t off = a.qoff[q];
+  for (int t = tid; t < k; t += QM) {
+    a.ids[off + t] = (li[t] == INT32_MAX) ? -1 : (int64_t)li[t];
+    a.dists[off + t] = (float)ld[t];
+  }
+  atomicAdd(&s_hsum, hsum);
+  atomicAdd(&s_hmix, hmix);
+  __syncthreads();
+  if (tid == 0 && a.qstats) {
+    int32_t* st = a.qstats + q * PDET_QSTAT_WORDS;
+    st[PDET_QSTAT_ROUNDS] = rounds;
+    st[PDET_QSTAT_NCAND] = (int32_t)nS;
+    st[PDET_QSTAT_STOP] = stop;
+    st[PDET_QSTAT_LEAVES] = (int32_t)leaves;
+    st[PDET_QSTAT_HSUM] = (int32_t)s_hsum;
+    st[PDET_QSTAT_HMIX] = (int32_t)s_hmix;
+    st[6] = 0;
+    st[7] = 0;
+  }
+}
+
+}  // namespace
+
+void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
+  const int64_t nq = qc.nq;
+  if (nq == 0) return;
+  const int LK = ix.L * ix.K;
+  // per-query parameters
+  std::vector<int64_t> T(nq), off(nq);
+  int maxKL = 1;
+  int64_t acc = 0;
+  for (int64_t q = 0; q < nq; ++q) {
+    const int k = qc.k_host[q];
+    T[q] = (int64_t)std::ceil(qc.beta * (double)ix.n) + k;
+    off[q] = acc;
+    acc += k;
+    maxKL = std::max(maxKL, qc.precision == PDET_FP32 ? k : k * qc.rescore);
+  }
+  DevBuf dk((size_t)nq * 4), dc((size_t)nq * 8), dT((size_t)nq * 8), doff((size_t)nq * 8);
+  PDET_HIP(hipMemcpyAsync(dk.p, qc.k_host, nq * 4, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(dc.p, qc.c_host, nq * 8, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(dT.p, T.data(), nq * 8, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(doff.p, off.data(), nq * 8, hipMemcpyHostToDevice, s));
+
+  DevBuf qp((size_t)nq * LK * 4);
+  project_points(ix, qc.Q, nq, qp.as<float>(), s);
+
+  // scratch per query slot; the number of slots is bounded by device memory
+  const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
+  const int64_t nwords = (ix.n + 31) / 32;
+  const int64_t admcap = std::max<int64_t>(ix.nl_max, 1);
+  const size_t per_slot = (size_t)ix.L * nlpad + (size_t)nwords * 4 + (size_t)admcap * 12 +
+                          (size_t)(admcap + 1) * 8 + NRHO * 12;
+  size_t freeb = 0, totalb = 0;
+  PDET_HIP(hipMemGetInfo(&freeb, &totalb));
+  const size_t budget = std::min<size_t>(freeb / 3, (size_t)24 << 30);
+  const int64_t nslots = std::max<int64_t>(1, std::min<int64_t>(nq, budget / per_slot));
+  DevBuf rho((size_t)nslots * ix.L * nlpad), bitmap((size_t)nslots * nwords * 4);
+  DevBuf admb((size_t)nslots * admcap * 12), adm2((size_t)nslots * (admcap + 1) * 8);
+  DevBuf t2((size_t)nslots * NRHO * 4), crr((size_t)nslots * NRHO * 8);
+  PDET_HIP(hipMemsetAsync(rho.p, 0xff, rho.bytes, s));   // entries past a tree's leaves: never
+
+  QArgs a{};
+  a.n = ix.n; a.d = ix.d; a.L = ix.L; a.K = ix.K; a.dpad = ix.dpad;
+  a.X = ix.X;
+  a.xbf = ix.xbf16.as<uint16_t>();
+  a.xf8 = ix.xfp8.as<uint8_t>();
+  a.xscale = ix.xscale.as<float>();
+  a.perm = ix.perm.as<int32_t>();
+  for (int i = 0; i < ix.L; ++i) {
+    a.lstart[i] = ix.leaf_start[i].as<int32_t>();
+    a.lcount[i] = ix.leaf_count[i].as<int32_t>();
+    a.box[i] = ix.box[i].as<float>();
+    a.nl[i] = ix.nl[i];
+  }
+  a.nlpad = nlpad;
+  a.Q = qc.Q;
+  a.qp = qp.as<float>();
+  a.qk = dk.as<int32_t>();
+  a.qT = dT.as<int64_t>();
+  a.qoff = doff.as<int64_t>();
+  a.qc = dc.as<double>();
+  a.t2 = t2.as<float>();
+  a.crr = crr.as<double>();
+  a.rho = rho.as<uint8_t>();
+  a.bitmap = bitmap.as<uint32_t>();
+  a.nwords = nwords;
+  a.adm_leaf = admb.as<uint32_t>();
+  a.adm_w = a.adm_leaf + nslots * admcap;
+  a.adm_lb = reinterpret_cast<float*>(a.adm_w + nslots * admcap);
+  a.adm2_leaf = adm2.as<uint32_t>();
+  a.adm2_pre = a.adm2_leaf + nslots * (admcap + 1);
+  a.admcap = admcap;
+  a.ids = qc.ids;
+  a.dists = qc.dists;
+  a.qstats = qc.qstats;
+  a.rescore = qc.rescore;
+  a.r_min = qc.r_min;
+  a.eps = qc.eps;
+  int NM = 1;
+  while (NM < maxKL + CB) NM <<= 1;
+  a.NM = NM;
+  const int dq = (qc.precision == PDET_FP32) ? ((ix.d + 3) & ~3) : ix.dpad;
+  const size_t smem = (size_t)NM * 12 + (size_t)dq * 4 + (size_t)LK * 4;
+
+  for (int64_t q0 = 0; q0 < nq; q0 += nslots) {
+    a.q0 = q0;
+    a.nslots = (int)std::min<int64_t>(nslots, nq - q0);
+    hipLaunchKernelGGL(q_setup, dim3(cdiv(a.nslots, 64)), dim3(64), 0, s, a);
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(q_rho, dim3(cdiv(ix.nl_max, 256), ix.L, cdiv(a.nslots, QT)), dim3(256), 0,
+                       s, a);
+    PDET_HIP(hipGetLastError());
+    switch (qc.precision) {
+      case PDET_FP32:
+        hipLaunchKernelGGL(q_main<PDET_FP32>, dim3(a.nslots), dim3(QM), smem, s, a);
+        break;
+      case PDET_BF16:
+        hipLaunchKernelGGL(q_main<PDET_BF16>, dim3(a.nslots), dim3(QM), smem, s, a);
+        break;
+      default:
+        hipLaunchKernelGGL(q_main<PDET_FP8_E4M3>, dim3(a.nslots), dim3(QM), smem, s, a);
+        break;
+    }
+    PDET_HIP(hipGetLastError());
+  }
+  // scratch buffers are released when this returns: wait for the kernels first
+  PDET_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace pdet

@@ -1,0 +1,526 @@
+// DE-Tree creation (Algorithm 2, node split rule of the indexing phase), bulk form.
+//
+// A tree is flattened over a point permutation `perm`: every node owns a contiguous
+// range, a split partitions its range by the chosen bit (bit-0 child first), so the
+// final leaf order along `perm` is the depth-first order of the tree.
+//
+//  1. first layer: counting sort of points by the K leading code bits (2^K nodes);
+//  2. nodes larger than LDS_SEG_CAP: level-synchronous global passes (bit counts per
+//     dimension, choice of the most balanced dimension, partition into a scratch
+//     permutation, copy back);
+//  3. nodes of (max_leaf, LDS_SEG_CAP] points: one workgroup finishes the whole
+//     subtree in LDS with an explicit depth-first stack;
+//  4. leaves are recorded at their start position, numbered by a prefix scan, and
+//     written as flat tables with their breakpoint boxes.
+// A node is a leaf iff it has at most max_leaf points or every dimension is fully
+// refined. Empty nodes are dropped. Inside a leaf the point order is unspecified.
+#include "internal.h"
+
+namespace pdet {
+namespace {
+
+struct Seg {
+  int32_t tree, start, count, pad;
+  uint8_t depth[KP];
+  uint8_t prefix[KP];
+};
+
+struct LeafOut {
+  uint32_t* cnt_at;     // [L][n] leaf size recorded at the leaf's first position
+  uint16_t* hidx_at;    // [L][n][KP]
+};
+
+struct Lists {
+  Seg* big_next; uint32_t* n_big_next; uint32_t* max_big_next;
+  Seg* mid; uint32_t* n_mid;
+};
+
+__device__ inline void load_row(const uint8_t* codes, int64_t off, uint8_t (&c)[KP]) {
+  const uint4 v = *reinterpret_cast<const uint4*>(codes + off);
+  *reinterpret_cast<uint4*>(c) = v;
+}
+
+__device__ inline uint32_t code_byte(const uint4& v, int j) {
+  const uint32_t w = (j < 8) ? ((j < 4) ? v.x : v.y) : ((j < 12) ? v.z : v.w);
+  return (w >> (8 * (j & 3))) & 255u;
+}
+
+__device__ inline uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  const int lane = threadIdx.x & 63;
+  return __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__device__ void emit_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start, int count,
+                          const uint8_t* depth, const uint8_t* prefix, int K) {
+  lo.cnt_at[(int64_t)tree * n + start] = (uint32_t)count;
+  uint16_t* h = lo.hidx_at + ((int64_t)tree * n + start) * KP;
+  for (int j = 0; j < KP; ++j)
+    h[j] = (j < K) ? (uint16_t)((1u << depth[j]) | prefix[j]) : (uint16_t)0;
+}
+
+__device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, const LeafOut& lo,
+                      const Lists& li) {
+  if (s.count <= 0) return;
+  bool fully = true;
+  for (int j = 0; j < K; ++j) fully = fully && (s.depth[j] >= bits);
+  if (s.count <= max_leaf || fully) {
+    emit_leaf(lo, n, s.tree, s.start, s.count, s.depth, s.prefix, K);
+  } else if (s.count <= LDS_SEG_CAP) {
+    li.mid[atomicAdd(li.n_mid, 1u)] = s;
+  } else {
+    li.big_next[atomicAdd(li.n_big_next, 1u)] = s;
+    atomicMax(li.max_big_next, (uint32_t)s.count);
+  }
+}
+
+__device__ inline uint32_t first_layer_key(const uint8_t (&c)[KP], int K, int bits) {
+  uint32_t key = 0;
+  for (int j = 0; j < K; ++j) key |= (uint32_t)((c[j] >> (bits - 1)) & 1) << (K - 1 - j);
+  return key;
+}
+
+__global__ void fl_hist(const uint8_t* codes, int64_t n, int K, int bits, uint32_t* hist) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tree = blockIdx.y;
+  if (p >= n) return;
+  uint8_t c[KP];
+  load_row(codes, ((int64_t)tree * n + p) * KP, c);
+  atomicAdd(&hist[((int64_t)tree << K) + first_layer_key(c, K, bits)], 1u);
+}
+
+__global__ void fl_scatter(const uint8_t* codes, int64_t n, int K, int bits, const uint32_t* off,
+                           uint32_t* cursor, int32_t* perm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tree = blockIdx.y;
+  if (p >= n) return;
+  uint8_t c[KP];
+  load_row(codes, ((int64_t)tree * n + p) * KP, c);
+  const int64_t b = ((int64_t)tree << K) + first_layer_key(c, K, bits);
+  const uint32_t pos = off[b] + atomicAdd(&cursor[b], 1u);
+  perm[(int64_t)tree * n + pos] = (int32_t)p;
+}
+
+__global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, int K, int bits,
+                            int max_leaf, int64_t n, LeafOut lo, Lists li) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ((int64_t)L << K)) return;
+  const uint32_t c = hist[g];
+  if (c == 0) return;
+  const uint32_t key = (uint32_t)(g & ((1ll << K) - 1));
+  Seg s;
+  s.tree = (int32_t)(g >> K);
+  s.start = (int32_t)off[g];
+  s.count = (int32_t)c;
+  s.pad = 0;
+  for (int j = 0; j < KP; ++j) {
+    s.depth[j] = (j < K) ? 1 : (uint8_t)bits;
+    s.prefix[j] = (j < K) ? (uint8_t)((key >> (K - 1 - j)) & 1) : 0;
+  }
+  route(s, K, bits, max_leaf, n, lo, li);
+}
+
+// ---- global passes over nodes larger than LDS_SEG_CAP
+__global__ void seg_bitcount(const Seg* segs, const int32_t* perm, const uint8_t* codes,
+                             int64_t n, int K, int bits, uint32_t* cnt) {
+  const Seg s = segs[blockIdx.x];
+  uint32_t local[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) local[j] = 0;
+  const int64_t base = (int64_t)s.tree * n + s.start;
+  for (int64_t p = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; p < s.count;
+       p += (int64_t)gridDim.y * blockDim.x) {
+    uint8_t c[KP];
+    load_row(codes, ((int64_t)s.tree * n + perm[base + p]) * KP, c);
+#pragma unroll
+    for (int j = 0; j < KP; ++j)
+      if (j < K && s.depth[j] < bits) local[j] += (c[j] >> (bits - 1 - s.depth[j])) & 1;
+  }
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const uint32_t v = wave_sum(local[j]);
+    if ((threadIdx.x & 63) == 0 && v && j < K) atomicAdd(&cnt[(int64_t)blockIdx.x * KP + j], v);
+  }
+}
+
+__global__ void seg_choose(const Seg* segs, int nseg, const uint32_t* cnt, int K, int bits,
+                           int32_t* split, uint32_t* c0, uint32_t* cur0, uint32_t* cur1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nseg) return;
+  const Seg s = segs[i];
+  int best = -1;
+  int64_t best_score = 0;
+  for (int j = 0; j < K; ++j) {
+    if (s.depth[j] >= bits) continue;
+    const int64_t sc = llabs(2 * (int64_t)cnt[(int64_t)i * KP + j] - s.count);
+    if (best < 0 || sc < best_score) { best = j; best_score = sc; }
+  }
+  // a node routed here is never fully refined, so best >= 0
+  split[i] = best;
+  const uint32_t z = (uint32_t)s.count - cnt[(int64_t)i * KP + best];
+  c0[i] = z;
+  cur0[i] = (uint32_t)s.start;
+  cur1[i] = (uint32_t)s.start + z;
+}
+
+__global__ void seg_partition(const Seg* segs, const int32_t* split, const int32_t* perm,
+                              int32_t* perm_tmp, const uint8_t* codes, int64_t n, int bits,
+                              uint32_t* cur0, uint32_t* cur1) {
+  const Seg s = segs[blockIdx.x];
+  const int j = split[blockIdx.x];
+  const int sh = bits - 1 - s.depth[j];
+  const int64_t tb = (int64_t)s.tree * n;
+  for (int64_t b = (int64_t)blockIdx.y * blockDim.x; b < s.count;
+       b += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t p = b + threadIdx.x;
+    const bool valid = p < s.count;
+    int32_t id = 0;
+    int bit = 0;
+    if (valid) {
+      id = perm[tb + s.start + p];
+      bit = (codes[(tb + id) * KP + j] >> sh) & 1;
+    }
+    const uint64_t mz = __ballot(valid && bit == 0);
+    const uint64_t mo = __ballot(valid && bit == 1);
+    uint32_t bz = 0, bo = 0;
+    if ((threadIdx.x & 63) == 0) {
+      if (mz) bz = atomicAdd(&cur0[blockIdx.x], (uint32_t)__popcll(mz));
+      if (mo) bo = atomicAdd(&cur1[blockIdx.x], (uint32_t)__popcll(mo));
+    }
+    bz = __shfl(bz, 0);
+    bo = __shfl(bo, 0);
+    if (valid) {
+      const uint32_t pos = bit ? bo + lanes_below(mo) : bz + lanes_below(mz);
+      perm_tmp[tb + pos] = id;
+    }
+  }
+}
+
+__global__ void seg_copyback(const Seg* segs, const int32_t* perm_tmp, int32_t* perm, int64_t n) {
+  const Seg s = segs[blockIdx.x];
+  const int64_t b = (int64_t)s.tree * n + s.start;
+  for (int64_t p = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; p < s.count;
+       p += (int64_t)gridDim.y * blockDim.x)
+    perm[b + p] = perm_tmp[b + p];
+}
+
+__global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, const uint32_t* c0,
+                             int K, int bits, int max_leaf, int64_t n, LeafOut lo, Lists li) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nseg) return;
+  const Seg s = segs[i];
+  const int j = split[i];
+  Seg a = s, b = s;
+  a.count = (int32_t)c0[i];
+  b.start = s.start + a.count;
+  b.count = s.count - a.count;
+  a.depth[j] = b.depth[j] = s.depth[j] + 1;
+  a.prefix[j] = (uint8_t)(s.prefix[j] * 2);
+  b.prefix[j] = (uint8_t)(s.prefix[j] * 2 + 1);
+  route(a, K, bits, max_leaf, n, lo, li);
+  route(b, K, bits, max_leaf, n, lo, li);
+}
+
+// ---- one workgroup finishes a node of at most LDS_SEG_CAP points in LDS
+constexpr int FIN_THREADS = 256;
+constexpr int STACK_MAX = KP * 8 + 8;
+
+struct Node {
+  int16_t lstart, lcount;
+  uint8_t depth[KP];
+  uint8_t prefix[KP];
+};
+
+__global__ __launch_bounds__(FIN_THREADS) void seg_lds_finish(const Seg* mid, int32_t* perm,
+                                                              const uint8_t* codes, int64_t n,
+                                                              int K, int bits, int max_leaf,
+                                                              LeafOut lo) {
+  __shared__ int32_t ids[LDS_SEG_CAP];
+  __shared__ uint4 rows[LDS_SEG_CAP];
+  __shared__ uint16_t idx[LDS_SEG_CAP];
+  __shared__ uint16_t tmp[LDS_SEG_CAP];
+  __shared__ Node stack[STACK_MAX];
+  __shared__ Node cur;
+  __shared__ int sp;
+  __shared__ int state;          // 0 done, 1 leaf, 2 split
+  __shared__ uint32_t cnt[KP];
+  __shared__ uint32_t cz, co;
+  __shared__ int jsplit;
+
+  const Seg s = mid[blockIdx.x];
+  const int64_t tb = (int64_t)s.tree * n;
+  for (int t = threadIdx.x; t < s.count; t += blockDim.x) {
+    const int32_t id = perm[tb + s.start + t];
+    ids[t] = id;
+    rows[t] = *reinterpret_cast<const uint4*>(codes + (tb + id) * KP);
+    idx[t] = (uint16_t)t;
+  }
+  if (threadIdx.x == 0) {
+    Node r;
+    r.lstart = 0;
+    r.lcount = (int16_t)s.count;
+    for (int j = 0; j < KP; ++j) { r.depth[j] = s.depth[j]; r.prefix[j] = s.prefix[j]; }
+    stack[0] = r;
+    sp = 1;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (sp == 0) {
+        state = 0;
+      } else {
+        cur = stack[--sp];
+        bool fully = true;
+        for (int j = 0; j < K; ++j) fully = fully && (cur.depth[j] >= bits);
+        state = (cur.lcount <= max_leaf || fully) ? 1 : 2;
+        if (state == 1)
+          emit_leaf(lo, n, s.tree, (int64_t)s.start + cur.lstart, cur.lcount, cur.depth,
+                    cur.prefix, K);
+      }
+    }
+    if (threadIdx.x < KP) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int st = state;
+    __syncthreads();            // every thread has read `state` before thread 0 pops again
+    if (st == 0) break;
+    if (st == 1) continue;
+
+    uint32_t local[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) local[j] = 0;
+    for (int t = threadIdx.x; t < cur.lcount; t += blockDim.x) {
+      uint8_t c[KP];
+      *reinterpret_cast<uint4*>(c) = rows[idx[cur.lstart + t]];
+#pragma unroll
+      for (int j = 0; j < KP; ++j)
+        if (j < K && cur.depth[j] < bits) local[j] += (c[j] >> (bits - 1 - cur.depth[j])) & 1;
+    }
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const uint32_t v = wave_sum(local[j]);
+      if (lane == 0 && v && j < K) atomicAdd(&cnt[j], v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int best = -1;
+      int best_score = 0;
+      for (int j = 0; j < K; ++j) {
+        if (cur.depth[j] >= bits) continue;
+        const int sc = abs(2 * (int)cnt[j] - cur.lcount);
+        if (best < 0 || sc < best_score) { best = j; best_score = sc; }
+      }
+      const int c0 = cur.lcount - (int)cnt[best];
+      Node a = cur, b = cur;
+      a.lcount = (int16_t)c0;
+      b.lstart = (int16_t)(cur.lstart + c0);
+      b.lcount = (int16_t)(cur.lcount - c0);
+      a.depth[best] = b.depth[best] = cur.depth[best] + 1;
+      a.prefix[best] = (uint8_t)(cur.prefix[best] * 2);
+      b.prefix[best] = (uint8_t)(cur.prefix[best] * 2 + 1);
+      if (b.lcount > 0) stack[sp++] = b;     // popped after the bit-0 child
+      if (a.lcount > 0) stack[sp++] = a;
+      jsplit = best;
+      cz = (uint32_t)cur.lstart;
+      co = (uint32_t)(cur.lstart + c0);
+    }
+    __syncthreads();
+    const int j = jsplit;
+    const int sh = bits - 1 - cur.depth[j];
+    for (int b = 0; b < cur.lcount; b += blockDim.x) {
+      const int t = b + threadIdx.x;
+      const bool valid = t < cur.lcount;
+      uint16_t e = 0;
+      int bit = 0;
+      if (valid) {
+        e = idx[cur.lstart + t];
+        bit = (code_byte(rows[e], j) >> sh) & 1;
+      }
+      const uint64_t mz = __ballot(valid && bit == 0);
+      const uint64_t mo = __ballot(valid && bit == 1);
+      uint32_t bz = 0, bo = 0;
+      if (lane == 0) {
+        if (mz) bz = atomicAdd(&cz, (uint32_t)__popcll(mz));
+        if (mo) bo = atomicAdd(&co, (uint32_t)__popcll(mo));
+      }
+      bz = __shfl(bz, 0);
+      bo = __shfl(bo, 0);
+      if (valid) tmp[bit ? bo + lanes_below(mo) : bz + lanes_below(mz)] = e;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cur.lcount; t += blockDim.x) idx[cur.lstart + t] = tmp[cur.lstart + t];
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < s.count; t += blockDim.x) perm[tb + s.start + t] = ids[idx[t]];
+}
+
+// ---- leaf tables
+__global__ void leaf_flags(const uint32_t* cnt_at, uint32_t* flags, int64_t total) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < total) flags[g] = cnt_at[g] ? 1u : 0u;
+}
+
+struct LeafTables {
+  int32_t* start[PDET_MAX_L];
+  int32_t* count[PDET_MAX_L];
+  uint16_t* hidx[PDET_MAX_L];
+  float* box[PDET_MAX_L];
+  int64_t nl[PDET_MAX_L];
+};
+
+__global__ void leaf_compact(const uint32_t* cnt_at, const uint16_t* hidx_at, const uint32_t* ord,
+                             int64_t n, int K, int bits, int Nr, const float* B, LeafTables t) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tree = blockIdx.y;
+  if (p >= n) return;
+  const int64_t g = (int64_t)tree * n + p;
+  const uint32_t c = cnt_at[g];
+  if (!c) return;
+  const int64_t o = ord[g];
+  const int64_t nl = t.nl[tree];
+  t.start[tree][o] = (int32_t)p;
+  t.count[tree][o] = (int32_t)c;
+  for (int j = 0; j < KP; ++j) {
+    const uint16_t h = hidx_at[g * KP + j];
+    t.hidx[tree][o * KP + j] = h;
+    if (j < K) {
+      const int dep = 31 - __clz((int)h);
+      const int pre = h & ((1 << dep) - 1);
+      const int lo_code = pre << (bits - dep);
+      const int hi_code = ((pre + 1) << (bits - dep)) - 1;
+      const float* Bc = B + (int64_t)(tree * K + j) * (Nr + 1);
+      t.box[tree][(int64_t)j * nl + o] = Bc[lo_code];
+      t.box[tree][(int64_t)(K + j) * nl + o] = Bc[hi_code + 1];
+    }
+  }
+}
+
+}  // namespace
+
+void build_trees(Index& ix, hipStream_t s) {
+  const int64_t n = ix.n;
+  const int L = ix.L, K = ix.K, bits = ix.bits;
+  const int64_t NK = 1ll << K;
+
+  DevBuf hist((size_t)L * NK * 4), off((size_t)L * NK * 4), cursor((size_t)L * NK * 4);
+  DevBuf scan_tmp;
+  PDET_HIP(hipMemsetAsync(hist.p, 0, hist.bytes, s));
+  PDET_HIP(hipMemsetAsync(cursor.p, 0, cursor.bytes, s));
+  const uint8_t* codes = ix.codes.as<uint8_t>();
+  int32_t* perm = ix.perm.as<int32_t>();
+
+  hipLaunchKernelGGL(fl_hist, dim3(cdiv(n, 256), L), dim3(256), 0, s, codes, n, K, bits,
+                     hist.as<uint32_t>());
+  PDET_HIP(hipGetLastError());
+  scan_rows(hist.as<uint32_t>(), off.as<uint32_t>(), nullptr, L, NK, scan_tmp, s);
+  hipLaunchKernelGGL(fl_scatter, dim3(cdiv(n, 256), L), dim3(256), 0, s, codes, n, K, bits,
+                     off.as<uint32_t>(), cursor.as<uint32_t>(), perm);
+  PDET_HIP(hipGetLastError());
+
+  // leaf records at start positions
+  DevBuf cnt_at((size_t)L * n * 4), hidx_at((size_t)L * n * KP * 2);
+  PDET_HIP(hipMemsetAsync(cnt_at.p, 0, cnt_at.bytes, s));
+  LeafOut lo{cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>()};
+
+  // segment lists; counters: [0] n_big_a [1] max_big_a [2] n_big_b [3] max_big_b [4] n_mid
+  const int64_t mid_cap = (int64_t)L * (n / (ix.max_leaf + 1) + 1);
+  const int64_t big_cap = (int64_t)L * (n / (LDS_SEG_CAP + 1) + 1);
+  DevBuf mid((size_t)mid_cap * sizeof(Seg));
+  DevBuf bigA((size_t)big_cap * sizeof(Seg)), bigB((size_t)big_cap * sizeof(Seg));
+  DevBuf ctr(8 * 4);
+  PDET_HIP(hipMemsetAsync(ctr.p, 0, ctr.bytes, s));
+  uint32_t* c = ctr.as<uint32_t>();
+  Lists li{bigA.as<Seg>(), c + 0, c + 1, mid.as<Seg>(), c + 4};
+  hipLaunchKernelGGL(fl_segments, dim3(cdiv(L * NK, 256)), dim3(256), 0, s, hist.as<uint32_t>(),
+                     off.as<uint32_t>(), L, K, bits, ix.max_leaf, n, lo, li);
+  PDET_HIP(hipGetLastError());
+
+  uint32_t hc[8];
+  PDET_HIP(hipMemcpyAsync(hc, c, sizeof(hc), hipMemcpyDeviceToHost, s));
+  PDET_HIP(hipStreamSynchronize(s));
+  uint32_t nbig = hc[0], maxbig = hc[1];
+  Seg* cur_big = bigA.as<Seg>();
+  Seg* nxt_big = bigB.as<Seg>();
+  int cur_slot = 0;   // counters of the current list at c[2*cur_slot]
+  DevBuf perm_tmp, cntbuf, split, c0, cur0, cur1;
+  if (nbig) perm_tmp.alloc((size_t)L * n * 4);
+  while (nbig > 0) {
+    if (cntbuf.bytes < (size_t)nbig * KP * 4) {
+      cntbuf.alloc((size_t)big_cap * KP * 4);
+      split.alloc((size_t)big_cap * 4); c0.alloc((size_t)big_cap * 4);
+      cur0.alloc((size_t)big_cap * 4); cur1.alloc((size_t)big_cap * 4);
+    }
+    PDET_HIP(hipMemsetAsync(cntbuf.p, 0, (size_t)nbig * KP * 4, s));
+    const int nxt_slot = 1 - cur_slot;
+    PDET_HIP(hipMemsetAsync(c + 2 * nxt_slot, 0, 8, s));
+    const unsigned ch = std::max(1u, std::min(1024u, cdiv(maxbig, 256 * 16)));
+    hipLaunchKernelGGL(seg_bitcount, dim3(nbig, ch), dim3(256), 0, s, cur_big, perm, codes, n, K,
+                       bits, cntbuf.as<uint32_t>());
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(seg_choose, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
+                       cntbuf.as<uint32_t>(), K, bits, split.as<int32_t>(), c0.as<uint32_t>(),
+                       cur0.as<uint32_t>(), cur1.as<uint32_t>());
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(seg_partition, dim3(nbig, ch), dim3(256), 0, s, cur_big, split.as<int32_t>(),
+                       perm, perm_tmp.as<int32_t>(), codes, n, bits, cur0.as<uint32_t>(),
+                       cur1.as<uint32_t>());
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(seg_copyback, dim3(nbig, ch), dim3(256), 0, s, cur_big,
+                       perm_tmp.as<int32_t>(), perm, n);
+    PDET_HIP(hipGetLastError());
+    Lists ln{nxt_big, c + 2 * nxt_slot, c + 2 * nxt_slot + 1, mid.as<Seg>(), c + 4};
+    hipLaunchKernelGGL(seg_children, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
+                       split.as<int32_t>(), c0.as<uint32_t>(), K, bits, ix.max_leaf, n, lo, ln);
+    PDET_HIP(hipGetLastError());
+    PDET_HIP(hipMemcpyAsync(hc, c, sizeof(hc), hipMemcpyDeviceToHost, s));
+    PDET_HIP(hipStreamSynchronize(s));
+    nbig = hc[2 * nxt_slot];
+    maxbig = hc[2 * nxt_slot + 1];
+    std::swap(cur_big, nxt_big);
+    cur_slot = nxt_slot;
+  }
+  const uint32_t nmid = hc[4];
+  if (nmid) {
+    hipLaunchKernelGGL(seg_lds_finish, dim3(nmid), dim3(FIN_THREADS), 0, s, mid.as<Seg>(), perm,
+                       codes, n, K, bits, ix.max_leaf, lo);
+    PDET_HIP(hipGetLastError());
+  }
+
+  // number the leaves in position (= depth-first) order
+  DevBuf flags((size_t)L * n * 4), totals((size_t)L * 4);
+  hipLaunchKernelGGL(leaf_flags, dim3(cdiv((int64_t)L * n, 256)), dim3(256), 0, s,
+                     cnt_at.as<uint32_t>(), flags.as<uint32_t>(), (int64_t)L * n);
+  PDET_HIP(hipGetLastError());
+  scan_rows(flags.as<uint32_t>(), flags.as<uint32_t>(), totals.as<uint32_t>(), L, n, scan_tmp, s);
+  std::vector<uint32_t> nl(L);
+  PDET_HIP(hipMemcpyAsync(nl.data(), totals.p, L * 4, hipMemcpyDeviceToHost, s));
+  PDET_HIP(hipStreamSynchronize(s));
+  LeafTables t{};
+  ix.nl_max = 0;
+  for (int i = 0; i < L; ++i) {
+    ix.nl[i] = nl[i];
+    ix.nl_max = std::max<int64_t>(ix.nl_max, nl[i]);
+    ix.leaf_start[i].alloc((size_t)nl[i] * 4);
+    ix.leaf_count[i].alloc((size_t)nl[i] * 4);
+    ix.leaf_hidx[i].alloc((size_t)nl[i] * KP * 2);
+    ix.box[i].alloc((size_t)nl[i] * 2 * K * 4);
+    t.start[i] = ix.leaf_start[i].as<int32_t>();
+    t.count[i] = ix.leaf_count[i].as<int32_t>();
+    t.hidx[i] = ix.leaf_hidx[i].as<uint16_t>();
+    t.box[i] = ix.box[i].as<float>();
+    t.nl[i] = nl[i];
+  }
+  hipLaunchKernelGGL(leaf_compact, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
+                     hidx_at.as<uint16_t>(), flags.as<uint32_t>(), n, K, bits, ix.Nr,
+                     ix.B.as<float>(), t);
+  PDET_HIP(hipGetLastError());
+  PDET_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
+}
+
+}  // namespace pdet

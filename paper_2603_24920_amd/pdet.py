@@ -1,0 +1,194 @@
+"""ctypes binding of libpdet (argument marshalling only; every step runs in HIP kernels).
+
+Device buffers are torch CUDA tensors (HIP on ROCm); torch supplies memory and the
+current stream, the library does all the computation. Importing this module does not
+touch the GPU; the library is loaded on first use and a missing build is an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpdet.so")
+
+PDET_OK, PDET_EINVAL, PDET_ENOMEM, PDET_EDEVICE, PDET_EUNSUPPORTED = 0, -1, -2, -3, -4
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+MAX_K, MAX_L, MAX_TOPK, MAX_ROUNDS = 16, 16, 1024, 255
+QSTAT_WORDS = 8
+QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5)
+X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX = range(6)
+EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_info", "pdet_export", "pdet_project",
+            "pdet_epsilon", "pdet_last_error"]
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("K", c_int32), ("L", c_int32), ("Nr", c_int32), ("max_leaf", c_int32),
+                ("proj", POINTER(c_float)), ("sample_ids", POINTER(c_int64)),
+                ("n_sample", c_int64), ("lowp_copies", c_uint32)]
+
+
+class QueryParams(ctypes.Structure):
+    _fields_ = [("k", c_int32), ("c", c_double), ("k_per_query", POINTER(c_int32)),
+                ("c_per_query", POINTER(c_double)), ("beta", c_double), ("r_min", c_double),
+                ("eps", c_double), ("precision", c_int32), ("rescore", c_int32)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("n_sample", c_int64), ("d", c_int32), ("K", c_int32),
+                ("L", c_int32), ("Nr", c_int32), ("max_leaf", c_int32),
+                ("lowp_copies", c_uint32), ("leaves", c_int64 * MAX_L),
+                ("device_bytes", c_int64)]
+
+
+class PdetError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pdet status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpdet.so (built in-tree by ``build_lib``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2603_24920_amd.build_lib`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pdet_build.argtypes = [c_void_p, c_int64, c_int32, POINTER(BuildParams), c_void_p,
+                                 POINTER(c_void_p)]
+        L.pdet_query.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams), c_void_p,
+                                 c_void_p, c_void_p, c_void_p]
+        L.pdet_free.argtypes = [c_void_p]
+        L.pdet_free.restype = None
+        L.pdet_info.argtypes = [c_void_p, POINTER(IndexInfo)]
+        L.pdet_export.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_size_t]
+        L.pdet_project.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+        L.pdet_epsilon.argtypes = [c_int32, c_int32]
+        L.pdet_epsilon.restype = c_double
+        L.pdet_last_error.restype = ctypes.c_char_p
+        for f in ("pdet_build", "pdet_query", "pdet_info", "pdet_export", "pdet_project"):
+            getattr(L, f).restype = c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != PDET_OK:
+        raise PdetError(status, lib().pdet_last_error().decode())
+
+
+def epsilon(K: int, L: int) -> float:
+    """Projected-radius factor from Eq. 2 / Lemma 3, computed by the library's host code."""
+    return lib().pdet_epsilon(K, L)
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+class Index:
+    """A DE-Tree index resident on the GPU. ``X`` (CUDA float32 [n][d]) is borrowed."""
+
+    def __init__(self, X, proj, sample_ids, K=16, L=4, Nr=256, max_leaf=128, lowp=(),
+                 stream=None):
+        import torch
+        if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
+                and X.dim() == 2 and X.is_contiguous()):
+            raise ValueError("X must be a contiguous CUDA float32 [n][d] tensor")
+        self.X = X
+        self.n, self.d = X.shape
+        self._proj = np.ascontiguousarray(proj, dtype=np.float32)
+        self._sample = np.ascontiguousarray(sample_ids, dtype=np.int64)
+        if self._proj.shape != (self.d, L * K):
+            raise ValueError("proj must be [d][L*K]")
+        mask = 0
+        for name in lowp:
+            mask |= 1 << PRECISIONS[name]
+        p = BuildParams(K, L, Nr, max_leaf, self._proj.ctypes.data_as(POINTER(c_float)),
+                        self._sample.ctypes.data_as(POINTER(c_int64)), len(self._sample), mask)
+        h = c_void_p()
+        _check(lib().pdet_build(c_void_p(X.data_ptr()), self.n, self.d, ctypes.byref(p),
+                                _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.K, self.L, self.Nr, self.max_leaf = K, L, Nr, max_leaf
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pdet_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def info(self) -> dict:
+        inf = IndexInfo()
+        _check(lib().pdet_info(self._h, ctypes.byref(inf)))
+        return dict(n=inf.n, n_sample=inf.n_sample, d=inf.d, K=inf.K, L=inf.L, Nr=inf.Nr,
+                    max_leaf=inf.max_leaf, lowp_copies=inf.lowp_copies,
+                    leaves=list(inf.leaves[:inf.L]), device_bytes=inf.device_bytes)
+
+    def export(self, what: int, tree: int = 0) -> np.ndarray:
+        nl = self.info()["leaves"]
+        shape, dt = {
+            X_BREAKPOINTS: ((self.L * self.K, self.Nr + 1), np.float32),
+            X_CODES: ((self.L, self.n, 16), np.uint8),
+            X_PERM: ((self.n,), np.int32),
+            X_LEAF_START: ((nl[tree],), np.int32),
+            X_LEAF_COUNT: ((nl[tree],), np.int32),
+            X_LEAF_HIDX: ((nl[tree], 16), np.uint16),
+        }[what]
+        out = np.empty(shape, dtype=dt)
+        _check(lib().pdet_export(self._h, what, tree, out.ctypes.data_as(c_void_p), out.nbytes))
+        return out
+
+    def project(self, x, stream=None):
+        import torch
+        out = torch.empty((x.shape[0], self.L * self.K), dtype=torch.float32, device=x.device)
+        _check(lib().pdet_project(self._h, c_void_p(x.data_ptr()), x.shape[0],
+                                  c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def query(self, Q, k=10, c=1.5, beta=0.1, r_min=1.0, eps=0.0, precision="fp32",
+              rescore=4, k_per_query=None, c_per_query=None, stats=False, stream=None,
+              out=None):
+        """c^2-k-ANN for every row of Q (CUDA float32 [nq][d]).
+
+        Returns (ids int64, dists float32[, qstats int32 [nq][8]]). With per-query k the
+        outputs are flat (CSR in query order); with uniform k they are [nq][k]."""
+        import torch
+        if not (Q.is_cuda and Q.dtype == torch.float32 and Q.is_contiguous()
+                and Q.dim() == 2 and Q.shape[1] == self.d):
+            raise ValueError("Q must be a contiguous CUDA float32 [nq][d] tensor")
+        nq = Q.shape[0]
+        kp = cp = None
+        if k_per_query is not None:
+            kp = np.ascontiguousarray(k_per_query, dtype=np.int32)
+            total = int(kp.sum())
+        else:
+            total = nq * k
+        if c_per_query is not None:
+            cp = np.ascontiguousarray(c_per_query, dtype=np.float64)
+        p = QueryParams(k, c, kp.ctypes.data_as(POINTER(c_int32)) if kp is not None else None,
+                        cp.ctypes.data_as(POINTER(c_double)) if cp is not None else None,
+                        beta, r_min, eps, PRECISIONS[precision], rescore)
+        if out is None:
+            ids = torch.empty(total, dtype=torch.int64, device=Q.device)
+            dists = torch.empty(total, dtype=torch.float32, device=Q.device)
+            st = torch.empty((nq, QSTAT_WORDS), dtype=torch.int32, device=Q.device) if stats else None
+        else:
+            ids, dists, st = out
+        _check(lib().pdet_query(self._h, c_void_p(Q.data_ptr()), nq, ctypes.byref(p),
+                                c_void_p(ids.data_ptr()), c_void_p(dists.data_ptr()),
+                                c_void_p(st.data_ptr()) if st is not None else None,
+                                _stream(stream)))
+        if k_per_query is None:
+            ids, dists = ids.view(nq, k), dists.view(nq, k)
+        return (ids, dists, st) if stats else (ids, dists)

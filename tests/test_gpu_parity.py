@@ -1,0 +1,347 @@
+"""GPU parity: libpdet (HIP, through the C ABI) against the FP64 CPU oracle.
+
+Checked step by step so that a mismatch names its step:
+  projection  within the FP32 dot-product error bound (d+1) u sum|x_t a_t|;
+  breakpoints within that bound (order statistics are 1-Lipschitz);
+  codes       bit-exact except coordinates within 1e-5 of the column range of a breakpoint
+              (counted and reported);
+  trees       the oracle's tree built on the GPU's codes equals the GPU tree exactly
+              (leaf order, sizes, node ids; point sets per leaf);
+  queries     the oracle's query run on the GPU's breakpoints, codes and trees gives the
+              same candidate set (size and two hashes), stop rule, rounds, admitted leaves,
+              ids, and distances within 1e-9 relative (FP64 accumulation on both sides);
+              a difference is allowed only where a leaf bound lies within 1e-5 of a radius
+              threshold or the k-th distance within 1e-5 of c*r.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_24920_amd import pdet
+from paper_2603_24920_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+BAND = 1e-5
+
+
+def mix32(h):
+    h = h.astype(np.uint64) & 0xFFFFFFFF
+    h ^= h >> 16; h = (h * 0x85EBCA6B) & 0xFFFFFFFF
+    h ^= h >> 13; h = (h * 0xC2B2AE35) & 0xFFFFFFFF
+    h ^= h >> 16
+    return h
+
+
+def set_hashes(ids):
+    ids = np.asarray(ids, dtype=np.uint64)
+    hs = int(ids.sum() & 0xFFFFFFFF)
+    hm = int(mix32(ids).sum() & 0xFFFFFFFF)
+    to32 = lambda v: v - (1 << 32) if v >= (1 << 31) else v
+    return to32(hs), to32(hm)
+
+
+def proj_bound(X, A):
+    d = X.shape[1]
+    return 1.01 * (d + 1) * U32 * (np.abs(X.astype(np.float64)) @ np.abs(A.astype(np.float64)))
+
+
+class Case:
+    def __init__(self, X, A, sid, K, L, Nr, max_leaf, lowp=()):
+        self.X, self.A, self.sid = X, A, sid
+        self.K, self.L, self.Nr, self.max_leaf = K, L, Nr, max_leaf
+        self.Xd = torch.from_numpy(X).cuda()
+        print(f"\n[case] n={len(X)} d={X.shape[1]} K={K} L={L} Nr={Nr} max_leaf={max_leaf}",
+              flush=True)
+        self.idx = pdet.Index(self.Xd, A, sid, K, L, Nr, max_leaf, lowp=lowp)
+        torch.cuda.synchronize()
+        self.H = oracle.project(X, A)
+        self.B_or = oracle.breakpoints(self.H[sid], Nr, self.H.min(axis=0), self.H.max(axis=0))
+        self.B_gpu = self.idx.export(pdet.X_BREAKPOINTS).astype(np.float64)
+        self.codes_gpu = np.ascontiguousarray(self.idx.export(pdet.X_CODES)[:, :, :K])
+        self.eps = pdet.epsilon(K, L)
+        self._stepwise = None
+
+    def stepwise_oracle(self):
+        """Oracle index on the GPU's breakpoints and codes."""
+        if self._stepwise is None:
+            self._stepwise = oracle.build_index(self.X, self.A, self.sid, self.L, self.K,
+                                                self.Nr, self.max_leaf, B=self.B_gpu,
+                                                codes=self.codes_gpu)
+        return self._stepwise
+
+
+def check_projection(cs, rows=2000):
+    m = min(rows, len(cs.X))
+    P = cs.idx.project(cs.Xd[:m]).cpu().numpy().astype(np.float64)
+    bound = proj_bound(cs.X[:m], cs.A)
+    err = np.abs(P - cs.H[:m])
+    assert np.all(err <= bound), float((err / bound).max())
+
+
+def check_breakpoints(cs):
+    E_s = proj_bound(cs.X[cs.sid], cs.A).max(axis=0)
+    E_all = proj_bound(cs.X, cs.A).max(axis=0)
+    Bo, Bg = cs.B_or, cs.B_gpu
+    assert np.all(np.abs(Bg[:, 1:-1] - Bo[:, 1:-1]) <= E_s[:, None] + 1e-30)
+    assert np.all(np.abs(Bg[:, [0, -1]] - Bo[:, [0, -1]]) <= E_all[:, None] + 1e-30)
+
+
+def check_codes(cs):
+    codes_or = oracle.encode(cs.H, cs.B_or, cs.L, cs.K)
+    mism = cs.codes_gpu != codes_or
+    banded = np.zeros_like(mism)
+    for i in range(cs.L):
+        for j in range(cs.K):
+            col = i * cs.K + j
+            inner = cs.B_or[col, 1:-1]
+            h = cs.H[:, col]
+            pos = np.searchsorted(inner, h)
+            lo = np.abs(h - inner[np.clip(pos - 1, 0, len(inner) - 1)])
+            hi = np.abs(h - inner[np.clip(pos, 0, len(inner) - 1)])
+            rng = cs.B_or[col, -1] - cs.B_or[col, 0]
+            banded[i, :, j] = np.minimum(lo, hi) <= BAND * rng
+    bad = mism & ~banded
+    print(f"[codes] coords={mism.size} banded={int(banded.sum())} "
+          f"mismatched={int(mism.sum())} (all banded: {not bad.any()})", flush=True)
+    assert not bad.any(), np.argwhere(bad)[:10]
+
+
+def check_trees(cs):
+    for i in range(cs.L):
+        t = oracle.build_tree(cs.codes_gpu[i], cs.Nr, cs.max_leaf)
+        gs = cs.idx.export(pdet.X_LEAF_START, i)
+        gc = cs.idx.export(pdet.X_LEAF_COUNT, i)
+        gh = cs.idx.export(pdet.X_LEAF_HIDX, i)[:, :cs.K]
+        gp = cs.idx.export(pdet.X_PERM, i)
+        assert len(gs) == t.nl, (i, len(gs), t.nl)
+        np.testing.assert_array_equal(gs, t.leaf_start)
+        np.testing.assert_array_equal(gc, t.leaf_count)
+        np.testing.assert_array_equal(gh, t.hidx())
+        leaf_of_pos = np.repeat(np.arange(t.nl), t.leaf_count)
+        np.testing.assert_array_equal(gp[np.lexsort((gp, leaf_of_pos))], t.perm)
+
+
+def near_threshold(idx_or, q, rounds, r_min, c, eps):
+    """True if some leaf bound of q is within BAND of a radius threshold used."""
+    qp = q.astype(np.float64) @ idx_or.A
+    t2 = np.array([(eps * r) ** 2 for r in oracle.radius_ladder(r_min, c, rounds + 1)])
+    for i in range(idx_or.L):
+        lo, hi = idx_or.boxes[i]
+        lb2 = oracle.lower_bound_sq(qp[i * idx_or.K:(i + 1) * idx_or.K], lo, hi)
+        if np.any(np.abs(lb2[:, None] - t2[None, :]) <= BAND * t2[None, :]):
+            return True
+    return False
+
+
+def near_stop_b(X, q, cand, k, rounds, r_min, c):
+    if len(cand) < k:
+        return False
+    dd = np.sort(np.sqrt(((X[cand].astype(np.float64) - q.astype(np.float64)) ** 2).sum(axis=1)))
+    kth = dd[k - 1]
+    return any(abs(kth - c * r) <= BAND * c * r for r in oracle.radius_ladder(r_min, c, rounds + 1))
+
+
+def run_and_compare(cs, idx_or, Q, k, c, beta, r_min, label, allow_frac=0.0):
+    Qd = torch.from_numpy(Q).cuda()
+    print(f"[query {label}] nq={len(Q)} k={k} c={c} beta={beta} r_min={r_min}", flush=True)
+    ids, dists, st = cs.idx.query(Qd, k=k, c=c, beta=beta, r_min=r_min, stats=True)
+    ids, dists, st = ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
+    n_diff = n_band = 0
+    for qi, q in enumerate(Q):
+        res = oracle.query(idx_or, cs.X, q, k, c, beta, r_min, cs.eps)
+        hs, hm = set_hashes(res.cand)
+        same_set = (st[qi, pdet.QSTAT["ncand"]] == res.n_cand and st[qi, pdet.QSTAT["hsum"]] == hs
+                    and st[qi, pdet.QSTAT["hmix"]] == hm)
+        same_flow = (st[qi, pdet.QSTAT["stop"]] == (1 if res.stop == "A" else 2)
+                     and st[qi, pdet.QSTAT["rounds"]] == res.rounds
+                     and st[qi, pdet.QSTAT["leaves"]] == res.leaves)
+        if same_set and same_flow:
+            if not np.array_equal(ids[qi], res.ids):
+                # allowed only at an exact distance tie at the k boundary
+                dk = res.dists[k - 1]
+                tie = np.sum(np.abs(np.sqrt(((cs.X[res.cand].astype(np.float64) - q) ** 2).sum(1))
+                                    - dk) <= 1e-12 * dk) > 1
+                assert tie, (label, qi, ids[qi], res.ids)
+            np.testing.assert_allclose(dists[qi], res.dists, rtol=1e-6)
+            continue
+        n_diff += 1
+        rounds = max(res.rounds, int(st[qi, pdet.QSTAT["rounds"]]))
+        banded = (near_threshold(idx_or, q, rounds, r_min, c, cs.eps)
+                  or near_stop_b(cs.X, q, res.cand, k, rounds, r_min, c))
+        assert banded, (label, qi, st[qi], res.n_cand, res.stop, res.rounds, res.leaves, hs, hm)
+        n_band += 1
+    print(f"[query {label}] identical={len(Q) - n_diff}/{len(Q)} banded={n_band}", flush=True)
+    assert n_diff <= max(1, allow_frac * len(Q))
+    return ids, dists, st
+
+
+# --------------------------------------------------------------------------- cases
+@pytest.fixture(scope="module")
+def mixture():
+    w = wl.SMALL_MIXTURE
+    return w, Case(w.data(), w.proj(), w.sample(), w.K, w.L, w.Nr, w.max_leaf,
+                   lowp=("bf16", "fp8"))
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # n not a multiple of any tile, d not a multiple of 4, K < 16, L = 3, Nr = 16
+    w = wl.SMALL_MIXTURE.scaled(n=3001, d=37, K=5, L=3, Nr=16, max_leaf=7)
+    X = w.data()
+    A = wl.projection_matrix(37, 3, 5, seed=77)
+    sid = wl.sample_ids(len(X), 600, 78)
+    return w, Case(X, A, sid, 5, 3, 16, 7)
+
+
+def test_projection_within_fp32_bound(mixture, ragged):
+    check_projection(mixture[1])
+    check_projection(ragged[1])
+
+
+def test_breakpoints_within_bound(mixture, ragged):
+    check_breakpoints(mixture[1])
+    check_breakpoints(ragged[1])
+
+
+def test_codes_exact_outside_band(mixture, ragged):
+    check_codes(mixture[1])
+    check_codes(ragged[1])
+
+
+def test_trees_equal_oracle_on_gpu_codes(mixture, ragged):
+    check_trees(mixture[1])
+    check_trees(ragged[1])
+
+
+@pytest.mark.parametrize("beta,r_min", [(0.1, 4.0), (0.02, 1.0), (1.0, 6.0)])
+def test_query_stepwise_mixture(mixture, beta, r_min):
+    w, cs = mixture
+    run_and_compare(cs, cs.stepwise_oracle(), w.queries(), w.k, w.c, beta, r_min,
+                    f"mixture b={beta}")
+
+
+@pytest.mark.parametrize("beta,r_min,k,c", [(0.05, 2.0, 7, 1.5), (0.3, 0.5, 1, 2.0),
+                                            (0.0, 3.0, 30, 1.2)])
+def test_query_stepwise_ragged(ragged, beta, r_min, k, c):
+    w, cs = ragged
+    run_and_compare(cs, cs.stepwise_oracle(), w.queries(40), k, c, beta, r_min,
+                    f"ragged k={k}")
+
+
+def test_query_end_to_end_against_oracle_from_scratch(mixture):
+    """Oracle built from its own FP64 projections; differences must be explained by
+    banded codes (which can move points between leaves) and are counted."""
+    w, cs = mixture
+    idx_or = oracle.build_index(cs.X, cs.A, cs.sid, w.L, w.K, w.Nr, w.max_leaf)
+    Q = w.queries()
+    Qd = torch.from_numpy(Q).cuda()
+    ids, dists, st = cs.idx.query(Qd, k=w.k, c=w.c, beta=w.beta, r_min=4.0, stats=True)
+    ids, st = ids.cpu().numpy(), st.cpu().numpy()
+    same = 0
+    for qi, q in enumerate(Q):
+        res = oracle.query(idx_or, cs.X, q, w.k, w.c, w.beta, 4.0, cs.eps)
+        hs, hm = set_hashes(res.cand)
+        if st[qi, 1] == res.n_cand and st[qi, 4] == hs and st[qi, 5] == hm:
+            same += 1
+            np.testing.assert_array_equal(ids[qi], res.ids)
+    print(f"[end-to-end] identical candidate sets {same}/{len(Q)}", flush=True)
+    codes_or = oracle.encode(cs.H, cs.B_or, w.L, w.K)
+    if np.array_equal(codes_or, cs.codes_gpu):
+        assert same == len(Q)
+
+
+def test_exact_knn_when_everything_is_admitted(mixture):
+    """beta = 1 and a first radius covering every point: S = D, output = exact kNN."""
+    w, cs = mixture
+    Q = w.queries(30)
+    ids, dists, st = cs.idx.query(torch.from_numpy(Q).cuda(), k=25, c=1.5, beta=1.0,
+                                  r_min=1e4, stats=True)
+    ex_ids, ex_d = oracle.knn_exact(cs.X, Q, 25)
+    np.testing.assert_array_equal(ids.cpu().numpy(), ex_ids)
+    np.testing.assert_allclose(dists.cpu().numpy(), ex_d, rtol=1e-6)
+    st = st.cpu().numpy()
+    assert np.all(st[:, pdet.QSTAT["ncand"]] == len(cs.X)) and np.all(st[:, 2] == 2)
+
+
+def test_batch_composition_does_not_change_results(mixture):
+    w, cs = mixture
+    Q = torch.from_numpy(w.queries()).cuda()
+    ids_b, d_b = cs.idx.query(Q, k=10, c=1.5, beta=0.05, r_min=3.0)
+    for sel in ([3], [17, 5], list(range(40, 47))):
+        ids_s, d_s = cs.idx.query(Q[sel].contiguous(), k=10, c=1.5, beta=0.05, r_min=3.0)
+        assert torch.equal(ids_s, ids_b[sel]) and torch.equal(d_s, d_b[sel])
+
+
+def test_per_query_k_and_c(mixture):
+    w, cs = mixture
+    Q = w.queries(24)
+    rng = np.random.default_rng(3)
+    ks = rng.choice([1, 10, 100], size=len(Q)).astype(np.int32)
+    cc = rng.choice([1.2, 1.5, 2.0], size=len(Q))
+    ids, dists = cs.idx.query(torch.from_numpy(Q).cuda(), k=0, beta=0.05, r_min=3.0,
+                              k_per_query=ks, c_per_query=cc)
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    idx_or = cs.stepwise_oracle()
+    off = 0
+    for qi, q in enumerate(Q):
+        res = oracle.query(idx_or, cs.X, q, int(ks[qi]), float(cc[qi]), 0.05, 3.0, cs.eps)
+        np.testing.assert_array_equal(ids[off:off + ks[qi]], res.ids)
+        off += ks[qi]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_low_precision_forms_recall_and_rescored_distances(mixture, prec):
+    w, cs = mixture
+    Q = torch.from_numpy(w.queries()).cuda()
+    i32, d32 = cs.idx.query(Q, k=10, c=1.5, beta=0.1, r_min=4.0)
+    il, dl = cs.idx.query(Q, k=10, c=1.5, beta=0.1, r_min=4.0, precision=prec, rescore=4)
+    i32, il, dl = i32.cpu().numpy(), il.cpu().numpy(), dl.cpu().numpy()
+    rec = np.mean([len(np.intersect1d(a, b)) / 10 for a, b in zip(il, i32)])
+    print(f"[{prec}] recall vs fp32 path = {rec:.4f}", flush=True)
+    assert rec >= 0.95
+    # distances of returned ids are exact (re-ranked from float32 data)
+    ex = np.sqrt(((cs.X[il].astype(np.float64) - w.queries()[:, None, :]) ** 2).sum(-1))
+    np.testing.assert_allclose(dl, ex, rtol=1e-6)
+
+
+def test_duplicates_make_a_fully_refined_leaf():
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((700, 16)).astype(np.float32)
+    X[100:400] = X[100]
+    A = wl.projection_matrix(16, 2, 8, seed=3)
+    cs = Case(X, A, np.arange(700), 8, 2, 64, 20)
+    check_codes(cs)
+    check_trees(cs)
+    counts = cs.idx.export(pdet.X_LEAF_COUNT, 0)
+    assert counts.max() >= 300
+    Q = rng.standard_normal((10, 16)).astype(np.float32)
+    run_and_compare(cs, cs.stepwise_oracle(), Q, 5, 1.5, 0.1, 0.3, "duplicates")
+
+
+def test_tiny_index_k_equals_n():
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((16, 3)).astype(np.float32)
+    A = wl.projection_matrix(3, 1, 1, seed=5)
+    cs = Case(X, A, np.arange(16), 1, 1, 2, 1)
+    check_trees(cs)
+    Q = rng.standard_normal((4, 3)).astype(np.float32)
+    ids, dists = cs.idx.query(torch.from_numpy(Q).cuda(), k=16, c=2.0, beta=0.0, r_min=0.01)
+    ex_ids, ex_d = oracle.knn_exact(X, Q, 16)
+    np.testing.assert_array_equal(ids.cpu().numpy(), ex_ids)
+
+
+def test_minimum_sample_one_point_per_region():
+    w = wl.SMALL_MIXTURE.scaled(n=2000, L=1)
+    X = w.data()
+    A = wl.projection_matrix(128, 1, 16, seed=8)
+    sid = wl.sample_ids(2000, 256, 9)              # m = floor(256/256) = 1
+    cs = Case(X, A, sid, 16, 1, 256, 32)
+    check_breakpoints(cs)
+    check_codes(cs)
+    check_trees(cs)
+    run_and_compare(cs, cs.stepwise_oracle(), w.queries(20), 5, 1.5, 0.1, 3.0, "m=1")

@@ -1,0 +1,78 @@
+"""Host-side checks of libpdet: it loads, exports every symbol pdet.h declares, and its
+host logic (parameter checks, eps from Eq. 2) is right. No GPU compute is called."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_24920_amd import pdet
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "pdet.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(pdet_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert set(syms) == set(pdet.EXPORTED), syms
+    L = pdet.lib()
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+@pytest.mark.parametrize("K,L", [(16, 4), (16, 1), (16, 16), (8, 2), (5, 3), (1, 1)])
+def test_epsilon_matches_eq2(K, L):
+    assert abs(pdet.epsilon(K, L) - oracle.epsilon(K, L)) < 1e-9 * oracle.epsilon(K, L)
+
+
+def test_epsilon_invalid():
+    assert math.isnan(pdet.epsilon(0, 4))
+
+
+def _params(**kw):
+    proj = np.zeros((8, 64), dtype=np.float32)
+    ids = np.arange(256, dtype=np.int64)
+    base = dict(K=16, L=4, Nr=256, max_leaf=128, proj=proj.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                sample_ids=ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_sample=256,
+                lowp_copies=0)
+    base.update(kw)
+    return pdet.BuildParams(**base), (proj, ids)
+
+
+@pytest.mark.parametrize("kw,n,d", [
+    (dict(K=17), 1000, 8), (dict(K=0), 1000, 8), (dict(L=0), 1000, 8), (dict(L=17), 1000, 8),
+    (dict(Nr=100), 1000, 8), (dict(Nr=512), 1000, 8), (dict(Nr=1), 1000, 8),
+    (dict(max_leaf=0), 1000, 8), (dict(n_sample=100), 1000, 8), (dict(n_sample=2000), 1000, 8),
+    (dict(lowp_copies=8), 1000, 8), ({}, 0, 8), ({}, 1000, 0), ({}, 1 << 31, 8),
+])
+def test_build_rejects_invalid_arguments_before_touching_the_device(kw, n, d):
+    p, keep = _params(**kw)
+    h = ctypes.c_void_p(1234)
+    st = pdet.lib().pdet_build(ctypes.c_void_p(4096), n, d, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == pdet.PDET_EINVAL
+    assert h.value is None
+    assert pdet.lib().pdet_last_error()
+
+
+def test_build_rejects_out_of_range_sample_ids():
+    p, keep = _params()
+    keep[1][7] = 5000
+    h = ctypes.c_void_p()
+    st = pdet.lib().pdet_build(ctypes.c_void_p(4096), 1000, 8, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == pdet.PDET_EINVAL and b"sample id" in pdet.lib().pdet_last_error()
+
+
+def test_null_handles_are_rejected():
+    q = pdet.QueryParams(10, 1.5, None, None, 0.1, 1.0, 0.0, 0, 4)
+    assert pdet.lib().pdet_query(None, None, 1, ctypes.byref(q), None, None, None, None) == pdet.PDET_EINVAL
+    assert pdet.lib().pdet_info(None, None) == pdet.PDET_EINVAL
+    assert pdet.lib().pdet_export(None, 0, 0, None, 0) == pdet.PDET_EINVAL
+    pdet.lib().pdet_free(None)
