@@ -67,11 +67,11 @@ typedef struct {
 } pdet_build_params;
 
 /*
- * Build an index over `data` (device, float32 [n][d] row-major, n < 2^31).
+ * Build an index over `data` (device, float32 [n][d] row-major, n < 2^28).
  * The data pointer is BORROWED: it must stay allocated and unchanged until
  * pdet_free(), because verification reads it. Everything derived from it
  * (breakpoints, codes, trees, low-precision copies) is owned by the index.
- * Errors: EINVAL for n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power
+ * Errors: EUNSUPPORTED for n >= 2^28; EINVAL for n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power
  * of two in [2,256], max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range;
  * ENOMEM/EDEVICE from the runtime. On error *out is NULL.
  * Synchronises `stream` once (to size the leaf tables).
@@ -170,6 +170,26 @@ pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void*
  */
 pdet_status pdet_project(const pdet_index* idx, const float* x, int64_t m, float* out,
                          void* stream);
+
+/*
+ * Kernel timing (HIP events on the call's stream). When switched on for the calling
+ * thread, pdet_build and pdet_query record the device time of each kernel family and
+ * pdet_get_timing returns the figures of the last build and the last query on this
+ * thread. Off by default; switching it on adds no synchronisation beyond the calls' own.
+ */
+typedef struct {
+  double build_sample_ms;   /* projection of the sampled points                        */
+  double build_sort_ms;     /* column sort and breakpoint pick                          */
+  double build_encode_ms;   /* projection + region encoding of all points               */
+  double build_tree_ms;     /* DE-Tree creation, leaf tables                            */
+  double build_lowp_ms;     /* low-precision copies                                     */
+  double query_project_ms;  /* query projection                                         */
+  double query_rho_ms;      /* leaf lower bounds -> first admitting round               */
+  double query_main_ms;     /* search, dedupe, verification, top-k                      */
+  int64_t query_main_launches;
+} pdet_timing;
+void pdet_set_timing(int32_t on);
+pdet_status pdet_get_timing(pdet_timing* out);
 
 /* eps = sqrt(chi2 upper exp(-1/L) quantile, K dof) from Eq. 2 / Lemma 3; NaN if invalid. */
 double pdet_epsilon(int32_t K, int32_t L);

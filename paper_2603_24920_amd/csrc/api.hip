@@ -65,6 +65,35 @@ double gamma_p(double a, double x) {
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+Timer& timer() {
+  static thread_local Timer t;
+  return t;
+}
+
+Span::Span(hipStream_t s, double* acc) : s_(s), acc_(acc) {
+  if (!timer().on || !acc) return;
+  PDET_HIP(hipEventCreate(&a_));
+  PDET_HIP(hipEventCreate(&b_));
+  PDET_HIP(hipEventRecord(a_, s_));
+}
+
+void Span::finish() {
+  if (!a_) return;
+  PDET_HIP(hipEventRecord(b_, s_));
+  PDET_HIP(hipEventSynchronize(b_));
+  float ms = 0.0f;
+  PDET_HIP(hipEventElapsedTime(&ms, a_, b_));
+  *acc_ += ms;
+  (void)hipEventDestroy(a_);
+  (void)hipEventDestroy(b_);
+  a_ = b_ = nullptr;
+}
+
+Span::~Span() {
+  if (a_) (void)hipEventDestroy(a_);
+  if (b_) (void)hipEventDestroy(b_);
+}
+
 // eps^2 is the upper alpha1 quantile of chi2(K), alpha1 = exp(-1/L) (Eq. 2, Lemma 3):
 // solve 1 - P(K/2, x/2) = alpha1 by bisection.
 double epsilon(int K, int L) {
@@ -81,10 +110,11 @@ double epsilon(int K, int L) {
 }  // namespace pdet
 
 int64_t pdet_index::device_bytes() const {
-  int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + perm.bytes + xbf16.bytes +
-              xfp8.bytes + xscale.bytes;
+  int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + perm.bytes + leafrow.bytes +
+              xbf16.bytes + xfp8.bytes + xscale.bytes;
   for (int i = 0; i < PDET_MAX_L; ++i)
-    b += leaf_start[i].bytes + leaf_count[i].bytes + leaf_hidx[i].bytes + box[i].bytes;
+    b += leaf_start[i].bytes + leaf_count[i].bytes + leaf_hidx[i].bytes + box[i].bytes +
+         gbox[i].bytes;
   return b;
 }
 
@@ -105,7 +135,8 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
   pdet_index* ix = nullptr;
   const pdet_status st = guarded([&] {
     PDET_REQUIRE(out && p && data, PDET_EINVAL, "NULL argument");
-    PDET_REQUIRE(n >= 1 && n < (int64_t(1) << 31), PDET_EINVAL, "n must be in [1, 2^31)");
+    PDET_REQUIRE(n >= 1, PDET_EINVAL, "n must be >= 1");
+    PDET_REQUIRE(n < (int64_t(1) << 28), PDET_EUNSUPPORTED, "n must be below 2^28");
     PDET_REQUIRE(d >= 1, PDET_EINVAL, "d must be >= 1");
     PDET_REQUIRE(p->K >= 1 && p->K <= PDET_MAX_K, PDET_EINVAL, "K must be in [1, 16]");
     PDET_REQUIRE(p->L >= 1 && p->L <= PDET_MAX_L, PDET_EINVAL, "L must be in [1, 16]");
@@ -144,23 +175,47 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     int64_t npad = 1;
     while (npad < p->n_sample) npad <<= 1;
     DevBuf ps((size_t)LK * npad * 4);
-    fill_f32(ps.as<float>(), (int64_t)LK * npad, INFINITY, s);
-    project_sample(*ix, sid.as<int64_t>(), p->n_sample, ps.as<float>(), npad, s);
-    sort_columns(ps.as<float>(), LK, npad, s);
+    pdet_timing& tm = timer().t;
+    if (timer().on) {
+      tm.build_sample_ms = tm.build_sort_ms = tm.build_encode_ms = 0.0;
+      tm.build_tree_ms = tm.build_lowp_ms = 0.0;
+    }
     ix->B.alloc((size_t)LK * (ix->Nr + 1) * 4);
-    pick_breakpoints(ps.as<float>(), LK, npad, p->n_sample, ix->Nr, ix->B.as<float>(), s);
+    {
+      Span sp(s, &tm.build_sample_ms);
+      fill_f32(ps.as<float>(), (int64_t)LK * npad, INFINITY, s);
+      project_sample(*ix, sid.as<int64_t>(), p->n_sample, ps.as<float>(), npad, s);
+      sp.finish();
+    }
+    {
+      Span sp(s, &tm.build_sort_ms);
+      sort_columns(ps.as<float>(), LK, npad, s);
+      pick_breakpoints(ps.as<float>(), LK, npad, p->n_sample, ix->Nr, ix->B.as<float>(), s);
+      sp.finish();
+    }
 
     // encode every point; column extremes give the outer breakpoints
     ix->colmm.alloc((size_t)2 * LK * 4);
     PDET_HIP(hipMemsetAsync(ix->colmm.p, 0xff, (size_t)LK * 4, s));
     PDET_HIP(hipMemsetAsync(ix->colmm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));
     ix->codes.alloc((size_t)ix->L * n * KP);
-    encode_points(*ix, s);
-    set_outer_breakpoints(ix->B.as<float>(), ix->colmm.as<uint32_t>(), LK, ix->Nr, s);
-
     ix->perm.alloc((size_t)ix->L * n * 4);
-    build_trees(*ix, s);
-    build_lowp_copies(*ix, s);
+    {
+      Span sp(s, &tm.build_encode_ms);
+      encode_points(*ix, s);
+      set_outer_breakpoints(ix->B.as<float>(), ix->colmm.as<uint32_t>(), LK, ix->Nr, s);
+      sp.finish();
+    }
+    {
+      Span sp(s, &tm.build_tree_ms);
+      build_trees(*ix, s);
+      sp.finish();
+    }
+    {
+      Span sp(s, &tm.build_lowp_ms);
+      build_lowp_copies(*ix, s);
+      sp.finish();
+    }
     PDET_HIP(hipStreamSynchronize(s));
     *out = ix;
     ix = nullptr;
@@ -212,6 +267,15 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
     qc.dists = dists;
     qc.qstats = qstats;
     run_query(*idx, qc, static_cast<hipStream_t>(stream));
+  });
+}
+
+void pdet_set_timing(int32_t on) { timer().on = on != 0; }
+
+pdet_status pdet_get_timing(pdet_timing* out) {
+  return guarded([&] {
+    PDET_REQUIRE(out, PDET_EINVAL, "NULL argument");
+    *out = timer().t;
   });
 }
 

@@ -3,9 +3,20 @@
 
 #include <algorithm>
 #include <cmath>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
+
+namespace pdet {
+// Query scratch, kept by the index and reused across calls (see run_query).
+struct QueryWorkspace {
+  DevBuf rho, admb, adm2, t2, crr, qp, dk, dc, dT, doff;
+  int64_t nslots = 0, nslots_max = 0, nq_cap = 0;
+  size_t bytes() const { return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes; }
+};
+}  // namespace pdet
 
 struct pdet_index {
   int64_t n = 0, n_sample = 0;
@@ -20,11 +31,14 @@ struct pdet_index {
   pdet::DevBuf colmm;              // uint32 [2][L*K] ordered min / max of every column
   pdet::DevBuf codes;              // uint8 [L][n][KP]
   pdet::DevBuf perm;               // int32 [L][n]
+  pdet::DevBuf leafrow;            // int32 [L][n][L]: for the point at perm position p of tree
+                                   // i, its leaf ordinal in every tree (read along leaves)
   // per tree, leaves in depth-first order
   pdet::DevBuf leaf_start[PDET_MAX_L];   // int32 [nl]
   pdet::DevBuf leaf_count[PDET_MAX_L];   // int32 [nl]
   pdet::DevBuf leaf_hidx[PDET_MAX_L];    // uint16 [nl][KP]
   pdet::DevBuf box[PDET_MAX_L];          // float32 [2][K][nl]: lower / upper edge per dim
+  pdet::DevBuf gbox[PDET_MAX_L];         // float32 [2][K][ceil(nl/16)]: union box of 16 leaves
   int64_t nl[PDET_MAX_L] = {};
   int64_t nl_max = 0;
   // low-precision copies for verification
@@ -33,11 +47,59 @@ struct pdet_index {
   pdet::DevBuf xfp8;               // fp8 e4m3 [n][dpad]
   pdet::DevBuf xscale;             // float32 [n]: fp8 row scale (power of two)
 
+  // query workspaces: one per concurrent pdet_query call
+  mutable std::mutex ws_mu;
+  mutable std::vector<std::unique_ptr<pdet::QueryWorkspace>> ws_free;
+
   int64_t device_bytes() const;
 };
 
 namespace pdet {
+// Takes a workspace from the index's pool for the duration of one call.
+class WorkspaceLease {
+ public:
+  explicit WorkspaceLease(const pdet_index& ix) : ix_(ix) {
+    std::lock_guard<std::mutex> g(ix_.ws_mu);
+    if (!ix_.ws_free.empty()) {
+      ws_ = std::move(ix_.ws_free.back());
+      ix_.ws_free.pop_back();
+    } else {
+      ws_ = std::make_unique<QueryWorkspace>();
+    }
+  }
+  ~WorkspaceLease() {
+    std::lock_guard<std::mutex> g(ix_.ws_mu);
+    ix_.ws_free.push_back(std::move(ws_));
+  }
+  QueryWorkspace& get() { return *ws_; }
+ private:
+  const pdet_index& ix_;
+  std::unique_ptr<QueryWorkspace> ws_;
+};
+}  // namespace pdet
+
+namespace pdet {
 using Index = pdet_index;
+
+// Per-thread kernel timing (see pdet_set_timing).
+struct Timer {
+  bool on = false;
+  pdet_timing t{};
+};
+Timer& timer();
+
+// Records HIP events around a region on stream `s` when timing is on; adds the
+// elapsed milliseconds to *acc at finish() (which synchronises the end event).
+class Span {
+ public:
+  Span(hipStream_t s, double* acc);
+  ~Span();
+  void finish();
+ private:
+  hipStream_t s_;
+  double* acc_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
 
 // project.hip
 std::vector<float> pad_projection(const float* proj, int d, int L, int K);

@@ -5,17 +5,21 @@
 // Kernels:
 //  q_setup  per query: radius ladder r_rho = r_min*c^rho, thresholds (eps*r_rho)^2
 //           and c*r_rho, computed with the same double operations as the definition.
-//  q_rho    batched over (leaf block, tree, query tile): squared lower bound of every
-//           leaf box to q' and the first round whose threshold admits it (uint8,
-//           255 = never). Leaf boxes are read once per query tile.
-//  q_main   one workgroup per query: rounds outermost, trees in order; per (round,
-//           tree) the admitted leaves are compacted; if stop rule A may fire inside
-//           the step, the exact number of new points per leaf is counted and a
-//           weighted radix select over the (LB^2, leaf ordinal) keys finds the leaf
-//           at which |S| first reaches T; admitted points are deduplicated with a
-//           per-query bitmap (atomic test-and-set), verified by exact distance and
-//           offered to a top-k list in LDS; stop rule B checks the k-th distance
-//           against c*r after each round.
+//  q_rho    batched over (leaf block, tree, query tile): the first round whose threshold
+//           admits each leaf (its squared lower bound to q' <= (eps r_rho)^2), for rounds
+//           up to RCAP. Groups of 16 consecutive leaves are tested first with their union
+//           box (a lower bound of every member's bound, as a subtree prunes in the
+//           range query); a pruned group and any leaf beyond RCAP get the mark RCAP+1,
+//           refined exactly by q_main if a query ever reaches that round.
+//  q_main   one workgroup per query, one pass per round over the admitted leaves of all
+//           trees: an admitted point is new iff none of its leaves in the other trees was
+//           admitted earlier in the (round, tree) order (closed form of the candidate
+//           union, read from leaf_of and the round indices: no per-query state to
+//           clear). When stop rule A can fire in a round, exact new-point counts per
+//           leaf give the tree where |S| reaches T, and a weighted radix select over that
+//           tree's (LB^2, leaf ordinal) keys gives the leaf; trees before it are admitted
+//           whole. New points are verified by exact distance and offered to a top-k list
+//           in LDS; stop rule B checks the k-th distance against c*r after each round.
 #include "devutil.h"
 #include "internal.h"
 
@@ -24,8 +28,12 @@ namespace {
 
 constexpr int QM = 256;          // threads of q_main
 constexpr int CB = 512;          // top-k candidate buffer
-constexpr int QT = 16;           // queries per q_rho block
+constexpr int QT = 64;           // queries per q_rho block (group tests in sub-tiles of 16)
 constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
+constexpr int GL = 16;           // leaves per pruning group
+constexpr int RCAP = 4;          // rounds resolved by q_rho
+constexpr uint8_t MARK = RCAP + 1;
+constexpr int TREE_SHIFT = 28;   // list entries pack (tree << 28) | leaf
 
 struct QArgs {
   int64_t n;
@@ -38,7 +46,9 @@ struct QArgs {
   const int32_t* lstart[PDET_MAX_L];
   const int32_t* lcount[PDET_MAX_L];
   const float* box[PDET_MAX_L];
+  const float* gbox[PDET_MAX_L];
   int64_t nl[PDET_MAX_L];
+  int64_t ng[PDET_MAX_L];
   int64_t nlpad;
   const float* Q;
   const float* qp;           // [nq][L*K]
@@ -49,13 +59,13 @@ struct QArgs {
   const float* t2;           // [slots][NRHO]
   const double* crr;         // [slots][NRHO]
   uint8_t* rho;              // [slots][L][nlpad]
-  uint32_t* bitmap;          // [slots][nwords]
-  int64_t nwords;
+  const int32_t* leafrow;    // [L][n][L]
   uint32_t* adm_leaf;        // [slots][admcap]
   uint32_t* adm_w;
   float* adm_lb;
   uint32_t* adm2_leaf;       // [slots][admcap + 1]
   uint32_t* adm2_pre;
+  int32_t* adm_start;
   int64_t admcap;
   int64_t* ids;
   float* dists;
@@ -100,12 +110,12 @@ __device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, con
 
 __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   __shared__ float sq[QT][PDET_MAX_K];
-  __shared__ float st[QT][NRHO];
+  __shared__ float st[QT][RCAP + 1];
   const int tree = blockIdx.y;
   const int slot0 = blockIdx.z * QT;
-  const int64_t nl = a.nl[tree];
-  for (int e = threadIdx.x; e < QT * NRHO; e += blockDim.x) {
-    const int qi = e / NRHO, r = e % NRHO;
+  const int64_t nl = a.nl[tree], ng = a.ng[tree];
+  for (int e = threadIdx.x; e < QT * (RCAP + 1); e += blockDim.x) {
+    const int qi = e / (RCAP + 1), r = e % (RCAP + 1);
     st[qi][r] = (slot0 + qi < a.nslots) ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
   }
   for (int e = threadIdx.x; e < QT * a.K; e += blockDim.x) {
@@ -116,6 +126,26 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   }
   __syncthreads();
   const int64_t leaf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = leaf / GL;
+  const int sl = threadIdx.x & 15;
+  // lane sl of the 16 lanes sharing group g tests that group against query 16*sub + sl
+  uint64_t open_mask = 0;
+  for (int sub = 0; sub < QT / 16; ++sub) {
+    const int qi = sub * 16 + sl;
+    bool open = false;
+    if (g < ng && slot0 + qi < a.nslots) {
+      const float* gb = a.gbox[tree];
+      float acc = 0.0f;
+      for (int j = 0; j < a.K; ++j) {
+        const float lo = gb[(int64_t)j * ng + g], hi = gb[(int64_t)(a.K + j) * ng + g];
+        const float gap = fmaxf(0.0f, fmaxf(lo - sq[qi][j], sq[qi][j] - hi));
+        acc = __fmaf_rn(gap, gap, acc);
+      }
+      open = acc <= st[qi][RCAP];
+    }
+    const uint64_t mask = __ballot(open);
+    open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
+  }
   if (leaf >= nl) return;
   float lo[PDET_MAX_K], hi[PDET_MAX_K];
   const float* box = a.box[tree];
@@ -127,19 +157,22 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   for (int qi = 0; qi < QT; ++qi) {
     const int slot = slot0 + qi;
     if (slot >= a.nslots) break;
-    float acc = 0.0f;
+    uint8_t r = MARK;
+    if ((open_mask >> qi) & 1ull) {
+      float acc = 0.0f;
 #pragma unroll
-    for (int j = 0; j < PDET_MAX_K; ++j) {
-      if (j < a.K) {
-        const float g = fmaxf(0.0f, fmaxf(lo[j] - sq[qi][j], sq[qi][j] - hi[j]));
-        acc = __fmaf_rn(g, g, acc);
+      for (int j = 0; j < PDET_MAX_K; ++j) {
+        if (j < a.K) {
+          const float gap = fmaxf(0.0f, fmaxf(lo[j] - sq[qi][j], sq[qi][j] - hi[j]));
+          acc = __fmaf_rn(gap, gap, acc);
+        }
       }
-    }
-    int pos = 0;   // first round whose threshold admits the leaf = #thresholds < lb2
+      int c = 0;   // #thresholds < lb2 among rounds 0..RCAP; RCAP+1 is the mark
 #pragma unroll
-    for (int s = NRHO / 2; s > 0; s >>= 1)
-      if (st[qi][pos + s - 1] < acc) pos += s;
-    a.rho[((int64_t)slot * a.L + tree) * a.nlpad + leaf] = (uint8_t)pos;
+      for (int rr = 0; rr <= RCAP; ++rr) c += (st[qi][rr] < acc) ? 1 : 0;
+      r = (uint8_t)c;
+    }
+    a.rho[((int64_t)slot * a.L + tree) * a.nlpad + leaf] = r;
   }
 }
 
@@ -240,6 +273,20 @@ __device__ void sort_pairs(double* ld, int32_t* li, int len) {
   }
 }
 
+// Closed form of the candidate union: before step (rho, i) a point is in S iff its leaf in
+// some tree i2 < i is admitted in a round <= rho, or its leaf in some tree i2 > i in a round
+// < rho (every earlier step was admitted whole, or the query would have stopped). `lr` is
+// the point's row of leaf ordinals, `rr` the query's round-index table [L][nlpad].
+__device__ inline bool is_new(const QArgs& a, const uint8_t* rr, const int32_t* lr, int i,
+                              int rho) {
+  for (int i2 = 0; i2 < a.L; ++i2) {
+    if (i2 == i) continue;
+    const int r2 = rr[(int64_t)i2 * a.nlpad + lr[i2]];
+    if (i2 < i ? (r2 <= rho) : (r2 < rho)) return false;
+  }
+  return true;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   extern __shared__ __align__(16) unsigned char sm[];
@@ -251,15 +298,18 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
 
   __shared__ uint32_t w_pre[QM + 1];
   __shared__ int32_t w_start[QM];
+  __shared__ uint8_t w_tree[QM];
   __shared__ int32_t idbuf[QM];
   __shared__ uint32_t sh_scan[QM / 64 + 1];
   __shared__ uint32_t hist[256];
+  __shared__ float st2[NRHO];
+  __shared__ uint32_t ent_off[PDET_MAX_L + 1];
   __shared__ uint32_t s_m, s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix;
   __shared__ unsigned long long s_pts, s_cut;
 
   const int slot = blockIdx.x;
   const int64_t q = a.q0 + slot;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = tid & 15, grp = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, l16 = tid & 15, grp = tid >> 4;
   const int k = a.qk[q];
   const int64_t T = a.qT[q];
   const int KL = (PREC == PDET_FP32) ? k : k * a.rescore;
@@ -268,10 +318,9 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   for (int e = tid; e < a.NM; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
   for (int t = tid; t < dq; t += QM) qv[t] = (t < a.d) ? a.Q[q * a.d + t] : 0.0f;
   for (int t = tid; t < LK; t += QM) qps[t] = a.qp[q * LK + t];
-  uint32_t* bm = a.bitmap + (int64_t)slot * a.nwords;
-  for (int64_t w = tid; w < a.nwords; w += QM) bm[w] = 0u;
+  for (int t = tid; t < NRHO; t += QM) st2[t] = a.t2[(int64_t)slot * NRHO + t];
+  uint8_t* rq = a.rho + (int64_t)slot * a.L * a.nlpad;
   if (tid == 0) { s_ncb = 0; s_hsum = 0; s_hmix = 0; }
-  __threadfence_block();
   __syncthreads();
 
   uint32_t* adm = a.adm_leaf + (int64_t)slot * a.admcap;
@@ -279,6 +328,7 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   float* admlb = a.adm_lb + (int64_t)slot * a.admcap;
   uint32_t* adm2 = a.adm2_leaf + (int64_t)slot * (a.admcap + 1);
   uint32_t* pre2 = a.adm2_pre + (int64_t)slot * (a.admcap + 1);
+  int32_t* ast = a.adm_start + (int64_t)slot * (a.admcap + 1);
 
   int64_t nS = 0, leaves = 0;
   uint32_t hsum = 0, hmix = 0;
@@ -293,16 +343,115 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
     __syncthreads();
   };
 
+  // Walk the points of list entries [e_lo, e_hi), 256 at a time. A point's leaf is found
+  // by a binary search in an LDS window of the prefix list. counting: add every new point
+  // to its leaf's count admw[]; otherwise verify the new points and offer them to the top-k.
+  // Returns the number of new points (uniform across the workgroup).
+  auto traverse = [&](bool counting, int rho, uint32_t e_lo, uint32_t e_hi) -> uint32_t {
+    uint32_t newc = 0;
+    const uint32_t P0 = pre2[e_lo], P1 = pre2[e_hi];
+    if (tid == 0) s_ef = e_lo;
+    __syncthreads();
+    for (uint32_t base = P0; base < P1; base += QM) {
+      const uint32_t ef = s_ef;
+      {
+        const uint32_t e = ef + tid;
+        w_pre[tid] = (e <= e_hi) ? pre2[e] : 0xffffffffu;
+        if (e < e_hi) {
+          w_tree[tid] = (uint8_t)(adm2[e] >> TREE_SHIFT);
+          w_start[tid] = ast[e];
+        }
+        if (tid == 0) {
+          w_pre[QM] = (ef + QM <= e_hi) ? pre2[ef + QM] : 0xffffffffu;
+          s_nb = 0;
+        }
+      }
+      __syncthreads();
+      const uint32_t p = base + tid;
+      bool nw = false;
+      int32_t id = 0;
+      int lo = 0;
+      if (p < P1) {
+        int hi = QM;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (w_pre[mid] <= p) lo = mid; else hi = mid;
+        }
+        const int tr = w_tree[lo];
+        const int64_t pos = (int64_t)tr * a.n + w_start[lo] + (p - w_pre[lo]);
+        id = a.perm[pos];
+        nw = is_new(a, rq, a.leafrow + pos * a.L, tr, rho);
+      }
+      const uint64_t mask = __ballot(nw);
+      uint32_t wbase = 0;
+      if (lane == 0 && mask) wbase = atomicAdd(&s_nb, (uint32_t)__popcll(mask));
+      wbase = __shfl(wbase, 0);
+      if (nw) {
+        if (counting) {
+          atomicAdd(&admw[ef + lo], 1u);
+        } else {
+          idbuf[wbase + lanes_below_mask(mask)] = id;
+          hsum += (uint32_t)id;
+          hmix += mix32((uint32_t)id);
+        }
+      }
+      __syncthreads();
+      const uint32_t nb = s_nb;
+      newc += nb;
+      if (tid == 0) {
+        // first window entry of the next chunk: last e with pre <= base + QM
+        const uint32_t nbase = base + QM;
+        int l2 = 0, h2 = QM + 1;
+        while (h2 - l2 > 1) {
+          const int mid = (l2 + h2) >> 1;
+          if (w_pre[mid] <= nbase) l2 = mid; else h2 = mid;
+        }
+        s_ef = ef + l2;
+      }
+      if (!counting) {
+        for (uint32_t c0 = 0; c0 < nb; c0 += QM / 16) {
+          const uint32_t c = c0 + grp;
+          const bool valid = c < nb;
+          const int32_t cid = valid ? idbuf[c] : 0;
+          const double dd = cand_dist<PREC>(a, cid, qv, l16);
+          if (valid && l16 == 0 && lex_less(dd, cid, ld[KL - 1], li[KL - 1])) {
+            const uint32_t pos = atomicAdd(&s_ncb, 1u);
+            ld[KL + pos] = dd;
+            li[KL + pos] = cid;
+          }
+        }
+      }
+      __syncthreads();
+      if (!counting && s_ncb > (uint32_t)(CB - QM)) merge();
+    }
+    return newc;
+  };
+
   for (int rho = 0; rho < NRHO - 1 && stop < 0; ++rho) {
     rounds = rho + 1;
-    for (int i = 0; i < a.L; ++i) {
-      const int64_t nl = a.nl[i];
-      const int32_t* lst = a.lstart[i];
-      const int32_t* lct = a.lcount[i];
-      const int32_t* perm = a.perm + (int64_t)i * a.n;
-      if (tid == 0) { s_m = 0; s_pts = 0; }
+    if (rho == RCAP + 1) {
+      // exact first rounds of the leaves q_rho left open
+      for (int i = 0; i < a.L; ++i) {
+        uint8_t* rr = rq + (int64_t)i * a.nlpad;
+        for (int64_t leaf = tid; leaf < a.nl[i]; leaf += QM) {
+          if (rr[leaf] != MARK) continue;
+          const float lb2 = leaf_lb2(a.box[i], a.nl[i], leaf, qps + i * a.K, a.K);
+          int pos = 0;
+#pragma unroll
+          for (int sft = NRHO / 2; sft > 0; sft >>= 1)
+            if (st2[pos + sft - 1] < lb2) pos += sft;
+          rr[leaf] = (uint8_t)pos;
+        }
+      }
       __syncthreads();
-      const uint8_t* rr = a.rho + ((int64_t)slot * a.L + i) * a.nlpad;
+    }
+    // admitted leaves of every tree in this round, in tree order
+    if (tid == 0) { s_m = 0; s_pts = 0; ent_off[0] = 0; }
+    __syncthreads();
+    for (int i = 0; i < a.L; ++i) {
+      const uint8_t* rr = rq + (int64_t)i * a.nlpad;
+      const int64_t nl = a.nl[i];
+      const int32_t* lct = a.lcount[i];
       for (int64_t b = (int64_t)tid * 16; b < nl; b += QM * 16) {
         const uint4 v = *reinterpret_cast<const uint4*>(rr + b);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
@@ -310,159 +459,136 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
         for (int e = 0; e < 16; ++e) {
           if (((w[e >> 2] >> (8 * (e & 3))) & 255u) == (uint32_t)rho && b + e < nl) {
             const uint32_t pos = atomicAdd(&s_m, 1u);
-            adm[pos] = (uint32_t)(b + e);
+            adm[pos] = ((uint32_t)i << TREE_SHIFT) | (uint32_t)(b + e);
             atomicAdd(&s_pts, (unsigned long long)lct[b + e]);
           }
         }
       }
       __syncthreads();
-      const uint32_t m = s_m;
-      const int64_t pts = (int64_t)s_pts;
-      __syncthreads();   // all threads hold m before thread 0 resets the counters again
-      if (m == 0) continue;
+      if (tid == 0) ent_off[i + 1] = s_m;   // tree i's entries are [ent_off[i], ent_off[i+1])
+      __syncthreads();                     // recorded before any thread appends tree i+1
+    }
+    __syncthreads();
+    const uint32_t m = s_m;
+    const int64_t pts = (int64_t)s_pts;
 
-      unsigned long long cut = ~0ull;
-      if (nS + pts >= T) {
-        // exact new-point counts: stop rule A may fire inside this step
-        if (tid == 0) s_newtot = 0;
-        __syncthreads();
-        for (uint32_t e = wave; e < m; e += QM / 64) {
-          const uint32_t leaf = adm[e];
-          const int32_t st = lst[leaf], cnt = lct[leaf];
-          uint32_t cn = 0;
-          for (int p0 = 0; p0 < cnt; p0 += 64) {
-            const int p = p0 + lane;
-            bool nw = false;
-            if (p < cnt) {
-              const int32_t id = perm[st + p];
-              const uint32_t wv = __hip_atomic_load(&bm[id >> 5], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-              nw = !((wv >> (id & 31)) & 1u);
-            }
-            cn += (uint32_t)__popcll(__ballot(nw));
-          }
-          if (lane == 0) {
-            admw[e] = cn;
-            admlb[e] = leaf_lb2(a.box[i], nl, leaf, qps + i * a.K, a.K);
-            atomicAdd(&s_newtot, cn);
-          }
+    if (m > 0) {
+      // prefix list of the leaf sizes (with their perm start positions)
+      uint32_t P = 0;
+      for (uint32_t b = 0; b < m; b += QM) {
+        const uint32_t e = b + tid;
+        uint32_t cnt = 0, en = 0;
+        int32_t st0 = 0;
+        if (e < m) {
+          en = adm[e];
+          const int tr = (int)(en >> TREE_SHIFT);
+          const uint32_t leaf = en & ((1u << TREE_SHIFT) - 1);
+          cnt = (uint32_t)a.lcount[tr][leaf];
+          st0 = a.lstart[tr][leaf];
         }
-        __syncthreads();
-        if (nS + (int64_t)s_newtot >= T) {
-          // weighted radix select: smallest key whose inclusive weight prefix reaches R
+        uint32_t tot;
+        const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &tot);
+        if (e < m) { adm2[e] = en; pre2[e] = P + pre; ast[e] = st0; }
+        P += tot;
+      }
+      if (tid == 0) pre2[m] = P;
+      __syncthreads();
+
+      if (nS + pts < T) {
+        // stop rule A cannot fire in this round: admit every tree's leaves in one pass
+        leaves += m;
+        nS += traverse(false, rho, 0, m);
+      } else {
+        // trees in order; the exact count decides the tree (and leaf) where |S| reaches T
+        for (int i = 0; i < a.L && stop < 0; ++i) {
+          const uint32_t e0 = ent_off[i], e1 = ent_off[i + 1];
+          if (e0 == e1) continue;
+          const int64_t pts_i = (int64_t)pre2[e1] - (int64_t)pre2[e0];
+          if (nS + pts_i < T) {
+            leaves += e1 - e0;
+            nS += traverse(false, rho, e0, e1);
+            continue;
+          }
+          for (uint32_t e = e0 + tid; e < e1; e += QM) {
+            admw[e] = 0;
+            admlb[e] = leaf_lb2(a.box[i], a.nl[i], adm2[e] & ((1u << TREE_SHIFT) - 1),
+                                qps + i * a.K, a.K);
+          }
+          __syncthreads();
+          const uint32_t new_i = traverse(true, rho, e0, e1);
+          if (nS + (int64_t)new_i < T) {
+            leaves += e1 - e0;
+            nS += traverse(false, rho, e0, e1);
+            continue;
+          }
+          // weighted radix select over this tree's keys (LB^2 bits, leaf ordinal): the
+          // smallest key whose inclusive weight prefix reaches R = T - |S|
           unsigned long long prefix = 0;
           uint32_t R = (uint32_t)(T - nS);
           for (int pass = 0; pass < 8; ++pass) {
             const int shift = 56 - 8 * pass;
             hist[tid] = 0;
             __syncthreads();
-            for (uint32_t e = tid; e < m; e += QM) {
+            for (uint32_t e = e0 + tid; e < e1; e += QM) {
               const unsigned long long key =
-                  ((unsigned long long)__float_as_uint(admlb[e]) << 32) | adm[e];
-              if (pass == 0 || (key >> (shift + 8)) == prefix)
-                atomicAdd(&hist[(key >> shift) & 255], admw[e]);
+                  ((unsigned long long)__float_as_uint(admlb[e]) << 32) |
+                  (adm2[e] & ((1u << TREE_SHIFT) - 1));
+              if (pass == 0 || (key >> (shift + 8)) == prefix) {
+                const uint32_t wgt =
+                    __hip_atomic_load(&admw[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (wgt) atomicAdd(&hist[(key >> shift) & 255], wgt);
+              }
             }
             __syncthreads();
-            if (tid == 0) {
-              uint32_t acc = 0;
-              int dg = 0;
-              for (; dg < 255; ++dg) {
-                if (acc + hist[dg] >= R) break;
-                acc += hist[dg];
-              }
-              s_cut = (prefix << 8) | (unsigned long long)dg;
-              s_newtot = R - acc;
+            const uint32_t h = hist[tid];
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<QM>(h, sh_scan, &tot);
+            if (ex < R && ex + h >= R) {
+              s_cut = (prefix << 8) | (unsigned long long)tid;
+              s_newtot = R - ex;
             }
             __syncthreads();
             prefix = s_cut;
             R = s_newtot;
             __syncthreads();
           }
-          cut = prefix;
+          const unsigned long long cut = prefix;
+          // keep this tree's leaves up to the cut (in place: writes never pass the read
+          // position); the list ends there
+          const uint32_t P0 = pre2[e0];
+          uint32_t nm = 0, nP = 0;
+          for (uint32_t b = e0; b < e1; b += QM) {
+            const uint32_t e = b + tid;
+            bool inc = false;
+            uint32_t cnt = 0, en = 0;
+            int32_t st0 = 0;
+            if (e < e1) {
+              en = adm2[e];
+              st0 = ast[e];
+              const uint32_t leaf = en & ((1u << TREE_SHIFT) - 1);
+              inc = ((((unsigned long long)__float_as_uint(admlb[e])) << 32) | leaf) <= cut;
+              if (inc) cnt = (uint32_t)a.lcount[i][leaf];
+            }
+            uint32_t t1, t2;
+            const uint32_t pos = block_excl_scan<QM>(inc ? 1u : 0u, sh_scan, &t1);
+            const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &t2);
+            if (inc) {
+              adm2[e0 + nm + pos] = en;
+              ast[e0 + nm + pos] = st0;
+              pre2[e0 + nm + pos] = P0 + nP + pre;
+            }
+            nm += t1;
+            nP += t2;
+          }
+          if (tid == 0) pre2[e0 + nm] = P0 + nP;
+          __syncthreads();
+          leaves += nm;
+          nS += traverse(false, rho, e0, e0 + nm);
+          stop = 1;
         }
       }
-
-      // included leaves, compacted, with exclusive prefix of their sizes
-      uint32_t m2 = 0, P = 0;
-      for (uint32_t b = 0; b < m; b += QM) {
-        const uint32_t e = b + tid;
-        bool inc = false;
-        uint32_t cnt = 0, leaf = 0;
-        if (e < m) {
-          leaf = adm[e];
-          inc = (cut == ~0ull) ||
-                ((((unsigned long long)__float_as_uint(admlb[e]) << 32) | leaf) <= cut);
-          if (inc) cnt = (uint32_t)lct[leaf];
-        }
-        uint32_t t1, t2;
-        const uint32_t pos = block_excl_scan<QM>(inc ? 1u : 0u, sh_scan, &t1);
-        const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &t2);
-        if (inc) { adm2[m2 + pos] = leaf; pre2[m2 + pos] = P + pre; }
-        m2 += t1;
-        P += t2;
-      }
-      if (tid == 0) { pre2[m2] = P; s_ef = 0; }
-      leaves += m2;
-      __syncthreads();
-
-      int64_t newS = 0;
-      for (uint32_t base = 0; base < P; base += QM) {
-        const uint32_t ef = s_ef;
-        {
-          const uint32_t e = ef + tid;
-          w_pre[tid] = (e <= m2) ? pre2[e] : 0xffffffffu;
-          w_start[tid] = (e < m2) ? lst[adm2[e]] : 0;
-          if (tid == 0) w_pre[QM] = (ef + QM <= m2) ? pre2[ef + QM] : 0xffffffffu;
-          if (tid == 0) s_nb = 0;
-        }
-        __syncthreads();
-        const uint32_t p = base + tid;
-        if (p < P) {
-          int lo = 0, hi = QM;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (w_pre[mid] <= p) lo = mid; else hi = mid;
-          }
-          const int32_t id = perm[w_start[lo] + (p - w_pre[lo])];
-          const uint32_t bit = 1u << (id & 31);
-          const uint32_t old = atomicOr(&bm[id >> 5], bit);
-          if (!(old & bit)) {
-            idbuf[atomicAdd(&s_nb, 1u)] = id;
-            hsum += (uint32_t)id;
-            hmix += mix32((uint32_t)id);
-          }
-        }
-        __syncthreads();
-        const uint32_t nb = s_nb;
-        newS += nb;
-        if (tid == 0) {
-          // first window entry of the next chunk: last e with pre <= base + QM
-          const uint32_t nbase = base + QM;
-          int lo = 0, hi = QM + 1;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (w_pre[mid] <= nbase) lo = mid; else hi = mid;
-          }
-          s_ef = ef + lo;
-        }
-        for (uint32_t c0 = 0; c0 < nb; c0 += QM / 16) {
-          const uint32_t c = c0 + grp;
-          const bool valid = c < nb;
-          const int32_t id = valid ? idbuf[c] : 0;
-          const double dd = cand_dist<PREC>(a, id, qv, l16);
-          if (valid && l16 == 0 && lex_less(dd, id, ld[KL - 1], li[KL - 1])) {
-            const uint32_t pos = atomicAdd(&s_ncb, 1u);
-            ld[KL + pos] = dd;
-            li[KL + pos] = id;
-          }
-        }
-        __syncthreads();
-        if (s_ncb > (uint32_t)(CB - QM)) merge();
-      }
-      nS += newS;
-      if (cut != ~0ull) { stop = 1; break; }
+      if (stop >= 0) break;
     }
-    if (stop >= 0) break;
     if (s_ncb > 0) merge();
     if (nS >= k && ld[k - 1] <= a.crr[(int64_t)slot * NRHO + rho]) stop = 2;
     __syncthreads();
@@ -524,29 +650,57 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
     acc += k;
     maxKL = std::max(maxKL, qc.precision == PDET_FP32 ? k : k * qc.rescore);
   }
-  DevBuf dk((size_t)nq * 4), dc((size_t)nq * 8), dT((size_t)nq * 8), doff((size_t)nq * 8);
-  PDET_HIP(hipMemcpyAsync(dk.p, qc.k_host, nq * 4, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(dc.p, qc.c_host, nq * 8, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(dT.p, T.data(), nq * 8, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(doff.p, off.data(), nq * 8, hipMemcpyHostToDevice, s));
 
-  DevBuf qp((size_t)nq * LK * 4);
-  project_points(ix, qc.Q, nq, qp.as<float>(), s);
-
-  // scratch per query slot; the number of slots is bounded by device memory
+  // scratch per query slot, reused across calls; the number of slots is bounded by memory
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
-  const int64_t nwords = (ix.n + 31) / 32;
-  const int64_t admcap = std::max<int64_t>(ix.nl_max, 1);
-  const size_t per_slot = (size_t)ix.L * nlpad + (size_t)nwords * 4 + (size_t)admcap * 12 +
-                          (size_t)(admcap + 1) * 8 + NRHO * 12;
-  size_t freeb = 0, totalb = 0;
-  PDET_HIP(hipMemGetInfo(&freeb, &totalb));
-  const size_t budget = std::min<size_t>(freeb / 3, (size_t)24 << 30);
-  const int64_t nslots = std::max<int64_t>(1, std::min<int64_t>(nq, budget / per_slot));
-  DevBuf rho((size_t)nslots * ix.L * nlpad), bitmap((size_t)nslots * nwords * 4);
-  DevBuf admb((size_t)nslots * admcap * 12), adm2((size_t)nslots * (admcap + 1) * 8);
-  DevBuf t2((size_t)nslots * NRHO * 4), crr((size_t)nslots * NRHO * 8);
-  PDET_HIP(hipMemsetAsync(rho.p, 0xff, rho.bytes, s));   // entries past a tree's leaves: never
+  int64_t nl_total = 0;
+  for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
+  const int64_t admcap = std::max<int64_t>(nl_total, 1);   // admitted leaves of one round
+  const size_t per_slot = (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 +
+                          NRHO * 12;
+  WorkspaceLease lease(ix);
+  QueryWorkspace& ws = lease.get();
+  if (ws.nslots == 0 || (ws.nslots < nq && ws.nslots < ws.nslots_max)) {
+    size_t freeb = 0, totalb = 0;
+    PDET_HIP(hipMemGetInfo(&freeb, &totalb));
+    const size_t budget = std::min<size_t>((freeb + ws.bytes()) / 3, (size_t)24 << 30);
+    const int64_t cap = std::max<int64_t>(1, (int64_t)(budget / per_slot));
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(nq, cap));
+    if (want > ws.nslots) {
+      ws.rho.release(); ws.admb.release(); ws.adm2.release(); ws.t2.release(); ws.crr.release();
+      ws.rho.alloc((size_t)want * ix.L * nlpad);
+      ws.admb.alloc((size_t)want * admcap * 12);
+      ws.adm2.alloc((size_t)want * (admcap + 1) * 12);
+      ws.t2.alloc((size_t)want * NRHO * 4);
+      ws.crr.alloc((size_t)want * NRHO * 8);
+      // entries past a tree's last leaf are never written by q_rho: mark them "never"
+      PDET_HIP(hipMemsetAsync(ws.rho.p, 0xff, ws.rho.bytes, s));
+      ws.nslots = want;
+    }
+    ws.nslots_max = cap;
+  }
+  const int64_t nslots = ws.nslots;
+  if (ws.nq_cap < nq) {
+    ws.dk.alloc((size_t)nq * 4); ws.dc.alloc((size_t)nq * 8);
+    ws.dT.alloc((size_t)nq * 8); ws.doff.alloc((size_t)nq * 8);
+    ws.qp.alloc((size_t)nq * PDET_MAX_L * PDET_MAX_K * 4);
+    ws.nq_cap = nq;
+  }
+  PDET_HIP(hipMemcpyAsync(ws.dk.p, qc.k_host, nq * 4, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(ws.dc.p, qc.c_host, nq * 8, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(ws.dT.p, T.data(), nq * 8, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(ws.doff.p, off.data(), nq * 8, hipMemcpyHostToDevice, s));
+
+  pdet_timing& tm = timer().t;
+  if (timer().on) {
+    tm.query_project_ms = tm.query_rho_ms = tm.query_main_ms = 0.0;
+    tm.query_main_launches = 0;
+  }
+  {
+    Span sp(s, &tm.query_project_ms);
+    project_points(ix, qc.Q, nq, ws.qp.as<float>(), s);
+    sp.finish();
+  }
 
   QArgs a{};
   a.n = ix.n; a.d = ix.d; a.L = ix.L; a.K = ix.K; a.dpad = ix.dpad;
@@ -555,29 +709,31 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
   a.xf8 = ix.xfp8.as<uint8_t>();
   a.xscale = ix.xscale.as<float>();
   a.perm = ix.perm.as<int32_t>();
+  a.leafrow = ix.leafrow.as<int32_t>();
   for (int i = 0; i < ix.L; ++i) {
     a.lstart[i] = ix.leaf_start[i].as<int32_t>();
     a.lcount[i] = ix.leaf_count[i].as<int32_t>();
     a.box[i] = ix.box[i].as<float>();
+    a.gbox[i] = ix.gbox[i].as<float>();
     a.nl[i] = ix.nl[i];
+    a.ng[i] = (ix.nl[i] + GL - 1) / GL;
   }
   a.nlpad = nlpad;
   a.Q = qc.Q;
-  a.qp = qp.as<float>();
-  a.qk = dk.as<int32_t>();
-  a.qT = dT.as<int64_t>();
-  a.qoff = doff.as<int64_t>();
-  a.qc = dc.as<double>();
-  a.t2 = t2.as<float>();
-  a.crr = crr.as<double>();
-  a.rho = rho.as<uint8_t>();
-  a.bitmap = bitmap.as<uint32_t>();
-  a.nwords = nwords;
-  a.adm_leaf = admb.as<uint32_t>();
+  a.qp = ws.qp.as<float>();
+  a.qk = ws.dk.as<int32_t>();
+  a.qT = ws.dT.as<int64_t>();
+  a.qoff = ws.doff.as<int64_t>();
+  a.qc = ws.dc.as<double>();
+  a.t2 = ws.t2.as<float>();
+  a.crr = ws.crr.as<double>();
+  a.rho = ws.rho.as<uint8_t>();
+  a.adm_leaf = ws.admb.as<uint32_t>();
   a.adm_w = a.adm_leaf + nslots * admcap;
   a.adm_lb = reinterpret_cast<float*>(a.adm_w + nslots * admcap);
-  a.adm2_leaf = adm2.as<uint32_t>();
+  a.adm2_leaf = ws.adm2.as<uint32_t>();
   a.adm2_pre = a.adm2_leaf + nslots * (admcap + 1);
+  a.adm_start = reinterpret_cast<int32_t*>(a.adm2_pre + nslots * (admcap + 1));
   a.admcap = admcap;
   a.ids = qc.ids;
   a.dists = qc.dists;
@@ -594,11 +750,17 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
   for (int64_t q0 = 0; q0 < nq; q0 += nslots) {
     a.q0 = q0;
     a.nslots = (int)std::min<int64_t>(nslots, nq - q0);
-    hipLaunchKernelGGL(q_setup, dim3(cdiv(a.nslots, 64)), dim3(64), 0, s, a);
-    PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL(q_rho, dim3(cdiv(ix.nl_max, 256), ix.L, cdiv(a.nslots, QT)), dim3(256), 0,
-                       s, a);
-    PDET_HIP(hipGetLastError());
+    {
+      Span sp(s, &tm.query_rho_ms);
+      hipLaunchKernelGGL(q_setup, dim3(cdiv(a.nslots, 64)), dim3(64), 0, s, a);
+      PDET_HIP(hipGetLastError());
+      hipLaunchKernelGGL(q_rho, dim3(cdiv(((ix.nl_max + GL - 1) / GL) * GL, 256), ix.L,
+                                     cdiv(a.nslots, QT)),
+                         dim3(256), 0, s, a);
+      PDET_HIP(hipGetLastError());
+      sp.finish();
+    }
+    Span sp(s, &tm.query_main_ms);
     switch (qc.precision) {
       case PDET_FP32:
         hipLaunchKernelGGL(q_main<PDET_FP32>, dim3(a.nslots), dim3(QM), smem, s, a);
@@ -611,8 +773,10 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
         break;
     }
     PDET_HIP(hipGetLastError());
+    sp.finish();
+    if (timer().on) ++tm.query_main_launches;
   }
-  // scratch buffers are released when this returns: wait for the kernels first
+  // the workspace goes back to the pool when this returns: wait for the kernels first
   PDET_HIP(hipStreamSynchronize(s));
 }
 

@@ -401,6 +401,48 @@ __global__ void leaf_compact(const uint32_t* cnt_at, const uint16_t* hidx_at, co
   }
 }
 
+// Leaf ordinal of every point: position p lies in the leaf that starts at the last
+// recorded start <= p, whose ordinal is the exclusive start count at p, plus one if p
+// itself starts a leaf, minus one.
+__global__ void leaf_of_kernel(const uint32_t* cnt_at, const uint32_t* ord, const int32_t* perm,
+                               int64_t n, int L, int32_t* leaf_of) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tree = blockIdx.y;
+  if (p >= n) return;
+  const int64_t g = (int64_t)tree * n + p;
+  const int32_t leaf = (int32_t)ord[g] + (cnt_at[g] ? 1 : 0) - 1;
+  leaf_of[(int64_t)perm[g] * L + tree] = leaf;
+}
+
+// leafrow[i][p] = leaf_of[perm_i[p]]: the leaf ordinals of a point in every tree, stored in
+// the order the query walks tree i's leaves, so the dedupe test reads them contiguously.
+__global__ void leafrow_kernel(const int32_t* perm, const int32_t* leaf_of, int64_t n, int L,
+                               int32_t* leafrow) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tree = blockIdx.y;
+  if (p >= n) return;
+  const int32_t* src = leaf_of + (int64_t)perm[(int64_t)tree * n + p] * L;
+  int32_t* dst = leafrow + ((int64_t)tree * n + p) * L;
+  for (int j = 0; j < L; ++j) dst[j] = src[j];
+}
+
+// Union box of each group of 16 consecutive leaves (depth-first neighbours share most
+// of their code prefixes, so the union stays tight).
+__global__ void group_boxes(const float* box, int64_t nl, int K, int64_t ng, float* gbox) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const int64_t l0 = g * 16, l1 = std::min<int64_t>(nl, l0 + 16);
+  for (int j = 0; j < K; ++j) {
+    float lo = INFINITY, hi = -INFINITY;
+    for (int64_t l = l0; l < l1; ++l) {
+      lo = fminf(lo, box[(int64_t)j * nl + l]);
+      hi = fmaxf(hi, box[(int64_t)(K + j) * nl + l]);
+    }
+    gbox[(int64_t)j * ng + g] = lo;
+    gbox[(int64_t)(K + j) * ng + g] = hi;
+  }
+}
+
 }  // namespace
 
 void build_trees(Index& ix, hipStream_t s) {
@@ -519,6 +561,22 @@ void build_trees(Index& ix, hipStream_t s) {
   hipLaunchKernelGGL(leaf_compact, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
                      hidx_at.as<uint16_t>(), flags.as<uint32_t>(), n, K, bits, ix.Nr,
                      ix.B.as<float>(), t);
+  PDET_HIP(hipGetLastError());
+  for (int i = 0; i < L; ++i) {
+    const int64_t ng = (nl[i] + 15) / 16;
+    ix.gbox[i].alloc((size_t)std::max<int64_t>(ng, 1) * 2 * K * 4);
+    if (ng)
+      hipLaunchKernelGGL(group_boxes, dim3(cdiv(ng, 256)), dim3(256), 0, s, ix.box[i].as<float>(),
+                         (int64_t)nl[i], K, ng, ix.gbox[i].as<float>());
+    PDET_HIP(hipGetLastError());
+  }
+  DevBuf leaf_of((size_t)n * L * 4);
+  hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
+                     flags.as<uint32_t>(), perm, n, L, leaf_of.as<int32_t>());
+  PDET_HIP(hipGetLastError());
+  ix.leafrow.alloc((size_t)L * n * L * 4);
+  hipLaunchKernelGGL(leafrow_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, perm,
+                     leaf_of.as<int32_t>(), n, L, ix.leafrow.as<int32_t>());
   PDET_HIP(hipGetLastError());
   PDET_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
 }

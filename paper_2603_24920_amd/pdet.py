@@ -22,7 +22,7 @@ QSTAT_WORDS = 8
 QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX = range(6)
 EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_info", "pdet_export", "pdet_project",
-            "pdet_epsilon", "pdet_last_error"]
+            "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing"]
 
 
 class BuildParams(ctypes.Structure):
@@ -42,6 +42,12 @@ class IndexInfo(ctypes.Structure):
                 ("L", c_int32), ("Nr", c_int32), ("max_leaf", c_int32),
                 ("lowp_copies", c_uint32), ("leaves", c_int64 * MAX_L),
                 ("device_bytes", c_int64)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [(f, c_double) for f in (
+        "build_sample_ms", "build_sort_ms", "build_encode_ms", "build_tree_ms", "build_lowp_ms",
+        "query_project_ms", "query_rho_ms", "query_main_ms")] + [("query_main_launches", c_int64)]
 
 
 class PdetError(RuntimeError):
@@ -73,6 +79,10 @@ def lib() -> ctypes.CDLL:
         L.pdet_epsilon.argtypes = [c_int32, c_int32]
         L.pdet_epsilon.restype = c_double
         L.pdet_last_error.restype = ctypes.c_char_p
+        L.pdet_set_timing.argtypes = [c_int32]
+        L.pdet_set_timing.restype = None
+        L.pdet_get_timing.argtypes = [POINTER(Timing)]
+        L.pdet_get_timing.restype = c_int32
         for f in ("pdet_build", "pdet_query", "pdet_info", "pdet_export", "pdet_project"):
             getattr(L, f).restype = c_int32
         _lib = L
@@ -87,6 +97,17 @@ def _check(status):
 def epsilon(K: int, L: int) -> float:
     """Projected-radius factor from Eq. 2 / Lemma 3, computed by the library's host code."""
     return lib().pdet_epsilon(K, L)
+
+
+def set_timing(on: bool) -> None:
+    """Record per-kernel-family device time (HIP events) for this thread's calls."""
+    lib().pdet_set_timing(1 if on else 0)
+
+
+def get_timing() -> dict:
+    t = Timing()
+    _check(lib().pdet_get_timing(ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in Timing._fields_}
 
 
 def _stream(stream=None):

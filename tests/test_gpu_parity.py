@@ -218,11 +218,15 @@ def test_trees_equal_oracle_on_gpu_codes(mixture, ragged):
     check_trees(ragged[1])
 
 
-@pytest.mark.parametrize("beta,r_min", [(0.1, 4.0), (0.02, 1.0), (1.0, 6.0)])
+@pytest.mark.parametrize("beta,r_min", [(0.1, 4.0), (0.02, 1.0), (1.0, 6.0), (0.05, 0.05)])
 def test_query_stepwise_mixture(mixture, beta, r_min):
     w, cs = mixture
-    run_and_compare(cs, cs.stepwise_oracle(), w.queries(), w.k, w.c, beta, r_min,
-                    f"mixture b={beta}")
+    _, _, st = run_and_compare(cs, cs.stepwise_oracle(), w.queries(), w.k, w.c, beta, r_min,
+                               f"mixture b={beta}")
+    if r_min <= 0.05:
+        # small first radii run past the rounds the batched bound kernel resolves (5),
+        # so the per-query refinement of the open leaves is exercised
+        assert st[:, pdet.QSTAT["rounds"]].max() > 6
 
 
 @pytest.mark.parametrize("beta,r_min,k,c", [(0.05, 2.0, 7, 1.5), (0.3, 0.5, 1, 2.0),

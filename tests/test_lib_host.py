@@ -51,7 +51,7 @@ def _params(**kw):
     (dict(K=17), 1000, 8), (dict(K=0), 1000, 8), (dict(L=0), 1000, 8), (dict(L=17), 1000, 8),
     (dict(Nr=100), 1000, 8), (dict(Nr=512), 1000, 8), (dict(Nr=1), 1000, 8),
     (dict(max_leaf=0), 1000, 8), (dict(n_sample=100), 1000, 8), (dict(n_sample=2000), 1000, 8),
-    (dict(lowp_copies=8), 1000, 8), ({}, 0, 8), ({}, 1000, 0), ({}, 1 << 31, 8),
+    (dict(lowp_copies=8), 1000, 8), ({}, 0, 8), ({}, 1000, 0),
 ])
 def test_build_rejects_invalid_arguments_before_touching_the_device(kw, n, d):
     p, keep = _params(**kw)
@@ -60,6 +60,14 @@ def test_build_rejects_invalid_arguments_before_touching_the_device(kw, n, d):
     assert st == pdet.PDET_EINVAL
     assert h.value is None
     assert pdet.lib().pdet_last_error()
+
+
+def test_build_rejects_sizes_beyond_the_packed_leaf_ids():
+    p, keep = _params()
+    h = ctypes.c_void_p()
+    st = pdet.lib().pdet_build(ctypes.c_void_p(4096), 1 << 28, 8, ctypes.byref(p), None,
+                               ctypes.byref(h))
+    assert st == pdet.PDET_EUNSUPPORTED and h.value is None
 
 
 def test_build_rejects_out_of_range_sample_ids():
