@@ -87,7 +87,8 @@ void pdet_free(pdet_index* idx);
  *   k, c          uniform k >= 1 and c > 1, used when the per-query arrays are NULL.
  *   k_per_query   host int32 [nq] or NULL; c_per_query host double [nq] or NULL.
  *   beta          stop rule A fires once |S| >= ceil(beta*n) + k (beta >= 0).
- *   r_min         first search radius (> 0); radii r_min*c^rho for rho < 255.
+ *   r_min         first search radius; radii r_min*c^rho for rho < 255. <= 0 selects the
+ *                 index's tuned value (pdet_autotune).
  *   eps           projected-radius factor; <= 0 selects sqrt(chi2 upper quantile of
  *                 exp(-1/L) with K degrees of freedom) (Eq. 2 and Lemma 3).
  *   precision     pdet_precision of candidate verification. FP32 reads the float32
@@ -123,7 +124,7 @@ typedef struct {
  *   ids    int64: neighbour ids sorted by (distance, id) ascending.
  *   dists  float32: Euclidean distances (not squared) of those neighbours.
  *   qstats int32 [nq][PDET_QSTAT_WORDS] or NULL.
- * Errors: EINVAL for k < 1, k > n, c <= 1, beta < 0, r_min <= 0, a low-precision form
+ * Errors: EINVAL for k < 1, k > n, c <= 1, beta < 0, r_min <= 0 on an untuned index, a low-precision form
  * whose copy the index lacks, rescore < 1; EUNSUPPORTED for k*rescore > PDET_MAX_TOPK.
  * A query whose radius ladder runs out before a stop rule fires gets stop = -1.
  * Concurrent calls on one index are allowed on different streams (the index is
@@ -190,6 +191,75 @@ typedef struct {
 } pdet_timing;
 void pdet_set_timing(int32_t on);
 pdet_status pdet_get_timing(pdet_timing* out);
+
+/*
+ * Radius-schedule autotuner (the dataset-level "magic" r_min of the parameter-setting
+ * section, which the paper takes from PM-LSH: at r_min the candidate set reaches
+ * beta*n + k, at r_min/c it does not). Runs the pilot queries (device float32
+ * [n_pilot][d]) from a tiny first radius, sets the index's tuned r_min one ladder step
+ * below the median terminating radius, then sets how many rounds the batched bound kernel
+ * resolves (rounds_resolved, 1..8) to cover 95% of the pilots. Queries passing r_min <= 0
+ * use the tuned value. Must not run concurrently with queries on the same index.
+ */
+typedef struct {
+  double r_min;
+  int32_t rounds_resolved;
+  double median_rounds, p95_rounds;
+} pdet_tuning;
+pdet_status pdet_autotune(pdet_index* idx, const float* pilot, int64_t n_pilot, int32_t k,
+                          double c, double beta, int32_t precision, void* stream,
+                          pdet_tuning* out);
+/* Sets the tuned schedule directly (e.g. a saved pdet_tuning): r_min > 0, 1 <= rounds <= 8. */
+pdet_status pdet_set_tuning(pdet_index* idx, double r_min, int32_t rounds_resolved);
+
+/*
+ * Query plans (batching form): the whole launch sequence of one batch - parameter upload,
+ * query projection, round indices, search - captured once into a HIP graph. The query,
+ * output and per-query k / c arguments are fixed at creation (same meaning as pdet_query);
+ * the caller may rewrite the query buffer between launches. pdet_plan_launch replays the
+ * graph on `stream`; outputs are valid when the stream reaches the end of the launch.
+ * Launches of one plan must not overlap. The plan holds its own scratch until freed.
+ */
+typedef struct pdet_plan pdet_plan;
+pdet_status pdet_plan_create(const pdet_index* idx, const float* queries, int64_t nq,
+                             const pdet_query_params* p, int64_t* ids, float* dists,
+                             int32_t* qstats, pdet_plan** out);
+pdet_status pdet_plan_launch(pdet_plan* plan, void* stream);
+void pdet_plan_free(pdet_plan* plan);
+
+/*
+ * Serving form: a continuous-batching request loop over a resident index. submit() copies
+ * a host query (float32 [d]) into the queue and returns at once; a worker thread admits
+ * queued requests into batches of at most min(max_batch, slots the memory budget holds)
+ * queries and keeps up to `lanes` batches in flight on separate streams, so requests that
+ * arrive while others run are admitted as lanes free up. wait() blocks until a request is
+ * done and returns its k ids and distances (host) and its latency (submit to completion).
+ * A result is the same whatever batch it was served in (each query has its own
+ * workgroup). memory_budget 0 takes a quarter of the free device memory; r_min <= 0 takes
+ * the tuned value; eps <= 0 takes Eq. 2.
+ */
+typedef struct pdet_server pdet_server;
+typedef struct {
+  int32_t max_batch;      /* 1..1024                                      */
+  int32_t lanes;          /* batches in flight, 1..4                      */
+  int32_t k_max;          /* largest k a request may ask for             */
+  int32_t precision;      /* pdet_precision                               */
+  int32_t rescore;
+  double beta, r_min, eps;
+  int64_t memory_budget;  /* bytes of query scratch over all lanes       */
+} pdet_server_params;
+typedef struct {
+  int64_t completed, batches, batch_cap;
+  double mean_batch, p50_ms, p99_ms, qps;
+} pdet_server_stats;
+pdet_status pdet_server_create(const pdet_index* idx, const pdet_server_params* p,
+                               pdet_server** out);
+pdet_status pdet_server_submit(pdet_server* sv, const float* query, int32_t k, double c,
+                               int64_t* request_id);
+pdet_status pdet_server_wait(pdet_server* sv, int64_t request_id, int64_t* ids, float* dists,
+                             double* latency_ms);
+pdet_status pdet_server_get_stats(pdet_server* sv, pdet_server_stats* out);
+void pdet_server_free(pdet_server* sv);   /* drains queued requests first */
 
 /* eps = sqrt(chi2 upper exp(-1/L) quantile, K dof) from Eq. 2 / Lemma 3; NaN if invalid. */
 double pdet_epsilon(int32_t K, int32_t L);

@@ -11,25 +11,6 @@ namespace pdet {
 
 namespace {
 thread_local std::string g_last_error;
-
-template <class F>
-pdet_status guarded(F&& f) {
-  try {
-    g_last_error.clear();
-    f();
-    return PDET_OK;
-  } catch (const Error& e) {
-    g_last_error = e.msg;
-    return e.status;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return PDET_ENOMEM;
-  } catch (...) {
-    g_last_error = "unexpected failure";
-    return PDET_EDEVICE;
-  }
-}
-
 // Regularised lower incomplete gamma P(a, x): power series for x < a + 1, otherwise
 // 1 - Q from the continued fraction of Q (modified Lentz).
 double gamma_p(double a, double x) {
@@ -64,6 +45,55 @@ double gamma_p(double a, double x) {
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+// Checks query arguments and fills per-query k and c (host) and the query configuration.
+QueryConfig check_query(const pdet_index* idx, const float* queries, int64_t nq,
+                        const pdet_query_params* p, int64_t* ids, float* dists, int32_t* qstats,
+                        std::vector<int32_t>& k, std::vector<double>& c) {
+  PDET_REQUIRE(idx && p, PDET_EINVAL, "NULL argument");
+  PDET_REQUIRE(nq >= 0, PDET_EINVAL, "nq must be >= 0");
+  PDET_REQUIRE(nq == 0 || (queries && ids && dists), PDET_EINVAL, "NULL queries or outputs");
+  PDET_REQUIRE(p->beta >= 0.0 && std::isfinite(p->beta), PDET_EINVAL, "beta must be >= 0");
+  double r_min = p->r_min;
+  if (r_min <= 0.0) {
+    PDET_REQUIRE(idx->tuned_r_min > 0.0, PDET_EINVAL,
+                 "r_min <= 0 selects the tuned radius, but the index has not been tuned");
+    r_min = idx->tuned_r_min;
+  }
+  PDET_REQUIRE(std::isfinite(r_min), PDET_EINVAL, "r_min must be finite");
+  PDET_REQUIRE(p->precision >= PDET_FP32 && p->precision <= PDET_FP8_E4M3, PDET_EINVAL,
+               "unknown precision");
+  if (p->precision != PDET_FP32) {
+    PDET_REQUIRE(idx->lowp & (1u << p->precision), PDET_EINVAL,
+                 "index was built without this low-precision copy");
+    PDET_REQUIRE(p->rescore >= 1, PDET_EINVAL, "rescore must be >= 1");
+  }
+  k.resize(nq);
+  c.resize(nq);
+  for (int64_t q = 0; q < nq; ++q) {
+    k[q] = p->k_per_query ? p->k_per_query[q] : p->k;
+    c[q] = p->c_per_query ? p->c_per_query[q] : p->c;
+    PDET_REQUIRE(k[q] >= 1 && k[q] <= idx->n, PDET_EINVAL, "k must be in [1, n]");
+    PDET_REQUIRE(c[q] > 1.0 && std::isfinite(c[q]), PDET_EINVAL, "c must be > 1");
+    const int64_t kl = (p->precision == PDET_FP32) ? k[q] : (int64_t)k[q] * p->rescore;
+    PDET_REQUIRE(kl <= PDET_MAX_TOPK, PDET_EUNSUPPORTED, "k * rescore exceeds 1024");
+  }
+  QueryConfig qc{};
+  qc.Q = queries;
+  qc.nq = nq;
+  qc.k_host = k.data();
+  qc.c_host = c.data();
+  qc.beta = p->beta;
+  qc.r_min = r_min;
+  qc.eps = (p->eps > 0.0) ? p->eps : epsilon(idx->K, idx->L);
+  qc.precision = p->precision;
+  qc.rescore = p->precision == PDET_FP32 ? 1 : p->rescore;
+  qc.ids = ids;
+  qc.dists = dists;
+  qc.qstats = qstats;
+  return qc;
+}
 
 Timer& timer() {
   static thread_local Timer t;
@@ -230,42 +260,10 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
                        const pdet_query_params* p, int64_t* ids, float* dists, int32_t* qstats,
                        void* stream) {
   return guarded([&] {
-    PDET_REQUIRE(idx && p, PDET_EINVAL, "NULL argument");
-    PDET_REQUIRE(nq >= 0, PDET_EINVAL, "nq must be >= 0");
+    std::vector<int32_t> k;
+    std::vector<double> c;
+    const QueryConfig qc = check_query(idx, queries, nq, p, ids, dists, qstats, k, c);
     if (nq == 0) return;
-    PDET_REQUIRE(queries && ids && dists, PDET_EINVAL, "NULL queries or outputs");
-    PDET_REQUIRE(p->beta >= 0.0 && std::isfinite(p->beta), PDET_EINVAL, "beta must be >= 0");
-    PDET_REQUIRE(p->r_min > 0.0 && std::isfinite(p->r_min), PDET_EINVAL, "r_min must be > 0");
-    PDET_REQUIRE(p->precision >= PDET_FP32 && p->precision <= PDET_FP8_E4M3, PDET_EINVAL,
-                 "unknown precision");
-    if (p->precision != PDET_FP32) {
-      PDET_REQUIRE(idx->lowp & (1u << p->precision), PDET_EINVAL,
-                   "index was built without this low-precision copy");
-      PDET_REQUIRE(p->rescore >= 1, PDET_EINVAL, "rescore must be >= 1");
-    }
-    std::vector<int32_t> k(nq);
-    std::vector<double> c(nq);
-    for (int64_t q = 0; q < nq; ++q) {
-      k[q] = p->k_per_query ? p->k_per_query[q] : p->k;
-      c[q] = p->c_per_query ? p->c_per_query[q] : p->c;
-      PDET_REQUIRE(k[q] >= 1 && k[q] <= idx->n, PDET_EINVAL, "k must be in [1, n]");
-      PDET_REQUIRE(c[q] > 1.0 && std::isfinite(c[q]), PDET_EINVAL, "c must be > 1");
-      const int64_t kl = (p->precision == PDET_FP32) ? k[q] : (int64_t)k[q] * p->rescore;
-      PDET_REQUIRE(kl <= PDET_MAX_TOPK, PDET_EUNSUPPORTED, "k * rescore exceeds 1024");
-    }
-    QueryConfig qc{};
-    qc.Q = queries;
-    qc.nq = nq;
-    qc.k_host = k.data();
-    qc.c_host = c.data();
-    qc.beta = p->beta;
-    qc.r_min = p->r_min;
-    qc.eps = (p->eps > 0.0) ? p->eps : pdet::epsilon(idx->K, idx->L);
-    qc.precision = p->precision;
-    qc.rescore = p->precision == PDET_FP32 ? 1 : p->rescore;
-    qc.ids = ids;
-    qc.dists = dists;
-    qc.qstats = qstats;
     run_query(*idx, qc, static_cast<hipStream_t>(stream));
   });
 }

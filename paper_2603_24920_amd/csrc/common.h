@@ -71,6 +71,32 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host buffer (hipHostMalloc), for asynchronous copies and graph memcpy nodes.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{PDET_ENOMEM, "hipHostMalloc(" + std::to_string(b) + " bytes) failed"};
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
 // Total-order mapping float -> uint32 (for atomic min/max on floats).
 __host__ __device__ inline uint32_t float_to_ordered(float f) {
   const uint32_t u = __builtin_bit_cast(uint32_t, f);

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "common.h"
@@ -13,6 +14,7 @@ namespace pdet {
 // Query scratch, kept by the index and reused across calls (see run_query).
 struct QueryWorkspace {
   DevBuf rho, admb, adm2, t2, crr, qp, dk, dc, dT, doff;
+  PinnedBuf h_k, h_c, h_T, h_off;   // staging of the per-query parameters
   int64_t nslots = 0, nslots_max = 0, nq_cap = 0;
   size_t bytes() const { return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes; }
 };
@@ -41,6 +43,9 @@ struct pdet_index {
   pdet::DevBuf gbox[PDET_MAX_L];         // float32 [2][K][ceil(nl/16)]: union box of 16 leaves
   int64_t nl[PDET_MAX_L] = {};
   int64_t nl_max = 0;
+  // radius schedule chosen by pdet_autotune (r_min <= 0 in a query selects tuned_r_min)
+  double tuned_r_min = 0.0;
+  int rcap = 4;                    // rounds resolved by the batched bound kernel
   // low-precision copies for verification
   int dpad = 0;                    // row length of the copies (multiple of 16)
   pdet::DevBuf xbf16;              // bf16 [n][dpad]
@@ -136,5 +141,37 @@ struct QueryConfig {
   int32_t* qstats;
 };
 void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s);
+int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws);
+size_t slot_bytes(const Index& ix);
+void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t budget,
+                       hipStream_t s);
+void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
+                   hipStream_t s, bool timed);
+
+// api.hip
+double epsilon(int K, int L);
+void clear_error();
+QueryConfig check_query(const pdet_index* idx, const float* queries, int64_t nq,
+                        const pdet_query_params* p, int64_t* ids, float* dists, int32_t* qstats,
+                        std::vector<int32_t>& k, std::vector<double>& c);
+
+// Runs f, converting library failures into a status and the thread's error message.
+template <class F>
+pdet_status guarded(F&& f) {
+  try {
+    clear_error();
+    f();
+    return PDET_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return PDET_ENOMEM;
+  } catch (...) {
+    set_error("unexpected failure");
+    return PDET_EDEVICE;
+  }
+}
 
 }  // namespace pdet

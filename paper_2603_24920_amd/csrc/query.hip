@@ -7,9 +7,9 @@
 //           and c*r_rho, computed with the same double operations as the definition.
 //  q_rho    batched over (leaf block, tree, query tile): the first round whose threshold
 //           admits each leaf (its squared lower bound to q' <= (eps r_rho)^2), for rounds
-//           up to RCAP. Groups of 16 consecutive leaves are tested first with their union
+//           up to rcap. Groups of 16 consecutive leaves are tested first with their union
 //           box (a lower bound of every member's bound, as a subtree prunes in the
-//           range query); a pruned group and any leaf beyond RCAP get the mark RCAP+1,
+//           range query); a pruned group and any leaf beyond rcap get the mark rcap+1,
 //           refined exactly by q_main if a query ever reaches that round.
 //  q_main   one workgroup per query, one pass per round over the admitted leaves of all
 //           trees: an admitted point is new iff none of its leaves in the other trees was
@@ -31,8 +31,7 @@ constexpr int CB = 512;          // top-k candidate buffer
 constexpr int QT = 64;           // queries per q_rho block (group tests in sub-tiles of 16)
 constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
 constexpr int GL = 16;           // leaves per pruning group
-constexpr int RCAP = 4;          // rounds resolved by q_rho
-constexpr uint8_t MARK = RCAP + 1;
+constexpr int RCAP_MAX = 8;      // most rounds q_rho resolves (the index's rcap <= this)
 constexpr int TREE_SHIFT = 28;   // list entries pack (tree << 28) | leaf
 
 struct QArgs {
@@ -71,6 +70,7 @@ struct QArgs {
   float* dists;
   int32_t* qstats;
   int rescore, NM;
+  int rcap;                  // rounds resolved by q_rho; later ones are refined per query
   int64_t q0;
   int nslots;
   double r_min, eps;
@@ -110,12 +110,14 @@ __device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, con
 
 __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   __shared__ float sq[QT][PDET_MAX_K];
-  __shared__ float st[QT][RCAP + 1];
+  __shared__ float st[QT][RCAP_MAX + 1];
   const int tree = blockIdx.y;
   const int slot0 = blockIdx.z * QT;
   const int64_t nl = a.nl[tree], ng = a.ng[tree];
-  for (int e = threadIdx.x; e < QT * (RCAP + 1); e += blockDim.x) {
-    const int qi = e / (RCAP + 1), r = e % (RCAP + 1);
+  const int rcap = a.rcap;
+  const uint8_t mark = (uint8_t)(rcap + 1);
+  for (int e = threadIdx.x; e < QT * (RCAP_MAX + 1); e += blockDim.x) {
+    const int qi = e / (RCAP_MAX + 1), r = e % (RCAP_MAX + 1);
     st[qi][r] = (slot0 + qi < a.nslots) ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
   }
   for (int e = threadIdx.x; e < QT * a.K; e += blockDim.x) {
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
         const float gap = fmaxf(0.0f, fmaxf(lo - sq[qi][j], sq[qi][j] - hi));
         acc = __fmaf_rn(gap, gap, acc);
       }
-      open = acc <= st[qi][RCAP];
+      open = acc <= st[qi][rcap];
     }
     const uint64_t mask = __ballot(open);
     open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   for (int qi = 0; qi < QT; ++qi) {
     const int slot = slot0 + qi;
     if (slot >= a.nslots) break;
-    uint8_t r = MARK;
+    uint8_t r = mark;
     if ((open_mask >> qi) & 1ull) {
       float acc = 0.0f;
 #pragma unroll
@@ -167,9 +169,9 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
           acc = __fmaf_rn(gap, gap, acc);
         }
       }
-      int c = 0;   // #thresholds < lb2 among rounds 0..RCAP; RCAP+1 is the mark
+      int c = 0;   // #thresholds < lb2 among rounds 0..rcap; rcap+1 is the mark
 #pragma unroll
-      for (int rr = 0; rr <= RCAP; ++rr) c += (st[qi][rr] < acc) ? 1 : 0;
+      for (int rr = 0; rr <= RCAP_MAX; ++rr) c += (rr <= rcap && st[qi][rr] < acc) ? 1 : 0;
       r = (uint8_t)c;
     }
     a.rho[((int64_t)slot * a.L + tree) * a.nlpad + leaf] = r;
@@ -429,12 +431,12 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
 
   for (int rho = 0; rho < NRHO - 1 && stop < 0; ++rho) {
     rounds = rho + 1;
-    if (rho == RCAP + 1) {
+    if (rho == a.rcap + 1) {
       // exact first rounds of the leaves q_rho left open
       for (int i = 0; i < a.L; ++i) {
         uint8_t* rr = rq + (int64_t)i * a.nlpad;
         for (int64_t leaf = tid; leaf < a.nl[i]; leaf += QM) {
-          if (rr[leaf] != MARK) continue;
+          if (rr[leaf] != (uint8_t)(a.rcap + 1)) continue;
           const float lb2 = leaf_lb2(a.box[i], a.nl[i], leaf, qps + i * a.K, a.K);
           int pos = 0;
 #pragma unroll
@@ -635,35 +637,46 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
 
 }  // namespace
 
-void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
-  const int64_t nq = qc.nq;
-  if (nq == 0) return;
-  const int LK = ix.L * ix.K;
-  // per-query parameters
-  std::vector<int64_t> T(nq), off(nq);
+// Per-query parameters of a batch into the workspace's pinned staging arrays.
+int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws) {
   int maxKL = 1;
   int64_t acc = 0;
-  for (int64_t q = 0; q < nq; ++q) {
+  for (int64_t q = 0; q < qc.nq; ++q) {
     const int k = qc.k_host[q];
-    T[q] = (int64_t)std::ceil(qc.beta * (double)ix.n) + k;
-    off[q] = acc;
+    ws.h_k.as<int32_t>()[q] = k;
+    ws.h_c.as<double>()[q] = qc.c_host[q];
+    ws.h_T.as<int64_t>()[q] = (int64_t)std::ceil(qc.beta * (double)ix.n) + k;
+    ws.h_off.as<int64_t>()[q] = acc;
     acc += k;
     maxKL = std::max(maxKL, qc.precision == PDET_FP32 ? k : k * qc.rescore);
   }
+  return maxKL;
+}
 
-  // scratch per query slot, reused across calls; the number of slots is bounded by memory
+size_t slot_bytes(const Index& ix) {
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
   int64_t nl_total = 0;
   for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
-  const int64_t admcap = std::max<int64_t>(nl_total, 1);   // admitted leaves of one round
-  const size_t per_slot = (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 +
-                          NRHO * 12;
-  WorkspaceLease lease(ix);
-  QueryWorkspace& ws = lease.get();
+  const int64_t admcap = std::max<int64_t>(nl_total, 1);
+  return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 + NRHO * 12;
+}
+
+// Sizes the workspace for a batch of nq queries: per-query arrays, and as many query slots
+// (concurrent per-query scratch) as `budget` bytes allow (0: a third of free memory, at
+// most 24 GiB). Allocation happens here, never during a launch sequence.
+void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t budget,
+                       hipStream_t s) {
+  const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
+  int64_t nl_total = 0;
+  for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
+  const int64_t admcap = std::max<int64_t>(nl_total, 1);
+  const size_t per_slot = slot_bytes(ix);
   if (ws.nslots == 0 || (ws.nslots < nq && ws.nslots < ws.nslots_max)) {
-    size_t freeb = 0, totalb = 0;
-    PDET_HIP(hipMemGetInfo(&freeb, &totalb));
-    const size_t budget = std::min<size_t>((freeb + ws.bytes()) / 3, (size_t)24 << 30);
+    if (budget == 0) {
+      size_t freeb = 0, totalb = 0;
+      PDET_HIP(hipMemGetInfo(&freeb, &totalb));
+      budget = std::min<size_t>((freeb + ws.bytes()) / 3, (size_t)24 << 30);
+    }
     const int64_t cap = std::max<int64_t>(1, (int64_t)(budget / per_slot));
     const int64_t want = std::max<int64_t>(1, std::min<int64_t>(nq, cap));
     if (want > ws.nslots) {
@@ -679,25 +692,42 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
     }
     ws.nslots_max = cap;
   }
-  const int64_t nslots = ws.nslots;
   if (ws.nq_cap < nq) {
     ws.dk.alloc((size_t)nq * 4); ws.dc.alloc((size_t)nq * 8);
     ws.dT.alloc((size_t)nq * 8); ws.doff.alloc((size_t)nq * 8);
     ws.qp.alloc((size_t)nq * PDET_MAX_L * PDET_MAX_K * 4);
+    ws.h_k.alloc((size_t)nq * 4); ws.h_c.alloc((size_t)nq * 8);
+    ws.h_T.alloc((size_t)nq * 8); ws.h_off.alloc((size_t)nq * 8);
     ws.nq_cap = nq;
   }
-  PDET_HIP(hipMemcpyAsync(ws.dk.p, qc.k_host, nq * 4, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(ws.dc.p, qc.c_host, nq * 8, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(ws.dT.p, T.data(), nq * 8, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(ws.doff.p, off.data(), nq * 8, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipStreamSynchronize(s));
+}
 
-  pdet_timing& tm = timer().t;
-  if (timer().on) {
+// Enqueues the whole query sequence on stream s (parameter upload from the pinned staging,
+// query projection, then per chunk of slots: thresholds, round indices, search). No host
+// synchronisation unless `timed` (HIP events per kernel family).
+void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
+                   hipStream_t s, bool timed) {
+  const int64_t nq = qc.nq;
+  const int LK = ix.L * ix.K;
+  const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
+  int64_t nl_total = 0;
+  for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
+  const int64_t admcap = std::max<int64_t>(nl_total, 1);
+  const int64_t nslots = ws.nslots;
+  PDET_HIP(hipMemcpyAsync(ws.dk.p, ws.h_k.p, nq * 4, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(ws.dc.p, ws.h_c.p, nq * 8, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(ws.dT.p, ws.h_T.p, nq * 8, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipMemcpyAsync(ws.doff.p, ws.h_off.p, nq * 8, hipMemcpyHostToDevice, s));
+
+  pdet_timing scratch_tm{};
+  pdet_timing& tm = timed ? timer().t : scratch_tm;
+  if (timed) {
     tm.query_project_ms = tm.query_rho_ms = tm.query_main_ms = 0.0;
     tm.query_main_launches = 0;
   }
   {
-    Span sp(s, &tm.query_project_ms);
+    Span sp(s, timed ? &tm.query_project_ms : nullptr);
     project_points(ix, qc.Q, nq, ws.qp.as<float>(), s);
     sp.finish();
   }
@@ -739,6 +769,7 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
   a.dists = qc.dists;
   a.qstats = qc.qstats;
   a.rescore = qc.rescore;
+  a.rcap = std::max(0, std::min(RCAP_MAX, ix.rcap));
   a.r_min = qc.r_min;
   a.eps = qc.eps;
   int NM = 1;
@@ -751,7 +782,7 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
     a.q0 = q0;
     a.nslots = (int)std::min<int64_t>(nslots, nq - q0);
     {
-      Span sp(s, &tm.query_rho_ms);
+      Span sp(s, timed ? &tm.query_rho_ms : nullptr);
       hipLaunchKernelGGL(q_setup, dim3(cdiv(a.nslots, 64)), dim3(64), 0, s, a);
       PDET_HIP(hipGetLastError());
       hipLaunchKernelGGL(q_rho, dim3(cdiv(((ix.nl_max + GL - 1) / GL) * GL, 256), ix.L,
@@ -760,7 +791,7 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
       PDET_HIP(hipGetLastError());
       sp.finish();
     }
-    Span sp(s, &tm.query_main_ms);
+    Span sp(s, timed ? &tm.query_main_ms : nullptr);
     switch (qc.precision) {
       case PDET_FP32:
         hipLaunchKernelGGL(q_main<PDET_FP32>, dim3(a.nslots), dim3(QM), smem, s, a);
@@ -774,8 +805,17 @@ void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
     }
     PDET_HIP(hipGetLastError());
     sp.finish();
-    if (timer().on) ++tm.query_main_launches;
+    if (timed) ++tm.query_main_launches;
   }
+}
+
+void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
+  if (qc.nq == 0) return;
+  WorkspaceLease lease(ix);
+  QueryWorkspace& ws = lease.get();
+  reserve_workspace(ix, ws, qc.nq, 0, s);
+  const int maxKL = stage_params(ix, qc, ws);
+  enqueue_query(ix, qc, ws, maxKL, s, timer().on);
   // the workspace goes back to the pool when this returns: wait for the kernels first
   PDET_HIP(hipStreamSynchronize(s));
 }

@@ -22,7 +22,10 @@ QSTAT_WORDS = 8
 QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX = range(6)
 EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_info", "pdet_export", "pdet_project",
-            "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing"]
+            "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
+            "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
+            "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
+            "pdet_server_get_stats", "pdet_server_free"]
 
 
 class BuildParams(ctypes.Structure):
@@ -48,6 +51,23 @@ class Timing(ctypes.Structure):
     _fields_ = [(f, c_double) for f in (
         "build_sample_ms", "build_sort_ms", "build_encode_ms", "build_tree_ms", "build_lowp_ms",
         "query_project_ms", "query_rho_ms", "query_main_ms")] + [("query_main_launches", c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("r_min", c_double), ("rounds_resolved", c_int32), ("median_rounds", c_double),
+                ("p95_rounds", c_double)]
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("max_batch", c_int32), ("lanes", c_int32), ("k_max", c_int32),
+                ("precision", c_int32), ("rescore", c_int32), ("beta", c_double),
+                ("r_min", c_double), ("eps", c_double), ("memory_budget", c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", c_int64), ("batches", c_int64), ("batch_cap", c_int64),
+                ("mean_batch", c_double), ("p50_ms", c_double), ("p99_ms", c_double),
+                ("qps", c_double)]
 
 
 class PdetError(RuntimeError):
@@ -83,7 +103,24 @@ def lib() -> ctypes.CDLL:
         L.pdet_set_timing.restype = None
         L.pdet_get_timing.argtypes = [POINTER(Timing)]
         L.pdet_get_timing.restype = c_int32
-        for f in ("pdet_build", "pdet_query", "pdet_info", "pdet_export", "pdet_project"):
+        L.pdet_autotune.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_double, c_double,
+                                    c_int32, c_void_p, POINTER(Tuning)]
+        L.pdet_set_tuning.argtypes = [c_void_p, c_double, c_int32]
+        L.pdet_plan_create.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
+                                       c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]
+        L.pdet_plan_launch.argtypes = [c_void_p, c_void_p]
+        L.pdet_plan_free.argtypes = [c_void_p]
+        L.pdet_plan_free.restype = None
+        L.pdet_server_create.argtypes = [c_void_p, POINTER(ServerParams), POINTER(c_void_p)]
+        L.pdet_server_submit.argtypes = [c_void_p, c_void_p, c_int32, c_double, POINTER(c_int64)]
+        L.pdet_server_wait.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, POINTER(c_double)]
+        L.pdet_server_get_stats.argtypes = [c_void_p, POINTER(ServerStats)]
+        L.pdet_server_free.argtypes = [c_void_p]
+        L.pdet_server_free.restype = None
+        for f in ("pdet_build", "pdet_query", "pdet_info", "pdet_export", "pdet_project",
+                  "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
+                  "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
+                  "pdet_server_get_stats"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib
@@ -177,6 +214,38 @@ class Index:
                                   c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
+    def autotune(self, Q_pilot, k=10, c=1.5, beta=0.1, precision="fp32", stream=None) -> dict:
+        """Tune the radius schedule from pilot queries (CUDA float32 [m][d]); see pdet.h."""
+        t = Tuning()
+        _check(lib().pdet_autotune(self._h, c_void_p(Q_pilot.data_ptr()), Q_pilot.shape[0], k, c,
+                                   beta, PRECISIONS[precision], _stream(stream), ctypes.byref(t)))
+        return dict(r_min=t.r_min, rounds_resolved=t.rounds_resolved,
+                    median_rounds=t.median_rounds, p95_rounds=t.p95_rounds)
+
+    def set_tuning(self, r_min: float, rounds_resolved: int = 4) -> None:
+        _check(lib().pdet_set_tuning(self._h, r_min, rounds_resolved))
+
+    def _params(self, k, c, beta, r_min, eps, precision, rescore, k_per_query, c_per_query):
+        kp = cp = None
+        if k_per_query is not None:
+            kp = np.ascontiguousarray(k_per_query, dtype=np.int32)
+        if c_per_query is not None:
+            cp = np.ascontiguousarray(c_per_query, dtype=np.float64)
+        p = QueryParams(k, c, kp.ctypes.data_as(POINTER(c_int32)) if kp is not None else None,
+                        cp.ctypes.data_as(POINTER(c_double)) if cp is not None else None,
+                        beta, r_min, eps, PRECISIONS[precision], rescore)
+        return p, (kp, cp)
+
+    def plan(self, Q, k=10, c=1.5, beta=0.1, r_min=1.0, eps=0.0, precision="fp32", rescore=4,
+             k_per_query=None, c_per_query=None, stats=False):
+        return Plan(self, Q, k, c, beta, r_min, eps, precision, rescore, k_per_query,
+                    c_per_query, stats)
+
+    def server(self, max_batch=256, lanes=2, k_max=10, precision="fp32", rescore=4, beta=0.1,
+               r_min=0.0, eps=0.0, memory_budget=0):
+        return Server(self, max_batch, lanes, k_max, precision, rescore, beta, r_min, eps,
+                      memory_budget)
+
     def query(self, Q, k=10, c=1.5, beta=0.1, r_min=1.0, eps=0.0, precision="fp32",
               rescore=4, k_per_query=None, c_per_query=None, stats=False, stream=None,
               out=None):
@@ -189,17 +258,9 @@ class Index:
                 and Q.dim() == 2 and Q.shape[1] == self.d):
             raise ValueError("Q must be a contiguous CUDA float32 [nq][d] tensor")
         nq = Q.shape[0]
-        kp = cp = None
-        if k_per_query is not None:
-            kp = np.ascontiguousarray(k_per_query, dtype=np.int32)
-            total = int(kp.sum())
-        else:
-            total = nq * k
-        if c_per_query is not None:
-            cp = np.ascontiguousarray(c_per_query, dtype=np.float64)
-        p = QueryParams(k, c, kp.ctypes.data_as(POINTER(c_int32)) if kp is not None else None,
-                        cp.ctypes.data_as(POINTER(c_double)) if cp is not None else None,
-                        beta, r_min, eps, PRECISIONS[precision], rescore)
+        p, keep = self._params(k, c, beta, r_min, eps, precision, rescore, k_per_query,
+                               c_per_query)
+        total = int(keep[0].sum()) if keep[0] is not None else nq * k
         if out is None:
             ids = torch.empty(total, dtype=torch.int64, device=Q.device)
             dists = torch.empty(total, dtype=torch.float32, device=Q.device)
@@ -213,3 +274,78 @@ class Index:
         if k_per_query is None:
             ids, dists = ids.view(nq, k), dists.view(nq, k)
         return (ids, dists, st) if stats else (ids, dists)
+
+
+class Plan:
+    """A captured launch sequence for one batch (HIP graph); replay with ``launch()``.
+    Outputs live in ``ids`` / ``dists`` (flat CSR in query order) and ``qstats``."""
+
+    def __init__(self, index, Q, k, c, beta, r_min, eps, precision, rescore, k_per_query,
+                 c_per_query, stats):
+        import torch
+        self.index, self.Q = index, Q
+        nq = Q.shape[0]
+        p, keep = index._params(k, c, beta, r_min, eps, precision, rescore, k_per_query,
+                                c_per_query)
+        total = int(keep[0].sum()) if keep[0] is not None else nq * k
+        self.ids = torch.empty(total, dtype=torch.int64, device=Q.device)
+        self.dists = torch.empty(total, dtype=torch.float32, device=Q.device)
+        self.qstats = (torch.empty((nq, QSTAT_WORDS), dtype=torch.int32, device=Q.device)
+                       if stats else None)
+        h = c_void_p()
+        torch.cuda.synchronize()
+        _check(lib().pdet_plan_create(index._h, c_void_p(Q.data_ptr()), nq, ctypes.byref(p),
+                                      c_void_p(self.ids.data_ptr()), c_void_p(self.dists.data_ptr()),
+                                      c_void_p(self.qstats.data_ptr()) if stats else None,
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().pdet_plan_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pdet_plan_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+class Server:
+    """Continuous-batching request loop over a resident index (see pdet.h)."""
+
+    def __init__(self, index, max_batch, lanes, k_max, precision, rescore, beta, r_min, eps,
+                 memory_budget):
+        self.index, self.k_max = index, k_max
+        p = ServerParams(max_batch, lanes, k_max, PRECISIONS[precision], rescore, beta, r_min,
+                         eps, memory_budget)
+        h = c_void_p()
+        _check(lib().pdet_server_create(index._h, ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, q: np.ndarray, k: int, c: float = 1.5) -> int:
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        rid = c_int64()
+        _check(lib().pdet_server_submit(self._h, q.ctypes.data_as(c_void_p), k, c,
+                                        ctypes.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int, k: int):
+        ids = np.empty(k, dtype=np.int64)
+        dists = np.empty(k, dtype=np.float32)
+        lat = c_double()
+        _check(lib().pdet_server_wait(self._h, rid, ids.ctypes.data_as(c_void_p),
+                                      dists.ctypes.data_as(c_void_p), ctypes.byref(lat)))
+        return ids, dists, lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().pdet_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pdet_server_free(self._h)
+            self._h = None
+
+    __del__ = close

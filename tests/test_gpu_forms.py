@@ -1,0 +1,137 @@
+"""GPU tests of the batching and serving forms and of the radius-schedule autotuner.
+
+* autotune: the tuned schedule is used when r_min <= 0 and matches an explicit call; the
+  number of rounds the batched bound kernel resolves never changes a result (checked
+  against the oracle for 1 and 8 resolved rounds).
+* plans: a HIP-graph replay of a batch with uneven k and c equals the eager call, replay
+  after replay, with eager work in between, and after the query buffer is rewritten.
+* serving: each result is the same alone and in a mix of concurrently submitted requests,
+  and equals the batched call.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_24920_amd import pdet
+from paper_2603_24920_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    w = wl.SMALL_MIXTURE
+    X, A, sid = w.data(), w.proj(), w.sample()
+    print(f"\n[forms] n={len(X)} d={X.shape[1]}", flush=True)
+    Xd = torch.from_numpy(X).cuda()
+    idx = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=("bf16",))
+    Q = w.queries()
+    return w, X, A, sid, idx, Q, torch.from_numpy(Q).cuda()
+
+
+def uneven(nq, seed=5):
+    rng = np.random.default_rng(seed)
+    return (rng.choice([1, 10, 100], size=nq).astype(np.int32),
+            rng.choice([1.2, 1.5, 2.0], size=nq).astype(np.float64))
+
+
+def test_autotune_sets_schedule_and_auto_radius_matches(env):
+    w, X, A, sid, idx, Q, Qd = env
+    t = idx.autotune(Qd[:64].contiguous(), k=w.k, c=w.c, beta=w.beta)
+    print(f"[autotune] {t}", flush=True)
+    assert t["r_min"] > 0 and 1 <= t["rounds_resolved"] <= 8
+    a_ids, a_d = idx.query(Qd, k=w.k, c=w.c, beta=w.beta, r_min=0.0)
+    e_ids, e_d = idx.query(Qd, k=w.k, c=w.c, beta=w.beta, r_min=t["r_min"])
+    assert torch.equal(a_ids, e_ids) and torch.equal(a_d, e_d)
+
+
+@pytest.mark.parametrize("rounds", [1, 8])
+def test_rounds_resolved_never_changes_results(env, rounds):
+    w, X, A, sid, idx, Q, Qd = env
+    idx.set_tuning(0.5, rounds)
+    ids, dists, st = idx.query(Qd, k=w.k, c=w.c, beta=0.05, r_min=0.5, stats=True)
+    ids = ids.cpu().numpy()
+    B = idx.export(pdet.X_BREAKPOINTS).astype(np.float64)
+    codes = np.ascontiguousarray(idx.export(pdet.X_CODES)[:, :, :w.K])
+    ref = oracle.build_index(X, A, sid, w.L, w.K, w.Nr, w.max_leaf, B=B, codes=codes)
+    eps = pdet.epsilon(w.K, w.L)
+    same = 0
+    for qi in range(len(Q)):
+        res = oracle.query(ref, X, Q[qi], w.k, w.c, 0.05, 0.5, eps)
+        same += int(np.array_equal(ids[qi], res.ids))
+    assert same >= len(Q) - 1, same
+    if rounds == 1:   # the per-query refinement of open leaves runs
+        assert st.cpu().numpy()[:, pdet.QSTAT["rounds"]].max() > 2
+
+
+def test_plan_replays_equal_eager_calls(env):
+    w, X, A, sid, idx, Q, Qd = env
+    ks, cs = uneven(len(Q))
+    Qbuf = Qd.clone()
+    plan = idx.plan(Qbuf, k=0, beta=0.05, r_min=3.0, k_per_query=ks, c_per_query=cs,
+                    stats=True)
+    e_ids, e_d, e_st = idx.query(Qd, k=0, beta=0.05, r_min=3.0, k_per_query=ks,
+                                 c_per_query=cs, stats=True)
+    for rep in range(3):
+        plan.ids.fill_(-7)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.ids, e_ids) and torch.equal(plan.dists, e_d), rep
+        assert torch.equal(plan.qstats, e_st), rep
+        # eager work between replays
+        idx.query(Qd[:7].contiguous(), k=5, beta=0.1, r_min=2.0)
+        torch.cuda.synchronize()
+    # new queries in the same buffer
+    Q2 = torch.from_numpy(w.queries(len(Q) + 50)[50:]).cuda()
+    Qbuf.copy_(Q2)
+    torch.cuda.synchronize()
+    plan.launch()
+    torch.cuda.synchronize()
+    f_ids, f_d = idx.query(Q2, k=0, beta=0.05, r_min=3.0, k_per_query=ks, c_per_query=cs)
+    assert torch.equal(plan.ids, f_ids) and torch.equal(plan.dists, f_d)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_server_results_same_alone_and_in_the_mix(env, precision):
+    w, X, A, sid, idx, Q, Qd = env
+    ks, cs = uneven(len(Q), seed=9)
+    ks = np.minimum(ks, 50)
+    ref_ids, ref_d = idx.query(Qd, k=0, beta=0.05, r_min=3.0, k_per_query=ks, c_per_query=cs,
+                               precision=precision, rescore=4)
+    ref_ids, ref_d = ref_ids.cpu().numpy(), ref_d.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(ks)])
+    sv = idx.server(max_batch=16, lanes=2, k_max=50, precision=precision, beta=0.05, r_min=3.0)
+    # alone: one request in flight at a time
+    alone = []
+    for qi in range(12):
+        rid = sv.submit(Q[qi], int(ks[qi]), float(cs[qi]))
+        alone.append(sv.wait(rid, int(ks[qi])))
+    # mix: two client threads submit everything at once
+    rids = [None] * len(Q)
+
+    def client(sl):
+        for qi in sl:
+            rids[qi] = sv.submit(Q[qi], int(ks[qi]), float(cs[qi]))
+
+    th = [threading.Thread(target=client, args=(range(j, len(Q), 2),)) for j in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    mix = [sv.wait(rids[qi], int(ks[qi])) for qi in range(len(Q))]
+    st = sv.stats()
+    print(f"[server {precision}] {st}", flush=True)
+    sv.close()
+    for qi in range(len(Q)):
+        np.testing.assert_array_equal(mix[qi][0], ref_ids[off[qi]:off[qi + 1]])
+        np.testing.assert_array_equal(mix[qi][1], ref_d[off[qi]:off[qi + 1]])
+        if qi < 12:
+            np.testing.assert_array_equal(alone[qi][0], mix[qi][0])
+            np.testing.assert_array_equal(alone[qi][1], mix[qi][1])
+    assert st["completed"] == 12 + len(Q)
+    assert st["mean_batch"] > 1.0          # the mix was batched
+    assert st["p99_ms"] >= st["p50_ms"] > 0
