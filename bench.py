@@ -77,7 +77,11 @@ def main():
     ap.add_argument("--r-min", type=float, default=None)
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-lowp", action="store_true", help="skip the bf16 comparison")
+    ap.add_argument("--no-lowp", action="store_true", help="skip the bf16 / fp8 comparison")
+    ap.add_argument("--lowp", default="bf16,fp8", help="low-precision verification forms")
+    ap.add_argument("--rcap", type=int, default=4, help="rounds resolved (with --beta/--r-min)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-plan", action="store_true", help="skip the graph-launched batch")
     ap.add_argument("--no-recall", action="store_true",
                     help="with --beta/--r-min: skip the ground truth (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -116,42 +120,51 @@ def main():
     pdet.set_timing(True)
 
     # ---- untimed calibration: index, ground truth, beta / r_min per recall target
-    idx = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=() if args.no_lowp else ("bf16",))
+    lowp_forms = [] if args.no_lowp else [f for f in args.lowp.split(",") if f]
+    idx = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=tuple(lowp_forms))
     nrec = min(args.recall_queries, nq)
     Qr = Qd[:nrec].contiguous()
+    Qp = Qd[:256].contiguous()
     if not args.no_recall:
         exact_ids, _ = idx.query(Qr, k=10, c=w.c, beta=1.0, r_min=1e30)
         exact_ids = exact_ids.cpu().numpy()
         log(f"[bench] ground truth for {nrec} queries (exhaustive mode)")
 
     def calibrate(precision):
+        """(beta, r_min, rounds resolved, recall@10) at the smallest beta reaching 0.9."""
         if args.no_recall:
             if args.beta is None or args.r_min is None:
                 raise SystemExit("--no-recall needs --beta and --r-min")
-            return args.beta, args.r_min, None
+            return args.beta, args.r_min, args.rcap, None
+
+        def at(beta):
+            if args.r_min is not None:
+                idx.set_tuning(args.r_min, args.rcap)
+                t = dict(r_min=args.r_min, rounds_resolved=args.rcap)
+            else:
+                t = idx.autotune(Qp, k=w.k, c=w.c, beta=beta, precision=precision)
+            ids, _ = idx.query(Qr, k=w.k, c=w.c, beta=beta, r_min=t["r_min"],
+                               precision=precision, rescore=4)
+            rec = recall_at(ids.cpu().numpy(), exact_ids)
+            log(f"[bench] {precision} beta={beta} r_min={t['r_min']:.4g} "
+                f"rounds_resolved={t['rounds_resolved']} recall@10={rec:.4f}")
+            return beta, t["r_min"], t["rounds_resolved"], rec
+
         if args.beta is not None:
-            r = args.r_min or autotune_r_min(idx, Qd[:256].contiguous(), w.k, w.c, args.beta)
-            ids, _ = idx.query(Qr, k=w.k, c=w.c, beta=args.beta, r_min=r, precision=precision)
-            return args.beta, r, recall_at(ids.cpu().numpy(), exact_ids)
+            return at(args.beta)
         chosen = None
         for beta in BETA_LADDER:
-            r = autotune_r_min(idx, Qd[:256].contiguous(), w.k, w.c, beta)
-            ids, _ = idx.query(Qr, k=w.k, c=w.c, beta=beta, r_min=r, precision=precision)
-            rec = recall_at(ids.cpu().numpy(), exact_ids)
-            log(f"[bench] {precision} beta={beta} r_min={r:.4g} recall@10={rec:.4f}")
-            if rec >= 0.9:
-                chosen = (beta, r, rec)
+            res = at(beta)
+            if res[3] >= 0.9:
+                chosen = res
             else:
                 break
         if chosen is None:
             raise SystemExit("no beta on the ladder reaches recall@10 >= 0.9")
         return chosen
 
-    beta, r_min, rec = calibrate("fp32")
-    lowp = None
-    if not args.no_lowp:
-        lbeta, lr, lrec = calibrate("bf16")
-        lowp = dict(precision="bf16", beta=lbeta, r_min=lr, recall_at_10=lrec)
+    beta, r_min, rcap, rec = calibrate("fp32")
+    lowp_cal = {f: calibrate(f) for f in lowp_forms}
     idx.close()
     del idx
     torch.cuda.synchronize()
@@ -163,6 +176,7 @@ def main():
         ix = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf)
         torch.cuda.synchronize()
         tbt = pdet.get_timing()
+        ix.set_tuning(r_min, rcap)
         tq = time.perf_counter()
         ids, dists, st = ix.query(Qd, k=w.k, c=w.c, beta=beta, r_min=r_min, stats=True)
         torch.cuda.synchronize()
@@ -171,7 +185,9 @@ def main():
         if record is not None:
             record.append(dict(build_s=tq - tb, query_s=te - tq, tb=tbt, tq=tqt,
                                ncand=st[:, 1].to(torch.int64).sum().item(),
-                               stops=st[:, 2].cpu().numpy()))
+                               stops=st[:, 2].cpu().numpy(), qtime=st[:, 6].cpu().numpy(),
+                               visits=st[:, 7].cpu().numpy(),
+                               khz=ix.info()["wall_clock_khz"]))
         ix.close()
 
     for _ in range(args.warmup):
@@ -199,20 +215,52 @@ def main():
     enc_ms = float(np.mean([r["tb"]["build_encode_ms"] for r in recs]))
     enc_bytes = w.n * (4 * w.d + 16 * w.L)
 
-    # bf16 form at its own recall-matched beta (same steps, query phase only)
-    if lowp is not None:
-        ix = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=("bf16",))
+    # resident index with every low-precision copy for the forms below (query phase only)
+    ix = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=tuple(lowp_forms))
+
+    def timed(fn):
         ts = []
         for it in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            ix.query(Qd, k=w.k, c=w.c, beta=lowp["beta"], r_min=lowp["r_min"], precision="bf16",
-                     rescore=4)
+            fn()
             torch.cuda.synchronize()
             if it >= args.warmup:
                 ts.append(time.perf_counter() - t1)
-        lowp["qps"] = nq / float(np.mean(ts))
-        ix.close()
+        return float(np.mean(ts))
+
+    # precision forms at their own recall-matched beta
+    lowp = {}
+    for f, (lb, lr, lc, lrec) in lowp_cal.items():
+        ix.set_tuning(lr, lc)
+        sec = timed(lambda: ix.query(Qd, k=w.k, c=w.c, beta=lb, r_min=lr, precision=f,
+                                     rescore=4))
+        lowp[f] = dict(beta=lb, r_min=lr, rounds_resolved=lc, recall_at_10=lrec, qps=nq / sec,
+                       rescore=4)
+        log(f"[bench] {f}: {lowp[f]}")
+
+    # batching form: one graph-launched batch with k in {1,10,100}, c in {1.2,1.5,2.0}
+    batching = None
+    if not args.no_plan:
+        ix.set_tuning(r_min, rcap)
+        rng = np.random.default_rng(7)
+        ks = rng.choice([1, 10, 100], size=nq).astype(np.int32)
+        cs = rng.choice([1.2, 1.5, 2.0], size=nq)
+        plan = ix.plan(Qd, k=0, beta=beta, r_min=r_min, k_per_query=ks, c_per_query=cs)
+        sec_plan = timed(plan.launch)
+        sec_eager = timed(lambda: ix.query(Qd, k=0, beta=beta, r_min=r_min, k_per_query=ks,
+                                           c_per_query=cs))
+        plan.close()
+        batching = dict(qps_graph=nq / sec_plan, qps_eager=nq / sec_eager,
+                        k_mix=[1, 10, 100], c_mix=[1.2, 1.5, 2.0], beta=beta, r_min=r_min)
+        log(f"[bench] batching: {batching}")
+
+    # serving form: Poisson arrivals into the continuous-batching server
+    serving = None
+    if not args.no_serve:
+        serving = serve_measurement(ix, Q, w, beta, r_min, rcap)
+        log(f"[bench] serving: {serving}")
+    ix.close()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, X, A, sid, Q, beta, r_min)
 
@@ -231,13 +279,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "L": w.L, "K": w.K, "Nr": w.Nr,
                    "max_leaf": w.max_leaf, "nq": nq, "k": w.k, "c": w.c, "beta": beta,
-                   "r_min": r_min, "verify": "fp32 (fp64 accumulate)"},
+                   "r_min": r_min, "rounds_resolved": rcap,
+                   "verify": "fp32 (fp64 accumulate)"},
         "recall_at_10": rec,
         "build_mpts_per_s": mpts,
         "build_ms": 1e3 * build_s,
         "query_ms": 1e3 * query_s,
         "mean_candidates_per_query": ncand / nq,
         "stop_rule_A_fraction": float(np.mean([np.mean(r["stops"] == 1) for r in recs])),
+        "per_query_search_us": {
+            "p50": float(np.percentile(recs[-1]["qtime"], 50) * 1e3 / recs[-1]["khz"]),
+            "p99": float(np.percentile(recs[-1]["qtime"], 99) * 1e3 / recs[-1]["khz"]),
+            "max": float(recs[-1]["qtime"].max() * 1e3 / recs[-1]["khz"])},
+        "mean_point_visits_per_query": float(recs[-1]["visits"].mean()),
         "roofline": {"bound": "hbm", "kernel": "q_main", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_alg,
@@ -247,20 +301,68 @@ def main():
                                   "ms": enc_ms,
                                   "tflops": 2.0 * w.n * w.d * 16 * w.L / (enc_ms * 1e-3) / 1e12},
         "lowp": lowp,
+        "batching": batching,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def serve_measurement(ix, Q, w, beta, r_min, rcap, seconds=1.0, max_batch=1024):
+    """Saturation QPS from a burst, then Poisson arrivals at fractions of it (capped by
+    what one Python client thread can submit): p50 / p99 latency and achieved QPS."""
+    ix.set_tuning(r_min, rcap)
+    out = {}
+    sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min)
+    n_burst = min(len(Q), 4096)
+    t0 = time.perf_counter()
+    rids = [sv.submit(Q[i], w.k, w.c) for i in range(n_burst)]
+    for r in rids:
+        sv.wait(r, w.k)
+    sat = n_burst / (time.perf_counter() - t0)
+    out["burst"] = dict(sv.stats(), requests=n_burst)
+    sv.close()
+    client_cap = 50000.0
+    rng = np.random.default_rng(11)
+    for frac in (0.25, 0.5, 0.9):
+        rate = min(frac * sat, client_cap)
+        sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min)
+        nreq = max(200, int(rate * seconds))
+        gaps = rng.exponential(1.0 / rate, size=nreq)
+        t_arr = np.cumsum(gaps)
+        rids = []
+        t0 = time.perf_counter()
+        for i in range(nreq):
+            while time.perf_counter() - t0 < t_arr[i]:
+                pass
+            rids.append(sv.submit(Q[i % len(Q)], w.k, w.c))
+        for r in rids:
+            sv.wait(r, w.k)
+        st = sv.stats()
+        sv.close()
+        out[f"poisson_{int(frac * 100)}pct"] = dict(offered_qps=rate, achieved_qps=st["qps"],
+                                                    p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
+                                                    mean_batch=st["mean_batch"], requests=nreq)
+    out["saturation_qps_burst"] = sat
+    out["note"] = "offered rate capped at 50k/s by the single Python client thread"
+    return out
 
 
 def cpu_baseline(w, X, A, sid, Q, beta, r_min, nq_cpu=20):
     """The FP64 oracle, single-threaded, on this host: full index build over the same data,
     then `nq_cpu` queries of the batch with the GPU's beta and r_min."""
     import oracle
+    from paper_2603_24920_amd import workloads as wl
     try:
         from threadpoolctl import threadpool_limits
         lim = threadpool_limits(1)
     except Exception:  # pragma: no cover
         lim = None
+    # bounded sample: the oracle's index over at most 2e8 coordinates of the same data
+    n_cpu = min(w.n, int(2e8 // w.d))
+    if n_cpu < w.n:
+        X = X[:n_cpu]
+        sid = wl.sample_ids(n_cpu, wl.sample_size(n_cpu, w.sample_frac, w.Nr), w.seeds["sample"])
     t0 = time.perf_counter()
     idx = oracle.build_index(X, A, sid, w.L, w.K, w.Nr, w.max_leaf)
     tb = time.perf_counter() - t0
@@ -272,9 +374,10 @@ def cpu_baseline(w, X, A, sid, Q, beta, r_min, nq_cpu=20):
     if lim is not None:
         lim.unregister() if hasattr(lim, "unregister") else None
     return {"value": nq_cpu / tq, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nq_cpu} queries of the {w.name} batch on the oracle's own full index "
-                      f"(build {tb:.1f}s = {w.n / tb / 1e6:.3f} Mpts/s, single thread, FP64)",
-            "build_mpts_per_s": w.n / tb / 1e6}
+            "sample": f"{nq_cpu} queries of the {w.name} batch on the oracle's own index over "
+                      f"the first {n_cpu} points (build {tb:.1f}s = {n_cpu / tb / 1e6:.3f} Mpts/s, "
+                      f"single thread, FP64)",
+            "build_mpts_per_s": n_cpu / tb / 1e6}
 
 
 if __name__ == "__main__":

@@ -116,6 +116,9 @@ typedef struct {
 #define PDET_QSTAT_LEAVES 3   /* leaves admitted                                            */
 #define PDET_QSTAT_HSUM 4     /* sum of candidate ids mod 2^32                               */
 #define PDET_QSTAT_HMIX 5     /* sum of mix32(id) mod 2^32, mix32 = murmur3 finaliser        */
+#define PDET_QSTAT_TIME 6     /* device time of the query's search in wall-clock ticks       */
+                              /* (pdet_index_info.wall_clock_khz ticks per millisecond)      */
+#define PDET_QSTAT_VISITS 7   /* point occurrences examined (a point counts once per leaf)   */
 
 /*
  * Answer nq queries (device float32 [nq][d]).
@@ -141,6 +144,7 @@ typedef struct {
   uint32_t lowp_copies;
   int64_t leaves[PDET_MAX_L];   /* non-empty leaves per tree                          */
   int64_t device_bytes;         /* device memory owned by the index                   */
+  int32_t wall_clock_khz;       /* device wall-clock rate (query timing stats)        */
 } pdet_index_info;
 
 pdet_status pdet_info(const pdet_index* idx, pdet_index_info* out);
@@ -198,7 +202,7 @@ pdet_status pdet_get_timing(pdet_timing* out);
  * beta*n + k, at r_min/c it does not). Runs the pilot queries (device float32
  * [n_pilot][d]) from a tiny first radius, sets the index's tuned r_min one ladder step
  * below the median terminating radius, then sets how many rounds the batched bound kernel
- * resolves (rounds_resolved, 1..8) to cover 95% of the pilots. Queries passing r_min <= 0
+ * resolves (rounds_resolved, 1..8) to cover the rounds every pilot query needed. Queries passing r_min <= 0
  * use the tuned value. Must not run concurrently with queries on the same index.
  */
 typedef struct {

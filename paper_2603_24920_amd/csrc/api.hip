@@ -291,6 +291,9 @@ pdet_status pdet_info(const pdet_index* idx, pdet_index_info* out) {
     out->lowp_copies = idx->lowp;
     for (int i = 0; i < idx->L; ++i) out->leaves[i] = idx->nl[i];
     out->device_bytes = idx->device_bytes();
+    int khz = 0;
+    PDET_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, idx->device));
+    out->wall_clock_khz = khz;
   });
 }
 

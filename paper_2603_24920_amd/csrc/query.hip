@@ -32,6 +32,8 @@ constexpr int QT = 64;           // queries per q_rho block (group tests in sub-
 constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
 constexpr int GL = 16;           // leaves per pruning group
 constexpr int RCAP_MAX = 8;      // most rounds q_rho resolves (the index's rcap <= this)
+constexpr int RWIN = 3;          // rounds resolved per refinement step inside q_main
+constexpr int GCH = 2048;        // groups per refinement chunk (LDS bitmap of GCH bits)
 constexpr int TREE_SHIFT = 28;   // list entries pack (tree << 28) | leaf
 
 struct QArgs {
@@ -71,6 +73,7 @@ struct QArgs {
   int32_t* qstats;
   int rescore, NM;
   int rcap;                  // rounds resolved by q_rho; later ones are refined per query
+  int lpc, lpc32;            // lanes per candidate row: verification form, float32 re-rank
   int64_t q0;
   int nslots;
   double r_min, eps;
@@ -185,75 +188,96 @@ __device__ inline bool lex_less(double a, int32_t ia, double b, int32_t ib) {
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
-// Euclidean distance of candidate `id` to the query, computed by a group of 16 lanes
-// (every lane of the group must call it). PREC 0: float32 data, FP64 accumulation;
+constexpr int NCH = 2;           // 16-byte loads a lane keeps in flight per candidate row
+
+// Euclidean distance of candidate `id` to the query, computed by a group of `lpc` lanes
+// (a power of two; every lane of the group must call it). Each lane issues its (up to NCH)
+// 16-byte loads of the row before using them. PREC 0: float32 data, FP64 accumulation;
 // 1: bf16 copy; 2: fp8 e4m3 copy with a per-row scale (FP32 accumulation).
 template <int PREC>
-__device__ inline double cand_dist(const QArgs& a, int32_t id, const float* qv, int l16) {
+__device__ inline double cand_dist(const QArgs& a, int32_t id, const float* qv, int lg, int lpc) {
+  double accd = 0.0;
+  float accf = 0.0f;
   if constexpr (PREC == PDET_FP32) {
     const float* xr = a.X + (int64_t)id * a.d;
-    double acc = 0.0;
     if ((a.d & 3) == 0) {
       const float4* x4 = reinterpret_cast<const float4*>(xr);
       const float4* q4 = reinterpret_cast<const float4*>(qv);
-      for (int c = l16; c < (a.d >> 2); c += 16) {
-        const float4 x = x4[c], q = q4[c];
-        const double d0 = (double)x.x - (double)q.x, d1 = (double)x.y - (double)q.y;
-        const double d2 = (double)x.z - (double)q.z, d3 = (double)x.w - (double)q.w;
-        acc = fma(d0, d0, acc); acc = fma(d1, d1, acc);
-        acc = fma(d2, d2, acc); acc = fma(d3, d3, acc);
+      const int n4 = a.d >> 2;
+      for (int base = 0; base < n4; base += NCH * lpc) {
+        float4 buf[NCH];
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int c = base + lg + u * lpc;
+          if (c < n4) buf[u] = x4[c];
+        }
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int c = base + lg + u * lpc;
+          if (c < n4) {
+            const float4 x = buf[u], q = q4[c];
+            const double d0 = (double)x.x - (double)q.x, d1 = (double)x.y - (double)q.y;
+            const double d2 = (double)x.z - (double)q.z, d3 = (double)x.w - (double)q.w;
+            accd = fma(d0, d0, accd); accd = fma(d1, d1, accd);
+            accd = fma(d2, d2, accd); accd = fma(d3, d3, accd);
+          }
+        }
       }
     } else {
-      for (int t = l16; t < a.d; t += 16) {
+      for (int t = lg; t < a.d; t += lpc) {
         const double df = (double)xr[t] - (double)qv[t];
-        acc = fma(df, df, acc);
+        accd = fma(df, df, accd);
       }
     }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    return sqrt(acc);
-  } else if constexpr (PREC == PDET_BF16) {
-    const uint4* xr = reinterpret_cast<const uint4*>(a.xbf + (int64_t)id * a.dpad);
-    float acc = 0.0f;
-    for (int c = l16; c < (a.dpad >> 3); c += 16) {
-      const uint4 v = xr[c];
-      const float* q = qv + c * 8;
-      float df;
-      df = bf16_lo(v.x) - q[0]; acc = fmaf(df, df, acc);
-      df = bf16_hi(v.x) - q[1]; acc = fmaf(df, df, acc);
-      df = bf16_lo(v.y) - q[2]; acc = fmaf(df, df, acc);
-      df = bf16_hi(v.y) - q[3]; acc = fmaf(df, df, acc);
-      df = bf16_lo(v.z) - q[4]; acc = fmaf(df, df, acc);
-      df = bf16_hi(v.z) - q[5]; acc = fmaf(df, df, acc);
-      df = bf16_lo(v.w) - q[6]; acc = fmaf(df, df, acc);
-      df = bf16_hi(v.w) - q[7]; acc = fmaf(df, df, acc);
-    }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    return sqrt((double)acc);
   } else {
-    const uint4* xr = reinterpret_cast<const uint4*>(a.xf8 + (int64_t)id * a.dpad);
-    const float sc = a.xscale[id];
-    float acc = 0.0f;
-    for (int c = l16; c < (a.dpad >> 4); c += 16) {
-      const uint4 v = xr[c];
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-      const float* q = qv + c * 16;
+    const uint4* xr = (PREC == PDET_BF16)
+                          ? reinterpret_cast<const uint4*>(a.xbf + (int64_t)id * a.dpad)
+                          : reinterpret_cast<const uint4*>(a.xf8 + (int64_t)id * a.dpad);
+    const int nv = (PREC == PDET_BF16) ? (a.dpad >> 3) : (a.dpad >> 4);
+    const float sc = (PREC == PDET_BF16) ? 1.0f : a.xscale[id];
+    for (int base = 0; base < nv; base += NCH * lpc) {
+      uint4 buf[NCH];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int wi = (int)w[u];
-        const float x0 = __builtin_amdgcn_cvt_f32_fp8(wi, 0) * sc - q[u * 4 + 0];
-        const float x1 = __builtin_amdgcn_cvt_f32_fp8(wi, 1) * sc - q[u * 4 + 1];
-        const float x2 = __builtin_amdgcn_cvt_f32_fp8(wi, 2) * sc - q[u * 4 + 2];
-        const float x3 = __builtin_amdgcn_cvt_f32_fp8(wi, 3) * sc - q[u * 4 + 3];
-        acc = fmaf(x0, x0, acc); acc = fmaf(x1, x1, acc);
-        acc = fmaf(x2, x2, acc); acc = fmaf(x3, x3, acc);
+      for (int u = 0; u < NCH; ++u) {
+        const int c = base + lg + u * lpc;
+        if (c < nv) buf[u] = xr[c];
+      }
+#pragma unroll
+      for (int u = 0; u < NCH; ++u) {
+        const int c = base + lg + u * lpc;
+        if (c >= nv) continue;
+        const uint4 v = buf[u];
+        if constexpr (PREC == PDET_BF16) {
+          const float* q = qv + c * 8;
+          float df;
+          df = bf16_lo(v.x) - q[0]; accf = fmaf(df, df, accf);
+          df = bf16_hi(v.x) - q[1]; accf = fmaf(df, df, accf);
+          df = bf16_lo(v.y) - q[2]; accf = fmaf(df, df, accf);
+          df = bf16_hi(v.y) - q[3]; accf = fmaf(df, df, accf);
+          df = bf16_lo(v.z) - q[4]; accf = fmaf(df, df, accf);
+          df = bf16_hi(v.z) - q[5]; accf = fmaf(df, df, accf);
+          df = bf16_lo(v.w) - q[6]; accf = fmaf(df, df, accf);
+          df = bf16_hi(v.w) - q[7]; accf = fmaf(df, df, accf);
+        } else {
+          const float* q = qv + c * 16;
+          const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const int wi = (int)w[h];
+            const float x0 = __builtin_amdgcn_cvt_f32_fp8(wi, 0) * sc - q[h * 4 + 0];
+            const float x1 = __builtin_amdgcn_cvt_f32_fp8(wi, 1) * sc - q[h * 4 + 1];
+            const float x2 = __builtin_amdgcn_cvt_f32_fp8(wi, 2) * sc - q[h * 4 + 2];
+            const float x3 = __builtin_amdgcn_cvt_f32_fp8(wi, 3) * sc - q[h * 4 + 3];
+            accf = fmaf(x0, x0, accf); accf = fmaf(x1, x1, accf);
+            accf = fmaf(x2, x2, accf); accf = fmaf(x3, x3, accf);
+          }
+        }
       }
     }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    return sqrt((double)acc);
+    accd = (double)accf;
   }
+  for (int o = lpc >> 1; o > 0; o >>= 1) accd += __shfl_xor(accd, o);
+  return sqrt(accd);
 }
 
 // Bitonic sort of (distance, id) pairs, ascending, over `len` (a power of two) entries.
@@ -305,13 +329,16 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   __shared__ uint32_t sh_scan[QM / 64 + 1];
   __shared__ uint32_t hist[256];
   __shared__ float st2[NRHO];
+  __shared__ uint32_t gopen[GCH / 32];
   __shared__ uint32_t ent_off[PDET_MAX_L + 1];
   __shared__ uint32_t s_m, s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix;
   __shared__ unsigned long long s_pts, s_cut;
 
   const int slot = blockIdx.x;
   const int64_t q = a.q0 + slot;
-  const int tid = threadIdx.x, lane = tid & 63, l16 = tid & 15, grp = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int lpc = a.lpc;                          // lanes per candidate (power of two)
+  const int lg = tid & (lpc - 1), grp = tid / lpc;
   const int k = a.qk[q];
   const int64_t T = a.qT[q];
   const int KL = (PREC == PDET_FP32) ? k : k * a.rescore;
@@ -332,9 +359,11 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   uint32_t* pre2 = a.adm2_pre + (int64_t)slot * (a.admcap + 1);
   int32_t* ast = a.adm_start + (int64_t)slot * (a.admcap + 1);
 
-  int64_t nS = 0, leaves = 0;
+  int64_t nS = 0, leaves = 0, visits = 0;
   uint32_t hsum = 0, hmix = 0;
   int stop = -1, rounds = 0;
+  int cap = a.rcap;            // rounds whose leaf indices are resolved
+  const uint64_t t_start = wall_clock64();
 
   auto merge = [&]() {
     const int used = KL + (int)s_ncb;
@@ -352,6 +381,7 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   auto traverse = [&](bool counting, int rho, uint32_t e_lo, uint32_t e_hi) -> uint32_t {
     uint32_t newc = 0;
     const uint32_t P0 = pre2[e_lo], P1 = pre2[e_hi];
+    visits += P1 - P0;
     if (tid == 0) s_ef = e_lo;
     __syncthreads();
     for (uint32_t base = P0; base < P1; base += QM) {
@@ -411,12 +441,12 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
         s_ef = ef + l2;
       }
       if (!counting) {
-        for (uint32_t c0 = 0; c0 < nb; c0 += QM / 16) {
+        for (uint32_t c0 = 0; c0 < nb; c0 += QM / lpc) {
           const uint32_t c = c0 + grp;
           const bool valid = c < nb;
           const int32_t cid = valid ? idbuf[c] : 0;
-          const double dd = cand_dist<PREC>(a, cid, qv, l16);
-          if (valid && l16 == 0 && lex_less(dd, cid, ld[KL - 1], li[KL - 1])) {
+          const double dd = cand_dist<PREC>(a, cid, qv, lg, lpc);
+          if (valid && lg == 0 && lex_less(dd, cid, ld[KL - 1], li[KL - 1])) {
             const uint32_t pos = atomicAdd(&s_ncb, 1u);
             ld[KL + pos] = dd;
             li[KL + pos] = cid;
@@ -429,22 +459,123 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
     return newc;
   };
 
-  for (int rho = 0; rho < NRHO - 1 && stop < 0; ++rho) {
-    rounds = rho + 1;
-    if (rho == a.rcap + 1) {
-      // exact first rounds of the leaves q_rho left open
-      for (int i = 0; i < a.L; ++i) {
-        uint8_t* rr = rq + (int64_t)i * a.nlpad;
-        for (int64_t leaf = tid; leaf < a.nl[i]; leaf += QM) {
-          if (rr[leaf] != (uint8_t)(a.rcap + 1)) continue;
-          const float lb2 = leaf_lb2(a.box[i], a.nl[i], leaf, qps + i * a.K, a.K);
-          int pos = 0;
-#pragma unroll
-          for (int sft = NRHO / 2; sft > 0; sft >>= 1)
-            if (st2[pos + sft - 1] < lb2) pos += sft;
-          rr[leaf] = (uint8_t)pos;
+  // Weighted radix select over list entries [e0, e1) keyed by (LB^2 bits, leaf ordinal):
+  // the smallest key whose inclusive weight prefix reaches R. Weights: the leaf sizes
+  // (by_counts) or the exact new-point counts admw[].
+  auto select_key = [&](uint32_t e0, uint32_t e1, uint32_t R, bool by_counts) {
+    unsigned long long prefix = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+      const int shift = 56 - 8 * pass;
+      hist[tid] = 0;
+      __syncthreads();
+      for (uint32_t e = e0 + tid; e < e1; e += QM) {
+        const unsigned long long key = ((unsigned long long)__float_as_uint(admlb[e]) << 32) |
+                                       (adm2[e] & ((1u << TREE_SHIFT) - 1));
+        if (pass == 0 || (key >> (shift + 8)) == prefix) {
+          const uint32_t wgt =
+              by_counts ? pre2[e + 1] - pre2[e]
+                        : __hip_atomic_load(&admw[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (wgt) atomicAdd(&hist[(key >> shift) & 255], wgt);
         }
       }
+      __syncthreads();
+      const uint32_t h = hist[tid];
+      uint32_t tot;
+      const uint32_t ex = block_excl_scan<QM>(h, sh_scan, &tot);
+      if (ex < R && ex + h >= R) {
+        s_cut = (prefix << 8) | (unsigned long long)tid;
+        s_newtot = R - ex;
+      }
+      __syncthreads();
+      prefix = s_cut;
+      R = s_newtot;
+      __syncthreads();
+    }
+    return prefix;
+  };
+
+  // Keeps the entries of [e0, e1) whose key is <= cut, compacted in place (writes never pass
+  // the read position), with their prefix sums; returns how many remain.
+  auto keep_upto = [&](uint32_t e0, uint32_t e1, unsigned long long cut) -> uint32_t {
+    const uint32_t P0 = pre2[e0];
+    uint32_t nm = 0, nP = 0;
+    for (uint32_t b = e0; b < e1; b += QM) {
+      const uint32_t e = b + tid;
+      bool inc = false;
+      uint32_t cnt = 0, en = 0;
+      int32_t st0 = 0;
+      float lb = 0.0f;
+      if (e < e1) {
+        en = adm2[e];
+        st0 = ast[e];
+        lb = admlb[e];
+        inc = ((((unsigned long long)__float_as_uint(lb)) << 32) |
+               (en & ((1u << TREE_SHIFT) - 1))) <= cut;
+        if (inc) cnt = pre2[e + 1] - pre2[e];
+      }
+      uint32_t t1, t2;
+      const uint32_t pos = block_excl_scan<QM>(inc ? 1u : 0u, sh_scan, &t1);
+      const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &t2);
+      if (inc) {
+        adm2[e0 + nm + pos] = en;
+        ast[e0 + nm + pos] = st0;
+        admlb[e0 + nm + pos] = lb;
+        pre2[e0 + nm + pos] = P0 + nP + pre;
+      }
+      nm += t1;
+      nP += t2;
+      __syncthreads();   // pre2[e + 1] of this chunk's last entry is read before it moves
+    }
+    if (tid == 0) pre2[e0 + nm] = P0 + nP;
+    __syncthreads();
+    return nm;
+  };
+
+  for (int rho = 0; rho < NRHO - 1 && stop < 0; ++rho) {
+    rounds = rho + 1;
+    if (rho == cap + 1) {
+      // Leaves left open (mark cap+1: "first round > cap") get their exact first round if it
+      // is within the next RWIN rounds; groups whose union box lies beyond stay open. Per
+      // chunk of groups: group tests into an LDS bitmap, then one leaf per thread.
+      const int ncap = std::min(NRHO - 2, cap + RWIN);
+      const uint8_t mark = (uint8_t)(cap + 1), nmark = (uint8_t)(ncap + 1);
+      for (int i = 0; i < a.L; ++i) {
+        uint8_t* rr = rq + (int64_t)i * a.nlpad;
+        const int64_t nl = a.nl[i], ng = a.ng[i];
+        const float* gb = a.gbox[i];
+        const float* qi = qps + i * a.K;
+        for (int64_t g0 = 0; g0 < ng; g0 += GCH) {
+          for (int w = tid; w < GCH / 32; w += QM) gopen[w] = 0u;
+          __syncthreads();
+          for (int64_t g = g0 + tid; g < std::min<int64_t>(ng, g0 + GCH); g += QM) {
+            float acc = 0.0f;
+            for (int j = 0; j < a.K; ++j) {
+              const float lo = gb[(int64_t)j * ng + g], hi = gb[(int64_t)(a.K + j) * ng + g];
+              const float gap = fmaxf(0.0f, fmaxf(lo - qi[j], qi[j] - hi));
+              acc = __fmaf_rn(gap, gap, acc);
+            }
+            if (acc <= st2[ncap]) atomicOr(&gopen[(g - g0) >> 5], 1u << ((g - g0) & 31));
+          }
+          __syncthreads();
+          const int64_t l1 = std::min<int64_t>(nl, (g0 + GCH) * GL);
+          for (int64_t leaf = g0 * GL + tid; leaf < l1; leaf += QM) {
+            if (rr[leaf] != mark) continue;
+            const int64_t gl = leaf / GL - g0;
+            uint8_t r = nmark;
+            if ((gopen[gl >> 5] >> (gl & 31)) & 1u) {
+              const float lb2 = leaf_lb2(a.box[i], nl, leaf, qi, a.K);
+              int pos = 0;
+#pragma unroll
+              for (int sft = NRHO / 2; sft > 0; sft >>= 1)
+                if (st2[pos + sft - 1] < lb2) pos += sft;
+              r = (uint8_t)std::min(pos, ncap + 1);
+            }
+            rr[leaf] = r;
+          }
+          __syncthreads();
+        }
+      }
+      cap = ncap;
       __syncthreads();
     }
     // admitted leaves of every tree in this round, in tree order
@@ -511,79 +642,30 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
             nS += traverse(false, rho, e0, e1);
             continue;
           }
-          for (uint32_t e = e0 + tid; e < e1; e += QM) {
-            admw[e] = 0;
+          for (uint32_t e = e0 + tid; e < e1; e += QM)
             admlb[e] = leaf_lb2(a.box[i], a.nl[i], adm2[e] & ((1u << TREE_SHIFT) - 1),
                                 qps + i * a.K, a.K);
-          }
           __syncthreads();
-          const uint32_t new_i = traverse(true, rho, e0, e1);
+          uint32_t e1c = e1;
+          if (pts_i >= T) {
+            // A tree's leaves are disjoint, so at most |S| of their points are already in S:
+            // the shortest (LB^2, ordinal) prefix holding >= T points has >= T - |S| new
+            // points, and the leaf where |S| reaches T lies in it. Only it is counted.
+            const unsigned long long kap = select_key(e0, e1, (uint32_t)T, true);
+            e1c = e0 + keep_upto(e0, e1, kap);
+          }
+          for (uint32_t e = e0 + tid; e < e1c; e += QM) admw[e] = 0;
+          __syncthreads();
+          const uint32_t new_i = traverse(true, rho, e0, e1c);
           if (nS + (int64_t)new_i < T) {
+            if (e1c != e1) { stop = -2; break; }   // contradicts the bound above
             leaves += e1 - e0;
             nS += traverse(false, rho, e0, e1);
             continue;
           }
-          // weighted radix select over this tree's keys (LB^2 bits, leaf ordinal): the
-          // smallest key whose inclusive weight prefix reaches R = T - |S|
-          unsigned long long prefix = 0;
-          uint32_t R = (uint32_t)(T - nS);
-          for (int pass = 0; pass < 8; ++pass) {
-            const int shift = 56 - 8 * pass;
-            hist[tid] = 0;
-            __syncthreads();
-            for (uint32_t e = e0 + tid; e < e1; e += QM) {
-              const unsigned long long key =
-                  ((unsigned long long)__float_as_uint(admlb[e]) << 32) |
-                  (adm2[e] & ((1u << TREE_SHIFT) - 1));
-              if (pass == 0 || (key >> (shift + 8)) == prefix) {
-                const uint32_t wgt =
-                    __hip_atomic_load(&admw[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (wgt) atomicAdd(&hist[(key >> shift) & 255], wgt);
-              }
-            }
-            __syncthreads();
-            const uint32_t h = hist[tid];
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan<QM>(h, sh_scan, &tot);
-            if (ex < R && ex + h >= R) {
-              s_cut = (prefix << 8) | (unsigned long long)tid;
-              s_newtot = R - ex;
-            }
-            __syncthreads();
-            prefix = s_cut;
-            R = s_newtot;
-            __syncthreads();
-          }
-          const unsigned long long cut = prefix;
-          // keep this tree's leaves up to the cut (in place: writes never pass the read
-          // position); the list ends there
-          const uint32_t P0 = pre2[e0];
-          uint32_t nm = 0, nP = 0;
-          for (uint32_t b = e0; b < e1; b += QM) {
-            const uint32_t e = b + tid;
-            bool inc = false;
-            uint32_t cnt = 0, en = 0;
-            int32_t st0 = 0;
-            if (e < e1) {
-              en = adm2[e];
-              st0 = ast[e];
-              const uint32_t leaf = en & ((1u << TREE_SHIFT) - 1);
-              inc = ((((unsigned long long)__float_as_uint(admlb[e])) << 32) | leaf) <= cut;
-              if (inc) cnt = (uint32_t)a.lcount[i][leaf];
-            }
-            uint32_t t1, t2;
-            const uint32_t pos = block_excl_scan<QM>(inc ? 1u : 0u, sh_scan, &t1);
-            const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &t2);
-            if (inc) {
-              adm2[e0 + nm + pos] = en;
-              ast[e0 + nm + pos] = st0;
-              pre2[e0 + nm + pos] = P0 + nP + pre;
-            }
-            nm += t1;
-            nP += t2;
-          }
-          if (tid == 0) pre2[e0 + nm] = P0 + nP;
-          __syncthreads();
+          // the smallest key whose inclusive new-point prefix reaches R = T - |S|
+          const unsigned long long cut = select_key(e0, e1c, (uint32_t)(T - nS), false);
+          const uint32_t nm = keep_upto(e0, e1c, cut);
           leaves += nm;
           nS += traverse(false, rho, e0, e0 + nm);
           stop = 1;
@@ -599,12 +681,13 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
 
   if constexpr (PREC != PDET_FP32) {
     // re-rank the kept low-precision candidates with exact float32 distances
-    for (int t0 = 0; t0 < KL; t0 += QM / 16) {
-      const int t = t0 + grp;
+    const int lpc32 = a.lpc32, lg32 = tid & (lpc32 - 1), grp32 = tid / lpc32;
+    for (int t0 = 0; t0 < KL; t0 += QM / lpc32) {
+      const int t = t0 + grp32;
       const bool valid = t < KL && li[t] != INT32_MAX;
       const int32_t id = valid ? li[t] : 0;
-      const double dd = cand_dist<PDET_FP32>(a, id, qv, l16);
-      if (valid && l16 == 0) ld[t] = dd;
+      const double dd = cand_dist<PDET_FP32>(a, id, qv, lg32, lpc32);
+      if (valid && lg32 == 0) ld[t] = dd;
     }
     __syncthreads();
     int len = 1;
@@ -630,8 +713,8 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
     st[PDET_QSTAT_LEAVES] = (int32_t)leaves;
     st[PDET_QSTAT_HSUM] = (int32_t)s_hsum;
     st[PDET_QSTAT_HMIX] = (int32_t)s_hmix;
-    st[6] = 0;
-    st[7] = 0;
+    st[PDET_QSTAT_TIME] = (int32_t)std::min<uint64_t>(wall_clock64() - t_start, INT32_MAX);
+    st[PDET_QSTAT_VISITS] = (int32_t)std::min<int64_t>(visits, INT32_MAX);
   }
 }
 
@@ -770,6 +853,16 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   a.qstats = qc.qstats;
   a.rescore = qc.rescore;
   a.rcap = std::max(0, std::min(RCAP_MAX, ix.rcap));
+  // lanes per candidate: enough that each lane's share of a row is at most NCH 16-byte loads
+  auto lanes_for = [](int64_t chunks) {
+    int l = 4;
+    while (l < 64 && (int64_t)l * NCH < chunks) l <<= 1;
+    return l;
+  };
+  const int64_t ch32 = (ix.d % 4 == 0) ? ix.d / 4 : ix.d;
+  a.lpc32 = lanes_for(ch32);
+  a.lpc = qc.precision == PDET_FP32 ? a.lpc32
+          : lanes_for(qc.precision == PDET_BF16 ? ix.dpad / 8 : ix.dpad / 16);
   a.r_min = qc.r_min;
   a.eps = qc.eps;
   int NM = 1;

@@ -246,11 +246,12 @@ pdet_status pdet_autotune(pdet_index* idx, const float* pilot, int64_t n_pilot, 
       const int steps = std::max(0, med - 2);
       double r = r0;
       for (int i = 0; i < steps; ++i) r = c * r;
-      // rounds a tuned query needs: let the batched kernel resolve 95% of them
+      // rounds a tuned query needs: the batched kernel resolves every round a pilot query
+      // reached, so per-query refinement stays rare
       rounds = pilot_rounds(idx, pilot, n_pilot, k, c, beta, precision, r, s);
       const int32_t p95 = rounds[std::min(rounds.size() - 1, (size_t)(0.95 * rounds.size()))];
       idx->tuned_r_min = r;
-      idx->rcap = std::max(1, std::min(8, (int)p95 - 1));
+      idx->rcap = std::max(1, std::min(8, (int)rounds.back() - 1));
       out->r_min = r;
       out->rounds_resolved = idx->rcap;
       out->median_rounds = rounds[rounds.size() / 2];

@@ -19,7 +19,7 @@ FP32, BF16, FP8_E4M3 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 MAX_K, MAX_L, MAX_TOPK, MAX_ROUNDS = 16, 16, 1024, 255
 QSTAT_WORDS = 8
-QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5)
+QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits=7)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX = range(6)
 EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_info", "pdet_export", "pdet_project",
             "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
@@ -44,7 +44,7 @@ class IndexInfo(ctypes.Structure):
     _fields_ = [("n", c_int64), ("n_sample", c_int64), ("d", c_int32), ("K", c_int32),
                 ("L", c_int32), ("Nr", c_int32), ("max_leaf", c_int32),
                 ("lowp_copies", c_uint32), ("leaves", c_int64 * MAX_L),
-                ("device_bytes", c_int64)]
+                ("device_bytes", c_int64), ("wall_clock_khz", c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -176,12 +176,14 @@ class Index:
         h = c_void_p()
         _check(lib().pdet_build(c_void_p(X.data_ptr()), self.n, self.d, ctypes.byref(p),
                                 _stream(stream), ctypes.byref(h)))
-        self._h = h
+        self._h, self._lib = h, lib()
         self.K, self.L, self.Nr, self.max_leaf = K, L, Nr, max_leaf
 
     def close(self):
+        # the library handle is held on the object: module globals may already be gone when
+        # this runs at interpreter exit
         if getattr(self, "_h", None):
-            lib().pdet_free(self._h)
+            self._lib.pdet_free(self._h)
             self._h = None
 
     __del__ = close
@@ -191,7 +193,8 @@ class Index:
         _check(lib().pdet_info(self._h, ctypes.byref(inf)))
         return dict(n=inf.n, n_sample=inf.n_sample, d=inf.d, K=inf.K, L=inf.L, Nr=inf.Nr,
                     max_leaf=inf.max_leaf, lowp_copies=inf.lowp_copies,
-                    leaves=list(inf.leaves[:inf.L]), device_bytes=inf.device_bytes)
+                    leaves=list(inf.leaves[:inf.L]), device_bytes=inf.device_bytes,
+                    wall_clock_khz=inf.wall_clock_khz)
 
     def export(self, what: int, tree: int = 0) -> np.ndarray:
         nl = self.info()["leaves"]
@@ -298,14 +301,14 @@ class Plan:
                                       c_void_p(self.ids.data_ptr()), c_void_p(self.dists.data_ptr()),
                                       c_void_p(self.qstats.data_ptr()) if stats else None,
                                       ctypes.byref(h)))
-        self._h = h
+        self._h, self._lib = h, lib()
 
     def launch(self, stream=None):
         _check(lib().pdet_plan_launch(self._h, _stream(stream)))
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().pdet_plan_free(self._h)
+            self._lib.pdet_plan_free(self._h)
             self._h = None
 
     __del__ = close
@@ -321,7 +324,7 @@ class Server:
                          eps, memory_budget)
         h = c_void_p()
         _check(lib().pdet_server_create(index._h, ctypes.byref(p), ctypes.byref(h)))
-        self._h = h
+        self._h, self._lib = h, lib()
 
     def submit(self, q: np.ndarray, k: int, c: float = 1.5) -> int:
         q = np.ascontiguousarray(q, dtype=np.float32)
@@ -345,7 +348,7 @@ class Server:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().pdet_server_free(self._h)
+            self._lib.pdet_server_free(self._h)
             self._h = None
 
     __del__ = close

@@ -80,7 +80,8 @@ def test_plan_replays_equal_eager_calls(env):
         plan.launch()
         torch.cuda.synchronize()
         assert torch.equal(plan.ids, e_ids) and torch.equal(plan.dists, e_d), rep
-        assert torch.equal(plan.qstats, e_st), rep
+        keep = [0, 1, 2, 3, 4, 5, 7]          # word 6 is the query's device time
+        assert torch.equal(plan.qstats[:, keep], e_st[:, keep]), rep
         # eager work between replays
         idx.query(Qd[:7].contiguous(), k=5, beta=0.1, r_min=2.0)
         torch.cuda.synchronize()
