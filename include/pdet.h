@@ -71,8 +71,8 @@ typedef struct {
  * The data pointer is BORROWED: it must stay allocated and unchanged until
  * pdet_free(), because verification reads it. Everything derived from it
  * (breakpoints, codes, trees, low-precision copies) is owned by the index.
- * Errors: EUNSUPPORTED for n >= 2^28; EINVAL for n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power
- * of two in [2,256], max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range;
+ * Errors: EUNSUPPORTED for n >= 2^28 or a tree with 2^24 leaves or more; EINVAL for
+ * n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power of two in [2,256], max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range;
  * ENOMEM/EDEVICE from the runtime. On error *out is NULL.
  * Synchronises `stream` once (to size the leaf tables).
  */
@@ -136,6 +136,15 @@ typedef struct {
 pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
                        const pdet_query_params* p, int64_t* ids, float* dists,
                        int32_t* qstats, void* stream);
+
+/* Sizes the index's query workspace (per-query scratch: round-index tables, admitted-leaf
+ * lists, thresholds) for batches of up to nq queries, so that a later pdet_query of at most
+ * nq queries allocates nothing. Not an operation of the method itself: the search of
+ * Algorithm 5 needs this scratch, and a caller that serves a resident index wants it sized
+ * once, before the first batch. Device memory is taken with hipMalloc and kept until
+ * pdet_free; at most a third of free device memory (and 24 GiB) is used, so large batches
+ * are then run in chunks of query slots. Waits for `stream`. nq < 0 -> PDET_EINVAL. */
+pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream);
 
 /* Description of a built index. */
 typedef struct {

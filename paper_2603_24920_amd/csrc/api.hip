@@ -241,6 +241,9 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
       build_trees(*ix, s);
       sp.finish();
     }
+    for (int i = 0; i < ix->L; ++i)   // per-query leaf lists pack (round << 24) | leaf
+      PDET_REQUIRE(ix->nl[i] < (int64_t(1) << 24), PDET_EUNSUPPORTED,
+                   "a tree has 2^24 leaves or more (raise max_leaf)");
     {
       Span sp(s, &tm.build_lowp_ms);
       build_lowp_copies(*ix, s);
@@ -265,6 +268,16 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
     const QueryConfig qc = check_query(idx, queries, nq, p, ids, dists, qstats, k, c);
     if (nq == 0) return;
     run_query(*idx, qc, static_cast<hipStream_t>(stream));
+  });
+}
+
+pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream) {
+  return guarded([&] {
+    PDET_REQUIRE(idx, PDET_EINVAL, "NULL index");
+    PDET_REQUIRE(nq >= 0, PDET_EINVAL, "nq must be >= 0");
+    if (nq == 0) return;
+    WorkspaceLease lease(*idx);
+    reserve_workspace(*idx, lease.get(), nq, 0, static_cast<hipStream_t>(stream));
   });
 }
 

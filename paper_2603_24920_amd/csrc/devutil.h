@@ -7,6 +7,16 @@
 
 namespace pdet {
 
+// A value every lane of the wave holds (read from LDS after a barrier, say), moved to a
+// scalar register so that arithmetic on it stays scalar.
+__device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int32_t uni(int32_t v) { return (int32_t)__builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t uni(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Exclusive scan of one uint32 per thread over a workgroup of NT threads.
 // sh must hold NT/64 + 1 words. Contains barriers: call from every thread.
 template <int NT>
@@ -31,7 +41,7 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* t
   }
   __syncthreads();
   const uint32_t r = sh[wave] + x - v;
-  *total = sh[NT / 64];
+  *total = uni(sh[NT / 64]);
   __syncthreads();
   return r;
 }

@@ -13,10 +13,12 @@
 namespace pdet {
 // Query scratch, kept by the index and reused across calls (see run_query).
 struct QueryWorkspace {
-  DevBuf rho, admb, adm2, t2, crr, qp, dk, dc, dT, doff;
+  DevBuf rho, admb, adm2, t2, crr, lcnt, qp, dk, dc, dT, doff;
   PinnedBuf h_k, h_c, h_T, h_off;   // staging of the per-query parameters
   int64_t nslots = 0, nslots_max = 0, nq_cap = 0;
-  size_t bytes() const { return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes; }
+  size_t bytes() const {
+    return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes + lcnt.bytes;
+  }
 };
 }  // namespace pdet
 

@@ -8,18 +8,21 @@
 //  q_rho    batched over (leaf block, tree, query tile): the first round whose threshold
 //           admits each leaf (its squared lower bound to q' <= (eps r_rho)^2), for rounds
 //           up to rcap. Groups of 16 consecutive leaves are tested first with their union
-//           box (a lower bound of every member's bound, as a subtree prunes in the
-//           range query); a pruned group and any leaf beyond rcap get the mark rcap+1,
-//           refined exactly by q_main if a query ever reaches that round.
+//           box (a lower bound of every member's bound, as a subtree prunes in the range
+//           query). Only leaves admitted by round rcap are written, as (round, leaf)
+//           entries of a per-query, per-tree list; later rounds are found by q_main if a
+//           query ever reaches them.
 //  q_main   one workgroup per query, one pass per round over the admitted leaves of all
-//           trees: an admitted point is new iff none of its leaves in the other trees was
-//           admitted earlier in the (round, tree) order (closed form of the candidate
-//           union, read from leaf_of and the round indices: no per-query state to
-//           clear). When stop rule A can fire in a round, exact new-point counts per
-//           leaf give the tree where |S| reaches T, and a weighted radix select over that
-//           tree's (LB^2, leaf ordinal) keys gives the leaf; trees before it are admitted
-//           whole. New points are verified by exact distance and offered to a top-k list
-//           in LDS; stop rule B checks the k-th distance against c*r after each round.
+//           trees (the list entries of that round): an admitted point is new iff none of
+//           its leaves in the other trees was admitted earlier in the (round, tree) order
+//           (closed form of the candidate union, read from leafrow and the admission
+//           rounds of the leaves admitted so far, kept in an LDS hash, or in a dense table
+//           in device memory past 1024 leaves). When stop rule A can fire in a round,
+//           exact new-point counts per leaf give the tree where |S| reaches T, and a
+//           weighted select over that tree's (LB^2, leaf ordinal) keys gives the leaf;
+//           trees before it are admitted whole. New points are verified by exact distance
+//           and offered to a top-k list in LDS; stop rule B checks the k-th distance
+//           against c*r after each round.
 #include "devutil.h"
 #include "internal.h"
 
@@ -27,14 +30,19 @@ namespace pdet {
 namespace {
 
 constexpr int QM = 256;          // threads of q_main
-constexpr int CB = 512;          // top-k candidate buffer
+constexpr int CBMIN = 384;       // least pending-candidate buffer beside the top-k list (>= QM)
 constexpr int QT = 64;           // queries per q_rho block (group tests in sub-tiles of 16)
 constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
 constexpr int GL = 16;           // leaves per pruning group
 constexpr int RCAP_MAX = 8;      // most rounds q_rho resolves (the index's rcap <= this)
 constexpr int RWIN = 3;          // rounds resolved per refinement step inside q_main
 constexpr int GCH = 2048;        // groups per refinement chunk (LDS bitmap of GCH bits)
-constexpr int TREE_SHIFT = 28;   // list entries pack (tree << 28) | leaf
+constexpr int TREE_SHIFT = 28;   // admitted-leaf entries pack (tree << 28) | leaf
+constexpr int LEAF_BITS = 24;    // leaf-list entries pack (round << 24) | leaf
+constexpr int HSZ = 2048;        // LDS hash of (tree, leaf) -> round for the dedupe test
+constexpr int HMAX = HSZ / 2;    // most entries it takes; beyond, a dense table in HBM
+constexpr uint32_t HEMPTY = 0xffffffffu;
+constexpr int LBCH = 4;          // box dimensions q_main loads at a time for a lower bound
 
 struct QArgs {
   int64_t n;
@@ -49,6 +57,7 @@ struct QArgs {
   const float* box[PDET_MAX_L];
   const float* gbox[PDET_MAX_L];
   int64_t nl[PDET_MAX_L];
+  int64_t nlo[PDET_MAX_L];   // first slot of tree i's region in a per-query leaf list
   int64_t ng[PDET_MAX_L];
   int64_t nlpad;
   const float* Q;
@@ -59,9 +68,10 @@ struct QArgs {
   const double* qc;
   const float* t2;           // [slots][NRHO]
   const double* crr;         // [slots][NRHO]
-  uint8_t* rho;              // [slots][L][nlpad]
+  uint8_t* rho;              // [slots][L][nlpad] dense round table (0xff: not admitted)
+  uint32_t* lcnt;            // [slots][PDET_MAX_L] leaf-list lengths
   const int32_t* leafrow;    // [L][n][L]
-  uint32_t* adm_leaf;        // [slots][admcap]
+  uint32_t* adm_leaf;        // [slots][admcap] leaf lists: tree i from nlo[i]
   uint32_t* adm_w;
   float* adm_lb;
   uint32_t* adm2_leaf;       // [slots][admcap + 1]
@@ -95,18 +105,57 @@ __global__ void q_setup(QArgs a) {
   }
   t2[NRHO - 1] = INFINITY;
   crr[NRHO - 1] = INFINITY;
+  for (int i = 0; i < PDET_MAX_L; ++i) a.lcnt[(int64_t)slot * PDET_MAX_L + i] = 0;
 }
 
-// Squared lower-bound distance from q' to a leaf box; explicit fma keeps it identical
-// wherever it is evaluated.
+// Box `b` of a structure-of-arrays box table [2][K][nb] (lower corners, then upper). The
+// loop runs over the largest K so that all 2K loads are issued before the first is used.
+__device__ inline void load_box(const float* box, int64_t nb, int64_t b, int K,
+                                float (&lo)[PDET_MAX_K], float (&hi)[PDET_MAX_K]) {
+#pragma unroll
+  for (int j = 0; j < PDET_MAX_K; ++j) {
+    lo[j] = (j < K) ? box[(int64_t)j * nb + b] : 0.0f;
+    hi[j] = (j < K) ? box[(int64_t)(K + j) * nb + b] : 0.0f;
+  }
+}
+
+// Squared lower-bound distance from q' to a box; explicit fma in dimension order keeps it
+// identical wherever it is evaluated.
+__device__ inline float box_lb2(const float (&lo)[PDET_MAX_K], const float (&hi)[PDET_MAX_K],
+                                const float* q, int K) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int j = 0; j < PDET_MAX_K; ++j) {
+    if (j < K) {
+      const float g = fmaxf(0.0f, fmaxf(lo[j] - q[j], q[j] - hi[j]));
+      acc = __fmaf_rn(g, g, acc);
+    }
+  }
+  return acc;
+}
+
+// The same bound with the box read CH dimensions at a time (fewer registers; the same
+// fma sequence, so the same value).
+template <int CH>
 __device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, const float* q,
                                  int K) {
   float acc = 0.0f;
-  for (int j = 0; j < K; ++j) {
-    const float lo = box[(int64_t)j * nl + leaf];
-    const float hi = box[(int64_t)(K + j) * nl + leaf];
-    const float g = fmaxf(0.0f, fmaxf(lo - q[j], q[j] - hi));
-    acc = __fmaf_rn(g, g, acc);
+  for (int j0 = 0; j0 < K; j0 += CH) {
+    float lo[CH], hi[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int j = j0 + u;
+      lo[u] = (j < K) ? box[(int64_t)j * nl + leaf] : 0.0f;
+      hi[u] = (j < K) ? box[(int64_t)(K + j) * nl + leaf] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int j = j0 + u;
+      if (j < K) {
+        const float g = fmaxf(0.0f, fmaxf(lo[u] - q[j], q[j] - hi[u]));
+        acc = __fmaf_rn(g, g, acc);
+      }
+    }
   }
   return acc;
 }
@@ -118,7 +167,6 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   const int slot0 = blockIdx.z * QT;
   const int64_t nl = a.nl[tree], ng = a.ng[tree];
   const int rcap = a.rcap;
-  const uint8_t mark = (uint8_t)(rcap + 1);
   for (int e = threadIdx.x; e < QT * (RCAP_MAX + 1); e += blockDim.x) {
     const int qi = e / (RCAP_MAX + 1), r = e % (RCAP_MAX + 1);
     st[qi][r] = (slot0 + qi < a.nslots) ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
@@ -135,49 +183,29 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   const int sl = threadIdx.x & 15;
   // lane sl of the 16 lanes sharing group g tests that group against query 16*sub + sl
   uint64_t open_mask = 0;
+  float lo[PDET_MAX_K], hi[PDET_MAX_K];
+  if (g < ng) load_box(a.gbox[tree], ng, g, a.K, lo, hi);
   for (int sub = 0; sub < QT / 16; ++sub) {
     const int qi = sub * 16 + sl;
     bool open = false;
-    if (g < ng && slot0 + qi < a.nslots) {
-      const float* gb = a.gbox[tree];
-      float acc = 0.0f;
-      for (int j = 0; j < a.K; ++j) {
-        const float lo = gb[(int64_t)j * ng + g], hi = gb[(int64_t)(a.K + j) * ng + g];
-        const float gap = fmaxf(0.0f, fmaxf(lo - sq[qi][j], sq[qi][j] - hi));
-        acc = __fmaf_rn(gap, gap, acc);
-      }
-      open = acc <= st[qi][rcap];
-    }
+    if (g < ng && slot0 + qi < a.nslots) open = box_lb2(lo, hi, sq[qi], a.K) <= st[qi][rcap];
     const uint64_t mask = __ballot(open);
     open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
   }
-  if (leaf >= nl) return;
-  float lo[PDET_MAX_K], hi[PDET_MAX_K];
-  const float* box = a.box[tree];
-#pragma unroll
-  for (int j = 0; j < PDET_MAX_K; ++j) {
-    lo[j] = (j < a.K) ? box[(int64_t)j * nl + leaf] : 0.0f;
-    hi[j] = (j < a.K) ? box[(int64_t)(a.K + j) * nl + leaf] : 0.0f;
-  }
-  for (int qi = 0; qi < QT; ++qi) {
+  if (leaf >= nl || open_mask == 0) return;
+  load_box(a.box[tree], nl, leaf, a.K, lo, hi);
+  for (uint64_t mq = open_mask; mq; mq &= mq - 1) {
+    const int qi = __ffsll((unsigned long long)mq) - 1;   // open only for slots < nslots
     const int slot = slot0 + qi;
-    if (slot >= a.nslots) break;
-    uint8_t r = mark;
-    if ((open_mask >> qi) & 1ull) {
-      float acc = 0.0f;
+    const float acc = box_lb2(lo, hi, sq[qi], a.K);
+    int c = 0;   // #thresholds < lb2 among rounds 0..rcap: the leaf's first round if <= rcap
 #pragma unroll
-      for (int j = 0; j < PDET_MAX_K; ++j) {
-        if (j < a.K) {
-          const float gap = fmaxf(0.0f, fmaxf(lo[j] - sq[qi][j], sq[qi][j] - hi[j]));
-          acc = __fmaf_rn(gap, gap, acc);
-        }
-      }
-      int c = 0;   // #thresholds < lb2 among rounds 0..rcap; rcap+1 is the mark
-#pragma unroll
-      for (int rr = 0; rr <= RCAP_MAX; ++rr) c += (rr <= rcap && st[qi][rr] < acc) ? 1 : 0;
-      r = (uint8_t)c;
+    for (int rr = 0; rr <= RCAP_MAX; ++rr) c += (rr <= rcap && st[qi][rr] < acc) ? 1 : 0;
+    if (c <= rcap) {
+      const uint32_t pos = atomicAdd(&a.lcnt[(int64_t)slot * PDET_MAX_L + tree], 1u);
+      a.adm_leaf[(int64_t)slot * a.admcap + a.nlo[tree] + pos] =
+          ((uint32_t)c << LEAF_BITS) | (uint32_t)leaf;
     }
-    a.rho[((int64_t)slot * a.L + tree) * a.nlpad + leaf] = r;
   }
 }
 
@@ -188,7 +216,10 @@ __device__ inline bool lex_less(double a, int32_t ia, double b, int32_t ib) {
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
-constexpr int NCH = 2;           // 16-byte loads a lane keeps in flight per candidate row
+// 16-byte loads a lane keeps in flight per candidate row: float32 rows (FP64 accumulation
+// needs more registers per load) and the low-precision copies
+constexpr int NCH32 = 2;
+constexpr int NCHLP = 4;
 
 // Euclidean distance of candidate `id` to the query, computed by a group of `lpc` lanes
 // (a power of two; every lane of the group must call it). Each lane issues its (up to NCH)
@@ -204,6 +235,7 @@ __device__ inline double cand_dist(const QArgs& a, int32_t id, const float* qv, 
       const float4* x4 = reinterpret_cast<const float4*>(xr);
       const float4* q4 = reinterpret_cast<const float4*>(qv);
       const int n4 = a.d >> 2;
+      constexpr int NCH = NCH32;
       for (int base = 0; base < n4; base += NCH * lpc) {
         float4 buf[NCH];
 #pragma unroll
@@ -235,6 +267,7 @@ __device__ inline double cand_dist(const QArgs& a, int32_t id, const float* qv, 
                           : reinterpret_cast<const uint4*>(a.xf8 + (int64_t)id * a.dpad);
     const int nv = (PREC == PDET_BF16) ? (a.dpad >> 3) : (a.dpad >> 4);
     const float sc = (PREC == PDET_BF16) ? 1.0f : a.xscale[id];
+    constexpr int NCH = NCHLP;
     for (int base = 0; base < nv; base += NCH * lpc) {
       uint4 buf[NCH];
 #pragma unroll
@@ -299,22 +332,39 @@ __device__ void sort_pairs(double* ld, int32_t* li, int len) {
   }
 }
 
+// Round in which leaf `key` = (tree << 28) | leaf was admitted, from the LDS hash of the
+// admitted leaves (linear probing; never more than half full), or 255 if it was not.
+__device__ inline int hash_round(const uint32_t* hk, const uint8_t* hr, uint32_t key) {
+  uint32_t h = mix32(key) & (HSZ - 1);
+  for (;;) {
+    const uint32_t k = hk[h];
+    if (k == key) return hr[h];
+    if (k == HEMPTY) return 255;
+    h = (h + 1) & (HSZ - 1);
+  }
+}
+
 // Closed form of the candidate union: before step (rho, i) a point is in S iff its leaf in
 // some tree i2 < i is admitted in a round <= rho, or its leaf in some tree i2 > i in a round
 // < rho (every earlier step was admitted whole, or the query would have stopped). `lr` is
-// the point's row of leaf ordinals, `rr` the query's round-index table [L][nlpad].
-__device__ inline bool is_new(const QArgs& a, const uint8_t* rr, const int32_t* lr, int i,
-                              int rho) {
+// the point's row of leaf ordinals; the admission rounds come from the LDS hash, or from
+// the dense table rr [L][nlpad] once the hash has overflowed.
+__device__ inline bool is_new(const QArgs& a, bool dense, const uint8_t* rr, const uint32_t* hk,
+                              const uint8_t* hr, const int32_t* lr, int i, int rho) {
   for (int i2 = 0; i2 < a.L; ++i2) {
     if (i2 == i) continue;
-    const int r2 = rr[(int64_t)i2 * a.nlpad + lr[i2]];
+    const int r2 = dense ? rr[(int64_t)i2 * a.nlpad + lr[i2]]
+                         : hash_round(hk, hr, ((uint32_t)i2 << TREE_SHIFT) | (uint32_t)lr[i2]);
     if (i2 < i ? (r2 <= rho) : (r2 < rho)) return false;
   }
   return true;
 }
 
+// One workgroup per query (see the file header). The kernels below instantiate it with the
+// occupancy each form reaches: float32 verification keeps a small top-k list and runs six
+// workgroups per CU; the low-precision forms keep k * rescore candidates and run five.
 template <int PREC>
-__global__ __launch_bounds__(QM) void q_main(QArgs a) {
+__device__ __forceinline__ void q_main_body(const QArgs& a) {
   extern __shared__ __align__(16) unsigned char sm[];
   double* ld = reinterpret_cast<double*>(sm);
   int32_t* li = reinterpret_cast<int32_t*>(ld + a.NM);
@@ -322,17 +372,26 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   const int dq = (PREC == PDET_FP32) ? ((a.d + 3) & ~3) : a.dpad;
   float* qps = qv + dq;
 
-  __shared__ uint32_t w_pre[QM + 1];
-  __shared__ int32_t w_start[QM];
+  // the walk's window (traverse) and the select scratch (select_key) are never live at once
+  __shared__ __align__(16) uint32_t wbuf[3 * QM + 2];
+  uint32_t* w_pre = wbuf;                                       // [QM + 1]
+  int32_t* w_start = reinterpret_cast<int32_t*>(wbuf + QM + 2);  // [QM], 8-byte aligned
+  int32_t* idbuf = w_start + QM;                                // [QM]
+  unsigned long long* sel_key = reinterpret_cast<unsigned long long*>(w_start);  // [QM]
+  uint32_t* sel_w = w_pre;                                      // [QM]
   __shared__ uint8_t w_tree[QM];
-  __shared__ int32_t idbuf[QM];
   __shared__ uint32_t sh_scan[QM / 64 + 1];
   __shared__ uint32_t hist[256];
   __shared__ float st2[NRHO];
   __shared__ uint32_t gopen[GCH / 32];
   __shared__ uint32_t ent_off[PDET_MAX_L + 1];
-  __shared__ uint32_t s_m, s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix;
-  __shared__ unsigned long long s_pts, s_cut;
+  __shared__ uint32_t s_mt[PDET_MAX_L];
+  __shared__ uint32_t s_lc[PDET_MAX_L];          // leaf-list lengths per tree
+  __shared__ uint32_t s_lco[PDET_MAX_L + 1];     // their prefix (lists in tree order)
+  __shared__ uint32_t hkey[HSZ];
+  __shared__ uint8_t hrnd[HSZ];
+  __shared__ uint32_t s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix, s_cnt;
+  __shared__ unsigned long long s_cut;
 
   const int slot = blockIdx.x;
   const int64_t q = a.q0 + slot;
@@ -342,6 +401,7 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   const int k = a.qk[q];
   const int64_t T = a.qT[q];
   const int KL = (PREC == PDET_FP32) ? k : k * a.rescore;
+  const int CBcap = a.NM - KL;   // pending candidates beside the list (>= CBMIN >= QM)
   const int LK = a.L * a.K;
 
   for (int e = tid; e < a.NM; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
@@ -349,6 +409,8 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   for (int t = tid; t < LK; t += QM) qps[t] = a.qp[q * LK + t];
   for (int t = tid; t < NRHO; t += QM) st2[t] = a.t2[(int64_t)slot * NRHO + t];
   uint8_t* rq = a.rho + (int64_t)slot * a.L * a.nlpad;
+  for (int e = tid; e < HSZ; e += QM) hkey[e] = HEMPTY;
+  if (tid < a.L) s_lc[tid] = a.lcnt[(int64_t)slot * PDET_MAX_L + tid];
   if (tid == 0) { s_ncb = 0; s_hsum = 0; s_hmix = 0; }
   __syncthreads();
 
@@ -360,16 +422,22 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   int32_t* ast = a.adm_start + (int64_t)slot * (a.admcap + 1);
 
   int64_t nS = 0, leaves = 0, visits = 0;
+  uint32_t hn = 0;             // leaves in the hash (all admitted in rounds <= rho)
+  bool dense = false;          // the hash overflowed: rounds live in the dense table rq
   uint32_t hsum = 0, hmix = 0;
   int stop = -1, rounds = 0;
   int cap = a.rcap;            // rounds whose leaf indices are resolved
   const uint64_t t_start = wall_clock64();
 
+  // Sorts the kept list and the pending buffer together (over the power of two that holds
+  // them; entries past that are stale and never read); the first KL are the new list.
   auto merge = [&]() {
-    const int used = KL + (int)s_ncb;
-    for (int e = used + tid; e < a.NM; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
+    const int used = KL + (int)uni(s_ncb);
+    int len = 1;
+    while (len < used) len <<= 1;
+    for (int e = used + tid; e < len; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
     __syncthreads();
-    sort_pairs(ld, li, a.NM);
+    sort_pairs(ld, li, len);
     if (tid == 0) s_ncb = 0;
     __syncthreads();
   };
@@ -380,12 +448,12 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   // Returns the number of new points (uniform across the workgroup).
   auto traverse = [&](bool counting, int rho, uint32_t e_lo, uint32_t e_hi) -> uint32_t {
     uint32_t newc = 0;
-    const uint32_t P0 = pre2[e_lo], P1 = pre2[e_hi];
+    const uint32_t P0 = uni(pre2[e_lo]), P1 = uni(pre2[e_hi]);
     visits += P1 - P0;
     if (tid == 0) s_ef = e_lo;
     __syncthreads();
     for (uint32_t base = P0; base < P1; base += QM) {
-      const uint32_t ef = s_ef;
+      const uint32_t ef = uni(s_ef);
       {
         const uint32_t e = ef + tid;
         w_pre[tid] = (e <= e_hi) ? pre2[e] : 0xffffffffu;
@@ -412,7 +480,7 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
         const int tr = w_tree[lo];
         const int64_t pos = (int64_t)tr * a.n + w_start[lo] + (p - w_pre[lo]);
         id = a.perm[pos];
-        nw = is_new(a, rq, a.leafrow + pos * a.L, tr, rho);
+        nw = is_new(a, dense, rq, hkey, hrnd, a.leafrow + pos * a.L, tr, rho);
       }
       const uint64_t mask = __ballot(nw);
       uint32_t wbase = 0;
@@ -428,7 +496,7 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
         }
       }
       __syncthreads();
-      const uint32_t nb = s_nb;
+      const uint32_t nb = uni(s_nb);
       newc += nb;
       if (tid == 0) {
         // first window entry of the next chunk: last e with pre <= base + QM
@@ -454,7 +522,7 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
         }
       }
       __syncthreads();
-      if (!counting && s_ncb > (uint32_t)(CB - QM)) merge();
+      if (!counting && uni(s_ncb) > (uint32_t)(CBcap - QM)) merge();
     }
     return newc;
   };
@@ -463,6 +531,33 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   // the smallest key whose inclusive weight prefix reaches R. Weights: the leaf sizes
   // (by_counts) or the exact new-point counts admw[].
   auto select_key = [&](uint32_t e0, uint32_t e1, uint32_t R, bool by_counts) {
+    if (e1 - e0 <= (uint32_t)QM) {
+      // at most one entry per thread: each entry's inclusive prefix in key order is a sum
+      // over all entries (keys are distinct within a tree); the cut is the least key whose
+      // prefix reaches R, the same key the radix passes find
+      const uint32_t m = e1 - e0, e = e0 + tid;
+      unsigned long long key = ~0ull;
+      uint32_t wgt = 0;
+      if (e < e1) {
+        key = ((unsigned long long)__float_as_uint(admlb[e]) << 32) |
+              (adm2[e] & ((1u << TREE_SHIFT) - 1));
+        wgt = by_counts ? pre2[e + 1] - pre2[e]
+                        : __hip_atomic_load(&admw[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      sel_key[tid] = key;
+      sel_w[tid] = wgt;
+      if (tid == 0) s_cut = ~0ull;
+      __syncthreads();
+      if (e < e1) {
+        uint32_t pref = 0;
+        for (uint32_t u = 0; u < m; ++u) pref += (sel_key[u] <= key) ? sel_w[u] : 0u;
+        if (pref >= R) atomicMin(&s_cut, key);
+      }
+      __syncthreads();
+      const unsigned long long cut = uni((uint64_t)s_cut);
+      __syncthreads();
+      return cut;
+    }
     unsigned long long prefix = 0;
     for (int pass = 0; pass < 8; ++pass) {
       const int shift = 56 - 8 * pass;
@@ -487,8 +582,8 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
         s_newtot = R - ex;
       }
       __syncthreads();
-      prefix = s_cut;
-      R = s_newtot;
+      prefix = uni((uint64_t)s_cut);
+      R = uni(s_newtot);
       __syncthreads();
     }
     return prefix;
@@ -497,7 +592,7 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   // Keeps the entries of [e0, e1) whose key is <= cut, compacted in place (writes never pass
   // the read position), with their prefix sums; returns how many remain.
   auto keep_upto = [&](uint32_t e0, uint32_t e1, unsigned long long cut) -> uint32_t {
-    const uint32_t P0 = pre2[e0];
+    const uint32_t P0 = uni(pre2[e0]);
     uint32_t nm = 0, nP = 0;
     for (uint32_t b = e0; b < e1; b += QM) {
       const uint32_t e = b + tid;
@@ -534,98 +629,111 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   for (int rho = 0; rho < NRHO - 1 && stop < 0; ++rho) {
     rounds = rho + 1;
     if (rho == cap + 1) {
-      // Leaves left open (mark cap+1: "first round > cap") get their exact first round if it
-      // is within the next RWIN rounds; groups whose union box lies beyond stay open. Per
-      // chunk of groups: group tests into an LDS bitmap, then one leaf per thread.
+      // The lists hold every leaf whose first round is <= cap. Leaves whose first round is
+      // within the next RWIN rounds are appended: per chunk of groups, group tests into an
+      // LDS bitmap, then one leaf per thread for the open groups.
       const int ncap = std::min(NRHO - 2, cap + RWIN);
-      const uint8_t mark = (uint8_t)(cap + 1), nmark = (uint8_t)(ncap + 1);
       for (int i = 0; i < a.L; ++i) {
-        uint8_t* rr = rq + (int64_t)i * a.nlpad;
         const int64_t nl = a.nl[i], ng = a.ng[i];
         const float* gb = a.gbox[i];
         const float* qi = qps + i * a.K;
+        uint32_t* lst = adm + a.nlo[i];
         for (int64_t g0 = 0; g0 < ng; g0 += GCH) {
           for (int w = tid; w < GCH / 32; w += QM) gopen[w] = 0u;
           __syncthreads();
           for (int64_t g = g0 + tid; g < std::min<int64_t>(ng, g0 + GCH); g += QM) {
-            float acc = 0.0f;
-            for (int j = 0; j < a.K; ++j) {
-              const float lo = gb[(int64_t)j * ng + g], hi = gb[(int64_t)(a.K + j) * ng + g];
-              const float gap = fmaxf(0.0f, fmaxf(lo - qi[j], qi[j] - hi));
-              acc = __fmaf_rn(gap, gap, acc);
-            }
-            if (acc <= st2[ncap]) atomicOr(&gopen[(g - g0) >> 5], 1u << ((g - g0) & 31));
+            if (leaf_lb2<LBCH>(gb, ng, g, qi, a.K) <= st2[ncap])
+              atomicOr(&gopen[(g - g0) >> 5], 1u << ((g - g0) & 31));
           }
           __syncthreads();
           const int64_t l1 = std::min<int64_t>(nl, (g0 + GCH) * GL);
           for (int64_t leaf = g0 * GL + tid; leaf < l1; leaf += QM) {
-            if (rr[leaf] != mark) continue;
             const int64_t gl = leaf / GL - g0;
-            uint8_t r = nmark;
-            if ((gopen[gl >> 5] >> (gl & 31)) & 1u) {
-              const float lb2 = leaf_lb2(a.box[i], nl, leaf, qi, a.K);
-              int pos = 0;
+            if (!((gopen[gl >> 5] >> (gl & 31)) & 1u)) continue;
+            const float lb2 = leaf_lb2<LBCH>(a.box[i], nl, leaf, qi, a.K);
+            int pos = 0;   // first round whose threshold admits the leaf
 #pragma unroll
-              for (int sft = NRHO / 2; sft > 0; sft >>= 1)
-                if (st2[pos + sft - 1] < lb2) pos += sft;
-              r = (uint8_t)std::min(pos, ncap + 1);
-            }
-            rr[leaf] = r;
+            for (int sft = NRHO / 2; sft > 0; sft >>= 1)
+              if (st2[pos + sft - 1] < lb2) pos += sft;
+            if (pos > cap && pos <= ncap)
+              lst[atomicAdd(&s_lc[i], 1u)] = ((uint32_t)pos << LEAF_BITS) | (uint32_t)leaf;
           }
           __syncthreads();
         }
       }
       cap = ncap;
-      __syncthreads();
     }
-    // admitted leaves of every tree in this round, in tree order
-    if (tid == 0) { s_m = 0; s_pts = 0; ent_off[0] = 0; }
-    __syncthreads();
-    for (int i = 0; i < a.L; ++i) {
-      const uint8_t* rr = rq + (int64_t)i * a.nlpad;
-      const int64_t nl = a.nl[i];
-      const int32_t* lct = a.lcount[i];
-      for (int64_t b = (int64_t)tid * 16; b < nl; b += QM * 16) {
-        const uint4 v = *reinterpret_cast<const uint4*>(rr + b);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          if (((w[e >> 2] >> (8 * (e & 3))) & 255u) == (uint32_t)rho && b + e < nl) {
-            const uint32_t pos = atomicAdd(&s_m, 1u);
-            adm[pos] = ((uint32_t)i << TREE_SHIFT) | (uint32_t)(b + e);
-            atomicAdd(&s_pts, (unsigned long long)lct[b + e]);
-          }
-        }
-      }
-      __syncthreads();
-      if (tid == 0) ent_off[i + 1] = s_m;   // tree i's entries are [ent_off[i], ent_off[i+1])
-      __syncthreads();                     // recorded before any thread appends tree i+1
+    // admitted leaves of this round, from the lists in tree order: entries, their sizes'
+    // prefix sums and their perm start positions
+    if (tid < a.L) s_mt[tid] = 0;
+    if (tid == 0) {
+      s_cnt = 0;
+      s_lco[0] = 0;
+      for (int i = 0; i < a.L; ++i) s_lco[i + 1] = s_lco[i] + s_lc[i];
     }
     __syncthreads();
-    const uint32_t m = s_m;
-    const int64_t pts = (int64_t)s_pts;
-
-    if (m > 0) {
-      // prefix list of the leaf sizes (with their perm start positions)
-      uint32_t P = 0;
-      for (uint32_t b = 0; b < m; b += QM) {
-        const uint32_t e = b + tid;
-        uint32_t cnt = 0, en = 0;
-        int32_t st0 = 0;
-        if (e < m) {
-          en = adm[e];
-          const int tr = (int)(en >> TREE_SHIFT);
-          const uint32_t leaf = en & ((1u << TREE_SHIFT) - 1);
+    const uint32_t E = uni(s_lco[a.L]);
+    uint32_t m = 0, P = 0;
+    for (uint32_t v0 = 0; v0 < E; v0 += QM) {
+      const uint32_t v = v0 + tid;
+      bool match = false;
+      uint32_t en = 0, cnt = 0;
+      int32_t st0 = 0;
+      if (v < E) {
+        int tr = 0;
+        while (tr + 1 < a.L && s_lco[tr + 1] <= v) ++tr;
+        const uint32_t ent = adm[a.nlo[tr] + (v - s_lco[tr])];
+        if ((ent >> LEAF_BITS) == (uint32_t)rho) {
+          const uint32_t leaf = ent & ((1u << LEAF_BITS) - 1);
+          match = true;
+          en = ((uint32_t)tr << TREE_SHIFT) | leaf;
           cnt = (uint32_t)a.lcount[tr][leaf];
           st0 = a.lstart[tr][leaf];
+          atomicAdd(&s_mt[tr], 1u);
         }
-        uint32_t tot;
-        const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &tot);
-        if (e < m) { adm2[e] = en; pre2[e] = P + pre; ast[e] = st0; }
-        P += tot;
       }
-      if (tid == 0) pre2[m] = P;
-      __syncthreads();
+      uint32_t t1, t2;
+      const uint32_t pos = block_excl_scan<QM>(match ? 1u : 0u, sh_scan, &t1);
+      const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &t2);
+      if (match) { adm2[m + pos] = en; pre2[m + pos] = P + pre; ast[m + pos] = st0; }
+      m += t1;
+      P += t2;
+    }
+    if (tid == 0) {
+      pre2[m] = P;
+      ent_off[0] = 0;   // tree i's entries are [ent_off[i], ent_off[i+1]) of the list
+      for (int i = 0; i < a.L; ++i) ent_off[i + 1] = ent_off[i] + s_mt[i];
+    }
+    __syncthreads();
+    // this round's leaves join the dedupe state (every thread reads the lists and hn alike)
+    if (!dense && hn + m > (uint32_t)HMAX) {
+      dense = true;   // every leaf admitted so far, this round's included, into the table
+      for (uint32_t v = tid; v < E; v += QM) {
+        int tr = 0;
+        while (tr + 1 < a.L && s_lco[tr + 1] <= v) ++tr;
+        const uint32_t ent = adm[a.nlo[tr] + (v - s_lco[tr])];
+        if ((ent >> LEAF_BITS) <= (uint32_t)rho)
+          rq[(int64_t)tr * a.nlpad + (ent & ((1u << LEAF_BITS) - 1))] = (uint8_t)(ent >> LEAF_BITS);
+      }
+    } else if (dense) {
+      for (uint32_t e = tid; e < m; e += QM) {
+        const uint32_t en = adm2[e];
+        rq[(int64_t)(en >> TREE_SHIFT) * a.nlpad + (en & ((1u << TREE_SHIFT) - 1))] =
+            (uint8_t)rho;
+      }
+    } else {
+      for (uint32_t e = tid; e < m; e += QM) {
+        const uint32_t key = adm2[e];
+        uint32_t h = mix32(key) & (HSZ - 1);
+        while (atomicCAS(&hkey[h], HEMPTY, key) != HEMPTY) h = (h + 1) & (HSZ - 1);
+        hrnd[h] = (uint8_t)rho;
+      }
+    }
+    hn += m;
+    __syncthreads();
+    const int64_t pts = (int64_t)P;
+
+    if (m > 0) {
 
       if (nS + pts < T) {
         // stop rule A cannot fire in this round: admit every tree's leaves in one pass
@@ -634,16 +742,16 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
       } else {
         // trees in order; the exact count decides the tree (and leaf) where |S| reaches T
         for (int i = 0; i < a.L && stop < 0; ++i) {
-          const uint32_t e0 = ent_off[i], e1 = ent_off[i + 1];
+          const uint32_t e0 = uni(ent_off[i]), e1 = uni(ent_off[i + 1]);
           if (e0 == e1) continue;
-          const int64_t pts_i = (int64_t)pre2[e1] - (int64_t)pre2[e0];
+          const int64_t pts_i = (int64_t)uni(pre2[e1]) - (int64_t)uni(pre2[e0]);
           if (nS + pts_i < T) {
             leaves += e1 - e0;
             nS += traverse(false, rho, e0, e1);
             continue;
           }
           for (uint32_t e = e0 + tid; e < e1; e += QM)
-            admlb[e] = leaf_lb2(a.box[i], a.nl[i], adm2[e] & ((1u << TREE_SHIFT) - 1),
+            admlb[e] = leaf_lb2<LBCH>(a.box[i], a.nl[i], adm2[e] & ((1u << TREE_SHIFT) - 1),
                                 qps + i * a.K, a.K);
           __syncthreads();
           uint32_t e1c = e1;
@@ -673,11 +781,32 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
       }
       if (stop >= 0) break;
     }
-    if (s_ncb > 0) merge();
-    if (nS >= k && ld[k - 1] <= a.crr[(int64_t)slot * NRHO + rho]) stop = 2;
+    if (nS >= k) {
+      // stop rule B: the k-th smallest distance of the kept list and the pending buffer is
+      // <= c*r iff at least k of them are
+      const double crr = a.crr[(int64_t)slot * NRHO + rho];
+      const uint32_t tot = (uint32_t)KL + uni(s_ncb);
+      uint32_t cnt = 0;
+      for (uint32_t e = tid; e < tot; e += QM) cnt += (ld[e] <= crr) ? 1u : 0u;
+      if (cnt) atomicAdd(&s_cnt, cnt);
+      __syncthreads();
+      if (uni(s_cnt) >= (uint32_t)k) stop = 2;
+    }
     __syncthreads();
   }
-  if (s_ncb > 0) merge();
+  if (uni(s_ncb) > 0) merge();
+  if (dense) {
+    // leave the dense table all 0xff for the slot's next query: every entry written was a
+    // listed leaf
+    __syncthreads();
+    const uint32_t E = uni(s_lco[a.L]);
+    for (uint32_t v = tid; v < E; v += QM) {
+      int tr = 0;
+      while (tr + 1 < a.L && s_lco[tr + 1] <= v) ++tr;
+      const uint32_t ent = adm[a.nlo[tr] + (v - s_lco[tr])];
+      rq[(int64_t)tr * a.nlpad + (ent & ((1u << LEAF_BITS) - 1))] = 0xff;
+    }
+  }
 
   if constexpr (PREC != PDET_FP32) {
     // re-rank the kept low-precision candidates with exact float32 distances
@@ -718,6 +847,15 @@ __global__ __launch_bounds__(QM) void q_main(QArgs a) {
   }
 }
 
+__global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(6))) void q_main_f32(QArgs a) {
+  q_main_body<PDET_FP32>(a);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(5))) void q_main_lowp(QArgs a) {
+  q_main_body<PREC>(a);
+}
+
 }  // namespace
 
 // Per-query parameters of a batch into the workspace's pinned staging arrays.
@@ -741,7 +879,8 @@ size_t slot_bytes(const Index& ix) {
   int64_t nl_total = 0;
   for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
   const int64_t admcap = std::max<int64_t>(nl_total, 1);
-  return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 + NRHO * 12;
+  return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 + NRHO * 12 +
+         PDET_MAX_L * 4;
 }
 
 // Sizes the workspace for a batch of nq queries: per-query arrays, and as many query slots
@@ -764,12 +903,14 @@ void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t b
     const int64_t want = std::max<int64_t>(1, std::min<int64_t>(nq, cap));
     if (want > ws.nslots) {
       ws.rho.release(); ws.admb.release(); ws.adm2.release(); ws.t2.release(); ws.crr.release();
+      ws.lcnt.release();
       ws.rho.alloc((size_t)want * ix.L * nlpad);
       ws.admb.alloc((size_t)want * admcap * 12);
       ws.adm2.alloc((size_t)want * (admcap + 1) * 12);
       ws.t2.alloc((size_t)want * NRHO * 4);
       ws.crr.alloc((size_t)want * NRHO * 8);
-      // entries past a tree's last leaf are never written by q_rho: mark them "never"
+      ws.lcnt.alloc((size_t)want * PDET_MAX_L * 4);
+      // the dense round table starts "never admitted"; a query that writes it restores it
       PDET_HIP(hipMemsetAsync(ws.rho.p, 0xff, ws.rho.bytes, s));
       ws.nslots = want;
     }
@@ -823,7 +964,10 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   a.xscale = ix.xscale.as<float>();
   a.perm = ix.perm.as<int32_t>();
   a.leafrow = ix.leafrow.as<int32_t>();
+  int64_t nlo = 0;
   for (int i = 0; i < ix.L; ++i) {
+    a.nlo[i] = nlo;
+    nlo += ix.nl[i];
     a.lstart[i] = ix.leaf_start[i].as<int32_t>();
     a.lcount[i] = ix.leaf_count[i].as<int32_t>();
     a.box[i] = ix.box[i].as<float>();
@@ -841,6 +985,7 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   a.t2 = ws.t2.as<float>();
   a.crr = ws.crr.as<double>();
   a.rho = ws.rho.as<uint8_t>();
+  a.lcnt = ws.lcnt.as<uint32_t>();
   a.adm_leaf = ws.admb.as<uint32_t>();
   a.adm_w = a.adm_leaf + nslots * admcap;
   a.adm_lb = reinterpret_cast<float*>(a.adm_w + nslots * admcap);
@@ -853,20 +998,21 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   a.qstats = qc.qstats;
   a.rescore = qc.rescore;
   a.rcap = std::max(0, std::min(RCAP_MAX, ix.rcap));
-  // lanes per candidate: enough that each lane's share of a row is at most NCH 16-byte loads
-  auto lanes_for = [](int64_t chunks) {
+  // lanes per candidate: enough that each lane's share of a row is at most nch 16-byte loads
+  auto lanes_for = [](int64_t chunks, int nch) {
     int l = 4;
-    while (l < 64 && (int64_t)l * NCH < chunks) l <<= 1;
+    while (l < 64 && (int64_t)l * nch < chunks) l <<= 1;
     return l;
   };
   const int64_t ch32 = (ix.d % 4 == 0) ? ix.d / 4 : ix.d;
-  a.lpc32 = lanes_for(ch32);
-  a.lpc = qc.precision == PDET_FP32 ? a.lpc32
-          : lanes_for(qc.precision == PDET_BF16 ? ix.dpad / 8 : ix.dpad / 16);
+  a.lpc32 = lanes_for(ch32, NCH32);
+  a.lpc = qc.precision == PDET_FP32
+              ? a.lpc32
+              : lanes_for(qc.precision == PDET_BF16 ? ix.dpad / 8 : ix.dpad / 16, NCHLP);
   a.r_min = qc.r_min;
   a.eps = qc.eps;
   int NM = 1;
-  while (NM < maxKL + CB) NM <<= 1;
+  while (NM < maxKL + CBMIN) NM <<= 1;
   a.NM = NM;
   const int dq = (qc.precision == PDET_FP32) ? ((ix.d + 3) & ~3) : ix.dpad;
   const size_t smem = (size_t)NM * 12 + (size_t)dq * 4 + (size_t)LK * 4;
@@ -887,13 +1033,13 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
     Span sp(s, timed ? &tm.query_main_ms : nullptr);
     switch (qc.precision) {
       case PDET_FP32:
-        hipLaunchKernelGGL(q_main<PDET_FP32>, dim3(a.nslots), dim3(QM), smem, s, a);
+        hipLaunchKernelGGL(q_main_f32, dim3(a.nslots), dim3(QM), smem, s, a);
         break;
       case PDET_BF16:
-        hipLaunchKernelGGL(q_main<PDET_BF16>, dim3(a.nslots), dim3(QM), smem, s, a);
+        hipLaunchKernelGGL(q_main_lowp<PDET_BF16>, dim3(a.nslots), dim3(QM), smem, s, a);
         break;
       default:
-        hipLaunchKernelGGL(q_main<PDET_FP8_E4M3>, dim3(a.nslots), dim3(QM), smem, s, a);
+        hipLaunchKernelGGL(q_main_lowp<PDET_FP8_E4M3>, dim3(a.nslots), dim3(QM), smem, s, a);
         break;
     }
     PDET_HIP(hipGetLastError());

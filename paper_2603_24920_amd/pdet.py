@@ -21,7 +21,7 @@ MAX_K, MAX_L, MAX_TOPK, MAX_ROUNDS = 16, 16, 1024, 255
 QSTAT_WORDS = 8
 QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits=7)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX = range(6)
-EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_info", "pdet_export", "pdet_project",
+EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
             "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
                                  POINTER(c_void_p)]
         L.pdet_query.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams), c_void_p,
                                  c_void_p, c_void_p, c_void_p]
+        L.pdet_reserve.argtypes = [c_void_p, c_int64, c_void_p]
         L.pdet_free.argtypes = [c_void_p]
         L.pdet_free.restype = None
         L.pdet_info.argtypes = [c_void_p, POINTER(IndexInfo)]
@@ -117,7 +118,7 @@ def lib() -> ctypes.CDLL:
         L.pdet_server_get_stats.argtypes = [c_void_p, POINTER(ServerStats)]
         L.pdet_server_free.argtypes = [c_void_p]
         L.pdet_server_free.restype = None
-        for f in ("pdet_build", "pdet_query", "pdet_info", "pdet_export", "pdet_project",
+        for f in ("pdet_build", "pdet_query", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
                   "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
                   "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
                   "pdet_server_get_stats"):
@@ -187,6 +188,10 @@ class Index:
             self._h = None
 
     __del__ = close
+
+    def reserve(self, nq: int, stream=None):
+        """Size the query workspace for batches of up to nq queries (pdet_reserve)."""
+        _check(lib().pdet_reserve(self._h, int(nq), _stream(stream)))
 
     def info(self) -> dict:
         inf = IndexInfo()

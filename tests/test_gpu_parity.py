@@ -229,6 +229,21 @@ def test_query_stepwise_mixture(mixture, beta, r_min):
         assert st[:, pdet.QSTAT["rounds"]].max() > 6
 
 
+
+def test_query_stepwise_past_the_lds_hash(mixture):
+    # k = 1000 and c = 1.05 keep stop rule B from firing early: every query admits more than
+    # 1024 leaves, so its dedupe state moves from the LDS hash to the dense round table in
+    # device memory (and is restored for the slot's next query)
+    w, cs = mixture
+    Q = w.queries(20)
+    _, _, st = run_and_compare(cs, cs.stepwise_oracle(), Q, 1000, 1.05, 1.0, 1.0, "dense")
+    assert st[:, pdet.QSTAT["leaves"]].min() > 1024
+    # the same slots with the queries reversed: a table left dirty by the first call
+    # would mark other queries' leaves as admitted
+    run_and_compare(cs, cs.stepwise_oracle(), np.ascontiguousarray(Q[::-1]), 1000, 1.05, 1.0,
+                    1.0, "dense reversed")
+
+
 @pytest.mark.parametrize("beta,r_min,k,c", [(0.05, 2.0, 7, 1.5), (0.3, 0.5, 1, 2.0),
                                             (0.0, 3.0, 30, 1.2)])
 def test_query_stepwise_ragged(ragged, beta, r_min, k, c):
