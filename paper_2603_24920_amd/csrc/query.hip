@@ -42,7 +42,10 @@ constexpr int LEAF_BITS = 24;    // leaf-list entries pack (round << 24) | leaf
 constexpr int HSZ = 2048;        // LDS hash of (tree, leaf) -> round for the dedupe test
 constexpr int HMAX = HSZ / 2;    // most entries it takes; beyond, a dense table in HBM
 constexpr uint32_t HEMPTY = 0xffffffffu;
+constexpr uint32_t NO_CUT = 0xffffffffu;
+constexpr int WALK_VERIFY = 0, WALK_COUNT = 1, WALK_CUT = 2;
 constexpr int LBCH = 4;          // box dimensions q_main loads at a time for a lower bound
+constexpr int RLBCH = 2;         // the same in the (rare) refinement, which is kept lean
 
 struct QArgs {
   int64_t n;
@@ -220,97 +223,122 @@ __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0
 // needs more registers per load) and the low-precision copies
 constexpr int NCH32 = 2;
 constexpr int NCHLP = 4;
+constexpr int NR32 = 1;          // float32 candidate rows per lane group per trip
 
-// Euclidean distance of candidate `id` to the query, computed by a group of `lpc` lanes
-// (a power of two; every lane of the group must call it). Each lane issues its (up to NCH)
-// 16-byte loads of the row before using them. PREC 0: float32 data, FP64 accumulation;
-// 1: bf16 copy; 2: fp8 e4m3 copy with a per-row scale (FP32 accumulation).
-template <int PREC>
-__device__ inline double cand_dist(const QArgs& a, int32_t id, const float* qv, int lg, int lpc) {
-  double accd = 0.0;
-  float accf = 0.0f;
+// Euclidean distances of NR candidates `id[r]` to the query, computed by a group of `lpc`
+// lanes (a power of two; every lane of the group must call it; rows with valid[r] false
+// are not read). Each lane issues all its 16-byte loads of the NR rows (up to NCH per row)
+// before using them. PREC 0: float32 data, FP64 accumulation; 1: bf16 copy; 2: fp8 e4m3
+// copy with a per-row scale (FP32 accumulation).
+template <int PREC, int NR>
+__device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const bool (&valid)[NR],
+                                 const float* qv, int lg, int lpc, double (&out)[NR]) {
+  double accd[NR];
+  float accf[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) { accd[r] = 0.0; accf[r] = 0.0f; }
   if constexpr (PREC == PDET_FP32) {
-    const float* xr = a.X + (int64_t)id * a.d;
     if ((a.d & 3) == 0) {
-      const float4* x4 = reinterpret_cast<const float4*>(xr);
       const float4* q4 = reinterpret_cast<const float4*>(qv);
       const int n4 = a.d >> 2;
       constexpr int NCH = NCH32;
       for (int base = 0; base < n4; base += NCH * lpc) {
-        float4 buf[NCH];
+        float4 buf[NR][NCH];
 #pragma unroll
-        for (int u = 0; u < NCH; ++u) {
-          const int c = base + lg + u * lpc;
-          if (c < n4) buf[u] = x4[c];
+        for (int r = 0; r < NR; ++r) {
+          const float4* x4 = reinterpret_cast<const float4*>(a.X + (int64_t)id[r] * a.d);
+#pragma unroll
+          for (int u = 0; u < NCH; ++u) {
+            const int c = base + lg + u * lpc;
+            if (valid[r] && c < n4) buf[r][u] = x4[c];
+          }
         }
 #pragma unroll
-        for (int u = 0; u < NCH; ++u) {
-          const int c = base + lg + u * lpc;
-          if (c < n4) {
-            const float4 x = buf[u], q = q4[c];
-            const double d0 = (double)x.x - (double)q.x, d1 = (double)x.y - (double)q.y;
-            const double d2 = (double)x.z - (double)q.z, d3 = (double)x.w - (double)q.w;
-            accd = fma(d0, d0, accd); accd = fma(d1, d1, accd);
-            accd = fma(d2, d2, accd); accd = fma(d3, d3, accd);
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+          for (int u = 0; u < NCH; ++u) {
+            const int c = base + lg + u * lpc;
+            if (valid[r] && c < n4) {
+              const float4 x = buf[r][u], q = q4[c];
+              const double d0 = (double)x.x - (double)q.x, d1 = (double)x.y - (double)q.y;
+              const double d2 = (double)x.z - (double)q.z, d3 = (double)x.w - (double)q.w;
+              accd[r] = fma(d0, d0, accd[r]); accd[r] = fma(d1, d1, accd[r]);
+              accd[r] = fma(d2, d2, accd[r]); accd[r] = fma(d3, d3, accd[r]);
+            }
           }
         }
       }
     } else {
-      for (int t = lg; t < a.d; t += lpc) {
-        const double df = (double)xr[t] - (double)qv[t];
-        accd = fma(df, df, accd);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (!valid[r]) continue;
+        const float* xr = a.X + (int64_t)id[r] * a.d;
+        for (int t = lg; t < a.d; t += lpc) {
+          const double df = (double)xr[t] - (double)qv[t];
+          accd[r] = fma(df, df, accd[r]);
+        }
       }
     }
   } else {
-    const uint4* xr = (PREC == PDET_BF16)
-                          ? reinterpret_cast<const uint4*>(a.xbf + (int64_t)id * a.dpad)
-                          : reinterpret_cast<const uint4*>(a.xf8 + (int64_t)id * a.dpad);
     const int nv = (PREC == PDET_BF16) ? (a.dpad >> 3) : (a.dpad >> 4);
-    const float sc = (PREC == PDET_BF16) ? 1.0f : a.xscale[id];
     constexpr int NCH = NCHLP;
     for (int base = 0; base < nv; base += NCH * lpc) {
-      uint4 buf[NCH];
+      uint4 buf[NR][NCH];
 #pragma unroll
-      for (int u = 0; u < NCH; ++u) {
-        const int c = base + lg + u * lpc;
-        if (c < nv) buf[u] = xr[c];
+      for (int r = 0; r < NR; ++r) {
+        const uint4* xr = (PREC == PDET_BF16)
+                              ? reinterpret_cast<const uint4*>(a.xbf + (int64_t)id[r] * a.dpad)
+                              : reinterpret_cast<const uint4*>(a.xf8 + (int64_t)id[r] * a.dpad);
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int c = base + lg + u * lpc;
+          if (valid[r] && c < nv) buf[r][u] = xr[c];
+        }
       }
 #pragma unroll
-      for (int u = 0; u < NCH; ++u) {
-        const int c = base + lg + u * lpc;
-        if (c >= nv) continue;
-        const uint4 v = buf[u];
-        if constexpr (PREC == PDET_BF16) {
-          const float* q = qv + c * 8;
-          float df;
-          df = bf16_lo(v.x) - q[0]; accf = fmaf(df, df, accf);
-          df = bf16_hi(v.x) - q[1]; accf = fmaf(df, df, accf);
-          df = bf16_lo(v.y) - q[2]; accf = fmaf(df, df, accf);
-          df = bf16_hi(v.y) - q[3]; accf = fmaf(df, df, accf);
-          df = bf16_lo(v.z) - q[4]; accf = fmaf(df, df, accf);
-          df = bf16_hi(v.z) - q[5]; accf = fmaf(df, df, accf);
-          df = bf16_lo(v.w) - q[6]; accf = fmaf(df, df, accf);
-          df = bf16_hi(v.w) - q[7]; accf = fmaf(df, df, accf);
-        } else {
-          const float* q = qv + c * 16;
-          const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      for (int r = 0; r < NR; ++r) {
+        const float sc = (PREC == PDET_BF16 || !valid[r]) ? 1.0f : a.xscale[id[r]];
 #pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            const int wi = (int)w[h];
-            const float x0 = __builtin_amdgcn_cvt_f32_fp8(wi, 0) * sc - q[h * 4 + 0];
-            const float x1 = __builtin_amdgcn_cvt_f32_fp8(wi, 1) * sc - q[h * 4 + 1];
-            const float x2 = __builtin_amdgcn_cvt_f32_fp8(wi, 2) * sc - q[h * 4 + 2];
-            const float x3 = __builtin_amdgcn_cvt_f32_fp8(wi, 3) * sc - q[h * 4 + 3];
-            accf = fmaf(x0, x0, accf); accf = fmaf(x1, x1, accf);
-            accf = fmaf(x2, x2, accf); accf = fmaf(x3, x3, accf);
+        for (int u = 0; u < NCH; ++u) {
+          const int c = base + lg + u * lpc;
+          if (!valid[r] || c >= nv) continue;
+          const uint4 v = buf[r][u];
+          if constexpr (PREC == PDET_BF16) {
+            const float* q = qv + c * 8;
+            float df;
+            df = bf16_lo(v.x) - q[0]; accf[r] = fmaf(df, df, accf[r]);
+            df = bf16_hi(v.x) - q[1]; accf[r] = fmaf(df, df, accf[r]);
+            df = bf16_lo(v.y) - q[2]; accf[r] = fmaf(df, df, accf[r]);
+            df = bf16_hi(v.y) - q[3]; accf[r] = fmaf(df, df, accf[r]);
+            df = bf16_lo(v.z) - q[4]; accf[r] = fmaf(df, df, accf[r]);
+            df = bf16_hi(v.z) - q[5]; accf[r] = fmaf(df, df, accf[r]);
+            df = bf16_lo(v.w) - q[6]; accf[r] = fmaf(df, df, accf[r]);
+            df = bf16_hi(v.w) - q[7]; accf[r] = fmaf(df, df, accf[r]);
+          } else {
+            const float* q = qv + c * 16;
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+              const int wi = (int)w[h];
+              const float x0 = __builtin_amdgcn_cvt_f32_fp8(wi, 0) * sc - q[h * 4 + 0];
+              const float x1 = __builtin_amdgcn_cvt_f32_fp8(wi, 1) * sc - q[h * 4 + 1];
+              const float x2 = __builtin_amdgcn_cvt_f32_fp8(wi, 2) * sc - q[h * 4 + 2];
+              const float x3 = __builtin_amdgcn_cvt_f32_fp8(wi, 3) * sc - q[h * 4 + 3];
+              accf[r] = fmaf(x0, x0, accf[r]); accf[r] = fmaf(x1, x1, accf[r]);
+              accf[r] = fmaf(x2, x2, accf[r]); accf[r] = fmaf(x3, x3, accf[r]);
+            }
           }
         }
       }
     }
-    accd = (double)accf;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) accd[r] = (double)accf[r];
   }
-  for (int o = lpc >> 1; o > 0; o >>= 1) accd += __shfl_xor(accd, o);
-  return sqrt(accd);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    for (int o = lpc >> 1; o > 0; o >>= 1) accd[r] += __shfl_xor(accd[r], o);
+    out[r] = sqrt(accd[r]);
+  }
 }
 
 // Bitonic sort of (distance, id) pairs, ascending, over `len` (a power of two) entries.
@@ -382,6 +410,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   __shared__ uint8_t w_tree[QM];
   __shared__ uint32_t sh_scan[QM / 64 + 1];
   __shared__ uint32_t hist[256];
+  uint32_t* wcnt = hist;   // per-entry counts of a WALK_CUT chunk (hist: radix select only)
   __shared__ float st2[NRHO];
   __shared__ uint32_t gopen[GCH / 32];
   __shared__ uint32_t ent_off[PDET_MAX_L + 1];
@@ -390,7 +419,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   __shared__ uint32_t s_lco[PDET_MAX_L + 1];     // their prefix (lists in tree order)
   __shared__ uint32_t hkey[HSZ];
   __shared__ uint8_t hrnd[HSZ];
-  __shared__ uint32_t s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix, s_cnt;
+  __shared__ uint32_t s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix, s_cnt, s_cute;
   __shared__ unsigned long long s_cut;
 
   const int slot = blockIdx.x;
@@ -443,16 +472,21 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   };
 
   // Walk the points of list entries [e_lo, e_hi), 256 at a time. A point's leaf is found
-  // by a binary search in an LDS window of the prefix list. counting: add every new point
-  // to its leaf's count admw[]; otherwise verify the new points and offer them to the top-k.
-  // Returns the number of new points (uniform across the workgroup).
-  auto traverse = [&](bool counting, int rho, uint32_t e_lo, uint32_t e_hi) -> uint32_t {
+  // by a binary search in an LDS window of the prefix list. WALK_COUNT adds every new point
+  // to its leaf's count admw[]; WALK_VERIFY verifies the new points and offers them to the
+  // top-k; WALK_CUT (entries in admission order) does the same up to and including the
+  // first leaf after which R new points have been admitted, whose entry goes to cut_e
+  // (NO_CUT if the range holds fewer). Returns the number of new points admitted (uniform).
+  auto traverse = [&](int mode, int rho, uint32_t e_lo, uint32_t e_hi, uint32_t R,
+                      uint32_t& cut_e) -> uint32_t {
     uint32_t newc = 0;
-    const uint32_t P0 = uni(pre2[e_lo]), P1 = uni(pre2[e_hi]);
-    visits += P1 - P0;
+    const uint32_t P0 = uni(pre2[e_lo]);
+    uint32_t P1 = uni(pre2[e_hi]);
+    cut_e = NO_CUT;
     if (tid == 0) s_ef = e_lo;
     __syncthreads();
     for (uint32_t base = P0; base < P1; base += QM) {
+      visits += std::min<uint32_t>(QM, P1 - base);
       const uint32_t ef = uni(s_ef);
       {
         const uint32_t e = ef + tid;
@@ -461,9 +495,11 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           w_tree[tid] = (uint8_t)(adm2[e] >> TREE_SHIFT);
           w_start[tid] = ast[e];
         }
+        wcnt[tid] = 0;
         if (tid == 0) {
           w_pre[QM] = (ef + QM <= e_hi) ? pre2[ef + QM] : 0xffffffffu;
           s_nb = 0;
+          s_cute = NO_CUT;
         }
       }
       __syncthreads();
@@ -482,12 +518,25 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
         id = a.perm[pos];
         nw = is_new(a, dense, rq, hkey, hrnd, a.leafrow + pos * a.L, tr, rho);
       }
+      if (mode == WALK_CUT && cut_e == NO_CUT) {
+        // new points per window entry; the first entry whose inclusive count reaches R
+        if (nw) atomicAdd(&wcnt[lo], 1u);
+        __syncthreads();
+        const uint32_t c = wcnt[tid];
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<QM>(c, sh_scan, &tot);
+        if (ef + tid < e_hi && newc + ex + c >= R) atomicMin(&s_cute, ef + tid);
+        __syncthreads();
+        cut_e = uni(s_cute);
+        if (cut_e != NO_CUT) P1 = std::min(P1, uni(pre2[cut_e + 1]));   // the rest of that leaf
+      }
+      if (mode == WALK_CUT && cut_e != NO_CUT) nw = nw && ef + lo <= cut_e;
       const uint64_t mask = __ballot(nw);
       uint32_t wbase = 0;
       if (lane == 0 && mask) wbase = atomicAdd(&s_nb, (uint32_t)__popcll(mask));
       wbase = __shfl(wbase, 0);
       if (nw) {
-        if (counting) {
+        if (mode == WALK_COUNT) {
           atomicAdd(&admw[ef + lo], 1u);
         } else {
           idbuf[wbase + lanes_below_mask(mask)] = id;
@@ -508,23 +557,64 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
         }
         s_ef = ef + l2;
       }
-      if (!counting) {
-        for (uint32_t c0 = 0; c0 < nb; c0 += QM / lpc) {
-          const uint32_t c = c0 + grp;
-          const bool valid = c < nb;
-          const int32_t cid = valid ? idbuf[c] : 0;
-          const double dd = cand_dist<PREC>(a, cid, qv, lg, lpc);
-          if (valid && lg == 0 && lex_less(dd, cid, ld[KL - 1], li[KL - 1])) {
-            const uint32_t pos = atomicAdd(&s_ncb, 1u);
-            ld[KL + pos] = dd;
-            li[KL + pos] = cid;
+      if (mode != WALK_COUNT) {
+        constexpr int NRV = (PREC == PDET_FP32) ? NR32 : 1;
+        const uint32_t G = QM / lpc;   // lane groups: candidates per row of a trip
+        for (uint32_t c0 = 0; c0 < nb; c0 += NRV * G) {
+          int32_t cid[NRV];
+          bool valid[NRV];
+          double dd[NRV];
+#pragma unroll
+          for (int r = 0; r < NRV; ++r) {
+            const uint32_t c = c0 + r * G + grp;
+            valid[r] = c < nb;
+            cid[r] = valid[r] ? idbuf[c] : 0;
+          }
+          cand_dist<PREC, NRV>(a, cid, valid, qv, lg, lpc, dd);
+#pragma unroll
+          for (int r = 0; r < NRV; ++r) {
+            if (valid[r] && lg == 0 && lex_less(dd[r], cid[r], ld[KL - 1], li[KL - 1])) {
+              const uint32_t pos = atomicAdd(&s_ncb, 1u);
+              ld[KL + pos] = dd[r];
+              li[KL + pos] = cid[r];
+            }
           }
         }
       }
       __syncthreads();
-      if (!counting && uni(s_ncb) > (uint32_t)(CBcap - QM)) merge();
+      if (mode != WALK_COUNT && uni(s_ncb) > (uint32_t)(CBcap - QM)) merge();
     }
     return newc;
+  };
+
+  // Puts the entries [e0, e1) of tree i (at most QM) in admission order, ascending
+  // (LB^2, leaf ordinal) (keys are distinct within a tree), with their prefix list rebuilt.
+  auto order_entries = [&](uint32_t e0, uint32_t e1, int i) {
+    const uint32_t mi = e1 - e0, e = e0 + tid;
+    const uint32_t P0 = uni(pre2[e0]);
+    unsigned long long key = ~0ull;
+    uint32_t en = 0, cnt = 0;
+    int32_t st0 = 0;
+    if (tid < mi) {
+      en = adm2[e];
+      st0 = ast[e];
+      cnt = pre2[e + 1] - pre2[e];
+      const uint32_t leaf = en & ((1u << TREE_SHIFT) - 1);
+      const float lb = leaf_lb2<LBCH>(a.box[i], a.nl[i], leaf, qps + i * a.K, a.K);
+      key = ((unsigned long long)__float_as_uint(lb) << 32) | leaf;
+    }
+    sel_key[tid] = key;
+    __syncthreads();
+    uint32_t rank = 0;
+    if (tid < mi)
+      for (uint32_t u = 0; u < mi; ++u) rank += (sel_key[u] < key) ? 1u : 0u;
+    __syncthreads();
+    if (tid < mi) { adm2[e0 + rank] = en; ast[e0 + rank] = st0; sel_w[rank] = cnt; }
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<QM>(tid < mi ? sel_w[tid] : 0u, sh_scan, &tot);
+    if (tid < mi) pre2[e0 + tid] = P0 + ex;   // pre2[e1] = P0 + tot is unchanged
+    __syncthreads();
   };
 
   // Weighted radix select over list entries [e0, e1) keyed by (LB^2 bits, leaf ordinal):
@@ -642,7 +732,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           for (int w = tid; w < GCH / 32; w += QM) gopen[w] = 0u;
           __syncthreads();
           for (int64_t g = g0 + tid; g < std::min<int64_t>(ng, g0 + GCH); g += QM) {
-            if (leaf_lb2<LBCH>(gb, ng, g, qi, a.K) <= st2[ncap])
+            if (leaf_lb2<RLBCH>(gb, ng, g, qi, a.K) <= st2[ncap])
               atomicOr(&gopen[(g - g0) >> 5], 1u << ((g - g0) & 31));
           }
           __syncthreads();
@@ -650,7 +740,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           for (int64_t leaf = g0 * GL + tid; leaf < l1; leaf += QM) {
             const int64_t gl = leaf / GL - g0;
             if (!((gopen[gl >> 5] >> (gl & 31)) & 1u)) continue;
-            const float lb2 = leaf_lb2<LBCH>(a.box[i], nl, leaf, qi, a.K);
+            const float lb2 = leaf_lb2<RLBCH>(a.box[i], nl, leaf, qi, a.K);
             int pos = 0;   // first round whose threshold admits the leaf
 #pragma unroll
             for (int sft = NRHO / 2; sft > 0; sft >>= 1)
@@ -735,24 +825,36 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
 
     if (m > 0) {
 
+      uint32_t ce;
       if (nS + pts < T) {
         // stop rule A cannot fire in this round: admit every tree's leaves in one pass
         leaves += m;
-        nS += traverse(false, rho, 0, m);
+        nS += traverse(WALK_VERIFY, rho, 0, m, 0, ce);
       } else {
-        // trees in order; the exact count decides the tree (and leaf) where |S| reaches T
+        // trees in order; exact counts decide the tree (and leaf) where |S| reaches T
         for (int i = 0; i < a.L && stop < 0; ++i) {
           const uint32_t e0 = uni(ent_off[i]), e1 = uni(ent_off[i + 1]);
           if (e0 == e1) continue;
           const int64_t pts_i = (int64_t)uni(pre2[e1]) - (int64_t)uni(pre2[e0]);
-          if (nS + pts_i < T) {
-            leaves += e1 - e0;
-            nS += traverse(false, rho, e0, e1);
+          if (nS + pts_i < T || e1 - e0 <= (uint32_t)QM) {
+            // whole tree, or its leaves in admission order up to the one where |S| reaches T
+            const bool may_stop = nS + pts_i >= T;
+            if (may_stop) order_entries(e0, e1, i);
+            nS += traverse(may_stop ? WALK_CUT : WALK_VERIFY, rho, e0, e1,
+                           (uint32_t)(T - nS), ce);
+            if (ce != NO_CUT) {
+              leaves += ce - e0 + 1;
+              stop = 1;
+            } else {
+              leaves += e1 - e0;
+            }
             continue;
           }
+          // more leaves than one ordering pass takes: count new points per leaf over a
+          // bounded prefix, then select the leaf by key
           for (uint32_t e = e0 + tid; e < e1; e += QM)
             admlb[e] = leaf_lb2<LBCH>(a.box[i], a.nl[i], adm2[e] & ((1u << TREE_SHIFT) - 1),
-                                qps + i * a.K, a.K);
+                                      qps + i * a.K, a.K);
           __syncthreads();
           uint32_t e1c = e1;
           if (pts_i >= T) {
@@ -764,19 +866,18 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           }
           for (uint32_t e = e0 + tid; e < e1c; e += QM) admw[e] = 0;
           __syncthreads();
-          const uint32_t new_i = traverse(true, rho, e0, e1c);
+          const uint32_t new_i = traverse(WALK_COUNT, rho, e0, e1c, 0, ce);
+          uint32_t e_end = e1;
           if (nS + (int64_t)new_i < T) {
             if (e1c != e1) { stop = -2; break; }   // contradicts the bound above
-            leaves += e1 - e0;
-            nS += traverse(false, rho, e0, e1);
-            continue;
+          } else {
+            // the smallest key whose inclusive new-point prefix reaches R = T - |S|
+            const unsigned long long cut = select_key(e0, e1c, (uint32_t)(T - nS), false);
+            e_end = e0 + keep_upto(e0, e1c, cut);
+            stop = 1;
           }
-          // the smallest key whose inclusive new-point prefix reaches R = T - |S|
-          const unsigned long long cut = select_key(e0, e1c, (uint32_t)(T - nS), false);
-          const uint32_t nm = keep_upto(e0, e1c, cut);
-          leaves += nm;
-          nS += traverse(false, rho, e0, e0 + nm);
-          stop = 1;
+          leaves += e_end - e0;
+          nS += traverse(WALK_VERIFY, rho, e0, e_end, 0, ce);
         }
       }
       if (stop >= 0) break;
@@ -811,12 +912,21 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   if constexpr (PREC != PDET_FP32) {
     // re-rank the kept low-precision candidates with exact float32 distances
     const int lpc32 = a.lpc32, lg32 = tid & (lpc32 - 1), grp32 = tid / lpc32;
-    for (int t0 = 0; t0 < KL; t0 += QM / lpc32) {
-      const int t = t0 + grp32;
-      const bool valid = t < KL && li[t] != INT32_MAX;
-      const int32_t id = valid ? li[t] : 0;
-      const double dd = cand_dist<PDET_FP32>(a, id, qv, lg32, lpc32);
-      if (valid && lg32 == 0) ld[t] = dd;
+    const int G32 = QM / lpc32;
+    for (int t0 = 0; t0 < KL; t0 += 2 * G32) {
+      int32_t id[2];
+      bool valid[2];
+      double dd[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int t = t0 + r * G32 + grp32;
+        valid[r] = t < KL && li[t] != INT32_MAX;
+        id[r] = valid[r] ? li[t] : 0;
+      }
+      cand_dist<PDET_FP32, 2>(a, id, valid, qv, lg32, lpc32, dd);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        if (valid[r] && lg32 == 0) ld[t0 + r * G32 + grp32] = dd[r];
     }
     __syncthreads();
     int len = 1;

@@ -244,8 +244,10 @@ def test_query_stepwise_past_the_lds_hash(mixture):
                     1.0, "dense reversed")
 
 
+# r_min = 1000 admits every leaf in round 0: the stop tree then has more leaves than one
+# ordering pass takes and the counted-prefix selection runs
 @pytest.mark.parametrize("beta,r_min,k,c", [(0.05, 2.0, 7, 1.5), (0.3, 0.5, 1, 2.0),
-                                            (0.0, 3.0, 30, 1.2)])
+                                            (0.0, 3.0, 30, 1.2), (0.3, 1000.0, 10, 1.5)])
 def test_query_stepwise_ragged(ragged, beta, r_min, k, c):
     w, cs = ragged
     run_and_compare(cs, cs.stepwise_oracle(), w.queries(40), k, c, beta, r_min,
