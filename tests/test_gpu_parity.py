@@ -151,9 +151,21 @@ def run_and_compare(cs, idx_or, Q, k, c, beta, r_min, label, allow_frac=0.0):
     print(f"[query {label}] nq={len(Q)} k={k} c={c} beta={beta} r_min={r_min}", flush=True)
     ids, dists, st = cs.idx.query(Qd, k=k, c=c, beta=beta, r_min=r_min, stats=True)
     ids, dists, st = ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
+    compare_queries(cs, idx_or, Q, range(len(Q)), ids, dists, st, k, c, beta, r_min, label,
+                    allow_frac)
+    return ids, dists, st
+
+
+def compare_queries(cs, idx_or, Q, sel, ids, dists, st, k, c, beta, r_min, label,
+                    allow_frac=0.0):
+    """GPU results of the queries `sel` of batch Q against the oracle run one by one."""
+    sel = list(sel)
     n_diff = n_band = 0
-    for qi, q in enumerate(Q):
+    results = {}
+    for qi in sel:
+        q = Q[qi]
         res = oracle.query(idx_or, cs.X, q, k, c, beta, r_min, cs.eps)
+        results[qi] = res
         hs, hm = set_hashes(res.cand)
         same_set = (st[qi, pdet.QSTAT["ncand"]] == res.n_cand and st[qi, pdet.QSTAT["hsum"]] == hs
                     and st[qi, pdet.QSTAT["hmix"]] == hm)
@@ -175,9 +187,10 @@ def run_and_compare(cs, idx_or, Q, k, c, beta, r_min, label, allow_frac=0.0):
                   or near_stop_b(cs.X, q, res.cand, k, rounds, r_min, c))
         assert banded, (label, qi, st[qi], res.n_cand, res.stop, res.rounds, res.leaves, hs, hm)
         n_band += 1
-    print(f"[query {label}] identical={len(Q) - n_diff}/{len(Q)} banded={n_band}", flush=True)
-    assert n_diff <= max(1, allow_frac * len(Q))
-    return ids, dists, st
+    print(f"[query {label}] identical={len(sel) - n_diff}/{len(sel)} banded={n_band}",
+          flush=True)
+    assert n_diff <= max(1, allow_frac * len(sel))
+    return results
 
 
 # --------------------------------------------------------------------------- cases
