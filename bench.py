@@ -13,7 +13,7 @@ ground truth for recall is the library's own exhaustive mode (beta = 1 and a fir
 radius covering every point, which the tests show equals brute-force exact kNN).
 
 Prints one JSON line. `value` is queries/s of the query phase (inputs resident in HBM);
-`build_mpts_per_s` is n / build time. `roofline` describes the search kernel q_main
+`build_mpts_per_s` is n / build time. `roofline` describes the search kernel q_main_f32
 (timed live with HIP events); `cpu_baseline` is the FP64 oracle on the host.
 """
 from __future__ import annotations
@@ -55,7 +55,7 @@ def kernel_source_hash():
 
 
 def pmc_traffic(bytes_alg_per_launch):
-    """HBM traffic of q_main per launch from committed rocprofv3 counter runs, or None if the
+    """HBM traffic of q_main_f32 per launch from committed rocprofv3 counter runs, or None if the
     kernel source changed since they were taken."""
     if not os.path.exists(PROFILE_PMC):
         return None
@@ -296,7 +296,7 @@ def main():
             "p99": float(np.percentile(recs[-1]["qtime"], 99) * 1e3 / recs[-1]["khz"]),
             "max": float(recs[-1]["qtime"].max() * 1e3 / recs[-1]["khz"])},
         "mean_point_visits_per_query": float(recs[-1]["visits"].mean()),
-        "roofline": {"bound": "hbm", "kernel": "q_main", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "q_main_f32", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_alg,
                      "ms_per_launch": main_ms},
