@@ -54,14 +54,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(bytes_alg_per_launch):
-    """HBM traffic of q_main_f32 per launch from committed rocprofv3 counter runs, or None if the
-    kernel source changed since they were taken."""
+def pmc_traffic(workload_name, nq):
+    """HBM traffic of q_main_f32 per launch from committed rocprofv3 counter runs on this
+    workload, or None if they were taken on another workload or the kernel source changed."""
     if not os.path.exists(PROFILE_PMC):
         return None
     with open(PROFILE_PMC) as f:
         p = json.load(f)
-    if p.get("kernel_hash") != kernel_source_hash():
+    if (p.get("kernel_hash") != kernel_source_hash() or p.get("workload_name") != workload_name
+            or p.get("nq") != nq):
         return None
     return p.get("traffic_bytes_per_launch")
 
@@ -214,7 +215,7 @@ def main():
     launches = int(recs[-1]["tq"]["query_main_launches"])
     bytes_alg = ncand * (4 * w.d + 4 + 4 * (w.L - 1)) / max(1, launches)
     achieved = bytes_alg / (main_ms * 1e-3) / 1e9
-    traffic = pmc_traffic(bytes_alg)
+    traffic = pmc_traffic(w.name, nq)
     enc_ms = float(np.mean([r["tb"]["build_encode_ms"] for r in recs]))
     enc_bytes = w.n * (4 * w.d + 16 * w.L)
 

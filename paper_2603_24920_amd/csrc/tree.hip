@@ -427,19 +427,34 @@ __global__ void leafrow_kernel(const int32_t* perm, const int32_t* leaf_of, int6
 }
 
 // Union box of each group of 16 consecutive leaves (depth-first neighbours share most
-// of their code prefixes, so the union stays tight).
-__global__ void group_boxes(const float* box, int64_t nl, int K, int64_t ng, float* gbox) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ng) return;
-  const int64_t l0 = g * 16, l1 = std::min<int64_t>(nl, l0 + 16);
-  for (int j = 0; j < K; ++j) {
-    float lo = INFINITY, hi = -INFINITY;
-    for (int64_t l = l0; l < l1; ++l) {
-      lo = fminf(lo, box[(int64_t)j * nl + l]);
-      hi = fmaxf(hi, box[(int64_t)(K + j) * nl + l]);
+// of their code prefixes, so the union stays tight). One thread per leaf (coalesced reads of
+// the box table); the 16 lanes of a group reduce with shuffles. All trees in one launch.
+struct GroupArgs {
+  const float* box[PDET_MAX_L];
+  float* gbox[PDET_MAX_L];
+  int64_t nl[PDET_MAX_L];
+  int K;
+};
+
+__global__ __launch_bounds__(256) void group_boxes(GroupArgs a) {
+  const int i = blockIdx.y;
+  const int64_t nl = a.nl[i], ng = (nl + 15) / 16;
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= ng * 16) return;   // whole groups: the 16 lanes of a group stay together
+  const int64_t g = l >> 4;
+  const float* box = a.box[i];
+  float* gbox = a.gbox[i];
+  for (int j = 0; j < a.K; ++j) {
+    float lo = (l < nl) ? box[(int64_t)j * nl + l] : INFINITY;
+    float hi = (l < nl) ? box[(int64_t)(a.K + j) * nl + l] : -INFINITY;
+    for (int o = 8; o > 0; o >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, o, 16));
+      hi = fmaxf(hi, __shfl_xor(hi, o, 16));
     }
-    gbox[(int64_t)j * ng + g] = lo;
-    gbox[(int64_t)(K + j) * ng + g] = hi;
+    if ((l & 15) == 0) {
+      gbox[(int64_t)j * ng + g] = lo;
+      gbox[(int64_t)(a.K + j) * ng + g] = hi;
+    }
   }
 }
 
@@ -562,12 +577,19 @@ void build_trees(Index& ix, hipStream_t s) {
                      hidx_at.as<uint16_t>(), flags.as<uint32_t>(), n, K, bits, ix.Nr,
                      ix.B.as<float>(), t);
   PDET_HIP(hipGetLastError());
+  GroupArgs ga{};
+  int64_t nl_pad = 0;
   for (int i = 0; i < L; ++i) {
     const int64_t ng = (nl[i] + 15) / 16;
     ix.gbox[i].alloc((size_t)std::max<int64_t>(ng, 1) * 2 * K * 4);
-    if (ng)
-      hipLaunchKernelGGL(group_boxes, dim3(cdiv(ng, 256)), dim3(256), 0, s, ix.box[i].as<float>(),
-                         (int64_t)nl[i], K, ng, ix.gbox[i].as<float>());
+    ga.box[i] = ix.box[i].as<float>();
+    ga.gbox[i] = ix.gbox[i].as<float>();
+    ga.nl[i] = nl[i];
+    nl_pad = std::max<int64_t>(nl_pad, ng * 16);
+  }
+  ga.K = K;
+  if (nl_pad) {
+    hipLaunchKernelGGL(group_boxes, dim3(cdiv(nl_pad, 256), L), dim3(256), 0, s, ga);
     PDET_HIP(hipGetLastError());
   }
   DevBuf leaf_of((size_t)n * L * 4);
