@@ -227,7 +227,6 @@ __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, co
 }
 
 // ---- one workgroup finishes a node of at most LDS_SEG_CAP points in LDS
-constexpr int FIN_THREADS = 256;
 constexpr int STACK_MAX = KP * 8 + 8;
 
 struct Node {
@@ -236,14 +235,18 @@ struct Node {
   uint8_t prefix[KP];
 };
 
-__global__ __launch_bounds__(FIN_THREADS) void seg_lds_finish(const Seg* mid, int32_t* perm,
-                                                              const uint8_t* codes, int64_t n,
-                                                              int K, int bits, int max_leaf,
-                                                              LeafOut lo) {
-  __shared__ int32_t ids[LDS_SEG_CAP];
-  __shared__ uint4 rows[LDS_SEG_CAP];
-  __shared__ uint16_t idx[LDS_SEG_CAP];
-  __shared__ uint16_t tmp[LDS_SEG_CAP];
+// Instantiated per size class (count in (below, CAP], NT threads): LDS and threads scale
+// with the node, so small nodes run many workgroups per CU. Blocks whose node is outside
+// the class return at once.
+template <int CAP, int NT>
+__global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* perm,
+                                                     const uint8_t* codes, int64_t n, int K,
+                                                     int bits, int max_leaf, int below,
+                                                     LeafOut lo) {
+  __shared__ int32_t ids[CAP];
+  __shared__ uint4 rows[CAP];
+  __shared__ uint16_t idx[CAP];
+  __shared__ uint16_t tmp[CAP];
   __shared__ Node stack[STACK_MAX];
   __shared__ Node cur;
   __shared__ int sp;
@@ -253,6 +256,7 @@ __global__ __launch_bounds__(FIN_THREADS) void seg_lds_finish(const Seg* mid, in
   __shared__ int jsplit;
 
   const Seg s = mid[blockIdx.x];
+  if (s.count <= below || s.count > CAP) return;
   const int64_t tb = (int64_t)s.tree * n;
   for (int t = threadIdx.x; t < s.count; t += blockDim.x) {
     const int32_t id = perm[tb + s.start + t];
@@ -544,8 +548,18 @@ void build_trees(Index& ix, hipStream_t s) {
   }
   const uint32_t nmid = hc[4];
   if (nmid) {
-    hipLaunchKernelGGL(seg_lds_finish, dim3(nmid), dim3(FIN_THREADS), 0, s, mid.as<Seg>(), perm,
-                       codes, n, K, bits, ix.max_leaf, lo);
+    // size classes (below, CAP]: each block of a launch finishes one node of its class
+    hipLaunchKernelGGL((seg_lds_finish<256, 64>), dim3(nmid), dim3(64), 0, s, mid.as<Seg>(),
+                       perm, codes, n, K, bits, ix.max_leaf, 0, lo);
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL((seg_lds_finish<512, 128>), dim3(nmid), dim3(128), 0, s, mid.as<Seg>(),
+                       perm, codes, n, K, bits, ix.max_leaf, 256, lo);
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL((seg_lds_finish<1024, 256>), dim3(nmid), dim3(256), 0, s, mid.as<Seg>(),
+                       perm, codes, n, K, bits, ix.max_leaf, 512, lo);
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL((seg_lds_finish<LDS_SEG_CAP, 256>), dim3(nmid), dim3(256), 0, s,
+                       mid.as<Seg>(), perm, codes, n, K, bits, ix.max_leaf, 1024, lo);
     PDET_HIP(hipGetLastError());
   }
 
