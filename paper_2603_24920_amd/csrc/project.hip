@@ -20,6 +20,8 @@ enum Mode { MODE_PROJECT = 0, MODE_SAMPLE = 1, MODE_ENCODE = 2 };
 
 constexpr int PROJ_THREADS = 1024;
 constexpr int PROJ_WAVES = PROJ_THREADS / 64;
+constexpr int DK_MAX = 128;              // rows of A staged per chunk (at most)
+constexpr int KB_MAX = DK_MAX / 16;      // 16-column steps per chunk
 
 struct ProjArgs {
   const float* X;          // [rows of X][d]
@@ -46,9 +48,17 @@ template <int NT, bool VEC4, int MODE>
 __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
   constexpr int NC = NT * 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* As = reinterpret_cast<float*>(smem_raw);                 // [dk][NC]
-  float* Bs = As + a.dk * NC;                                      // [NT*K][Nr] interior + inf
-  uint8_t* stage = reinterpret_cast<uint8_t*>(Bs + (MODE == MODE_ENCODE ? NT * a.K * a.Nr : 0));
+  // [dk][NC + 4]: with the padding, the rows that the two lane groups of a half-wave read
+  // per MFMA operand fall in disjoint LDS bank halves
+  constexpr int ASTR = NC + 4;
+  float* As = reinterpret_cast<float*>(smem_raw);
+  // [NT*K][Nr + 1]: interior breakpoints + inf, one padding word per column so that the
+  // 16 columns a wave searches at once sit in different LDS banks
+  float* Bs = As + ((a.dk * ASTR + 3) & ~3);
+  const int bstride = a.Nr + 1;
+  // the code staging area starts 16-byte aligned (rounded table size)
+  uint8_t* stage = reinterpret_cast<uint8_t*>(
+      Bs + (MODE == MODE_ENCODE ? ((NT * a.K * bstride + 3) & ~3) : 0));
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -62,8 +72,9 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
       const int c = e / a.Nr, u = e % a.Nr;
       const int gcol = (a.tree0 + c / a.K) * a.K + c % a.K;
-      Bs[e] = (u < a.Nr - 1 && c / a.K < a.ntrees) ? a.Btab[(int64_t)gcol * (a.Nr + 1) + 1 + u]
-                                                   : INFINITY;
+      Bs[c * bstride + u] = (u < a.Nr - 1 && c / a.K < a.ntrees)
+                                ? a.Btab[(int64_t)gcol * (a.Nr + 1) + 1 + u]
+                                : INFINITY;
     }
   }
 
@@ -72,9 +83,16 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
     const int tot = a.dk * NC;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
       const int r = e / NC, c = e % NC;
-      As[e] = (k0 + r < a.d) ? a.A[(int64_t)(k0 + r) * NC + c] : 0.0f;
+      As[r * ASTR + c] = (k0 + r < a.d) ? a.A[(int64_t)(k0 + r) * NC + c] : 0.0f;
     }
   };
+  // column min / max of this workgroup (ordered uints), reduced in LDS before one global
+  // atomic per column: all workgroups update the same few cache lines
+  __shared__ uint32_t wg_min[NT * 16], wg_max[NT * 16];
+  if (MODE == MODE_ENCODE && threadIdx.x < NT * 16) {
+    wg_min[threadIdx.x] = float_to_ordered(INFINITY);
+    wg_max[threadIdx.x] = float_to_ordered(-INFINITY);
+  }
   if (nchunks == 1) load_A(0);
   __syncthreads();
 
@@ -105,22 +123,34 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
       }
       const int k0 = chunk * a.dk;
       const int kend = min(a.dk, a.d - k0);
-      for (int kb = 0; kb < kend; kb += 16) {
-        const int kk = k0 + kb + 4 * grp;                 // first of this lane's 4 columns
-        float xv[4];
-        if (VEC4 && load_ok && kk + 3 < a.d) {
-          const float4 v = *reinterpret_cast<const float4*>(xr + kk);
-          xv[0] = v.x; xv[1] = v.y; xv[2] = v.z; xv[3] = v.w;
-        } else {
+      // this lane's values of the chunk (4 columns per 16-column step), all loads issued
+      // before the first MFMA
+      float4 xb[KB_MAX];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) xv[e] = (load_ok && kk + e < a.d) ? xr[kk + e] : 0.0f;
+      for (int u = 0; u < KB_MAX; ++u) {
+        const int kk = k0 + u * 16 + 4 * grp;             // first of this lane's 4 columns
+        if (u * 16 < kend) {
+          if (VEC4 && load_ok && kk + 3 < a.d) {
+            xb[u] = *reinterpret_cast<const float4*>(xr + kk);
+          } else {
+            xb[u].x = (load_ok && kk + 0 < a.d) ? xr[kk + 0] : 0.0f;
+            xb[u].y = (load_ok && kk + 1 < a.d) ? xr[kk + 1] : 0.0f;
+            xb[u].z = (load_ok && kk + 2 < a.d) ? xr[kk + 2] : 0.0f;
+            xb[u].w = (load_ok && kk + 3 < a.d) ? xr[kk + 3] : 0.0f;
+          }
         }
+      }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float* brow = As + (kb + 4 * grp + e) * NC + col16;
+      for (int u = 0; u < KB_MAX; ++u) {
+        if (u * 16 < kend) {
+          const float xv[4] = {xb[u].x, xb[u].y, xb[u].z, xb[u].w};
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[e], brow[t * 16], acc[t], 0, 0, 0);
+          for (int e = 0; e < 4; ++e) {
+            const float* brow = As + (u * 16 + 4 * grp + e) * ASTR + col16;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[e], brow[t * 16], acc[t], 0, 0, 0);
+          }
         }
       }
     }
@@ -153,7 +183,7 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
           uint8_t code = 0;
           if (col16 < a.K && t < a.ntrees) {
             const float h = acc[t][i];
-            const float* tab = Bs + (t * a.K + col16) * a.Nr;
+            const float* tab = Bs + (t * a.K + col16) * bstride;
             int pos = 0;
             for (int s = a.Nr >> 1; s > 0; s >>= 1)
               if (tab[pos + s - 1] <= h) pos += s;
@@ -186,9 +216,18 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
       lo = fminf(lo, __shfl_xor(lo, 16)); hi = fmaxf(hi, __shfl_xor(hi, 16));
       lo = fminf(lo, __shfl_xor(lo, 32)); hi = fmaxf(hi, __shfl_xor(hi, 32));
       if (lane < a.K && t < a.ntrees && lo <= hi) {
-        const int gcol = (a.tree0 + t) * a.K + lane;
-        atomicMin(&a.colmin[gcol], float_to_ordered(lo));
-        atomicMax(&a.colmax[gcol], float_to_ordered(hi));
+        atomicMin(&wg_min[t * 16 + lane], float_to_ordered(lo));
+        atomicMax(&wg_max[t * 16 + lane], float_to_ordered(hi));
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < NT * 16) {
+      const int t = threadIdx.x >> 4, j = threadIdx.x & 15;
+      const uint32_t lo = wg_min[threadIdx.x], hi = wg_max[threadIdx.x];
+      if (j < a.K && t < a.ntrees && lo <= hi) {
+        const int gcol = (a.tree0 + t) * a.K + j;
+        atomicMin(&a.colmin[gcol], lo);
+        atomicMax(&a.colmax[gcol], hi);
       }
     }
   }
@@ -247,9 +286,10 @@ void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* r
     // A is stored per launch group: [group][d][NC]
     a.A = ix.A.as<float>() + (int64_t)(t0 / TREES_PER_LAUNCH) * ix.d * (TREES_PER_LAUNCH * 16);
     const int NC = nt * 16;
-    a.dk = std::min(((ix.d + 15) / 16) * 16, 128);
-    size_t smem = (size_t)a.dk * NC * 4;
-    if (mode == MODE_ENCODE) smem += (size_t)nt * ix.K * ix.Nr * 4 + (size_t)PROJ_WAVES * 16 * nt * KP;
+    a.dk = std::min(((ix.d + 15) / 16) * 16, DK_MAX);
+    size_t smem = (size_t)((a.dk * (NC + 4) + 3) & ~3) * 4;
+    if (mode == MODE_ENCODE)
+      smem += (size_t)((nt * ix.K * (ix.Nr + 1) + 3) & ~3) * 4 + (size_t)PROJ_WAVES * 16 * nt * KP;
     const bool vec4 = (ix.d % 4) == 0;
     const int grid = grid_for(m, ix.num_cus);
     if (mode == MODE_PROJECT) launch_mode<MODE_PROJECT>(nt, vec4, a, s, smem, grid);
