@@ -110,13 +110,20 @@ Span::Span(hipStream_t s, double* acc) : s_(s), acc_(acc) {
 void Span::finish() {
   if (!a_) return;
   PDET_HIP(hipEventRecord(b_, s_));
-  PDET_HIP(hipEventSynchronize(b_));
-  float ms = 0.0f;
-  PDET_HIP(hipEventElapsedTime(&ms, a_, b_));
-  *acc_ += ms;
-  (void)hipEventDestroy(a_);
-  (void)hipEventDestroy(b_);
+  timer().pending.push_back({a_, b_, acc_});
   a_ = b_ = nullptr;
+}
+
+void flush_timing() {
+  Timer& tm = timer();
+  for (const Timer::Pending& pd : tm.pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(pd.b) == hipSuccess && hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess)
+      *pd.acc += ms;
+    (void)hipEventDestroy(pd.a);
+    (void)hipEventDestroy(pd.b);
+  }
+  tm.pending.clear();
 }
 
 Span::~Span() {
@@ -250,6 +257,7 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
       sp.finish();
     }
     PDET_HIP(hipStreamSynchronize(s));
+    flush_timing();
     *out = ix;
     ix = nullptr;
   });
@@ -268,6 +276,7 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
     const QueryConfig qc = check_query(idx, queries, nq, p, ids, dists, qstats, k, c);
     if (nq == 0) return;
     run_query(*idx, qc, static_cast<hipStream_t>(stream));
+    flush_timing();
   });
 }
 
@@ -286,6 +295,7 @@ void pdet_set_timing(int32_t on) { timer().on = on != 0; }
 pdet_status pdet_get_timing(pdet_timing* out) {
   return guarded([&] {
     PDET_REQUIRE(out, PDET_EINVAL, "NULL argument");
+    flush_timing();
     *out = timer().t;
   });
 }

@@ -92,11 +92,16 @@ using Index = pdet_index;
 struct Timer {
   bool on = false;
   pdet_timing t{};
+  struct Pending { hipEvent_t a, b; double* acc; };
+  std::vector<Pending> pending;   // finished spans whose events are read at the next flush
 };
 Timer& timer();
+// Reads the events of every finished span into its accumulator (waits for them).
+void flush_timing();
 
-// Records HIP events around a region on stream `s` when timing is on; adds the
-// elapsed milliseconds to *acc at finish() (which synchronises the end event).
+// Records HIP events around a region on stream `s` when timing is on. finish() records
+// the end event without waiting; flush_timing() later adds the elapsed milliseconds to
+// *acc, so timed runs keep their kernels back to back.
 class Span {
  public:
   Span(hipStream_t s, double* acc);

@@ -27,7 +27,7 @@ def env():
     X, A, sid = w.data(), w.proj(), w.sample()
     print(f"\n[forms] n={len(X)} d={X.shape[1]}", flush=True)
     Xd = torch.from_numpy(X).cuda()
-    idx = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=("bf16",))
+    idx = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=("bf16", "fp8"))
     Q = w.queries()
     return w, X, A, sid, idx, Q, torch.from_numpy(Q).cuda()
 
@@ -96,7 +96,30 @@ def test_plan_replays_equal_eager_calls(env):
     plan.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_reserved_workspace_gives_the_same_results(env):
+    w, X, A, sid, idx, Q, Qd = env
+    before = idx.query(Qd, k=w.k, c=w.c, beta=0.05, r_min=3.0)
+    idx.reserve(4 * len(Q))
+    after = idx.query(Qd, k=w.k, c=w.c, beta=0.05, r_min=3.0)
+    assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
+
+
+def test_plan_low_precision_equals_eager(env):
+    w, X, A, sid, idx, Q, Qd = env
+    ks, cs = uneven(len(Q), seed=11)
+    plan = idx.plan(Qd, k=0, beta=0.05, r_min=3.0, k_per_query=ks, c_per_query=cs,
+                    precision="bf16", rescore=4)
+    e_ids, e_d = idx.query(Qd, k=0, beta=0.05, r_min=3.0, k_per_query=ks, c_per_query=cs,
+                           precision="bf16", rescore=4)
+    for rep in range(2):
+        plan.ids.fill_(-7)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.ids, e_ids) and torch.equal(plan.dists, e_d), rep
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 def test_server_results_same_alone_and_in_the_mix(env, precision):
     w, X, A, sid, idx, Q, Qd = env
     ks, cs = uneven(len(Q), seed=9)
