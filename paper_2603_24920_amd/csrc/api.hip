@@ -148,10 +148,11 @@ double epsilon(int K, int L) {
 
 int64_t pdet_index::device_bytes() const {
   int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + perm.bytes + leafrow.bytes +
-              xbf16.bytes + xfp8.bytes + xscale.bytes;
+              xbf16.bytes + xfp8.bytes + xscale.bytes + leaf_arena.bytes;
+  auto own = [](const pdet::DevBuf& x) { return x.owned ? (int64_t)x.bytes : 0; };
   for (int i = 0; i < PDET_MAX_L; ++i)
-    b += leaf_start[i].bytes + leaf_count[i].bytes + leaf_hidx[i].bytes + box[i].bytes +
-         gbox[i].bytes;
+    b += own(leaf_start[i]) + own(leaf_count[i]) + own(leaf_hidx[i]) + own(box[i]) +
+         own(gbox[i]);
   return b;
 }
 

@@ -38,17 +38,25 @@ void set_error(const std::string& msg);
     if (!(cond)) throw ::pdet::Error{(status), (msg)};      \
   } while (0)
 
-// Device buffer owned by RAII; freed with hipFree.
+// Device buffer owned by RAII; freed with hipFree. A view (view()) points into another
+// buffer and is never freed through itself.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) {
+    o.p = nullptr; o.bytes = 0; o.owned = true;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; owned = o.owned;
+      o.p = nullptr; o.bytes = 0; o.owned = true;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
@@ -63,10 +71,17 @@ struct DevBuf {
     }
     bytes = b;
   }
+  void view(void* q, size_t b) {
+    release();
+    p = q;
+    bytes = b;
+    owned = false;
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
   }
   template <class T> T* as() const { return static_cast<T*>(p); }
 };

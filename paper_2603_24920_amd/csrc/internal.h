@@ -37,7 +37,8 @@ struct pdet_index {
   pdet::DevBuf perm;               // int32 [L][n]
   pdet::DevBuf leafrow;            // int32 [L][n][L]: for the point at perm position p of tree
                                    // i, its leaf ordinal in every tree (read along leaves)
-  // per tree, leaves in depth-first order
+  // per tree, leaves in depth-first order (views into leaf_arena)
+  pdet::DevBuf leaf_arena;
   pdet::DevBuf leaf_start[PDET_MAX_L];   // int32 [nl]
   pdet::DevBuf leaf_count[PDET_MAX_L];   // int32 [nl]
   pdet::DevBuf leaf_hidx[PDET_MAX_L];    // uint16 [nl][KP]

@@ -462,6 +462,59 @@ __global__ __launch_bounds__(256) void group_boxes(GroupArgs a) {
   }
 }
 
+// Build temporaries come from a process-wide pool: they go back only after the build has
+// synchronised its stream (or are freed if an error unwinds the build), so a later build
+// of the same size reuses them without hipMalloc / hipFree. At most kPoolCap bytes are kept.
+class ScratchPool {
+ public:
+  DevBuf take(size_t b) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (size_t i = 0; i < free_.size(); ++i)
+        if (free_[i].bytes == b) {
+          DevBuf d = std::move(free_[i]);
+          free_.erase(free_.begin() + (int64_t)i);
+          held_ -= b;
+          return d;
+        }
+    }
+    return DevBuf(b);
+  }
+  void give(DevBuf&& d) {
+    if (!d.p) return;
+    if (std::uncaught_exceptions() > 0) { d.release(); return; }
+    std::lock_guard<std::mutex> g(mu_);
+    if (held_ + d.bytes > kPoolCap) { d.release(); return; }
+    held_ += d.bytes;
+    free_.push_back(std::move(d));
+  }
+ private:
+  static constexpr size_t kPoolCap = size_t(2) << 30;
+  std::mutex mu_;
+  std::vector<DevBuf> free_;
+  size_t held_ = 0;
+};
+
+ScratchPool& scratch_pool() {
+  static ScratchPool* p = new ScratchPool();   // lives until the process ends
+  return *p;
+}
+
+// A build temporary with DevBuf's interface, taken from and returned to the pool.
+struct PooledBuf {
+  DevBuf d;
+  PooledBuf() = default;
+  explicit PooledBuf(size_t b) { alloc(b); }
+  ~PooledBuf() { scratch_pool().give(std::move(d)); }
+  void alloc(size_t b) {
+    scratch_pool().give(std::move(d));
+    if (b) d = scratch_pool().take(b);
+  }
+  size_t bytes() const { return d.bytes; }
+  void* ptr() const { return d.p; }
+  template <class T> T* as() const { return d.as<T>(); }
+};
+
 }  // namespace
 
 void build_trees(Index& ix, hipStream_t s) {
@@ -469,10 +522,10 @@ void build_trees(Index& ix, hipStream_t s) {
   const int L = ix.L, K = ix.K, bits = ix.bits;
   const int64_t NK = 1ll << K;
 
-  DevBuf hist((size_t)L * NK * 4), off((size_t)L * NK * 4), cursor((size_t)L * NK * 4);
+  PooledBuf hist((size_t)L * NK * 4), off((size_t)L * NK * 4), cursor((size_t)L * NK * 4);
   DevBuf scan_tmp;
-  PDET_HIP(hipMemsetAsync(hist.p, 0, hist.bytes, s));
-  PDET_HIP(hipMemsetAsync(cursor.p, 0, cursor.bytes, s));
+  PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
+  PDET_HIP(hipMemsetAsync(cursor.ptr(), 0, cursor.bytes(), s));
   const uint8_t* codes = ix.codes.as<uint8_t>();
   int32_t* perm = ix.perm.as<int32_t>();
 
@@ -485,17 +538,17 @@ void build_trees(Index& ix, hipStream_t s) {
   PDET_HIP(hipGetLastError());
 
   // leaf records at start positions
-  DevBuf cnt_at((size_t)L * n * 4), hidx_at((size_t)L * n * KP * 2);
-  PDET_HIP(hipMemsetAsync(cnt_at.p, 0, cnt_at.bytes, s));
+  PooledBuf cnt_at((size_t)L * n * 4), hidx_at((size_t)L * n * KP * 2);
+  PDET_HIP(hipMemsetAsync(cnt_at.ptr(), 0, cnt_at.bytes(), s));
   LeafOut lo{cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>()};
 
   // segment lists; counters: [0] n_big_a [1] max_big_a [2] n_big_b [3] max_big_b [4] n_mid
   const int64_t mid_cap = (int64_t)L * (n / (ix.max_leaf + 1) + 1);
   const int64_t big_cap = (int64_t)L * (n / (LDS_SEG_CAP + 1) + 1);
-  DevBuf mid((size_t)mid_cap * sizeof(Seg));
-  DevBuf bigA((size_t)big_cap * sizeof(Seg)), bigB((size_t)big_cap * sizeof(Seg));
-  DevBuf ctr(8 * 4);
-  PDET_HIP(hipMemsetAsync(ctr.p, 0, ctr.bytes, s));
+  PooledBuf mid((size_t)mid_cap * sizeof(Seg));
+  PooledBuf bigA((size_t)big_cap * sizeof(Seg)), bigB((size_t)big_cap * sizeof(Seg));
+  PooledBuf ctr(8 * 4);
+  PDET_HIP(hipMemsetAsync(ctr.ptr(), 0, ctr.bytes(), s));
   uint32_t* c = ctr.as<uint32_t>();
   Lists li{bigA.as<Seg>(), c + 0, c + 1, mid.as<Seg>(), c + 4};
   hipLaunchKernelGGL(fl_segments, dim3(cdiv(L * NK, 256)), dim3(256), 0, s, hist.as<uint32_t>(),
@@ -509,15 +562,15 @@ void build_trees(Index& ix, hipStream_t s) {
   Seg* cur_big = bigA.as<Seg>();
   Seg* nxt_big = bigB.as<Seg>();
   int cur_slot = 0;   // counters of the current list at c[2*cur_slot]
-  DevBuf perm_tmp, cntbuf, split, c0, cur0, cur1;
+  PooledBuf perm_tmp, cntbuf, split, c0, cur0, cur1;
   if (nbig) perm_tmp.alloc((size_t)L * n * 4);
   while (nbig > 0) {
-    if (cntbuf.bytes < (size_t)nbig * KP * 4) {
+    if (cntbuf.bytes() < (size_t)nbig * KP * 4) {
       cntbuf.alloc((size_t)big_cap * KP * 4);
       split.alloc((size_t)big_cap * 4); c0.alloc((size_t)big_cap * 4);
       cur0.alloc((size_t)big_cap * 4); cur1.alloc((size_t)big_cap * 4);
     }
-    PDET_HIP(hipMemsetAsync(cntbuf.p, 0, (size_t)nbig * KP * 4, s));
+    PDET_HIP(hipMemsetAsync(cntbuf.ptr(), 0, (size_t)nbig * KP * 4, s));
     const int nxt_slot = 1 - cur_slot;
     PDET_HIP(hipMemsetAsync(c + 2 * nxt_slot, 0, 8, s));
     const unsigned ch = std::max(1u, std::min(1024u, cdiv(maxbig, 256 * 16)));
@@ -564,23 +617,35 @@ void build_trees(Index& ix, hipStream_t s) {
   }
 
   // number the leaves in position (= depth-first) order
-  DevBuf flags((size_t)L * n * 4), totals((size_t)L * 4);
+  PooledBuf flags((size_t)L * n * 4), totals((size_t)L * 4);
   hipLaunchKernelGGL(leaf_flags, dim3(cdiv((int64_t)L * n, 256)), dim3(256), 0, s,
                      cnt_at.as<uint32_t>(), flags.as<uint32_t>(), (int64_t)L * n);
   PDET_HIP(hipGetLastError());
   scan_rows(flags.as<uint32_t>(), flags.as<uint32_t>(), totals.as<uint32_t>(), L, n, scan_tmp, s);
   std::vector<uint32_t> nl(L);
-  PDET_HIP(hipMemcpyAsync(nl.data(), totals.p, L * 4, hipMemcpyDeviceToHost, s));
+  PDET_HIP(hipMemcpyAsync(nl.data(), totals.ptr(), L * 4, hipMemcpyDeviceToHost, s));
   PDET_HIP(hipStreamSynchronize(s));
   LeafTables t{};
   ix.nl_max = 0;
+  // every tree's leaf tables and group boxes in one allocation (256-byte aligned parts)
+  auto part = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
+  size_t arena = 0;
+  for (int i = 0; i < L; ++i) {
+    const size_t ng = (size_t)std::max<int64_t>((nl[i] + 15) / 16, 1);
+    arena += part((size_t)nl[i] * 4) * 2 + part((size_t)nl[i] * KP * 2) +
+             part((size_t)nl[i] * 2 * K * 4) + part(ng * 2 * K * 4);
+  }
+  ix.leaf_arena.alloc(arena);
+  char* cur = ix.leaf_arena.as<char>();
+  auto take = [&](DevBuf& v, size_t b) { v.view(cur, b); cur += part(b); };
   for (int i = 0; i < L; ++i) {
     ix.nl[i] = nl[i];
     ix.nl_max = std::max<int64_t>(ix.nl_max, nl[i]);
-    ix.leaf_start[i].alloc((size_t)nl[i] * 4);
-    ix.leaf_count[i].alloc((size_t)nl[i] * 4);
-    ix.leaf_hidx[i].alloc((size_t)nl[i] * KP * 2);
-    ix.box[i].alloc((size_t)nl[i] * 2 * K * 4);
+    take(ix.leaf_start[i], (size_t)nl[i] * 4);
+    take(ix.leaf_count[i], (size_t)nl[i] * 4);
+    take(ix.leaf_hidx[i], (size_t)nl[i] * KP * 2);
+    take(ix.box[i], (size_t)nl[i] * 2 * K * 4);
+    take(ix.gbox[i], (size_t)std::max<int64_t>((nl[i] + 15) / 16, 1) * 2 * K * 4);
     t.start[i] = ix.leaf_start[i].as<int32_t>();
     t.count[i] = ix.leaf_count[i].as<int32_t>();
     t.hidx[i] = ix.leaf_hidx[i].as<uint16_t>();
@@ -595,7 +660,6 @@ void build_trees(Index& ix, hipStream_t s) {
   int64_t nl_pad = 0;
   for (int i = 0; i < L; ++i) {
     const int64_t ng = (nl[i] + 15) / 16;
-    ix.gbox[i].alloc((size_t)std::max<int64_t>(ng, 1) * 2 * K * 4);
     ga.box[i] = ix.box[i].as<float>();
     ga.gbox[i] = ix.gbox[i].as<float>();
     ga.nl[i] = nl[i];
@@ -606,7 +670,7 @@ void build_trees(Index& ix, hipStream_t s) {
     hipLaunchKernelGGL(group_boxes, dim3(cdiv(nl_pad, 256), L), dim3(256), 0, s, ga);
     PDET_HIP(hipGetLastError());
   }
-  DevBuf leaf_of((size_t)n * L * 4);
+  PooledBuf leaf_of((size_t)n * L * 4);
   hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
                      flags.as<uint32_t>(), perm, n, L, leaf_of.as<int32_t>());
   PDET_HIP(hipGetLastError());
