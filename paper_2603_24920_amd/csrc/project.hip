@@ -67,14 +67,18 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
   const int nchunks = (a.d + a.dk - 1) / a.dk;
 
   if constexpr (MODE == MODE_ENCODE) {
-    // interior breakpoints B(2..Nr) of every column of this launch, padded with +inf
-    const int tot = NT * a.K * a.Nr;
+    // the Nr - 1 interior breakpoints B(2..Nr) of every column of this launch, in
+    // breadth-first order of the implicit search tree (slot k = 1 .. Nr-1 holds the
+    // in-order element (2j+1) 2^(bits-1-depth) - 1, j = k - 2^depth): the candidates of one
+    // search step are neighbours, so the lanes searching a column spread over the banks
+    const int tot = NT * a.K * (a.Nr - 1);
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-      const int c = e / a.Nr, u = e % a.Nr;
+      const int c = e / (a.Nr - 1), k = e % (a.Nr - 1) + 1;
+      const int depth = 31 - __clz(k), j = k - (1 << depth);
+      const int inorder = ((2 * j + 1) << (a.bits - 1 - depth)) - 1;
       const int gcol = (a.tree0 + c / a.K) * a.K + c % a.K;
-      Bs[c * bstride + u] = (u < a.Nr - 1 && c / a.K < a.ntrees)
-                                ? a.Btab[(int64_t)gcol * (a.Nr + 1) + 1 + u]
-                                : INFINITY;
+      Bs[c * bstride + k] =
+          (c / a.K < a.ntrees) ? a.Btab[(int64_t)gcol * (a.Nr + 1) + 1 + inorder] : INFINITY;
     }
   }
 
@@ -184,10 +188,10 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
           if (col16 < a.K && t < a.ntrees) {
             const float h = acc[t][i];
             const float* tab = Bs + (t * a.K + col16) * bstride;
-            int pos = 0;
-            for (int s = a.Nr >> 1; s > 0; s >>= 1)
-              if (tab[pos + s - 1] <= h) pos += s;
-            code = static_cast<uint8_t>(pos);
+            // descend the implicit tree: after bits steps, node - Nr = #{B(z) <= h}
+            int node = 1;
+            for (int step = 0; step < a.bits; ++step) node = 2 * node + (tab[node] <= h ? 1 : 0);
+            code = static_cast<uint8_t>(node - a.Nr);
             if (pbase + i < a.m) { vmin[t] = fminf(vmin[t], h); vmax[t] = fmaxf(vmax[t], h); }
           }
           st[(pl * NT + t) * KP + col16] = code;

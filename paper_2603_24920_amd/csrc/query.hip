@@ -164,7 +164,8 @@ __device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, con
 }
 
 __global__ __launch_bounds__(256) void q_rho(QArgs a) {
-  __shared__ float sq[QT][PDET_MAX_K];
+  // one padding word per query row: the 16 queries a wave tests at once read 16 banks
+  __shared__ float sq[QT][PDET_MAX_K + 1];
   __shared__ float st[QT][RCAP_MAX + 1];
   const int tree = blockIdx.y;
   const int slot0 = blockIdx.z * QT;
