@@ -46,6 +46,30 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* t
   return r;
 }
 
+// A double moved across lanes with a DPP control (both 32-bit halves; every lane of the
+// row must be active).
+template <int CTRL>
+__device__ inline double dpp_double(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum of x over each aligned group of `width` lanes (a power of two <= 64); lane 0 of a
+// group holds the exact group sum of its order, other lanes a sum in another order.
+// Within a 16-lane row the steps are DPP moves (quad swaps, half-row mirror, row mirror);
+// across rows they are lane shuffles.
+__device__ inline double group_sum(double x, int width) {
+  if (width > 1) x += dpp_double<0xB1>(x);    // quad_perm [1,0,3,2]
+  if (width > 2) x += dpp_double<0x4E>(x);    // quad_perm [2,3,0,1]
+  if (width > 4) x += dpp_double<0x141>(x);   // row_half_mirror
+  if (width > 8) x += dpp_double<0x140>(x);   // row_mirror
+  if (width > 16) x += __shfl_xor(x, 16);
+  if (width > 32) x += __shfl_xor(x, 32);
+  return x;
+}
+
 __device__ inline uint32_t lanes_below_mask(uint64_t mask) {
   const int lane = threadIdx.x & 63;
   return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));

@@ -337,7 +337,7 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    for (int o = lpc >> 1; o > 0; o >>= 1) accd[r] += __shfl_xor(accd[r], o);
+    accd[r] = group_sum(accd[r], lpc);
     out[r] = sqrt(accd[r]);
   }
 }
@@ -416,6 +416,8 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   __shared__ uint32_t gopen[GCH / 32];
   __shared__ uint32_t ent_off[PDET_MAX_L + 1];
   __shared__ uint32_t s_mt[PDET_MAX_L];
+  __shared__ uint32_t s_pt[PDET_MAX_L];          // points of the round's leaves per tree
+  __shared__ uint32_t ent_pre[PDET_MAX_L + 1];   // pre2 at the tree boundaries ent_off[i]
   __shared__ uint32_t s_lc[PDET_MAX_L];          // leaf-list lengths per tree
   __shared__ uint32_t s_lco[PDET_MAX_L + 1];     // their prefix (lists in tree order)
   __shared__ uint32_t hkey[HSZ];
@@ -478,11 +480,10 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   // top-k; WALK_CUT (entries in admission order) does the same up to and including the
   // first leaf after which R new points have been admitted, whose entry goes to cut_e
   // (NO_CUT if the range holds fewer). Returns the number of new points admitted (uniform).
-  auto traverse = [&](int mode, int rho, uint32_t e_lo, uint32_t e_hi, uint32_t R,
-                      uint32_t& cut_e) -> uint32_t {
+  // P0, P1: the prefix values pre2[e_lo], pre2[e_hi] (uniform; passed in from LDS copies).
+  auto traverse = [&](int mode, int rho, uint32_t e_lo, uint32_t e_hi, uint32_t P0,
+                      uint32_t P1, uint32_t R, uint32_t& cut_e) -> uint32_t {
     uint32_t newc = 0;
-    const uint32_t P0 = uni(pre2[e_lo]);
-    uint32_t P1 = uni(pre2[e_hi]);
     cut_e = NO_CUT;
     if (tid == 0) s_ef = e_lo;
     __syncthreads();
@@ -529,7 +530,8 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
         if (ef + tid < e_hi && newc + ex + c >= R) atomicMin(&s_cute, ef + tid);
         __syncthreads();
         cut_e = uni(s_cute);
-        if (cut_e != NO_CUT) P1 = std::min(P1, uni(pre2[cut_e + 1]));   // the rest of that leaf
+        // the rest of that leaf (its end prefix is in the window: cut_e - ef < QM)
+        if (cut_e != NO_CUT) P1 = std::min(P1, uni(w_pre[cut_e + 1 - ef]));
       }
       if (mode == WALK_CUT && cut_e != NO_CUT) nw = nw && ef + lo <= cut_e;
       const uint64_t mask = __ballot(nw);
@@ -590,9 +592,8 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
 
   // Puts the entries [e0, e1) of tree i (at most QM) in admission order, ascending
   // (LB^2, leaf ordinal) (keys are distinct within a tree), with their prefix list rebuilt.
-  auto order_entries = [&](uint32_t e0, uint32_t e1, int i) {
+  auto order_entries = [&](uint32_t e0, uint32_t e1, uint32_t P0, int i) {
     const uint32_t mi = e1 - e0, e = e0 + tid;
-    const uint32_t P0 = uni(pre2[e0]);
     unsigned long long key = ~0ull;
     uint32_t en = 0, cnt = 0;
     int32_t st0 = 0;
@@ -601,7 +602,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
       st0 = ast[e];
       cnt = pre2[e + 1] - pre2[e];
       const uint32_t leaf = en & ((1u << TREE_SHIFT) - 1);
-      const float lb = leaf_lb2<LBCH>(a.box[i], a.nl[i], leaf, qps + i * a.K, a.K);
+      const float lb = leaf_lb2<2 * LBCH>(a.box[i], a.nl[i], leaf, qps + i * a.K, a.K);
       key = ((unsigned long long)__float_as_uint(lb) << 32) | leaf;
     }
     sel_key[tid] = key;
@@ -756,7 +757,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     }
     // admitted leaves of this round, from the lists in tree order: entries, their sizes'
     // prefix sums and their perm start positions
-    if (tid < a.L) s_mt[tid] = 0;
+    if (tid < a.L) { s_mt[tid] = 0; s_pt[tid] = 0; }
     if (tid == 0) {
       s_cnt = 0;
       s_lco[0] = 0;
@@ -781,6 +782,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           cnt = (uint32_t)a.lcount[tr][leaf];
           st0 = a.lstart[tr][leaf];
           atomicAdd(&s_mt[tr], 1u);
+          atomicAdd(&s_pt[tr], cnt);
         }
       }
       uint32_t t1, t2;
@@ -793,7 +795,11 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     if (tid == 0) {
       pre2[m] = P;
       ent_off[0] = 0;   // tree i's entries are [ent_off[i], ent_off[i+1]) of the list
-      for (int i = 0; i < a.L; ++i) ent_off[i + 1] = ent_off[i] + s_mt[i];
+      ent_pre[0] = 0;
+      for (int i = 0; i < a.L; ++i) {
+        ent_off[i + 1] = ent_off[i] + s_mt[i];
+        ent_pre[i + 1] = ent_pre[i] + s_pt[i];
+      }
     }
     __syncthreads();
     // this round's leaves join the dedupe state (every thread reads the lists and hn alike)
@@ -830,18 +836,19 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
       if (nS + pts < T) {
         // stop rule A cannot fire in this round: admit every tree's leaves in one pass
         leaves += m;
-        nS += traverse(WALK_VERIFY, rho, 0, m, 0, ce);
+        nS += traverse(WALK_VERIFY, rho, 0, m, 0, P, 0, ce);
       } else {
         // trees in order; exact counts decide the tree (and leaf) where |S| reaches T
         for (int i = 0; i < a.L && stop < 0; ++i) {
           const uint32_t e0 = uni(ent_off[i]), e1 = uni(ent_off[i + 1]);
           if (e0 == e1) continue;
-          const int64_t pts_i = (int64_t)uni(pre2[e1]) - (int64_t)uni(pre2[e0]);
+          const uint32_t p0 = uni(ent_pre[i]), p1 = uni(ent_pre[i + 1]);
+          const int64_t pts_i = (int64_t)p1 - (int64_t)p0;
           if (nS + pts_i < T || e1 - e0 <= (uint32_t)QM) {
             // whole tree, or its leaves in admission order up to the one where |S| reaches T
             const bool may_stop = nS + pts_i >= T;
-            if (may_stop) order_entries(e0, e1, i);
-            nS += traverse(may_stop ? WALK_CUT : WALK_VERIFY, rho, e0, e1,
+            if (may_stop) order_entries(e0, e1, p0, i);
+            nS += traverse(may_stop ? WALK_CUT : WALK_VERIFY, rho, e0, e1, p0, p1,
                            (uint32_t)(T - nS), ce);
             if (ce != NO_CUT) {
               leaves += ce - e0 + 1;
@@ -867,7 +874,8 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           }
           for (uint32_t e = e0 + tid; e < e1c; e += QM) admw[e] = 0;
           __syncthreads();
-          const uint32_t new_i = traverse(WALK_COUNT, rho, e0, e1c, 0, ce);
+          const uint32_t new_i =
+              traverse(WALK_COUNT, rho, e0, e1c, p0, uni(pre2[e1c]), 0, ce);
           uint32_t e_end = e1;
           if (nS + (int64_t)new_i < T) {
             if (e1c != e1) { stop = -2; break; }   // contradicts the bound above
@@ -878,7 +886,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
             stop = 1;
           }
           leaves += e_end - e0;
-          nS += traverse(WALK_VERIFY, rho, e0, e_end, 0, ce);
+          nS += traverse(WALK_VERIFY, rho, e0, e_end, p0, uni(pre2[e_end]), 0, ce);
         }
       }
       if (stop >= 0) break;
