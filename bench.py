@@ -264,6 +264,11 @@ def main():
     if not args.no_serve:
         serving = serve_measurement(ix, Q, w, beta, r_min, rcap)
         log(f"[bench] serving: {serving}")
+        # the low-precision forms served at their own recall-matched beta
+        for f, (lb, lr, lc, lrec) in lowp_cal.items():
+            serving[f] = serve_measurement(ix, Q, w, lb, lr, lc, precision=f)
+            serving[f]["recall_at_10"] = lrec
+            log(f"[bench] serving {f}: {serving[f]}")
     ix.close()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, X, A, sid, Q, beta, r_min)
@@ -313,12 +318,14 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def serve_measurement(ix, Q, w, beta, r_min, rcap, seconds=1.0, max_batch=1024):
+def serve_measurement(ix, Q, w, beta, r_min, rcap, seconds=1.0, max_batch=1024,
+                      precision="fp32"):
     """Saturation QPS from a burst, then Poisson arrivals at fractions of it (capped by
     what one Python client thread can submit): p50 / p99 latency and achieved QPS."""
     ix.set_tuning(r_min, rcap)
-    out = {}
-    sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min)
+    out = {"precision": precision}
+    sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min,
+                   precision=precision)
     n_burst = min(len(Q), 4096)
     t0 = time.perf_counter()
     rids = [sv.submit(Q[i], w.k, w.c) for i in range(n_burst)]
@@ -331,7 +338,8 @@ def serve_measurement(ix, Q, w, beta, r_min, rcap, seconds=1.0, max_batch=1024):
     rng = np.random.default_rng(11)
     for frac in (0.25, 0.5, 0.9):
         rate = min(frac * sat, client_cap)
-        sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min)
+        sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min,
+                       precision=precision)
         nreq = max(200, int(rate * seconds))
         gaps = rng.exponential(1.0 / rate, size=nreq)
         t_arr = np.cumsum(gaps)

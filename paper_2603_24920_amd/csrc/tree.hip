@@ -250,7 +250,7 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
   __shared__ Node stack[STACK_MAX];
   __shared__ Node cur;
   __shared__ int sp;
-  __shared__ int state;          // 0 done, 1 leaf, 2 split
+  __shared__ int state;          // 0 done, 2 split
   __shared__ uint32_t cnt[KP];
   __shared__ uint32_t cz, co;
   __shared__ int jsplit;
@@ -276,16 +276,20 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
   const int lane = threadIdx.x & 63;
   for (;;) {
     if (threadIdx.x == 0) {
-      if (sp == 0) {
-        state = 0;
-      } else {
+      // pop until a node to split (state 2) or an empty stack (state 0); leaves met on the
+      // way are emitted here, in the same depth-first order
+      state = 0;
+      while (sp > 0) {
         cur = stack[--sp];
         bool fully = true;
         for (int j = 0; j < K; ++j) fully = fully && (cur.depth[j] >= bits);
-        state = (cur.lcount <= max_leaf || fully) ? 1 : 2;
-        if (state == 1)
+        if (cur.lcount <= max_leaf || fully) {
           emit_leaf(lo, n, s.tree, (int64_t)s.start + cur.lstart, cur.lcount, cur.depth,
                     cur.prefix, K);
+          continue;
+        }
+        state = 2;
+        break;
       }
     }
     if (threadIdx.x < KP) cnt[threadIdx.x] = 0;
@@ -293,7 +297,6 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
     const int st = state;
     __syncthreads();            // every thread has read `state` before thread 0 pops again
     if (st == 0) break;
-    if (st == 1) continue;
 
     uint32_t local[KP];
 #pragma unroll
