@@ -171,24 +171,43 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   const int slot0 = blockIdx.z * QT;
   const int64_t nl = a.nl[tree], ng = a.ng[tree];
   const int rcap = a.rcap;
-  for (int e = threadIdx.x; e < QT * (RCAP_MAX + 1); e += blockDim.x) {
-    const int qi = e / (RCAP_MAX + 1), r = e % (RCAP_MAX + 1);
-    st[qi][r] = (slot0 + qi < a.nslots) ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
-  }
-  for (int e = threadIdx.x; e < QT * a.K; e += blockDim.x) {
-    const int qi = e / a.K, j = e % a.K;
-    sq[qi][j] = (slot0 + qi < a.nslots)
-                    ? a.qp[(a.q0 + slot0 + qi) * (int64_t)(a.L * a.K) + tree * a.K + j]
-                    : 0.0f;
-  }
-  __syncthreads();
   const int64_t leaf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t g = leaf / GL;
   const int sl = threadIdx.x & 15;
-  // lane sl of the 16 lanes sharing group g tests that group against query 16*sub + sl
-  uint64_t open_mask = 0;
+  // the group box does not depend on the staged queries: its loads are issued first and
+  // are in flight while the query tile is staged
   float lo[PDET_MAX_K], hi[PDET_MAX_K];
   if (g < ng) load_box(a.gbox[tree], ng, g, a.K, lo, hi);
+  // thresholds and projected queries of the tile: every load issued before any is stored
+  constexpr int NST = (QT * (RCAP_MAX + 1) + 255) / 256, NSQ = QT * PDET_MAX_K / 256;
+  float stv[NST], sqv[NSQ];
+#pragma unroll
+  for (int u = 0; u < NST; ++u) {
+    const int e = threadIdx.x + u * 256;
+    const int qi = e / (RCAP_MAX + 1), r = e % (RCAP_MAX + 1);
+    stv[u] = (e < QT * (RCAP_MAX + 1) && slot0 + qi < a.nslots)
+                 ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
+  }
+#pragma unroll
+  for (int u = 0; u < NSQ; ++u) {
+    const int e = threadIdx.x + u * 256;
+    const int qi = e / a.K, j = e % a.K;
+    sqv[u] = (e < QT * a.K && slot0 + qi < a.nslots)
+                 ? a.qp[(a.q0 + slot0 + qi) * (int64_t)(a.L * a.K) + tree * a.K + j] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < NST; ++u) {
+    const int e = threadIdx.x + u * 256;
+    if (e < QT * (RCAP_MAX + 1)) st[e / (RCAP_MAX + 1)][e % (RCAP_MAX + 1)] = stv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NSQ; ++u) {
+    const int e = threadIdx.x + u * 256;
+    if (e < QT * a.K) sq[e / a.K][e % a.K] = sqv[u];
+  }
+  __syncthreads();
+  // lane sl of the 16 lanes sharing group g tests that group against query 16*sub + sl
+  uint64_t open_mask = 0;
   for (int sub = 0; sub < QT / 16; ++sub) {
     const int qi = sub * 16 + sl;
     bool open = false;
