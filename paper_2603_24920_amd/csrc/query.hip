@@ -17,7 +17,7 @@
 //           its leaves in the other trees was admitted earlier in the (round, tree) order
 //           (closed form of the candidate union, read from leafrow and the admission
 //           rounds of the leaves admitted so far, kept in an LDS hash, or in a dense table
-//           in device memory past 1024 leaves). When stop rule A can fire in a round,
+//           in device memory past 512 leaves). When stop rule A can fire in a round,
 //           exact new-point counts per leaf give the tree where |S| reaches T, and a
 //           weighted select over that tree's (LB^2, leaf ordinal) keys gives the leaf;
 //           trees before it are admitted whole. New points are verified by exact distance
@@ -39,7 +39,7 @@ constexpr int RWIN = 3;          // rounds resolved per refinement step inside q
 constexpr int GCH = 2048;        // groups per refinement chunk (LDS bitmap of GCH bits)
 constexpr int TREE_SHIFT = 28;   // admitted-leaf entries pack (tree << 28) | leaf
 constexpr int LEAF_BITS = 24;    // leaf-list entries pack (round << 24) | leaf
-constexpr int HSZ = 2048;        // LDS hash of (tree, leaf) -> round for the dedupe test
+constexpr int HSZ = 1024;        // LDS hash of (tree, leaf) -> round for the dedupe test
 constexpr int HMAX = HSZ / 2;    // most entries it takes; beyond, a dense table in HBM
 constexpr uint32_t HEMPTY = 0xffffffffu;
 constexpr uint32_t NO_CUT = 0xffffffffu;
@@ -409,8 +409,9 @@ __device__ inline bool is_new(const QArgs& a, bool dense, const uint8_t* rr, con
 }
 
 // One workgroup per query (see the file header). The kernels below instantiate it with the
-// occupancy each form reaches: float32 verification keeps a small top-k list and runs six
-// workgroups per CU; the low-precision forms keep k * rescore candidates and run five.
+// occupancy each form reaches: float32 verification keeps a small top-k list and runs eight
+// workgroups per CU (a few registers spill; the latency-bound kernel gains more from the
+// extra queries in flight); the low-precision forms keep k * rescore candidates and run five.
 template <int PREC>
 __device__ __forceinline__ void q_main_body(const QArgs& a) {
   extern __shared__ __align__(16) unsigned char sm[];
@@ -985,7 +986,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   }
 }
 
-__global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(6))) void q_main_f32(QArgs a) {
+__global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(8))) void q_main_f32(QArgs a) {
   q_main_body<PDET_FP32>(a);
 }
 

@@ -245,7 +245,7 @@ def test_query_stepwise_mixture(mixture, beta, r_min):
 
 def test_query_stepwise_past_the_lds_hash(mixture):
     # k = 1000 and c = 1.05 keep stop rule B from firing early: every query admits more than
-    # 1024 leaves, so its dedupe state moves from the LDS hash to the dense round table in
+    # 1024 leaves (the LDS hash holds 512), so its dedupe state moves to the dense round table in
     # device memory (and is restored for the slot's next query)
     w, cs = mixture
     Q = w.queries(20)
