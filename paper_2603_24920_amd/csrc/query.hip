@@ -411,7 +411,7 @@ __device__ inline bool is_new(const QArgs& a, bool dense, const uint8_t* rr, con
 // One workgroup per query (see the file header). The kernels below instantiate it with the
 // occupancy each form reaches: float32 verification keeps a small top-k list and runs eight
 // workgroups per CU (a few registers spill; the latency-bound kernel gains more from the
-// extra queries in flight); the low-precision forms keep k * rescore candidates and run five.
+// extra queries in flight); the low-precision forms keep k * rescore candidates and run six.
 template <int PREC>
 __device__ __forceinline__ void q_main_body(const QArgs& a) {
   extern __shared__ __align__(16) unsigned char sm[];
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(8))) void q_
 }
 
 template <int PREC>
-__global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(5))) void q_main_lowp(QArgs a) {
+__global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(6))) void q_main_lowp(QArgs a) {
   q_main_body<PREC>(a);
 }
 
