@@ -32,6 +32,7 @@ namespace {
 constexpr int QM = 256;          // threads of q_main
 constexpr int CBMIN = 384;       // least pending-candidate buffer beside the top-k list (>= QM)
 constexpr int QT = 64;           // queries per q_rho block (group tests in sub-tiles of 16)
+constexpr int QR_THREADS = 256;  // leaves per q_rho block (one per thread)
 constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
 constexpr int GL = 16;           // leaves per pruning group
 constexpr int RCAP_MAX = 8;      // most rounds q_rho resolves (the index's rcap <= this)
@@ -163,7 +164,7 @@ __device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, con
   return acc;
 }
 
-__global__ __launch_bounds__(256) void q_rho(QArgs a) {
+__global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
   // one padding word per query row: the 16 queries a wave tests at once read 16 banks
   __shared__ float sq[QT][PDET_MAX_K + 1];
   __shared__ float st[QT][RCAP_MAX + 1];
@@ -179,30 +180,31 @@ __global__ __launch_bounds__(256) void q_rho(QArgs a) {
   float lo[PDET_MAX_K], hi[PDET_MAX_K];
   if (g < ng) load_box(a.gbox[tree], ng, g, a.K, lo, hi);
   // thresholds and projected queries of the tile: every load issued before any is stored
-  constexpr int NST = (QT * (RCAP_MAX + 1) + 255) / 256, NSQ = QT * PDET_MAX_K / 256;
+  constexpr int NST = (QT * (RCAP_MAX + 1) + QR_THREADS - 1) / QR_THREADS;
+  constexpr int NSQ = (QT * PDET_MAX_K + QR_THREADS - 1) / QR_THREADS;
   float stv[NST], sqv[NSQ];
 #pragma unroll
   for (int u = 0; u < NST; ++u) {
-    const int e = threadIdx.x + u * 256;
+    const int e = threadIdx.x + u * QR_THREADS;
     const int qi = e / (RCAP_MAX + 1), r = e % (RCAP_MAX + 1);
     stv[u] = (e < QT * (RCAP_MAX + 1) && slot0 + qi < a.nslots)
                  ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
   }
 #pragma unroll
   for (int u = 0; u < NSQ; ++u) {
-    const int e = threadIdx.x + u * 256;
+    const int e = threadIdx.x + u * QR_THREADS;
     const int qi = e / a.K, j = e % a.K;
     sqv[u] = (e < QT * a.K && slot0 + qi < a.nslots)
                  ? a.qp[(a.q0 + slot0 + qi) * (int64_t)(a.L * a.K) + tree * a.K + j] : 0.0f;
   }
 #pragma unroll
   for (int u = 0; u < NST; ++u) {
-    const int e = threadIdx.x + u * 256;
+    const int e = threadIdx.x + u * QR_THREADS;
     if (e < QT * (RCAP_MAX + 1)) st[e / (RCAP_MAX + 1)][e % (RCAP_MAX + 1)] = stv[u];
   }
 #pragma unroll
   for (int u = 0; u < NSQ; ++u) {
-    const int e = threadIdx.x + u * 256;
+    const int e = threadIdx.x + u * QR_THREADS;
     if (e < QT * a.K) sq[e / a.K][e % a.K] = sqv[u];
   }
   __syncthreads();
@@ -1163,9 +1165,9 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
       Span sp(s, timed ? &tm.query_rho_ms : nullptr);
       hipLaunchKernelGGL(q_setup, dim3(cdiv(a.nslots, 64)), dim3(64), 0, s, a);
       PDET_HIP(hipGetLastError());
-      hipLaunchKernelGGL(q_rho, dim3(cdiv(((ix.nl_max + GL - 1) / GL) * GL, 256), ix.L,
+      hipLaunchKernelGGL(q_rho, dim3(cdiv(((ix.nl_max + GL - 1) / GL) * GL, QR_THREADS), ix.L,
                                      cdiv(a.nslots, QT)),
-                         dim3(256), 0, s, a);
+                         dim3(QR_THREADS), 0, s, a);
       PDET_HIP(hipGetLastError());
       sp.finish();
     }
