@@ -33,6 +33,7 @@ constexpr int QM = 256;          // threads of q_main
 constexpr int CBMIN = 384;       // least pending-candidate buffer beside the top-k list (>= QM)
 constexpr int QT = 64;           // queries per q_rho block (group tests in sub-tiles of 16)
 constexpr int QR_THREADS = 256;  // leaves per q_rho block (one per thread)
+constexpr int NXCD = 8;          // accelerator dies; workgroup i runs on die i % NXCD
 constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
 constexpr int GL = 16;           // leaves per pruning group
 constexpr int RCAP_MAX = 8;      // most rounds q_rho resolves (the index's rcap <= this)
@@ -64,6 +65,7 @@ struct QArgs {
   int64_t nlo[PDET_MAX_L];   // first slot of tree i's region in a per-query leaf list
   int64_t ng[PDET_MAX_L];
   int64_t nlpad;
+  int lb_per_die;            // q_rho leaf blocks (256 leaves) of a tree that each die takes
   const float* Q;
   const float* qp;           // [nq][L*K]
   const int32_t* qk;
@@ -112,14 +114,22 @@ __global__ void q_setup(QArgs a) {
   for (int i = 0; i < PDET_MAX_L; ++i) a.lcnt[(int64_t)slot * PDET_MAX_L + i] = 0;
 }
 
+// float in the global address space (a pointer rebuilt from scalar registers keeps it)
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) const char gchar;
+
 // Box `b` of a structure-of-arrays box table [2][K][nb] (lower corners, then upper). The
 // loop runs over the largest K so that all 2K loads are issued before the first is used.
-__device__ inline void load_box(const float* box, int64_t nb, int64_t b, int K,
+// Column starts are uniform and the row offset is a 32-bit lane value (2K*nb < 2^30 since a
+// tree has fewer than 2^24 leaves), so each load is a scalar base plus one vector offset.
+__device__ inline void load_box(const float* box, int64_t nb, uint32_t b, int K,
                                 float (&lo)[PDET_MAX_K], float (&hi)[PDET_MAX_K]) {
 #pragma unroll
   for (int j = 0; j < PDET_MAX_K; ++j) {
-    lo[j] = (j < K) ? box[(int64_t)j * nb + b] : 0.0f;
-    hi[j] = (j < K) ? box[(int64_t)(K + j) * nb + b] : 0.0f;
+    const gchar* cl = (const gchar*)uni((uint64_t)(box + (int64_t)j * nb));
+    const gchar* ch = (const gchar*)uni((uint64_t)(box + (int64_t)(K + j) * nb));
+    lo[j] = (j < K) ? *(const gfloat*)(cl + b * 4u) : 0.0f;
+    hi[j] = (j < K) ? *(const gfloat*)(ch + b * 4u) : 0.0f;
   }
 }
 
@@ -164,24 +174,34 @@ __device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, con
   return acc;
 }
 
+// KT: the projection width K when it is fixed at compile time (16, the usual case), else 0.
+template <int KT>
 __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
+  const int K = KT ? KT : a.K;
   // one padding word per query row: the 16 queries a wave tests at once read 16 banks
   __shared__ float sq[QT][PDET_MAX_K + 1];
   __shared__ float st[QT][RCAP_MAX + 1];
-  const int tree = blockIdx.y;
-  const int slot0 = blockIdx.z * QT;
+  // Grid (NXCD * query tiles, lb_per_die, L): the row length is a multiple of NXCD, so
+  // blockIdx.x % NXCD is the die a workgroup runs on. Each die takes a fixed share of every
+  // tree's leaf blocks and runs through the query tiles of one leaf block after another,
+  // which keeps its share of the box tables and the tile's queries in its own L2.
+  const int die = blockIdx.x % NXCD;
+  const int slot0 = (blockIdx.x / NXCD) * QT;
+  const int tree = blockIdx.z;
   const int64_t nl = a.nl[tree], ng = a.ng[tree];
+  const int64_t lb = (int64_t)die * a.lb_per_die + blockIdx.y;
+  if (lb * QR_THREADS >= nl) return;
   const int rcap = a.rcap;
-  const int64_t leaf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t leaf = lb * QR_THREADS + threadIdx.x;
   const int64_t g = leaf / GL;
   const int sl = threadIdx.x & 15;
   // the group box does not depend on the staged queries: its loads are issued first and
   // are in flight while the query tile is staged
   float lo[PDET_MAX_K], hi[PDET_MAX_K];
-  if (g < ng) load_box(a.gbox[tree], ng, g, a.K, lo, hi);
+  load_box(a.gbox[tree], ng, (uint32_t)std::min(g, ng - 1), K, lo, hi);   // tested if g < ng
   // thresholds and projected queries of the tile: every load issued before any is stored
   constexpr int NST = (QT * (RCAP_MAX + 1) + QR_THREADS - 1) / QR_THREADS;
-  constexpr int NSQ = (QT * PDET_MAX_K + QR_THREADS - 1) / QR_THREADS;
+  constexpr int NSQ = QT * PDET_MAX_K / QR_THREADS;   // rows of PDET_MAX_K, K used
   float stv[NST], sqv[NSQ];
 #pragma unroll
   for (int u = 0; u < NST; ++u) {
@@ -190,12 +210,12 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
     stv[u] = (e < QT * (RCAP_MAX + 1) && slot0 + qi < a.nslots)
                  ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
   }
+  const float* qpt = a.qp + (a.q0 + slot0) * (int64_t)(a.L * K) + tree * K;
 #pragma unroll
   for (int u = 0; u < NSQ; ++u) {
     const int e = threadIdx.x + u * QR_THREADS;
-    const int qi = e / a.K, j = e % a.K;
-    sqv[u] = (e < QT * a.K && slot0 + qi < a.nslots)
-                 ? a.qp[(a.q0 + slot0 + qi) * (int64_t)(a.L * a.K) + tree * a.K + j] : 0.0f;
+    const int qi = e / PDET_MAX_K, j = e % PDET_MAX_K;
+    sqv[u] = (j < K && slot0 + qi < a.nslots) ? qpt[(uint32_t)(qi * a.L * K + j)] : 0.0f;
   }
 #pragma unroll
   for (int u = 0; u < NST; ++u) {
@@ -205,7 +225,7 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
 #pragma unroll
   for (int u = 0; u < NSQ; ++u) {
     const int e = threadIdx.x + u * QR_THREADS;
-    if (e < QT * a.K) sq[e / a.K][e % a.K] = sqv[u];
+    sq[e / PDET_MAX_K][e % PDET_MAX_K] = sqv[u];
   }
   __syncthreads();
   // lane sl of the 16 lanes sharing group g tests that group against query 16*sub + sl
@@ -213,16 +233,16 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
   for (int sub = 0; sub < QT / 16; ++sub) {
     const int qi = sub * 16 + sl;
     bool open = false;
-    if (g < ng && slot0 + qi < a.nslots) open = box_lb2(lo, hi, sq[qi], a.K) <= st[qi][rcap];
+    if (g < ng && slot0 + qi < a.nslots) open = box_lb2(lo, hi, sq[qi], K) <= st[qi][rcap];
     const uint64_t mask = __ballot(open);
     open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
   }
   if (leaf >= nl || open_mask == 0) return;
-  load_box(a.box[tree], nl, leaf, a.K, lo, hi);
+  load_box(a.box[tree], nl, (uint32_t)leaf, K, lo, hi);
   for (uint64_t mq = open_mask; mq; mq &= mq - 1) {
     const int qi = __ffsll((unsigned long long)mq) - 1;   // open only for slots < nslots
     const int slot = slot0 + qi;
-    const float acc = box_lb2(lo, hi, sq[qi], a.K);
+    const float acc = box_lb2(lo, hi, sq[qi], K);
     int c = 0;   // #thresholds < lb2 among rounds 0..rcap: the leaf's first round if <= rcap
 #pragma unroll
     for (int rr = 0; rr <= RCAP_MAX; ++rr) c += (rr <= rcap && st[qi][rr] < acc) ? 1 : 0;
@@ -1117,6 +1137,7 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
     a.ng[i] = (ix.nl[i] + GL - 1) / GL;
   }
   a.nlpad = nlpad;
+  a.lb_per_die = (int)cdiv(cdiv(ix.nl_max, QR_THREADS), NXCD);
   a.Q = qc.Q;
   a.qp = ws.qp.as<float>();
   a.qk = ws.dk.as<int32_t>();
@@ -1165,9 +1186,12 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
       Span sp(s, timed ? &tm.query_rho_ms : nullptr);
       hipLaunchKernelGGL(q_setup, dim3(cdiv(a.nslots, 64)), dim3(64), 0, s, a);
       PDET_HIP(hipGetLastError());
-      hipLaunchKernelGGL(q_rho, dim3(cdiv(((ix.nl_max + GL - 1) / GL) * GL, QR_THREADS), ix.L,
-                                     cdiv(a.nslots, QT)),
-                         dim3(QR_THREADS), 0, s, a);
+      const dim3 rgrid((uint32_t)(NXCD * cdiv(a.nslots, QT)), (uint32_t)a.lb_per_die,
+                       (uint32_t)ix.L);
+      if (ix.K == 16)
+        hipLaunchKernelGGL(q_rho<16>, rgrid, dim3(QR_THREADS), 0, s, a);
+      else
+        hipLaunchKernelGGL(q_rho<0>, rgrid, dim3(QR_THREADS), 0, s, a);
       PDET_HIP(hipGetLastError());
       sp.finish();
     }

@@ -85,25 +85,95 @@ __device__ inline uint32_t first_layer_key(const uint8_t (&c)[KP], int K, int bi
   return key;
 }
 
-__global__ void fl_hist(const uint8_t* codes, int64_t n, int K, int bits, uint32_t* hist) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int tree = blockIdx.y;
-  if (p >= n) return;
-  uint8_t c[KP];
-  load_row(codes, ((int64_t)tree * n + p) * KP, c);
-  atomicAdd(&hist[((int64_t)tree << K) + first_layer_key(c, K, bits)], 1u);
+// First-layer counting sort. A block takes FL_PTS consecutive points of one tree and counts
+// their keys in an LDS hash first, so a key shared by many points of the block (clustered
+// data) costs one global atomic instead of one per point; a key that finds no slot within
+// FL_PROBES probes goes straight to the global counters. Points of a first-layer node come
+// out in no particular order (a node's later splits do not depend on it).
+constexpr int FL_PTS = 4096;
+constexpr int FL_PER_THREAD = FL_PTS / 256;
+constexpr int FL_HASH = 2048;
+constexpr int FL_PROBES = 32;
+constexpr uint32_t FL_EMPTY = 0xffffffffu;
+
+// Slot of `key` in the block's hash (inserted if absent), or -1 if none within FL_PROBES.
+__device__ inline int fl_insert(uint32_t* hk, uint32_t key) {
+  uint32_t sl = mix32(key) & (FL_HASH - 1);
+  for (int pr = 0; pr < FL_PROBES; ++pr) {
+    const uint32_t prev = atomicCAS(&hk[sl], FL_EMPTY, key);
+    if (prev == FL_EMPTY || prev == key) return (int)sl;
+    sl = (sl + 1) & (FL_HASH - 1);
+  }
+  return -1;
 }
 
-__global__ void fl_scatter(const uint8_t* codes, int64_t n, int K, int bits, const uint32_t* off,
-                           uint32_t* cursor, int32_t* perm) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void fl_hist(const uint8_t* codes, int64_t n, int K, int bits,
+                                               uint32_t* hist) {
+  __shared__ uint32_t hk[FL_HASH], hc[FL_HASH];
   const int tree = blockIdx.y;
-  if (p >= n) return;
-  uint8_t c[KP];
-  load_row(codes, ((int64_t)tree * n + p) * KP, c);
-  const int64_t b = ((int64_t)tree << K) + first_layer_key(c, K, bits);
-  const uint32_t pos = off[b] + atomicAdd(&cursor[b], 1u);
-  perm[(int64_t)tree * n + pos] = (int32_t)p;
+  const int64_t p0 = (int64_t)blockIdx.x * FL_PTS;
+  for (int i = threadIdx.x; i < FL_HASH; i += 256) { hk[i] = FL_EMPTY; hc[i] = 0; }
+  __syncthreads();
+  uint32_t* h = hist + ((int64_t)tree << K);
+  for (int u = 0; u < FL_PER_THREAD; ++u) {
+    const int64_t p = p0 + u * 256 + threadIdx.x;
+    if (p < n) {
+      uint8_t c[KP];
+      load_row(codes, ((int64_t)tree * n + p) * KP, c);
+      const uint32_t key = first_layer_key(c, K, bits);
+      const int sl = fl_insert(hk, key);
+      if (sl >= 0) atomicAdd(&hc[sl], 1u);
+      else atomicAdd(&h[key], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < FL_HASH; i += 256)
+    if (hk[i] != FL_EMPTY) atomicAdd(&h[hk[i]], hc[i]);
+}
+
+__global__ __launch_bounds__(256) void fl_scatter(const uint8_t* codes, int64_t n, int K,
+                                                  int bits, const uint32_t* off,
+                                                  uint32_t* cursor, int32_t* perm) {
+  __shared__ uint32_t hk[FL_HASH], hc[FL_HASH], hb[FL_HASH];
+  const int tree = blockIdx.y;
+  const int64_t p0 = (int64_t)blockIdx.x * FL_PTS;
+  for (int i = threadIdx.x; i < FL_HASH; i += 256) { hk[i] = FL_EMPTY; hc[i] = 0; }
+  __syncthreads();
+  const uint32_t* o = off + ((int64_t)tree << K);
+  uint32_t* cur = cursor + ((int64_t)tree << K);
+  int32_t* pm = perm + (int64_t)tree * n;
+  uint32_t key[FL_PER_THREAD];
+  int slot[FL_PER_THREAD];
+  // count per slot (keys without a slot take their position from the global cursor now)
+#pragma unroll
+  for (int u = 0; u < FL_PER_THREAD; ++u) {
+    const int64_t p = p0 + u * 256 + threadIdx.x;
+    slot[u] = -2;
+    if (p < n) {
+      uint8_t c[KP];
+      load_row(codes, ((int64_t)tree * n + p) * KP, c);
+      key[u] = first_layer_key(c, K, bits);
+      slot[u] = fl_insert(hk, key[u]);
+      if (slot[u] >= 0) atomicAdd(&hc[slot[u]], 1u);
+      else pm[o[key[u]] + atomicAdd(&cur[key[u]], 1u)] = (int32_t)p;
+    }
+  }
+  __syncthreads();
+  // one reservation per key of the block
+  for (int i = threadIdx.x; i < FL_HASH; i += 256) {
+    if (hk[i] != FL_EMPTY) {
+      hb[i] = o[hk[i]] + atomicAdd(&cur[hk[i]], hc[i]);
+      hc[i] = 0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < FL_PER_THREAD; ++u) {
+    if (slot[u] >= 0) {
+      const int64_t p = p0 + u * 256 + threadIdx.x;
+      pm[hb[slot[u]] + atomicAdd(&hc[slot[u]], 1u)] = (int32_t)p;
+    }
+  }
 }
 
 __global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, int K, int bits,
@@ -532,11 +602,11 @@ void build_trees(Index& ix, hipStream_t s) {
   const uint8_t* codes = ix.codes.as<uint8_t>();
   int32_t* perm = ix.perm.as<int32_t>();
 
-  hipLaunchKernelGGL(fl_hist, dim3(cdiv(n, 256), L), dim3(256), 0, s, codes, n, K, bits,
+  hipLaunchKernelGGL(fl_hist, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, codes, n, K, bits,
                      hist.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   scan_rows(hist.as<uint32_t>(), off.as<uint32_t>(), nullptr, L, NK, scan_tmp, s);
-  hipLaunchKernelGGL(fl_scatter, dim3(cdiv(n, 256), L), dim3(256), 0, s, codes, n, K, bits,
+  hipLaunchKernelGGL(fl_scatter, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, codes, n, K, bits,
                      off.as<uint32_t>(), cursor.as<uint32_t>(), perm);
   PDET_HIP(hipGetLastError());
 
