@@ -124,11 +124,14 @@ typedef struct {
  * Answer nq queries (device float32 [nq][d]).
  * Outputs (device, caller-owned) are laid out CSR in query order: query q owns
  * entries [off_q, off_q + k_q) with off_q = sum of k over earlier queries.
- *   ids    int64: neighbour ids sorted by (distance, id) ascending.
+ *   ids    int64: neighbour ids sorted by (distance, id) ascending, the distance taken
+ *          as the FP64 squared distance (the same order up to ties of the root).
  *   dists  float32: Euclidean distances (not squared) of those neighbours.
  *   qstats int32 [nq][PDET_QSTAT_WORDS] or NULL.
  * Errors: EINVAL for k < 1, k > n, c <= 1, beta < 0, r_min <= 0 on an untuned index, a low-precision form
- * whose copy the index lacks, rescore < 1; EUNSUPPORTED for k*rescore > PDET_MAX_TOPK.
+ * whose copy the index lacks, rescore < 1; EUNSUPPORTED for k*rescore > PDET_MAX_TOPK, or
+ * for d and k*rescore together too large for the query workgroup's LDS
+ * (12*d + 12*pow2(k*rescore + 384) bytes above 48 KiB).
  * A query whose radius ladder runs out before a stop rule fires gets stop = -1.
  * Concurrent calls on one index are allowed on different streams (the index is
  * read-only after build).

@@ -73,7 +73,7 @@ struct QArgs {
   const int64_t* qoff;
   const double* qc;
   const float* t2;           // [slots][NRHO]
-  const double* crr;         // [slots][NRHO]
+  const double* crr;         // [slots][NRHO]: (c*r)^2, compared with squared distances
   uint8_t* rho;              // [slots][L][nlpad] dense round table (0xff: not admitted)
   uint32_t* lcnt;            // [slots][PDET_MAX_L] leaf-list lengths
   const int32_t* leafrow;    // [L][n][L]
@@ -106,7 +106,7 @@ __global__ void q_setup(QArgs a) {
     const double t = a.eps * r;
     const double tt = t * t;
     t2[rho] = (float)tt;
-    crr[rho] = c * r;
+    crr[rho] = (c * r) * (c * r);
     r = c * r;
   }
   t2[NRHO - 1] = INFINITY;
@@ -267,21 +267,24 @@ constexpr int NCH32 = 2;
 constexpr int NCHLP = 4;
 constexpr int NR32 = 1;          // float32 candidate rows per lane group per trip
 
-// Euclidean distances of NR candidates `id[r]` to the query, computed by a group of `lpc`
-// lanes (a power of two; every lane of the group must call it; rows with valid[r] false
-// are not read). Each lane issues all its 16-byte loads of the NR rows (up to NCH per row)
-// before using them. PREC 0: float32 data, FP64 accumulation; 1: bf16 copy; 2: fp8 e4m3
-// copy with a per-row scale (FP32 accumulation).
+// Squared Euclidean distances of NR candidates `id[r]` to the query, computed by a group of
+// `lpc` lanes (a power of two; every lane of the group must call it; rows with valid[r]
+// false are not read). Each lane issues all its 16-byte loads of the NR rows (up to NCH per
+// row) before using them. PREC 0: float32 data against the query held in FP64 (qd), FP64
+// accumulation; 1: bf16 copy; 2: fp8 e4m3 copy with a per-row scale (both against the
+// float32 query qv, FP32 accumulation). Candidates are ranked by squared distance (the
+// square root is monotone) and the root is taken once, for the returned k.
 template <int PREC, int NR>
 __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const bool (&valid)[NR],
-                                 const float* qv, int lg, int lpc, double (&out)[NR]) {
+                                 const float* qv, const double* qd, int lg, int lpc,
+                                 double (&out)[NR]) {
   double accd[NR];
   float accf[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) { accd[r] = 0.0; accf[r] = 0.0f; }
   if constexpr (PREC == PDET_FP32) {
     if ((a.d & 3) == 0) {
-      const float4* q4 = reinterpret_cast<const float4*>(qv);
+      const double2* q2 = reinterpret_cast<const double2*>(qd);
       const int n4 = a.d >> 2;
       constexpr int NCH = NCH32;
       for (int base = 0; base < n4; base += NCH * lpc) {
@@ -301,9 +304,10 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
           for (int u = 0; u < NCH; ++u) {
             const int c = base + lg + u * lpc;
             if (valid[r] && c < n4) {
-              const float4 x = buf[r][u], q = q4[c];
-              const double d0 = (double)x.x - (double)q.x, d1 = (double)x.y - (double)q.y;
-              const double d2 = (double)x.z - (double)q.z, d3 = (double)x.w - (double)q.w;
+              const float4 x = buf[r][u];
+              const double2 qa = q2[2 * c], qb = q2[2 * c + 1];
+              const double d0 = (double)x.x - qa.x, d1 = (double)x.y - qa.y;
+              const double d2 = (double)x.z - qb.x, d3 = (double)x.w - qb.y;
               accd[r] = fma(d0, d0, accd[r]); accd[r] = fma(d1, d1, accd[r]);
               accd[r] = fma(d2, d2, accd[r]); accd[r] = fma(d3, d3, accd[r]);
             }
@@ -316,7 +320,7 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
         if (!valid[r]) continue;
         const float* xr = a.X + (int64_t)id[r] * a.d;
         for (int t = lg; t < a.d; t += lpc) {
-          const double df = (double)xr[t] - (double)qv[t];
+          const double df = (double)xr[t] - qd[t];
           accd[r] = fma(df, df, accd[r]);
         }
       }
@@ -377,10 +381,7 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
     for (int r = 0; r < NR; ++r) accd[r] = (double)accf[r];
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    accd[r] = group_sum(accd[r], lpc);
-    out[r] = sqrt(accd[r]);
-  }
+  for (int r = 0; r < NR; ++r) out[r] = group_sum(accd[r], lpc);
 }
 
 // Bitonic sort of (distance, id) pairs, ascending, over `len` (a power of two) entries.
@@ -437,10 +438,11 @@ __device__ inline bool is_new(const QArgs& a, bool dense, const uint8_t* rr, con
 template <int PREC>
 __device__ __forceinline__ void q_main_body(const QArgs& a) {
   extern __shared__ __align__(16) unsigned char sm[];
-  double* ld = reinterpret_cast<double*>(sm);
+  double* ld = reinterpret_cast<double*>(sm);     // squared distances of the top-k buffer
   int32_t* li = reinterpret_cast<int32_t*>(ld + a.NM);
-  float* qv = reinterpret_cast<float*>(li + a.NM);
   const int dq = (PREC == PDET_FP32) ? ((a.d + 3) & ~3) : a.dpad;
+  double* qd = reinterpret_cast<double*>(li + a.NM);   // NM is a multiple of 4: 16-byte aligned
+  float* qv = reinterpret_cast<float*>(qd + dq);
   float* qps = qv + dq;
 
   // the walk's window (traverse) and the select scratch (select_key) are never live at once
@@ -479,7 +481,11 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   const int LK = a.L * a.K;
 
   for (int e = tid; e < a.NM; e += QM) { ld[e] = INFINITY; li[e] = INT32_MAX; }
-  for (int t = tid; t < dq; t += QM) qv[t] = (t < a.d) ? a.Q[q * a.d + t] : 0.0f;
+  for (int t = tid; t < dq; t += QM) {
+    const float v = (t < a.d) ? a.Q[q * a.d + t] : 0.0f;
+    qv[t] = v;
+    qd[t] = (double)v;
+  }
   for (int t = tid; t < LK; t += QM) qps[t] = a.qp[q * LK + t];
   for (int t = tid; t < NRHO; t += QM) st2[t] = a.t2[(int64_t)slot * NRHO + t];
   uint8_t* rq = a.rho + (int64_t)slot * a.L * a.nlpad;
@@ -615,7 +621,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
             valid[r] = c < nb;
             cid[r] = valid[r] ? idbuf[c] : 0;
           }
-          cand_dist<PREC, NRV>(a, cid, valid, qv, lg, lpc, dd);
+          cand_dist<PREC, NRV>(a, cid, valid, qv, qd, lg, lpc, dd);
 #pragma unroll
           for (int r = 0; r < NRV; ++r) {
             if (valid[r] && lg == 0 && lex_less(dd[r], cid[r], ld[KL - 1], li[KL - 1])) {
@@ -935,7 +941,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     }
     if (nS >= k) {
       // stop rule B: the k-th smallest distance of the kept list and the pending buffer is
-      // <= c*r iff at least k of them are
+      // <= c*r iff at least k of them are (compared squared, with (c*r)^2)
       const double crr = a.crr[(int64_t)slot * NRHO + rho];
       const uint32_t tot = (uint32_t)KL + uni(s_ncb);
       uint32_t cnt = 0;
@@ -974,7 +980,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
         valid[r] = t < KL && li[t] != INT32_MAX;
         id[r] = valid[r] ? li[t] : 0;
       }
-      cand_dist<PDET_FP32, 2>(a, id, valid, qv, lg32, lpc32, dd);
+      cand_dist<PDET_FP32, 2>(a, id, valid, qv, qd, lg32, lpc32, dd);
 #pragma unroll
       for (int r = 0; r < 2; ++r)
         if (valid[r] && lg32 == 0) ld[t0 + r * G32 + grp32] = dd[r];
@@ -990,7 +996,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   const int64_t off = a.qoff[q];
   for (int t = tid; t < k; t += QM) {
     a.ids[off + t] = (li[t] == INT32_MAX) ? -1 : (int64_t)li[t];
-    a.dists[off + t] = (float)ld[t];
+    a.dists[off + t] = (float)sqrt(ld[t]);
   }
   atomicAdd(&s_hsum, hsum);
   atomicAdd(&s_hmix, hmix);
@@ -1177,7 +1183,10 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   while (NM < maxKL + CBMIN) NM <<= 1;
   a.NM = NM;
   const int dq = (qc.precision == PDET_FP32) ? ((ix.d + 3) & ~3) : ix.dpad;
-  const size_t smem = (size_t)NM * 12 + (size_t)dq * 4 + (size_t)LK * 4;
+  const size_t smem = (size_t)NM * 12 + (size_t)dq * 12 + (size_t)LK * 4;
+  // with the kernel's static LDS (under 16 KiB) a workgroup stays within 64 KiB
+  PDET_REQUIRE(smem <= 48 * 1024, PDET_EUNSUPPORTED,
+               "d and k * rescore too large for the query workgroup's LDS");
 
   for (int64_t q0 = 0; q0 < nq; q0 += nslots) {
     a.q0 = q0;
