@@ -51,8 +51,8 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* t
 template <int CTRL>
 __device__ inline double dpp_double(double x) {
   const uint64_t u = __builtin_bit_cast(uint64_t, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
@@ -67,6 +67,18 @@ __device__ inline double group_sum(double x, int width) {
   if (width > 8) x += dpp_double<0x140>(x);   // row_mirror
   if (width > 16) x += __shfl_xor(x, 16);
   if (width > 32) x += __shfl_xor(x, 32);
+  return x;
+}
+
+// The same sum for a width fixed at compile time (no per-level tests).
+template <int W>
+__device__ inline double group_sum(double x) {
+  if constexpr (W > 1) x += dpp_double<0xB1>(x);
+  if constexpr (W > 2) x += dpp_double<0x4E>(x);
+  if constexpr (W > 4) x += dpp_double<0x141>(x);
+  if constexpr (W > 8) x += dpp_double<0x140>(x);
+  if constexpr (W > 16) x += __shfl_xor(x, 16);
+  if constexpr (W > 32) x += __shfl_xor(x, 32);
   return x;
 }
 

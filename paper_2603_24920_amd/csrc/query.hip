@@ -23,6 +23,8 @@
 //           trees before it are admitted whole. New points are verified by exact distance
 //           and offered to a top-k list in LDS; stop rule B checks the k-th distance
 //           against c*r after each round.
+#include <type_traits>
+
 #include "devutil.h"
 #include "internal.h"
 
@@ -269,15 +271,16 @@ constexpr int NR32 = 1;          // float32 candidate rows per lane group per tr
 
 // Squared Euclidean distances of NR candidates `id[r]` to the query, computed by a group of
 // `lpc` lanes (a power of two; every lane of the group must call it; rows with valid[r]
-// false are not read). Each lane issues all its 16-byte loads of the NR rows (up to NCH per
+// false are not read; LPC > 0 fixes lpc at compile time). Each lane issues all its 16-byte loads of the NR rows (up to NCH per
 // row) before using them. PREC 0: float32 data against the query held in FP64 (qd), FP64
 // accumulation; 1: bf16 copy; 2: fp8 e4m3 copy with a per-row scale (both against the
 // float32 query qv, FP32 accumulation). Candidates are ranked by squared distance (the
 // square root is monotone) and the root is taken once, for the returned k.
-template <int PREC, int NR>
+template <int PREC, int NR, int LPC = 0>
 __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const bool (&valid)[NR],
-                                 const float* qv, const double* qd, int lg, int lpc,
+                                 const float* qv, const double* qd, int lg, int lpc_rt,
                                  double (&out)[NR]) {
+  const int lpc = LPC ? LPC : lpc_rt;
   double accd[NR];
   float accf[NR];
 #pragma unroll
@@ -381,7 +384,10 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
     for (int r = 0; r < NR; ++r) accd[r] = (double)accf[r];
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) out[r] = group_sum(accd[r], lpc);
+  for (int r = 0; r < NR; ++r) {
+    if constexpr (LPC > 0) out[r] = group_sum<LPC>(accd[r]);
+    else out[r] = group_sum(accd[r], lpc);
+  }
 }
 
 // Bitonic sort of (distance, id) pairs, ascending, over `len` (a power of two) entries.
@@ -610,25 +616,41 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
       }
       if (mode != WALK_COUNT) {
         constexpr int NRV = (PREC == PDET_FP32) ? NR32 : 1;
-        const uint32_t G = QM / lpc;   // lane groups: candidates per row of a trip
-        for (uint32_t c0 = 0; c0 < nb; c0 += NRV * G) {
-          int32_t cid[NRV];
-          bool valid[NRV];
-          double dd[NRV];
+        // the low-precision forms take one instance of the loop per lane-group width, so the
+        // reduction has no tests (for float32 the extra instances cost more in spills)
+        auto dist_rows = [&](auto lpc_c) {
+          constexpr int LPC = decltype(lpc_c)::value;   // 0: the runtime width
+          const uint32_t G = QM / (LPC ? LPC : lpc);   // lane groups: candidates per row
+          for (uint32_t c0 = 0; c0 < nb; c0 += NRV * G) {
+            int32_t cid[NRV];
+            bool valid[NRV];
+            double dd[NRV];
 #pragma unroll
-          for (int r = 0; r < NRV; ++r) {
-            const uint32_t c = c0 + r * G + grp;
-            valid[r] = c < nb;
-            cid[r] = valid[r] ? idbuf[c] : 0;
-          }
-          cand_dist<PREC, NRV>(a, cid, valid, qv, qd, lg, lpc, dd);
-#pragma unroll
-          for (int r = 0; r < NRV; ++r) {
-            if (valid[r] && lg == 0 && lex_less(dd[r], cid[r], ld[KL - 1], li[KL - 1])) {
-              const uint32_t pos = atomicAdd(&s_ncb, 1u);
-              ld[KL + pos] = dd[r];
-              li[KL + pos] = cid[r];
+            for (int r = 0; r < NRV; ++r) {
+              const uint32_t c = c0 + r * G + grp;
+              valid[r] = c < nb;
+              cid[r] = valid[r] ? idbuf[c] : 0;
             }
+            cand_dist<PREC, NRV, LPC>(a, cid, valid, qv, qd, lg, lpc, dd);
+#pragma unroll
+            for (int r = 0; r < NRV; ++r) {
+              if (valid[r] && lg == 0 && lex_less(dd[r], cid[r], ld[KL - 1], li[KL - 1])) {
+                const uint32_t pos = atomicAdd(&s_ncb, 1u);
+                ld[KL + pos] = dd[r];
+                li[KL + pos] = cid[r];
+              }
+            }
+          }
+        };
+        if constexpr (PREC == PDET_FP32) {
+          dist_rows(std::integral_constant<int, 0>{});
+        } else {
+          switch (lpc) {   // lanes_for gives a power of two in [4, 64]
+            case 4: dist_rows(std::integral_constant<int, 4>{}); break;
+            case 8: dist_rows(std::integral_constant<int, 8>{}); break;
+            case 16: dist_rows(std::integral_constant<int, 16>{}); break;
+            case 32: dist_rows(std::integral_constant<int, 32>{}); break;
+            default: dist_rows(std::integral_constant<int, 64>{}); break;
           }
         }
       }
