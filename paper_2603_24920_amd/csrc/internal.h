@@ -16,6 +16,11 @@ struct QueryWorkspace {
   DevBuf rho, admb, adm2, t2, crr, lcnt, qp, dk, dc, dT, doff;
   PinnedBuf h_k, h_c, h_T, h_off;   // staging of the per-query parameters
   int64_t nslots = 0, nslots_max = 0, nq_cap = 0;
+  // a batch whose queries share k and c passes them as scalars (no per-query upload)
+  bool uniform = false;
+  int32_t uk = 0;
+  int64_t uT = 0;
+  double uc = 0.0;
   size_t bytes() const {
     return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes + lcnt.bytes;
   }

@@ -70,10 +70,14 @@ struct QArgs {
   int lb_per_die;            // q_rho leaf blocks (256 leaves) of a tree that each die takes
   const float* Q;
   const float* qp;           // [nq][L*K]
-  const int32_t* qk;
+  const int32_t* qk;         // per-query k, T, offsets and c
   const int64_t* qT;
   const int64_t* qoff;
   const double* qc;
+  int32_t uk;                // uniform: the batch shares k and c, and q_setup writes the
+  int64_t uT;                // per-query arrays of its slots from these (no upload)
+  double uc;
+  int uniform;
   const float* t2;           // [slots][NRHO]
   const double* crr;         // [slots][NRHO]: (c*r)^2, compared with squared distances
   uint8_t* rho;              // [slots][L][nlpad] dense round table (0xff: not admitted)
@@ -100,7 +104,14 @@ struct QArgs {
 __global__ void q_setup(QArgs a) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= a.nslots) return;
-  const double c = a.qc[a.q0 + slot];
+  const int64_t q = a.q0 + slot;
+  if (a.uniform) {
+    const_cast<int32_t*>(a.qk)[q] = a.uk;
+    const_cast<int64_t*>(a.qT)[q] = a.uT;
+    const_cast<int64_t*>(a.qoff)[q] = q * (int64_t)a.uk;
+    const_cast<double*>(a.qc)[q] = a.uc;
+  }
+  const double c = a.uniform ? a.uc : a.qc[q];
   float* t2 = const_cast<float*>(a.t2) + (int64_t)slot * NRHO;
   double* crr = const_cast<double*>(a.crr) + (int64_t)slot * NRHO;
   double r = a.r_min;
@@ -1051,14 +1062,22 @@ __global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(6))) void q_
 int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws) {
   int maxKL = 1;
   int64_t acc = 0;
+  bool uniform = qc.nq > 0;
   for (int64_t q = 0; q < qc.nq; ++q) {
     const int k = qc.k_host[q];
+    uniform = uniform && k == qc.k_host[0] && qc.c_host[q] == qc.c_host[0];
     ws.h_k.as<int32_t>()[q] = k;
     ws.h_c.as<double>()[q] = qc.c_host[q];
     ws.h_T.as<int64_t>()[q] = (int64_t)std::ceil(qc.beta * (double)ix.n) + k;
     ws.h_off.as<int64_t>()[q] = acc;
     acc += k;
     maxKL = std::max(maxKL, qc.precision == PDET_FP32 ? k : k * qc.rescore);
+  }
+  ws.uniform = uniform;
+  if (uniform) {
+    ws.uk = qc.k_host[0];
+    ws.uc = qc.c_host[0];
+    ws.uT = ws.h_T.as<int64_t>()[0];
   }
   return maxKL;
 }
@@ -1128,10 +1147,12 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
   const int64_t admcap = std::max<int64_t>(nl_total, 1);
   const int64_t nslots = ws.nslots;
-  PDET_HIP(hipMemcpyAsync(ws.dk.p, ws.h_k.p, nq * 4, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(ws.dc.p, ws.h_c.p, nq * 8, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(ws.dT.p, ws.h_T.p, nq * 8, hipMemcpyHostToDevice, s));
-  PDET_HIP(hipMemcpyAsync(ws.doff.p, ws.h_off.p, nq * 8, hipMemcpyHostToDevice, s));
+  if (!ws.uniform) {
+    PDET_HIP(hipMemcpyAsync(ws.dk.p, ws.h_k.p, nq * 4, hipMemcpyHostToDevice, s));
+    PDET_HIP(hipMemcpyAsync(ws.dc.p, ws.h_c.p, nq * 8, hipMemcpyHostToDevice, s));
+    PDET_HIP(hipMemcpyAsync(ws.dT.p, ws.h_T.p, nq * 8, hipMemcpyHostToDevice, s));
+    PDET_HIP(hipMemcpyAsync(ws.doff.p, ws.h_off.p, nq * 8, hipMemcpyHostToDevice, s));
+  }
 
   pdet_timing scratch_tm{};
   pdet_timing& tm = timed ? timer().t : scratch_tm;
@@ -1172,6 +1193,10 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   a.qT = ws.dT.as<int64_t>();
   a.qoff = ws.doff.as<int64_t>();
   a.qc = ws.dc.as<double>();
+  a.uniform = ws.uniform ? 1 : 0;
+  a.uk = ws.uk;
+  a.uT = ws.uT;
+  a.uc = ws.uc;
   a.t2 = ws.t2.as<float>();
   a.crr = ws.crr.as<double>();
   a.rho = ws.rho.as<uint8_t>();

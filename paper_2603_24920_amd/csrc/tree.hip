@@ -568,6 +568,17 @@ class ScratchPool {
   size_t held_ = 0;
 };
 
+// A small pinned host area per thread for counter readbacks (kept until the thread ends).
+uint32_t* readback_words() {
+  struct Words {
+    uint32_t* p = nullptr;
+    ~Words() { if (p) (void)hipHostFree(p); }
+  };
+  static thread_local Words w;
+  if (!w.p) PDET_HIP(hipHostMalloc((void**)&w.p, 64 * sizeof(uint32_t), hipHostMallocDefault));
+  return w.p;
+}
+
 ScratchPool& scratch_pool() {
   static ScratchPool* p = new ScratchPool();   // lives until the process ends
   return *p;
@@ -595,6 +606,8 @@ void build_trees(Index& ix, hipStream_t s) {
   const int L = ix.L, K = ix.K, bits = ix.bits;
   const int64_t NK = 1ll << K;
 
+  // allocated first, while the encoder still runs: its size does not depend on the trees
+  ix.leafrow.alloc((size_t)L * n * L * 4);
   PooledBuf hist((size_t)L * NK * 4), off((size_t)L * NK * 4), cursor((size_t)L * NK * 4);
   DevBuf scan_tmp;
   PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
@@ -696,8 +709,25 @@ void build_trees(Index& ix, hipStream_t s) {
   PDET_HIP(hipGetLastError());
   scan_rows(flags.as<uint32_t>(), flags.as<uint32_t>(), totals.as<uint32_t>(), L, n, scan_tmp, s);
   std::vector<uint32_t> nl(L);
-  PDET_HIP(hipMemcpyAsync(nl.data(), totals.ptr(), L * 4, hipMemcpyDeviceToHost, s));
-  PDET_HIP(hipStreamSynchronize(s));
+  // per-point leaf ordinals and the leaf-row table need only the scan: they run while the
+  // host reads the leaf counts back (into pinned memory, so the copy does not wait for
+  // them) and sizes the leaf tables
+  uint32_t* hp = readback_words();
+  PDET_HIP(hipMemcpyAsync(hp, totals.ptr(), L * 4, hipMemcpyDeviceToHost, s));
+  hipEvent_t counts_ready;
+  PDET_HIP(hipEventCreateWithFlags(&counts_ready, hipEventDisableTiming));
+  PDET_HIP(hipEventRecord(counts_ready, s));
+  PooledBuf leaf_of((size_t)n * L * 4);
+  hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
+                     flags.as<uint32_t>(), perm, n, L, leaf_of.as<int32_t>());
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(leafrow_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, perm,
+                     leaf_of.as<int32_t>(), n, L, ix.leafrow.as<int32_t>());
+  PDET_HIP(hipGetLastError());
+  const hipError_t ce = hipEventSynchronize(counts_ready);
+  (void)hipEventDestroy(counts_ready);
+  PDET_HIP(ce);
+  for (int i = 0; i < L; ++i) nl[i] = hp[i];
   LeafTables t{};
   ix.nl_max = 0;
   // every tree's leaf tables and group boxes in one allocation (256-byte aligned parts)
@@ -743,14 +773,6 @@ void build_trees(Index& ix, hipStream_t s) {
     hipLaunchKernelGGL(group_boxes, dim3(cdiv(nl_pad, 256), L), dim3(256), 0, s, ga);
     PDET_HIP(hipGetLastError());
   }
-  PooledBuf leaf_of((size_t)n * L * 4);
-  hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
-                     flags.as<uint32_t>(), perm, n, L, leaf_of.as<int32_t>());
-  PDET_HIP(hipGetLastError());
-  ix.leafrow.alloc((size_t)L * n * L * 4);
-  hipLaunchKernelGGL(leafrow_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, perm,
-                     leaf_of.as<int32_t>(), n, L, ix.leafrow.as<int32_t>());
-  PDET_HIP(hipGetLastError());
   PDET_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
 }
 
