@@ -40,18 +40,32 @@ __global__ __launch_bounds__(SORT_THREADS) void bitonic_tile_sort(float* keys, i
   for (int e = threadIdx.x; e < tile; e += blockDim.x) keys[base + e] = sk[e];
 }
 
-// One compare-exchange step with stride j >= tile of stage k.
-__global__ void bitonic_global_step(float* keys, int64_t npad, int64_t k, int64_t j,
-                                    int64_t pairs_total) {
+// S consecutive steps j = J, J/2, .., J/2^(S-1) (all >= tile) of stage k in one pass: a
+// thread holds the 2^S keys whose indices differ only in those S bits, applies the S
+// compare-exchange levels in registers (largest stride first, as the network does), and
+// writes them back. All of a group's keys share bit k, hence one direction.
+template <int S>
+__global__ void bitonic_global_steps(float* keys, int64_t npad, int64_t k, int p0,
+                                     int64_t groups_total) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= pairs_total) return;
-  const int64_t half = npad / 2;
-  const int64_t col = g / half, t = g % half;
-  const int64_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+  if (g >= groups_total) return;
+  const int64_t per_col = npad >> S;
+  const int64_t col = g / per_col, t = g % per_col;
+  const int64_t base = ((t >> p0) << (p0 + S)) | (t & ((int64_t(1) << p0) - 1));
   float* c = keys + col * npad;
-  float a = c[i], b = c[i | j];
-  const bool asc = ((i & k) == 0);
-  if ((a > b) == asc) { c[i] = b; c[i | j] = a; }
+  constexpr int G = 1 << S;
+  float x[G];
+#pragma unroll
+  for (int a = 0; a < G; ++a) x[a] = c[base + ((int64_t)a << p0)];
+  const bool asc = ((base & k) == 0);
+#pragma unroll
+  for (int l = S - 1; l >= 0; --l) {
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+      if (!(a & (1 << l))) cas(x[a], x[a | (1 << l)], asc);
+  }
+#pragma unroll
+  for (int a = 0; a < G; ++a) c[base + ((int64_t)a << p0)] = x[a];
 }
 
 // Steps j = tile/2 .. 1 of stage k > tile inside each tile.
@@ -188,12 +202,25 @@ void sort_columns(float* keys, int ncols, int64_t npad, hipStream_t s) {
   hipLaunchKernelGGL(bitonic_tile_sort, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s, keys,
                      npad, tile);
   PDET_HIP(hipGetLastError());
-  const int64_t pairs = (int64_t)ncols * (npad / 2);
   for (int64_t k = 2 * (int64_t)tile; k <= npad; k <<= 1) {
-    for (int64_t j = k >> 1; j >= tile; j >>= 1) {
-      hipLaunchKernelGGL(bitonic_global_step, dim3(cdiv(pairs, 256)), dim3(256), 0, s, keys, npad,
-                         k, j, pairs);
+    // the steps j = k/2 .. tile, up to four per pass
+    int hi = 0;
+    while ((int64_t(1) << (hi + 1)) <= (k >> 1)) ++hi;   // log2(k/2)
+    int lo = 0;
+    while ((int64_t(1) << (lo + 1)) <= tile) ++lo;        // log2(tile)
+    while (hi >= lo) {
+      const int S = std::min(4, hi - lo + 1);
+      const int p0 = hi - S + 1;
+      const int64_t groups = (int64_t)ncols * (npad >> S);
+      const dim3 gr(cdiv(groups, 256));
+      switch (S) {
+        case 1: hipLaunchKernelGGL(bitonic_global_steps<1>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
+        case 2: hipLaunchKernelGGL(bitonic_global_steps<2>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
+        case 3: hipLaunchKernelGGL(bitonic_global_steps<3>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
+        default: hipLaunchKernelGGL(bitonic_global_steps<4>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
+      }
       PDET_HIP(hipGetLastError());
+      hi -= S;
     }
     hipLaunchKernelGGL(bitonic_tile_merge, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s, keys,
                        npad, tile, k);
