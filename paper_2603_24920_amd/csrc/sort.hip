@@ -40,6 +40,72 @@ __global__ __launch_bounds__(SORT_THREADS) void bitonic_tile_sort(float* keys, i
   for (int e = threadIdx.x; e < tile; e += blockDim.x) keys[base + e] = sk[e];
 }
 
+// Full tiles (TILE keys) run the same network with each of TILE_T threads holding KPT
+// consecutive keys: steps with stride j < KPT stay in registers, strides up to a wave's
+// 64*KPT keys go through lane shuffles, and only the larger ones through LDS (laid out
+// key-major so that consecutive threads hit consecutive banks).
+constexpr int KPT = 16;
+constexpr int TILE_T = TILE / KPT;   // 256 threads
+
+__device__ inline void tile_step(float (&x)[KPT], int t, int64_t gidx0, int64_t k, int j,
+                                 float* sk) {
+  if (j < KPT) {
+#pragma unroll
+    for (int e = 0; e < KPT; ++e)
+      if (!(e & j)) cas(x[e], x[e | j], ((gidx0 + e) & k) == 0);
+  } else if (j < 64 * KPT) {
+    const int m = j / KPT;                       // partner lane: t ^ m, same wave
+    const bool lower = (t & m) == 0;
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) {
+      const float y = __shfl_xor(x[e], m);
+      const bool asc = ((gidx0 + e) & k) == 0;
+      x[e] = (lower == asc) ? fminf(x[e], y) : fmaxf(x[e], y);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) sk[e * TILE_T + t] = x[e];
+    __syncthreads();
+    const int tp = t ^ (j / KPT);
+    const bool lower = (t & (j / KPT)) == 0;
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) {
+      const float y = sk[e * TILE_T + tp];
+      const bool asc = ((gidx0 + e) & k) == 0;
+      x[e] = (lower == asc) ? fminf(x[e], y) : fmaxf(x[e], y);
+    }
+    __syncthreads();
+  }
+}
+
+// MERGE false: stages k = 2..TILE of each tile; true: steps j = TILE/2..1 of stage `kst`.
+template <bool MERGE>
+__global__ __launch_bounds__(TILE_T) void bitonic_tile_reg(float* keys, int64_t npad,
+                                                           int64_t kst) {
+  __shared__ float sk[TILE];
+  const int64_t tiles_per_col = npad / TILE;
+  const int64_t col = blockIdx.x / tiles_per_col;
+  const int64_t gbase = (blockIdx.x % tiles_per_col) * TILE;
+  const int t = threadIdx.x;
+  float4* src = reinterpret_cast<float4*>(keys + col * npad + gbase + (int64_t)t * KPT);
+  float x[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT / 4; ++q) {
+    const float4 v = src[q];
+    x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+  }
+  const int64_t gidx0 = gbase + (int64_t)t * KPT;   // index inside the column of x[0]
+  if constexpr (MERGE) {
+    for (int j = TILE >> 1; j > 0; j >>= 1) tile_step(x, t, gidx0, kst, j, sk);
+  } else {
+    for (int k = 2; k <= TILE; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) tile_step(x, t, gidx0, k, j, sk);
+  }
+#pragma unroll
+  for (int q = 0; q < KPT / 4; ++q)
+    src[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+}
+
 // S consecutive steps j = J, J/2, .., J/2^(S-1) (all >= tile) of stage k in one pass: a
 // thread holds the 2^S keys whose indices differ only in those S bits, applies the S
 // compare-exchange levels in registers (largest stride first, as the network does), and
@@ -199,8 +265,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply(const uint32_t* in, u
 void sort_columns(float* keys, int ncols, int64_t npad, hipStream_t s) {
   const int tile = (int)std::min<int64_t>(npad, TILE);
   const int64_t tiles = ncols * (npad / tile);
-  hipLaunchKernelGGL(bitonic_tile_sort, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s, keys,
-                     npad, tile);
+  const bool full = tile == TILE;   // register / shuffle form for full tiles
+  if (full)
+    hipLaunchKernelGGL(bitonic_tile_reg<false>, dim3((unsigned)tiles), dim3(TILE_T), 0, s, keys,
+                       npad, (int64_t)0);
+  else
+    hipLaunchKernelGGL(bitonic_tile_sort, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s, keys,
+                       npad, tile);
   PDET_HIP(hipGetLastError());
   for (int64_t k = 2 * (int64_t)tile; k <= npad; k <<= 1) {
     // the steps j = k/2 .. tile, up to four per pass
@@ -222,8 +293,12 @@ void sort_columns(float* keys, int ncols, int64_t npad, hipStream_t s) {
       PDET_HIP(hipGetLastError());
       hi -= S;
     }
-    hipLaunchKernelGGL(bitonic_tile_merge, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s, keys,
-                       npad, tile, k);
+    if (full)
+      hipLaunchKernelGGL(bitonic_tile_reg<true>, dim3((unsigned)tiles), dim3(TILE_T), 0, s, keys,
+                         npad, k);
+    else
+      hipLaunchKernelGGL(bitonic_tile_merge, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s,
+                         keys, npad, tile, k);
     PDET_HIP(hipGetLastError());
   }
 }
