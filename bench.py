@@ -35,6 +35,8 @@ METRIC = "index build Mpts/s + QPS at recall@10>=0.9 (FP32 vs BF16/FP8 verify), 
 HBM_PEAK_GBS = 8000.0
 BETA_LADDER = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 5e-4, 2e-4, 1e-4, 5e-5, 2e-5, 1e-5)
 PROFILE_PMC = os.path.join(ROOT, "profiles", "q_main_traffic.json")
+BIG_N = 20_000_000            # above this: threaded generation, brute-force ground truth
+MAX_CAL_CANDIDATES = 2e5      # largest beta * n tried by the recall calibration
 
 
 def log(*a):
@@ -44,6 +46,25 @@ def log(*a):
 def recall_at(ids, exact, r=10):
     ids, exact = np.asarray(ids)[:, :r], np.asarray(exact)[:, :r]
     return float(np.mean([len(np.intersect1d(a, b)) / r for a, b in zip(ids, exact)]))
+
+
+def brute_force_knn(Xd, Qd, k, rows=1 << 18):
+    """Exact k nearest neighbours by FP64 distances over row chunks of the resident data
+    (torch matrix products; evaluation only, for sets too large for the exhaustive mode)."""
+    import torch
+    q = Qd.double()
+    qn = (q * q).sum(1, keepdim=True)
+    best_d = torch.full((q.shape[0], k), float("inf"), dtype=torch.float64, device=q.device)
+    best_i = torch.zeros((q.shape[0], k), dtype=torch.int64, device=q.device)
+    for r0 in range(0, Xd.shape[0], rows):
+        x = Xd[r0:r0 + rows].double()
+        d2 = qn - 2.0 * (q @ x.T) + (x * x).sum(1)[None, :]
+        dv, di = torch.topk(d2, min(k, x.shape[0]), dim=1, largest=False)
+        cat_d = torch.cat([best_d, dv], 1)
+        cat_i = torch.cat([best_i, di + r0], 1)
+        o = torch.argsort(cat_d, dim=1, stable=True)[:, :k]
+        best_d, best_i = torch.gather(cat_d, 1, o), torch.gather(cat_i, 1, o)
+    return best_i.cpu().numpy()
 
 
 def kernel_source_hash():
@@ -85,6 +106,8 @@ def main():
     ap.add_argument("--no-plan", action="store_true", help="skip the graph-launched batch")
     ap.add_argument("--no-recall", action="store_true",
                     help="with --beta/--r-min: skip the ground truth (profiling runs)")
+    ap.add_argument("--plan-precision", default="fp32",
+                    help="verification form of the graph-launched batch (fp32, bf16, fp8)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scales rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -112,7 +135,14 @@ def main():
     w = wl.WORKLOADS[args.workload]
     nq = args.nq or w.nq
     t0 = time.time()
-    X, A, sid, Q = w.data(), w.proj(), w.sample(), w.queries(nq)
+    big = w.n > BIG_N
+
+    def gen_progress(done, total):
+        if big and (done % 8 == 0 or done == total):
+            log(f"[bench] generating {w.name}: {done}/{total} chunks ({time.time() - t0:.0f}s)")
+
+    X = w.data(threads=16 if big else 1, progress=gen_progress)
+    A, sid, Q = w.proj(), w.sample(), w.queries(nq)
     log(f"[bench] generated {w.name}: n={w.n} d={w.d} nq={nq} ({time.time() - t0:.1f}s)")
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
@@ -126,10 +156,13 @@ def main():
     nrec = min(args.recall_queries, nq)
     Qr = Qd[:nrec].contiguous()
     Qp = Qd[:256].contiguous()
-    if not args.no_recall:
+    if not args.no_recall and not big:
         exact_ids, _ = idx.query(Qr, k=10, c=w.c, beta=1.0, r_min=1e30)
         exact_ids = exact_ids.cpu().numpy()
         log(f"[bench] ground truth for {nrec} queries (exhaustive mode)")
+    elif not args.no_recall:
+        exact_ids = brute_force_knn(Xd, Qr, 10)
+        log(f"[bench] ground truth for {nrec} queries (FP64 brute force)")
 
     def calibrate(precision):
         """(beta, r_min, rounds resolved, recall@10) at the smallest beta reaching 0.9."""
@@ -155,6 +188,8 @@ def main():
             return at(args.beta)
         chosen = None
         for beta in BETA_LADDER:
+            if beta * w.n > MAX_CAL_CANDIDATES and beta != BETA_LADDER[-1]:
+                continue   # a calibration batch at this beta would verify too many rows
             res = at(beta)
             if res[3] >= 0.9:
                 chosen = res
@@ -250,13 +285,18 @@ def main():
         rng = np.random.default_rng(7)
         ks = rng.choice([1, 10, 100], size=nq).astype(np.int32)
         cs = rng.choice([1.2, 1.5, 2.0], size=nq)
-        plan = ix.plan(Qd, k=0, beta=beta, r_min=r_min, k_per_query=ks, c_per_query=cs)
+        pp = args.plan_precision
+        pb, pr, pc = (beta, r_min, rcap) if pp == "fp32" else lowp_cal[pp][:3]
+        ix.set_tuning(pr, pc)
+        plan = ix.plan(Qd, k=0, beta=pb, r_min=pr, k_per_query=ks, c_per_query=cs, precision=pp,
+                       rescore=4)
         sec_plan = timed(plan.launch)
-        sec_eager = timed(lambda: ix.query(Qd, k=0, beta=beta, r_min=r_min, k_per_query=ks,
-                                           c_per_query=cs))
+        sec_eager = timed(lambda: ix.query(Qd, k=0, beta=pb, r_min=pr, k_per_query=ks,
+                                           c_per_query=cs, precision=pp, rescore=4))
         plan.close()
-        batching = dict(qps_graph=nq / sec_plan, qps_eager=nq / sec_eager,
-                        k_mix=[1, 10, 100], c_mix=[1.2, 1.5, 2.0], beta=beta, r_min=r_min)
+        batching = dict(qps_graph=nq / sec_plan, qps_eager=nq / sec_eager, precision=pp,
+                        k_mix=[1, 10, 100], c_mix=[1.2, 1.5, 2.0], beta=pb, r_min=pr,
+                        search_launches=int(pdet.get_timing()["query_main_launches"]))
         log(f"[bench] batching: {batching}")
 
     # serving form: Poisson arrivals into the continuous-batching server

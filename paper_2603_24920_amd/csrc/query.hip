@@ -1082,6 +1082,10 @@ int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws) {
   return maxKL;
 }
 
+// Query slots the default workspace budget aims for: one workgroup of q_main each, two per
+// compute unit.
+constexpr int64_t MIN_SLOTS = 512;
+
 size_t slot_bytes(const Index& ix) {
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
   int64_t nl_total = 0;
@@ -1093,7 +1097,9 @@ size_t slot_bytes(const Index& ix) {
 
 // Sizes the workspace for a batch of nq queries: per-query arrays, and as many query slots
 // (concurrent per-query scratch) as `budget` bytes allow (0: a third of free memory, at
-// most 24 GiB). Allocation happens here, never during a launch sequence.
+// most 24 GiB; a large index whose slots are so big that this holds fewer than
+// MIN_SLOTS of them may take up to half of free memory for MIN_SLOTS). Allocation happens
+// here, never during a launch sequence.
 void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t budget,
                        hipStream_t s) {
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
@@ -1105,7 +1111,9 @@ void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t b
     if (budget == 0) {
       size_t freeb = 0, totalb = 0;
       PDET_HIP(hipMemGetInfo(&freeb, &totalb));
-      budget = std::min<size_t>((freeb + ws.bytes()) / 3, (size_t)24 << 30);
+      const size_t avail = freeb + ws.bytes();
+      budget = std::max<size_t>(std::min<size_t>(avail / 3, (size_t)24 << 30),
+                                std::min<size_t>(avail / 2, (size_t)MIN_SLOTS * per_slot));
     }
     const int64_t cap = std::max<int64_t>(1, (int64_t)(budget / per_slot));
     const int64_t want = std::max<int64_t>(1, std::min<int64_t>(nq, cap));

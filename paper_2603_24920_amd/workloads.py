@@ -54,20 +54,36 @@ def _draw_rows(kind, centres, rows, rng, sigma, normalize):
 
 def mixture(kind: str, n: int, d: int, n_centres: int, sigma: float, seed: int,
             centre_seed: int | None = None, centre_std: float = 1.0,
-            normalize: bool = False) -> np.ndarray:
+            normalize: bool = False, threads: int = 1, progress=None) -> np.ndarray:
     """Draw ``n`` rows of a clustered mixture (float32, row-major [n][d]).
 
     ``centre_seed`` fixes the centres (defaults to ``seed``) so that queries can
     be fresh draws from the mixture of a dataset: same centres, other seed.
+    Chunks have their own generators, so ``threads`` > 1 draws several chunks at
+    once (numpy releases the GIL while filling) with the same result.
+    ``progress(done_chunks, total_chunks)`` is called as chunks finish.
     """
     cs = seed if centre_seed is None else centre_seed
     centres = _centres(kind, n_centres, d, cs, centre_std)
     out = np.empty((n, d), dtype=np.float32)
     nchunks = max(1, math.ceil(n / CHUNK_ROWS))
     children = np.random.SeedSequence(seed).spawn(nchunks + 1)[1:]
-    for c in range(nchunks):
+
+    def one(c):
         lo, hi = c * CHUNK_ROWS, min(n, (c + 1) * CHUNK_ROWS)
         out[lo:hi] = _draw_rows(kind, centres, hi - lo, _rng(children[c]), sigma, normalize)
+
+    if threads <= 1 or nchunks == 1:
+        for c in range(nchunks):
+            one(c)
+            if progress is not None:
+                progress(c + 1, nchunks)
+        return out
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for done, _ in enumerate(ex.map(one, range(nchunks)), 1):
+            if progress is not None:
+                progress(done, nchunks)
     return out
 
 
@@ -121,9 +137,10 @@ class Workload:
         b = self.seed_base
         return dict(data=b, queries=b + 1, proj=b + 2, sample=b + 3)
 
-    def data(self, n: int | None = None) -> np.ndarray:
+    def data(self, n: int | None = None, threads: int = 1, progress=None) -> np.ndarray:
         return mixture(self.kind, self.n if n is None else n, self.d, self.n_centres, self.sigma,
-                       self.seeds["data"], centre_std=self.centre_std, normalize=self.normalize)
+                       self.seeds["data"], centre_std=self.centre_std, normalize=self.normalize,
+                       threads=threads, progress=progress)
 
     def queries(self, nq: int | None = None) -> np.ndarray:
         return mixture(self.kind, self.nq if nq is None else nq, self.d, self.n_centres, self.sigma,

@@ -85,3 +85,16 @@ def test_null_handles_are_rejected():
     assert pdet.lib().pdet_export(None, 0, 0, None, 0) == pdet.PDET_EINVAL
     assert pdet.lib().pdet_reserve(None, 16, None) == pdet.PDET_EINVAL
     pdet.lib().pdet_free(None)
+
+
+def test_threaded_generation_reproduces_the_serial_draw(monkeypatch):
+    """Chunks carry their own generators: drawing them on several threads gives the same
+    rows as one thread (large workloads are generated this way)."""
+    from paper_2603_24920_amd import workloads as wl
+    monkeypatch.setattr(wl, "CHUNK_ROWS", 1000)
+    w = wl.SIFT_LIKE_100M.scaled(n=7_500)
+    seen = []
+    a = w.data()
+    b = w.data(threads=4, progress=lambda done, total: seen.append((done, total)))
+    assert np.array_equal(a, b)
+    assert seen[-1] == (8, 8) and len(seen) == 8
