@@ -71,7 +71,8 @@ typedef struct {
  * The data pointer is BORROWED: it must stay allocated and unchanged until
  * pdet_free(), because verification reads it. Everything derived from it
  * (breakpoints, codes, trees, low-precision copies) is owned by the index.
- * Errors: EUNSUPPORTED for n >= 2^28 or a tree with 2^24 leaves or more; EINVAL for
+ * Errors: EUNSUPPORTED for n >= 2^28, L*K*n_sample (rounded up to a power of two)
+ * >= 2^32, or a tree with 2^24 leaves or more; EINVAL for
  * n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power of two in [2,256], max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range;
  * ENOMEM/EDEVICE from the runtime. On error *out is NULL.
  * Synchronises `stream` once (to size the leaf tables).

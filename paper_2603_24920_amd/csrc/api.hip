@@ -186,6 +186,13 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
                  "n_sample must be in [Nr, n]");
     PDET_REQUIRE((p->lowp_copies & ~((1u << PDET_BF16) | (1u << PDET_FP8_E4M3))) == 0,
                  PDET_EINVAL, "unknown lowp_copies bit");
+    {
+      // the column sort runs up to one work-item per sampled key; a dispatch holds < 2^32
+      int64_t sp = 1;
+      while (sp < p->n_sample) sp <<= 1;
+      PDET_REQUIRE((int64_t)p->L * p->K * sp < (int64_t(1) << 32), PDET_EUNSUPPORTED,
+                   "L * K * n_sample (rounded up to a power of two) must be below 2^32");
+    }
     for (int64_t i = 0; i < p->n_sample; ++i)
       PDET_REQUIRE(p->sample_ids[i] >= 0 && p->sample_ids[i] < n, PDET_EINVAL,
                    "sample id out of range");

@@ -13,12 +13,9 @@ __device__ inline uint16_t to_bf16(float f) {
   return (uint16_t)(r >> 16);
 }
 
-// One wave per row.
-__global__ __launch_bounds__(256) void lowp_rows(const float* X, int64_t n, int d, int dpad,
-                                                 uint16_t* xbf, uint8_t* xf8, float* xscale) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+// One row by one wave: the bf16 copy and / or the fp8 copy with its power-of-two scale.
+__device__ inline void lowp_row(const float* X, int64_t row, int d, int dpad, int lane,
+                                uint16_t* xbf, uint8_t* xf8, float* xscale) {
   const float* xr = X + row * d;
   if (xbf) {
     for (int t = lane; t < dpad; t += 64) xbf[row * dpad + t] = (t < d) ? to_bf16(xr[t]) : 0;
@@ -44,6 +41,18 @@ __global__ __launch_bounds__(256) void lowp_rows(const float* X, int64_t n, int 
   }
 }
 
+// One wave per row; the grid strides over the rows (a dispatch holds fewer than 2^32
+// work-items, so a wave per row of a 100M-row set cannot be one launch).
+constexpr int64_t LOWP_MAX_BLOCKS = int64_t(1) << 20;
+
+__global__ __launch_bounds__(256) void lowp_rows(const float* X, int64_t n, int d, int dpad,
+                                                 uint16_t* xbf, uint8_t* xf8, float* xscale) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
+       row += (int64_t)gridDim.x * 4)
+    lowp_row(X, row, d, dpad, lane, xbf, xf8, xscale);
+}
+
 }  // namespace
 
 void build_lowp_copies(Index& ix, hipStream_t s) {
@@ -55,7 +64,8 @@ void build_lowp_copies(Index& ix, hipStream_t s) {
     ix.xfp8.alloc((size_t)ix.n * ix.dpad);
     ix.xscale.alloc((size_t)ix.n * 4);
   }
-  hipLaunchKernelGGL(lowp_rows, dim3(cdiv(ix.n, 4)), dim3(256), 0, s, ix.X, ix.n, ix.d, ix.dpad,
+  const unsigned grid = (unsigned)std::min<int64_t>(cdiv(ix.n, 4), LOWP_MAX_BLOCKS);
+  hipLaunchKernelGGL(lowp_rows, dim3(grid), dim3(256), 0, s, ix.X, ix.n, ix.d, ix.dpad,
                      bf ? ix.xbf16.as<uint16_t>() : nullptr, f8 ? ix.xfp8.as<uint8_t>() : nullptr,
                      f8 ? ix.xscale.as<float>() : nullptr);
   PDET_HIP(hipGetLastError());

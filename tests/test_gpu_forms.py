@@ -159,3 +159,31 @@ def test_server_results_same_alone_and_in_the_mix(env, precision):
     assert st["completed"] == 12 + len(Q)
     assert st["mean_batch"] > 1.0          # the mix was batched
     assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_low_precision_copies_past_one_grid_sweep():
+    """The bf16 / fp8 copies are written by a grid that strides over the rows (4M rows per
+    sweep); at 5M integer-valued rows of d = 16 the bf16 copy is exact, so bf16
+    verification returns the float32 path's ids and distances for every query."""
+    w = wl.SIFT_LIKE_1M.scaled(n=5_000_000, d=16, nq=100, k=10)
+    X = w.data()
+    print(f"\n[lowp-sweep] n={len(X)} d={X.shape[1]}", flush=True)
+    Xd = torch.from_numpy(X).cuda()
+    idx = pdet.Index(Xd, w.proj(), w.sample(), w.K, w.L, w.Nr, w.max_leaf,
+                     lowp=("bf16", "fp8"))
+    Qd = torch.from_numpy(w.queries()).cuda()
+    t = idx.autotune(Qd[:64].contiguous(), k=w.k, c=w.c, beta=0.001)
+    f_ids, f_d = idx.query(Qd, k=w.k, c=w.c, beta=0.001, r_min=t["r_min"])
+    b_ids, b_d = idx.query(Qd, k=w.k, c=w.c, beta=0.001, r_min=t["r_min"], precision="bf16",
+                           rescore=4)
+    assert torch.equal(f_ids, b_ids)
+    np.testing.assert_allclose(b_d.cpu().numpy(), f_d.cpu().numpy(), rtol=1e-6)
+    # fp8: every returned distance is the exact distance of the returned id (FP32 rescore)
+    e_ids, e_d = idx.query(Qd, k=w.k, c=w.c, beta=0.001, r_min=t["r_min"], precision="fp8",
+                           rescore=4)
+    ids = e_ids.cpu().numpy()
+    exact = np.sqrt(((X[ids].astype(np.float64) - w.queries()[:, None, :]) ** 2).sum(-1))
+    np.testing.assert_allclose(e_d.cpu().numpy(), exact, rtol=1e-6)
+    rec = np.mean([len(np.intersect1d(a, b)) / w.k for a, b in zip(ids, f_ids.cpu().numpy())])
+    print(f"[lowp-sweep] fp8 recall@{w.k} against float32: {rec:.3f}", flush=True)
+    idx.close()

@@ -98,3 +98,21 @@ def test_threaded_generation_reproduces_the_serial_draw(monkeypatch):
     b = w.data(threads=4, progress=lambda done, total: seen.append((done, total)))
     assert np.array_equal(a, b)
     assert seen[-1] == (8, 8) and len(seen) == 8
+
+
+def test_build_rejects_a_sample_too_large_for_one_sort_dispatch():
+    """L*K*n_sample (rounded up to a power of two) at 2^32 would need more work-items than
+    one dispatch holds; the build refuses it before any device work on the sample."""
+    p, keep = _params()
+    n = (1 << 28) - 1
+    ids = np.arange(1 << 26, dtype=np.int64)
+    p.L, p.K = 16, 16
+    p.sample_ids = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    p.n_sample = (1 << 26) + 0   # 256 columns * 2^26 = 2^34 keys
+    proj = np.zeros((8, 256), dtype=np.float32)
+    p.proj = proj.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    h = ctypes.c_void_p()
+    st = pdet.lib().pdet_build(ctypes.c_void_p(4096), n, 8, ctypes.byref(p), None,
+                               ctypes.byref(h))
+    assert st == pdet.PDET_EUNSUPPORTED and h.value is None
+    assert "2^32" in pdet.lib().pdet_last_error().decode()
