@@ -336,6 +336,7 @@ def main():
         "query_ms": 1e3 * query_s,
         "reserve_ms": 1e3 * float(np.mean([r["reserve_s"] for r in recs])),
         "mean_candidates_per_query": ncand / nq,
+        "queries_answered_again": int(recs[-1]["tq"].get("query_retried", 0)),
         "stop_rule_A_fraction": float(np.mean([np.mean(r["stops"] == 1) for r in recs])),
         "per_query_search_us": {
             "p50": float(np.percentile(recs[-1]["qtime"], 50) * 1e3 / recs[-1]["khz"]),

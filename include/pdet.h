@@ -150,6 +150,18 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
  * are then run in chunks of query slots. Waits for `stream`. nq < 0 -> PDET_EINVAL. */
 pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream);
 
+/* Per-tree capacity of the admitted-leaf lists in each query slot of pdet_query,
+ * pdet_reserve and plans (servers always hold every leaf). Not an operation of the
+ * method: it trades slot memory for concurrency. 0 (the default) holds every leaf unless
+ * the index is so large that fewer than min(nq, 2048) such slots fit the workspace budget;
+ * then the lists are capped at what 2048 slots allow (at least 16384 entries per tree).
+ * cap > 0 sets the capacity (trees with fewer leaves hold all of theirs). A query whose
+ * lists would exceed the capacity is answered again, after the batch, with slots that
+ * hold every leaf; results are the same either way, and pdet_get_timing counts such
+ * queries (query_retried). Drops the index's pooled query workspaces: must not run
+ * concurrently with queries on the same index. cap < 0 -> PDET_EINVAL. */
+pdet_status pdet_set_list_cap(pdet_index* idx, int64_t cap);
+
 /* Description of a built index. */
 typedef struct {
   int64_t n, n_sample;
@@ -205,6 +217,7 @@ typedef struct {
   double query_rho_ms;      /* leaf lower bounds -> first admitting round               */
   double query_main_ms;     /* search, dedupe, verification, top-k                      */
   int64_t query_main_launches;
+  int64_t query_retried;    /* queries answered again after their leaf lists overflowed */
 } pdet_timing;
 void pdet_set_timing(int32_t on);
 pdet_status pdet_get_timing(pdet_timing* out);
@@ -235,6 +248,8 @@ pdet_status pdet_set_tuning(pdet_index* idx, double r_min, int32_t rounds_resolv
  * output and per-query k / c arguments are fixed at creation (same meaning as pdet_query);
  * the caller may rewrite the query buffer between launches. pdet_plan_launch replays the
  * graph on `stream`; outputs are valid when the stream reaches the end of the launch.
+ * If the plan's query slots hold capped leaf lists (see pdet_set_list_cap), the launch
+ * also waits for the stream once and answers overflowed queries again on it.
  * Launches of one plan must not overlap. The plan holds its own scratch until freed.
  */
 typedef struct pdet_plan pdet_plan;

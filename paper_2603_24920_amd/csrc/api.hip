@@ -294,7 +294,17 @@ pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream) {
     PDET_REQUIRE(nq >= 0, PDET_EINVAL, "nq must be >= 0");
     if (nq == 0) return;
     WorkspaceLease lease(*idx);
-    reserve_workspace(*idx, lease.get(), nq, 0, static_cast<hipStream_t>(stream));
+    reserve_workspace(*idx, lease.get(), nq, 0, static_cast<hipStream_t>(stream), true);
+  });
+}
+
+pdet_status pdet_set_list_cap(pdet_index* idx, int64_t cap) {
+  return guarded([&] {
+    PDET_REQUIRE(idx, PDET_EINVAL, "NULL index");
+    PDET_REQUIRE(cap >= 0, PDET_EINVAL, "cap must be >= 0");
+    std::lock_guard<std::mutex> g(idx->ws_mu);
+    idx->list_cap = cap;
+    idx->ws_free.clear();
   });
 }
 

@@ -16,14 +16,26 @@ struct QueryWorkspace {
   DevBuf rho, admb, adm2, t2, crr, lcnt, qp, dk, dc, dT, doff;
   PinnedBuf h_k, h_c, h_T, h_off;   // staging of the per-query parameters
   int64_t nslots = 0, nslots_max = 0, nq_cap = 0;
+  // Leaf-list capacity of a slot per tree: tree i holds min(nl_i, list_cap) entries. A
+  // large index caps it so that more slots fit; a query whose lists would overflow is
+  // flagged in `ovf` (count, then query indices) and answered again in `full`, whose
+  // slots hold every leaf.
+  int64_t list_cap = 0;
+  int64_t cap_req = -1;            // the index's requested capacity when this was sized
+  DevBuf ovf;
+  PinnedBuf h_ovf;
+  std::unique_ptr<QueryWorkspace> full;
+  int64_t retried = 0;             // queries answered again in `full` (all batches)
   // a batch whose queries share k and c passes them as scalars (no per-query upload)
   bool uniform = false;
   int32_t uk = 0;
   int64_t uT = 0;
   double uc = 0.0;
   size_t bytes() const {
-    return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes + lcnt.bytes;
+    return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes + lcnt.bytes +
+           (full ? full->bytes() : 0);
   }
+  bool capped() const { return full != nullptr; }
 };
 }  // namespace pdet
 
@@ -54,6 +66,7 @@ struct pdet_index {
   // radius schedule chosen by pdet_autotune (r_min <= 0 in a query selects tuned_r_min)
   double tuned_r_min = 0.0;
   int rcap = 4;                    // rounds resolved by the batched bound kernel
+  int64_t list_cap = 0;            // per-tree leaf-list capacity of query slots (0: automatic)
   // low-precision copies for verification
   int dpad = 0;                    // row length of the copies (multiple of 16)
   pdet::DevBuf xbf16;              // bf16 [n][dpad]
@@ -156,10 +169,16 @@ struct QueryConfig {
 void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s);
 int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws);
 size_t slot_bytes(const Index& ix);
+// cap_lists: a large index may cap the slots' leaf lists (see QueryWorkspace); the
+// caller then runs retry_overflowed() after the batch.
 void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t budget,
-                       hipStream_t s);
+                       hipStream_t s, bool cap_lists = false);
 void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
                    hipStream_t s, bool timed);
+// For a workspace with capped lists: waits for stream s, then answers the batch's flagged
+// queries again with full-capacity slots (a no-op for uncapped workspaces).
+void retry_overflowed(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
+                      hipStream_t s, bool timed);
 
 // api.hip
 double epsilon(int K, int L);

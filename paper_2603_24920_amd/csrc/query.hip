@@ -48,6 +48,7 @@ constexpr int HMAX = HSZ / 2;    // most entries it takes; beyond, a dense table
 constexpr uint32_t HEMPTY = 0xffffffffu;
 constexpr uint32_t NO_CUT = 0xffffffffu;
 constexpr int WALK_VERIFY = 0, WALK_COUNT = 1, WALK_CUT = 2;
+constexpr int STOP_OVERFLOW = 3; // query-stat stop code: leaf lists overflowed (answered again)
 constexpr int LBCH = 4;          // box dimensions q_main loads at a time for a lower bound
 constexpr int RLBCH = 2;         // the same in the (rare) refinement, which is kept lean
 
@@ -65,6 +66,7 @@ struct QArgs {
   const float* gbox[PDET_MAX_L];
   int64_t nl[PDET_MAX_L];
   int64_t nlo[PDET_MAX_L];   // first slot of tree i's region in a per-query leaf list
+  uint32_t lcap[PDET_MAX_L]; // entries tree i's region holds (min(nl_i, the slot's cap))
   int64_t ng[PDET_MAX_L];
   int64_t nlpad;
   int lb_per_die;            // q_rho leaf blocks (256 leaves) of a tree that each die takes
@@ -99,12 +101,20 @@ struct QArgs {
   int64_t q0;
   int nslots;
   double r_min, eps;
+  const int32_t* qmap;       // null: slot s answers query q0 + s; else query qmap[q0 + s]
+  uint32_t* ovf;             // [1 + nq]: count of queries whose leaf lists overflowed, their ids
 };
+
+__device__ inline int64_t slot_query(const QArgs& a, int slot) {
+  return a.qmap ? (int64_t)a.qmap[a.q0 + slot] : a.q0 + slot;
+}
 
 __global__ void q_setup(QArgs a) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= a.nslots) return;
-  const int64_t q = a.q0 + slot;
+  const int64_t q = slot_query(a, slot);
+  // the overflow count of the batch starts at zero (written before any q_main of the batch)
+  if (!a.qmap && a.q0 == 0 && slot == 0) a.ovf[0] = 0;
   if (a.uniform) {
     const_cast<int32_t*>(a.qk)[q] = a.uk;
     const_cast<int64_t*>(a.qT)[q] = a.uT;
@@ -223,12 +233,22 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
     stv[u] = (e < QT * (RCAP_MAX + 1) && slot0 + qi < a.nslots)
                  ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
   }
-  const float* qpt = a.qp + (a.q0 + slot0) * (int64_t)(a.L * K) + tree * K;
+  if (!a.qmap) {
+    const float* qpt = a.qp + (a.q0 + slot0) * (int64_t)(a.L * K) + tree * K;
 #pragma unroll
-  for (int u = 0; u < NSQ; ++u) {
-    const int e = threadIdx.x + u * QR_THREADS;
-    const int qi = e / PDET_MAX_K, j = e % PDET_MAX_K;
-    sqv[u] = (j < K && slot0 + qi < a.nslots) ? qpt[(uint32_t)(qi * a.L * K + j)] : 0.0f;
+    for (int u = 0; u < NSQ; ++u) {
+      const int e = threadIdx.x + u * QR_THREADS;
+      const int qi = e / PDET_MAX_K, j = e % PDET_MAX_K;
+      sqv[u] = (j < K && slot0 + qi < a.nslots) ? qpt[(uint32_t)(qi * a.L * K + j)] : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < NSQ; ++u) {
+      const int e = threadIdx.x + u * QR_THREADS;
+      const int qi = e / PDET_MAX_K, j = e % PDET_MAX_K;
+      const bool ok = j < K && slot0 + qi < a.nslots;
+      sqv[u] = ok ? a.qp[slot_query(a, slot0 + qi) * (int64_t)(a.L * K) + tree * K + j] : 0.0f;
+    }
   }
 #pragma unroll
   for (int u = 0; u < NST; ++u) {
@@ -261,8 +281,10 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
     for (int rr = 0; rr <= RCAP_MAX; ++rr) c += (rr <= rcap && st[qi][rr] < acc) ? 1 : 0;
     if (c <= rcap) {
       const uint32_t pos = atomicAdd(&a.lcnt[(int64_t)slot * PDET_MAX_L + tree], 1u);
-      a.adm_leaf[(int64_t)slot * a.admcap + a.nlo[tree] + pos] =
-          ((uint32_t)c << LEAF_BITS) | (uint32_t)leaf;
+      // past the region's capacity only the count grows: q_main sees the overflow
+      if (pos < a.lcap[tree])
+        a.adm_leaf[(int64_t)slot * a.admcap + a.nlo[tree] + pos] =
+            ((uint32_t)c << LEAF_BITS) | (uint32_t)leaf;
     }
   }
 }
@@ -487,7 +509,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   __shared__ unsigned long long s_cut;
 
   const int slot = blockIdx.x;
-  const int64_t q = a.q0 + slot;
+  const int64_t q = slot_query(a, slot);
   const int tid = threadIdx.x, lane = tid & 63;
   const int lpc = a.lpc;                          // lanes per candidate (power of two)
   const int lg = tid & (lpc - 1), grp = tid / lpc;
@@ -524,6 +546,15 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   uint32_t hsum = 0, hmix = 0;
   int stop = -1, rounds = 0;
   int cap = a.rcap;            // rounds whose leaf indices are resolved
+  // Leaf lists past their slot's capacity (a large index caps them): the query is flagged
+  // and answered again with full-capacity slots. STOP_OVERFLOW leaves the round loop;
+  // the lists written so far are whole, so the dense table is restored from them.
+  auto overflowed = [&]() -> bool {
+    bool o = false;
+    for (int i = 0; i < a.L; ++i) o = o || s_lc[i] > a.lcap[i];
+    return o;
+  };
+  if (overflowed()) stop = STOP_OVERFLOW;
   const uint64_t t_start = wall_clock64();
 
   // Sorts the kept list and the pending buffer together (over the power of two that holds
@@ -828,13 +859,21 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
 #pragma unroll
             for (int sft = NRHO / 2; sft > 0; sft >>= 1)
               if (st2[pos + sft - 1] < lb2) pos += sft;
-            if (pos > cap && pos <= ncap)
-              lst[atomicAdd(&s_lc[i], 1u)] = ((uint32_t)pos << LEAF_BITS) | (uint32_t)leaf;
+            if (pos > cap && pos <= ncap) {
+              const uint32_t at = atomicAdd(&s_lc[i], 1u);
+              if (at < a.lcap[i]) lst[at] = ((uint32_t)pos << LEAF_BITS) | (uint32_t)leaf;
+            }
           }
           __syncthreads();
         }
       }
       cap = ncap;
+      if (overflowed()) {
+        // s_lco still holds the prefix of the lists before this append: every entry the
+        // dense table may hold lies in it
+        stop = STOP_OVERFLOW;
+        break;
+      }
     }
     // admitted leaves of this round, from the lists in tree order: entries, their sizes'
     // prefix sums and their perm start positions
@@ -1026,6 +1065,9 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     sort_pairs(ld, li, len);
   }
 
+  // (full-capacity slots never overflow; the guard keeps a retry from touching its own map)
+  if (stop == STOP_OVERFLOW && tid == 0 && !a.qmap)
+    a.ovf[1 + atomicAdd(&a.ovf[0], 1u)] = (uint32_t)q;
   const int64_t off = a.qoff[q];
   for (int t = tid; t < k; t += QM) {
     a.ids[off + t] = (li[t] == INT32_MAX) ? -1 : (int64_t)li[t];
@@ -1082,98 +1124,156 @@ int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws) {
   return maxKL;
 }
 
-// Query slots the default workspace budget aims for: one workgroup of q_main each, two per
-// compute unit.
-constexpr int64_t MIN_SLOTS = 512;
+// Query slots a capped workspace aims for: one q_main workgroup per slot, eight resident
+// per compute unit.
+constexpr int64_t TARGET_SLOTS = 2048;
+// Least per-tree leaf-list capacity of a capped slot, and the full-capacity slots that
+// answer overflowed queries again.
+constexpr int64_t MIN_LIST_CAP = 16384;
+constexpr int64_t RETRY_SLOTS = 16;
 
-size_t slot_bytes(const Index& ix) {
+int64_t total_leaves(const Index& ix) {
+  int64_t t = 0;
+  for (int i = 0; i < ix.L; ++i) t += ix.nl[i];
+  return std::max<int64_t>(t, 1);
+}
+
+// Entries of a slot's leaf lists when every tree's region holds min(nl_i, cap) of them.
+int64_t list_entries(const Index& ix, int64_t cap) {
+  int64_t t = 0;
+  for (int i = 0; i < ix.L; ++i) t += std::min<int64_t>(ix.nl[i], cap);
+  return std::max<int64_t>(t, 1);
+}
+
+size_t slot_bytes_at(const Index& ix, int64_t admcap) {
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
-  int64_t nl_total = 0;
-  for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
-  const int64_t admcap = std::max<int64_t>(nl_total, 1);
   return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 + NRHO * 12 +
          PDET_MAX_L * 4;
 }
 
+size_t slot_bytes(const Index& ix) { return slot_bytes_at(ix, total_leaves(ix)); }
+
+namespace {
+// (Re)allocates `want` slots whose lists hold min(nl_i, cap) entries per tree.
+void alloc_slots(const Index& ix, QueryWorkspace& ws, int64_t want, int64_t cap, hipStream_t s) {
+  const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
+  const int64_t admcap = list_entries(ix, cap);
+  ws.rho.release(); ws.admb.release(); ws.adm2.release(); ws.t2.release(); ws.crr.release();
+  ws.lcnt.release();
+  ws.rho.alloc((size_t)want * ix.L * nlpad);
+  ws.admb.alloc((size_t)want * admcap * 12);
+  ws.adm2.alloc((size_t)want * (admcap + 1) * 12);
+  ws.t2.alloc((size_t)want * NRHO * 4);
+  ws.crr.alloc((size_t)want * NRHO * 8);
+  ws.lcnt.alloc((size_t)want * PDET_MAX_L * 4);
+  // the dense round table starts "never admitted"; a query that writes it restores it
+  PDET_HIP(hipMemsetAsync(ws.rho.p, 0xff, ws.rho.bytes, s));
+  ws.nslots = want;
+  ws.list_cap = cap;
+}
+}  // namespace
+
 // Sizes the workspace for a batch of nq queries: per-query arrays, and as many query slots
 // (concurrent per-query scratch) as `budget` bytes allow (0: a third of free memory, at
-// most 24 GiB; a large index whose slots are so big that this holds fewer than
-// MIN_SLOTS of them may take up to half of free memory for MIN_SLOTS). Allocation happens
-// here, never during a launch sequence.
+// most 24 GiB). Slots normally hold every leaf of every tree. With cap_lists, an index
+// whose full-capacity slots would number fewer than min(nq, TARGET_SLOTS) in that budget
+// caps the lists instead (at least MIN_LIST_CAP entries per tree; the default budget may
+// then grow to a third of free memory) and keeps RETRY_SLOTS full-capacity slots for the
+// queries that overflow them. Allocation happens here, never during a launch sequence.
 void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t budget,
-                       hipStream_t s) {
-  const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
-  int64_t nl_total = 0;
-  for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
-  const int64_t admcap = std::max<int64_t>(nl_total, 1);
-  const size_t per_slot = slot_bytes(ix);
-  if (ws.nslots == 0 || (ws.nslots < nq && ws.nslots < ws.nslots_max)) {
-    if (budget == 0) {
+                       hipStream_t s, bool cap_lists) {
+  const int64_t nl_all = std::max<int64_t>(ix.nl_max, 1);
+  const bool resize = cap_lists && ws.cap_req != ix.list_cap;
+  if (resize || ws.nslots == 0 || (ws.nslots < nq && ws.nslots < ws.nslots_max)) {
+    size_t avail = 0;
+    const bool dflt = budget == 0;
+    if (dflt) {
       size_t freeb = 0, totalb = 0;
       PDET_HIP(hipMemGetInfo(&freeb, &totalb));
-      const size_t avail = freeb + ws.bytes();
-      budget = std::max<size_t>(std::min<size_t>(avail / 3, (size_t)24 << 30),
-                                std::min<size_t>(avail / 2, (size_t)MIN_SLOTS * per_slot));
+      avail = freeb + ws.bytes();
+      budget = std::min<size_t>(avail / 3, (size_t)24 << 30);
     }
-    const int64_t cap = std::max<int64_t>(1, (int64_t)(budget / per_slot));
-    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(nq, cap));
-    if (want > ws.nslots) {
-      ws.rho.release(); ws.admb.release(); ws.adm2.release(); ws.t2.release(); ws.crr.release();
-      ws.lcnt.release();
-      ws.rho.alloc((size_t)want * ix.L * nlpad);
-      ws.admb.alloc((size_t)want * admcap * 12);
-      ws.adm2.alloc((size_t)want * (admcap + 1) * 12);
-      ws.t2.alloc((size_t)want * NRHO * 4);
-      ws.crr.alloc((size_t)want * NRHO * 8);
-      ws.lcnt.alloc((size_t)want * PDET_MAX_L * 4);
-      // the dense round table starts "never admitted"; a query that writes it restores it
-      PDET_HIP(hipMemsetAsync(ws.rho.p, 0xff, ws.rho.bytes, s));
-      ws.nslots = want;
+    const int64_t target = std::max<int64_t>(1, std::min<int64_t>(nq, TARGET_SLOTS));
+    int64_t cap = nl_all;
+    if (cap_lists && ix.list_cap > 0) {
+      cap = std::min<int64_t>(ix.list_cap, nl_all);
+      if (cap < nl_all) {
+        const size_t retry = (size_t)RETRY_SLOTS * slot_bytes(ix);
+        budget = budget > retry ? budget - retry : slot_bytes_at(ix, list_entries(ix, cap));
+      }
+    } else if (cap_lists && (int64_t)(budget / slot_bytes(ix)) < target) {
+      if (dflt) budget = std::max<size_t>(budget, avail / 3);
+      // full-capacity retry slots come out of the same budget
+      const size_t retry = (size_t)RETRY_SLOTS * slot_bytes(ix);
+      const size_t rest = budget > retry ? budget - retry : 0;
+      const size_t per = rest / (size_t)target;
+      const size_t fixed = slot_bytes_at(ix, 0);
+      int64_t c = per > fixed ? (int64_t)((per - fixed) / 24 / (size_t)ix.L) : 0;
+      c = std::max<int64_t>(c, MIN_LIST_CAP);
+      if (c < nl_all) {
+        cap = c;
+        budget = rest;
+      }
     }
-    ws.nslots_max = cap;
+    const size_t per_slot = slot_bytes_at(ix, list_entries(ix, cap));
+    const int64_t slots_cap = std::max<int64_t>(1, (int64_t)(budget / per_slot));
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(nq, slots_cap));
+    if (want > ws.nslots || cap != ws.list_cap) alloc_slots(ix, ws, want, cap, s);
+    ws.nslots_max = slots_cap;
+    if (cap_lists) ws.cap_req = ix.list_cap;
+    if (cap < nl_all) {
+      if (!ws.full) ws.full.reset(new QueryWorkspace());
+      if (ws.full->nslots == 0) alloc_slots(ix, *ws.full, RETRY_SLOTS, nl_all, s);
+    } else {
+      ws.full.reset();
+    }
   }
   if (ws.nq_cap < nq) {
     ws.dk.alloc((size_t)nq * 4); ws.dc.alloc((size_t)nq * 8);
     ws.dT.alloc((size_t)nq * 8); ws.doff.alloc((size_t)nq * 8);
     ws.qp.alloc((size_t)nq * PDET_MAX_L * PDET_MAX_K * 4);
+    ws.ovf.alloc((size_t)(nq + 1) * 4);
     ws.h_k.alloc((size_t)nq * 4); ws.h_c.alloc((size_t)nq * 8);
     ws.h_T.alloc((size_t)nq * 8); ws.h_off.alloc((size_t)nq * 8);
     ws.nq_cap = nq;
   }
+  if (!ws.h_ovf.p) ws.h_ovf.alloc(4);
   PDET_HIP(hipStreamSynchronize(s));
 }
 
-// Enqueues the whole query sequence on stream s (parameter upload from the pinned staging,
-// query projection, then per chunk of slots: thresholds, round indices, search). No host
-// synchronisation unless `timed` (HIP events per kernel family).
-void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
-                   hipStream_t s, bool timed) {
-  const int64_t nq = qc.nq;
+namespace {
+// Points the per-slot arrays of `a` at the slots of workspace `sw`: tree i's leaf-list
+// region holds min(nl_i, sw.list_cap) entries.
+void bind_slots(const Index& ix, QArgs& a, QueryWorkspace& sw) {
+  const int64_t cap = sw.list_cap;
+  const int64_t admcap = list_entries(ix, cap);
+  const int64_t nslots = sw.nslots;
+  int64_t o = 0;
+  for (int i = 0; i < ix.L; ++i) {
+    const int64_t li = std::min<int64_t>(ix.nl[i], cap);
+    a.nlo[i] = o;
+    a.lcap[i] = (uint32_t)li;
+    o += li;
+  }
+  a.t2 = sw.t2.as<float>();
+  a.crr = sw.crr.as<double>();
+  a.rho = sw.rho.as<uint8_t>();
+  a.lcnt = sw.lcnt.as<uint32_t>();
+  a.adm_leaf = sw.admb.as<uint32_t>();
+  a.adm_w = a.adm_leaf + nslots * admcap;
+  a.adm_lb = reinterpret_cast<float*>(a.adm_w + nslots * admcap);
+  a.adm2_leaf = sw.adm2.as<uint32_t>();
+  a.adm2_pre = a.adm2_leaf + nslots * (admcap + 1);
+  a.adm_start = reinterpret_cast<int32_t*>(a.adm2_pre + nslots * (admcap + 1));
+  a.admcap = admcap;
+}
+
+// Everything of a batch's kernel arguments except the slot arrays; `smem` gets q_main's
+// dynamic LDS.
+QArgs batch_args(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
+                 size_t& smem) {
   const int LK = ix.L * ix.K;
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
-  int64_t nl_total = 0;
-  for (int i = 0; i < ix.L; ++i) nl_total += ix.nl[i];
-  const int64_t admcap = std::max<int64_t>(nl_total, 1);
-  const int64_t nslots = ws.nslots;
-  if (!ws.uniform) {
-    PDET_HIP(hipMemcpyAsync(ws.dk.p, ws.h_k.p, nq * 4, hipMemcpyHostToDevice, s));
-    PDET_HIP(hipMemcpyAsync(ws.dc.p, ws.h_c.p, nq * 8, hipMemcpyHostToDevice, s));
-    PDET_HIP(hipMemcpyAsync(ws.dT.p, ws.h_T.p, nq * 8, hipMemcpyHostToDevice, s));
-    PDET_HIP(hipMemcpyAsync(ws.doff.p, ws.h_off.p, nq * 8, hipMemcpyHostToDevice, s));
-  }
-
-  pdet_timing scratch_tm{};
-  pdet_timing& tm = timed ? timer().t : scratch_tm;
-  if (timed) {
-    tm.query_project_ms = tm.query_rho_ms = tm.query_main_ms = 0.0;
-    tm.query_main_launches = 0;
-  }
-  {
-    Span sp(s, timed ? &tm.query_project_ms : nullptr);
-    project_points(ix, qc.Q, nq, ws.qp.as<float>(), s);
-    sp.finish();
-  }
-
   QArgs a{};
   a.n = ix.n; a.d = ix.d; a.L = ix.L; a.K = ix.K; a.dpad = ix.dpad;
   a.X = ix.X;
@@ -1182,10 +1282,7 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   a.xscale = ix.xscale.as<float>();
   a.perm = ix.perm.as<int32_t>();
   a.leafrow = ix.leafrow.as<int32_t>();
-  int64_t nlo = 0;
   for (int i = 0; i < ix.L; ++i) {
-    a.nlo[i] = nlo;
-    nlo += ix.nl[i];
     a.lstart[i] = ix.leaf_start[i].as<int32_t>();
     a.lcount[i] = ix.leaf_count[i].as<int32_t>();
     a.box[i] = ix.box[i].as<float>();
@@ -1205,17 +1302,6 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   a.uk = ws.uk;
   a.uT = ws.uT;
   a.uc = ws.uc;
-  a.t2 = ws.t2.as<float>();
-  a.crr = ws.crr.as<double>();
-  a.rho = ws.rho.as<uint8_t>();
-  a.lcnt = ws.lcnt.as<uint32_t>();
-  a.adm_leaf = ws.admb.as<uint32_t>();
-  a.adm_w = a.adm_leaf + nslots * admcap;
-  a.adm_lb = reinterpret_cast<float*>(a.adm_w + nslots * admcap);
-  a.adm2_leaf = ws.adm2.as<uint32_t>();
-  a.adm2_pre = a.adm2_leaf + nslots * (admcap + 1);
-  a.adm_start = reinterpret_cast<int32_t*>(a.adm2_pre + nslots * (admcap + 1));
-  a.admcap = admcap;
   a.ids = qc.ids;
   a.dists = qc.dists;
   a.qstats = qc.qstats;
@@ -1238,11 +1324,19 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   while (NM < maxKL + CBMIN) NM <<= 1;
   a.NM = NM;
   const int dq = (qc.precision == PDET_FP32) ? ((ix.d + 3) & ~3) : ix.dpad;
-  const size_t smem = (size_t)NM * 12 + (size_t)dq * 12 + (size_t)LK * 4;
+  smem = (size_t)NM * 12 + (size_t)dq * 12 + (size_t)LK * 4;
   // with the kernel's static LDS (under 16 KiB) a workgroup stays within 64 KiB
   PDET_REQUIRE(smem <= 48 * 1024, PDET_EUNSUPPORTED,
                "d and k * rescore too large for the query workgroup's LDS");
+  a.qmap = nullptr;
+  a.ovf = ws.ovf.as<uint32_t>();
+  return a;
+}
 
+// Per chunk of `nslots` queries of the nq the arguments select: thresholds, round
+// indices, search.
+void launch_chunks(const Index& ix, int precision, QArgs a, int64_t nq, int64_t nslots,
+                   size_t smem, hipStream_t s, bool timed, pdet_timing& tm) {
   for (int64_t q0 = 0; q0 < nq; q0 += nslots) {
     a.q0 = q0;
     a.nslots = (int)std::min<int64_t>(nslots, nq - q0);
@@ -1260,7 +1354,7 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
       sp.finish();
     }
     Span sp(s, timed ? &tm.query_main_ms : nullptr);
-    switch (qc.precision) {
+    switch (precision) {
       case PDET_FP32:
         hipLaunchKernelGGL(q_main_f32, dim3(a.nslots), dim3(QM), smem, s, a);
         break;
@@ -1276,14 +1370,68 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
     if (timed) ++tm.query_main_launches;
   }
 }
+}  // namespace
+
+// Enqueues the whole query sequence on stream s (parameter upload from the pinned staging,
+// query projection, then per chunk of slots: thresholds, round indices, search). No host
+// synchronisation unless `timed` (HIP events per kernel family).
+void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
+                   hipStream_t s, bool timed) {
+  const int64_t nq = qc.nq;
+  if (!ws.uniform) {
+    PDET_HIP(hipMemcpyAsync(ws.dk.p, ws.h_k.p, nq * 4, hipMemcpyHostToDevice, s));
+    PDET_HIP(hipMemcpyAsync(ws.dc.p, ws.h_c.p, nq * 8, hipMemcpyHostToDevice, s));
+    PDET_HIP(hipMemcpyAsync(ws.dT.p, ws.h_T.p, nq * 8, hipMemcpyHostToDevice, s));
+    PDET_HIP(hipMemcpyAsync(ws.doff.p, ws.h_off.p, nq * 8, hipMemcpyHostToDevice, s));
+  }
+
+  pdet_timing scratch_tm{};
+  pdet_timing& tm = timed ? timer().t : scratch_tm;
+  if (timed) {
+    tm.query_project_ms = tm.query_rho_ms = tm.query_main_ms = 0.0;
+    tm.query_main_launches = 0;
+    tm.query_retried = 0;
+  }
+  {
+    Span sp(s, timed ? &tm.query_project_ms : nullptr);
+    project_points(ix, qc.Q, nq, ws.qp.as<float>(), s);
+    sp.finish();
+  }
+  size_t smem = 0;
+  QArgs a = batch_args(ix, qc, ws, maxKL, smem);
+  bind_slots(ix, a, ws);
+  launch_chunks(ix, qc.precision, a, nq, ws.nslots, smem, s, timed, tm);
+}
+
+void retry_overflowed(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
+                      hipStream_t s, bool timed) {
+  if (!ws.capped() || qc.nq == 0) return;
+  uint32_t* h = ws.h_ovf.as<uint32_t>();
+  PDET_HIP(hipMemcpyAsync(h, ws.ovf.p, 4, hipMemcpyDeviceToHost, s));
+  PDET_HIP(hipStreamSynchronize(s));
+  const int64_t n_ovf = *h;
+  if (n_ovf == 0) return;
+  PDET_REQUIRE(n_ovf <= qc.nq, PDET_EDEVICE, "overflow count exceeds the batch");
+  pdet_timing scratch_tm{};
+  pdet_timing& tm = timed ? timer().t : scratch_tm;
+  size_t smem = 0;
+  QArgs a = batch_args(ix, qc, ws, maxKL, smem);
+  bind_slots(ix, a, *ws.full);
+  // full-capacity slots: the lists hold every leaf, so none of these overflows
+  a.qmap = reinterpret_cast<const int32_t*>(ws.ovf.as<uint32_t>() + 1);
+  launch_chunks(ix, qc.precision, a, n_ovf, ws.full->nslots, smem, s, timed, tm);
+  ws.retried += n_ovf;
+  if (timed) tm.query_retried = n_ovf;
+}
 
 void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s) {
   if (qc.nq == 0) return;
   WorkspaceLease lease(ix);
   QueryWorkspace& ws = lease.get();
-  reserve_workspace(ix, ws, qc.nq, 0, s);
+  reserve_workspace(ix, ws, qc.nq, 0, s, true);
   const int maxKL = stage_params(ix, qc, ws);
   enqueue_query(ix, qc, ws, maxKL, s, timer().on);
+  retry_overflowed(ix, qc, ws, maxKL, s, timer().on);
   // the workspace goes back to the pool when this returns: wait for the kernels first
   PDET_HIP(hipStreamSynchronize(s));
 }

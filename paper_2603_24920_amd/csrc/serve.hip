@@ -24,6 +24,8 @@ struct pdet_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t nq = 0;
+  QueryConfig qc{};   // the captured batch (host arrays of k and c are not kept)
+  int maxKL = 0;
   ~pdet_plan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -291,8 +293,12 @@ pdet_status pdet_plan_create(const pdet_index* idx, const float* queries, int64_
     hipStream_t cs = nullptr;
     PDET_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     try {
-      reserve_workspace(*idx, plan->ws, nq, 0, cs);
+      reserve_workspace(*idx, plan->ws, nq, 0, cs, true);
       const int maxKL = stage_params(*idx, qc, plan->ws);
+      plan->qc = qc;
+      plan->qc.k_host = nullptr;
+      plan->qc.c_host = nullptr;
+      plan->maxKL = maxKL;
       PDET_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       try {
         enqueue_query(*idx, qc, plan->ws, maxKL, cs, false);
@@ -319,7 +325,10 @@ pdet_status pdet_plan_create(const pdet_index* idx, const float* queries, int64_
 pdet_status pdet_plan_launch(pdet_plan* plan, void* stream) {
   return guarded([&] {
     PDET_REQUIRE(plan, PDET_EINVAL, "NULL argument");
-    PDET_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    PDET_HIP(hipGraphLaunch(plan->exec, s));
+    // capped leaf lists: wait for the graph, answer overflowed queries again
+    retry_overflowed(*plan->ix, plan->qc, plan->ws, plan->maxKL, s, false);
   });
 }
 

@@ -25,7 +25,7 @@ EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_reserve", "pdet_info"
             "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
-            "pdet_server_get_stats", "pdet_server_free"]
+            "pdet_server_get_stats", "pdet_server_free", "pdet_set_list_cap"]
 
 
 class BuildParams(ctypes.Structure):
@@ -50,7 +50,8 @@ class IndexInfo(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [(f, c_double) for f in (
         "build_sample_ms", "build_sort_ms", "build_encode_ms", "build_tree_ms", "build_lowp_ms",
-        "query_project_ms", "query_rho_ms", "query_main_ms")] + [("query_main_launches", c_int64)]
+        "query_project_ms", "query_rho_ms", "query_main_ms")] + [("query_main_launches", c_int64),
+                                                           ("query_retried", c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -92,6 +93,7 @@ def lib() -> ctypes.CDLL:
         L.pdet_query.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams), c_void_p,
                                  c_void_p, c_void_p, c_void_p]
         L.pdet_reserve.argtypes = [c_void_p, c_int64, c_void_p]
+        L.pdet_set_list_cap.argtypes = [c_void_p, c_int64]
         L.pdet_free.argtypes = [c_void_p]
         L.pdet_free.restype = None
         L.pdet_info.argtypes = [c_void_p, POINTER(IndexInfo)]
@@ -121,7 +123,7 @@ def lib() -> ctypes.CDLL:
         for f in ("pdet_build", "pdet_query", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
                   "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
                   "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
-                  "pdet_server_get_stats"):
+                  "pdet_server_get_stats", "pdet_set_list_cap"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib
@@ -192,6 +194,10 @@ class Index:
     def reserve(self, nq: int, stream=None):
         """Size the query workspace for batches of up to nq queries (pdet_reserve)."""
         _check(lib().pdet_reserve(self._h, int(nq), _stream(stream)))
+
+    def set_list_cap(self, cap: int) -> None:
+        """Per-tree leaf-list capacity of the query slots (pdet_set_list_cap; 0: automatic)."""
+        _check(lib().pdet_set_list_cap(self._h, int(cap)))
 
     def info(self) -> dict:
         inf = IndexInfo()

@@ -187,3 +187,41 @@ def test_low_precision_copies_past_one_grid_sweep():
     rec = np.mean([len(np.intersect1d(a, b)) / w.k for a, b in zip(ids, f_ids.cpu().numpy())])
     print(f"[lowp-sweep] fp8 recall@{w.k} against float32: {rec:.3f}", flush=True)
     idx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_capped_leaf_lists_answer_overflowed_queries_again(env, precision):
+    """Query slots whose leaf lists hold only a few entries per tree (as a large index
+    gets to fit more slots): queries that overflow them, in the batched bound kernel or in
+    the per-query refinement of later rounds, are answered again with full-capacity slots,
+    so ids, distances and statistics equal the uncapped call, eagerly and in a plan."""
+    w, X, A, sid, idx, Q, Qd = env
+    ks, cs = uneven(len(Q), seed=3)
+    kw = dict(k=0, beta=0.05, r_min=3.0, k_per_query=ks, c_per_query=cs, precision=precision,
+              rescore=4)
+    keep = [0, 1, 2, 3, 4, 5, 7]          # word 6 is the query's device time
+    idx.set_tuning(3.0, 1)                # later rounds go through the refinement
+    ref_ids, ref_d, ref_st = idx.query(Qd, stats=True, **kw)
+    pdet.set_timing(True)
+    try:
+        for cap in (2, 16, 64):
+            idx.set_list_cap(cap)
+            ids, d, st = idx.query(Qd, stats=True, **kw)
+            retried = pdet.get_timing()["query_retried"]
+            print(f"[cap] {precision} cap={cap} retried={retried}/{len(Q)}", flush=True)
+            assert torch.equal(ids, ref_ids) and torch.equal(d, ref_d), cap
+            assert torch.equal(st[:, keep], ref_st[:, keep]), cap
+            if cap == 2:
+                assert retried > len(Q) // 2
+        idx.set_list_cap(16)
+        plan = idx.plan(Qd, stats=True, **kw)
+        for rep in range(2):
+            plan.ids.fill_(-7)
+            plan.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(plan.ids, ref_ids) and torch.equal(plan.dists, ref_d), rep
+            assert torch.equal(plan.qstats[:, keep], ref_st[:, keep]), rep
+        plan.close()
+    finally:
+        pdet.set_timing(False)
+        idx.set_list_cap(0)
