@@ -162,6 +162,17 @@ pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream);
  * concurrently with queries on the same index. cap < 0 -> PDET_EINVAL. */
 pdet_status pdet_set_list_cap(pdet_index* idx, int64_t cap);
 
+/* Device memory recycling. Not an operation of the method: freeing device blocks that
+ * kernels have touched and allocating them again is slow in the driver, and a process that
+ * rebuilds indexes or re-sizes query scratch would pay it on every cycle. Blocks of 32 MiB
+ * or more that the library releases (pdet_free, temporaries, re-sized scratch) are
+ * therefore kept, up to 60% of each device's memory, and reused for a later allocation of
+ * exactly the same size on the same device. Releasing a block waits for the device to be
+ * idle, as hipFree does. A failed allocation returns every cached block to the driver and
+ * tries once more. pdet_release_cache returns every cached block now (e.g. before handing
+ * the memory to another library); it must not run concurrently with other calls. */
+void pdet_release_cache(void);
+
 /* Description of a built index. */
 typedef struct {
   int64_t n, n_sample;

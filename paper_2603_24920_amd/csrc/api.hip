@@ -2,6 +2,7 @@
 // (encoding phase then indexing phase) and the query entry point.
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <limits>
 #include <new>
 
@@ -45,6 +46,81 @@ double gamma_p(double a, double x) {
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+// The block cache behind DevBuf (declared in common.h). Lives until the process ends, so
+// buffers released by static objects at exit still find it.
+struct BlockCache {
+  struct Block { void* p; size_t bytes; int dev; };
+  std::mutex mu;
+  std::vector<Block> blocks;
+  std::vector<size_t> held;    // per device
+  std::vector<size_t> cap;     // per device: 60% of its memory (0: not yet read)
+  size_t& at(std::vector<size_t>& v, int dev) {
+    if ((int)v.size() <= dev) v.resize((size_t)dev + 1, 0);
+    return v[(size_t)dev];
+  }
+};
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();
+  return *c;
+}
+}  // namespace
+
+bool cache_take(size_t bytes, void** p) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  for (size_t i = 0; i < c.blocks.size(); ++i) {
+    if (c.blocks[i].bytes == bytes && c.blocks[i].dev == dev) {
+      *p = c.blocks[i].p;
+      c.blocks.erase(c.blocks.begin() + (int64_t)i);
+      c.at(c.held, dev) -= bytes;
+      return true;
+    }
+  }
+  return false;
+}
+
+bool cache_give(void* p, size_t bytes, int dev) {
+  if (std::uncaught_exceptions() > 0) return false;   // error paths free at once
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != dev) return false;
+  BlockCache& c = block_cache();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    size_t& cp = c.at(c.cap, dev);
+    if (cp == 0) {
+      size_t total = 0;
+      if (hipDeviceTotalMem(&total, dev) != hipSuccess) return false;
+      cp = total / 10 * 6;
+    }
+    if (c.at(c.held, dev) + bytes > cp) return false;
+  }
+  // as hipFree does: no kernel may still use the block when it is handed out again
+  if (hipDeviceSynchronize() != hipSuccess) return false;
+  std::lock_guard<std::mutex> g(c.mu);
+  c.blocks.push_back({p, bytes, dev});
+  c.at(c.held, dev) += bytes;
+  return true;
+}
+
+void cache_flush() {
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  for (const auto& b : c.blocks) (void)hipFree(b.p);
+  c.blocks.clear();
+  std::fill(c.held.begin(), c.held.end(), 0);
+}
+
+size_t cache_held() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  return c.at(c.held, dev);
+}
 void clear_error() { g_last_error.clear(); }
 
 // Checks query arguments and fills per-query k and c (host) and the query configuration.
@@ -307,6 +383,8 @@ pdet_status pdet_set_list_cap(pdet_index* idx, int64_t cap) {
     idx->ws_free.clear();
   });
 }
+
+void pdet_release_cache(void) { cache_flush(); }
 
 void pdet_set_timing(int32_t on) { timer().on = on != 0; }
 

@@ -38,8 +38,21 @@ void set_error(const std::string& msg);
     if (!(cond)) throw ::pdet::Error{(status), (msg)};      \
   } while (0)
 
-// Device buffer owned by RAII; freed with hipFree. A view (view()) points into another
-// buffer and is never freed through itself.
+// Process-wide cache of large device blocks (api.hip). Freeing a block that kernels have
+// touched and allocating again costs the driver tens of milliseconds per GiB here, which a
+// process that rebuilds indexes or re-sizes query scratch pays on every cycle; blocks of at
+// least CACHE_MIN_BYTES are therefore kept on release and handed out again for a request of
+// exactly their size on the same device. A cached block is taken only after its device was
+// idle (as hipFree waits), so no kernel still uses it. hipMalloc failures flush the cache and
+// retry; pdet_release_cache() returns every cached block to the driver.
+constexpr size_t CACHE_MIN_BYTES = size_t(32) << 20;
+bool cache_take(size_t bytes, void** p);
+bool cache_give(void* p, size_t bytes, int device);
+void cache_flush();
+size_t cache_held();   // bytes cached for the current device
+
+// Device buffer owned by RAII; freed with hipFree (or kept by the block cache). A view
+// (view()) points into another buffer and is never freed through itself.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -48,13 +61,13 @@ struct DevBuf {
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned), dev(o.dev) {
     o.p = nullptr; o.bytes = 0; o.owned = true;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; bytes = o.bytes; owned = o.owned;
+      p = o.p; bytes = o.bytes; owned = o.owned; dev = o.dev;
       o.p = nullptr; o.bytes = 0; o.owned = true;
     }
     return *this;
@@ -63,7 +76,17 @@ struct DevBuf {
   void alloc(size_t b) {
     release();
     if (b == 0) return;
+    (void)hipGetDevice(&dev);
+    if (b >= CACHE_MIN_BYTES && cache_take(b, &p)) {
+      bytes = b;
+      return;
+    }
     hipError_t e = hipMalloc(&p, b);
+    if (e == hipErrorOutOfMemory && cache_held() > 0) {
+      (void)hipGetLastError();
+      cache_flush();
+      e = hipMalloc(&p, b);
+    }
     if (e != hipSuccess) {
       p = nullptr;
       throw Error{PDET_ENOMEM, "hipMalloc(" + std::to_string(b) + " bytes) failed: " +
@@ -78,12 +101,13 @@ struct DevBuf {
     owned = false;
   }
   void release() {
-    if (p && owned) (void)hipFree(p);
+    if (p && owned && !(bytes >= CACHE_MIN_BYTES && cache_give(p, bytes, dev))) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
     owned = true;
   }
   template <class T> T* as() const { return static_cast<T*>(p); }
+  int dev = 0;   // device of the allocation
 };
 
 // Pinned host buffer (hipHostMalloc), for asynchronous copies and graph memcpy nodes.

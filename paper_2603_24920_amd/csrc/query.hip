@@ -1130,6 +1130,7 @@ constexpr int64_t TARGET_SLOTS = 2048;
 // Least per-tree leaf-list capacity of a capped slot, and the full-capacity slots that
 // answer overflowed queries again.
 constexpr int64_t MIN_LIST_CAP = 16384;
+constexpr int64_t LIST_CAP_DIV = 16;
 constexpr int64_t RETRY_SLOTS = 16;
 
 int64_t total_leaves(const Index& ix) {
@@ -1175,10 +1176,11 @@ void alloc_slots(const Index& ix, QueryWorkspace& ws, int64_t want, int64_t cap,
 
 // Sizes the workspace for a batch of nq queries: per-query arrays, and as many query slots
 // (concurrent per-query scratch) as `budget` bytes allow (0: a third of free memory, at
-// most 24 GiB). Slots normally hold every leaf of every tree. With cap_lists, an index
-// whose full-capacity slots would number fewer than min(nq, TARGET_SLOTS) in that budget
-// caps the lists instead (at least MIN_LIST_CAP entries per tree; the default budget may
-// then grow to a third of free memory) and keeps RETRY_SLOTS full-capacity slots for the
+// most 24 GiB; memory held by the block cache counts as free). Slots normally hold every
+// leaf of every tree. With cap_lists, an index whose full-capacity slots would number fewer
+// than min(nq, TARGET_SLOTS) in that budget caps each tree's list at
+// max(MIN_LIST_CAP, nl_max / LIST_CAP_DIV) entries instead (the default budget may then
+// grow to a third of free memory) and keeps RETRY_SLOTS full-capacity slots for the
 // queries that overflow them. Allocation happens here, never during a launch sequence.
 void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t budget,
                        hipStream_t s, bool cap_lists) {
@@ -1190,7 +1192,7 @@ void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t b
     if (dflt) {
       size_t freeb = 0, totalb = 0;
       PDET_HIP(hipMemGetInfo(&freeb, &totalb));
-      avail = freeb + ws.bytes();
+      avail = freeb + ws.bytes() + cache_held();
       budget = std::min<size_t>(avail / 3, (size_t)24 << 30);
     }
     const int64_t target = std::max<int64_t>(1, std::min<int64_t>(nq, TARGET_SLOTS));
@@ -1202,21 +1204,21 @@ void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t b
         budget = budget > retry ? budget - retry : slot_bytes_at(ix, list_entries(ix, cap));
       }
     } else if (cap_lists && (int64_t)(budget / slot_bytes(ix)) < target) {
-      if (dflt) budget = std::max<size_t>(budget, avail / 3);
-      // full-capacity retry slots come out of the same budget
-      const size_t retry = (size_t)RETRY_SLOTS * slot_bytes(ix);
-      const size_t rest = budget > retry ? budget - retry : 0;
-      const size_t per = rest / (size_t)target;
-      const size_t fixed = slot_bytes_at(ix, 0);
-      int64_t c = per > fixed ? (int64_t)((per - fixed) / 24 / (size_t)ix.L) : 0;
-      c = std::max<int64_t>(c, MIN_LIST_CAP);
+      // The capacity depends on the index alone (a sixteenth of the largest tree's leaves,
+      // at least MIN_LIST_CAP), so repeated calls size the same blocks.
+      const int64_t c = std::max<int64_t>(MIN_LIST_CAP, nl_all / LIST_CAP_DIV);
       if (c < nl_all) {
+        if (dflt) budget = std::max<size_t>(budget, avail / 3);
+        // full-capacity retry slots come out of the same budget
+        const size_t retry = (size_t)RETRY_SLOTS * slot_bytes(ix);
         cap = c;
-        budget = rest;
+        budget = budget > retry ? budget - retry : 0;
       }
     }
     const size_t per_slot = slot_bytes_at(ix, list_entries(ix, cap));
-    const int64_t slots_cap = std::max<int64_t>(1, (int64_t)(budget / per_slot));
+    int64_t slots_cap = std::max<int64_t>(1, (int64_t)(budget / per_slot));
+    // capped slots: TARGET_SLOTS fill the device; more would only change the block sizes
+    if (cap < nl_all) slots_cap = std::min<int64_t>(slots_cap, TARGET_SLOTS);
     const int64_t want = std::max<int64_t>(1, std::min<int64_t>(nq, slots_cap));
     if (want > ws.nslots || cap != ws.list_cap) alloc_slots(ix, ws, want, cap, s);
     ws.nslots_max = slots_cap;

@@ -364,7 +364,7 @@ pdet_status pdet_server_create(const pdet_index* idx, const pdet_server_params* 
     if (budget == 0) {
       size_t freeb = 0, totalb = 0;
       PDET_HIP(hipMemGetInfo(&freeb, &totalb));
-      budget = freeb / 4;
+      budget = (freeb + cache_held()) / 4;
     }
     // admission: the batch size the per-lane share of the budget holds in query slots
     const size_t per_lane = budget / p->lanes;

@@ -25,7 +25,8 @@ EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_reserve", "pdet_info"
             "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
-            "pdet_server_get_stats", "pdet_server_free", "pdet_set_list_cap"]
+            "pdet_server_get_stats", "pdet_server_free", "pdet_set_list_cap",
+            "pdet_release_cache"]
 
 
 class BuildParams(ctypes.Structure):
@@ -94,6 +95,8 @@ def lib() -> ctypes.CDLL:
                                  c_void_p, c_void_p, c_void_p]
         L.pdet_reserve.argtypes = [c_void_p, c_int64, c_void_p]
         L.pdet_set_list_cap.argtypes = [c_void_p, c_int64]
+        L.pdet_release_cache.argtypes = []
+        L.pdet_release_cache.restype = None
         L.pdet_free.argtypes = [c_void_p]
         L.pdet_free.restype = None
         L.pdet_info.argtypes = [c_void_p, POINTER(IndexInfo)]
@@ -142,6 +145,11 @@ def epsilon(K: int, L: int) -> float:
 def set_timing(on: bool) -> None:
     """Record per-kernel-family device time (HIP events) for this thread's calls."""
     lib().pdet_set_timing(1 if on else 0)
+
+
+def release_cache() -> None:
+    """Return the library's cached device blocks to the driver (pdet_release_cache)."""
+    lib().pdet_release_cache()
 
 
 def get_timing() -> dict:

@@ -225,3 +225,31 @@ def test_capped_leaf_lists_answer_overflowed_queries_again(env, precision):
     finally:
         pdet.set_timing(False)
         idx.set_list_cap(0)
+
+
+def test_recycled_device_blocks_give_the_same_index_and_results():
+    """Indexes large enough that their buffers, build temporaries and query scratch go
+    through the library's block cache: a rebuild on recycled blocks (stale contents) gives
+    the same breakpoints, codes, leaves and neighbours, in FP32 and BF16."""
+    w = wl.SIFT_LIKE_1M.scaled(n=600_000)
+    X, A, sid = w.data(), w.proj(), w.sample()
+    Qd = torch.from_numpy(w.queries(500)).cuda()
+    print(f"\n[cache] n={w.n} d={w.d}", flush=True)
+    Xd = torch.from_numpy(X).cuda()
+    kw = dict(k=w.k, c=w.c, beta=0.002, r_min=30.0)
+    ref = None
+    for rep in range(3):
+        idx = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=("bf16",))
+        got = dict(B=idx.export(pdet.X_BREAKPOINTS), codes=idx.export(pdet.X_CODES),
+                   leaves=idx.export(pdet.X_LEAF_COUNT, tree=3),
+                   f32=[t.cpu() for t in idx.query(Qd, **kw)],
+                   bf16=[t.cpu() for t in idx.query(Qd, precision="bf16", rescore=4, **kw)])
+        idx.close()
+        if ref is None:
+            ref = got
+            continue
+        for key in ("B", "codes", "leaves"):
+            assert np.array_equal(got[key], ref[key]), (rep, key)
+        for key in ("f32", "bf16"):
+            assert all(torch.equal(a, b) for a, b in zip(got[key], ref[key])), (rep, key)
+    pdet.release_cache()

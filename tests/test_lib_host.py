@@ -85,6 +85,7 @@ def test_null_handles_are_rejected():
     assert pdet.lib().pdet_export(None, 0, 0, None, 0) == pdet.PDET_EINVAL
     assert pdet.lib().pdet_reserve(None, 16, None) == pdet.PDET_EINVAL
     assert pdet.lib().pdet_set_list_cap(None, 0) == pdet.PDET_EINVAL
+    pdet.release_cache()   # nothing cached on a host without a device: no device call
     pdet.lib().pdet_free(None)
 
 
