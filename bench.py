@@ -35,7 +35,8 @@ METRIC = "index build Mpts/s + QPS at recall@10>=0.9 (FP32 vs BF16/FP8 verify), 
 HBM_PEAK_GBS = 8000.0
 BETA_LADDER = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 5e-4, 2e-4, 1e-4, 5e-5, 2e-5, 1e-5)
 PROFILE_PMC = os.path.join(ROOT, "profiles", "q_main_traffic.json")
-BIG_N = 20_000_000            # above this: threaded generation, brute-force ground truth
+BIG_N = 20_000_000            # above this: brute-force ground truth
+GEN_THREADS_N = 4_000_000     # from this size: data drawn in parallel chunks (same values)
 MAX_CAL_CANDIDATES = 2e5      # largest beta * n tried by the recall calibration
 
 
@@ -141,7 +142,7 @@ def main():
         if big and (done % 8 == 0 or done == total):
             log(f"[bench] generating {w.name}: {done}/{total} chunks ({time.time() - t0:.0f}s)")
 
-    X = w.data(threads=16 if big else 1, progress=gen_progress)
+    X = w.data(threads=16 if w.n >= GEN_THREADS_N else 1, progress=gen_progress)
     A, sid, Q = w.proj(), w.sample(), w.queries(nq)
     log(f"[bench] generated {w.name}: n={w.n} d={w.d} nq={nq} ({time.time() - t0:.1f}s)")
     dev = torch.device("cuda:0")
