@@ -151,10 +151,11 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
 pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream);
 
 /* Per-tree capacity of the admitted-leaf lists in each query slot of pdet_query,
- * pdet_reserve and plans (servers always hold every leaf). Not an operation of the
+ * pdet_reserve, plans and servers created after the call. Not an operation of the
  * method: it trades slot memory for concurrency. 0 (the default) holds every leaf unless
  * the index is so large that fewer than min(nq, 2048) such slots fit the workspace budget;
- * then the lists are capped at what 2048 slots allow (at least 16384 entries per tree).
+ * then each tree's list is capped at max(16384, a sixteenth of the largest tree's leaves)
+ * entries, and at most 2048 slots are used.
  * cap > 0 sets the capacity (trees with fewer leaves hold all of theirs). A query whose
  * lists would exceed the capacity is answered again, after the batch, with slots that
  * hold every leaf; results are the same either way, and pdet_get_timing counts such
@@ -278,8 +279,10 @@ void pdet_plan_free(pdet_plan* plan);
  * arrive while others run are admitted as lanes free up. wait() blocks until a request is
  * done and returns its k ids and distances (host) and its latency (submit to completion).
  * A result is the same whatever batch it was served in (each query has its own
- * workgroup). memory_budget 0 takes a quarter of the free device memory; r_min <= 0 takes
- * the tuned value; eps <= 0 takes Eq. 2.
+ * workgroup). Slots of a large index hold capped leaf lists (see pdet_set_list_cap); a
+ * batch whose queries overflowed them answers those again on its lane before its results
+ * are returned. memory_budget 0 takes a quarter of the free device memory; r_min <= 0
+ * takes the tuned value; eps <= 0 takes Eq. 2.
  */
 typedef struct pdet_server pdet_server;
 typedef struct {

@@ -84,6 +84,9 @@ struct pdet_server {
     PinnedBuf hq, hids, hdists;
     std::vector<int64_t> batch;
     std::vector<int64_t> off;
+    QueryConfig qc{};   // the batch in flight (host arrays of k and c are not kept)
+    int maxKL = 0;
+    int64_t tot = 0;    // its output entries
     bool busy = false;
     ~Lane() {
       if (ev) (void)hipEventDestroy(ev);
@@ -131,6 +134,19 @@ void pdet_server::run() {
         const hipError_t e = hipEventQuery(ln.ev);
         if (e == hipErrorNotReady) continue;
         PDET_HIP(e);
+        if (ln.ws.capped()) {
+          // capped leaf lists: queries that overflowed them are answered again, then the
+          // outputs are copied once more (a rare, blocking path of this lane)
+          const int64_t before = ln.ws.retried;
+          retry_overflowed(*ix, ln.qc, ln.ws, ln.maxKL, ln.s, false);
+          if (ln.ws.retried != before) {
+            PDET_HIP(hipMemcpyAsync(ln.hids.p, ln.dids.p, (size_t)ln.tot * 8,
+                                    hipMemcpyDeviceToHost, ln.s));
+            PDET_HIP(hipMemcpyAsync(ln.hdists.p, ln.ddists.p, (size_t)ln.tot * 4,
+                                    hipMemcpyDeviceToHost, ln.s));
+            PDET_HIP(hipStreamSynchronize(ln.s));
+          }
+        }
         const double t = now_ms();
         {
           std::lock_guard<std::mutex> g(mu);
@@ -195,6 +211,11 @@ void pdet_server::run() {
         const int maxKL = stage_params(*ix, qc, ln.ws);
         enqueue_query(*ix, qc, ln.ws, maxKL, ln.s, false);
         const int64_t tot = ln.off.back() + k.back();
+        ln.qc = qc;
+        ln.qc.k_host = nullptr;
+        ln.qc.c_host = nullptr;
+        ln.maxKL = maxKL;
+        ln.tot = tot;
         PDET_HIP(hipMemcpyAsync(ln.hids.p, ln.dids.p, (size_t)tot * 8, hipMemcpyDeviceToHost, ln.s));
         PDET_HIP(hipMemcpyAsync(ln.hdists.p, ln.ddists.p, (size_t)tot * 4, hipMemcpyDeviceToHost,
                                 ln.s));
@@ -367,14 +388,14 @@ pdet_status pdet_server_create(const pdet_index* idx, const pdet_server_params* 
       budget = (freeb + cache_held()) / 4;
     }
     // admission: the batch size the per-lane share of the budget holds in query slots
+    // (capped leaf lists for a large index, as in pdet_query)
     const size_t per_lane = budget / p->lanes;
-    sv->cap = std::max<int64_t>(1, std::min<int64_t>(p->max_batch,
-                                                     (int64_t)(per_lane / slot_bytes(*idx))));
     for (int l = 0; l < p->lanes; ++l) {
       auto ln = std::make_unique<pdet_server::Lane>();
       PDET_HIP(hipStreamCreateWithFlags(&ln->s, hipStreamNonBlocking));
       PDET_HIP(hipEventCreateWithFlags(&ln->ev, hipEventDisableTiming));
-      reserve_workspace(*idx, ln->ws, sv->cap, per_lane, ln->s);
+      reserve_workspace(*idx, ln->ws, p->max_batch, per_lane, ln->s, true);
+      if (l == 0) sv->cap = std::max<int64_t>(1, std::min<int64_t>(p->max_batch, ln->ws.nslots));
       ln->dq.alloc((size_t)sv->cap * idx->d * 4);
       ln->hq.alloc((size_t)sv->cap * idx->d * 4);
       ln->dids.alloc((size_t)sv->cap * p->k_max * 8);

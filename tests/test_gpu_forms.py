@@ -119,8 +119,11 @@ def test_plan_low_precision_equals_eager(env):
     plan.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
-def test_server_results_same_alone_and_in_the_mix(env, precision):
+@pytest.mark.parametrize("precision,list_cap", [("fp32", 0), ("bf16", 0), ("fp8", 0),
+                                                ("fp32", 4), ("bf16", 4)])
+def test_server_results_same_alone_and_in_the_mix(env, precision, list_cap):
+    """list_cap 4: the lanes' slots hold 4 leaves per tree, so most batches answer their
+    queries again on full-capacity slots before returning them."""
     w, X, A, sid, idx, Q, Qd = env
     ks, cs = uneven(len(Q), seed=9)
     ks = np.minimum(ks, 50)
@@ -128,7 +131,12 @@ def test_server_results_same_alone_and_in_the_mix(env, precision):
                                precision=precision, rescore=4)
     ref_ids, ref_d = ref_ids.cpu().numpy(), ref_d.cpu().numpy()
     off = np.concatenate([[0], np.cumsum(ks)])
-    sv = idx.server(max_batch=16, lanes=2, k_max=50, precision=precision, beta=0.05, r_min=3.0)
+    idx.set_list_cap(list_cap)
+    try:
+        sv = idx.server(max_batch=16, lanes=2, k_max=50, precision=precision, beta=0.05,
+                        r_min=3.0)
+    finally:
+        idx.set_list_cap(0)
     # alone: one request in flight at a time
     alone = []
     for qi in range(12):
