@@ -118,3 +118,14 @@ def test_build_rejects_a_sample_too_large_for_one_sort_dispatch():
                                ctypes.byref(h))
     assert st == pdet.PDET_EUNSUPPORTED and h.value is None
     assert "2^32" in pdet.lib().pdet_last_error().decode()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; --gpus 2 exits with status 2 and says why, before it
+    imports torch or touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
