@@ -145,9 +145,11 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
  * lists, thresholds) for batches of up to nq queries, so that a later pdet_query of at most
  * nq queries allocates nothing. Not an operation of the method itself: the search of
  * Algorithm 5 needs this scratch, and a caller that serves a resident index wants it sized
- * once, before the first batch. Device memory is taken with hipMalloc and kept until
- * pdet_free; at most a third of free device memory (and 24 GiB) is used, so large batches
- * are then run in chunks of query slots. Waits for `stream`. nq < 0 -> PDET_EINVAL. */
+ * once, before the first batch. Device memory is taken with hipMalloc (or from the block
+ * cache, see pdet_release_cache) and kept until pdet_free; at most a third of free device
+ * memory (and 24 GiB, unless the index is large enough for capped leaf lists, see
+ * pdet_set_list_cap) is used, so large batches are then run in chunks of query slots.
+ * Waits for `stream`. nq < 0 -> PDET_EINVAL. */
 pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream);
 
 /* Per-tree capacity of the admitted-leaf lists in each query slot of pdet_query,
