@@ -1098,6 +1098,14 @@ __global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(6))) void q_
   q_main_body<PREC>(a);
 }
 
+// The same search for batches with long candidate walks (see use_long_walk): eight
+// workgroups per CU hide more of the walk's latency than the register spills cost there,
+// while short searches run faster at six (measured on 1M and 100M points).
+template <int PREC>
+__global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(8))) void q_main_lowp_long(QArgs a) {
+  q_main_body<PREC>(a);
+}
+
 }  // namespace
 
 // Per-query parameters of a batch into the workspace's pinned staging arrays.
@@ -1335,10 +1343,30 @@ QArgs batch_args(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int
   return a;
 }
 
+// Candidate target beta * n from which the low-precision search runs as q_main_lowp_long,
+// if that kernel then fits more workgroups per CU (a large top-k buffer or a long query row
+// can make LDS the limit instead).
+constexpr double LONG_WALK_T = 50000.0;
+
+template <int PREC>
+bool use_long_walk(const Index& ix, const QueryConfig& qc, size_t smem) {
+  if (qc.beta * (double)ix.n < LONG_WALK_T) return false;
+  int wg_long = 0, wg_short = 0;
+  PDET_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &wg_long, reinterpret_cast<const void*>(&q_main_lowp_long<PREC>), QM, smem));
+  PDET_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &wg_short, reinterpret_cast<const void*>(&q_main_lowp<PREC>), QM, smem));
+  return wg_long > wg_short;
+}
+
 // Per chunk of `nslots` queries of the nq the arguments select: thresholds, round
 // indices, search.
-void launch_chunks(const Index& ix, int precision, QArgs a, int64_t nq, int64_t nslots,
+void launch_chunks(const Index& ix, const QueryConfig& qc, QArgs a, int64_t nq, int64_t nslots,
                    size_t smem, hipStream_t s, bool timed, pdet_timing& tm) {
+  const bool long_walk =
+      qc.precision == PDET_BF16       ? use_long_walk<PDET_BF16>(ix, qc, smem)
+      : qc.precision == PDET_FP8_E4M3 ? use_long_walk<PDET_FP8_E4M3>(ix, qc, smem)
+                                      : false;
   for (int64_t q0 = 0; q0 < nq; q0 += nslots) {
     a.q0 = q0;
     a.nslots = (int)std::min<int64_t>(nslots, nq - q0);
@@ -1356,15 +1384,22 @@ void launch_chunks(const Index& ix, int precision, QArgs a, int64_t nq, int64_t 
       sp.finish();
     }
     Span sp(s, timed ? &tm.query_main_ms : nullptr);
-    switch (precision) {
+    switch (qc.precision) {
       case PDET_FP32:
         hipLaunchKernelGGL(q_main_f32, dim3(a.nslots), dim3(QM), smem, s, a);
         break;
       case PDET_BF16:
-        hipLaunchKernelGGL(q_main_lowp<PDET_BF16>, dim3(a.nslots), dim3(QM), smem, s, a);
+        if (long_walk)
+          hipLaunchKernelGGL(q_main_lowp_long<PDET_BF16>, dim3(a.nslots), dim3(QM), smem, s, a);
+        else
+          hipLaunchKernelGGL(q_main_lowp<PDET_BF16>, dim3(a.nslots), dim3(QM), smem, s, a);
         break;
       default:
-        hipLaunchKernelGGL(q_main_lowp<PDET_FP8_E4M3>, dim3(a.nslots), dim3(QM), smem, s, a);
+        if (long_walk)
+          hipLaunchKernelGGL(q_main_lowp_long<PDET_FP8_E4M3>, dim3(a.nslots), dim3(QM), smem, s,
+                             a);
+        else
+          hipLaunchKernelGGL(q_main_lowp<PDET_FP8_E4M3>, dim3(a.nslots), dim3(QM), smem, s, a);
         break;
     }
     PDET_HIP(hipGetLastError());
@@ -1402,7 +1437,7 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
   size_t smem = 0;
   QArgs a = batch_args(ix, qc, ws, maxKL, smem);
   bind_slots(ix, a, ws);
-  launch_chunks(ix, qc.precision, a, nq, ws.nslots, smem, s, timed, tm);
+  launch_chunks(ix, qc, a, nq, ws.nslots, smem, s, timed, tm);
 }
 
 void retry_overflowed(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
@@ -1421,7 +1456,7 @@ void retry_overflowed(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws
   bind_slots(ix, a, *ws.full);
   // full-capacity slots: the lists hold every leaf, so none of these overflows
   a.qmap = reinterpret_cast<const int32_t*>(ws.ovf.as<uint32_t>() + 1);
-  launch_chunks(ix, qc.precision, a, n_ovf, ws.full->nslots, smem, s, timed, tm);
+  launch_chunks(ix, qc, a, n_ovf, ws.full->nslots, smem, s, timed, tm);
   ws.retried += n_ovf;
   if (timed) tm.query_retried = n_ovf;
 }
