@@ -1344,8 +1344,9 @@ QArgs batch_args(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int
 }
 
 // Candidate target beta * n from which the low-precision search runs as q_main_lowp_long,
-// if that kernel then fits more workgroups per CU (a large top-k buffer or a long query row
-// can make LDS the limit instead).
+// if that kernel then fits at least a third more workgroups per CU (a large top-k buffer or
+// a long query row can make LDS the limit instead; seven against six did not pay for the
+// spills on 10M points of d = 256).
 constexpr double LONG_WALK_T = 50000.0;
 
 template <int PREC>
@@ -1356,7 +1357,7 @@ bool use_long_walk(const Index& ix, const QueryConfig& qc, size_t smem) {
       &wg_long, reinterpret_cast<const void*>(&q_main_lowp_long<PREC>), QM, smem));
   PDET_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &wg_short, reinterpret_cast<const void*>(&q_main_lowp<PREC>), QM, smem));
-  return wg_long > wg_short;
+  return 3 * wg_long >= 4 * wg_short;
 }
 
 // Per chunk of `nslots` queries of the nq the arguments select: thresholds, round
