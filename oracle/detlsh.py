@@ -32,6 +32,10 @@ is silent or ambiguous are stated where they are used:
   checked after every admitted leaf; stop rule B (at least k points of S within
   c*r) after all L trees of a round. Leaves admitted in an earlier round are
   not admitted again. Bounds are compared squared: LB^2 <= (eps*r)^2.
+* Literal query (Algorithms 3 and 4, and Algorithm 5 as printed): a leaf is pruned
+  when its lower bound exceeds r', taken whole when its upper bound is at most r',
+  and otherwise only its points at projected distance smaller than r' (strict, as
+  Algorithm 3 words it) are taken; stop rule A is checked once per tree.
 * Top-k: smallest (distance, id), returned in ascending order.
 """
 from __future__ import annotations
@@ -278,6 +282,10 @@ class QueryResult:
     leaves: int               # admitted leaves
     cand: np.ndarray          # int64 [|S|]: S in insertion order
     radius: float             # r of the last round
+    trace: list = dataclasses.field(default_factory=list)
+    # one (round, tree, leaf ordinal, LB^2, new points) record per admitted leaf, in
+    # admission order (the optimised query); the literal query records one
+    # (round, tree, -1, eps*r, new points) per range query instead
 
 
 def radius_ladder(r_min: float, c: float, rounds: int):
@@ -286,6 +294,10 @@ def radius_ladder(r_min: float, c: float, rounds: int):
     for _ in range(rounds):
         yield r
         r = c * r
+
+
+def _dist(X, ids, q64):
+    return np.sqrt(((np.asarray(X)[ids].astype(np.float64) - q64) ** 2).sum(axis=1))
 
 
 def query(index: Index, X, q, k: int, c: float, beta: float, r_min: float, eps: float,
@@ -297,7 +309,7 @@ def query(index: Index, X, q, k: int, c: float, beta: float, r_min: float, eps: 
     q64 = np.asarray(q, dtype=np.float64)
     qp = q64 @ index.A
     inS = np.zeros(n, dtype=bool)
-    cand, cdist = [], []
+    cand, cdist, trace = [], [], []
     n_s = 0
     leaves = 0
     prev_t2 = -1.0
@@ -315,25 +327,123 @@ def query(index: Index, X, q, k: int, c: float, beta: float, r_min: float, eps: 
                 leaves += 1
                 ids = tr.perm[tr.leaf_start[leaf]:tr.leaf_start[leaf] + tr.leaf_count[leaf]]
                 new = ids[~inS[ids]]
+                trace.append((rho, i, int(leaf), float(lb2[leaf]), len(new)))
                 if len(new):
                     inS[new] = True
                     n_s += len(new)
                     cand.append(new)
-                    cdist.append(np.sqrt(((X[new].astype(np.float64) - q64) ** 2).sum(axis=1)))
+                    cdist.append(_dist(X, new, q64))
                 if n_s >= T:
-                    return _finish(cand, cdist, k, rho + 1, "A", leaves, r)
+                    return _finish(cand, cdist, k, rho + 1, "A", leaves, r, trace)
         if n_s >= k:
             alld = np.concatenate(cdist)
             if np.partition(alld, k - 1)[k - 1] <= c * r:
-                return _finish(cand, cdist, k, rho + 1, "B", leaves, r)
+                return _finish(cand, cdist, k, rho + 1, "B", leaves, r, trace)
         prev_t2 = t2
     raise RuntimeError("radius ladder exhausted")
 
 
-def _finish(cand, cdist, k, rounds, stop, leaves, r) -> QueryResult:
+def _finish(cand, cdist, k, rounds, stop, leaves, r, trace=()) -> QueryResult:
     allc, alld = np.concatenate(cand), np.concatenate(cdist)
     o = np.lexsort((allc, alld))[:k]
-    return QueryResult(allc[o], alld[o], rounds, len(allc), stop, leaves, allc, r)
+    return QueryResult(allc[o], alld[o], rounds, len(allc), stop, leaves, allc, r, list(trace))
+
+
+# ------------------------------------------------ literal query (Algorithms 3 and 4)
+def range_query_literal(index: Index, X, i: int, qp_i: np.ndarray, r_prime: float):
+    """DET Range Query on tree i (Algorithm 3, as the query phase describes it).
+
+    Leaves whose lower bound exceeds r' are pruned (a pruned inner node prunes every
+    leaf below it, and bounds only tighten towards the leaves, so testing the leaves
+    gives the same set). A leaf whose upper bound is at most r' contributes all of its
+    points; a leaf with LB <= r' < UB contributes the points whose projected distance
+    to q' is smaller than r'. Projections are recomputed from X in FP64 (Eq. 1).
+    Returns (ids ascending, leaves examined, leaves taken whole)."""
+    tr = index.trees[i]
+    lo, hi = index.boxes[i]
+    K = index.K
+    qp_i = np.asarray(qp_i, dtype=np.float64)
+    lb2 = lower_bound_sq(qp_i, lo, hi)
+    ub2 = upper_bound_sq(qp_i, lo, hi)
+    r2 = r_prime * r_prime
+    out, examined, whole = [], 0, 0
+    A_i = index.A[:, i * K:(i + 1) * K]
+    for leaf in range(tr.nl):
+        if lb2[leaf] > r2:
+            continue
+        examined += 1
+        ids = tr.perm[tr.leaf_start[leaf]:tr.leaf_start[leaf] + tr.leaf_count[leaf]]
+        if ub2[leaf] <= r2:
+            whole += 1
+            out.append(ids)
+            continue
+        h = np.asarray(X)[ids].astype(np.float64) @ A_i
+        dist2 = ((h - qp_i[None, :]) ** 2).sum(axis=1)
+        out.append(ids[dist2 < r2])
+    ids = np.sort(np.concatenate(out)) if out else np.empty(0, dtype=np.int64)
+    return ids.astype(np.int64), examined, whole
+
+
+def rc_ann_query(index: Index, X, q, c: float, r: float, beta: float, eps: float):
+    """(r,c)-ANN query (Algorithm 4): range queries at eps*r tree by tree; once
+    |S| >= beta*n + 1 the point of S closest to q is returned; after all L trees the
+    closest point of S is returned if some point of S lies within c*r, else None.
+    Returns (id or None, distance or None, |S|, trees queried)."""
+    n = index.n
+    T1 = math.ceil(beta * n) + 1
+    q64 = np.asarray(q, dtype=np.float64)
+    qp = q64 @ index.A
+    S = np.empty(0, dtype=np.int64)
+
+    def closest(ids):
+        d = _dist(X, ids, q64)
+        o = np.lexsort((ids, d))[0]
+        return int(ids[o]), float(d[o])
+
+    for i in range(index.L):
+        Si, _, _ = range_query_literal(index, X, i, qp[i * index.K:(i + 1) * index.K], eps * r)
+        S = np.union1d(S, Si)
+        if len(S) >= T1:
+            return (*closest(S), len(S), i + 1)
+    if len(S) and np.any(_dist(X, S, q64) <= c * r):
+        return (*closest(S), len(S), index.L)
+    return None, None, len(S), index.L
+
+
+def query_literal(index: Index, X, q, k: int, c: float, beta: float, r_min: float, eps: float,
+                  max_rounds: int = 255) -> QueryResult:
+    """c^2-k-ANN query with the literal range query (Algorithm 5 as printed, without the
+    optimisations of the query-phase self-evaluation): every round re-runs Algorithm 3 on
+    each tree at eps*r, S is their union, stop rule A (|S| >= beta*n + k) is checked
+    after each tree, stop rule B (k points of S within c*r) after all L trees."""
+    X = np.asarray(X)
+    n = index.n
+    T = math.ceil(beta * n) + k
+    q64 = np.asarray(q, dtype=np.float64)
+    qp = q64 @ index.A
+    inS = np.zeros(n, dtype=bool)
+    cand, cdist, trace = [], [], []
+    n_s = 0
+    examined = 0
+    for rho, r in enumerate(radius_ladder(r_min, c, max_rounds)):
+        for i in range(index.L):
+            Si, ex, _ = range_query_literal(index, X, i, qp[i * index.K:(i + 1) * index.K],
+                                            eps * r)
+            examined += ex
+            new = Si[~inS[Si]]
+            trace.append((rho, i, -1, eps * r, len(new)))
+            if len(new):
+                inS[new] = True
+                n_s += len(new)
+                cand.append(new)
+                cdist.append(_dist(X, new, q64))
+            if n_s >= T:
+                return _finish(cand, cdist, k, rho + 1, "A", examined, r, trace)
+        if n_s >= k:
+            alld = np.concatenate(cdist)
+            if np.partition(alld, k - 1)[k - 1] <= c * r:
+                return _finish(cand, cdist, k, rho + 1, "B", examined, r, trace)
+    raise RuntimeError("radius ladder exhausted")
 
 
 # ---------------------------------------------------------------- brute force

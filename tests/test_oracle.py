@@ -293,22 +293,33 @@ def _leaf_lb2(idx, q):
     return out
 
 
+def _leaf_keys(idx, q, i):
+    """(LB^2, leaf ordinal) of every leaf of tree i for query q."""
+    qp = np.asarray(q, dtype=np.float64) @ idx.A
+    lo, hi = idx.boxes[i]
+    return oracle.lower_bound_sq(qp[i * idx.K:(i + 1) * idx.K], lo, hi)
+
+
 def test_candidate_set_closed_form(small_index):
     """S is the union over the admitted prefix of (round, tree) steps: before step
     (rho, i), o is in S iff LB_{i'}(o) <= (eps r_rho)^2 for some i' < i, or
-    LB_{i'}(o) <= (eps r_{rho-1})^2 for some i'. Stop rule A fires on the first leaf
-    that lifts |S| to T."""
+    LB_{i'}(o) <= (eps r_{rho-1})^2 for some i'. Within a step the admitted leaves are
+    the qualifying leaves in ascending (LB^2, ordinal) order (Section 6.2.2), all of them
+    unless stop rule A fires; stop rule A fires on the first leaf that lifts |S| to T
+    (the cut is minimal); stop rule B fires in the first round whose k-th distance in S
+    is within c*r (Algorithm 5), never earlier."""
     w, X, idx = small_index
     eps = oracle.epsilon(w.K, w.L)
     Q = w.queries(12)
-    for beta, r_min in ((0.05, 2.0), (0.2, 4.0), (0.01, 1.0)):
-        T = math.ceil(beta * len(X)) + 10
+    k, c = 10, 1.5
+    for beta, r_min in ((0.05, 2.0), (0.2, 4.0), (0.01, 1.0), (0.0, 0.5)):
+        T = math.ceil(beta * len(X)) + k
         for q in Q:
-            res = oracle.query(idx, X, q, 10, 1.5, beta, r_min, eps)
+            res = oracle.query(idx, X, q, k, c, beta, r_min, eps)
             lb = _leaf_lb2(idx, q)
             S = set(res.cand.tolist())
             assert len(S) == res.n_cand
-            ladder = list(oracle.radius_ladder(r_min, 1.5, res.rounds))
+            ladder = list(oracle.radius_ladder(r_min, c, res.rounds))
             t2 = [(eps * r) ** 2 for r in ladder]
             if res.stop == "B":
                 want = set(np.nonzero(lb.min(axis=0) <= t2[-1])[0].tolist())
@@ -320,11 +331,159 @@ def test_candidate_set_closed_form(small_index):
                 assert set(np.nonzero(before)[0].tolist()) <= S
                 within = set(np.nonzero(lb.min(axis=0) <= t2[-1])[0].tolist())
                 assert S <= within
+                # minimal cut: without the last admitted leaf's new points |S| < T
+                assert len(S) - res.trace[-1][4] < T
+            # the trace accounts for S exactly
+            assert sum(t[4] for t in res.trace) == len(S) and len(res.trace) == res.leaves
+            # admission per step: a prefix (all of it except at the stop cut) of the step's
+            # qualifying leaves sorted by (LB^2, ordinal)
+            steps = {}
+            for rho, i, leaf, l2, nn in res.trace:
+                steps.setdefault((rho, i), []).append((leaf, l2))
+            last = (res.trace[-1][0], res.trace[-1][1]) if res.trace else None
+            for rho in range(res.rounds):
+                for i in range(w.L):
+                    keys = _leaf_keys(idx, q, i)
+                    lo_t = t2[rho - 1] if rho > 0 else -1.0
+                    qual = np.nonzero((keys <= t2[rho]) & (keys > lo_t))[0]
+                    qual = [int(x) for x in qual[np.lexsort((qual, keys[qual]))]]
+                    got = [leaf for leaf, _ in steps.get((rho, i), [])]
+                    for leaf, l2 in steps.get((rho, i), []):
+                        assert l2 == keys[leaf]
+                    if res.stop == "A" and (rho, i) == last:
+                        assert got == qual[:len(got)] and len(got) >= 1
+                    elif res.stop == "A" and (rho, i) > last:
+                        assert got == []
+                    else:
+                        assert got == qual, (rho, i)
+            # stop rule B never held at the end of an earlier round, and holds at the end
+            # of the last round when it is the rule that fired
+            Xq = np.sqrt(((X.astype(np.float64) - q.astype(np.float64)) ** 2).sum(axis=1))
+            for rho in range(res.rounds):
+                ids_rho = [t for t in res.trace if t[0] <= rho]
+                n_rho = sum(t[4] for t in ids_rho)
+                members = res.cand[:n_rho]
+                if rho < res.rounds - 1 or res.stop == "B":
+                    holds = len(members) >= k and np.sort(Xq[members])[k - 1] <= c * ladder[rho]
+                    assert holds == (rho == res.rounds - 1 and res.stop == "B"), (rho, res.stop)
             # results are the top-k of S by (distance, id)
             cand = np.array(sorted(S))
             dd = np.sqrt(((X[cand].astype(np.float64) - q.astype(np.float64)) ** 2).sum(axis=1))
             o = np.lexsort((cand, dd))[:10]
             np.testing.assert_array_equal(res.ids, cand[o])
+
+
+def _golden_index():
+    g = golden("query_control_flow.json")
+    X = np.array(g["points"], dtype=np.float32)
+    A = np.eye(2, dtype=np.float32)
+    B = np.array(g["B"], dtype=np.float64)
+    idx = oracle.build_index(X, A, np.arange(len(X)), g["L"], g["K"], g["Nr"], g["max_leaf"], B=B)
+    return g, X, idx
+
+
+def test_golden_trees_and_bounds():
+    g, X, idx = _golden_index()
+    q = np.array(g["q"])
+    for i, want in enumerate(g["trees"]):
+        t = idx.trees[i]
+        assert t.nl == len(want["leaves"])
+        for ell, ids in enumerate(want["leaves"]):
+            np.testing.assert_array_equal(t.perm[t.leaf_start[ell]:t.leaf_start[ell] + t.leaf_count[ell]],
+                                          ids)
+        np.testing.assert_array_equal(t.hidx()[:, 0], want["hidx"])
+        np.testing.assert_array_equal(_leaf_keys(idx, q, i), want["lb_sq"])
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_golden_optimised_query_control_flow(case):
+    """Admission order by LB (Section 6.2.2), the leaf where |S| reaches ceil(beta n)+k,
+    and the round where stop rule B fires, against hand-worked values."""
+    g, X, idx = _golden_index()
+    cs = g["optimised"][case]
+    res = oracle.query(idx, X, np.array(g["q"], dtype=np.float32), cs["k"], cs["c"], cs["beta"],
+                       cs["r_min"], cs["eps"])
+    assert [list(t) for t in res.trace] == cs["trace"], cs["label"]
+    np.testing.assert_array_equal(res.cand, cs["cand"])
+    assert (res.stop, res.rounds, res.leaves) == (cs["stop"], cs["rounds"], cs["leaves"])
+    np.testing.assert_array_equal(res.ids, cs["ids"])
+    np.testing.assert_allclose(res.dists ** 2, cs["dists_sq"], rtol=1e-15)
+
+
+def test_golden_literal_range_query():
+    """Algorithm 3: LB pruning, whole leaves when UB <= r', per-point filter otherwise."""
+    g, X, idx = _golden_index()
+    q = np.array(g["q"], dtype=np.float64)
+    for cs in g["range_literal"]:
+        i = cs["tree"]
+        ids, examined, whole = oracle.range_query_literal(idx, X, i, q[i:i + 1], cs["r_prime"])
+        np.testing.assert_array_equal(ids, cs["ids"], err_msg=cs["label"])
+        assert (examined, whole) == (cs["examined"], cs["whole"]), cs["label"]
+
+
+def test_golden_rc_ann_query():
+    """Algorithm 4: stop at beta*n + 1 with the closest point of S, else the closest point
+    within c*r, else nothing."""
+    g, X, idx = _golden_index()
+    for cs in g["rc_ann"]:
+        oid, dist, n_c, trees = oracle.rc_ann_query(idx, X, np.array(g["q"]), cs["c"], cs["r"],
+                                                    cs["beta"], cs["eps"])
+        assert (oid, n_c, trees) == (cs["id"], cs["n_cand"], cs["trees"]), cs["label"]
+        if cs["dist"] is None:
+            assert dist is None
+        else:
+            assert abs(dist - cs["dist"]) < 1e-15
+
+
+def test_golden_literal_query():
+    """Algorithm 5 as printed: literal range queries re-run every round, stop rule A per tree."""
+    g, X, idx = _golden_index()
+    for cs in g["literal"]:
+        res = oracle.query_literal(idx, X, np.array(g["q"]), cs["k"], cs["c"], cs["beta"],
+                                   cs["r_min"], cs["eps"])
+        assert [list(t) for t in res.trace] == cs["trace"], cs["label"]
+        np.testing.assert_array_equal(res.cand, cs["cand"])
+        assert (res.stop, res.rounds) == (cs["stop"], cs["rounds"])
+        np.testing.assert_array_equal(res.ids, cs["ids"])
+        np.testing.assert_allclose(res.dists ** 2, cs["dists_sq"], rtol=1e-15)
+
+
+def test_literal_range_query_is_the_projected_ball(small_index):
+    """Every point of a leaf lies between the leaf's bounds, so Algorithm 3 returns exactly
+    the points whose projected distance to q' is smaller than r' (ties have measure zero
+    on this data): checked against brute force in the projected space."""
+    w, X, idx = small_index
+    H = oracle.project(X, idx.A)
+    for q in w.queries(6):
+        qp = q.astype(np.float64) @ idx.A
+        for i in range(w.L):
+            sl = slice(i * w.K, (i + 1) * w.K)
+            d2 = ((H[:, sl] - qp[sl]) ** 2).sum(axis=1)
+            for rp in np.quantile(np.sqrt(d2), [0.001, 0.01, 0.1]):
+                ids, examined, whole = oracle.range_query_literal(idx, X, i, qp[sl], rp)
+                np.testing.assert_array_equal(ids, np.nonzero(d2 < rp * rp)[0])
+                assert examined <= idx.trees[i].nl and whole <= examined
+
+
+def test_literal_query_candidates_within_the_relaxed_ones(small_index):
+    """Per round and tree the literal range query takes a subset of the points of the
+    leaves the relaxed admission takes whole (LB <= eps*r), and the literal stop rule A is
+    checked per tree: before the tree where it fires, |S| < T."""
+    w, X, idx = small_index
+    eps = oracle.epsilon(w.K, w.L)
+    for q in w.queries(5):
+        for beta, r_min in ((0.05, 2.0), (0.01, 1.0)):
+            lit = oracle.query_literal(idx, X, q, 10, 1.5, beta, r_min, eps)
+            T = math.ceil(beta * len(X)) + 10
+            lb = _leaf_lb2(idx, q)
+            t2 = (eps * lit.radius) ** 2
+            within = set(np.nonzero(lb.min(axis=0) <= t2)[0].tolist())
+            assert set(lit.cand.tolist()) <= within
+            sizes = np.cumsum([t[4] for t in lit.trace])
+            if lit.stop == "A":
+                assert sizes[-1] >= T and np.all(sizes[:-1] < T)
+            else:
+                assert np.all(sizes < T)
 
 
 def test_candidate_set_grows_with_radius(small_index):
