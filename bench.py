@@ -131,7 +131,6 @@ def main():
     import torch
     from paper_2603_24920_amd import pdet
     from paper_2603_24920_amd import workloads as wl
-    from paper_2603_24920_amd.tune import autotune_r_min
 
     w = wl.WORKLOADS[args.workload]
     nq = args.nq or w.nq

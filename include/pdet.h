@@ -1,11 +1,12 @@
 /*
  * pdet.h - DET-LSH index build and c^2-k-ANN search on AMD Instinct MI355X (gfx950).
  *
- * Method: arxiv 2603.24920 (DET-LSH / PDET-LSH). Section 3 defines the problem
- * (dataset D of n points in R^d, query q, approximation ratio c > 1, k); Section 4
- * defines the encoding phase (Eq. 1 projections, dynamic breakpoints, Algorithm 1),
- * the indexing phase (DE-Trees, Algorithm 2) and the query phase (Algorithms 3-5,
- * with the optimisations of the query-phase self-evaluation in Section 6).
+ * Method: arxiv 2603.24920 (DET-LSH / PDET-LSH). Section 2.1 defines the problem
+ * (dataset D of n points in R^d, query q, approximation ratio c > 1, k); Section 3
+ * defines the encoding phase (3.1: Eq. 1 projections, dynamic breakpoints, Algorithm 1),
+ * the indexing phase (3.2: DE-Trees, Algorithm 2) and the query phase (3.3: Algorithms
+ * 3-5), with the query-phase optimisations of Section 6.2.2; Section 4.3 gives the node
+ * bound distances, Section 5 (Lemma 3, Eq. 2) the parameters.
  *
  * Conventions for every entry point:
  *  - Plain C types only. "device" pointers are HIP device allocations on the
@@ -47,7 +48,7 @@ typedef enum { PDET_FP32 = 0, PDET_BF16 = 1, PDET_FP8_E4M3 = 2 } pdet_precision;
 #define PDET_MAX_ROUNDS 255    /* radius rounds r_min * c^rho, rho < 255                 */
 
 /*
- * Index build parameters (encoding phase and indexing phase, Section 4.1-4.2).
+ * Index build parameters (encoding phase and indexing phase, Sections 3.1-3.2).
  *   K, L        projections per space and number of spaces (Eq. 1: K*L Gaussian vectors).
  *   Nr          regions per dimension, a power of two in [2, 256] (8-bit symbols).
  *   max_leaf    leaf capacity ("max_size" of Algorithm 2), >= 1.
@@ -84,7 +85,7 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
 void pdet_free(pdet_index* idx);
 
 /*
- * Query parameters (c^2-k-ANN query, Algorithm 5, Section 4.3).
+ * Query parameters (c^2-k-ANN query, Algorithm 5, Section 3.3).
  *   k, c          uniform k >= 1 and c > 1, used when the per-query arrays are NULL.
  *   k_per_query   host int32 [nq] or NULL; c_per_query host double [nq] or NULL.
  *   beta          stop rule A fires once |S| >= ceil(beta*n) + k (beta >= 0).
@@ -110,16 +111,22 @@ typedef struct {
 } pdet_query_params;
 
 /* Per-query statistics words written to `qstats` (int32 [nq][PDET_QSTAT_WORDS]). */
-#define PDET_QSTAT_WORDS 8
+#define PDET_QSTAT_WORDS 10
 #define PDET_QSTAT_ROUNDS 0   /* radius rounds started                                      */
 #define PDET_QSTAT_NCAND 1    /* |S| at termination                                         */
-#define PDET_QSTAT_STOP 2     /* 1: stop rule A (|S| >= T), 2: stop rule B, <0: error       */
+#define PDET_QSTAT_STOP 2     /* 1: stop rule A (|S| >= T), 2: stop rule B, -1: radius       */
+                              /* ladder exhausted, -2: internal inconsistency (a bug)       */
 #define PDET_QSTAT_LEAVES 3   /* leaves admitted                                            */
 #define PDET_QSTAT_HSUM 4     /* sum of candidate ids mod 2^32                               */
 #define PDET_QSTAT_HMIX 5     /* sum of mix32(id) mod 2^32, mix32 = murmur3 finaliser        */
 #define PDET_QSTAT_TIME 6     /* device time of the query's search in wall-clock ticks       */
                               /* (pdet_index_info.wall_clock_khz ticks per millisecond)      */
 #define PDET_QSTAT_VISITS 7   /* point occurrences examined (a point counts once per leaf)   */
+#define PDET_QSTAT_BAND_LEAF 8  /* (leaf, round) pairs, over the rounds the query ran, whose */
+                              /* squared lower bound lies within 1e-5 relative of that      */
+                              /* round's threshold (eps r)^2: FP32-vs-FP64 admission ties   */
+#define PDET_QSTAT_BAND_STOPB 9 /* rounds whose stop-rule-B test was a near tie: the k-th   */
+                              /* squared distance within 2e-5 relative of (c r)^2           */
 
 /*
  * Answer nq queries (device float32 [nq][d]).
@@ -140,6 +147,18 @@ typedef struct {
 pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
                        const pdet_query_params* p, int64_t* ids, float* dists,
                        int32_t* qstats, void* stream);
+
+/*
+ * pdet_query, and in addition the candidate set S of every query (Algorithm 5: the union
+ * of the points the range queries admitted, up to the step where a stop rule fired), for
+ * step-by-step checking. cand (device int32 [nq][cand_cap], caller-owned) receives the
+ * distinct ids of S of query q in entries [q*cand_cap, q*cand_cap + min(|S|, cand_cap));
+ * their order is unspecified, |S| is qstats word PDET_QSTAT_NCAND, and ids past cand_cap
+ * are not written. Errors: those of pdet_query; EINVAL for cand NULL or cand_cap < 1.
+ */
+pdet_status pdet_query_candidates(const pdet_index* idx, const float* queries, int64_t nq,
+                                  const pdet_query_params* p, int64_t* ids, float* dists,
+                                  int32_t* qstats, int32_t* cand, int64_t cand_cap, void* stream);
 
 /* Sizes the index's query workspace (per-query scratch: round-index tables, admitted-leaf
  * lists, thresholds) for batches of up to nq queries, so that a later pdet_query of at most
@@ -198,11 +217,12 @@ pdet_status pdet_info(const pdet_index* idx, pdet_index_info* out);
  *   PDET_X_LEAF_START  int32 [leaves] for `tree`; PDET_X_LEAF_COUNT likewise.
  *   PDET_X_LEAF_HIDX   uint16 [leaves][16] for `tree`: (1 << t_j) | prefix_j, where the
  *                      leaf fixes the t_j leading bits prefix_j of dimension j's code.
+ *   PDET_X_LEAF_OF     int32 [n] for `tree`: the leaf ordinal of every point id.
  * `bytes` must equal the exact size; otherwise EINVAL. Synchronises the device.
  */
 enum {
   PDET_X_BREAKPOINTS = 0, PDET_X_CODES = 1, PDET_X_PERM = 2,
-  PDET_X_LEAF_START = 3, PDET_X_LEAF_COUNT = 4, PDET_X_LEAF_HIDX = 5
+  PDET_X_LEAF_START = 3, PDET_X_LEAF_COUNT = 4, PDET_X_LEAF_HIDX = 5, PDET_X_LEAF_OF = 6
 };
 pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void* host,
                         size_t bytes);

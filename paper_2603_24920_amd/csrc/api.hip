@@ -364,6 +364,22 @@ pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
   });
 }
 
+pdet_status pdet_query_candidates(const pdet_index* idx, const float* queries, int64_t nq,
+                                  const pdet_query_params* p, int64_t* ids, float* dists,
+                                  int32_t* qstats, int32_t* cand, int64_t cand_cap, void* stream) {
+  return guarded([&] {
+    std::vector<int32_t> k;
+    std::vector<double> c;
+    QueryConfig qc = check_query(idx, queries, nq, p, ids, dists, qstats, k, c);
+    PDET_REQUIRE(cand && cand_cap >= 1, PDET_EINVAL, "cand must be non-NULL and cand_cap >= 1");
+    if (nq == 0) return;
+    qc.cand = cand;
+    qc.cand_cap = cand_cap;
+    run_query(*idx, qc, static_cast<hipStream_t>(stream));
+    flush_timing();
+  });
+}
+
 pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream) {
   return guarded([&] {
     PDET_REQUIRE(idx, PDET_EINVAL, "NULL index");
@@ -437,6 +453,21 @@ pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void*
         src = idx->leaf_count[tree].p; want = (size_t)idx->nl[tree] * 4; break;
       case PDET_X_LEAF_HIDX:
         src = idx->leaf_hidx[tree].p; want = (size_t)idx->nl[tree] * KP * 2; break;
+      case PDET_X_LEAF_OF: {
+        // from the first tree's permutation and leaf rows: the point at position p of
+        // tree 0 is perm_0[p], and its leaf in `tree` is leafrow[0][p][tree]
+        want = (size_t)idx->n * 4;
+        PDET_REQUIRE(bytes == want, PDET_EINVAL,
+                     "export size mismatch: expected " + std::to_string(want) + " bytes");
+        std::vector<int32_t> perm0(idx->n), rows((size_t)idx->n * idx->L);
+        PDET_HIP(hipDeviceSynchronize());
+        PDET_HIP(hipMemcpy(perm0.data(), idx->perm.p, (size_t)idx->n * 4, hipMemcpyDeviceToHost));
+        PDET_HIP(hipMemcpy(rows.data(), idx->leafrow.p, rows.size() * 4, hipMemcpyDeviceToHost));
+        int32_t* out = static_cast<int32_t*>(host);
+        for (int64_t pos = 0; pos < idx->n; ++pos)
+          out[perm0[pos]] = rows[(size_t)pos * idx->L + tree];
+        return;
+      }
       default:
         throw Error{PDET_EINVAL, "unknown export item"};
     }

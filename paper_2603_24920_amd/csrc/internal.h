@@ -13,7 +13,7 @@
 namespace pdet {
 // Query scratch, kept by the index and reused across calls (see run_query).
 struct QueryWorkspace {
-  DevBuf rho, admb, adm2, t2, crr, lcnt, qp, dk, dc, dT, doff;
+  DevBuf rho, admb, adm2, t2, crr, lcnt, bandc, qp, dk, dc, dT, doff;
   PinnedBuf h_k, h_c, h_T, h_off;   // staging of the per-query parameters
   int64_t nslots = 0, nslots_max = 0, nq_cap = 0;
   // Leaf-list capacity of a slot per tree: tree i holds min(nl_i, list_cap) entries. A
@@ -32,7 +32,7 @@ struct QueryWorkspace {
   int64_t uT = 0;
   double uc = 0.0;
   size_t bytes() const {
-    return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes + lcnt.bytes +
+    return rho.bytes + admb.bytes + adm2.bytes + t2.bytes + crr.bytes + lcnt.bytes + bandc.bytes +
            (full ? full->bytes() : 0);
   }
   bool capped() const { return full != nullptr; }
@@ -165,6 +165,8 @@ struct QueryConfig {
   int64_t* ids;
   float* dists;
   int32_t* qstats;
+  int32_t* cand = nullptr;   // optional [nq][cand_cap]: the candidate set S of each query
+  int64_t cand_cap = 0;
 };
 void run_query(const Index& ix, const QueryConfig& qc, hipStream_t s);
 int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws);

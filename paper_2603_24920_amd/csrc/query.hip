@@ -1,4 +1,4 @@
-// c^2-k-ANN query (Algorithm 5) with the optimised range query of Section 6
+// c^2-k-ANN query (Algorithm 5) with the optimised range query of Section 6.2.2
 // (relaxed whole-leaf admission when the leaf's lower bound is within eps*r, and
 // admission in ascending lower-bound order), batched on gfx950.
 //
@@ -49,6 +49,8 @@ constexpr uint32_t HEMPTY = 0xffffffffu;
 constexpr uint32_t NO_CUT = 0xffffffffu;
 constexpr int WALK_VERIFY = 0, WALK_COUNT = 1, WALK_CUT = 2;
 constexpr int STOP_OVERFLOW = 3; // query-stat stop code: leaf lists overflowed (answered again)
+constexpr float BAND_REL = 1e-5f; // near-tie band: |LB^2 - (eps r)^2| <= BAND_REL (eps r)^2, and
+                                 // the k-th squared distance within 2 BAND_REL of (c r)^2
 constexpr int LBCH = 4;          // box dimensions q_main loads at a time for a lower bound
 constexpr int RLBCH = 2;         // the same in the (rare) refinement, which is kept lean
 
@@ -84,6 +86,8 @@ struct QArgs {
   const double* crr;         // [slots][NRHO]: (c*r)^2, compared with squared distances
   uint8_t* rho;              // [slots][L][nlpad] dense round table (0xff: not admitted)
   uint32_t* lcnt;            // [slots][PDET_MAX_L] leaf-list lengths
+  uint32_t* bandc;           // [slots][NRHO]: leaves whose LB^2 lies in the band of round
+                             // rho's threshold (counted where the leaf's bound is computed)
   const int32_t* leafrow;    // [L][n][L]
   uint32_t* adm_leaf;        // [slots][admcap] leaf lists: tree i from nlo[i]
   uint32_t* adm_w;
@@ -103,6 +107,8 @@ struct QArgs {
   double r_min, eps;
   const int32_t* qmap;       // null: slot s answers query q0 + s; else query qmap[q0 + s]
   uint32_t* ovf;             // [1 + nq]: count of queries whose leaf lists overflowed, their ids
+  int32_t* cand;             // optional [nq][cand_cap]: the ids of S in admission order of
+  int64_t cand_cap;          // the walk (the first cand_cap of them)
 };
 
 __device__ inline int64_t slot_query(const QArgs& a, int slot) {
@@ -135,6 +141,7 @@ __global__ void q_setup(QArgs a) {
   t2[NRHO - 1] = INFINITY;
   crr[NRHO - 1] = INFINITY;
   for (int i = 0; i < PDET_MAX_L; ++i) a.lcnt[(int64_t)slot * PDET_MAX_L + i] = 0;
+  for (int rho = 0; rho < NRHO; ++rho) a.bandc[(int64_t)slot * NRHO + rho] = 0;
 }
 
 // float in the global address space (a pointer rebuilt from scalar registers keeps it)
@@ -266,7 +273,8 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
   for (int sub = 0; sub < QT / 16; ++sub) {
     const int qi = sub * 16 + sl;
     bool open = false;
-    if (g < ng && slot0 + qi < a.nslots) open = box_lb2(lo, hi, sq[qi], K) <= st[qi][rcap];
+    if (g < ng && slot0 + qi < a.nslots)
+      open = box_lb2(lo, hi, sq[qi], K) <= st[qi][rcap] * (1.0f + BAND_REL);
     const uint64_t mask = __ballot(open);
     open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
   }
@@ -279,6 +287,11 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
     int c = 0;   // #thresholds < lb2 among rounds 0..rcap: the leaf's first round if <= rcap
 #pragma unroll
     for (int rr = 0; rr <= RCAP_MAX; ++rr) c += (rr <= rcap && st[qi][rr] < acc) ? 1 : 0;
+    // a near tie can only be with the thresholds on either side of the bound
+#pragma unroll
+    for (int rr = c - 1; rr <= c; ++rr)
+      if (rr >= 0 && rr <= rcap && fabsf(acc - st[qi][rr]) <= BAND_REL * st[qi][rr])
+        atomicAdd(&a.bandc[(int64_t)slot * NRHO + rr], 1u);
     if (c <= rcap) {
       const uint32_t pos = atomicAdd(&a.lcnt[(int64_t)slot * PDET_MAX_L + tree], 1u);
       // past the region's capacity only the count grows: q_main sees the overflow
@@ -505,7 +518,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   __shared__ uint32_t s_lco[PDET_MAX_L + 1];     // their prefix (lists in tree order)
   __shared__ uint32_t hkey[HSZ];
   __shared__ uint8_t hrnd[HSZ];
-  __shared__ uint32_t s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix, s_cnt, s_cute;
+  __shared__ uint32_t s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix, s_cnt, s_cute, s_clo, s_chi;
   __shared__ unsigned long long s_cut;
 
   const int slot = blockIdx.x;
@@ -545,6 +558,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   bool dense = false;          // the hash overflowed: rounds live in the dense table rq
   uint32_t hsum = 0, hmix = 0;
   int stop = -1, rounds = 0;
+  uint32_t band_b = 0;         // rounds whose stop-rule-B count was a near tie
   int cap = a.rcap;            // rounds whose leaf indices are resolved
   // Leaf lists past their slot's capacity (a large index caps them): the query is flagged
   // and answered again with full-capacity slots. STOP_OVERFLOW leaves the round loop;
@@ -641,6 +655,10 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           idbuf[wbase + lanes_below_mask(mask)] = id;
           hsum += (uint32_t)id;
           hmix += mix32((uint32_t)id);
+          if (a.cand) {
+            const int64_t at = nS + newc + wbase + lanes_below_mask(mask);
+            if (at < a.cand_cap) a.cand[q * a.cand_cap + at] = id;
+          }
         }
       }
       __syncthreads();
@@ -830,7 +848,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     return nm;
   };
 
-  for (int rho = 0; rho < NRHO - 1 && stop < 0; ++rho) {
+  for (int rho = 0; rho < NRHO - 1 && stop == -1; ++rho) {
     rounds = rho + 1;
     if (rho == cap + 1) {
       // The lists hold every leaf whose first round is <= cap. Leaves whose first round is
@@ -846,7 +864,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           for (int w = tid; w < GCH / 32; w += QM) gopen[w] = 0u;
           __syncthreads();
           for (int64_t g = g0 + tid; g < std::min<int64_t>(ng, g0 + GCH); g += QM) {
-            if (leaf_lb2<RLBCH>(gb, ng, g, qi, a.K) <= st2[ncap])
+            if (leaf_lb2<RLBCH>(gb, ng, g, qi, a.K) <= st2[ncap] * (1.0f + BAND_REL))
               atomicOr(&gopen[(g - g0) >> 5], 1u << ((g - g0) & 31));
           }
           __syncthreads();
@@ -859,6 +877,9 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
 #pragma unroll
             for (int sft = NRHO / 2; sft > 0; sft >>= 1)
               if (st2[pos + sft - 1] < lb2) pos += sft;
+            for (int rr = pos - 1; rr <= pos; ++rr)
+              if (rr > cap && rr <= ncap && fabsf(lb2 - st2[rr]) <= BAND_REL * st2[rr])
+                atomicAdd(&a.bandc[(int64_t)slot * NRHO + rr], 1u);
             if (pos > cap && pos <= ncap) {
               const uint32_t at = atomicAdd(&s_lc[i], 1u);
               if (at < a.lcap[i]) lst[at] = ((uint32_t)pos << LEAF_BITS) | (uint32_t)leaf;
@@ -880,6 +901,8 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     if (tid < a.L) { s_mt[tid] = 0; s_pt[tid] = 0; }
     if (tid == 0) {
       s_cnt = 0;
+      s_clo = 0;
+      s_chi = 0;
       s_lco[0] = 0;
       for (int i = 0; i < a.L; ++i) s_lco[i + 1] = s_lco[i] + s_lc[i];
     }
@@ -959,7 +982,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
         nS += traverse(WALK_VERIFY, rho, 0, m, 0, P, 0, ce);
       } else {
         // trees in order; exact counts decide the tree (and leaf) where |S| reaches T
-        for (int i = 0; i < a.L && stop < 0; ++i) {
+        for (int i = 0; i < a.L && stop == -1; ++i) {
           const uint32_t e0 = uni(ent_off[i]), e1 = uni(ent_off[i + 1]);
           if (e0 == e1) continue;
           const uint32_t p0 = uni(ent_pre[i]), p1 = uni(ent_pre[i + 1]);
@@ -998,7 +1021,9 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
               traverse(WALK_COUNT, rho, e0, e1c, p0, uni(pre2[e1c]), 0, ce);
           uint32_t e_end = e1;
           if (nS + (int64_t)new_i < T) {
-            if (e1c != e1) { stop = -2; break; }   // contradicts the bound above
+            // contradicts the bound above: the query ends with stop = -2 (an internal
+            // error the statistics report; it leaves the round loop)
+            if (e1c != e1) { stop = -2; break; }
           } else {
             // the smallest key whose inclusive new-point prefix reaches R = T - |S|
             const unsigned long long cut = select_key(e0, e1c, (uint32_t)(T - nS), false);
@@ -1009,18 +1034,58 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           nS += traverse(WALK_VERIFY, rho, e0, e_end, p0, uni(pre2[e_end]), 0, ce);
         }
       }
-      if (stop >= 0) break;
+      if (stop != -1) break;
     }
     if (nS >= k) {
-      // stop rule B: the k-th smallest distance of the kept list and the pending buffer is
-      // <= c*r iff at least k of them are (compared squared, with (c*r)^2)
+      // stop rule B: at least k points of S within c*r (compared squared, with (c*r)^2);
+      // the counts at (c r)^2 (1 -+ 2 BAND_REL) flag a near tie of the k-th distance
       const double crr = a.crr[(int64_t)slot * NRHO + rho];
-      const uint32_t tot = (uint32_t)KL + uni(s_ncb);
-      uint32_t cnt = 0;
-      for (uint32_t e = tid; e < tot; e += QM) cnt += (ld[e] <= crr) ? 1u : 0u;
+      const double blo = crr * (1.0 - 2.0 * BAND_REL), bhi = crr * (1.0 + 2.0 * BAND_REL);
+      uint32_t cnt = 0, clo = 0, chi = 0;
+      if constexpr (PREC == PDET_FP32) {
+        // the k-th smallest distance of the kept list and the pending buffer is <= c*r
+        // iff at least k of them are
+        const uint32_t tot = (uint32_t)KL + uni(s_ncb);
+        for (uint32_t e = tid; e < tot; e += QM) {
+          const double v = ld[e];
+          cnt += (v <= crr) ? 1u : 0u;
+          clo += (v <= blo) ? 1u : 0u;
+          chi += (v <= bhi) ? 1u : 0u;
+        }
+      } else {
+        // Low-precision distances only rank the candidates: the kept list (the best
+        // k * rescore of S by them) is counted by exact float32 distance, so quantisation
+        // error does not move the round in which the rule fires.
+        if (uni(s_ncb) > 0) merge();
+        const int lpc32 = a.lpc32, lg32 = tid & (lpc32 - 1), grp32 = tid / lpc32;
+        const int G32 = QM / lpc32;
+        for (int t0 = 0; t0 < KL; t0 += 2 * G32) {
+          int32_t id[2];
+          bool valid[2];
+          double dd[2];
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            const int t = t0 + r * G32 + grp32;
+            valid[r] = t < KL && li[t] != INT32_MAX;
+            id[r] = valid[r] ? li[t] : 0;
+          }
+          cand_dist<PDET_FP32, 2>(a, id, valid, qv, qd, lg32, lpc32, dd);
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            if (valid[r] && lg32 == 0) {
+              cnt += (dd[r] <= crr) ? 1u : 0u;
+              clo += (dd[r] <= blo) ? 1u : 0u;
+              chi += (dd[r] <= bhi) ? 1u : 0u;
+            }
+          }
+        }
+      }
       if (cnt) atomicAdd(&s_cnt, cnt);
+      if (clo) atomicAdd(&s_clo, clo);
+      if (chi) atomicAdd(&s_chi, chi);
       __syncthreads();
       if (uni(s_cnt) >= (uint32_t)k) stop = 2;
+      if (uni(s_clo) < (uint32_t)k && uni(s_chi) >= (uint32_t)k) ++band_b;
     }
     __syncthreads();
   }
@@ -1086,6 +1151,10 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     st[PDET_QSTAT_HMIX] = (int32_t)s_hmix;
     st[PDET_QSTAT_TIME] = (int32_t)std::min<uint64_t>(wall_clock64() - t_start, INT32_MAX);
     st[PDET_QSTAT_VISITS] = (int32_t)std::min<int64_t>(visits, INT32_MAX);
+    uint32_t bl = 0;
+    for (int rr = 0; rr < rounds; ++rr) bl += a.bandc[(int64_t)slot * NRHO + rr];
+    st[PDET_QSTAT_BAND_LEAF] = (int32_t)bl;
+    st[PDET_QSTAT_BAND_STOPB] = (int32_t)band_b;
   }
 }
 
@@ -1156,7 +1225,7 @@ int64_t list_entries(const Index& ix, int64_t cap) {
 
 size_t slot_bytes_at(const Index& ix, int64_t admcap) {
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
-  return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 + NRHO * 12 +
+  return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 + NRHO * 16 +
          PDET_MAX_L * 4;
 }
 
@@ -1168,13 +1237,14 @@ void alloc_slots(const Index& ix, QueryWorkspace& ws, int64_t want, int64_t cap,
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
   const int64_t admcap = list_entries(ix, cap);
   ws.rho.release(); ws.admb.release(); ws.adm2.release(); ws.t2.release(); ws.crr.release();
-  ws.lcnt.release();
+  ws.lcnt.release(); ws.bandc.release();
   ws.rho.alloc((size_t)want * ix.L * nlpad);
   ws.admb.alloc((size_t)want * admcap * 12);
   ws.adm2.alloc((size_t)want * (admcap + 1) * 12);
   ws.t2.alloc((size_t)want * NRHO * 4);
   ws.crr.alloc((size_t)want * NRHO * 8);
   ws.lcnt.alloc((size_t)want * PDET_MAX_L * 4);
+  ws.bandc.alloc((size_t)want * NRHO * 4);
   // the dense round table starts "never admitted"; a query that writes it restores it
   PDET_HIP(hipMemsetAsync(ws.rho.p, 0xff, ws.rho.bytes, s));
   ws.nslots = want;
@@ -1269,6 +1339,7 @@ void bind_slots(const Index& ix, QArgs& a, QueryWorkspace& sw) {
   a.crr = sw.crr.as<double>();
   a.rho = sw.rho.as<uint8_t>();
   a.lcnt = sw.lcnt.as<uint32_t>();
+  a.bandc = sw.bandc.as<uint32_t>();
   a.adm_leaf = sw.admb.as<uint32_t>();
   a.adm_w = a.adm_leaf + nslots * admcap;
   a.adm_lb = reinterpret_cast<float*>(a.adm_w + nslots * admcap);
@@ -1340,6 +1411,8 @@ QArgs batch_args(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int
                "d and k * rescore too large for the query workgroup's LDS");
   a.qmap = nullptr;
   a.ovf = ws.ovf.as<uint32_t>();
+  a.cand = qc.cand;
+  a.cand_cap = qc.cand_cap;
   return a;
 }
 

@@ -18,10 +18,11 @@ PDET_OK, PDET_EINVAL, PDET_ENOMEM, PDET_EDEVICE, PDET_EUNSUPPORTED = 0, -1, -2, 
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 MAX_K, MAX_L, MAX_TOPK, MAX_ROUNDS = 16, 16, 1024, 255
-QSTAT_WORDS = 8
-QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits=7)
-X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX = range(6)
-EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
+QSTAT_WORDS = 10
+QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits=7,
+             band_leaf=8, band_stop_b=9)
+X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF = range(7)
+EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_candidates", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
             "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -93,6 +94,9 @@ def lib() -> ctypes.CDLL:
                                  POINTER(c_void_p)]
         L.pdet_query.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams), c_void_p,
                                  c_void_p, c_void_p, c_void_p]
+        L.pdet_query_candidates.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
+                                            c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
+                                            c_void_p]
         L.pdet_reserve.argtypes = [c_void_p, c_int64, c_void_p]
         L.pdet_set_list_cap.argtypes = [c_void_p, c_int64]
         L.pdet_release_cache.argtypes = []
@@ -123,7 +127,7 @@ def lib() -> ctypes.CDLL:
         L.pdet_server_get_stats.argtypes = [c_void_p, POINTER(ServerStats)]
         L.pdet_server_free.argtypes = [c_void_p]
         L.pdet_server_free.restype = None
-        for f in ("pdet_build", "pdet_query", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
+        for f in ("pdet_build", "pdet_query", "pdet_query_candidates", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
                   "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
                   "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
                   "pdet_server_get_stats", "pdet_set_list_cap"):
@@ -224,6 +228,7 @@ class Index:
             X_LEAF_START: ((nl[tree],), np.int32),
             X_LEAF_COUNT: ((nl[tree],), np.int32),
             X_LEAF_HIDX: ((nl[tree], 16), np.uint16),
+            X_LEAF_OF: ((self.n,), np.int32),
         }[what]
         out = np.empty(shape, dtype=dt)
         _check(lib().pdet_export(self._h, what, tree, out.ctypes.data_as(c_void_p), out.nbytes))
@@ -296,6 +301,33 @@ class Index:
         if k_per_query is None:
             ids, dists = ids.view(nq, k), dists.view(nq, k)
         return (ids, dists, st) if stats else (ids, dists)
+
+
+    def query_candidates(self, Q, cand_cap, k=10, c=1.5, beta=0.1, r_min=1.0, eps=0.0,
+                         precision="fp32", rescore=4, k_per_query=None, c_per_query=None,
+                         stream=None):
+        """query() with stats, plus each query's candidate set S (pdet_query_candidates).
+
+        Returns (ids, dists, qstats, cands) where cands[q] is the sorted numpy array of the
+        first min(|S|, cand_cap) candidate ids of query q (all of S when |S| <= cand_cap)."""
+        import torch
+        nq = Q.shape[0]
+        p, keep = self._params(k, c, beta, r_min, eps, precision, rescore, k_per_query,
+                               c_per_query)
+        total = int(keep[0].sum()) if keep[0] is not None else nq * k
+        ids = torch.empty(total, dtype=torch.int64, device=Q.device)
+        dists = torch.empty(total, dtype=torch.float32, device=Q.device)
+        st = torch.empty((nq, QSTAT_WORDS), dtype=torch.int32, device=Q.device)
+        cand = torch.full((nq, cand_cap), -1, dtype=torch.int32, device=Q.device)
+        _check(lib().pdet_query_candidates(self._h, c_void_p(Q.data_ptr()), nq, ctypes.byref(p),
+                                           c_void_p(ids.data_ptr()), c_void_p(dists.data_ptr()),
+                                           c_void_p(st.data_ptr()), c_void_p(cand.data_ptr()),
+                                           int(cand_cap), _stream(stream)))
+        if k_per_query is None:
+            ids, dists = ids.view(nq, k), dists.view(nq, k)
+        cn, sn = cand.cpu().numpy(), st.cpu().numpy()
+        cands = [np.sort(cn[q, :min(int(sn[q, QSTAT["ncand"]]), cand_cap)]) for q in range(nq)]
+        return ids, dists, st, cands
 
 
 class Plan:

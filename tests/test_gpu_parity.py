@@ -25,29 +25,7 @@ from paper_2603_24920_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-U32 = 2.0 ** -24
-BAND = 1e-5
-
-
-def mix32(h):
-    h = h.astype(np.uint64) & 0xFFFFFFFF
-    h ^= h >> 16; h = (h * 0x85EBCA6B) & 0xFFFFFFFF
-    h ^= h >> 13; h = (h * 0xC2B2AE35) & 0xFFFFFFFF
-    h ^= h >> 16
-    return h
-
-
-def set_hashes(ids):
-    ids = np.asarray(ids, dtype=np.uint64)
-    hs = int(ids.sum() & 0xFFFFFFFF)
-    hm = int(mix32(ids).sum() & 0xFFFFFFFF)
-    to32 = lambda v: v - (1 << 32) if v >= (1 << 31) else v
-    return to32(hs), to32(hm)
-
-
-def proj_bound(X, A):
-    d = X.shape[1]
-    return 1.01 * (d + 1) * U32 * (np.abs(X.astype(np.float64)) @ np.abs(A.astype(np.float64)))
+from parity import BAND, compare_batch, near_stop_b, near_threshold, proj_bound, set_hashes  # noqa: E402
 
 
 class Case:
@@ -63,7 +41,8 @@ class Case:
         self.B_or = oracle.breakpoints(self.H[sid], Nr, self.H.min(axis=0), self.H.max(axis=0))
         self.B_gpu = self.idx.export(pdet.X_BREAKPOINTS).astype(np.float64)
         self.codes_gpu = np.ascontiguousarray(self.idx.export(pdet.X_CODES)[:, :, :K])
-        self.eps = pdet.epsilon(K, L)
+        # the oracle's own eps (Eq. 2 / Lemma 3), passed to both sides
+        self.eps = oracle.epsilon(K, L)
         self._stepwise = None
 
     def stepwise_oracle(self):
@@ -126,70 +105,33 @@ def check_trees(cs):
         np.testing.assert_array_equal(gp[np.lexsort((gp, leaf_of_pos))], t.perm)
 
 
-def near_threshold(idx_or, q, rounds, r_min, c, eps):
-    """True if some leaf bound of q is within BAND of a radius threshold used."""
-    qp = q.astype(np.float64) @ idx_or.A
-    t2 = np.array([(eps * r) ** 2 for r in oracle.radius_ladder(r_min, c, rounds + 1)])
-    for i in range(idx_or.L):
-        lo, hi = idx_or.boxes[i]
-        lb2 = oracle.lower_bound_sq(qp[i * idx_or.K:(i + 1) * idx_or.K], lo, hi)
-        if np.any(np.abs(lb2[:, None] - t2[None, :]) <= BAND * t2[None, :]):
-            return True
-    return False
-
-
-def near_stop_b(X, q, cand, k, rounds, r_min, c):
-    if len(cand) < k:
-        return False
-    dd = np.sort(np.sqrt(((X[cand].astype(np.float64) - q.astype(np.float64)) ** 2).sum(axis=1)))
-    kth = dd[k - 1]
-    return any(abs(kth - c * r) <= BAND * c * r for r in oracle.radius_ladder(r_min, c, rounds + 1))
-
-
 def run_and_compare(cs, idx_or, Q, k, c, beta, r_min, label, allow_frac=0.0):
+    """One GPU batch with candidate export, every query compared with the oracle."""
     Qd = torch.from_numpy(Q).cuda()
-    print(f"[query {label}] nq={len(Q)} k={k} c={c} beta={beta} r_min={r_min}", flush=True)
-    ids, dists, st = cs.idx.query(Qd, k=k, c=c, beta=beta, r_min=r_min, stats=True)
+    cap = min(len(cs.X), int(np.ceil(beta * len(cs.X))) + k + 8 * cs.max_leaf + 64)
+    print(f"[query {label}] nq={len(Q)} k={k} c={c} beta={beta} r_min={r_min} eps={cs.eps}",
+          flush=True)
+    ids, dists, st, cands = cs.idx.query_candidates(Qd, cap, k=k, c=c, beta=beta, r_min=r_min,
+                                                    eps=cs.eps)
     ids, dists, st = ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
     compare_queries(cs, idx_or, Q, range(len(Q)), ids, dists, st, k, c, beta, r_min, label,
-                    allow_frac)
+                    allow_frac, cands=cands)
     return ids, dists, st
 
 
 def compare_queries(cs, idx_or, Q, sel, ids, dists, st, k, c, beta, r_min, label,
-                    allow_frac=0.0):
-    """GPU results of the queries `sel` of batch Q against the oracle run one by one."""
+                    allow_frac=0.0, cands=None):
+    """GPU results of the queries `sel` of batch Q against the oracle run one by one; every
+    difference must be a classified near tie, and at most allow_frac of them (at least 1)."""
     sel = list(sel)
-    n_diff = n_band = 0
-    results = {}
-    for qi in sel:
-        q = Q[qi]
-        res = oracle.query(idx_or, cs.X, q, k, c, beta, r_min, cs.eps)
-        results[qi] = res
-        hs, hm = set_hashes(res.cand)
-        same_set = (st[qi, pdet.QSTAT["ncand"]] == res.n_cand and st[qi, pdet.QSTAT["hsum"]] == hs
-                    and st[qi, pdet.QSTAT["hmix"]] == hm)
-        same_flow = (st[qi, pdet.QSTAT["stop"]] == (1 if res.stop == "A" else 2)
-                     and st[qi, pdet.QSTAT["rounds"]] == res.rounds
-                     and st[qi, pdet.QSTAT["leaves"]] == res.leaves)
-        if same_set and same_flow:
-            if not np.array_equal(ids[qi], res.ids):
-                # allowed only at an exact distance tie at the k boundary
-                dk = res.dists[k - 1]
-                tie = np.sum(np.abs(np.sqrt(((cs.X[res.cand].astype(np.float64) - q) ** 2).sum(1))
-                                    - dk) <= 1e-12 * dk) > 1
-                assert tie, (label, qi, ids[qi], res.ids)
-            np.testing.assert_allclose(dists[qi], res.dists, rtol=1e-6)
-            continue
-        n_diff += 1
-        rounds = max(res.rounds, int(st[qi, pdet.QSTAT["rounds"]]))
-        banded = (near_threshold(idx_or, q, rounds, r_min, c, cs.eps)
-                  or near_stop_b(cs.X, q, res.cand, k, rounds, r_min, c))
-        assert banded, (label, qi, st[qi], res.n_cand, res.stop, res.rounds, res.leaves, hs, hm)
-        n_band += 1
-    print(f"[query {label}] identical={len(sel) - n_diff}/{len(sel)} banded={n_band}",
-          flush=True)
-    assert n_diff <= max(1, allow_frac * len(sel))
+    n_same, n_band, results = compare_batch(cs.X, idx_or, Q, sel, ids, dists, st, k, c, beta,
+                                            r_min, cs.eps, label, cands=cands,
+                                            log=lambda m: print(m, flush=True))
+    assert len(sel) - n_same <= max(1, allow_frac * len(sel))
+    if cands is not None:
+        whole = sum(len(cands[q]) == st[q, 1] for q in sel)
+        print(f"[query {label}] candidate sets compared element by element: {whole}/{len(sel)}",
+              flush=True)
     return results
 
 
@@ -267,26 +209,65 @@ def test_query_stepwise_ragged(ragged, beta, r_min, k, c):
                     f"ragged k={k}")
 
 
+def _first_layer_nodes_with_changed_codes(codes_a, codes_b, bits):
+    """Per tree, the first-layer keys of the points whose codes differ between two builds."""
+    out = []
+    for i in range(codes_a.shape[0]):
+        diff = np.nonzero(np.any(codes_a[i] != codes_b[i], axis=1))[0]
+        keys = set()
+        for codes in (codes_a[i], codes_b[i]):
+            keys |= set(oracle.first_layer_key(codes[diff], bits).tolist())
+        out.append(keys)
+    return out
+
+
 def test_query_end_to_end_against_oracle_from_scratch(mixture):
-    """Oracle built from its own FP64 projections; differences must be explained by
-    banded codes (which can move points between leaves) and are counted."""
+    """Oracle built from its own FP64 projections and breakpoints. Every query must give
+    the oracle's candidate set, control flow and ids, unless the difference is explained
+    (and counted): the query admitted a leaf of a first-layer node whose points' codes
+    differ (all such codes are banded, see the code test), or a leaf bound / k-th
+    distance lies in the band of a threshold (FP32 vs FP64 breakpoints)."""
     w, cs = mixture
     idx_or = oracle.build_index(cs.X, cs.A, cs.sid, w.L, w.K, w.Nr, w.max_leaf)
+    step = cs.stepwise_oracle()
     Q = w.queries()
     Qd = torch.from_numpy(Q).cuda()
-    ids, dists, st = cs.idx.query(Qd, k=w.k, c=w.c, beta=w.beta, r_min=4.0, stats=True)
-    ids, st = ids.cpu().numpy(), st.cpu().numpy()
-    same = 0
+    cap = len(cs.X)
+    ids, dists, st, cands = cs.idx.query_candidates(Qd, cap, k=w.k, c=w.c, beta=w.beta,
+                                                    r_min=4.0, eps=cs.eps)
+    ids, dists, st = ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
+    changed = _first_layer_nodes_with_changed_codes(idx_or.codes, cs.codes_gpu,
+                                                    int(np.log2(w.Nr)))
+    same = by_codes = by_band = 0
     for qi, q in enumerate(Q):
         res = oracle.query(idx_or, cs.X, q, w.k, w.c, w.beta, 4.0, cs.eps)
-        hs, hm = set_hashes(res.cand)
-        if st[qi, 1] == res.n_cand and st[qi, 4] == hs and st[qi, 5] == hm:
-            same += 1
+        if np.array_equal(cands[qi], np.sort(res.cand)) and st[qi, 2] == {"A": 1, "B": 2}[res.stop] \
+                and st[qi, 0] == res.rounds and st[qi, 3] == res.leaves:
             np.testing.assert_array_equal(ids[qi], res.ids)
-    print(f"[end-to-end] identical candidate sets {same}/{len(Q)}", flush=True)
-    codes_or = oracle.encode(cs.H, cs.B_or, w.L, w.K)
-    if np.array_equal(codes_or, cs.codes_gpu):
-        assert same == len(Q)
+            np.testing.assert_allclose(dists[qi], res.dists, rtol=1e-6)
+            same += 1
+            continue
+        # the GPU equals the oracle on its own breakpoints and codes
+        rs = oracle.query(step, cs.X, q, w.k, w.c, w.beta, 4.0, cs.eps)
+        assert np.array_equal(cands[qi], np.sort(rs.cand)), qi
+        touched = False
+        for index, r in ((idx_or, res), (step, rs)):
+            for rho, i, leaf, _, _ in r.trace:
+                t = index.trees[i]
+                o = t.perm[t.leaf_start[leaf]]
+                key = int(oracle.first_layer_key(index.codes[i][o:o + 1], int(np.log2(w.Nr)))[0])
+                touched = touched or key in changed[i]
+        if touched:
+            by_codes += 1
+            continue
+        rounds = max(res.rounds, rs.rounds)
+        assert (near_threshold(idx_or, q, rounds, 4.0, w.c, cs.eps)
+                or near_threshold(step, q, rounds, 4.0, w.c, cs.eps)
+                or near_stop_b(cs.X, q, res.cand, w.k, rounds, 4.0, w.c)), qi
+        by_band += 1
+    print(f"[end-to-end] identical {same}/{len(Q)}; explained by banded codes {by_codes}, "
+          f"by a threshold near tie {by_band}", flush=True)
+    assert same + by_codes + by_band == len(Q)
 
 
 def test_exact_knn_when_everything_is_admitted(mixture):
@@ -294,7 +275,7 @@ def test_exact_knn_when_everything_is_admitted(mixture):
     w, cs = mixture
     Q = w.queries(30)
     ids, dists, st = cs.idx.query(torch.from_numpy(Q).cuda(), k=25, c=1.5, beta=1.0,
-                                  r_min=1e4, stats=True)
+                                  r_min=1e4, eps=cs.eps, stats=True)
     ex_ids, ex_d = oracle.knn_exact(cs.X, Q, 25)
     np.testing.assert_array_equal(ids.cpu().numpy(), ex_ids)
     np.testing.assert_allclose(dists.cpu().numpy(), ex_d, rtol=1e-6)
@@ -318,7 +299,7 @@ def test_per_query_k_and_c(mixture):
     ks = rng.choice([1, 10, 100], size=len(Q)).astype(np.int32)
     cc = rng.choice([1.2, 1.5, 2.0], size=len(Q))
     ids, dists = cs.idx.query(torch.from_numpy(Q).cuda(), k=0, beta=0.05, r_min=3.0,
-                              k_per_query=ks, c_per_query=cc)
+                              eps=cs.eps, k_per_query=ks, c_per_query=cc)
     ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
     idx_or = cs.stepwise_oracle()
     off = 0
@@ -330,17 +311,34 @@ def test_per_query_k_and_c(mixture):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_low_precision_forms_recall_and_rescored_distances(mixture, prec):
+    """Recall against the float32 path, exact re-ranked distances, and the same stop rule
+    and round as the float32 path (stop rule B counts the kept candidates by their exact
+    distance): the queries that stop elsewhere are counted and must be rare."""
     w, cs = mixture
     Q = torch.from_numpy(w.queries()).cuda()
-    i32, d32 = cs.idx.query(Q, k=10, c=1.5, beta=0.1, r_min=4.0)
-    il, dl = cs.idx.query(Q, k=10, c=1.5, beta=0.1, r_min=4.0, precision=prec, rescore=4)
+    i32, d32, s32 = cs.idx.query(Q, k=10, c=1.5, beta=0.1, r_min=4.0, eps=cs.eps, stats=True)
+    il, dl, sl = cs.idx.query(Q, k=10, c=1.5, beta=0.1, r_min=4.0, eps=cs.eps, precision=prec,
+                              rescore=4, stats=True)
     i32, il, dl = i32.cpu().numpy(), il.cpu().numpy(), dl.cpu().numpy()
+    s32, sl = s32.cpu().numpy(), sl.cpu().numpy()
     rec = np.mean([len(np.intersect1d(a, b)) / 10 for a, b in zip(il, i32)])
-    print(f"[{prec}] recall vs fp32 path = {rec:.4f}", flush=True)
+    moved = int(np.sum((s32[:, 0] != sl[:, 0]) | (s32[:, 2] != sl[:, 2])))
+    print(f"[{prec}] recall vs fp32 path = {rec:.4f}; queries stopping in another round or "
+          f"by another rule than fp32: {moved}/{len(Q)}", flush=True)
     assert rec >= 0.95
+    assert moved <= max(1, len(Q) // 20)
     # distances of returned ids are exact (re-ranked from float32 data)
     ex = np.sqrt(((cs.X[il].astype(np.float64) - w.queries()[:, None, :]) ** 2).sum(-1))
     np.testing.assert_allclose(dl, ex, rtol=1e-6)
+    # with beta = 1 stop rule B decides every query: its round must match the float32 path
+    _, _, b32 = cs.idx.query(Q, k=10, c=1.5, beta=1.0, r_min=0.5, eps=cs.eps, stats=True)
+    _, _, bl = cs.idx.query(Q, k=10, c=1.5, beta=1.0, r_min=0.5, eps=cs.eps, precision=prec,
+                            rescore=4, stats=True)
+    b32, bl = b32.cpu().numpy(), bl.cpu().numpy()
+    assert np.all(b32[:, 2] == 2)
+    moved_b = int(np.sum(b32[:, 0] != bl[:, 0]))
+    print(f"[{prec}] stop rule B rounds differing from fp32: {moved_b}/{len(Q)}", flush=True)
+    assert moved_b <= max(1, len(Q) // 20)
 
 
 def test_duplicates_make_a_fully_refined_leaf():

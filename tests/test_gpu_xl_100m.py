@@ -125,7 +125,7 @@ def test_100m_capped_batch_equals_full_capacity(xl):
     finally:
         idx.set_list_cap(0)
         pdet.set_timing(False)
-    keep = [0, 1, 2, 3, 4, 5, 7]          # word 6 is the query's device time
+    keep = [0, 1, 2, 3, 4, 5, 7, 8, 9]    # word 6 is the query's device time
     s = torch.from_numpy(sel).cuda()
     assert torch.equal(ids[s], f_ids) and torch.equal(dists[s], f_d)
     assert torch.equal(st[s][:, keep], f_st[:, keep])
