@@ -3,18 +3,20 @@
 
 One step = build the index over the resident data (sample projection, breakpoints,
 projection + encoding of every point, the L DE-Trees) + answer the whole query batch
-(c^2-k-ANN with FP32 verification). Default workload: SIFT-like bytes, n = 1,000,000,
-d = 128, L = 4, K = 16, Nr = 256, 10,000 queries, k = 50, c = 1.5.
+(c^2-k-ANN with FP32 verification). Default workload: the 100M-point batching
+configuration (SIFT-like bytes, n = 100,000,000, d = 128, L = 4, K = 16, Nr = 256,
+10,000 queries, k = 10, c = 1.5; about 51 GB resident), followed by a secondary block on
+the 1M-point configuration (10,000 queries, k = 50).
 
-Before the timed steps (untimed): the stop-rule parameter beta is chosen as the
-smallest value of a ladder whose mean recall@10 reaches 0.9 on a 1,000-query subset,
-with r_min picked per beta by the library's pilot search (autotune_r_min). The
-ground truth for recall is the library's own exhaustive mode (beta = 1 and a first
-radius covering every point, which the tests show equals brute-force exact kNN).
+Per workload, before the timed steps (untimed): ground truth for recall@10 is FP64 brute
+force over every point for the first --recall-queries queries; the stop-rule parameter
+beta is the smallest value of a ladder whose mean recall@10 reaches 0.9 there, per
+verification form, with r_min picked per beta by the library's pilot search.
 
-Prints one JSON line. `value` is queries/s of the query phase (inputs resident in HBM);
-`build_mpts_per_s` is n / build time. `roofline` describes the search kernel q_main_f32
-(timed live with HIP events); `cpu_baseline` is the FP64 oracle on the host.
+Prints one JSON line. `value` is queries/s of the FP32 query phase of the primary workload
+(inputs resident in HBM); `build_mpts_per_s` is n / build time. `roofline` describes the
+search kernel q_main_f32 (timed live with HIP events on the library's stream), `roofline_build`
+the whole build; `cpu_baseline` is the FP64 oracle on the host (a bounded sample).
 """
 from __future__ import annotations
 
@@ -34,10 +36,13 @@ sys.path.insert(0, ROOT)
 METRIC = "index build Mpts/s + QPS at recall@10>=0.9 (FP32 vs BF16/FP8 verify), 1 GPU"
 HBM_PEAK_GBS = 8000.0
 BETA_LADDER = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 5e-4, 2e-4, 1e-4, 5e-5, 2e-5, 1e-5)
-PROFILE_PMC = os.path.join(ROOT, "profiles", "q_main_traffic.json")
-BIG_N = 20_000_000            # above this: brute-force ground truth
 GEN_THREADS_N = 4_000_000     # from this size: data drawn in parallel chunks (same values)
 MAX_CAL_CANDIDATES = 2e5      # largest beta * n tried by the recall calibration
+POOL = 16                     # host worker processes (the GPU machine's CPU share)
+# per workload: low-precision forms measured, and the form of the graph-launched batch
+FORMS = {"sift-like-100M-d128": (("bf16",), "bf16"), "sift-like-1M-d128": (("bf16", "fp8"), "fp32"),
+         "normed-1M-d960": (("bf16",), "bf16"), "normed-10M-d256": (("fp8",), "fp8"),
+         "mixture-10k-d128": (("bf16", "fp8"), "fp32")}
 
 
 def log(*a):
@@ -51,7 +56,7 @@ def recall_at(ids, exact, r=10):
 
 def brute_force_knn(Xd, Qd, k, rows=1 << 18):
     """Exact k nearest neighbours by FP64 distances over row chunks of the resident data
-    (torch matrix products; evaluation only, for sets too large for the exhaustive mode)."""
+    (torch FP64 matrix products on the device; evaluation only, never the library)."""
     import torch
     q = Qd.double()
     qn = (q * q).sum(1, keepdim=True)
@@ -78,91 +83,57 @@ def kernel_source_hash():
 
 def pmc_traffic(workload_name, nq):
     """HBM traffic of q_main_f32 per launch from committed rocprofv3 counter runs on this
-    workload, or None if they were taken on another workload or the kernel source changed."""
-    if not os.path.exists(PROFILE_PMC):
+    workload (profiles/q_main_traffic_<workload>.json), or None if absent, taken on another
+    batch or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"q_main_traffic_{workload_name}.json")
+    if not os.path.exists(path):
         return None
-    with open(PROFILE_PMC) as f:
+    with open(path) as f:
         p = json.load(f)
-    if (p.get("kernel_hash") != kernel_source_hash() or p.get("workload_name") != workload_name
-            or p.get("nq") != nq):
+    if p.get("kernel_hash") != kernel_source_hash() or p.get("nq") != nq:
         return None
     return p.get("traffic_bytes_per_launch")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sift-like-1M-d128")
-    ap.add_argument("--nq", type=int, default=None)
-    ap.add_argument("--beta", type=float, default=None, help="skip the recall calibration")
-    ap.add_argument("--r-min", type=float, default=None)
-    ap.add_argument("--recall-queries", type=int, default=1000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-lowp", action="store_true", help="skip the bf16 / fp8 comparison")
-    ap.add_argument("--lowp", default="bf16,fp8", help="low-precision verification forms")
-    ap.add_argument("--rcap", type=int, default=4, help="rounds resolved (with --beta/--r-min)")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--no-plan", action="store_true", help="skip the graph-launched batch")
-    ap.add_argument("--no-recall", action="store_true",
-                    help="with --beta/--r-min: skip the ground truth (profiling runs)")
-    ap.add_argument("--plan-precision", default="fp32",
-                    help="verification form of the graph-launched batch (fp32, bf16, fp8)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device copy (scales rocprofv3 byte counters)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}))
-        return
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build measures the DET-LSH path on a single "
-              "MI355X (multi-GPU sharding is a design note only). Use --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-
+def measure(w, args, primary, helper=None):
+    """Everything measured on one workload; returns a dict (the primary one becomes the line)."""
     import torch
     from paper_2603_24920_amd import pdet
-    from paper_2603_24920_amd import workloads as wl
 
-    w = wl.WORKLOADS[args.workload]
+    lowp_forms, plan_prec = FORMS.get(w.name, (("bf16",), "fp32"))
+    if args.no_lowp:
+        lowp_forms = ()
+    if args.plan_precision:
+        plan_prec = args.plan_precision
+    if plan_prec != "fp32" and plan_prec not in lowp_forms:
+        lowp_forms = tuple(lowp_forms) + (plan_prec,)
     nq = args.nq or w.nq
     t0 = time.time()
-    big = w.n > BIG_N
+    big = w.n >= GEN_THREADS_N
 
     def gen_progress(done, total):
-        if big and (done % 8 == 0 or done == total):
+        if big and (done % 16 == 0 or done == total):
             log(f"[bench] generating {w.name}: {done}/{total} chunks ({time.time() - t0:.0f}s)")
 
-    X = w.data(threads=16 if w.n >= GEN_THREADS_N else 1, progress=gen_progress)
+    X = w.data(threads=POOL if big else 1, progress=gen_progress)
     A, sid, Q = w.proj(), w.sample(), w.queries(nq)
     log(f"[bench] generated {w.name}: n={w.n} d={w.d} nq={nq} ({time.time() - t0:.1f}s)")
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
     torch.cuda.synchronize()
+    log(f"[bench] data resident on the device ({time.time() - t0:.1f}s)")
     pdet.set_timing(True)
 
     # ---- untimed calibration: index, ground truth, beta / r_min per recall target
-    lowp_forms = [] if args.no_lowp else [f for f in args.lowp.split(",") if f]
     idx = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=tuple(lowp_forms))
     nrec = min(args.recall_queries, nq)
     Qr = Qd[:nrec].contiguous()
     Qp = Qd[:256].contiguous()
-    if not args.no_recall and not big:
-        exact_ids, _ = idx.query(Qr, k=10, c=w.c, beta=1.0, r_min=1e30)
-        exact_ids = exact_ids.cpu().numpy()
-        log(f"[bench] ground truth for {nrec} queries (exhaustive mode)")
-    elif not args.no_recall:
+    exact_ids = None
+    if not args.no_recall:
         exact_ids = brute_force_knn(Xd, Qr, 10)
-        log(f"[bench] ground truth for {nrec} queries (FP64 brute force)")
+        log(f"[bench] FP64 brute-force ground truth for {nrec} queries ({time.time() - t0:.1f}s)")
 
     def calibrate(precision):
         """(beta, r_min, rounds resolved, recall@10) at the smallest beta reaching 0.9."""
@@ -180,7 +151,7 @@ def main():
             ids, _ = idx.query(Qr, k=w.k, c=w.c, beta=beta, r_min=t["r_min"],
                                precision=precision, rescore=4)
             rec = recall_at(ids.cpu().numpy(), exact_ids)
-            log(f"[bench] {precision} beta={beta} r_min={t['r_min']:.4g} "
+            log(f"[bench] {w.name} {precision} beta={beta} r_min={t['r_min']:.4g} "
                 f"rounds_resolved={t['rounds_resolved']} recall@10={rec:.4f}")
             return beta, t["r_min"], t["rounds_resolved"], rec
 
@@ -222,10 +193,10 @@ def main():
         te = time.perf_counter()
         tqt = pdet.get_timing()
         if record is not None:
+            s = st.cpu().numpy()
             record.append(dict(build_s=tr - tb, reserve_s=tq - tr, query_s=te - tq, tb=tbt, tq=tqt,
-                               ncand=st[:, 1].to(torch.int64).sum().item(),
-                               stops=st[:, 2].cpu().numpy(), qtime=st[:, 6].cpu().numpy(),
-                               visits=st[:, 7].cpu().numpy(),
+                               ncand=int(s[:, 1].astype(np.int64).sum()), stops=s[:, 2],
+                               qtime=s[:, 6], visits=s[:, 7], band_leaf=s[:, 8], band_b=s[:, 9],
                                khz=ix.info()["wall_clock_khz"]))
         ix.close()
 
@@ -238,10 +209,13 @@ def main():
         step(recs)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    log(f"[bench] {w.name}: {args.steps} timed steps in {total:.2f}s")
+    bad = sum(int(np.sum(r["stops"] < 0)) for r in recs)
+    if bad:
+        raise SystemExit(f"{bad} queries ended without a stop rule (stop < 0)")
     build_s = float(np.mean([r["build_s"] for r in recs]))
     query_s = float(np.mean([r["query_s"] for r in recs]))
     qps = nq / query_s
-    mpts = w.n / build_s / 1e6
 
     # roofline of q_main: algorithmic bytes = sum_q |S_q| (4d + 4) + (L-1) 4 |S_q|
     ncand = float(np.mean([r["ncand"] for r in recs]))
@@ -253,6 +227,10 @@ def main():
     traffic = pmc_traffic(w.name, nq)
     enc_ms = float(np.mean([r["tb"]["build_encode_ms"] for r in recs]))
     enc_bytes = w.n * (4 * w.d + 16 * w.L)
+    build_bpp = 4 * w.d + 2 * w.L * w.K + 4 * w.L     # read x, write + read codes, write perm
+    build_gbs = w.n * build_bpp / build_s / 1e9
+    bstage = {k: float(np.mean([r["tb"][k] for r in recs]))
+              for k in ("build_sample_ms", "build_sort_ms", "build_encode_ms", "build_tree_ms")}
 
     # resident index with every low-precision copy for the forms below (query phase only)
     ix = pdet.Index(Xd, A, sid, w.K, w.L, w.Nr, w.max_leaf, lowp=tuple(lowp_forms))
@@ -275,169 +253,331 @@ def main():
         sec = timed(lambda: ix.query(Qd, k=w.k, c=w.c, beta=lb, r_min=lr, precision=f,
                                      rescore=4))
         lowp[f] = dict(beta=lb, r_min=lr, rounds_resolved=lc, recall_at_10=lrec, qps=nq / sec,
-                       rescore=4)
-        log(f"[bench] {f}: {lowp[f]}")
+                       rescore=4, speedup_vs_fp32=(nq / sec) / qps)
+        log(f"[bench] {w.name} {f}: {lowp[f]}")
 
     # batching form: one graph-launched batch with k in {1,10,100}, c in {1.2,1.5,2.0}
     batching = None
     if not args.no_plan:
-        ix.set_tuning(r_min, rcap)
         rng = np.random.default_rng(7)
         ks = rng.choice([1, 10, 100], size=nq).astype(np.int32)
         cs = rng.choice([1.2, 1.5, 2.0], size=nq)
-        pp = args.plan_precision
-        pb, pr, pc = (beta, r_min, rcap) if pp == "fp32" else lowp_cal[pp][:3]
+        pb, pr, pc = (beta, r_min, rcap) if plan_prec == "fp32" else lowp_cal[plan_prec][:3]
         ix.set_tuning(pr, pc)
-        plan = ix.plan(Qd, k=0, beta=pb, r_min=pr, k_per_query=ks, c_per_query=cs, precision=pp,
-                       rescore=4)
+        plan = ix.plan(Qd, k=0, beta=pb, r_min=pr, k_per_query=ks, c_per_query=cs,
+                       precision=plan_prec, rescore=4)
         sec_plan = timed(plan.launch)
-        sec_eager = timed(lambda: ix.query(Qd, k=0, beta=pb, r_min=pr, k_per_query=ks,
-                                           c_per_query=cs, precision=pp, rescore=4))
+        pids = plan.ids.cpu().numpy()
         plan.close()
-        batching = dict(qps_graph=nq / sec_plan, qps_eager=nq / sec_eager, precision=pp,
+        sec_eager = timed(lambda: ix.query(Qd, k=0, beta=pb, r_min=pr, k_per_query=ks,
+                                           c_per_query=cs, precision=plan_prec, rescore=4))
+        brec = None
+        if exact_ids is not None:
+            off = np.concatenate([[0], np.cumsum(ks)])
+            sel = [q for q in range(nrec) if ks[q] >= 10]
+            brec = recall_at([pids[off[q]:off[q] + 10] for q in sel], exact_ids[sel])
+        batching = dict(qps_graph=nq / sec_plan, qps_eager=nq / sec_eager, precision=plan_prec,
                         k_mix=[1, 10, 100], c_mix=[1.2, 1.5, 2.0], beta=pb, r_min=pr,
+                        recall_at_10_k_ge_10=brec,
                         search_launches=int(pdet.get_timing()["query_main_launches"]))
-        log(f"[bench] batching: {batching}")
+        log(f"[bench] {w.name} batching: {batching}")
 
-    # serving form: Poisson arrivals into the continuous-batching server
+    # serving form: Poisson arrivals (native client) into the continuous-batching server
     serving = None
     if not args.no_serve:
-        serving = serve_measurement(ix, Q, w, beta, r_min, rcap)
-        log(f"[bench] serving: {serving}")
-        # the low-precision forms served at their own recall-matched beta
+        serving = {"fp32": serve_measurement(ix, Q, w, beta, r_min, rcap)}
+        log(f"[bench] {w.name} serving fp32: {serving['fp32']}")
         for f, (lb, lr, lc, lrec) in lowp_cal.items():
             serving[f] = serve_measurement(ix, Q, w, lb, lr, lc, precision=f)
             serving[f]["recall_at_10"] = lrec
-            log(f"[bench] serving {f}: {serving[f]}")
+            log(f"[bench] {w.name} serving {f}: {serving[f]}")
     ix.close()
+    del Xd
+    torch.cuda.empty_cache()
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w, X, A, sid, Q, beta, r_min)
+    last = recs[-1]
+    out = {
+        "workload": w.name, "n": w.n, "d": w.d, "L": w.L, "K": w.K, "Nr": w.Nr,
+        "max_leaf": w.max_leaf, "nq": nq, "k": w.k, "c": w.c, "beta": beta, "r_min": r_min,
+        "rounds_resolved": rcap, "verify": "fp32 (fp64 accumulate)",
+        "qps": qps, "recall_at_10": rec, "recall_queries": nrec,
+        "recall_ground_truth": "FP64 brute force over all n points",
+        "build_mpts_per_s": w.n / build_s / 1e6, "build_ms": 1e3 * build_s,
+        "build_stage_ms": bstage, "query_ms": 1e3 * query_s,
+        "reserve_ms": 1e3 * float(np.mean([r["reserve_s"] for r in recs])),
+        "step_ms": 1e3 * total / args.steps,
+        "mean_candidates_per_query": ncand / nq,
+        "queries_answered_again": int(last["tq"].get("query_retried", 0)),
+        "stop_rule_A_fraction": float(np.mean([np.mean(r["stops"] == 1) for r in recs])),
+        "band": {"leaf_edge_pairs_per_query": float(last["band_leaf"].mean()),
+                 "queries_with_leaf_edge_tie": int(np.sum(last["band_leaf"] > 0)),
+                 "queries_with_stop_b_tie": int(np.sum(last["band_b"] > 0))},
+        "per_query_search_us": {
+            "p50": float(np.percentile(last["qtime"], 50) * 1e3 / last["khz"]),
+            "p99": float(np.percentile(last["qtime"], 99) * 1e3 / last["khz"]),
+            "max": float(last["qtime"].max() * 1e3 / last["khz"])},
+        "mean_point_visits_per_query": float(last["visits"].mean()),
+        "roofline": {"bound": "hbm", "kernel": "q_main_f32", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": bytes_alg,
+                     "ms_per_launch": main_ms, "launches_per_batch": launches},
+        "roofline_build": {"bound": "hbm", "achieved": build_gbs, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": build_gbs / HBM_PEAK_GBS,
+                           "bytes_per_point": build_bpp,
+                           "note": "whole build (host gaps included): read x, write and read "
+                                   "codes, write perm"},
+        "roofline_build_encode": {"bound": "mfma", "kernel": "project_kernel(encode)",
+                                  "achieved_gbs": enc_bytes / (enc_ms * 1e-3) / 1e9,
+                                  "ms": enc_ms,
+                                  "tflops": 2.0 * w.n * w.d * 16 * w.L / (enc_ms * 1e-3) / 1e12,
+                                  "tflops_peak_fp32": 157.3},
+        "lowp": lowp,
+        "batching": batching,
+        "serving": serving,
+    }
+    if primary and helper is not None:
+        n_cpu = min(w.n, 1 << 20)
+        cpu = helper.run(workload=w.name, nq=nq, beta=beta, r_min=r_min)
+        if cpu.get("data_sha16") not in (None, hashlib.sha256(X[:n_cpu].tobytes()).hexdigest()[:16]):
+            cpu = {"error": "the oracle's sample differs from the benchmark's data"}
+        out["cpu_baseline"] = cpu
+    del X
+    return out
 
+
+def serve_measurement(ix, Q, w, beta, r_min, rcap, seconds=1.0, max_batch=1024,
+                      precision="fp32"):
+    """Saturation QPS from a burst, then Poisson arrivals at 25/50/90% of it offered by the
+    library's native client: p50 / p99 latency and achieved QPS."""
+    ix.set_tuning(r_min, rcap)
+    out = {"precision": precision}
+    kw = dict(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min,
+              precision=precision)
+    # untimed warm-up server: first-use costs (workspace, code loading) stay out of the burst
+    sv = ix.server(**kw)
+    sv.offer_poisson(Q[:256], 256, 1e7, w.k, w.c, seed=1)
+    sv.close()
+    sv = ix.server(**kw)
+    n_burst = min(len(Q), 4096)
+    t0 = time.perf_counter()
+    sv.offer_poisson(Q[:n_burst], n_burst, 1e9, w.k, w.c, seed=2)   # all at once
+    sat = n_burst / (time.perf_counter() - t0)
+    out["burst"] = dict(sv.stats(), requests=n_burst)
+    sv.close()
+    for i, frac in enumerate((0.25, 0.5, 0.9)):
+        rate = frac * sat
+        sv = ix.server(**kw)
+        nreq = max(200, int(rate * seconds))
+        offered = sv.offer_poisson(Q, nreq, rate, w.k, w.c, seed=11 + i)
+        st = sv.stats()
+        sv.close()
+        out[f"poisson_{int(frac * 100)}pct"] = dict(target_qps=rate, offered_qps=offered,
+                                                    achieved_qps=st["qps"], p50_ms=st["p50_ms"],
+                                                    p99_ms=st["p99_ms"],
+                                                    mean_batch=st["mean_batch"], requests=nreq)
+    out["saturation_qps_burst"] = sat
+    return out
+
+
+def _oracle_queries(args):
+    """Worker: oracle queries of one share (the index is inherited through fork)."""
+    import oracle
+    lo, hi = args
+    g = _ORACLE_JOB
+    out = []
+    for q in g["Q"][lo:hi]:
+        r = oracle.query(g["idx"], g["X"], q, g["k"], g["c"], g["beta"], g["r_min"], g["eps"])
+        out.append((r.ids, r.n_cand, r.stop, r.rounds))
+    return out
+
+
+def _oracle_tree(i):
+    import oracle
+    g = _ORACLE_JOB
+    return oracle.build_tree(g["codes"][i], g["Nr"], g["max_leaf"])
+
+
+_ORACLE_JOB = {}
+
+
+def cpu_baseline_job(workload, nq, beta, r_min, n_cpu_max=1 << 20, nq_cpu=200):
+    """The FP64 oracle on this host on a bounded sample of the workload: its own index over
+    the first n_cpu points (one generator chunk, drawn here from the same seeds; breakpoints
+    from its own sample of them) with the GPU's beta and r_min, then nq_cpu queries of the
+    batch. Run once on one thread and once on all worker processes (trees, then queries, in
+    parallel), with identical outputs asserted. Runs in a process that never touched the GPU."""
+    import multiprocessing as mp
+
+    import oracle
+    from paper_2603_24920_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
+    w = wl.WORKLOADS[workload]
+    n_cpu = min(w.n, n_cpu_max)
+    Xs = w.data(n=n_cpu)
+    Q = w.queries(nq)[:nq_cpu]
+    sid = wl.sample_ids(n_cpu, wl.sample_size(n_cpu, w.sample_frac, w.Nr), w.seeds["sample"])
+    A = w.proj()
+    eps = oracle.epsilon(w.K, w.L)
+    # one thread
+    t0 = time.perf_counter()
+    idx = oracle.build_index(Xs, A, sid, w.L, w.K, w.Nr, w.max_leaf)
+    tb1 = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    res1 = []
+    for q in Q:
+        r = oracle.query(idx, Xs, q, w.k, w.c, beta, r_min, eps)
+        res1.append((r.ids, r.n_cand, r.stop, r.rounds))
+    tq1 = time.perf_counter() - t1
+    # all worker processes: independent trees, then independent queries
+    cores = min(POOL, os.cpu_count() or 1)
+    _ORACLE_JOB.update(idx=idx, X=Xs, Q=Q, k=w.k, c=w.c, beta=beta, r_min=r_min, eps=eps,
+                       Nr=w.Nr, max_leaf=w.max_leaf)
+    ctx = mp.get_context("fork")
+    t2 = time.perf_counter()
+    H = oracle.project(Xs, A)
+    B = oracle.breakpoints(H[sid], w.Nr, H.min(axis=0), H.max(axis=0))
+    codes = oracle.encode(H, B, w.L, w.K)
+    del H
+    _ORACLE_JOB["codes"] = codes
+    with ctx.Pool(min(cores, w.L)) as pool:
+        trees = pool.map(_oracle_tree, range(w.L))
+    tbp = time.perf_counter() - t2
+    same_build = np.array_equal(codes, idx.codes) and all(
+        np.array_equal(a.perm, b.perm) for a, b in zip(trees, idx.trees))
+    shares = [(i * nq_cpu // cores, (i + 1) * nq_cpu // cores) for i in range(cores)]
+    t3 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        resp = [r for part in pool.map(_oracle_queries, shares) for r in part]
+    tqp = time.perf_counter() - t3
+    same_query = all(np.array_equal(a[0], b[0]) and a[1:] == b[1:] for a, b in zip(res1, resp))
+    _ORACLE_JOB.clear()
+    if not (same_build and same_query):
+        return {"error": "the oracle's all-core run differs from its one-thread run"}
+    return {"value": nq_cpu / tqp, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nq_cpu} queries of the {w.name} batch on the oracle's own index over the "
+                      f"first {n_cpu} points (beta={beta:g}, r_min={r_min:.4g} as on the GPU; "
+                      f"FP64 numpy); value on {cores} worker processes, outputs identical to "
+                      f"one thread",
+            "data_sha16": hashlib.sha256(Xs.tobytes()).hexdigest()[:16],
+            "one_thread": {"queries_per_s": nq_cpu / tq1, "build_mpts_per_s": n_cpu / tb1 / 1e6,
+                           "cores": 1},
+            "all_cores": {"queries_per_s": nq_cpu / tqp, "build_mpts_per_s": n_cpu / tbp / 1e6,
+                          "cores": cores, "build_parallel_over": "trees",
+                          "query_parallel_over": "queries"}}
+
+
+def _helper_main(conn):
+    while True:
+        job = conn.recv()
+        if job is None:
+            break
+        try:
+            conn.send(cpu_baseline_job(**job))
+        except Exception as e:  # pragma: no cover
+            conn.send({"error": repr(e)})
+
+
+class OracleHelper:
+    """A process forked before this one touches the GPU, which runs the oracle baseline (and
+    forks its own workers) without any inherited GPU state."""
+
+    def __init__(self):
+        import multiprocessing as mp
+        ctx = mp.get_context("fork")
+        self.conn, child = ctx.Pipe()
+        self.proc = ctx.Process(target=_helper_main, args=(child,))
+        self.proc.start()
+
+    def run(self, **job):
+        self.conn.send(job)
+        return self.conn.recv()
+
+    def close(self):
+        try:
+            self.conn.send(None)
+        except Exception:  # pragma: no cover
+            pass
+        self.proc.join(timeout=30)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sift-like-100M-d128")
+    ap.add_argument("--secondary", default="sift-like-1M-d128",
+                    help="comma-separated workloads measured after the primary ('' for none)")
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--beta", type=float, default=None, help="skip the recall calibration")
+    ap.add_argument("--r-min", type=float, default=None)
+    ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lowp", action="store_true", help="skip the low-precision forms")
+    ap.add_argument("--rcap", type=int, default=4, help="rounds resolved (with --beta/--r-min)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-plan", action="store_true", help="skip the graph-launched batch")
+    ap.add_argument("--no-recall", action="store_true",
+                    help="with --beta/--r-min: skip the ground truth (profiling runs)")
+    ap.add_argument("--plan-precision", default=None,
+                    help="verification form of the graph-launched batch (fp32, bf16, fp8)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scales rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}))
+        return
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build measures the DET-LSH path on a single "
+              "MI355X (multi-GPU sharding is a design note only). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2603_24920_amd import workloads as wl
+    t_all = time.time()
+    helper = None if args.no_cpu_baseline else OracleHelper()   # before any GPU use
+    try:
+        prim = measure(wl.WORKLOADS[args.workload], args, primary=True, helper=helper)
+        secondary = {}
+        for name in [s for s in args.secondary.split(",") if s and s != args.workload]:
+            secondary[name] = measure(wl.WORKLOADS[name], args, primary=False)
+    finally:
+        if helper is not None:
+            helper.close()
+    cpu = prim.pop("cpu_baseline", None)
     out = {
         "metric": METRIC,
-        "value": qps,
+        "value": prim["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
+        "ms_per_step": prim["step_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "d": w.d, "L": w.L, "K": w.K, "Nr": w.Nr,
-                   "max_leaf": w.max_leaf, "nq": nq, "k": w.k, "c": w.c, "beta": beta,
-                   "r_min": r_min, "rounds_resolved": rcap,
-                   "verify": "fp32 (fp64 accumulate)"},
-        "recall_at_10": rec,
-        "build_mpts_per_s": mpts,
-        "build_ms": 1e3 * build_s,
-        "query_ms": 1e3 * query_s,
-        "reserve_ms": 1e3 * float(np.mean([r["reserve_s"] for r in recs])),
-        "mean_candidates_per_query": ncand / nq,
-        "queries_answered_again": int(recs[-1]["tq"].get("query_retried", 0)),
-        "stop_rule_A_fraction": float(np.mean([np.mean(r["stops"] == 1) for r in recs])),
-        "per_query_search_us": {
-            "p50": float(np.percentile(recs[-1]["qtime"], 50) * 1e3 / recs[-1]["khz"]),
-            "p99": float(np.percentile(recs[-1]["qtime"], 99) * 1e3 / recs[-1]["khz"]),
-            "max": float(recs[-1]["qtime"].max() * 1e3 / recs[-1]["khz"])},
-        "mean_point_visits_per_query": float(recs[-1]["visits"].mean()),
-        "roofline": {"bound": "hbm", "kernel": "q_main_f32", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": bytes_alg,
-                     "ms_per_launch": main_ms},
-        "roofline_build_encode": {"bound": "mfma", "kernel": "project_kernel(encode)",
-                                  "achieved_gbs": enc_bytes / (enc_ms * 1e-3) / 1e9,
-                                  "ms": enc_ms,
-                                  "tflops": 2.0 * w.n * w.d * 16 * w.L / (enc_ms * 1e-3) / 1e12},
-        "lowp": lowp,
-        "batching": batching,
-        "serving": serving,
-        "cpu_baseline": cpu,
+        "config": {k: prim[k] for k in ("workload", "n", "d", "L", "K", "Nr", "max_leaf", "nq",
+                                        "k", "c", "beta", "r_min", "rounds_resolved", "verify")},
     }
+    out.update({k: v for k, v in prim.items() if k not in out["config"] and k != "qps"})
+    out["roofline"] = prim["roofline"]
+    out["cpu_baseline"] = cpu
+    out["secondary"] = secondary
+    out["bench_wall_s"] = time.time() - t_all
     print(json.dumps(out), flush=True)
-
-
-def serve_measurement(ix, Q, w, beta, r_min, rcap, seconds=1.0, max_batch=1024,
-                      precision="fp32"):
-    """Saturation QPS from a burst, then Poisson arrivals at fractions of it (capped by
-    what one Python client thread can submit): p50 / p99 latency and achieved QPS."""
-    ix.set_tuning(r_min, rcap)
-    out = {"precision": precision}
-    # untimed warm-up server: first-use costs (workspace, code loading) stay out of the burst
-    sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min,
-                   precision=precision)
-    for r in [sv.submit(Q[i % len(Q)], w.k, w.c) for i in range(256)]:
-        sv.wait(r, w.k)
-    sv.close()
-    sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min,
-                   precision=precision)
-    n_burst = min(len(Q), 4096)
-    t0 = time.perf_counter()
-    rids = [sv.submit(Q[i], w.k, w.c) for i in range(n_burst)]
-    for r in rids:
-        sv.wait(r, w.k)
-    sat = n_burst / (time.perf_counter() - t0)
-    out["burst"] = dict(sv.stats(), requests=n_burst)
-    sv.close()
-    client_cap = 50000.0
-    rng = np.random.default_rng(11)
-    for frac in (0.25, 0.5, 0.9):
-        rate = min(frac * sat, client_cap)
-        sv = ix.server(max_batch=max_batch, lanes=2, k_max=w.k, beta=beta, r_min=r_min,
-                       precision=precision)
-        nreq = max(200, int(rate * seconds))
-        gaps = rng.exponential(1.0 / rate, size=nreq)
-        t_arr = np.cumsum(gaps)
-        rids = []
-        t0 = time.perf_counter()
-        for i in range(nreq):
-            while time.perf_counter() - t0 < t_arr[i]:
-                pass
-            rids.append(sv.submit(Q[i % len(Q)], w.k, w.c))
-        for r in rids:
-            sv.wait(r, w.k)
-        st = sv.stats()
-        sv.close()
-        out[f"poisson_{int(frac * 100)}pct"] = dict(offered_qps=rate, achieved_qps=st["qps"],
-                                                    p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
-                                                    mean_batch=st["mean_batch"], requests=nreq)
-    out["saturation_qps_burst"] = sat
-    out["note"] = "offered rate capped at 50k/s by the single Python client thread"
-    return out
-
-
-def cpu_baseline(w, X, A, sid, Q, beta, r_min, nq_cpu=20):
-    """The FP64 oracle, single-threaded, on this host: full index build over the same data,
-    then `nq_cpu` queries of the batch with the GPU's beta and r_min."""
-    import oracle
-    from paper_2603_24920_amd import workloads as wl
-    try:
-        from threadpoolctl import threadpool_limits
-        lim = threadpool_limits(1)
-    except Exception:  # pragma: no cover
-        lim = None
-    # bounded sample: the oracle's index over at most 2e8 coordinates of the same data
-    n_cpu = min(w.n, int(2e8 // w.d))
-    if n_cpu < w.n:
-        X = X[:n_cpu]
-        sid = wl.sample_ids(n_cpu, wl.sample_size(n_cpu, w.sample_frac, w.Nr), w.seeds["sample"])
-    t0 = time.perf_counter()
-    idx = oracle.build_index(X, A, sid, w.L, w.K, w.Nr, w.max_leaf)
-    tb = time.perf_counter() - t0
-    eps = oracle.epsilon(w.K, w.L)
-    t1 = time.perf_counter()
-    for q in Q[:nq_cpu]:
-        oracle.query(idx, X, q, w.k, w.c, beta, r_min, eps)
-    tq = time.perf_counter() - t1
-    if lim is not None:
-        lim.unregister() if hasattr(lim, "unregister") else None
-    return {"value": nq_cpu / tq, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nq_cpu} queries of the {w.name} batch on the oracle's own index over "
-                      f"the first {n_cpu} points (build {tb:.1f}s = {n_cpu / tb / 1e6:.3f} Mpts/s, "
-                      f"single thread, FP64)",
-            "build_mpts_per_s": n_cpu / tb / 1e6}
 
 
 if __name__ == "__main__":

@@ -88,7 +88,9 @@ void pdet_free(pdet_index* idx);
  * Query parameters (c^2-k-ANN query, Algorithm 5, Section 3.3).
  *   k, c          uniform k >= 1 and c > 1, used when the per-query arrays are NULL.
  *   k_per_query   host int32 [nq] or NULL; c_per_query host double [nq] or NULL.
- *   beta          stop rule A fires once |S| >= ceil(beta*n) + k (beta >= 0).
+ *   beta          stop rule A fires once |S| >= ceil(beta*n) + k (beta >= 0). beta < 0
+ *                 selects the theoretical value of Lemma 3 for each query's c,
+ *                 2 - 2 alpha2^L with c^2 chi2_{alpha2}(K) = eps^2 (pdet_theoretical_beta).
  *   r_min         first search radius; radii r_min*c^rho for rho < 255. <= 0 selects the
  *                 index's tuned value (pdet_autotune).
  *   eps           projected-radius factor; <= 0 selects sqrt(chi2 upper quantile of
@@ -166,7 +168,7 @@ pdet_status pdet_query_candidates(const pdet_index* idx, const float* queries, i
  * Algorithm 5 needs this scratch, and a caller that serves a resident index wants it sized
  * once, before the first batch. Device memory is taken with hipMalloc (or from the block
  * cache, see pdet_release_cache) and kept until pdet_free; at most a third of free device
- * memory (and 24 GiB, unless the index is large enough for capped leaf lists, see
+ * memory (and 48 GiB, unless the index is large enough for capped leaf lists, see
  * pdet_set_list_cap) is used, so large batches are then run in chunks of query slots.
  * Waits for `stream`. nq < 0 -> PDET_EINVAL. */
 pdet_status pdet_reserve(pdet_index* idx, int64_t nq, void* stream);
@@ -328,6 +330,22 @@ pdet_status pdet_server_wait(pdet_server* sv, int64_t request_id, int64_t* ids, 
                              double* latency_ms);
 pdet_status pdet_server_get_stats(pdet_server* sv, pdet_server_stats* out);
 void pdet_server_free(pdet_server* sv);   /* drains queued requests first */
+
+/* Load generator for measuring a server (not part of the method): a native client that
+ * submits nreq requests at the arrival times of a Poisson process of rate_qps requests per
+ * second (exponential gaps drawn from a 64-bit Mersenne twister seeded with `seed`),
+ * request i being host query (i mod m) of queries (float32 [m][d]) with the given k and c,
+ * then waits for every one of them (results are discarded; the server's statistics hold
+ * their latencies). offered_qps (may be NULL) receives the rate actually offered, measured
+ * between the first and the last submission. Blocks the calling thread until all are done. */
+pdet_status pdet_server_offer_poisson(pdet_server* sv, const float* queries, int64_t m,
+                                      int64_t nreq, double rate_qps, int32_t k, double c,
+                                      uint64_t seed, double* offered_qps);
+
+/* beta = 2 - 2 alpha2^L of Lemma 3 (Section 5.1), where alpha2 = Pr[chi2(K) > eps^2 / c^2] and
+ * eps^2 = chi2_{alpha1}(K), alpha1 = exp(-1/L): the theoretical false-positive fraction that
+ * queries use when beta < 0 (Section 5.2.1, Figure "betal"). NaN for K < 1, L < 1, c <= 1. */
+double pdet_theoretical_beta(int32_t K, int32_t L, double c);
 
 /* eps = sqrt(chi2 upper exp(-1/L) quantile, K dof) from Eq. 2 / Lemma 3; NaN if invalid. */
 double pdet_epsilon(int32_t K, int32_t L);

@@ -474,3 +474,82 @@ def overall_ratio(dists, exact_dists) -> float:
     with np.errstate(divide="ignore", invalid="ignore"):
         r = np.where(e > 0, d / e, 1.0)
     return float(r.mean())
+
+
+# ------------------------------------------- parameters and radius schedule (Section 5.2)
+def candidate_count(index: Index, q, r: float, eps: float) -> int:
+    """|S| after one full round at radius r with no stop rule: the points whose leaf lower
+    bound in some tree is within eps*r (relaxed admission, Section 6.2.2)."""
+    qp = np.asarray(q, dtype=np.float64) @ index.A
+    t2 = (eps * r) ** 2
+    inS = np.zeros(index.n, dtype=bool)
+    for i in range(index.L):
+        tr = index.trees[i]
+        lo, hi = index.boxes[i]
+        lb2 = lower_bound_sq(qp[i * index.K:(i + 1) * index.K], lo, hi)
+        for leaf in np.nonzero(lb2 <= t2)[0]:
+            inS[tr.perm[tr.leaf_start[leaf]:tr.leaf_start[leaf] + tr.leaf_count[leaf]]] = True
+    return int(inS.sum())
+
+
+def magic_r_min(index: Index, q, k: int, beta: float, c: float, eps: float, r0: float,
+                max_steps: int = 254):
+    """The "magic" r_min of the parameter settings (Section 5.2.1) on the grid r0 * c^j:
+    the smallest grid radius at which |S| >= beta*n + k, so that at one grid step below it
+    |S| < beta*n + k. Returns (j, r) or None if the grid runs out."""
+    T = math.ceil(beta * index.n) + k
+    r = r0
+    for j in range(max_steps + 1):
+        if candidate_count(index, q, r, eps) >= T:
+            return j, r
+        r = c * r
+    return None
+
+
+def autotune_first_radius(B: np.ndarray, K: int, L: int) -> float:
+    """First pilot radius of the dataset-level schedule: its projected threshold eps*r0 is
+    1e-4 of the median breakpoint range (B(Nr+1) - B(1)) over the L*K columns (the upper
+    median for an even count)."""
+    rng = np.sort(np.asarray(B, dtype=np.float64)[:, -1] - np.asarray(B, dtype=np.float64)[:, 0])
+    return max(1e-30, 1e-4 * rng[len(rng) // 2] / epsilon(K, L))
+
+
+def autotune_r_min(index: Index, X, pilots, k: int, c: float, beta: float, eps: float,
+                   r0: float) -> float:
+    """Dataset-level r_min from pilot queries (a reading of Section 5.2.1, which defines the
+    magic r_min per query): run Algorithm 5 from r0 for every pilot, take the median number
+    of rounds started over the pilots (the upper median) and return the radius one grid
+    step below the median terminating radius, r0 * c^max(0, median - 2). For a pilot that
+    stops by rule A the terminating radius is its magic r_min on the r0 grid."""
+    rounds = sorted(query(index, X, q, k, c, beta, r0, eps).rounds for q in pilots)
+    med = rounds[len(rounds) // 2]
+    r = r0
+    for _ in range(max(0, med - 2)):
+        r = c * r
+    return r
+
+
+def theoretical_beta_for(K: int, L: int, c) -> np.ndarray:
+    """beta of Lemma 3 for each c (the library's theoretical mode takes it per query)."""
+    return np.array([theoretical_beta(K, L, float(x)) for x in np.atleast_1d(c)])
+
+
+# ------------------------------------------------ static encoding (Section 3.1, contrast)
+def static_breakpoints(H_sample: np.ndarray, Nr: int, col_min: np.ndarray,
+                       col_max: np.ndarray) -> np.ndarray:
+    """Static iSAX breakpoints (the scheme the encoding phase contrasts with its dynamic
+    one): interior breakpoints at the equal-mass quantiles of N(0,1), b_z = Phi^-1(z/Nr),
+    applied to each projected coordinate after normalising it by its sampled mean and
+    standard deviation (iSAX assumes normalised values): B(z) = mu + sigma * Phi^-1((z-1)/Nr)
+    for z = 2..Nr. B(1) and B(Nr+1) are the column min and max over all points, as for the
+    dynamic scheme. Returns FP64 [L*K][Nr+1]."""
+    from scipy.stats import norm
+    H = np.asarray(H_sample, dtype=np.float64)
+    mu = H.mean(axis=0)
+    sd = H.std(axis=0)
+    z = norm.ppf(np.arange(1, Nr) / Nr)
+    B = np.empty((H.shape[1], Nr + 1), dtype=np.float64)
+    B[:, 0] = col_min
+    B[:, 1:Nr] = mu[:, None] + sd[:, None] * z[None, :]
+    B[:, Nr] = col_max
+    return B

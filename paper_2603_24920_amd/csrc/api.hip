@@ -130,7 +130,7 @@ QueryConfig check_query(const pdet_index* idx, const float* queries, int64_t nq,
   PDET_REQUIRE(idx && p, PDET_EINVAL, "NULL argument");
   PDET_REQUIRE(nq >= 0, PDET_EINVAL, "nq must be >= 0");
   PDET_REQUIRE(nq == 0 || (queries && ids && dists), PDET_EINVAL, "NULL queries or outputs");
-  PDET_REQUIRE(p->beta >= 0.0 && std::isfinite(p->beta), PDET_EINVAL, "beta must be >= 0");
+  PDET_REQUIRE(std::isfinite(p->beta), PDET_EINVAL, "beta must be finite");
   double r_min = p->r_min;
   if (r_min <= 0.0) {
     PDET_REQUIRE(idx->tuned_r_min > 0.0, PDET_EINVAL,
@@ -207,6 +207,14 @@ Span::~Span() {
   if (b_) (void)hipEventDestroy(b_);
 }
 
+// Lemma 3 / Eq. 2: with eps^2 = chi2_{alpha1}(K) and c^2 chi2_{alpha2}(K) = eps^2, the false
+// positive fraction is beta = 2 - 2 alpha2^L, alpha2 = Pr[chi2(K) > eps^2 / c^2].
+double theoretical_beta(int K, int L, double c) {
+  const double e = epsilon(K, L);
+  const double alpha2 = 1.0 - gamma_p(0.5 * K, 0.5 * e * e / (c * c));
+  return 2.0 - 2.0 * std::pow(alpha2, (double)L);
+}
+
 // eps^2 is the upper alpha1 quantile of chi2(K), alpha1 = exp(-1/L) (Eq. 2, Lemma 3):
 // solve 1 - P(K/2, x/2) = alpha1 by bisection.
 double epsilon(int K, int L) {
@@ -219,6 +227,46 @@ double epsilon(int K, int L) {
   }
   return std::sqrt(0.5 * (lo + hi));
 }
+
+namespace {
+class ScratchPool {
+ public:
+  DevBuf take(size_t b) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (size_t i = 0; i < free_.size(); ++i)
+        if (free_[i].bytes == b) {
+          DevBuf d = std::move(free_[i]);
+          free_.erase(free_.begin() + (int64_t)i);
+          held_ -= b;
+          return d;
+        }
+    }
+    return DevBuf(b);
+  }
+  void give(DevBuf&& d) {
+    if (!d.p) return;
+    if (std::uncaught_exceptions() > 0) { d.release(); return; }
+    std::lock_guard<std::mutex> g(mu_);
+    if (held_ + d.bytes > kPoolCap) { d.release(); return; }
+    held_ += d.bytes;
+    free_.push_back(std::move(d));
+  }
+ private:
+  static constexpr size_t kPoolCap = size_t(2) << 30;
+  std::mutex mu_;
+  std::vector<DevBuf> free_;
+  size_t held_ = 0;
+};
+
+ScratchPool& scratch_pool() {
+  static ScratchPool* p = new ScratchPool();   // lives until the process ends
+  return *p;
+}
+}  // namespace
+
+DevBuf pool_take(size_t bytes) { return scratch_pool().take(bytes); }
+void pool_give(DevBuf&& d) { scratch_pool().give(std::move(d)); }
 
 }  // namespace pdet
 
@@ -237,6 +285,11 @@ using namespace pdet;
 extern "C" {
 
 const char* pdet_last_error(void) { return g_last_error.c_str(); }
+
+double pdet_theoretical_beta(int32_t K, int32_t L, double c) {
+  if (K < 1 || L < 1 || !(c > 1.0) || !std::isfinite(c)) return std::numeric_limits<double>::quiet_NaN();
+  return pdet::theoretical_beta(K, L, c);
+}
 
 double pdet_epsilon(int32_t K, int32_t L) {
   if (K < 1 || L < 1) return std::numeric_limits<double>::quiet_NaN();
@@ -262,13 +315,6 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
                  "n_sample must be in [Nr, n]");
     PDET_REQUIRE((p->lowp_copies & ~((1u << PDET_BF16) | (1u << PDET_FP8_E4M3))) == 0,
                  PDET_EINVAL, "unknown lowp_copies bit");
-    {
-      // the column sort runs up to one work-item per sampled key; a dispatch holds < 2^32
-      int64_t sp = 1;
-      while (sp < p->n_sample) sp <<= 1;
-      PDET_REQUIRE((int64_t)p->L * p->K * sp < (int64_t(1) << 32), PDET_EUNSUPPORTED,
-                   "L * K * n_sample (rounded up to a power of two) must be below 2^32");
-    }
     for (int64_t i = 0; i < p->n_sample; ++i)
       PDET_REQUIRE(p->sample_ids[i] >= 0 && p->sample_ids[i] < n, PDET_EINVAL,
                    "sample id out of range");
@@ -291,11 +337,10 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     const std::vector<float> Ap = pad_projection(p->proj, d, ix->L, ix->K);
     ix->A.alloc(Ap.size() * 4);
     PDET_HIP(hipMemcpyAsync(ix->A.p, Ap.data(), Ap.size() * 4, hipMemcpyHostToDevice, s));
-    DevBuf sid((size_t)p->n_sample * 8);
-    PDET_HIP(hipMemcpyAsync(sid.p, p->sample_ids, sid.bytes, hipMemcpyHostToDevice, s));
-    int64_t npad = 1;
-    while (npad < p->n_sample) npad <<= 1;
-    DevBuf ps((size_t)LK * npad * 4);
+    std::vector<PooledBuf> temps;   // build temporaries, held until the final synchronisation
+    PooledBuf sid((size_t)p->n_sample * 8);
+    PDET_HIP(hipMemcpyAsync(sid.ptr(), p->sample_ids, sid.bytes(), hipMemcpyHostToDevice, s));
+    PooledBuf ps((size_t)LK * p->n_sample * 4);   // sampled hash values, column-major
     pdet_timing& tm = timer().t;
     if (timer().on) {
       tm.build_sample_ms = tm.build_sort_ms = tm.build_encode_ms = 0.0;
@@ -304,14 +349,13 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     ix->B.alloc((size_t)LK * (ix->Nr + 1) * 4);
     {
       Span sp(s, &tm.build_sample_ms);
-      fill_f32(ps.as<float>(), (int64_t)LK * npad, INFINITY, s);
-      project_sample(*ix, sid.as<int64_t>(), p->n_sample, ps.as<float>(), npad, s);
+      project_sample(*ix, sid.as<int64_t>(), p->n_sample, ps.as<float>(), p->n_sample, s);
       sp.finish();
     }
     {
       Span sp(s, &tm.build_sort_ms);
-      sort_columns(ps.as<float>(), LK, npad, s);
-      pick_breakpoints(ps.as<float>(), LK, npad, p->n_sample, ix->Nr, ix->B.as<float>(), s);
+      select_breakpoints(ps.as<float>(), LK, p->n_sample, p->n_sample, ix->Nr,
+                         ix->B.as<float>(), temps, s);
       sp.finish();
     }
 
@@ -320,6 +364,7 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     PDET_HIP(hipMemsetAsync(ix->colmm.p, 0xff, (size_t)LK * 4, s));
     PDET_HIP(hipMemsetAsync(ix->colmm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));
     ix->codes.alloc((size_t)ix->L * n * KP);
+    ix->flkey.alloc((size_t)ix->L * n * 2);
     ix->perm.alloc((size_t)ix->L * n * 4);
     {
       Span sp(s, &tm.build_encode_ms);

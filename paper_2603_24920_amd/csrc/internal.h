@@ -11,6 +11,9 @@
 #include "common.h"
 
 namespace pdet {
+// Length of the per-slot radius tables (255 rounds r_min * c^rho and a sentinel).
+constexpr int NRHO_TABLE = 256;
+
 // Query scratch, kept by the index and reused across calls (see run_query).
 struct QueryWorkspace {
   DevBuf rho, admb, adm2, t2, crr, lcnt, bandc, qp, dk, dc, dT, doff;
@@ -51,6 +54,7 @@ struct pdet_index {
   pdet::DevBuf B;                  // float32 [L*K][Nr+1] breakpoints
   pdet::DevBuf colmm;              // uint32 [2][L*K] ordered min / max of every column
   pdet::DevBuf codes;              // uint8 [L][n][KP]
+  pdet::DevBuf flkey;              // uint16 [L][n] first-layer keys (during the build only)
   pdet::DevBuf perm;               // int32 [L][n]
   pdet::DevBuf leafrow;            // int32 [L][n][L]: for the point at perm position p of tree
                                    // i, its leaf ordinal in every tree (read along leaves)
@@ -107,6 +111,32 @@ class WorkspaceLease {
 namespace pdet {
 using Index = pdet_index;
 
+// Build temporaries come from a process-wide pool (api.hip): they go back only after the
+// build has synchronised its stream (or are freed if an error unwinds the build), so a later
+// build of the same size reuses them without hipMalloc / hipFree. At most 2 GiB are kept.
+DevBuf pool_take(size_t bytes);
+void pool_give(DevBuf&& d);
+
+// A build temporary with DevBuf's interface, taken from and returned to the pool.
+struct PooledBuf {
+  DevBuf d;
+  PooledBuf() = default;
+  explicit PooledBuf(size_t b) { alloc(b); }
+  PooledBuf(PooledBuf&& o) noexcept : d(std::move(o.d)) {}
+  PooledBuf& operator=(PooledBuf&& o) noexcept {
+    if (this != &o) { pool_give(std::move(d)); d = std::move(o.d); }
+    return *this;
+  }
+  ~PooledBuf() { pool_give(std::move(d)); }
+  void alloc(size_t b) {
+    pool_give(std::move(d));
+    if (b) d = pool_take(b);
+  }
+  size_t bytes() const { return d.bytes; }
+  void* ptr() const { return d.p; }
+  template <class T> T* as() const { return d.as<T>(); }
+};
+
 // Per-thread kernel timing (see pdet_set_timing).
 struct Timer {
   bool on = false;
@@ -140,10 +170,12 @@ void project_sample(const Index& ix, const int64_t* rows, int64_t m, float* out,
 void encode_points(const Index& ix, hipStream_t s);
 
 // sort.hip
-void sort_columns(float* keys, int ncols, int64_t npad, hipStream_t s);
+// Interior breakpoints B[col][u] (u = 1..Nr-1) of the sampled hash values keys[col][0..ns)
+// (column stride ld): the exact order statistics of 1-based rank floor(ns/Nr)*u.
+// Temporaries go to `keep`, which the caller holds until its stream has synchronised.
+void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,
+                        std::vector<PooledBuf>& keep, hipStream_t s);
 void fill_f32(float* p, int64_t count, float v, hipStream_t s);
-void pick_breakpoints(const float* sorted, int ncols, int64_t npad, int64_t ns, int Nr,
-                      float* B, hipStream_t s);
 void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, hipStream_t s);
 void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,
                DevBuf& tmp, hipStream_t s);
@@ -184,6 +216,7 @@ void retry_overflowed(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws
 
 // api.hip
 double epsilon(int K, int L);
+double theoretical_beta(int K, int L, double c);
 void clear_error();
 QueryConfig check_query(const pdet_index* idx, const float* queries, int64_t nq,
                         const pdet_query_params* p, int64_t* ids, float* dists, int32_t* qstats,

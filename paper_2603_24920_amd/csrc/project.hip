@@ -39,6 +39,8 @@ struct ProjArgs {
   // MODE_ENCODE
   const float* Btab;       // [L*K][Nr+1]
   uint8_t* codes;          // [L][n][KP]
+  uint16_t* flkey;         // [L][n]: first-layer key (leading code bit of each dimension,
+                           // dimension 0 most significant)
   int64_t n;
   uint32_t* colmin;        // [L*K] ordered-uint min / max
   uint32_t* colmax;
@@ -206,6 +208,11 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
         if (p < a.m) {
           const uint4 v = *reinterpret_cast<const uint4*>(st + (pl * NT + t) * KP);
           *reinterpret_cast<uint4*>(a.codes + ((int64_t)(a.tree0 + t) * a.n + p) * KP) = v;
+          const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+          uint32_t key = 0;
+          for (int j = 0; j < a.K; ++j)
+            key |= ((w[j >> 2] >> (8 * (j & 3) + a.bits - 1)) & 1u) << (a.K - 1 - j);
+          a.flkey[(int64_t)(a.tree0 + t) * a.n + p] = (uint16_t)key;
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -285,6 +292,7 @@ void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* r
     a.out = out; a.ld = ld;
     a.Btab = ix.B.as<float>();
     a.codes = ix.codes.as<uint8_t>();
+    a.flkey = ix.flkey.as<uint16_t>();
     a.colmin = ix.colmm.as<uint32_t>();
     a.colmax = ix.colmm.as<uint32_t>() + ix.L * ix.K;
     // A is stored per launch group: [group][d][NC]

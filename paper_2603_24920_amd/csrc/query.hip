@@ -36,7 +36,7 @@ constexpr int CBMIN = 384;       // least pending-candidate buffer beside the to
 constexpr int QT = 64;           // queries per q_rho block (group tests in sub-tiles of 16)
 constexpr int QR_THREADS = 256;  // leaves per q_rho block (one per thread)
 constexpr int NXCD = 8;          // accelerator dies; workgroup i runs on die i % NXCD
-constexpr int NRHO = 256;        // threshold table length (255 rounds + sentinel)
+constexpr int NRHO = NRHO_TABLE; // threshold table length (255 rounds + sentinel)
 constexpr int GL = 16;           // leaves per pruning group
 constexpr int RCAP_MAX = 8;      // most rounds q_rho resolves (the index's rcap <= this)
 constexpr int RWIN = 3;          // rounds resolved per refinement step inside q_main
@@ -51,6 +51,8 @@ constexpr int WALK_VERIFY = 0, WALK_COUNT = 1, WALK_CUT = 2;
 constexpr int STOP_OVERFLOW = 3; // query-stat stop code: leaf lists overflowed (answered again)
 constexpr float BAND_REL = 1e-5f; // near-tie band: |LB^2 - (eps r)^2| <= BAND_REL (eps r)^2, and
                                  // the k-th squared distance within 2 BAND_REL of (c r)^2
+constexpr double LOWP_SLACK_BF16 = 0.125;  // relative distance slack of the low-precision
+constexpr double LOWP_SLACK_FP8 = 0.5;     // pre-test of stop rule B (bf16 / fp8 e4m3 copies)
 constexpr int LBCH = 4;          // box dimensions q_main loads at a time for a lower bound
 constexpr int RLBCH = 2;         // the same in the (rare) refinement, which is kept lean
 
@@ -91,10 +93,11 @@ struct QArgs {
   const int32_t* leafrow;    // [L][n][L]
   uint32_t* adm_leaf;        // [slots][admcap] leaf lists: tree i from nlo[i]
   uint32_t* adm_w;
-  float* adm_lb;
-  uint32_t* adm2_leaf;       // [slots][admcap + 1]
+  float* adm_lb;             // [slots][admcap] the listed leaf's squared lower bound
+  uint32_t* adm2_leaf;       // [slots][admcap + 1] a round's admitted leaves
   uint32_t* adm2_pre;
   int32_t* adm_start;
+  float* adm2_lb;            // their squared lower bounds
   int64_t admcap;
   int64_t* ids;
   float* dists;
@@ -295,9 +298,11 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
     if (c <= rcap) {
       const uint32_t pos = atomicAdd(&a.lcnt[(int64_t)slot * PDET_MAX_L + tree], 1u);
       // past the region's capacity only the count grows: q_main sees the overflow
-      if (pos < a.lcap[tree])
-        a.adm_leaf[(int64_t)slot * a.admcap + a.nlo[tree] + pos] =
-            ((uint32_t)c << LEAF_BITS) | (uint32_t)leaf;
+      if (pos < a.lcap[tree]) {
+        const int64_t at = (int64_t)slot * a.admcap + a.nlo[tree] + pos;
+        a.adm_leaf[at] = ((uint32_t)c << LEAF_BITS) | (uint32_t)leaf;
+        a.adm_lb[at] = acc;
+      }
     }
   }
 }
@@ -518,7 +523,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
   __shared__ uint32_t s_lco[PDET_MAX_L + 1];     // their prefix (lists in tree order)
   __shared__ uint32_t hkey[HSZ];
   __shared__ uint8_t hrnd[HSZ];
-  __shared__ uint32_t s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix, s_cnt, s_cute, s_clo, s_chi;
+  __shared__ uint32_t s_nb, s_ncb, s_newtot, s_ef, s_hsum, s_hmix, s_cnt, s_cute, s_clo, s_chi, s_cl;
   __shared__ unsigned long long s_cut;
 
   const int slot = blockIdx.x;
@@ -548,10 +553,11 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
 
   uint32_t* adm = a.adm_leaf + (int64_t)slot * a.admcap;
   uint32_t* admw = a.adm_w + (int64_t)slot * a.admcap;
-  float* admlb = a.adm_lb + (int64_t)slot * a.admcap;
+  float* lstlb = a.adm_lb + (int64_t)slot * a.admcap;   // bounds of the list entries
   uint32_t* adm2 = a.adm2_leaf + (int64_t)slot * (a.admcap + 1);
   uint32_t* pre2 = a.adm2_pre + (int64_t)slot * (a.admcap + 1);
   int32_t* ast = a.adm_start + (int64_t)slot * (a.admcap + 1);
+  float* admlb = a.adm2_lb + (int64_t)slot * (a.admcap + 1);  // bounds of the round's leaves
 
   int64_t nS = 0, leaves = 0, visits = 0;
   uint32_t hn = 0;             // leaves in the hash (all admitted in rounds <= rho)
@@ -722,18 +728,18 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
 
   // Puts the entries [e0, e1) of tree i (at most QM) in admission order, ascending
   // (LB^2, leaf ordinal) (keys are distinct within a tree), with their prefix list rebuilt.
-  auto order_entries = [&](uint32_t e0, uint32_t e1, uint32_t P0, int i) {
+  auto order_entries = [&](uint32_t e0, uint32_t e1, uint32_t P0) {
     const uint32_t mi = e1 - e0, e = e0 + tid;
     unsigned long long key = ~0ull;
     uint32_t en = 0, cnt = 0;
     int32_t st0 = 0;
+    float lb = 0.0f;
     if (tid < mi) {
       en = adm2[e];
       st0 = ast[e];
       cnt = pre2[e + 1] - pre2[e];
-      const uint32_t leaf = en & ((1u << TREE_SHIFT) - 1);
-      const float lb = leaf_lb2<2 * LBCH>(a.box[i], a.nl[i], leaf, qps + i * a.K, a.K);
-      key = ((unsigned long long)__float_as_uint(lb) << 32) | leaf;
+      lb = admlb[e];
+      key = ((unsigned long long)__float_as_uint(lb) << 32) | (en & ((1u << TREE_SHIFT) - 1));
     }
     sel_key[tid] = key;
     __syncthreads();
@@ -741,7 +747,12 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     if (tid < mi)
       for (uint32_t u = 0; u < mi; ++u) rank += (sel_key[u] < key) ? 1u : 0u;
     __syncthreads();
-    if (tid < mi) { adm2[e0 + rank] = en; ast[e0 + rank] = st0; sel_w[rank] = cnt; }
+    if (tid < mi) {
+      adm2[e0 + rank] = en;
+      ast[e0 + rank] = st0;
+      admlb[e0 + rank] = lb;
+      sel_w[rank] = cnt;
+    }
     __syncthreads();
     uint32_t tot;
     const uint32_t ex = block_excl_scan<QM>(tid < mi ? sel_w[tid] : 0u, sh_scan, &tot);
@@ -882,7 +893,10 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
                 atomicAdd(&a.bandc[(int64_t)slot * NRHO + rr], 1u);
             if (pos > cap && pos <= ncap) {
               const uint32_t at = atomicAdd(&s_lc[i], 1u);
-              if (at < a.lcap[i]) lst[at] = ((uint32_t)pos << LEAF_BITS) | (uint32_t)leaf;
+              if (at < a.lcap[i]) {
+                lst[at] = ((uint32_t)pos << LEAF_BITS) | (uint32_t)leaf;
+                lstlb[a.nlo[i] + at] = lb2;
+              }
             }
           }
           __syncthreads();
@@ -903,6 +917,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
       s_cnt = 0;
       s_clo = 0;
       s_chi = 0;
+      s_cl = 0;
       s_lco[0] = 0;
       for (int i = 0; i < a.L; ++i) s_lco[i + 1] = s_lco[i] + s_lc[i];
     }
@@ -914,11 +929,13 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
       bool match = false;
       uint32_t en = 0, cnt = 0;
       int32_t st0 = 0;
+      float lbv = 0.0f;
       if (v < E) {
         int tr = 0;
         while (tr + 1 < a.L && s_lco[tr + 1] <= v) ++tr;
         const uint32_t ent = adm[a.nlo[tr] + (v - s_lco[tr])];
         if ((ent >> LEAF_BITS) == (uint32_t)rho) {
+          lbv = lstlb[a.nlo[tr] + (v - s_lco[tr])];
           const uint32_t leaf = ent & ((1u << LEAF_BITS) - 1);
           match = true;
           en = ((uint32_t)tr << TREE_SHIFT) | leaf;
@@ -931,7 +948,12 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
       uint32_t t1, t2;
       const uint32_t pos = block_excl_scan<QM>(match ? 1u : 0u, sh_scan, &t1);
       const uint32_t pre = block_excl_scan<QM>(cnt, sh_scan, &t2);
-      if (match) { adm2[m + pos] = en; pre2[m + pos] = P + pre; ast[m + pos] = st0; }
+      if (match) {
+        adm2[m + pos] = en;
+        pre2[m + pos] = P + pre;
+        ast[m + pos] = st0;
+        admlb[m + pos] = lbv;
+      }
       m += t1;
       P += t2;
     }
@@ -990,7 +1012,7 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           if (nS + pts_i < T || e1 - e0 <= (uint32_t)QM) {
             // whole tree, or its leaves in admission order up to the one where |S| reaches T
             const bool may_stop = nS + pts_i >= T;
-            if (may_stop) order_entries(e0, e1, p0, i);
+            if (may_stop) order_entries(e0, e1, p0);
             nS += traverse(may_stop ? WALK_CUT : WALK_VERIFY, rho, e0, e1, p0, p1,
                            (uint32_t)(T - nS), ce);
             if (ce != NO_CUT) {
@@ -1003,10 +1025,6 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           }
           // more leaves than one ordering pass takes: count new points per leaf over a
           // bounded prefix, then select the leaf by key
-          for (uint32_t e = e0 + tid; e < e1; e += QM)
-            admlb[e] = leaf_lb2<LBCH>(a.box[i], a.nl[i], adm2[e] & ((1u << TREE_SHIFT) - 1),
-                                      qps + i * a.K, a.K);
-          __syncthreads();
           uint32_t e1c = e1;
           if (pts_i >= T) {
             // A tree's leaves are disjoint, so at most |S| of their points are already in S:
@@ -1053,13 +1071,24 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
           chi += (v <= bhi) ? 1u : 0u;
         }
       } else {
-        // Low-precision distances only rank the candidates: the kept list (the best
-        // k * rescore of S by them) is counted by exact float32 distance, so quantisation
-        // error does not move the round in which the rule fires.
-        if (uni(s_ncb) > 0) merge();
+        // Low-precision distances rank the candidates. The rule is tested on them first,
+        // against (c r)^2 widened by the format's error (LOWP_SLACK); when that count
+        // reaches k, the rule is decided on exact float32 distances of the kept list (the
+        // best k * rescore of S by low-precision distance), so quantisation error neither
+        // stops a query that the exact count would not stop nor, unless a kept candidate's
+        // error exceeds the slack, keeps one running that it would stop.
+        const double slack = (PREC == PDET_BF16) ? LOWP_SLACK_BF16 : LOWP_SLACK_FP8;
+        const double crr_wide = crr * (1.0 + slack) * (1.0 + slack);
+        const uint32_t tot = (uint32_t)KL + uni(s_ncb);
+        uint32_t cl = 0;
+        for (uint32_t e = tid; e < tot; e += QM) cl += (ld[e] <= crr_wide) ? 1u : 0u;
+        if (cl) atomicAdd(&s_cl, cl);
+        __syncthreads();
+        const bool fires = uni(s_cl) >= (uint32_t)k;
+        if (fires && uni(s_ncb) > 0) merge();
         const int lpc32 = a.lpc32, lg32 = tid & (lpc32 - 1), grp32 = tid / lpc32;
         const int G32 = QM / lpc32;
-        for (int t0 = 0; t0 < KL; t0 += 2 * G32) {
+        for (int t0 = 0; fires && t0 < KL; t0 += 2 * G32) {
           int32_t id[2];
           bool valid[2];
           double dd[2];
@@ -1178,16 +1207,25 @@ __global__ __launch_bounds__(QM) __attribute__((amdgpu_waves_per_eu(8))) void q_
 }  // namespace
 
 // Per-query parameters of a batch into the workspace's pinned staging arrays.
+double query_beta(const Index& ix, const QueryConfig& qc, double c, double& memo_c,
+                  double& memo_b) {
+  if (qc.beta >= 0.0) return qc.beta;
+  if (c != memo_c) { memo_c = c; memo_b = theoretical_beta(ix.K, ix.L, c); }
+  return memo_b;
+}
+
 int stage_params(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws) {
   int maxKL = 1;
   int64_t acc = 0;
   bool uniform = qc.nq > 0;
+  double memo_c = 0.0, memo_b = 0.0;   // theoretical beta of the last c (batches mix few c)
   for (int64_t q = 0; q < qc.nq; ++q) {
     const int k = qc.k_host[q];
     uniform = uniform && k == qc.k_host[0] && qc.c_host[q] == qc.c_host[0];
     ws.h_k.as<int32_t>()[q] = k;
     ws.h_c.as<double>()[q] = qc.c_host[q];
-    ws.h_T.as<int64_t>()[q] = (int64_t)std::ceil(qc.beta * (double)ix.n) + k;
+    const double beta = query_beta(ix, qc, qc.c_host[q], memo_c, memo_b);
+    ws.h_T.as<int64_t>()[q] = (int64_t)std::ceil(beta * (double)ix.n) + k;
     ws.h_off.as<int64_t>()[q] = acc;
     acc += k;
     maxKL = std::max(maxKL, qc.precision == PDET_FP32 ? k : k * qc.rescore);
@@ -1225,7 +1263,7 @@ int64_t list_entries(const Index& ix, int64_t cap) {
 
 size_t slot_bytes_at(const Index& ix, int64_t admcap) {
   const int64_t nlpad = ((ix.nl_max + 15) / 16) * 16;
-  return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 12 + NRHO * 16 +
+  return (size_t)ix.L * nlpad + (size_t)admcap * 12 + (size_t)(admcap + 1) * 16 + NRHO * 16 +
          PDET_MAX_L * 4;
 }
 
@@ -1240,7 +1278,7 @@ void alloc_slots(const Index& ix, QueryWorkspace& ws, int64_t want, int64_t cap,
   ws.lcnt.release(); ws.bandc.release();
   ws.rho.alloc((size_t)want * ix.L * nlpad);
   ws.admb.alloc((size_t)want * admcap * 12);
-  ws.adm2.alloc((size_t)want * (admcap + 1) * 12);
+  ws.adm2.alloc((size_t)want * (admcap + 1) * 16);
   ws.t2.alloc((size_t)want * NRHO * 4);
   ws.crr.alloc((size_t)want * NRHO * 8);
   ws.lcnt.alloc((size_t)want * PDET_MAX_L * 4);
@@ -1254,7 +1292,7 @@ void alloc_slots(const Index& ix, QueryWorkspace& ws, int64_t want, int64_t cap,
 
 // Sizes the workspace for a batch of nq queries: per-query arrays, and as many query slots
 // (concurrent per-query scratch) as `budget` bytes allow (0: a third of free memory, at
-// most 24 GiB; memory held by the block cache counts as free). Slots normally hold every
+// most 48 GiB; memory held by the block cache counts as free). Slots normally hold every
 // leaf of every tree. With cap_lists, an index whose full-capacity slots would number fewer
 // than min(nq, TARGET_SLOTS) in that budget caps each tree's list at
 // max(MIN_LIST_CAP, nl_max / LIST_CAP_DIV) entries instead (the default budget may then
@@ -1271,7 +1309,7 @@ void reserve_workspace(const Index& ix, QueryWorkspace& ws, int64_t nq, size_t b
       size_t freeb = 0, totalb = 0;
       PDET_HIP(hipMemGetInfo(&freeb, &totalb));
       avail = freeb + ws.bytes() + cache_held();
-      budget = std::min<size_t>(avail / 3, (size_t)24 << 30);
+      budget = std::min<size_t>(avail / 3, (size_t)48 << 30);
     }
     const int64_t target = std::max<int64_t>(1, std::min<int64_t>(nq, TARGET_SLOTS));
     int64_t cap = nl_all;
@@ -1346,6 +1384,7 @@ void bind_slots(const Index& ix, QArgs& a, QueryWorkspace& sw) {
   a.adm2_leaf = sw.adm2.as<uint32_t>();
   a.adm2_pre = a.adm2_leaf + nslots * (admcap + 1);
   a.adm_start = reinterpret_cast<int32_t*>(a.adm2_pre + nslots * (admcap + 1));
+  a.adm2_lb = reinterpret_cast<float*>(a.adm_start + nslots * (admcap + 1));
   a.admcap = admcap;
 }
 

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <random>
 #include <thread>
 #include <unordered_map>
 
@@ -365,7 +366,7 @@ pdet_status pdet_server_create(const pdet_index* idx, const pdet_server_params* 
                  "max_batch must be in [1, 1024]");
     PDET_REQUIRE(p->lanes >= 1 && p->lanes <= 4, PDET_EINVAL, "lanes must be in [1, 4]");
     PDET_REQUIRE(p->k_max >= 1 && p->k_max <= idx->n, PDET_EINVAL, "k_max must be in [1, n]");
-    PDET_REQUIRE(p->beta >= 0.0, PDET_EINVAL, "beta must be >= 0");
+    PDET_REQUIRE(std::isfinite(p->beta), PDET_EINVAL, "beta must be finite");
     PDET_REQUIRE(p->precision >= PDET_FP32 && p->precision <= PDET_FP8_E4M3, PDET_EINVAL,
                  "unknown precision");
     if (p->precision != PDET_FP32) {
@@ -467,6 +468,42 @@ pdet_status pdet_server_get_stats(pdet_server* sv, pdet_server_stats* out) {
     out->qps = (sv->completed && sv->t_last > sv->t_first)
                    ? sv->completed / ((sv->t_last - sv->t_first) * 1e-3) : 0.0;
     out->batch_cap = sv->cap;
+  });
+}
+
+pdet_status pdet_server_offer_poisson(pdet_server* sv, const float* queries, int64_t m,
+                                      int64_t nreq, double rate_qps, int32_t k, double c,
+                                      uint64_t seed, double* offered_qps) {
+  return guarded([&] {
+    PDET_REQUIRE(sv && queries, PDET_EINVAL, "NULL argument");
+    PDET_REQUIRE(m >= 1 && nreq >= 1, PDET_EINVAL, "m and nreq must be >= 1");
+    PDET_REQUIRE(rate_qps > 0.0 && std::isfinite(rate_qps), PDET_EINVAL, "rate must be > 0");
+    const int d = sv->ix->d;
+    // arrival times: cumulative exponential gaps of mean 1 / rate (a Poisson process)
+    std::mt19937_64 gen(seed);
+    std::exponential_distribution<double> gap(rate_qps);
+    std::vector<double> t_arr((size_t)nreq);
+    double t = 0.0;
+    for (int64_t i = 0; i < nreq; ++i) { t += gap(gen); t_arr[(size_t)i] = t; }
+    std::vector<int64_t> rid((size_t)nreq);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto elapsed = [&] {
+      return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    };
+    double t_last = 0.0;
+    for (int64_t i = 0; i < nreq; ++i) {
+      while (elapsed() < t_arr[(size_t)i]) {
+      }
+      t_last = elapsed();
+      const pdet_status st = pdet_server_submit(sv, queries + (size_t)(i % m) * d, k, c,
+                                                &rid[(size_t)i]);
+      PDET_REQUIRE(st == PDET_OK, st, std::string("submit failed: ") + pdet_last_error());
+    }
+    for (int64_t i = 0; i < nreq; ++i) {
+      const pdet_status st = pdet_server_wait(sv, rid[(size_t)i], nullptr, nullptr, nullptr);
+      PDET_REQUIRE(st == PDET_OK, st, std::string("wait failed: ") + pdet_last_error());
+    }
+    if (offered_qps) *offered_qps = (nreq > 1 && t_last > 0.0) ? (double)(nreq - 1) / t_last : 0.0;
   });
 }
 

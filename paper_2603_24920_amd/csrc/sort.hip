@@ -1,172 +1,241 @@
 // Breakpoint selection (encoding phase, dynamic breakpoints) and device scans.
 //
-// The paper selects the Nr-1 interior order statistics of each sampled column with
-// rounds of QuickSelect. On the GPU every column is sorted instead (a bitonic
-// network: tiles sorted in LDS, cross-tile merge steps in global memory), then the
-// breakpoint ranks are read off: B(z) = C-up(m*(z-1)), m = floor(ns/Nr). Sorting gives
-// the same order statistics as selection.
+// The paper selects the Nr-1 interior order statistics of each sampled column with rounds
+// of QuickSelect. Here each column's order statistics B(z) = C-up(m*(z-1)), m = floor(ns/Nr)
+// (1-based ranks) are selected without sorting the column:
+//  1. the column's sample min and max;
+//  2. a histogram of NB equal-width value buckets between them (bucket index is a
+//     monotone function of the value, so bucket order is value order);
+//  3. per target rank, its bucket and its rank inside the bucket (a scan of the histogram);
+//  4. the keys of the buckets that hold a target are gathered, bucket by bucket;
+//  5. per target, an exact radix select (four 8-bit passes over the order-preserving
+//     integer image of the floats) inside its bucket.
+// The result is the exact order statistic whatever the distribution (a bucket may hold
+// any number of keys; large ones only take longer).
 #include "internal.h"
 
 namespace pdet {
 namespace {
 
-constexpr int TILE = 4096;         // keys per LDS tile (16 KB)
-constexpr int SORT_THREADS = 512;
+constexpr int NB = 4096;            // value buckets per column
+constexpr int SEL_THREADS = 256;
+constexpr int GATHER_KEYS = 4096;   // keys per gather / histogram block
 
-__device__ inline void cas(float& a, float& b, bool asc) {
-  if ((a > b) == asc) { float t = a; a = b; b = t; }
+__device__ inline int bucket_of(float v, float lo, float scale) {
+  const int b = (int)__fmul_rn(__fsub_rn(v, lo), scale);   // no contraction: one rounding each
+  return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
 }
 
-// Stages k = 2..tile of the network on one tile; directions from the global index.
-__global__ __launch_bounds__(SORT_THREADS) void bitonic_tile_sort(float* keys, int64_t npad,
-                                                                  int tile) {
-  __shared__ float sk[TILE];
-  const int64_t tiles_per_col = npad / tile;
-  const int64_t col = blockIdx.x / tiles_per_col;
-  const int64_t base = col * npad + (blockIdx.x % tiles_per_col) * tile;
-  const int64_t gbase = (blockIdx.x % tiles_per_col) * tile;    // index inside the column
-  for (int e = threadIdx.x; e < tile; e += blockDim.x) sk[e] = keys[base + e];
+// Column min / max of the sample (ordered uints; mm[col] = min, mm[ncols + col] = max).
+__global__ __launch_bounds__(256) void col_minmax(const float* keys, int64_t ld, int64_t ns,
+                                                  int ncols, uint32_t* mm) {
+  const int col = blockIdx.y;
+  const float* c = keys + (int64_t)col * ld;
+  float lo = INFINITY, hi = -INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ns; i += (int64_t)gridDim.x * 256) {
+    const float v = c[i];
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o));
+    hi = fmaxf(hi, __shfl_xor(hi, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[col], float_to_ordered(lo));
+    atomicMax(&mm[ncols + col], float_to_ordered(hi));
+  }
+}
+
+__device__ inline void col_range(const uint32_t* mm, int ncols, int col, float& lo, float& scale) {
+  lo = ordered_to_float(mm[col]);
+  const float hi = ordered_to_float(mm[ncols + col]);
+  scale = (hi > lo) ? (float)NB / (hi - lo) : 0.0f;
+}
+
+// Bucket histogram of every column, counted in LDS per block.
+__global__ __launch_bounds__(256) void col_hist(const float* keys, int64_t ld, int64_t ns,
+                                                int ncols, const uint32_t* mm, uint32_t* hist) {
+  __shared__ uint32_t h[NB];
+  const int col = blockIdx.y;
+  for (int i = threadIdx.x; i < NB; i += 256) h[i] = 0;
   __syncthreads();
-  for (int k = 2; k <= tile; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < tile / 2; t += blockDim.x) {
-        const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-        const bool asc = (((gbase + i) & k) == 0);
-        cas(sk[i], sk[i | j], asc);
+  float lo, scale;
+  col_range(mm, ncols, col, lo, scale);
+  const float* c = keys + (int64_t)col * ld;
+  const int64_t k0 = (int64_t)blockIdx.x * GATHER_KEYS;
+  for (int u = threadIdx.x; u < GATHER_KEYS; u += 256) {
+    const int64_t i = k0 + u;
+    if (i < ns) atomicAdd(&h[bucket_of(c[i], lo, scale)], 1u);
+  }
+  __syncthreads();
+  uint32_t* g = hist + (int64_t)col * NB;
+  for (int i = threadIdx.x; i < NB; i += 256)
+    if (h[i]) atomicAdd(&g[i], h[i]);
+}
+
+// Per column (one block): the bucket and in-bucket rank of every target rank m*u, and the
+// gather offset of every bucket that holds a target (-1 for the others).
+__global__ __launch_bounds__(1024) void col_targets(const uint32_t* hist, int Nr, int64_t m,
+                                                    int32_t* tbucket, uint32_t* trank,
+                                                    int32_t* boff) {
+  __shared__ uint32_t cum[NB];      // inclusive prefix of the histogram
+  __shared__ uint32_t need[NB];
+  __shared__ uint32_t wsum[1024 / 64 + 1];
+  const int col = blockIdx.x;
+  const uint32_t* h = hist + (int64_t)col * NB;
+  constexpr int PER = NB / 1024;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // inclusive scan of the histogram (each thread PER consecutive buckets)
+  auto scan = [&](const uint32_t* in_lds_or_null, const uint32_t* in_glob, uint32_t* out) {
+    uint32_t v[PER], s = 0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      v[e] = in_lds_or_null ? in_lds_or_null[threadIdx.x * PER + e] : in_glob[threadIdx.x * PER + e];
+      s += v[e];
+    }
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t acc = 0;
+      for (int w = 0; w < 1024 / 64; ++w) { const uint32_t t = wsum[w]; wsum[w] = acc; acc += t; }
+    }
+    __syncthreads();
+    uint32_t run = wsum[wave] + x - s;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) { run += v[e]; out[threadIdx.x * PER + e] = run; }
+    __syncthreads();
+  };
+  scan(nullptr, h, cum);
+  for (int i = threadIdx.x; i < NB; i += 1024) need[i] = 0;
+  __syncthreads();
+  for (int u = 1 + threadIdx.x; u < Nr; u += 1024) {
+    const uint32_t r = (uint32_t)(m * u);      // 1-based rank, r <= ns
+    int lo = 0, hi = NB - 1;                    // first bucket with cum >= r
+    while (lo < hi) {
+      const int md = (lo + hi) >> 1;
+      if (cum[md] >= r) hi = md; else lo = md + 1;
+    }
+    const uint32_t before = lo ? cum[lo - 1] : 0u;
+    tbucket[(int64_t)col * (Nr - 1) + u - 1] = lo;
+    trank[(int64_t)col * (Nr - 1) + u - 1] = r - before;
+    need[lo] = 1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NB; i += 1024) need[i] = need[i] ? (cum[i] - (i ? cum[i - 1] : 0u)) : 0u;
+  __syncthreads();
+  scan(need, nullptr, cum);                     // inclusive: end offset of each needed bucket
+  int32_t* bo = boff + (int64_t)col * NB;
+  for (int i = threadIdx.x; i < NB; i += 1024)
+    bo[i] = need[i] ? (int32_t)(cum[i] - need[i]) : -1;
+}
+
+// Keys of the needed buckets, gathered per column bucket by bucket (order inside a bucket
+// unspecified) as order-preserving uints: a block counts its keys per bucket in LDS, takes
+// one global reservation per bucket, then writes.
+__global__ __launch_bounds__(256) void col_gather(const float* keys, int64_t ld, int64_t ns,
+                                                  int ncols, const uint32_t* mm,
+                                                  const int32_t* boff, uint32_t* fill,
+                                                  uint32_t* gbuf) {
+  __shared__ uint32_t cntl[NB];
+  __shared__ uint32_t basel[NB];
+  constexpr int PER = GATHER_KEYS / 256;
+  const int col = blockIdx.y;
+  for (int i = threadIdx.x; i < NB; i += 256) cntl[i] = 0;
+  __syncthreads();
+  float lo, scale;
+  col_range(mm, ncols, col, lo, scale);
+  const float* c = keys + (int64_t)col * ld;
+  const int32_t* bo = boff + (int64_t)col * NB;
+  const int64_t k0 = (int64_t)blockIdx.x * GATHER_KEYS;
+  int bk[PER];
+  uint32_t rk[PER];
+  float kv[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int64_t i = k0 + e * 256 + threadIdx.x;
+    bk[e] = -1;
+    if (i < ns) {
+      kv[e] = c[i];
+      const int b = bucket_of(kv[e], lo, scale);
+      if (bo[b] >= 0) {
+        bk[e] = b;
+        rk[e] = atomicAdd(&cntl[b], 1u);
       }
-      __syncthreads();
     }
   }
-  for (int e = threadIdx.x; e < tile; e += blockDim.x) keys[base + e] = sk[e];
-}
-
-// Full tiles (TILE keys) run the same network with each of TILE_T threads holding KPT
-// consecutive keys: steps with stride j < KPT stay in registers, strides up to a wave's
-// 64*KPT keys go through lane shuffles, and only the larger ones through LDS (laid out
-// key-major so that consecutive threads hit consecutive banks).
-constexpr int KPT = 16;
-constexpr int TILE_T = TILE / KPT;   // 256 threads
-
-__device__ inline void tile_step(float (&x)[KPT], int t, int64_t gidx0, int64_t k, int j,
-                                 float* sk) {
-  if (j < KPT) {
-#pragma unroll
-    for (int e = 0; e < KPT; ++e)
-      if (!(e & j)) cas(x[e], x[e | j], ((gidx0 + e) & k) == 0);
-  } else if (j < 64 * KPT) {
-    const int m = j / KPT;                       // partner lane: t ^ m, same wave
-    const bool lower = (t & m) == 0;
-#pragma unroll
-    for (int e = 0; e < KPT; ++e) {
-      const float y = __shfl_xor(x[e], m);
-      const bool asc = ((gidx0 + e) & k) == 0;
-      x[e] = (lower == asc) ? fminf(x[e], y) : fmaxf(x[e], y);
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < KPT; ++e) sk[e * TILE_T + t] = x[e];
-    __syncthreads();
-    const int tp = t ^ (j / KPT);
-    const bool lower = (t & (j / KPT)) == 0;
-#pragma unroll
-    for (int e = 0; e < KPT; ++e) {
-      const float y = sk[e * TILE_T + tp];
-      const bool asc = ((gidx0 + e) & k) == 0;
-      x[e] = (lower == asc) ? fminf(x[e], y) : fmaxf(x[e], y);
-    }
-    __syncthreads();
-  }
-}
-
-// MERGE false: stages k = 2..TILE of each tile; true: steps j = TILE/2..1 of stage `kst`.
-template <bool MERGE>
-__global__ __launch_bounds__(TILE_T) void bitonic_tile_reg(float* keys, int64_t npad,
-                                                           int64_t kst) {
-  __shared__ float sk[TILE];
-  const int64_t tiles_per_col = npad / TILE;
-  const int64_t col = blockIdx.x / tiles_per_col;
-  const int64_t gbase = (blockIdx.x % tiles_per_col) * TILE;
-  const int t = threadIdx.x;
-  float4* src = reinterpret_cast<float4*>(keys + col * npad + gbase + (int64_t)t * KPT);
-  float x[KPT];
-#pragma unroll
-  for (int q = 0; q < KPT / 4; ++q) {
-    const float4 v = src[q];
-    x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
-  }
-  const int64_t gidx0 = gbase + (int64_t)t * KPT;   // index inside the column of x[0]
-  if constexpr (MERGE) {
-    for (int j = TILE >> 1; j > 0; j >>= 1) tile_step(x, t, gidx0, kst, j, sk);
-  } else {
-    for (int k = 2; k <= TILE; k <<= 1)
-      for (int j = k >> 1; j > 0; j >>= 1) tile_step(x, t, gidx0, k, j, sk);
-  }
-#pragma unroll
-  for (int q = 0; q < KPT / 4; ++q)
-    src[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-}
-
-// S consecutive steps j = J, J/2, .., J/2^(S-1) (all >= tile) of stage k in one pass: a
-// thread holds the 2^S keys whose indices differ only in those S bits, applies the S
-// compare-exchange levels in registers (largest stride first, as the network does), and
-// writes them back. All of a group's keys share bit k, hence one direction.
-template <int S>
-__global__ void bitonic_global_steps(float* keys, int64_t npad, int64_t k, int p0,
-                                     int64_t groups_total) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= groups_total) return;
-  const int64_t per_col = npad >> S;
-  const int64_t col = g / per_col, t = g % per_col;
-  const int64_t base = ((t >> p0) << (p0 + S)) | (t & ((int64_t(1) << p0) - 1));
-  float* c = keys + col * npad;
-  constexpr int G = 1 << S;
-  float x[G];
-#pragma unroll
-  for (int a = 0; a < G; ++a) x[a] = c[base + ((int64_t)a << p0)];
-  const bool asc = ((base & k) == 0);
-#pragma unroll
-  for (int l = S - 1; l >= 0; --l) {
-#pragma unroll
-    for (int a = 0; a < G; ++a)
-      if (!(a & (1 << l))) cas(x[a], x[a | (1 << l)], asc);
-  }
-#pragma unroll
-  for (int a = 0; a < G; ++a) c[base + ((int64_t)a << p0)] = x[a];
-}
-
-// Steps j = tile/2 .. 1 of stage k > tile inside each tile.
-__global__ __launch_bounds__(SORT_THREADS) void bitonic_tile_merge(float* keys, int64_t npad,
-                                                                   int tile, int64_t k) {
-  __shared__ float sk[TILE];
-  const int64_t tiles_per_col = npad / tile;
-  const int64_t col = blockIdx.x / tiles_per_col;
-  const int64_t gbase = (blockIdx.x % tiles_per_col) * tile;
-  const int64_t base = col * npad + gbase;
-  const bool asc = ((gbase & k) == 0);
-  for (int e = threadIdx.x; e < tile; e += blockDim.x) sk[e] = keys[base + e];
   __syncthreads();
-  for (int j = tile >> 1; j > 0; j >>= 1) {
-    for (int t = threadIdx.x; t < tile / 2; t += blockDim.x) {
-      const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-      cas(sk[i], sk[i | j], asc);
+  uint32_t* fl = fill + (int64_t)col * NB;
+  for (int i = threadIdx.x; i < NB; i += 256)
+    if (cntl[i]) basel[i] = (uint32_t)bo[i] + atomicAdd(&fl[i], cntl[i]);
+  __syncthreads();
+  uint32_t* g = gbuf + (int64_t)col * ns;
+#pragma unroll
+  for (int e = 0; e < PER; ++e)
+    if (bk[e] >= 0) g[basel[bk[e]] + rk[e]] = float_to_ordered(kv[e]);
+}
+
+// B[col][u] = the trank-th smallest key of target u's bucket: radix select, 8 bits a pass.
+__global__ __launch_bounds__(SEL_THREADS) void col_select(const uint32_t* hist,
+                                                          const int32_t* tbucket,
+                                                          const uint32_t* trank,
+                                                          const int32_t* boff,
+                                                          const uint32_t* gbuf, int64_t ns,
+                                                          int Nr, float* B) {
+  __shared__ uint32_t h[256];
+  __shared__ uint32_t wsum[SEL_THREADS / 64 + 1];
+  __shared__ uint32_t s_pick, s_rem;
+  const int u = blockIdx.x + 1, col = blockIdx.y;
+  const int b = tbucket[(int64_t)col * (Nr - 1) + u - 1];
+  uint32_t r = trank[(int64_t)col * (Nr - 1) + u - 1];
+  const uint32_t size = hist[(int64_t)col * NB + b];
+  const uint32_t* keys = gbuf + (int64_t)col * ns + boff[(int64_t)col * NB + b];
+  uint32_t prefix = 0;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int sh = 24 - 8 * pass;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < size; i += SEL_THREADS) {
+      const uint32_t k = keys[i];
+      if (pass == 0 || (k >> (sh + 8)) == prefix) atomicAdd(&h[(k >> sh) & 255u], 1u);
     }
     __syncthreads();
+    // the bin where the remaining rank falls (inclusive prefix over bins)
+    const uint32_t v = h[threadIdx.x];
+    uint32_t x = v;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t acc = 0;
+      for (int w = 0; w < SEL_THREADS / 64; ++w) { const uint32_t t = wsum[w]; wsum[w] = acc; acc += t; }
+    }
+    __syncthreads();
+    const uint32_t incl = wsum[wave] + x;
+    if (incl - v < r && r <= incl) { s_pick = (uint32_t)threadIdx.x; s_rem = r - (incl - v); }
+    __syncthreads();
+    prefix = (prefix << 8) | s_pick;
+    r = s_rem;
+    __syncthreads();
   }
-  for (int e = threadIdx.x; e < tile; e += blockDim.x) keys[base + e] = sk[e];
+  if (threadIdx.x == 0) B[(int64_t)col * (Nr + 1) + u] = ordered_to_float(prefix);
 }
 
 __global__ void fill_kernel(float* p, int64_t count, float v) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < count) p[g] = v;
-}
-
-// B[col][u] = sorted[col][m*u - 1] for u = 1..Nr-1 (1-based rank m*u).
-__global__ void pick_kernel(const float* sorted, int ncols, int64_t npad, int64_t m, int Nr,
-                            float* B) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ncols * (Nr - 1)) return;
-  const int col = g / (Nr - 1), u = 1 + g % (Nr - 1);
-  B[(int64_t)col * (Nr + 1) + u] = sorted[(int64_t)col * npad + m * u - 1];
 }
 
 __global__ void outer_kernel(float* B, const uint32_t* colmm, int ncols, int Nr) {
@@ -262,60 +331,42 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply(const uint32_t* in, u
 
 }  // namespace
 
-void sort_columns(float* keys, int ncols, int64_t npad, hipStream_t s) {
-  const int tile = (int)std::min<int64_t>(npad, TILE);
-  const int64_t tiles = ncols * (npad / tile);
-  const bool full = tile == TILE;   // register / shuffle form for full tiles
-  if (full)
-    hipLaunchKernelGGL(bitonic_tile_reg<false>, dim3((unsigned)tiles), dim3(TILE_T), 0, s, keys,
-                       npad, (int64_t)0);
-  else
-    hipLaunchKernelGGL(bitonic_tile_sort, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s, keys,
-                       npad, tile);
-  PDET_HIP(hipGetLastError());
-  for (int64_t k = 2 * (int64_t)tile; k <= npad; k <<= 1) {
-    // the steps j = k/2 .. tile, up to four per pass
-    int hi = 0;
-    while ((int64_t(1) << (hi + 1)) <= (k >> 1)) ++hi;   // log2(k/2)
-    int lo = 0;
-    while ((int64_t(1) << (lo + 1)) <= tile) ++lo;        // log2(tile)
-    while (hi >= lo) {
-      const int S = std::min(4, hi - lo + 1);
-      const int p0 = hi - S + 1;
-      const int64_t groups = (int64_t)ncols * (npad >> S);
-      const dim3 gr(cdiv(groups, 256));
-      switch (S) {
-        case 1: hipLaunchKernelGGL(bitonic_global_steps<1>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
-        case 2: hipLaunchKernelGGL(bitonic_global_steps<2>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
-        case 3: hipLaunchKernelGGL(bitonic_global_steps<3>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
-        default: hipLaunchKernelGGL(bitonic_global_steps<4>, gr, dim3(256), 0, s, keys, npad, k, p0, groups); break;
-      }
-      PDET_HIP(hipGetLastError());
-      hi -= S;
-    }
-    if (full)
-      hipLaunchKernelGGL(bitonic_tile_reg<true>, dim3((unsigned)tiles), dim3(TILE_T), 0, s, keys,
-                         npad, k);
-    else
-      hipLaunchKernelGGL(bitonic_tile_merge, dim3((unsigned)tiles), dim3(SORT_THREADS), 0, s,
-                         keys, npad, tile, k);
-    PDET_HIP(hipGetLastError());
-  }
-}
-
 void fill_f32(float* p, int64_t count, float v, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(cdiv(count, 256)), dim3(256), 0, s, p, count, v);
   PDET_HIP(hipGetLastError());
 }
 
-void pick_breakpoints(const float* sorted, int ncols, int64_t npad, int64_t ns, int Nr, float* B,
-                      hipStream_t s) {
+void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,
+                        std::vector<PooledBuf>& keep, hipStream_t s) {
   const int64_t m = ns / Nr;
-  const int tot = ncols * (Nr - 1);
-  hipLaunchKernelGGL(pick_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, sorted, ncols, npad, m,
-                     Nr, B);
+  PooledBuf mm((size_t)2 * ncols * 4), hist((size_t)ncols * NB * 4), fill((size_t)ncols * NB * 4);
+  PooledBuf boff((size_t)ncols * NB * 4), tb((size_t)ncols * (Nr - 1) * 4);
+  PooledBuf tr((size_t)ncols * (Nr - 1) * 4), gbuf((size_t)ncols * ns * 4);
+  PDET_HIP(hipMemsetAsync(mm.ptr(), 0xff, (size_t)ncols * 4, s));
+  PDET_HIP(hipMemsetAsync(mm.as<uint32_t>() + ncols, 0, (size_t)ncols * 4, s));
+  PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
+  PDET_HIP(hipMemsetAsync(fill.ptr(), 0, fill.bytes(), s));
+  const unsigned mmg = (unsigned)std::min<int64_t>(cdiv(ns, 256), 1024);
+  hipLaunchKernelGGL(col_minmax, dim3(mmg, ncols), dim3(256), 0, s, keys, ld, ns, ncols,
+                     mm.as<uint32_t>());
   PDET_HIP(hipGetLastError());
+  const dim3 kg(cdiv(ns, GATHER_KEYS), ncols);
+  hipLaunchKernelGGL(col_hist, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm.as<uint32_t>(),
+                     hist.as<uint32_t>());
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(col_targets, dim3(ncols), dim3(1024), 0, s, hist.as<uint32_t>(), Nr, m,
+                     tb.as<int32_t>(), tr.as<uint32_t>(), boff.as<int32_t>());
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(col_gather, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm.as<uint32_t>(),
+                     boff.as<int32_t>(), fill.as<uint32_t>(), gbuf.as<uint32_t>());
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(col_select, dim3(Nr - 1, ncols), dim3(SEL_THREADS), 0, s,
+                     hist.as<uint32_t>(), tb.as<int32_t>(), tr.as<uint32_t>(), boff.as<int32_t>(),
+                     gbuf.as<uint32_t>(), ns, Nr, B);
+  PDET_HIP(hipGetLastError());
+  // the kernels above still use the temporaries: the caller keeps them until it synchronises
+  for (PooledBuf* t : {&mm, &hist, &fill, &boff, &tb, &tr, &gbuf}) keep.push_back(std::move(*t));
 }
 
 void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, hipStream_t s) {

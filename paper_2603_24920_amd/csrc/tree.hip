@@ -4,25 +4,44 @@
 // range, a split partitions its range by the chosen bit (bit-0 child first), so the
 // final leaf order along `perm` is the depth-first order of the tree.
 //
-//  1. first layer: counting sort of points by the K leading code bits (2^K nodes);
+//  1. first layer: counting sort of the points by the K-bit first-layer keys the encoder
+//     wrote (2^K nodes); the scatter also moves each point's 16-byte code row next to its
+//     id, so later passes read contiguous (row, id) ranges instead of gathering rows;
 //  2. nodes larger than LDS_SEG_CAP: level-synchronous global passes (bit counts per
-//     dimension, choice of the most balanced dimension, partition into a scratch
-//     permutation, copy back);
-//  3. nodes of (max_leaf, LDS_SEG_CAP] points: one workgroup finishes the whole
-//     subtree in LDS with an explicit depth-first stack;
-//  4. leaves are recorded at their start position, numbered by a prefix scan, and
-//     written as flat tables with their breakpoint boxes.
+//     dimension over the node's contiguous rows, the most balanced dimension, a partition
+//     into the other of two (row, id) buffers); a node keeps the index of the buffer that
+//     holds it, and a leaf that ends up in the second buffer has its ids copied back;
+//  3. nodes of (max_leaf, LDS_SEG_CAP] points: one workgroup loads the node into LDS and
+//     splits every open node of a level at once (bit counts by wave ballots, one
+//     workgroup-wide scan for the partition), level after level; for very small max_leaf
+//     (more open nodes than the workgroup tracks) a depth-first variant splits one node at
+//     a time;
+//  4. leaves are recorded at their start position, numbered by a prefix scan, and written
+//     as flat tables with their breakpoint boxes.
 // A node is a leaf iff it has at most max_leaf points or every dimension is fully
 // refined. Empty nodes are dropped. Inside a leaf the point order is unspecified.
+#include "devutil.h"
 #include "internal.h"
 
 namespace pdet {
 namespace {
 
 struct Seg {
-  int32_t tree, start, count, pad;
+  int32_t tree, start, count;
+  uint8_t buf, pad[3];        // buffer (0 or 1) that holds the node's rows and ids
   uint8_t depth[KP];
   uint8_t prefix[KP];
+};
+
+// Row and id buffers, [L][n] each, in permutation order. ids[0] is the index's perm (the
+// final output); rows[1] / ids[1] are build temporaries.
+struct Bufs {
+  uint4* rows[2];
+  int32_t* ids[2];
+};
+
+struct Copy {
+  int32_t tree, start, count;
 };
 
 struct LeafOut {
@@ -33,12 +52,8 @@ struct LeafOut {
 struct Lists {
   Seg* big_next; uint32_t* n_big_next; uint32_t* max_big_next;
   Seg* mid; uint32_t* n_mid;
+  Copy* copies; uint32_t* n_copies;   // leaves whose ids sit in buffer 1
 };
-
-__device__ inline void load_row(const uint8_t* codes, int64_t off, uint8_t (&c)[KP]) {
-  const uint4 v = *reinterpret_cast<const uint4*>(codes + off);
-  *reinterpret_cast<uint4*>(c) = v;
-}
 
 __device__ inline uint32_t code_byte(const uint4& v, int j) {
   const uint32_t w = (j < 8) ? ((j < 4) ? v.x : v.y) : ((j < 12) ? v.z : v.w);
@@ -64,25 +79,24 @@ __device__ void emit_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start,
     h[j] = (j < K) ? (uint16_t)((1u << depth[j]) | prefix[j]) : (uint16_t)0;
 }
 
+__device__ inline bool fully_refined(const uint8_t* depth, int K, int bits) {
+  bool f = true;
+  for (int j = 0; j < K; ++j) f = f && (depth[j] >= bits);
+  return f;
+}
+
 __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, const LeafOut& lo,
                       const Lists& li) {
   if (s.count <= 0) return;
-  bool fully = true;
-  for (int j = 0; j < K; ++j) fully = fully && (s.depth[j] >= bits);
-  if (s.count <= max_leaf || fully) {
+  if (s.count <= max_leaf || fully_refined(s.depth, K, bits)) {
     emit_leaf(lo, n, s.tree, s.start, s.count, s.depth, s.prefix, K);
+    if (s.buf == 1) li.copies[atomicAdd(li.n_copies, 1u)] = Copy{s.tree, s.start, s.count};
   } else if (s.count <= LDS_SEG_CAP) {
     li.mid[atomicAdd(li.n_mid, 1u)] = s;
   } else {
     li.big_next[atomicAdd(li.n_big_next, 1u)] = s;
     atomicMax(li.max_big_next, (uint32_t)s.count);
   }
-}
-
-__device__ inline uint32_t first_layer_key(const uint8_t (&c)[KP], int K, int bits) {
-  uint32_t key = 0;
-  for (int j = 0; j < K; ++j) key |= (uint32_t)((c[j] >> (bits - 1)) & 1) << (K - 1 - j);
-  return key;
 }
 
 // First-layer counting sort. A block takes FL_PTS consecutive points of one tree and counts
@@ -107,7 +121,7 @@ __device__ inline int fl_insert(uint32_t* hk, uint32_t key) {
   return -1;
 }
 
-__global__ __launch_bounds__(256) void fl_hist(const uint8_t* codes, int64_t n, int K, int bits,
+__global__ __launch_bounds__(256) void fl_hist(const uint16_t* flkey, int64_t n, int K,
                                                uint32_t* hist) {
   __shared__ uint32_t hk[FL_HASH], hc[FL_HASH];
   const int tree = blockIdx.y;
@@ -115,12 +129,11 @@ __global__ __launch_bounds__(256) void fl_hist(const uint8_t* codes, int64_t n, 
   for (int i = threadIdx.x; i < FL_HASH; i += 256) { hk[i] = FL_EMPTY; hc[i] = 0; }
   __syncthreads();
   uint32_t* h = hist + ((int64_t)tree << K);
+  const uint16_t* kt = flkey + (int64_t)tree * n;
   for (int u = 0; u < FL_PER_THREAD; ++u) {
     const int64_t p = p0 + u * 256 + threadIdx.x;
     if (p < n) {
-      uint8_t c[KP];
-      load_row(codes, ((int64_t)tree * n + p) * KP, c);
-      const uint32_t key = first_layer_key(c, K, bits);
+      const uint32_t key = kt[p];
       const int sl = fl_insert(hk, key);
       if (sl >= 0) atomicAdd(&hc[sl], 1u);
       else atomicAdd(&h[key], 1u);
@@ -131,9 +144,9 @@ __global__ __launch_bounds__(256) void fl_hist(const uint8_t* codes, int64_t n, 
     if (hk[i] != FL_EMPTY) atomicAdd(&h[hk[i]], hc[i]);
 }
 
-__global__ __launch_bounds__(256) void fl_scatter(const uint8_t* codes, int64_t n, int K,
-                                                  int bits, const uint32_t* off,
-                                                  uint32_t* cursor, int32_t* perm) {
+__global__ __launch_bounds__(256) void fl_scatter(const uint16_t* flkey, const uint8_t* codes,
+                                                  int64_t n, int K, const uint32_t* off,
+                                                  uint32_t* cursor, Bufs b) {
   __shared__ uint32_t hk[FL_HASH], hc[FL_HASH], hb[FL_HASH];
   const int tree = blockIdx.y;
   const int64_t p0 = (int64_t)blockIdx.x * FL_PTS;
@@ -141,7 +154,11 @@ __global__ __launch_bounds__(256) void fl_scatter(const uint8_t* codes, int64_t 
   __syncthreads();
   const uint32_t* o = off + ((int64_t)tree << K);
   uint32_t* cur = cursor + ((int64_t)tree << K);
-  int32_t* pm = perm + (int64_t)tree * n;
+  const int64_t tb = (int64_t)tree * n;
+  const uint16_t* kt = flkey + tb;
+  const uint4* ct = reinterpret_cast<const uint4*>(codes) + tb;
+  int32_t* pm = b.ids[0] + tb;
+  uint4* rw = b.rows[0] + tb;
   uint32_t key[FL_PER_THREAD];
   int slot[FL_PER_THREAD];
   // count per slot (keys without a slot take their position from the global cursor now)
@@ -150,12 +167,15 @@ __global__ __launch_bounds__(256) void fl_scatter(const uint8_t* codes, int64_t 
     const int64_t p = p0 + u * 256 + threadIdx.x;
     slot[u] = -2;
     if (p < n) {
-      uint8_t c[KP];
-      load_row(codes, ((int64_t)tree * n + p) * KP, c);
-      key[u] = first_layer_key(c, K, bits);
+      key[u] = kt[p];
       slot[u] = fl_insert(hk, key[u]);
-      if (slot[u] >= 0) atomicAdd(&hc[slot[u]], 1u);
-      else pm[o[key[u]] + atomicAdd(&cur[key[u]], 1u)] = (int32_t)p;
+      if (slot[u] >= 0) {
+        atomicAdd(&hc[slot[u]], 1u);
+      } else {
+        const uint32_t pos = o[key[u]] + atomicAdd(&cur[key[u]], 1u);
+        pm[pos] = (int32_t)p;
+        rw[pos] = ct[p];
+      }
     }
   }
   __syncthreads();
@@ -171,7 +191,9 @@ __global__ __launch_bounds__(256) void fl_scatter(const uint8_t* codes, int64_t 
   for (int u = 0; u < FL_PER_THREAD; ++u) {
     if (slot[u] >= 0) {
       const int64_t p = p0 + u * 256 + threadIdx.x;
-      pm[hb[slot[u]] + atomicAdd(&hc[slot[u]], 1u)] = (int32_t)p;
+      const uint32_t pos = hb[slot[u]] + atomicAdd(&hc[slot[u]], 1u);
+      pm[pos] = (int32_t)p;
+      rw[pos] = ct[p];
     }
   }
 }
@@ -187,7 +209,8 @@ __global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, in
   s.tree = (int32_t)(g >> K);
   s.start = (int32_t)off[g];
   s.count = (int32_t)c;
-  s.pad = 0;
+  s.buf = 0;
+  s.pad[0] = s.pad[1] = s.pad[2] = 0;
   for (int j = 0; j < KP; ++j) {
     s.depth[j] = (j < K) ? 1 : (uint8_t)bits;
     s.prefix[j] = (j < K) ? (uint8_t)((key >> (K - 1 - j)) & 1) : 0;
@@ -195,21 +218,19 @@ __global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, in
   route(s, K, bits, max_leaf, n, lo, li);
 }
 
-// ---- global passes over nodes larger than LDS_SEG_CAP
-__global__ void seg_bitcount(const Seg* segs, const int32_t* perm, const uint8_t* codes,
-                             int64_t n, int K, int bits, uint32_t* cnt) {
+// ---- global passes over nodes larger than LDS_SEG_CAP (contiguous rows, no gathers)
+__global__ void seg_count(const Seg* segs, Bufs b, int64_t n, int K, int bits, uint32_t* cnt) {
   const Seg s = segs[blockIdx.x];
   uint32_t local[KP];
 #pragma unroll
   for (int j = 0; j < KP; ++j) local[j] = 0;
-  const int64_t base = (int64_t)s.tree * n + s.start;
+  const uint4* rows = b.rows[s.buf] + (int64_t)s.tree * n + s.start;
   for (int64_t p = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; p < s.count;
        p += (int64_t)gridDim.y * blockDim.x) {
-    uint8_t c[KP];
-    load_row(codes, ((int64_t)s.tree * n + perm[base + p]) * KP, c);
+    const uint4 v = rows[p];
 #pragma unroll
     for (int j = 0; j < KP; ++j)
-      if (j < K && s.depth[j] < bits) local[j] += (c[j] >> (bits - 1 - s.depth[j])) & 1;
+      if (j < K && s.depth[j] < bits) local[j] += (code_byte(v, j) >> (bits - 1 - s.depth[j])) & 1;
   }
 #pragma unroll
   for (int j = 0; j < KP; ++j) {
@@ -218,8 +239,11 @@ __global__ void seg_bitcount(const Seg* segs, const int32_t* perm, const uint8_t
   }
 }
 
+// The most balanced dimension of each node (ties to the smallest), the size of its bit-0
+// child, the children's write cursors, and whether each child is a leaf (bit 0 / bit 1).
 __global__ void seg_choose(const Seg* segs, int nseg, const uint32_t* cnt, int K, int bits,
-                           int32_t* split, uint32_t* c0, uint32_t* cur0, uint32_t* cur1) {
+                           int max_leaf, int32_t* split, uint32_t* c0, uint32_t* cur0,
+                           uint32_t* cur1, uint8_t* leafs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nseg) return;
   const Seg s = segs[i];
@@ -236,24 +260,39 @@ __global__ void seg_choose(const Seg* segs, int nseg, const uint32_t* cnt, int K
   c0[i] = z;
   cur0[i] = (uint32_t)s.start;
   cur1[i] = (uint32_t)s.start + z;
+  uint8_t d[KP];
+  for (int j = 0; j < KP; ++j) d[j] = s.depth[j];
+  d[best] = (uint8_t)(d[best] + 1);
+  const bool full = fully_refined(d, K, bits);
+  const uint32_t z1 = (uint32_t)s.count - z;
+  leafs[i] = (uint8_t)(((z <= (uint32_t)max_leaf || full) ? 1 : 0) |
+                       ((z1 <= (uint32_t)max_leaf || full) ? 2 : 0));
 }
 
-__global__ void seg_partition(const Seg* segs, const int32_t* split, const int32_t* perm,
-                              int32_t* perm_tmp, const uint8_t* codes, int64_t n, int bits,
-                              uint32_t* cur0, uint32_t* cur1) {
+// Partition of each node's rows and ids into the other buffer, bit-0 child first. A
+// child that is a leaf needs no rows any more: only its ids are written.
+__global__ void seg_split(const Seg* segs, const int32_t* split, const uint8_t* leafs, Bufs b,
+                          int64_t n, int bits, uint32_t* cur0, uint32_t* cur1) {
   const Seg s = segs[blockIdx.x];
   const int j = split[blockIdx.x];
   const int sh = bits - 1 - s.depth[j];
+  const uint8_t lf = leafs[blockIdx.x];
   const int64_t tb = (int64_t)s.tree * n;
-  for (int64_t b = (int64_t)blockIdx.y * blockDim.x; b < s.count;
-       b += (int64_t)gridDim.y * blockDim.x) {
-    const int64_t p = b + threadIdx.x;
+  const uint4* rs = b.rows[s.buf] + tb + s.start;
+  const int32_t* is = b.ids[s.buf] + tb + s.start;
+  uint4* rd = b.rows[1 - s.buf] + tb;
+  int32_t* id_d = b.ids[1 - s.buf] + tb;
+  for (int64_t b0 = (int64_t)blockIdx.y * blockDim.x; b0 < s.count;
+       b0 += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t p = b0 + threadIdx.x;
     const bool valid = p < s.count;
     int32_t id = 0;
+    uint4 row = make_uint4(0, 0, 0, 0);
     int bit = 0;
     if (valid) {
-      id = perm[tb + s.start + p];
-      bit = (codes[(tb + id) * KP + j] >> sh) & 1;
+      row = rs[p];
+      id = is[p];
+      bit = (code_byte(row, j) >> sh) & 1;
     }
     const uint64_t mz = __ballot(valid && bit == 0);
     const uint64_t mo = __ballot(valid && bit == 1);
@@ -266,17 +305,10 @@ __global__ void seg_partition(const Seg* segs, const int32_t* split, const int32
     bo = __shfl(bo, 0);
     if (valid) {
       const uint32_t pos = bit ? bo + lanes_below(mo) : bz + lanes_below(mz);
-      perm_tmp[tb + pos] = id;
+      id_d[pos] = id;
+      if (!((lf >> bit) & 1)) rd[pos] = row;
     }
   }
-}
-
-__global__ void seg_copyback(const Seg* segs, const int32_t* perm_tmp, int32_t* perm, int64_t n) {
-  const Seg s = segs[blockIdx.x];
-  const int64_t b = (int64_t)s.tree * n + s.start;
-  for (int64_t p = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; p < s.count;
-       p += (int64_t)gridDim.y * blockDim.x)
-    perm[b + p] = perm_tmp[b + p];
 }
 
 __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, const uint32_t* c0,
@@ -286,6 +318,7 @@ __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, co
   const Seg s = segs[i];
   const int j = split[i];
   Seg a = s, b = s;
+  a.buf = b.buf = (uint8_t)(1 - s.buf);
   a.count = (int32_t)c0[i];
   b.start = s.start + a.count;
   b.count = s.count - a.count;
@@ -296,11 +329,22 @@ __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, co
   route(b, K, bits, max_leaf, n, lo, li);
 }
 
-// ---- one workgroup finishes a node of at most LDS_SEG_CAP points in LDS
-constexpr int STACK_MAX = KP * 8 + 8;
+// Ids of leaves whose data sits in buffer 1 go to the permutation (buffer 0).
+__global__ void seg_copy(const Copy* cp, Bufs b, int64_t n) {
+  const Copy c = cp[blockIdx.x];
+  const int64_t base = (int64_t)c.tree * n + c.start;
+  for (int t = threadIdx.x; t < c.count; t += blockDim.x) b.ids[0][base + t] = b.ids[1][base + t];
+}
 
-struct Node {
-  int16_t lstart, lcount;
+// ---- one workgroup finishes a node of at most LDS_SEG_CAP points in LDS
+
+// Frontier form: every open node of a level is split at once. Open nodes hold more than
+// max_leaf points each, so a workgroup of capacity CAP tracks at most CAP / (max_leaf + 1)
+// of them; the host takes this form when that is at most FR_MAXS.
+constexpr int FR_MAXS = 64;
+
+struct SegL {
+  int16_t start, count;       // range within the workgroup's node
   uint8_t depth[KP];
   uint8_t prefix[KP];
 };
@@ -309,10 +353,211 @@ struct Node {
 // with the node, so small nodes run many workgroups per CU. Blocks whose node is outside
 // the class return at once.
 template <int CAP, int NT>
-__global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* perm,
-                                                     const uint8_t* codes, int64_t n, int K,
-                                                     int bits, int max_leaf, int below,
-                                                     LeafOut lo) {
+__global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, int64_t n, int K,
+                                                       int bits, int max_leaf, int below,
+                                                       LeafOut lo) {
+  constexpr int PER = CAP / NT;           // consecutive positions per thread in the scan
+  static_assert(PER * NT == CAP && PER <= 32, "class shape");
+  __shared__ uint4 rows[CAP];
+  __shared__ int32_t ids[CAP];
+  __shared__ uint16_t ord[CAP];
+  __shared__ uint16_t tmp[CAP];
+  __shared__ SegL segs[2][FR_MAXS];
+  __shared__ uint32_t cnt[FR_MAXS][KP];
+  __shared__ uint32_t zstart[FR_MAXS];
+  __shared__ uint16_t c0s[FR_MAXS];
+  __shared__ uint8_t jsel[FR_MAXS];
+  __shared__ uint32_t sh_scan[NT / 64 + 1];
+  __shared__ uint32_t s_nact;
+
+  const Seg s = mid[blockIdx.x];
+  if (s.count <= below || s.count > CAP) return;
+  const int count = s.count;
+  const int64_t tb = (int64_t)s.tree * n;
+  const uint4* rsrc = b.rows[s.buf] + tb + s.start;
+  const int32_t* isrc = b.ids[s.buf] + tb + s.start;
+  for (int t = threadIdx.x; t < count; t += NT) {
+    rows[t] = rsrc[t];
+    ids[t] = isrc[t];
+    ord[t] = (uint16_t)t;
+  }
+  if (threadIdx.x == 0) {
+    SegL r;
+    r.start = 0;
+    r.count = (int16_t)count;
+    for (int j = 0; j < KP; ++j) { r.depth[j] = s.depth[j]; r.prefix[j] = s.prefix[j]; }
+    segs[0][0] = r;
+    s_nact = 1;   // routed here: more than max_leaf points and not fully refined
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  int cur = 0;
+  for (;;) {
+    const int nact = (int)uni(s_nact);
+    if (nact == 0) break;
+    const SegL* S = segs[cur];
+    // open node holding position p (binary search over the sorted starts), or -1
+    auto find = [&](int p) -> int {
+      int lo = 0, hi = nact;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (S[mid].start <= p) lo = mid; else hi = mid;
+      }
+      return (S[lo].start <= p && p < S[lo].start + S[lo].count) ? lo : -1;
+    };
+    for (int e = threadIdx.x; e < nact * KP; e += NT) cnt[e / KP][e % KP] = 0;
+    __syncthreads();
+    // 1. next-bit counts per open node and dimension: per wave, one ballot per dimension
+    //    for the lanes of each node present in the wave
+    for (int base = 0; base < count; base += NT) {
+      const int p = base + threadIdx.x;
+      const int sg = (p < count) ? find(p) : -1;
+      uint32_t bitsv = 0;          // bit j: next bit of dimension j (unrefined dims only)
+      if (sg >= 0) {
+        const uint4 v = rows[ord[p]];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          const int dj = S[sg].depth[j];
+          if (j < K && dj < bits) bitsv |= ((code_byte(v, j) >> (bits - 1 - dj)) & 1u) << j;
+        }
+      }
+      uint64_t pending = __ballot(sg >= 0);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int s0 = __shfl(sg, leader);
+        const bool mine = sg == s0;
+        const uint64_t mm = __ballot(mine);
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          if (j < K) {
+            const uint32_t c = (uint32_t)__popcll(__ballot(mine && ((bitsv >> j) & 1u)));
+            if (lane == leader && c) atomicAdd(&cnt[s0][j], c);
+          }
+        }
+        pending &= ~mm;
+      }
+    }
+    __syncthreads();
+    // 2. split dimension of every open node: the most balanced one, ties to the smallest
+    if ((int)threadIdx.x < nact) {
+      const SegL& g = S[threadIdx.x];
+      int best = -1, best_score = 0;
+      for (int j = 0; j < K; ++j) {
+        if (g.depth[j] >= bits) continue;
+        const int sc = abs(2 * (int)cnt[threadIdx.x][j] - g.count);
+        if (best < 0 || sc < best_score) { best = j; best_score = sc; }
+      }
+      jsel[threadIdx.x] = (uint8_t)best;
+      c0s[threadIdx.x] = (uint16_t)(g.count - (int)cnt[threadIdx.x][best]);
+    }
+    __syncthreads();
+    // 3. stable partition of every open node: a workgroup-wide scan of the bit-0 flags
+    //    over consecutive position runs gives each point its rank among its node's zeros
+    const int p0 = threadIdx.x * PER;
+    uint32_t zmask = 0;
+    int sg = (p0 < count) ? find(p0) : -1;
+    int snext = -1;                                   // first open node starting after p0
+    {
+      int lo2 = 0, hi2 = nact;                        // first start > p0
+      while (lo2 < hi2) {
+        const int md = (lo2 + hi2) >> 1;
+        if (S[md].start <= p0) lo2 = md + 1; else hi2 = md;
+      }
+      snext = lo2;
+    }
+    int segof[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int p = p0 + e;
+      segof[e] = -1;
+      if (p >= count) continue;
+      if (snext < nact && S[snext].start == p) { sg = snext; ++snext; }
+      if (sg >= 0 && p >= S[sg].start + S[sg].count) sg = -1;
+      if (sg < 0) continue;
+      segof[e] = sg;
+      const int j = jsel[sg];
+      const uint32_t bit = (code_byte(rows[ord[p]], j) >> (bits - 1 - S[sg].depth[j])) & 1u;
+      if (!bit) zmask |= 1u << e;
+    }
+    uint32_t ztot;
+    const uint32_t zbase = block_excl_scan<NT>((uint32_t)__popc(zmask), sh_scan, &ztot);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int g = segof[e];
+      if (g >= 0 && p0 + e == S[g].start)
+        zstart[g] = zbase + (uint32_t)__popc(zmask & ((1u << e) - 1u));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int p = p0 + e;
+      if (p >= count) continue;
+      const int g = segof[e];
+      if (g < 0) { tmp[p] = ord[p]; continue; }
+      const uint32_t zb = zbase + (uint32_t)__popc(zmask & ((1u << e) - 1u)) - zstart[g];
+      const int off = p - S[g].start;
+      const int np = ((zmask >> e) & 1u) ? S[g].start + (int)zb
+                                         : S[g].start + (int)c0s[g] + (off - (int)zb);
+      tmp[np] = ord[p];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < count; t += NT) ord[t] = tmp[t];
+    // 4. children: leaves are emitted, open ones form the next level's list (in position
+    //    order: children of a node are adjacent, bit 0 first)
+    uint32_t nopen = 0;
+    SegL ca, cb;
+    bool oa = false, ob = false;
+    if ((int)threadIdx.x < nact) {
+      const SegL& g = S[threadIdx.x];
+      const int j = jsel[threadIdx.x];
+      const int z = c0s[threadIdx.x];
+      ca = g;
+      cb = g;
+      ca.count = (int16_t)z;
+      cb.start = (int16_t)(g.start + z);
+      cb.count = (int16_t)(g.count - z);
+      ca.depth[j] = cb.depth[j] = (uint8_t)(g.depth[j] + 1);
+      ca.prefix[j] = (uint8_t)(g.prefix[j] * 2);
+      cb.prefix[j] = (uint8_t)(g.prefix[j] * 2 + 1);
+      const bool full = fully_refined(ca.depth, K, bits);
+      oa = ca.count > max_leaf && !full;
+      ob = cb.count > max_leaf && !full;
+      if (!oa && ca.count > 0)
+        emit_leaf(lo, n, s.tree, (int64_t)s.start + ca.start, ca.count, ca.depth, ca.prefix, K);
+      if (!ob && cb.count > 0)
+        emit_leaf(lo, n, s.tree, (int64_t)s.start + cb.start, cb.count, cb.depth, cb.prefix, K);
+      nopen = (oa ? 1u : 0u) + (ob ? 1u : 0u);
+    }
+    uint32_t total;
+    const uint32_t at = block_excl_scan<NT>(nopen, sh_scan, &total);
+    if ((int)threadIdx.x < nact) {
+      SegL* Nx = segs[cur ^ 1];
+      uint32_t w = at;
+      if (oa) Nx[w++] = ca;
+      if (ob) Nx[w] = cb;
+    }
+    if (threadIdx.x == 0) s_nact = total;
+    __syncthreads();
+    cur ^= 1;
+  }
+  int32_t* out = b.ids[0] + tb + s.start;
+  for (int t = threadIdx.x; t < count; t += NT) out[t] = ids[ord[t]];
+}
+
+// Depth-first form for small max_leaf (more open nodes than the frontier form tracks):
+// one node split at a time, with an explicit stack.
+constexpr int STACK_MAX = KP * 8 + 8;
+
+struct Node {
+  int16_t lstart, lcount;
+  uint8_t depth[KP];
+  uint8_t prefix[KP];
+};
+
+template <int CAP, int NT>
+__global__ __launch_bounds__(NT) void seg_lds_dfs(const Seg* mid, Bufs b, int64_t n, int K,
+                                                  int bits, int max_leaf, int below,
+                                                  LeafOut lo) {
   __shared__ int32_t ids[CAP];
   __shared__ uint4 rows[CAP];
   __shared__ uint16_t idx[CAP];
@@ -328,10 +573,11 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
   const Seg s = mid[blockIdx.x];
   if (s.count <= below || s.count > CAP) return;
   const int64_t tb = (int64_t)s.tree * n;
+  const uint4* rsrc = b.rows[s.buf] + tb + s.start;
+  const int32_t* isrc = b.ids[s.buf] + tb + s.start;
   for (int t = threadIdx.x; t < s.count; t += blockDim.x) {
-    const int32_t id = perm[tb + s.start + t];
-    ids[t] = id;
-    rows[t] = *reinterpret_cast<const uint4*>(codes + (tb + id) * KP);
+    ids[t] = isrc[t];
+    rows[t] = rsrc[t];
     idx[t] = (uint16_t)t;
   }
   if (threadIdx.x == 0) {
@@ -347,13 +593,11 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
   for (;;) {
     if (threadIdx.x == 0) {
       // pop until a node to split (state 2) or an empty stack (state 0); leaves met on the
-      // way are emitted here, in the same depth-first order
+      // way are emitted here
       state = 0;
       while (sp > 0) {
         cur = stack[--sp];
-        bool fully = true;
-        for (int j = 0; j < K; ++j) fully = fully && (cur.depth[j] >= bits);
-        if (cur.lcount <= max_leaf || fully) {
+        if (cur.lcount <= max_leaf || fully_refined(cur.depth, K, bits)) {
           emit_leaf(lo, n, s.tree, (int64_t)s.start + cur.lstart, cur.lcount, cur.depth,
                     cur.prefix, K);
           continue;
@@ -372,11 +616,10 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
 #pragma unroll
     for (int j = 0; j < KP; ++j) local[j] = 0;
     for (int t = threadIdx.x; t < cur.lcount; t += blockDim.x) {
-      uint8_t c[KP];
-      *reinterpret_cast<uint4*>(c) = rows[idx[cur.lstart + t]];
+      const uint4 v = rows[idx[cur.lstart + t]];
 #pragma unroll
       for (int j = 0; j < KP; ++j)
-        if (j < K && cur.depth[j] < bits) local[j] += (c[j] >> (bits - 1 - cur.depth[j])) & 1;
+        if (j < K && cur.depth[j] < bits) local[j] += (code_byte(v, j) >> (bits - 1 - cur.depth[j])) & 1;
     }
 #pragma unroll
     for (int j = 0; j < KP; ++j) {
@@ -393,14 +636,14 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
         if (best < 0 || sc < best_score) { best = j; best_score = sc; }
       }
       const int c0 = cur.lcount - (int)cnt[best];
-      Node a = cur, b = cur;
+      Node a = cur, bn = cur;
       a.lcount = (int16_t)c0;
-      b.lstart = (int16_t)(cur.lstart + c0);
-      b.lcount = (int16_t)(cur.lcount - c0);
-      a.depth[best] = b.depth[best] = cur.depth[best] + 1;
+      bn.lstart = (int16_t)(cur.lstart + c0);
+      bn.lcount = (int16_t)(cur.lcount - c0);
+      a.depth[best] = bn.depth[best] = cur.depth[best] + 1;
       a.prefix[best] = (uint8_t)(cur.prefix[best] * 2);
-      b.prefix[best] = (uint8_t)(cur.prefix[best] * 2 + 1);
-      if (b.lcount > 0) stack[sp++] = b;     // popped after the bit-0 child
+      bn.prefix[best] = (uint8_t)(cur.prefix[best] * 2 + 1);
+      if (bn.lcount > 0) stack[sp++] = bn;     // popped after the bit-0 child
       if (a.lcount > 0) stack[sp++] = a;
       jsplit = best;
       cz = (uint32_t)cur.lstart;
@@ -409,8 +652,8 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
     __syncthreads();
     const int j = jsplit;
     const int sh = bits - 1 - cur.depth[j];
-    for (int b = 0; b < cur.lcount; b += blockDim.x) {
-      const int t = b + threadIdx.x;
+    for (int b0 = 0; b0 < cur.lcount; b0 += blockDim.x) {
+      const int t = b0 + threadIdx.x;
       const bool valid = t < cur.lcount;
       uint16_t e = 0;
       int bit = 0;
@@ -434,7 +677,8 @@ __global__ __launch_bounds__(NT) void seg_lds_finish(const Seg* mid, int32_t* pe
     __syncthreads();
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < s.count; t += blockDim.x) perm[tb + s.start + t] = ids[idx[t]];
+  int32_t* out = b.ids[0] + tb + s.start;
+  for (int t = threadIdx.x; t < s.count; t += blockDim.x) out[t] = ids[idx[t]];
 }
 
 // ---- leaf tables
@@ -535,39 +779,6 @@ __global__ __launch_bounds__(256) void group_boxes(GroupArgs a) {
   }
 }
 
-// Build temporaries come from a process-wide pool: they go back only after the build has
-// synchronised its stream (or are freed if an error unwinds the build), so a later build
-// of the same size reuses them without hipMalloc / hipFree. At most kPoolCap bytes are kept.
-class ScratchPool {
- public:
-  DevBuf take(size_t b) {
-    {
-      std::lock_guard<std::mutex> g(mu_);
-      for (size_t i = 0; i < free_.size(); ++i)
-        if (free_[i].bytes == b) {
-          DevBuf d = std::move(free_[i]);
-          free_.erase(free_.begin() + (int64_t)i);
-          held_ -= b;
-          return d;
-        }
-    }
-    return DevBuf(b);
-  }
-  void give(DevBuf&& d) {
-    if (!d.p) return;
-    if (std::uncaught_exceptions() > 0) { d.release(); return; }
-    std::lock_guard<std::mutex> g(mu_);
-    if (held_ + d.bytes > kPoolCap) { d.release(); return; }
-    held_ += d.bytes;
-    free_.push_back(std::move(d));
-  }
- private:
-  static constexpr size_t kPoolCap = size_t(2) << 30;
-  std::mutex mu_;
-  std::vector<DevBuf> free_;
-  size_t held_ = 0;
-};
-
 // A small pinned host area per thread for counter readbacks (kept until the thread ends).
 uint32_t* readback_words() {
   struct Words {
@@ -578,26 +789,6 @@ uint32_t* readback_words() {
   if (!w.p) PDET_HIP(hipHostMalloc((void**)&w.p, 64 * sizeof(uint32_t), hipHostMallocDefault));
   return w.p;
 }
-
-ScratchPool& scratch_pool() {
-  static ScratchPool* p = new ScratchPool();   // lives until the process ends
-  return *p;
-}
-
-// A build temporary with DevBuf's interface, taken from and returned to the pool.
-struct PooledBuf {
-  DevBuf d;
-  PooledBuf() = default;
-  explicit PooledBuf(size_t b) { alloc(b); }
-  ~PooledBuf() { scratch_pool().give(std::move(d)); }
-  void alloc(size_t b) {
-    scratch_pool().give(std::move(d));
-    if (b) d = scratch_pool().take(b);
-  }
-  size_t bytes() const { return d.bytes; }
-  void* ptr() const { return d.p; }
-  template <class T> T* as() const { return d.as<T>(); }
-};
 
 }  // namespace
 
@@ -612,15 +803,18 @@ void build_trees(Index& ix, hipStream_t s) {
   DevBuf scan_tmp;
   PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
   PDET_HIP(hipMemsetAsync(cursor.ptr(), 0, cursor.bytes(), s));
-  const uint8_t* codes = ix.codes.as<uint8_t>();
-  int32_t* perm = ix.perm.as<int32_t>();
+  const uint16_t* flkey = ix.flkey.as<uint16_t>();
+  DevBuf rows0((size_t)L * n * KP);   // code rows in permutation order (buffer 0)
+  Bufs bf{};
+  bf.rows[0] = rows0.as<uint4>();
+  bf.ids[0] = ix.perm.as<int32_t>();
 
-  hipLaunchKernelGGL(fl_hist, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, codes, n, K, bits,
+  hipLaunchKernelGGL(fl_hist, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, flkey, n, K,
                      hist.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   scan_rows(hist.as<uint32_t>(), off.as<uint32_t>(), nullptr, L, NK, scan_tmp, s);
-  hipLaunchKernelGGL(fl_scatter, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, codes, n, K, bits,
-                     off.as<uint32_t>(), cursor.as<uint32_t>(), perm);
+  hipLaunchKernelGGL(fl_scatter, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, flkey,
+                     ix.codes.as<uint8_t>(), n, K, off.as<uint32_t>(), cursor.as<uint32_t>(), bf);
   PDET_HIP(hipGetLastError());
 
   // leaf records at start positions
@@ -628,58 +822,68 @@ void build_trees(Index& ix, hipStream_t s) {
   PDET_HIP(hipMemsetAsync(cnt_at.ptr(), 0, cnt_at.bytes(), s));
   LeafOut lo{cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>()};
 
-  // segment lists; counters: [0] n_big_a [1] max_big_a [2] n_big_b [3] max_big_b [4] n_mid
+  // node lists; counters: [0] n_big_a [1] max_big_a [2] n_big_b [3] max_big_b [4] n_mid
+  // [5] n_copies
   const int64_t mid_cap = (int64_t)L * (n / (ix.max_leaf + 1) + 1);
   const int64_t big_cap = (int64_t)L * (n / (LDS_SEG_CAP + 1) + 1);
   PooledBuf mid((size_t)mid_cap * sizeof(Seg));
   PooledBuf bigA((size_t)big_cap * sizeof(Seg)), bigB((size_t)big_cap * sizeof(Seg));
+  PooledBuf copies((size_t)2 * big_cap * sizeof(Copy));
   PooledBuf ctr(8 * 4);
   PDET_HIP(hipMemsetAsync(ctr.ptr(), 0, ctr.bytes(), s));
   uint32_t* c = ctr.as<uint32_t>();
-  Lists li{bigA.as<Seg>(), c + 0, c + 1, mid.as<Seg>(), c + 4};
+  Lists li{bigA.as<Seg>(), c + 0, c + 1, mid.as<Seg>(), c + 4, copies.as<Copy>(), c + 5};
   hipLaunchKernelGGL(fl_segments, dim3(cdiv(L * NK, 256)), dim3(256), 0, s, hist.as<uint32_t>(),
                      off.as<uint32_t>(), L, K, bits, ix.max_leaf, n, lo, li);
   PDET_HIP(hipGetLastError());
 
-  uint32_t hc[8];
-  PDET_HIP(hipMemcpyAsync(hc, c, sizeof(hc), hipMemcpyDeviceToHost, s));
+  uint32_t* hc = readback_words();
+  PDET_HIP(hipMemcpyAsync(hc, c, 8 * 4, hipMemcpyDeviceToHost, s));
   PDET_HIP(hipStreamSynchronize(s));
   uint32_t nbig = hc[0], maxbig = hc[1];
   Seg* cur_big = bigA.as<Seg>();
   Seg* nxt_big = bigB.as<Seg>();
   int cur_slot = 0;   // counters of the current list at c[2*cur_slot]
-  PooledBuf perm_tmp, cntbuf, split, c0, cur0, cur1;
-  if (nbig) perm_tmp.alloc((size_t)L * n * 4);
+  DevBuf rows1;
+  PooledBuf ids1, cntbuf, split, c0, cur0, cur1, leafs;
+  if (nbig) {
+    rows1.alloc((size_t)L * n * KP);
+    ids1.alloc((size_t)L * n * 4);
+    bf.rows[1] = rows1.as<uint4>();
+    bf.ids[1] = ids1.as<int32_t>();
+    cntbuf.alloc((size_t)big_cap * KP * 4);
+    split.alloc((size_t)big_cap * 4); c0.alloc((size_t)big_cap * 4);
+    cur0.alloc((size_t)big_cap * 4); cur1.alloc((size_t)big_cap * 4);
+    leafs.alloc((size_t)big_cap);
+  }
   while (nbig > 0) {
-    if (cntbuf.bytes() < (size_t)nbig * KP * 4) {
-      cntbuf.alloc((size_t)big_cap * KP * 4);
-      split.alloc((size_t)big_cap * 4); c0.alloc((size_t)big_cap * 4);
-      cur0.alloc((size_t)big_cap * 4); cur1.alloc((size_t)big_cap * 4);
-    }
     PDET_HIP(hipMemsetAsync(cntbuf.ptr(), 0, (size_t)nbig * KP * 4, s));
     const int nxt_slot = 1 - cur_slot;
     PDET_HIP(hipMemsetAsync(c + 2 * nxt_slot, 0, 8, s));
+    PDET_HIP(hipMemsetAsync(c + 5, 0, 4, s));
     const unsigned ch = std::max(1u, std::min(1024u, cdiv(maxbig, 256 * 16)));
-    hipLaunchKernelGGL(seg_bitcount, dim3(nbig, ch), dim3(256), 0, s, cur_big, perm, codes, n, K,
-                       bits, cntbuf.as<uint32_t>());
+    hipLaunchKernelGGL(seg_count, dim3(nbig, ch), dim3(256), 0, s, cur_big, bf, n, K, bits,
+                       cntbuf.as<uint32_t>());
     PDET_HIP(hipGetLastError());
     hipLaunchKernelGGL(seg_choose, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
-                       cntbuf.as<uint32_t>(), K, bits, split.as<int32_t>(), c0.as<uint32_t>(),
-                       cur0.as<uint32_t>(), cur1.as<uint32_t>());
+                       cntbuf.as<uint32_t>(), K, bits, ix.max_leaf, split.as<int32_t>(),
+                       c0.as<uint32_t>(), cur0.as<uint32_t>(), cur1.as<uint32_t>(),
+                       leafs.as<uint8_t>());
     PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL(seg_partition, dim3(nbig, ch), dim3(256), 0, s, cur_big, split.as<int32_t>(),
-                       perm, perm_tmp.as<int32_t>(), codes, n, bits, cur0.as<uint32_t>(),
-                       cur1.as<uint32_t>());
+    hipLaunchKernelGGL(seg_split, dim3(nbig, ch), dim3(256), 0, s, cur_big, split.as<int32_t>(),
+                       leafs.as<uint8_t>(), bf, n, bits, cur0.as<uint32_t>(), cur1.as<uint32_t>());
     PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL(seg_copyback, dim3(nbig, ch), dim3(256), 0, s, cur_big,
-                       perm_tmp.as<int32_t>(), perm, n);
-    PDET_HIP(hipGetLastError());
-    Lists ln{nxt_big, c + 2 * nxt_slot, c + 2 * nxt_slot + 1, mid.as<Seg>(), c + 4};
+    Lists ln{nxt_big, c + 2 * nxt_slot, c + 2 * nxt_slot + 1, mid.as<Seg>(), c + 4,
+             copies.as<Copy>(), c + 5};
     hipLaunchKernelGGL(seg_children, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
                        split.as<int32_t>(), c0.as<uint32_t>(), K, bits, ix.max_leaf, n, lo, ln);
     PDET_HIP(hipGetLastError());
-    PDET_HIP(hipMemcpyAsync(hc, c, sizeof(hc), hipMemcpyDeviceToHost, s));
+    PDET_HIP(hipMemcpyAsync(hc, c, 8 * 4, hipMemcpyDeviceToHost, s));
     PDET_HIP(hipStreamSynchronize(s));
+    if (hc[5]) {
+      hipLaunchKernelGGL(seg_copy, dim3(hc[5]), dim3(256), 0, s, copies.as<Copy>(), bf, n);
+      PDET_HIP(hipGetLastError());
+    }
     nbig = hc[2 * nxt_slot];
     maxbig = hc[2 * nxt_slot + 1];
     std::swap(cur_big, nxt_big);
@@ -687,19 +891,22 @@ void build_trees(Index& ix, hipStream_t s) {
   }
   const uint32_t nmid = hc[4];
   if (nmid) {
-    // size classes (below, CAP]: each block of a launch finishes one node of its class
-    hipLaunchKernelGGL((seg_lds_finish<256, 64>), dim3(nmid), dim3(64), 0, s, mid.as<Seg>(),
-                       perm, codes, n, K, bits, ix.max_leaf, 0, lo);
-    PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL((seg_lds_finish<512, 128>), dim3(nmid), dim3(128), 0, s, mid.as<Seg>(),
-                       perm, codes, n, K, bits, ix.max_leaf, 256, lo);
-    PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL((seg_lds_finish<1024, 256>), dim3(nmid), dim3(256), 0, s, mid.as<Seg>(),
-                       perm, codes, n, K, bits, ix.max_leaf, 512, lo);
-    PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL((seg_lds_finish<LDS_SEG_CAP, 256>), dim3(nmid), dim3(256), 0, s,
-                       mid.as<Seg>(), perm, codes, n, K, bits, ix.max_leaf, 1024, lo);
-    PDET_HIP(hipGetLastError());
+    // size classes (below, CAP]: each block of a launch finishes one node of its class, in
+    // the frontier form when the class holds at most FR_MAXS open nodes
+    auto finish = [&](auto cap_c, auto nt_c, int below) {
+      constexpr int CAP = decltype(cap_c)::value, NT = decltype(nt_c)::value;
+      if (CAP / (ix.max_leaf + 1) <= FR_MAXS)
+        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT>), dim3(nmid), dim3(NT), 0, s,
+                           mid.as<Seg>(), bf, n, K, bits, ix.max_leaf, below, lo);
+      else
+        hipLaunchKernelGGL((seg_lds_dfs<CAP, NT>), dim3(nmid), dim3(NT), 0, s, mid.as<Seg>(),
+                           bf, n, K, bits, ix.max_leaf, below, lo);
+      PDET_HIP(hipGetLastError());
+    };
+    finish(std::integral_constant<int, 256>{}, std::integral_constant<int, 64>{}, 0);
+    finish(std::integral_constant<int, 512>{}, std::integral_constant<int, 128>{}, 256);
+    finish(std::integral_constant<int, 1024>{}, std::integral_constant<int, 256>{}, 512);
+    finish(std::integral_constant<int, LDS_SEG_CAP>{}, std::integral_constant<int, 256>{}, 1024);
   }
 
   // number the leaves in position (= depth-first) order
@@ -712,17 +919,17 @@ void build_trees(Index& ix, hipStream_t s) {
   // per-point leaf ordinals and the leaf-row table need only the scan: they run while the
   // host reads the leaf counts back (into pinned memory, so the copy does not wait for
   // them) and sizes the leaf tables
-  uint32_t* hp = readback_words();
+  uint32_t* hp = readback_words() + 32;   // apart from the level counters (words 0..7)
   PDET_HIP(hipMemcpyAsync(hp, totals.ptr(), L * 4, hipMemcpyDeviceToHost, s));
   hipEvent_t counts_ready;
   PDET_HIP(hipEventCreateWithFlags(&counts_ready, hipEventDisableTiming));
   PDET_HIP(hipEventRecord(counts_ready, s));
   PooledBuf leaf_of((size_t)n * L * 4);
   hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
-                     flags.as<uint32_t>(), perm, n, L, leaf_of.as<int32_t>());
+                     flags.as<uint32_t>(), ix.perm.as<int32_t>(), n, L, leaf_of.as<int32_t>());
   PDET_HIP(hipGetLastError());
-  hipLaunchKernelGGL(leafrow_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, perm,
-                     leaf_of.as<int32_t>(), n, L, ix.leafrow.as<int32_t>());
+  hipLaunchKernelGGL(leafrow_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s,
+                     ix.perm.as<int32_t>(), leaf_of.as<int32_t>(), n, L, ix.leafrow.as<int32_t>());
   PDET_HIP(hipGetLastError());
   const hipError_t ce = hipEventSynchronize(counts_ready);
   (void)hipEventDestroy(counts_ready);
@@ -774,6 +981,7 @@ void build_trees(Index& ix, hipStream_t s) {
     PDET_HIP(hipGetLastError());
   }
   PDET_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
+  ix.flkey.release();
 }
 
 }  // namespace pdet

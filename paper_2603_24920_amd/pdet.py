@@ -23,10 +23,11 @@ QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits
              band_leaf=8, band_stop_b=9)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF = range(7)
 EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_candidates", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
-            "pdet_epsilon", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
+            "pdet_epsilon", "pdet_theoretical_beta", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
-            "pdet_server_get_stats", "pdet_server_free", "pdet_set_list_cap",
+            "pdet_server_get_stats", "pdet_server_free", "pdet_server_offer_poisson",
+            "pdet_set_list_cap",
             "pdet_release_cache"]
 
 
@@ -108,6 +109,8 @@ def lib() -> ctypes.CDLL:
         L.pdet_project.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.pdet_epsilon.argtypes = [c_int32, c_int32]
         L.pdet_epsilon.restype = c_double
+        L.pdet_theoretical_beta.argtypes = [c_int32, c_int32, c_double]
+        L.pdet_theoretical_beta.restype = c_double
         L.pdet_last_error.restype = ctypes.c_char_p
         L.pdet_set_timing.argtypes = [c_int32]
         L.pdet_set_timing.restype = None
@@ -125,9 +128,14 @@ def lib() -> ctypes.CDLL:
         L.pdet_server_submit.argtypes = [c_void_p, c_void_p, c_int32, c_double, POINTER(c_int64)]
         L.pdet_server_wait.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, POINTER(c_double)]
         L.pdet_server_get_stats.argtypes = [c_void_p, POINTER(ServerStats)]
+        L.pdet_server_offer_poisson.argtypes = [c_void_p, c_void_p, c_int64, c_int64, c_double,
+                                                c_int32, c_double, ctypes.c_uint64,
+                                                POINTER(c_double)]
+        L.pdet_server_offer_poisson.restype = c_int32
         L.pdet_server_free.argtypes = [c_void_p]
         L.pdet_server_free.restype = None
-        for f in ("pdet_build", "pdet_query", "pdet_query_candidates", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
+        for f in ("pdet_build", "pdet_query", "pdet_query_candidates", 
+                  "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
                   "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
                   "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
                   "pdet_server_get_stats", "pdet_set_list_cap"):
@@ -144,6 +152,11 @@ def _check(status):
 def epsilon(K: int, L: int) -> float:
     """Projected-radius factor from Eq. 2 / Lemma 3, computed by the library's host code."""
     return lib().pdet_epsilon(K, L)
+
+
+def theoretical_beta(K: int, L: int, c: float) -> float:
+    """beta of Lemma 3 for (K, L, c), computed by the library's host code."""
+    return lib().pdet_theoretical_beta(K, L, c)
 
 
 def set_timing(on: bool) -> None:
@@ -391,6 +404,16 @@ class Server:
         _check(lib().pdet_server_wait(self._h, rid, ids.ctypes.data_as(c_void_p),
                                       dists.ctypes.data_as(c_void_p), ctypes.byref(lat)))
         return ids, dists, lat.value
+
+    def offer_poisson(self, Q: np.ndarray, nreq: int, rate_qps: float, k: int, c: float = 1.5,
+                      seed: int = 0) -> float:
+        """Native Poisson client (pdet_server_offer_poisson); returns the offered rate."""
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        off = c_double()
+        _check(lib().pdet_server_offer_poisson(self._h, Q.ctypes.data_as(c_void_p), Q.shape[0],
+                                               int(nreq), float(rate_qps), int(k), float(c),
+                                               int(seed), ctypes.byref(off)))
+        return off.value
 
     def stats(self) -> dict:
         st = ServerStats()

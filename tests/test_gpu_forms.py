@@ -265,3 +265,42 @@ def test_recycled_device_blocks_give_the_same_index_and_results():
         for key in ("f32", "bf16"):
             assert all(torch.equal(a, b) for a, b in zip(got[key], ref[key])), (rep, key)
     pdet.release_cache()
+
+
+def test_theoretical_beta_mode_equals_explicit_beta(env):
+    """beta < 0 takes Lemma 3's beta for each query's c: a mixed-c batch equals the same
+    queries run with their theoretical beta passed explicitly (c by c)."""
+    w, X, A, sid, idx, Q, Qd = env
+    ks, cs = uneven(len(Q), seed=21)
+    ks = np.minimum(ks, 10).astype(np.int32)
+    ids, dists, st = idx.query(Qd, k=0, beta=-1.0, r_min=2.0, k_per_query=ks, c_per_query=cs,
+                               stats=True)
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(ks)])
+    for c in (1.2, 1.5, 2.0):
+        sel = np.nonzero(cs == c)[0]
+        beta = oracle.theoretical_beta(w.K, w.L, c)
+        e_ids, e_d = idx.query(Qd[torch.from_numpy(sel).cuda()].contiguous(), k=0, beta=beta,
+                               r_min=2.0, k_per_query=ks[sel], c_per_query=cs[sel])
+        e_ids, e_d = e_ids.cpu().numpy(), e_d.cpu().numpy()
+        eo = np.concatenate([[0], np.cumsum(ks[sel])])
+        for j, q in enumerate(sel):
+            np.testing.assert_array_equal(ids[off[q]:off[q + 1]], e_ids[eo[j]:eo[j + 1]])
+            np.testing.assert_array_equal(dists[off[q]:off[q + 1]], e_d[eo[j]:eo[j + 1]])
+
+
+def test_autotuned_radius_equals_the_oracle_counterpart(env):
+    """The dataset-level r_min of pdet_autotune against the oracle's reading of the magic
+    r_min (first radius from the breakpoint ranges, pilots run from it, one grid step below
+    the median terminating radius) on the GPU's breakpoints and codes."""
+    w, X, A, sid, idx, Q, Qd = env
+    pilots = 64
+    t = idx.autotune(Qd[:pilots].contiguous(), k=w.k, c=w.c, beta=0.05)
+    B = idx.export(pdet.X_BREAKPOINTS).astype(np.float64)
+    codes = np.ascontiguousarray(idx.export(pdet.X_CODES)[:, :, :w.K])
+    ref = oracle.build_index(X, A, sid, w.L, w.K, w.Nr, w.max_leaf, B=B, codes=codes)
+    eps = oracle.epsilon(w.K, w.L)
+    r0 = oracle.autotune_first_radius(B, w.K, w.L)
+    r = oracle.autotune_r_min(ref, X, Q[:pilots], w.k, w.c, 0.05, eps, r0)
+    print(f"[autotune] library r_min={t['r_min']:.9g} oracle r_min={r:.9g}", flush=True)
+    assert abs(t["r_min"] - r) <= 1e-9 * r

@@ -68,7 +68,8 @@ def test_full_batch_sampled_queries_fp32(full):
     w, cs, Q, Qd, t, sel = full
     print(f"[full fp32] nq={len(Q)} beta={BETA} r_min={t['r_min']:.6g} "
           f"rounds_resolved={t['rounds_resolved']}", flush=True)
-    ids, dists, st = cs.idx.query(Qd, k=w.k, c=w.c, beta=BETA, r_min=t["r_min"], stats=True)
+    ids, dists, st = cs.idx.query(Qd, k=w.k, c=w.c, beta=BETA, r_min=t["r_min"], eps=cs.eps,
+                                  stats=True)
     ids, dists, st = ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
     compare_queries(cs, cs.stepwise_oracle(), Q, sel, ids, dists, st, w.k, w.c, BETA,
                     t["r_min"], "full fp32", allow_frac=0.02)
@@ -83,7 +84,8 @@ def test_full_batch_sampled_queries_fp32(full):
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_full_batch_low_precision_recall(full, prec):
     w, cs, Q, Qd, t, sel = full
-    ids, dists = cs.idx.query(Qd, k=w.k, c=w.c, beta=BETA, r_min=t["r_min"], precision=prec,
+    ids, dists = cs.idx.query(Qd, k=w.k, c=w.c, beta=BETA, r_min=t["r_min"], eps=cs.eps,
+                              precision=prec,
                               rescore=4)
     ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
     idx_or = cs.stepwise_oracle()

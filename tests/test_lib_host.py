@@ -102,24 +102,6 @@ def test_threaded_generation_reproduces_the_serial_draw(monkeypatch):
     assert seen[-1] == (8, 8) and len(seen) == 8
 
 
-def test_build_rejects_a_sample_too_large_for_one_sort_dispatch():
-    """L*K*n_sample (rounded up to a power of two) at 2^32 would need more work-items than
-    one dispatch holds; the build refuses it before any device work on the sample."""
-    p, keep = _params()
-    n = (1 << 28) - 1
-    ids = np.arange(1 << 26, dtype=np.int64)
-    p.L, p.K = 16, 16
-    p.sample_ids = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-    p.n_sample = (1 << 26) + 0   # 256 columns * 2^26 = 2^34 keys
-    proj = np.zeros((8, 256), dtype=np.float32)
-    p.proj = proj.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-    h = ctypes.c_void_p()
-    st = pdet.lib().pdet_build(ctypes.c_void_p(4096), n, 8, ctypes.byref(p), None,
-                               ctypes.byref(h))
-    assert st == pdet.PDET_EUNSUPPORTED and h.value is None
-    assert "2^32" in pdet.lib().pdet_last_error().decode()
-
-
 def test_bench_refuses_more_than_one_gpu():
     """The benchmark measures one GPU; --gpus 2 exits with status 2 and says why, before it
     imports torch or touches a device."""
@@ -129,3 +111,16 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("L", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("c", [1.2, 1.5, 2.0])
+def test_theoretical_beta_matches_lemma3(L, c):
+    """The library's theoretical beta (Lemma 3) against the oracle's (SciPy chi2)."""
+    want = oracle.theoretical_beta(16, L, c)
+    assert abs(pdet.theoretical_beta(16, L, c) - want) <= 1e-9 * max(want, 1e-12)
+
+
+def test_theoretical_beta_invalid():
+    assert math.isnan(pdet.theoretical_beta(16, 4, 1.0))
+    assert math.isnan(pdet.theoretical_beta(0, 4, 1.5))
