@@ -162,6 +162,27 @@ pdet_status pdet_query_candidates(const pdet_index* idx, const float* queries, i
                                   const pdet_query_params* p, int64_t* ids, float* dists,
                                   int32_t* qstats, int32_t* cand, int64_t cand_cap, void* stream);
 
+/*
+ * pdet_query without device allocation. For callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same arguments,
+ * results and errors as pdet_query, except that k and c must be uniform (k_per_query and
+ * c_per_query NULL, else EINVAL), and the per-query scratch lives in one static device
+ * array of PDET_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends. The array holds the batch's per-query arrays (4*L*K + 32 bytes
+ * per query) and as many query slots as then fit (a slot holds every leaf of every tree:
+ * about L*nl + 28*(sum of the trees' leaves) bytes); the batch runs in chunks of that many
+ * queries. A batch for which the per-query arrays and one slot exceed the array gets
+ * EUNSUPPORTED with the sizes in the message. The call makes no hipMalloc / hipFree and no
+ * allocating library call, and never synchronises the stream (pdet_build looked the array
+ * up on its device, so the runtime placed it there before). Calls that overlap on one
+ * device share the array and race: serialise them (one stream, or wait between calls).
+ * Must run with the index's device current.
+ */
+#define PDET_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pdet_status pdet_query_noalloc(const pdet_index* idx, const float* queries, int64_t nq,
+                               const pdet_query_params* p, int64_t* ids, float* dists,
+                               int32_t* qstats, void* stream);
+
 /* Sizes the index's query workspace (per-query scratch: round-index tables, admitted-leaf
  * lists, thresholds) for batches of up to nq queries, so that a later pdet_query of at most
  * nq queries allocates nothing. Not an operation of the method itself: the search of

@@ -329,6 +329,7 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     ix->X = data;
     ix->dpad = ((d + 15) / 16) * 16;
     PDET_HIP(hipGetDevice(&ix->device));
+    noalloc_setup(ix->device);
     PDET_HIP(hipDeviceGetAttribute(&ix->num_cus, hipDeviceAttributeMultiprocessorCount,
                                    ix->device));
     const int LK = ix->L * ix->K;

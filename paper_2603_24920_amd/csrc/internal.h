@@ -211,6 +211,13 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
                    hipStream_t s, bool timed);
 // For a workspace with capped lists: waits for stream s, then answers the batch's flagged
 // queries again with full-capacity slots (a no-op for uncapped workspaces).
+// pdet_query_noalloc (noalloc.hip): the batch in chunks of slots laid out in the library's
+// static scratch array; uniform k and c.
+void run_query_noalloc(const Index& ix, const QueryConfig& qc, int32_t k, double c,
+                       hipStream_t s);
+// Looks up this device's copy of the scratch array (once per device; pdet_build calls it, so
+// that the runtime has placed the array before any allocation-free query runs).
+void noalloc_setup(int dev);
 void retry_overflowed(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, int maxKL,
                       hipStream_t s, bool timed);
 

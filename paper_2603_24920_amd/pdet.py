@@ -22,7 +22,7 @@ QSTAT_WORDS = 10
 QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits=7,
              band_leaf=8, band_stop_b=9)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF = range(7)
-EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_candidates", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
+EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
             "pdet_epsilon", "pdet_theoretical_beta", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.pdet_query_candidates.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
                                             c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                             c_void_p]
+        L.pdet_query_noalloc.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
+                                         c_void_p, c_void_p, c_void_p, c_void_p]
         L.pdet_reserve.argtypes = [c_void_p, c_int64, c_void_p]
         L.pdet_set_list_cap.argtypes = [c_void_p, c_int64]
         L.pdet_release_cache.argtypes = []
@@ -134,7 +136,7 @@ def lib() -> ctypes.CDLL:
         L.pdet_server_offer_poisson.restype = c_int32
         L.pdet_server_free.argtypes = [c_void_p]
         L.pdet_server_free.restype = None
-        for f in ("pdet_build", "pdet_query", "pdet_query_candidates", 
+        for f in ("pdet_build", "pdet_query", "pdet_query_candidates", "pdet_query_noalloc",
                   "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
                   "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
                   "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -315,6 +317,17 @@ class Index:
             ids, dists = ids.view(nq, k), dists.view(nq, k)
         return (ids, dists, st) if stats else (ids, dists)
 
+
+    def query_noalloc(self, Q, ids, dists, qstats=None, k=10, c=1.5, beta=0.1, r_min=1.0,
+                      eps=0.0, precision="fp32", rescore=4, stream=None):
+        """pdet_query_noalloc into caller-owned outputs (ids int64 [nq*k], dists float32
+        [nq*k], qstats int32 [nq][QSTAT_WORDS] or None): uniform k and c, no allocation."""
+        p, _ = self._params(k, c, beta, r_min, eps, precision, rescore, None, None)
+        _check(lib().pdet_query_noalloc(self._h, c_void_p(Q.data_ptr()), Q.shape[0],
+                                        ctypes.byref(p), c_void_p(ids.data_ptr()),
+                                        c_void_p(dists.data_ptr()),
+                                        c_void_p(qstats.data_ptr()) if qstats is not None else None,
+                                        _stream(stream)))
 
     def query_candidates(self, Q, cand_cap, k=10, c=1.5, beta=0.1, r_min=1.0, eps=0.0,
                          precision="fp32", rescore=4, k_per_query=None, c_per_query=None,
