@@ -39,6 +39,7 @@ BETA_LADDER = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 5e-4, 2e-4, 1e-4, 5e-
 GEN_THREADS_N = 4_000_000     # from this size: data drawn in parallel chunks (same values)
 MAX_CAL_CANDIDATES = 2e5      # largest beta * n tried by the recall calibration
 POOL = 16                     # host worker processes (the GPU machine's CPU share)
+LITERAL_MAX_N = 4_000_000     # largest index on which the literal query form is timed
 # per workload: low-precision forms measured, and the form of the graph-launched batch
 FORMS = {"sift-like-100M-d128": (("bf16",), "bf16"), "sift-like-1M-d128": (("bf16", "fp8"), "fp32"),
          "normed-1M-d960": (("bf16",), "bf16"), "normed-10M-d256": (("fp8",), "fp8"),
@@ -256,6 +257,29 @@ def measure(w, args, primary, helper=None):
                        rescore=4, speedup_vs_fp32=(nq / sec) / qps)
         log(f"[bench] {w.name} {f}: {lowp[f]}")
 
+    # Algorithm 5 as printed (literal range query, every round over every tree) beside the
+    # optimised query at the same beta, r_min and eps, on the recall queries
+    literal = None
+    if not args.no_literal and w.n <= LITERAL_MAX_N and exact_ids is not None:
+        ix.set_tuning(r_min, rcap)
+        sec_l = timed(lambda: ix.query_literal(Qr, k=w.k, c=w.c, beta=beta, r_min=r_min))
+        lids, _, lst = ix.query_literal(Qr, k=w.k, c=w.c, beta=beta, r_min=r_min)
+        sec_o = timed(lambda: ix.query(Qr, k=w.k, c=w.c, beta=beta, r_min=r_min))
+        oids, _, ost = ix.query(Qr, k=w.k, c=w.c, beta=beta, r_min=r_min, stats=True)
+        lst, ost = lst.cpu().numpy(), ost.cpu().numpy()
+        literal = dict(queries=nrec, beta=beta, r_min=r_min,
+                       qps_literal=nrec / sec_l, qps_optimised=nrec / sec_o,
+                       speedup_optimised=sec_l / sec_o,
+                       recall_at_10_literal=recall_at(lids.cpu().numpy(), exact_ids),
+                       recall_at_10_optimised=recall_at(oids.cpu().numpy(), exact_ids),
+                       mean_rounds_literal=float(lst[:, 0].mean()),
+                       mean_rounds_optimised=float(ost[:, 0].mean()),
+                       mean_candidates_literal=float(lst[:, 1].mean()),
+                       mean_candidates_optimised=float(ost[:, 1].mean()),
+                       mean_point_visits_literal=float(lst[:, 7].mean()),
+                       mean_point_visits_optimised=float(ost[:, 7].mean()))
+        log(f"[bench] {w.name} literal vs optimised: {literal}")
+
     # batching form: one graph-launched batch with k in {1,10,100}, c in {1.2,1.5,2.0}
     batching = None
     if not args.no_plan:
@@ -332,6 +356,7 @@ def measure(w, args, primary, helper=None):
                                   "tflops": 2.0 * w.n * w.d * 16 * w.L / (enc_ms * 1e-3) / 1e12,
                                   "tflops_peak_fp32": 157.3},
         "lowp": lowp,
+        "literal_vs_optimised": literal,
         "batching": batching,
         "serving": serving,
     }
@@ -521,6 +546,8 @@ def main():
     ap.add_argument("--rcap", type=int, default=4, help="rounds resolved (with --beta/--r-min)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-plan", action="store_true", help="skip the graph-launched batch")
+    ap.add_argument("--no-literal", action="store_true",
+                    help="skip timing the literal query form beside the optimised one")
     ap.add_argument("--no-recall", action="store_true",
                     help="with --beta/--r-min: skip the ground truth (profiling runs)")
     ap.add_argument("--plan-precision", default=None,

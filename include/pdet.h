@@ -183,6 +183,38 @@ pdet_status pdet_query_noalloc(const pdet_index* idx, const float* queries, int6
                                const pdet_query_params* p, int64_t* ids, float* dists,
                                int32_t* qstats, void* stream);
 
+/*
+ * The c^2-k-ANN query of Algorithm 5 as printed, without the optimisations that Section
+ * 6.2.2 evaluates: every round re-runs the DET Range Query (Algorithm 3) on each tree at
+ * radius eps*r - a leaf whose lower bound exceeds eps*r is pruned, a leaf whose upper bound
+ * is at most eps*r contributes all its points, any other admitted leaf contributes the
+ * points whose projected distance to q' is smaller than eps*r - and stop rule A
+ * (|S| >= ceil(beta n) + k) is checked after each tree. For comparing the two forms of the
+ * query. Arguments, outputs and errors as pdet_query, except: k and c uniform
+ * (k_per_query / c_per_query non-NULL: EINVAL), FP32 verification only (EINVAL
+ * otherwise), k <= 1024; qstats word PDET_QSTAT_LEAVES counts the leaves examined (LB
+ * within the radius) and PDET_QSTAT_BAND_LEAF the leaf bounds and projected distances that
+ * lie within 1e-5 relative of the threshold. The first call on an index computes and keeps
+ * the float32 hash values of every point (4*L*K bytes per point, the encoder's arithmetic),
+ * which the per-point filter reads. Synchronises `stream`.
+ */
+pdet_status pdet_query_literal(const pdet_index* idx, const float* queries, int64_t nq,
+                               const pdet_query_params* p, int64_t* ids, float* dists,
+                               int32_t* qstats, void* stream);
+
+/*
+ * (r,c)-ANN query (Algorithm 4) at one radius r > 0 for each of nq queries: the literal range
+ * query at eps*r tree by tree, the candidate set S their union; once |S| >= ceil(beta n) + 1
+ * the point of S closest to q is returned; after all L trees the closest point of S is
+ * returned if it lies within c*r, else none. ids int64 [nq] (-1: none), dists float32 [nq]
+ * (+inf: none); qstats as pdet_query_literal, with PDET_QSTAT_STOP 1 (|S| reached beta n + 1),
+ * 2 (a point within c r) or 0 (none). beta < 0 takes Lemma 3's beta for c; eps <= 0 takes
+ * Eq. 2's. Synchronises `stream`.
+ */
+pdet_status pdet_rc_ann(const pdet_index* idx, const float* queries, int64_t nq, double r,
+                        double c, double beta, double eps, int64_t* ids, float* dists,
+                        int32_t* qstats, void* stream);
+
 /* Sizes the index's query workspace (per-query scratch: round-index tables, admitted-leaf
  * lists, thresholds) for batches of up to nq queries, so that a later pdet_query of at most
  * nq queries allocates nothing. Not an operation of the method itself: the search of

@@ -271,7 +271,7 @@ void pool_give(DevBuf&& d) { scratch_pool().give(std::move(d)); }
 }  // namespace pdet
 
 int64_t pdet_index::device_bytes() const {
-  int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + perm.bytes + leafrow.bytes +
+  int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + H.bytes + perm.bytes + leafrow.bytes +
               xbf16.bytes + xfp8.bytes + xscale.bytes + leaf_arena.bytes;
   auto own = [](const pdet::DevBuf& x) { return x.owned ? (int64_t)x.bytes : 0; };
   for (int i = 0; i < PDET_MAX_L; ++i)

@@ -54,6 +54,8 @@ struct pdet_index {
   pdet::DevBuf B;                  // float32 [L*K][Nr+1] breakpoints
   pdet::DevBuf colmm;              // uint32 [2][L*K] ordered min / max of every column
   pdet::DevBuf codes;              // uint8 [L][n][KP]
+  mutable pdet::DevBuf H;          // float32 [n][L*K] hash values (first literal query, kept)
+  mutable std::mutex hash_mu;
   pdet::DevBuf flkey;              // uint16 [L][n] first-layer keys (during the build only)
   pdet::DevBuf perm;               // int32 [L][n]
   pdet::DevBuf leafrow;            // int32 [L][n][L]: for the point at perm position p of tree
@@ -215,6 +217,10 @@ void enqueue_query(const Index& ix, const QueryConfig& qc, QueryWorkspace& ws, i
 // static scratch array; uniform k and c.
 void run_query_noalloc(const Index& ix, const QueryConfig& qc, int32_t k, double c,
                        hipStream_t s);
+// literal.hip: Algorithm 5 as printed (rc_mode false) or Algorithm 4 (rc_mode true, k = 1)
+void run_query_literal(const Index& ix, const QueryConfig& qc, int32_t k, double c, bool rc_mode,
+                       hipStream_t s);
+
 // Looks up this device's copy of the scratch array (once per device; pdet_build calls it, so
 // that the runtime has placed the array before any allocation-free query runs).
 void noalloc_setup(int dev);

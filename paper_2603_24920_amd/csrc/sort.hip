@@ -26,9 +26,11 @@ __device__ inline int bucket_of(float v, float lo, float scale) {
   return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
 }
 
-// Column min / max of the sample (ordered uints; mm[col] = min, mm[ncols + col] = max).
+// Column min / max of the sample (ordered uints; mm[col] = min, mm[ncols + col] = max): a
+// few blocks per column, reduced in the block, two atomics per block.
 __global__ __launch_bounds__(256) void col_minmax(const float* keys, int64_t ld, int64_t ns,
                                                   int ncols, uint32_t* mm) {
+  __shared__ float wlo[4], whi[4];
   const int col = blockIdx.y;
   const float* c = keys + (int64_t)col * ld;
   float lo = INFINITY, hi = -INFINITY;
@@ -42,7 +44,10 @@ __global__ __launch_bounds__(256) void col_minmax(const float* keys, int64_t ld,
     lo = fminf(lo, __shfl_xor(lo, o));
     hi = fmaxf(hi, __shfl_xor(hi, o));
   }
-  if ((threadIdx.x & 63) == 0) {
+  if ((threadIdx.x & 63) == 0) { wlo[threadIdx.x >> 6] = lo; whi[threadIdx.x >> 6] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) { lo = fminf(lo, wlo[w]); hi = fmaxf(hi, whi[w]); }
     atomicMin(&mm[col], float_to_ordered(lo));
     atomicMax(&mm[ncols + col], float_to_ordered(hi));
   }
@@ -347,7 +352,7 @@ void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
   PDET_HIP(hipMemsetAsync(mm.as<uint32_t>() + ncols, 0, (size_t)ncols * 4, s));
   PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
   PDET_HIP(hipMemsetAsync(fill.ptr(), 0, fill.bytes(), s));
-  const unsigned mmg = (unsigned)std::min<int64_t>(cdiv(ns, 256), 1024);
+  const unsigned mmg = (unsigned)std::min<int64_t>(cdiv(ns, 256 * 32), 64);
   hipLaunchKernelGGL(col_minmax, dim3(mmg, ncols), dim3(256), 0, s, keys, ld, ns, ncols,
                      mm.as<uint32_t>());
   PDET_HIP(hipGetLastError());

@@ -340,7 +340,8 @@ __global__ void seg_copy(const Copy* cp, Bufs b, int64_t n) {
 
 // Frontier form: every open node of a level is split at once. Open nodes hold more than
 // max_leaf points each, so a workgroup of capacity CAP tracks at most CAP / (max_leaf + 1)
-// of them; the host takes this form when that is at most FR_MAXS.
+// of them; the host takes this form (with MAXS of 16 or 64, the smaller LDS footprint when it
+// suffices) when that is at most 64.
 constexpr int FR_MAXS = 64;
 
 struct SegL {
@@ -352,21 +353,20 @@ struct SegL {
 // Instantiated per size class (count in (below, CAP], NT threads): LDS and threads scale
 // with the node, so small nodes run many workgroups per CU. Blocks whose node is outside
 // the class return at once.
-template <int CAP, int NT>
+template <int CAP, int NT, int MAXS>
 __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, int64_t n, int K,
                                                        int bits, int max_leaf, int below,
                                                        LeafOut lo) {
   constexpr int PER = CAP / NT;           // consecutive positions per thread in the scan
-  static_assert(PER * NT == CAP && PER <= 32, "class shape");
+  static_assert(PER * NT == CAP && PER <= 32 && MAXS <= NT, "class shape");
   __shared__ uint4 rows[CAP];
-  __shared__ int32_t ids[CAP];
   __shared__ uint16_t ord[CAP];
   __shared__ uint16_t tmp[CAP];
-  __shared__ SegL segs[2][FR_MAXS];
-  __shared__ uint32_t cnt[FR_MAXS][KP];
-  __shared__ uint32_t zstart[FR_MAXS];
-  __shared__ uint16_t c0s[FR_MAXS];
-  __shared__ uint8_t jsel[FR_MAXS];
+  __shared__ SegL segs[2][MAXS];
+  __shared__ uint32_t cnt[MAXS][KP];
+  __shared__ uint32_t zstart[MAXS];
+  __shared__ uint16_t c0s[MAXS];
+  __shared__ uint8_t jsel[MAXS];
   __shared__ uint32_t sh_scan[NT / 64 + 1];
   __shared__ uint32_t s_nact;
 
@@ -378,7 +378,6 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
   const int32_t* isrc = b.ids[s.buf] + tb + s.start;
   for (int t = threadIdx.x; t < count; t += NT) {
     rows[t] = rsrc[t];
-    ids[t] = isrc[t];
     ord[t] = (uint16_t)t;
   }
   if (threadIdx.x == 0) {
@@ -540,8 +539,21 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
     __syncthreads();
     cur ^= 1;
   }
+  // the ids in leaf order: every read (the node's ids may sit in the output array) before
+  // any write
+  int32_t outv[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int t = threadIdx.x + e * NT;
+    outv[e] = (t < count) ? isrc[ord[t]] : 0;
+  }
+  __syncthreads();
   int32_t* out = b.ids[0] + tb + s.start;
-  for (int t = threadIdx.x; t < count; t += NT) out[t] = ids[ord[t]];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int t = threadIdx.x + e * NT;
+    if (t < count) out[t] = outv[e];
+  }
 }
 
 // Depth-first form for small max_leaf (more open nodes than the frontier form tracks):
@@ -895,8 +907,12 @@ void build_trees(Index& ix, hipStream_t s) {
     // the frontier form when the class holds at most FR_MAXS open nodes
     auto finish = [&](auto cap_c, auto nt_c, int below) {
       constexpr int CAP = decltype(cap_c)::value, NT = decltype(nt_c)::value;
-      if (CAP / (ix.max_leaf + 1) <= FR_MAXS)
-        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT>), dim3(nmid), dim3(NT), 0, s,
+      const int open_max = CAP / (ix.max_leaf + 1);
+      if (open_max <= 16)
+        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT, 16>), dim3(nmid), dim3(NT), 0, s,
+                           mid.as<Seg>(), bf, n, K, bits, ix.max_leaf, below, lo);
+      else if (open_max <= FR_MAXS)
+        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT, FR_MAXS>), dim3(nmid), dim3(NT), 0, s,
                            mid.as<Seg>(), bf, n, K, bits, ix.max_leaf, below, lo);
       else
         hipLaunchKernelGGL((seg_lds_dfs<CAP, NT>), dim3(nmid), dim3(NT), 0, s, mid.as<Seg>(),

@@ -22,7 +22,7 @@ QSTAT_WORDS = 10
 QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits=7,
              band_leaf=8, band_stop_b=9)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF = range(7)
-EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
+EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_literal", "pdet_rc_ann", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
             "pdet_epsilon", "pdet_theoretical_beta", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -100,6 +100,12 @@ def lib() -> ctypes.CDLL:
                                             c_void_p]
         L.pdet_query_noalloc.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
                                          c_void_p, c_void_p, c_void_p, c_void_p]
+        L.pdet_query_literal.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
+                                         c_void_p, c_void_p, c_void_p, c_void_p]
+        L.pdet_query_literal.restype = c_int32
+        L.pdet_rc_ann.argtypes = [c_void_p, c_void_p, c_int64, c_double, c_double, c_double,
+                                  c_double, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.pdet_rc_ann.restype = c_int32
         L.pdet_reserve.argtypes = [c_void_p, c_int64, c_void_p]
         L.pdet_set_list_cap.argtypes = [c_void_p, c_int64]
         L.pdet_release_cache.argtypes = []
@@ -293,7 +299,7 @@ class Index:
               out=None):
         """c^2-k-ANN for every row of Q (CUDA float32 [nq][d]).
 
-        Returns (ids int64, dists float32[, qstats int32 [nq][8]]). With per-query k the
+        Returns (ids int64, dists float32[, qstats int32 [nq][QSTAT_WORDS]]). With per-query k the
         outputs are flat (CSR in query order); with uniform k they are [nq][k]."""
         import torch
         if not (Q.is_cuda and Q.dtype == torch.float32 and Q.is_contiguous()
@@ -328,6 +334,34 @@ class Index:
                                         c_void_p(dists.data_ptr()),
                                         c_void_p(qstats.data_ptr()) if qstats is not None else None,
                                         _stream(stream)))
+
+    def query_literal(self, Q, k=10, c=1.5, beta=0.1, r_min=1.0, eps=0.0, stream=None):
+        """Algorithm 5 with the literal range query (pdet_query_literal): (ids [nq][k],
+        dists [nq][k], qstats [nq][QSTAT_WORDS])."""
+        import torch
+        nq = Q.shape[0]
+        p, _ = self._params(k, c, beta, r_min, eps, "fp32", 1, None, None)
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        st = torch.empty((nq, QSTAT_WORDS), dtype=torch.int32, device=Q.device)
+        _check(lib().pdet_query_literal(self._h, c_void_p(Q.data_ptr()), nq, ctypes.byref(p),
+                                        c_void_p(ids.data_ptr()), c_void_p(dists.data_ptr()),
+                                        c_void_p(st.data_ptr()), _stream(stream)))
+        return ids, dists, st
+
+    def rc_ann(self, Q, r, c=1.5, beta=0.1, eps=0.0, stream=None):
+        """(r,c)-ANN query of Algorithm 4 (pdet_rc_ann): (ids [nq] (-1: none), dists [nq],
+        qstats [nq][QSTAT_WORDS])."""
+        import torch
+        nq = Q.shape[0]
+        ids = torch.empty(nq, dtype=torch.int64, device=Q.device)
+        dists = torch.empty(nq, dtype=torch.float32, device=Q.device)
+        st = torch.empty((nq, QSTAT_WORDS), dtype=torch.int32, device=Q.device)
+        _check(lib().pdet_rc_ann(self._h, c_void_p(Q.data_ptr()), nq, float(r), float(c),
+                                 float(beta), float(eps), c_void_p(ids.data_ptr()),
+                                 c_void_p(dists.data_ptr()), c_void_p(st.data_ptr()),
+                                 _stream(stream)))
+        return ids, dists, st
 
     def query_candidates(self, Q, cand_cap, k=10, c=1.5, beta=0.1, r_min=1.0, eps=0.0,
                          precision="fp32", rescore=4, k_per_query=None, c_per_query=None,
