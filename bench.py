@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "index build Mpts/s + QPS at recall@10>=0.9 (FP32 vs BF16/FP8 verify), 1 GPU"
 HBM_PEAK_GBS = 8000.0
-BETA_LADDER = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 5e-4, 2e-4, 1e-4, 5e-5, 2e-5, 1e-5)
+BETA_LADDER = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 7e-4, 5e-4, 3.5e-4, 2.5e-4, 1.8e-4,
+               1.3e-4, 1e-4, 7e-5, 5e-5, 3.5e-5, 2.5e-5, 1.8e-5, 1.3e-5, 1e-5)
 GEN_THREADS_N = 4_000_000     # from this size: data drawn in parallel chunks (same values)
 MAX_CAL_CANDIDATES = 2e5      # largest beta * n tried by the recall calibration
 POOL = 16                     # host worker processes (the GPU machine's CPU share)
@@ -137,24 +138,27 @@ def measure(w, args, primary, helper=None):
         log(f"[bench] FP64 brute-force ground truth for {nrec} queries ({time.time() - t0:.1f}s)")
 
     def calibrate(precision):
-        """(beta, r_min, rounds resolved, recall@10) at the smallest beta reaching 0.9."""
+        """(beta, r_min, rounds resolved, recall@10) at the smallest beta reaching 0.9. At
+        each beta (descending) the radius schedule autotuned for it and the one accepted at
+        the previous beta are both tried; the one with the higher recall is kept."""
         if args.no_recall:
             if args.beta is None or args.r_min is None:
                 raise SystemExit("--no-recall needs --beta and --r-min")
             return args.beta, args.r_min, args.rcap, None
 
-        def at(beta):
+        def at(beta, tuning=None):
             if args.r_min is not None:
-                idx.set_tuning(args.r_min, args.rcap)
-                t = dict(r_min=args.r_min, rounds_resolved=args.rcap)
-            else:
+                tuning = (args.r_min, args.rcap)
+            if tuning is None:
                 t = idx.autotune(Qp, k=w.k, c=w.c, beta=beta, precision=precision)
-            ids, _ = idx.query(Qr, k=w.k, c=w.c, beta=beta, r_min=t["r_min"],
+                tuning = (t["r_min"], t["rounds_resolved"])
+            idx.set_tuning(*tuning)
+            ids, _ = idx.query(Qr, k=w.k, c=w.c, beta=beta, r_min=tuning[0],
                                precision=precision, rescore=4)
             rec = recall_at(ids.cpu().numpy(), exact_ids)
-            log(f"[bench] {w.name} {precision} beta={beta} r_min={t['r_min']:.4g} "
-                f"rounds_resolved={t['rounds_resolved']} recall@10={rec:.4f}")
-            return beta, t["r_min"], t["rounds_resolved"], rec
+            log(f"[bench] {w.name} {precision} beta={beta} r_min={tuning[0]:.4g} "
+                f"rounds_resolved={tuning[1]} recall@10={rec:.4f}")
+            return beta, tuning[0], tuning[1], rec
 
         if args.beta is not None:
             return at(args.beta)
@@ -163,6 +167,10 @@ def measure(w, args, primary, helper=None):
             if beta * w.n > MAX_CAL_CANDIDATES and beta != BETA_LADDER[-1]:
                 continue   # a calibration batch at this beta would verify too many rows
             res = at(beta)
+            if chosen is not None and args.r_min is None and res[1] != chosen[1]:
+                alt = at(beta, (chosen[1], chosen[2]))
+                if alt[3] > res[3]:
+                    res = alt
             if res[3] >= 0.9:
                 chosen = res
             else:

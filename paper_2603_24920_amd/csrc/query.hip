@@ -1023,6 +1023,17 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
             }
             continue;
           }
+          if (nS == 0) {
+            // S is empty, so every point of this tree's leaves is new (a tree's leaves are
+            // disjoint): the leaf sizes are the new-point counts and the cut they select
+            // is the leaf where |S| reaches T
+            const unsigned long long cut = select_key(e0, e1, (uint32_t)T, true);
+            const uint32_t e_end = e0 + keep_upto(e0, e1, cut);
+            stop = 1;
+            leaves += e_end - e0;
+            nS += traverse(WALK_VERIFY, rho, e0, e_end, p0, uni(pre2[e_end]), 0, ce);
+            continue;
+          }
           // more leaves than one ordering pass takes: count new points per leaf over a
           // bounded prefix, then select the leaf by key
           uint32_t e1c = e1;

@@ -49,10 +49,28 @@ struct LeafOut {
   uint16_t* hidx_at;    // [L][n][KP]
 };
 
+// Nodes finished in LDS come in size classes (CLS_BELOW[c], CLS_CAP[c]], one list each.
+constexpr int NCLS = 4;
+constexpr int CLS_CAP[NCLS] = {256, 512, 1024, LDS_SEG_CAP};
+constexpr int CLS_BELOW[NCLS] = {0, 256, 512, 1024};
+
+__host__ __device__ inline int size_class(int count) {
+  return count <= 256 ? 0 : count <= 512 ? 1 : count <= 1024 ? 2 : 3;
+}
+
 struct Lists {
-  Seg* big_next; uint32_t* n_big_next; uint32_t* max_big_next;
-  Seg* mid; uint32_t* n_mid;
+  Seg* big_next; uint32_t* n_big_next; uint32_t* pts_big_next;   // and their total size
+  Seg* mid[NCLS]; uint32_t* n_mid;                              // n_mid[c]: class c
   Copy* copies; uint32_t* n_copies;   // leaves whose ids sit in buffer 1
+};
+
+// A global pass over the nodes larger than LDS_SEG_CAP gives each workgroup one unit: at
+// most SEG_CHUNK consecutive positions of one node (so the grid follows the points, not
+// the largest node).
+constexpr int SEG_CHUNK = 4096;
+struct Unit {
+  uint32_t seg;      // node index in the level's list
+  uint32_t first;    // first position within the node
 };
 
 __device__ inline uint32_t code_byte(const uint4& v, int j) {
@@ -64,6 +82,11 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// 1 in every byte of w that is not zero, 0 in the others.
+__device__ inline uint32_t nonzero_bytes(uint32_t w) {
+  return ((((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u) >> 7;
 }
 
 __device__ inline uint32_t lanes_below(uint64_t mask) {
@@ -92,10 +115,11 @@ __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, co
     emit_leaf(lo, n, s.tree, s.start, s.count, s.depth, s.prefix, K);
     if (s.buf == 1) li.copies[atomicAdd(li.n_copies, 1u)] = Copy{s.tree, s.start, s.count};
   } else if (s.count <= LDS_SEG_CAP) {
-    li.mid[atomicAdd(li.n_mid, 1u)] = s;
+    const int c = size_class(s.count);
+    li.mid[c][atomicAdd(&li.n_mid[c], 1u)] = s;
   } else {
     li.big_next[atomicAdd(li.n_big_next, 1u)] = s;
-    atomicMax(li.max_big_next, (uint32_t)s.count);
+    atomicAdd(li.pts_big_next, (uint32_t)s.count);
   }
 }
 
@@ -219,14 +243,32 @@ __global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, in
 }
 
 // ---- global passes over nodes larger than LDS_SEG_CAP (contiguous rows, no gathers)
-__global__ void seg_count(const Seg* segs, Bufs b, int64_t n, int K, int bits, uint32_t* cnt) {
-  const Seg s = segs[blockIdx.x];
+// The units of every listed node, in no particular order.
+__global__ __launch_bounds__(256) void seg_units(const Seg* segs, int nseg, Unit* units,
+                                                 uint32_t* n_units) {
+  __shared__ uint32_t sh[256 / 64 + 1];
+  __shared__ uint32_t base;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t m = (i < nseg) ? (uint32_t)((segs[i].count + SEG_CHUNK - 1) / SEG_CHUNK) : 0u;
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan<256>(m, sh, &tot);
+  if (threadIdx.x == 0) base = atomicAdd(n_units, tot);
+  __syncthreads();
+  for (uint32_t t = 0; t < m; ++t) units[base + ex + t] = Unit{(uint32_t)i, t * (uint32_t)SEG_CHUNK};
+}
+
+__global__ __launch_bounds__(256) void seg_count(const Seg* segs, const Unit* units,
+                                                 const uint32_t* n_units, Bufs b, int64_t n,
+                                                 int K, int bits, uint32_t* cnt) {
+  if (blockIdx.x >= *n_units) return;
+  const Unit u = units[blockIdx.x];
+  const Seg s = segs[u.seg];
   uint32_t local[KP];
 #pragma unroll
   for (int j = 0; j < KP; ++j) local[j] = 0;
   const uint4* rows = b.rows[s.buf] + (int64_t)s.tree * n + s.start;
-  for (int64_t p = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; p < s.count;
-       p += (int64_t)gridDim.y * blockDim.x) {
+  const int end = min(s.count, (int)u.first + SEG_CHUNK);
+  for (int p = (int)u.first + threadIdx.x; p < end; p += 256) {
     const uint4 v = rows[p];
 #pragma unroll
     for (int j = 0; j < KP; ++j)
@@ -235,7 +277,7 @@ __global__ void seg_count(const Seg* segs, Bufs b, int64_t n, int K, int bits, u
 #pragma unroll
   for (int j = 0; j < KP; ++j) {
     const uint32_t v = wave_sum(local[j]);
-    if ((threadIdx.x & 63) == 0 && v && j < K) atomicAdd(&cnt[(int64_t)blockIdx.x * KP + j], v);
+    if ((threadIdx.x & 63) == 0 && v && j < K) atomicAdd(&cnt[(int64_t)u.seg * KP + j], v);
   }
 }
 
@@ -271,21 +313,25 @@ __global__ void seg_choose(const Seg* segs, int nseg, const uint32_t* cnt, int K
 
 // Partition of each node's rows and ids into the other buffer, bit-0 child first. A
 // child that is a leaf needs no rows any more: only its ids are written.
-__global__ void seg_split(const Seg* segs, const int32_t* split, const uint8_t* leafs, Bufs b,
-                          int64_t n, int bits, uint32_t* cur0, uint32_t* cur1) {
-  const Seg s = segs[blockIdx.x];
-  const int j = split[blockIdx.x];
+__global__ __launch_bounds__(256) void seg_split(const Seg* segs, const Unit* units,
+                                                 const uint32_t* n_units, const int32_t* split,
+                                                 const uint8_t* leafs, Bufs b, int64_t n,
+                                                 int bits, uint32_t* cur0, uint32_t* cur1) {
+  if (blockIdx.x >= *n_units) return;
+  const Unit u = units[blockIdx.x];
+  const Seg s = segs[u.seg];
+  const int j = split[u.seg];
   const int sh = bits - 1 - s.depth[j];
-  const uint8_t lf = leafs[blockIdx.x];
+  const uint8_t lf = leafs[u.seg];
   const int64_t tb = (int64_t)s.tree * n;
   const uint4* rs = b.rows[s.buf] + tb + s.start;
   const int32_t* is = b.ids[s.buf] + tb + s.start;
   uint4* rd = b.rows[1 - s.buf] + tb;
   int32_t* id_d = b.ids[1 - s.buf] + tb;
-  for (int64_t b0 = (int64_t)blockIdx.y * blockDim.x; b0 < s.count;
-       b0 += (int64_t)gridDim.y * blockDim.x) {
-    const int64_t p = b0 + threadIdx.x;
-    const bool valid = p < s.count;
+  const int end = min(s.count, (int)u.first + SEG_CHUNK);
+  for (int b0 = (int)u.first; b0 < end; b0 += 256) {
+    const int p = b0 + threadIdx.x;
+    const bool valid = p < end;
     int32_t id = 0;
     uint4 row = make_uint4(0, 0, 0, 0);
     int bit = 0;
@@ -298,8 +344,8 @@ __global__ void seg_split(const Seg* segs, const int32_t* split, const uint8_t* 
     const uint64_t mo = __ballot(valid && bit == 1);
     uint32_t bz = 0, bo = 0;
     if ((threadIdx.x & 63) == 0) {
-      if (mz) bz = atomicAdd(&cur0[blockIdx.x], (uint32_t)__popcll(mz));
-      if (mo) bo = atomicAdd(&cur1[blockIdx.x], (uint32_t)__popcll(mo));
+      if (mz) bz = atomicAdd(&cur0[u.seg], (uint32_t)__popcll(mz));
+      if (mo) bo = atomicAdd(&cur1[u.seg], (uint32_t)__popcll(mo));
     }
     bz = __shfl(bz, 0);
     bo = __shfl(bo, 0);
@@ -363,6 +409,7 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
   __shared__ uint16_t ord[CAP];
   __shared__ uint16_t tmp[CAP];
   __shared__ SegL segs[2][MAXS];
+  __shared__ uint4 smask[MAXS];
   __shared__ uint32_t cnt[MAXS][KP];
   __shared__ uint32_t zstart[MAXS];
   __shared__ uint16_t c0s[MAXS];
@@ -404,36 +451,83 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
       }
       return (S[lo].start <= p && p < S[lo].start + S[lo].count) ? lo : -1;
     };
-    for (int e = threadIdx.x; e < nact * KP; e += NT) cnt[e / KP][e % KP] = 0;
-    __syncthreads();
-    // 1. next-bit counts per open node and dimension: per wave, one ballot per dimension
-    //    for the lanes of each node present in the wave
-    for (int base = 0; base < count; base += NT) {
-      const int p = base + threadIdx.x;
-      const int sg = (p < count) ? find(p) : -1;
-      uint32_t bitsv = 0;          // bit j: next bit of dimension j (unrefined dims only)
-      if (sg >= 0) {
-        const uint4 v = rows[ord[p]];
-#pragma unroll
-        for (int j = 0; j < KP; ++j) {
-          const int dj = S[sg].depth[j];
-          if (j < K && dj < bits) bitsv |= ((code_byte(v, j) >> (bits - 1 - dj)) & 1u) << j;
-        }
+    // open node holding position p0 and the first open node starting after p0
+    auto locate = [&](int p0, int& sg, int& snext) {
+      sg = (p0 < count) ? find(p0) : -1;
+      int lo2 = 0, hi2 = nact;
+      while (lo2 < hi2) {
+        const int md = (lo2 + hi2) >> 1;
+        if (S[md].start <= p0) lo2 = md + 1; else hi2 = md;
       }
-      uint64_t pending = __ballot(sg >= 0);
-      while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int s0 = __shfl(sg, leader);
-        const bool mine = sg == s0;
-        const uint64_t mm = __ballot(mine);
+      snext = lo2;
+    };
+    // 1. next-bit counts per open node and dimension. Byte j of a code row is dimension
+    //    j's code; a node's mask keeps the next unrefined bit of each of its dimensions, so
+    //    a masked row has at most one bit per byte. A thread sums its PER consecutive
+    //    positions as byte counters, one per dimension; each wave then adds up the counters
+    //    of its lanes in one node (as 16-bit fields) and adds them to the node's counts.
+    if ((int)threadIdx.x < nact) {
+      const SegL& g = S[threadIdx.x];
+      uint32_t m[4] = {0u, 0u, 0u, 0u};
+      for (int j = 0; j < K; ++j)
+        if (g.depth[j] < bits) m[j >> 2] |= 1u << (8 * (j & 3) + bits - 1 - g.depth[j]);
+      smask[threadIdx.x] = make_uint4(m[0], m[1], m[2], m[3]);
 #pragma unroll
-        for (int j = 0; j < KP; ++j) {
-          if (j < K) {
-            const uint32_t c = (uint32_t)__popcll(__ballot(mine && ((bitsv >> j) & 1u)));
-            if (lane == leader && c) atomicAdd(&cnt[s0][j], c);
+      for (int j = 0; j < KP; ++j) cnt[threadIdx.x][j] = 0;
+    }
+    __syncthreads();
+    {
+      int sg, snext;
+      locate(threadIdx.x * PER, sg, snext);
+      uint32_t acc[4] = {0u, 0u, 0u, 0u};
+      int run = -1;   // node whose counts acc holds
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int p = threadIdx.x * PER + e;
+        if (p < count) {
+          if (snext < nact && S[snext].start == p) { sg = snext; ++snext; }
+          if (sg >= 0 && p >= S[sg].start + S[sg].count) sg = -1;
+          if (sg != run) {
+            // a node boundary inside the thread's positions: the finished run's counts go
+            // to its node directly
+            if (run >= 0)
+              for (int j = 0; j < K; ++j) {
+                const uint32_t c = (acc[j >> 2] >> (8 * (j & 3))) & 255u;
+                if (c) atomicAdd(&cnt[run][j], c);
+              }
+            acc[0] = acc[1] = acc[2] = acc[3] = 0u;
+            run = sg;
+          }
+          if (sg >= 0) {
+            const uint4 v = rows[ord[p]];
+            const uint4 M = smask[sg];
+            acc[0] += nonzero_bytes(v.x & M.x);
+            acc[1] += nonzero_bytes(v.y & M.y);
+            acc[2] += nonzero_bytes(v.z & M.z);
+            acc[3] += nonzero_bytes(v.w & M.w);
           }
         }
-        pending &= ~mm;
+      }
+      uint64_t pending = __ballot(run >= 0);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int s0 = __shfl(run, leader);
+        const bool mine = run == s0;
+        // bytes 0 and 2 (even dimensions), bytes 1 and 3 (odd) as 16-bit fields
+        uint32_t w[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          w[2 * i] = mine ? (acc[i] & 0x00ff00ffu) : 0u;
+          w[2 * i + 1] = mine ? ((acc[i] >> 8) & 0x00ff00ffu) : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = wave_sum(w[i]);
+        if (lane == leader)
+          for (int j = 0; j < K; ++j) {
+            const uint32_t c = (w[2 * (j >> 2) + (j & 1)] >> (16 * ((j >> 1) & 1))) & 0xffffu;
+            if (c) atomicAdd(&cnt[s0][j], c);
+          }
+        pending &= ~__ballot(mine);
       }
     }
     __syncthreads();
@@ -454,16 +548,8 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
     //    over consecutive position runs gives each point its rank among its node's zeros
     const int p0 = threadIdx.x * PER;
     uint32_t zmask = 0;
-    int sg = (p0 < count) ? find(p0) : -1;
-    int snext = -1;                                   // first open node starting after p0
-    {
-      int lo2 = 0, hi2 = nact;                        // first start > p0
-      while (lo2 < hi2) {
-        const int md = (lo2 + hi2) >> 1;
-        if (S[md].start <= p0) lo2 = md + 1; else hi2 = md;
-      }
-      snext = lo2;
-    }
+    int sg, snext;
+    locate(p0, sg, snext);
     int segof[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
@@ -834,31 +920,37 @@ void build_trees(Index& ix, hipStream_t s) {
   PDET_HIP(hipMemsetAsync(cnt_at.ptr(), 0, cnt_at.bytes(), s));
   LeafOut lo{cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>()};
 
-  // node lists; counters: [0] n_big_a [1] max_big_a [2] n_big_b [3] max_big_b [4] n_mid
-  // [5] n_copies
-  const int64_t mid_cap = (int64_t)L * (n / (ix.max_leaf + 1) + 1);
+  // node lists; counters: [0] n_big_a [1] pts_big_a [2] n_big_b [3] pts_big_b
+  // [4..7] n_mid per size class [8] n_copies [9] n_units. A class-c node has more than
+  // max(CLS_BELOW[c], max_leaf) points, which bounds its list.
+  int64_t mid_off[NCLS + 1] = {0};
+  for (int cl = 0; cl < NCLS; ++cl)
+    mid_off[cl + 1] = mid_off[cl] +
+                      (int64_t)L * (n / (std::max(CLS_BELOW[cl], ix.max_leaf) + 1) + 1);
   const int64_t big_cap = (int64_t)L * (n / (LDS_SEG_CAP + 1) + 1);
-  PooledBuf mid((size_t)mid_cap * sizeof(Seg));
+  PooledBuf mid((size_t)mid_off[NCLS] * sizeof(Seg));
   PooledBuf bigA((size_t)big_cap * sizeof(Seg)), bigB((size_t)big_cap * sizeof(Seg));
   PooledBuf copies((size_t)2 * big_cap * sizeof(Copy));
-  PooledBuf ctr(8 * 4);
+  PooledBuf ctr(16 * 4);
   PDET_HIP(hipMemsetAsync(ctr.ptr(), 0, ctr.bytes(), s));
   uint32_t* c = ctr.as<uint32_t>();
-  Lists li{bigA.as<Seg>(), c + 0, c + 1, mid.as<Seg>(), c + 4, copies.as<Copy>(), c + 5};
+  Lists li{bigA.as<Seg>(), c + 0, c + 1, {}, c + 4, copies.as<Copy>(), c + 8};
+  for (int cl = 0; cl < NCLS; ++cl) li.mid[cl] = mid.as<Seg>() + mid_off[cl];
   hipLaunchKernelGGL(fl_segments, dim3(cdiv(L * NK, 256)), dim3(256), 0, s, hist.as<uint32_t>(),
                      off.as<uint32_t>(), L, K, bits, ix.max_leaf, n, lo, li);
   PDET_HIP(hipGetLastError());
 
   uint32_t* hc = readback_words();
-  PDET_HIP(hipMemcpyAsync(hc, c, 8 * 4, hipMemcpyDeviceToHost, s));
+  PDET_HIP(hipMemcpyAsync(hc, c, 16 * 4, hipMemcpyDeviceToHost, s));
   PDET_HIP(hipStreamSynchronize(s));
-  uint32_t nbig = hc[0], maxbig = hc[1];
+  uint32_t nbig = hc[0], ptsbig = hc[1];
   Seg* cur_big = bigA.as<Seg>();
   Seg* nxt_big = bigB.as<Seg>();
   int cur_slot = 0;   // counters of the current list at c[2*cur_slot]
   DevBuf rows1;
-  PooledBuf ids1, cntbuf, split, c0, cur0, cur1, leafs;
+  PooledBuf ids1, cntbuf, split, c0, cur0, cur1, leafs, units;
   if (nbig) {
+    units.alloc(((size_t)L * n / SEG_CHUNK + (size_t)big_cap) * sizeof(Unit));
     rows1.alloc((size_t)L * n * KP);
     ids1.alloc((size_t)L * n * 4);
     bf.rows[1] = rows1.as<uint4>();
@@ -872,57 +964,68 @@ void build_trees(Index& ix, hipStream_t s) {
     PDET_HIP(hipMemsetAsync(cntbuf.ptr(), 0, (size_t)nbig * KP * 4, s));
     const int nxt_slot = 1 - cur_slot;
     PDET_HIP(hipMemsetAsync(c + 2 * nxt_slot, 0, 8, s));
-    PDET_HIP(hipMemsetAsync(c + 5, 0, 4, s));
-    const unsigned ch = std::max(1u, std::min(1024u, cdiv(maxbig, 256 * 16)));
-    hipLaunchKernelGGL(seg_count, dim3(nbig, ch), dim3(256), 0, s, cur_big, bf, n, K, bits,
-                       cntbuf.as<uint32_t>());
+    PDET_HIP(hipMemsetAsync(c + 8, 0, 8, s));   // copies, units
+    // every node gives at most count / SEG_CHUNK + 1 units
+    const unsigned nu = (unsigned)(ptsbig / SEG_CHUNK + nbig);
+    hipLaunchKernelGGL(seg_units, dim3(cdiv(nbig, 256)), dim3(256), 0, s, cur_big, (int)nbig,
+                       units.as<Unit>(), c + 9);
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(seg_count, dim3(nu), dim3(256), 0, s, cur_big, units.as<Unit>(), c + 9, bf,
+                       n, K, bits, cntbuf.as<uint32_t>());
     PDET_HIP(hipGetLastError());
     hipLaunchKernelGGL(seg_choose, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
                        cntbuf.as<uint32_t>(), K, bits, ix.max_leaf, split.as<int32_t>(),
                        c0.as<uint32_t>(), cur0.as<uint32_t>(), cur1.as<uint32_t>(),
                        leafs.as<uint8_t>());
     PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL(seg_split, dim3(nbig, ch), dim3(256), 0, s, cur_big, split.as<int32_t>(),
-                       leafs.as<uint8_t>(), bf, n, bits, cur0.as<uint32_t>(), cur1.as<uint32_t>());
+    hipLaunchKernelGGL(seg_split, dim3(nu), dim3(256), 0, s, cur_big, units.as<Unit>(), c + 9,
+                       split.as<int32_t>(), leafs.as<uint8_t>(), bf, n, bits,
+                       cur0.as<uint32_t>(), cur1.as<uint32_t>());
     PDET_HIP(hipGetLastError());
-    Lists ln{nxt_big, c + 2 * nxt_slot, c + 2 * nxt_slot + 1, mid.as<Seg>(), c + 4,
-             copies.as<Copy>(), c + 5};
+    Lists ln = li;
+    ln.big_next = nxt_big;
+    ln.n_big_next = c + 2 * nxt_slot;
+    ln.pts_big_next = c + 2 * nxt_slot + 1;
     hipLaunchKernelGGL(seg_children, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
                        split.as<int32_t>(), c0.as<uint32_t>(), K, bits, ix.max_leaf, n, lo, ln);
     PDET_HIP(hipGetLastError());
-    PDET_HIP(hipMemcpyAsync(hc, c, 8 * 4, hipMemcpyDeviceToHost, s));
+    PDET_HIP(hipMemcpyAsync(hc, c, 16 * 4, hipMemcpyDeviceToHost, s));
     PDET_HIP(hipStreamSynchronize(s));
-    if (hc[5]) {
-      hipLaunchKernelGGL(seg_copy, dim3(hc[5]), dim3(256), 0, s, copies.as<Copy>(), bf, n);
+    if (hc[8]) {
+      hipLaunchKernelGGL(seg_copy, dim3(hc[8]), dim3(256), 0, s, copies.as<Copy>(), bf, n);
       PDET_HIP(hipGetLastError());
     }
     nbig = hc[2 * nxt_slot];
-    maxbig = hc[2 * nxt_slot + 1];
+    ptsbig = hc[2 * nxt_slot + 1];
     std::swap(cur_big, nxt_big);
     cur_slot = nxt_slot;
   }
-  const uint32_t nmid = hc[4];
-  if (nmid) {
-    // size classes (below, CAP]: each block of a launch finishes one node of its class, in
-    // the frontier form when the class holds at most FR_MAXS open nodes
-    auto finish = [&](auto cap_c, auto nt_c, int below) {
+  {
+    // one launch per size class, one node per block, in the frontier form when the class
+    // holds at most FR_MAXS open nodes
+    auto finish = [&](auto cap_c, auto nt_c, int cl) {
       constexpr int CAP = decltype(cap_c)::value, NT = decltype(nt_c)::value;
+      static_assert(CAP <= LDS_SEG_CAP, "class");
+      const uint32_t nm = hc[4 + cl];
+      if (!nm) return;
+      const Seg* list = mid.as<Seg>() + mid_off[cl];
+      const int below = CLS_BELOW[cl];
       const int open_max = CAP / (ix.max_leaf + 1);
       if (open_max <= 16)
-        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT, 16>), dim3(nmid), dim3(NT), 0, s,
-                           mid.as<Seg>(), bf, n, K, bits, ix.max_leaf, below, lo);
+        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT, 16>), dim3(nm), dim3(NT), 0, s, list, bf,
+                           n, K, bits, ix.max_leaf, below, lo);
       else if (open_max <= FR_MAXS)
-        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT, FR_MAXS>), dim3(nmid), dim3(NT), 0, s,
-                           mid.as<Seg>(), bf, n, K, bits, ix.max_leaf, below, lo);
-      else
-        hipLaunchKernelGGL((seg_lds_dfs<CAP, NT>), dim3(nmid), dim3(NT), 0, s, mid.as<Seg>(),
+        hipLaunchKernelGGL((seg_lds_frontier<CAP, NT, FR_MAXS>), dim3(nm), dim3(NT), 0, s, list,
                            bf, n, K, bits, ix.max_leaf, below, lo);
+      else
+        hipLaunchKernelGGL((seg_lds_dfs<CAP, NT>), dim3(nm), dim3(NT), 0, s, list, bf, n, K,
+                           bits, ix.max_leaf, below, lo);
       PDET_HIP(hipGetLastError());
     };
     finish(std::integral_constant<int, 256>{}, std::integral_constant<int, 64>{}, 0);
-    finish(std::integral_constant<int, 512>{}, std::integral_constant<int, 128>{}, 256);
-    finish(std::integral_constant<int, 1024>{}, std::integral_constant<int, 256>{}, 512);
-    finish(std::integral_constant<int, LDS_SEG_CAP>{}, std::integral_constant<int, 256>{}, 1024);
+    finish(std::integral_constant<int, 512>{}, std::integral_constant<int, 128>{}, 1);
+    finish(std::integral_constant<int, 1024>{}, std::integral_constant<int, 256>{}, 2);
+    finish(std::integral_constant<int, LDS_SEG_CAP>{}, std::integral_constant<int, 512>{}, 3);
   }
 
   // number the leaves in position (= depth-first) order
