@@ -246,8 +246,10 @@ pdet_status pdet_set_list_cap(pdet_index* idx, int64_t cap);
  * therefore kept, up to 60% of each device's memory, and reused for a later allocation of
  * exactly the same size on the same device. Releasing a block waits for the device to be
  * idle, as hipFree does. A failed allocation returns every cached block to the driver and
- * tries once more. pdet_release_cache returns every cached block now (e.g. before handing
- * the memory to another library); it must not run concurrently with other calls. */
+ * tries once more. Build temporaries (up to 2 GiB in all) are kept for the next build of
+ * the same size. pdet_release_cache returns every cached block and kept temporary now (e.g.
+ * before handing the memory to another library); it must not run concurrently with other
+ * calls. */
 void pdet_release_cache(void);
 
 /* Description of a built index. */

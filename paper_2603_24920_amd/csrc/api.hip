@@ -252,6 +252,14 @@ class ScratchPool {
     held_ += d.bytes;
     free_.push_back(std::move(d));
   }
+  void drain() {
+    std::vector<DevBuf> out;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      out.swap(free_);
+      held_ = 0;
+    }
+  }
  private:
   static constexpr size_t kPoolCap = size_t(2) << 30;
   std::mutex mu_;
@@ -446,7 +454,10 @@ pdet_status pdet_set_list_cap(pdet_index* idx, int64_t cap) {
   });
 }
 
-void pdet_release_cache(void) { cache_flush(); }
+void pdet_release_cache(void) {
+  scratch_pool().drain();   // its buffers go back to the block cache, which is then emptied
+  cache_flush();
+}
 
 void pdet_set_timing(int32_t on) { timer().on = on != 0; }
 

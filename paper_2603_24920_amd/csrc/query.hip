@@ -5,13 +5,15 @@
 // Kernels:
 //  q_setup  per query: radius ladder r_rho = r_min*c^rho, thresholds (eps*r_rho)^2
 //           and c*r_rho, computed with the same double operations as the definition.
-//  q_rho    batched over (leaf block, tree, query tile): the first round whose threshold
+//  q_rho    batched over (leaf block, tree, query tiles): the first round whose threshold
 //           admits each leaf (its squared lower bound to q' <= (eps r_rho)^2), for rounds
 //           up to rcap. Groups of 16 consecutive leaves are tested first with their union
 //           box (a lower bound of every member's bound, as a subtree prunes in the range
 //           query). Only leaves admitted by round rcap are written, as (round, leaf)
 //           entries of a per-query, per-tree list; later rounds are found by q_main if a
-//           query ever reaches them.
+//           query ever reaches them. Two forms: one query tile per workgroup (q_rho_tile),
+//           or runs of tiles per workgroup in two passes (q_rho_runs) when the chunk has
+//           enough tiles and leaf blocks to fill the device that way.
 //  q_main   one workgroup per query, one pass per round over the admitted leaves of all
 //           trees (the list entries of that round): an admitted point is new iff none of
 //           its leaves in the other trees was admitted earlier in the (round, tree) order
@@ -39,6 +41,8 @@ constexpr int NXCD = 8;          // accelerator dies; workgroup i runs on die i 
 constexpr int NRHO = NRHO_TABLE; // threshold table length (255 rounds + sentinel)
 constexpr int GL = 16;           // leaves per pruning group
 constexpr int RCAP_MAX = 8;      // most rounds q_rho resolves (the index's rcap <= this)
+constexpr int QR_TILES_MAX = 64; // query tiles one q_rho workgroup runs through
+constexpr int QR_TARGET_WG = 32768;  // q_rho workgroups a chunk aims for
 constexpr int RWIN = 3;          // rounds resolved per refinement step inside q_main
 constexpr int GCH = 2048;        // groups per refinement chunk (LDS bitmap of GCH bits)
 constexpr int TREE_SHIFT = 28;   // admitted-leaf entries pack (tree << 28) | leaf
@@ -74,6 +78,7 @@ struct QArgs {
   int64_t ng[PDET_MAX_L];
   int64_t nlpad;
   int lb_per_die;            // q_rho leaf blocks (256 leaves) of a tree that each die takes
+  int qr_tiles;              // query tiles per q_rho workgroup
   const float* Q;
   const float* qp;           // [nq][L*K]
   const int32_t* qk;         // per-query k, T, offsets and c
@@ -208,8 +213,10 @@ __device__ inline float leaf_lb2(const float* box, int64_t nl, int64_t leaf, con
 }
 
 // KT: the projection width K when it is fixed at compile time (16, the usual case), else 0.
+// One workgroup per block of 256 leaves of one tree and one query tile (taken when runs of
+// tiles would leave too few workgroups to fill the device).
 template <int KT>
-__global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
+__global__ __launch_bounds__(QR_THREADS) void q_rho_tile(QArgs a) {
   const int K = KT ? KT : a.K;
   // one padding word per query row: the 16 queries a wave tests at once read 16 banks
   __shared__ float sq[QT][PDET_MAX_K + 1];
@@ -302,6 +309,161 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho(QArgs a) {
         const int64_t at = (int64_t)slot * a.admcap + a.nlo[tree] + pos;
         a.adm_leaf[at] = ((uint32_t)c << LEAF_BITS) | (uint32_t)leaf;
         a.adm_lb[at] = acc;
+      }
+    }
+  }
+}
+
+// One workgroup per block of 256 leaves (16 groups) of one tree and run of a.qr_tiles query
+// tiles (the host sizes runs so that the grid still fills the device), in two passes over
+// them. Pass 1 holds each lane's group box in registers and tests it against every query,
+// keeping the open-query bits of each group and tile in LDS. Pass 2 holds the lane's leaf
+// box in the same registers and bounds the leaf for the queries that opened its group, on
+// the tiles where some group of the block is open. A wave takes the list positions for one
+// query with one atomic.
+template <int KT>
+__global__ __launch_bounds__(QR_THREADS) void q_rho_runs(QArgs a) {
+  const int K = KT ? KT : a.K;
+  constexpr int NGB = QR_THREADS / GL;   // groups per leaf block
+  static_assert(64 % GL == 0 && 64 / GL == 4 && QR_THREADS % 64 == 0, "a wave holds 4 groups");
+  // one padding word per query row: the 16 queries a wave tests at once read 16 banks
+  __shared__ float sq[2][QT][PDET_MAX_K + 1];
+  __shared__ float st[2][QT][RCAP_MAX + 1];
+  __shared__ uint64_t gmask[QR_TILES_MAX][NGB];   // pass 1: open queries per tile and group
+  __shared__ uint8_t open_tiles[QR_TILES_MAX];    // tiles where some group is open, in order
+  __shared__ uint32_t n_open;
+  // Grid (NXCD * lb_per_die, L, runs of a.qr_tiles tiles): blockIdx.x % NXCD is the die a
+  // workgroup runs on. Each die takes a fixed share of every tree's leaf blocks, which keeps
+  // its share of the box tables in its own L2.
+  const int die = blockIdx.x % NXCD;
+  const int tree = blockIdx.y;
+  const int64_t nl = a.nl[tree], ng = a.ng[tree];
+  const int64_t lb = (int64_t)die * a.lb_per_die + blockIdx.x / NXCD;
+  if (lb * QR_THREADS >= nl) return;
+  const int rcap = a.rcap;
+  const int64_t leaf = lb * QR_THREADS + threadIdx.x;
+  const int gl = threadIdx.x / GL;
+  const int64_t g = lb * NGB + gl;
+  const int sl = threadIdx.x & 15;
+  const int t0 = blockIdx.z * a.qr_tiles;
+  const int ntiles = std::min((a.nslots + QT - 1) / QT - t0, a.qr_tiles);
+  if (threadIdx.x == 0) n_open = 0;
+  constexpr int NST = (QT * (RCAP_MAX + 1) + QR_THREADS - 1) / QR_THREADS;
+  constexpr int NSQ = QT * PDET_MAX_K / QR_THREADS;   // rows of PDET_MAX_K, K used
+  float stv[NST], sqv[NSQ];
+  // thresholds and projected queries of a tile into registers (every load issued first),
+  // then into LDS buffer b
+  auto fetch = [&](int slot0) {
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int e = threadIdx.x + u * QR_THREADS;
+      const int qi = e / (RCAP_MAX + 1), r = e % (RCAP_MAX + 1);
+      stv[u] = (e < QT * (RCAP_MAX + 1) && slot0 + qi < a.nslots)
+                   ? a.t2[(int64_t)(slot0 + qi) * NRHO + r] : INFINITY;
+    }
+#pragma unroll
+    for (int u = 0; u < NSQ; ++u) {
+      const int e = threadIdx.x + u * QR_THREADS;
+      const int qi = e / PDET_MAX_K, j = e % PDET_MAX_K;
+      const bool ok = j < K && slot0 + qi < a.nslots;
+      sqv[u] = !ok ? 0.0f
+               : !a.qmap ? a.qp[(a.q0 + slot0 + qi) * (int64_t)(a.L * K) + tree * K + j]
+                         : a.qp[slot_query(a, slot0 + qi) * (int64_t)(a.L * K) + tree * K + j];
+    }
+  };
+  auto stage = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int e = threadIdx.x + u * QR_THREADS;
+      if (e < QT * (RCAP_MAX + 1)) st[b][e / (RCAP_MAX + 1)][e % (RCAP_MAX + 1)] = stv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NSQ; ++u) {
+      const int e = threadIdx.x + u * QR_THREADS;
+      sq[b][e / PDET_MAX_K][e % PDET_MAX_K] = sqv[u];
+    }
+  };
+  float lo[PDET_MAX_K], hi[PDET_MAX_K];
+  load_box(a.gbox[tree], ng, (uint32_t)std::min(g, ng - 1), K, lo, hi);   // tested if g < ng
+  fetch(t0 * QT);
+  // pass 1: group tests (double buffered: past a tile's barrier, a thread has finished
+  // reading the other buffer)
+  for (int tile = 0; tile < ntiles; ++tile) {
+    const int b = tile & 1, slot0 = (t0 + tile) * QT;
+    stage(b);
+    __syncthreads();
+    if (tile + 1 < ntiles) fetch(slot0 + QT);
+    // lane sl of the 16 lanes sharing group gl tests that group against query 16*sub + sl
+    uint64_t open_mask = 0;
+#pragma unroll
+    for (int sub = 0; sub < QT / 16; ++sub) {
+      const int qi = sub * 16 + sl;
+      bool open = false;
+      if (g < ng && slot0 + qi < a.nslots)
+        open = box_lb2(lo, hi, sq[b][qi], K) <= st[b][qi][rcap] * (1.0f + BAND_REL);
+      const uint64_t mask = __ballot(open);
+      open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
+    }
+    if (sl == 0) gmask[tile][gl] = open_mask;
+    // the tiles where some group of the block is open, listed in order
+    const uint32_t any = __syncthreads_or(open_mask != 0);
+    if (threadIdx.x == 0 && any) open_tiles[n_open++] = (uint8_t)tile;
+  }
+  __syncthreads();
+  // pass 2: leaf bounds for the queries that opened the leaf's group, over the open tiles
+  // (the next one's queries and thresholds load while the current one is tested; a run
+  // that is one tile long, the chunk's last, still holds it in buffer 0)
+  const int nop = (int)n_open;
+  if (nop == 0) return;
+  if (leaf < nl) load_box(a.box[tree], nl, (uint32_t)leaf, K, lo, hi);
+  const bool resident = ntiles == 1;
+  if (!resident) fetch((t0 + open_tiles[0]) * QT);
+  for (int oi = 0; oi < nop; ++oi) {
+    const int tile = open_tiles[oi], b = resident ? 0 : (oi & 1);
+    const int slot0 = (t0 + tile) * QT;
+    if (!resident) {
+      stage(b);
+      __syncthreads();
+      if (oi + 1 < nop) fetch((t0 + open_tiles[oi + 1]) * QT);
+    }
+    const uint64_t open_mask = (leaf < nl) ? gmask[tile][gl] : 0ull;
+    // the queries that open one of the wave's 4 groups, one at a time for the whole wave
+    // (the same sequence in every lane: the ballot below counts lanes of one query)
+    const int wg0 = (threadIdx.x >> 6) * (64 / GL);
+    const uint64_t wave_open =
+        gmask[tile][wg0] | gmask[tile][wg0 + 1] | gmask[tile][wg0 + 2] | gmask[tile][wg0 + 3];
+    for (uint64_t mq = wave_open; mq; mq &= mq - 1) {
+      const int qi = __ffsll((unsigned long long)mq) - 1;   // open only for slots < nslots
+      const int slot = slot0 + qi;
+      bool adm = false;
+      int c = 0;   // #thresholds < lb2 among rounds 0..rcap: the leaf's first round if <= rcap
+      float acc = 0.0f;
+      if ((open_mask >> qi) & 1u) {
+        acc = box_lb2(lo, hi, sq[b][qi], K);
+#pragma unroll
+        for (int rr = 0; rr <= RCAP_MAX; ++rr) c += (rr <= rcap && st[b][qi][rr] < acc) ? 1 : 0;
+        // a near tie can only be with the thresholds on either side of the bound
+#pragma unroll
+        for (int rr = c - 1; rr <= c; ++rr)
+          if (rr >= 0 && rr <= rcap && fabsf(acc - st[b][qi][rr]) <= BAND_REL * st[b][qi][rr])
+            atomicAdd(&a.bandc[(int64_t)slot * NRHO + rr], 1u);
+        adm = c <= rcap;
+      }
+      const uint64_t am = __ballot(adm);
+      if (!am) continue;
+      const int leader = __ffsll((unsigned long long)am) - 1;
+      uint32_t base = 0;
+      if ((threadIdx.x & 63) == leader)
+        base = atomicAdd(&a.lcnt[(int64_t)slot * PDET_MAX_L + tree], (uint32_t)__popcll(am));
+      base = __shfl(base, leader);
+      if (adm) {
+        const uint32_t pos = base + (uint32_t)__popcll(am & ((1ull << (threadIdx.x & 63)) - 1ull));
+        // past the region's capacity only the count grows: q_main sees the overflow
+        if (pos < a.lcap[tree]) {
+          const int64_t at = (int64_t)slot * a.admcap + a.nlo[tree] + pos;
+          a.adm_leaf[at] = ((uint32_t)c << LEAF_BITS) | (uint32_t)leaf;
+          a.adm_lb[at] = acc;
+        }
       }
     }
   }
@@ -1498,12 +1660,26 @@ void launch_chunks(const Index& ix, const QueryConfig& qc, QArgs a, int64_t nq, 
       Span sp(s, timed ? &tm.query_rho_ms : nullptr);
       hipLaunchKernelGGL(q_setup, dim3(cdiv(a.nslots, 64)), dim3(64), 0, s, a);
       PDET_HIP(hipGetLastError());
-      const dim3 rgrid((uint32_t)(NXCD * cdiv(a.nslots, QT)), (uint32_t)a.lb_per_die,
-                       (uint32_t)ix.L);
-      if (ix.K == 16)
-        hipLaunchKernelGGL(q_rho<16>, rgrid, dim3(QR_THREADS), 0, s, a);
-      else
-        hipLaunchKernelGGL(q_rho<0>, rgrid, dim3(QR_THREADS), 0, s, a);
+      // runs of query tiles per workgroup: long enough to amortise the block's group boxes,
+      // short enough that the chunk still gives about QR_TARGET_WG workgroups
+      const int64_t ntile = cdiv(a.nslots, QT);
+      const int64_t nblk = (int64_t)NXCD * a.lb_per_die * ix.L;
+      a.qr_tiles = (int)std::max<int64_t>(
+          1, std::min<int64_t>(QR_TILES_MAX, ntile * nblk / QR_TARGET_WG));
+      if (a.qr_tiles == 1) {
+        const dim3 grid((uint32_t)(NXCD * ntile), (uint32_t)a.lb_per_die, (uint32_t)ix.L);
+        if (ix.K == 16)
+          hipLaunchKernelGGL(q_rho_tile<16>, grid, dim3(QR_THREADS), 0, s, a);
+        else
+          hipLaunchKernelGGL(q_rho_tile<0>, grid, dim3(QR_THREADS), 0, s, a);
+      } else {
+        const dim3 grid((uint32_t)(NXCD * a.lb_per_die), (uint32_t)ix.L,
+                        (uint32_t)cdiv(ntile, a.qr_tiles));
+        if (ix.K == 16)
+          hipLaunchKernelGGL(q_rho_runs<16>, grid, dim3(QR_THREADS), 0, s, a);
+        else
+          hipLaunchKernelGGL(q_rho_runs<0>, grid, dim3(QR_THREADS), 0, s, a);
+      }
       PDET_HIP(hipGetLastError());
       sp.finish();
     }

@@ -81,6 +81,21 @@ def test_full_batch_sampled_queries_fp32(full):
     np.testing.assert_allclose(dists[::97], exact, rtol=1e-6)
 
 
+def test_full_batch_order_does_not_change_results(full):
+    """Every query of the batch gives the same candidate set, stop rule, rounds, leaves and
+    ids when the batch runs in reverse order, so that each query shares its bound tiles and
+    waves with other queries (a query's search must not depend on its neighbours)."""
+    w, cs, Q, Qd, t, sel = full
+    kw = dict(k=w.k, c=w.c, beta=BETA, r_min=t["r_min"], eps=cs.eps, stats=True)
+    ids, _, st = cs.idx.query(Qd, **kw)
+    rids, _, rst = cs.idx.query(torch.flip(Qd, [0]).contiguous(), **kw)
+    ids, st = ids.cpu().numpy(), st.cpu().numpy()
+    rids, rst = rids.cpu().numpy()[::-1], rst.cpu().numpy()[::-1]
+    words = [pdet.QSTAT[f] for f in ("rounds", "ncand", "stop", "leaves", "hsum", "hmix")]
+    bad = np.nonzero((st[:, words] != rst[:, words]).any(axis=1) | (ids != rids).any(axis=1))[0]
+    assert len(bad) == 0, (len(bad), bad[:10].tolist())
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_full_batch_low_precision_recall(full, prec):
     w, cs, Q, Qd, t, sel = full
