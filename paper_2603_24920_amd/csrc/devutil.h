@@ -82,9 +82,11 @@ __device__ inline double group_sum(double x) {
   return x;
 }
 
+// Set bits of `mask` in the lanes below the calling one (v_mbcnt: no per-lane 64-bit
+// mask to keep in registers).
 __device__ inline uint32_t lanes_below_mask(uint64_t mask) {
-  const int lane = threadIdx.x & 63;
-  return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 }  // namespace pdet

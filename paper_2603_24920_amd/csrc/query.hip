@@ -457,7 +457,7 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_runs(QArgs a) {
         base = atomicAdd(&a.lcnt[(int64_t)slot * PDET_MAX_L + tree], (uint32_t)__popcll(am));
       base = __shfl(base, leader);
       if (adm) {
-        const uint32_t pos = base + (uint32_t)__popcll(am & ((1ull << (threadIdx.x & 63)) - 1ull));
+        const uint32_t pos = base + lanes_below_mask(am);
         // past the region's capacity only the count grows: q_main sees the overflow
         if (pos < a.lcap[tree]) {
           const int64_t at = (int64_t)slot * a.admcap + a.nlo[tree] + pos;
@@ -504,29 +504,30 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
       const int n4 = a.d >> 2;
       constexpr int NCH = NCH32;
       for (int base = 0; base < n4; base += NCH * lpc) {
+        // Every load is issued, unconditionally, before any is used (a lane without a row
+        // or past the row's end reads a valid address and discards it): loads under a
+        // branch would each wait for the one before.
         float4 buf[NR][NCH];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const float4* x4 = reinterpret_cast<const float4*>(a.X + (int64_t)id[r] * a.d);
 #pragma unroll
-          for (int u = 0; u < NCH; ++u) {
-            const int c = base + lg + u * lpc;
-            if (valid[r] && c < n4) buf[r][u] = x4[c];
-          }
+          for (int u = 0; u < NCH; ++u) buf[r][u] = x4[min(base + lg + u * lpc, n4 - 1)];
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
 #pragma unroll
           for (int u = 0; u < NCH; ++u) {
-            const int c = base + lg + u * lpc;
-            if (valid[r] && c < n4) {
-              const float4 x = buf[r][u];
-              const double2 qa = q2[2 * c], qb = q2[2 * c + 1];
-              const double d0 = (double)x.x - qa.x, d1 = (double)x.y - qa.y;
-              const double d2 = (double)x.z - qb.x, d3 = (double)x.w - qb.y;
-              accd[r] = fma(d0, d0, accd[r]); accd[r] = fma(d1, d1, accd[r]);
-              accd[r] = fma(d2, d2, accd[r]); accd[r] = fma(d3, d3, accd[r]);
-            }
+            // no branch around the arithmetic either (one would let the compiler move the
+            // load into it): a discarded row contributes zeros
+            const int c = min(base + lg + u * lpc, n4 - 1);
+            const bool ok = valid[r] && base + lg + u * lpc < n4;
+            const float4 x = buf[r][u];
+            const double2 qa = q2[2 * c], qb = q2[2 * c + 1];
+            const double d0 = ok ? (double)x.x - qa.x : 0.0, d1 = ok ? (double)x.y - qa.y : 0.0;
+            const double d2 = ok ? (double)x.z - qb.x : 0.0, d3 = ok ? (double)x.w - qb.y : 0.0;
+            accd[r] = fma(d0, d0, accd[r]); accd[r] = fma(d1, d1, accd[r]);
+            accd[r] = fma(d2, d2, accd[r]); accd[r] = fma(d3, d3, accd[r]);
           }
         }
       }
@@ -545,6 +546,8 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
     const int nv = (PREC == PDET_BF16) ? (a.dpad >> 3) : (a.dpad >> 4);
     constexpr int NCH = NCHLP;
     for (int base = 0; base < nv; base += NCH * lpc) {
+      // bf16: loads issued unconditionally before use, as for float32 rows; fp8 keeps
+      // them under the row test (issuing all four first costs more in spilled registers)
       uint4 buf[NR][NCH];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -554,7 +557,11 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
 #pragma unroll
         for (int u = 0; u < NCH; ++u) {
           const int c = base + lg + u * lpc;
-          if (valid[r] && c < nv) buf[r][u] = xr[c];
+          if constexpr (PREC == PDET_BF16) {
+            buf[r][u] = xr[min(c, nv - 1)];
+          } else {
+            if (valid[r] && c < nv) buf[r][u] = xr[c];
+          }
         }
       }
 #pragma unroll
@@ -562,21 +569,22 @@ __device__ inline void cand_dist(const QArgs& a, const int32_t (&id)[NR], const 
         const float sc = (PREC == PDET_BF16 || !valid[r]) ? 1.0f : a.xscale[id[r]];
 #pragma unroll
         for (int u = 0; u < NCH; ++u) {
-          const int c = base + lg + u * lpc;
-          if (!valid[r] || c >= nv) continue;
+          // no branch around the arithmetic (see the float32 form): a discarded row
+          // contributes zeros
+          const int c = min(base + lg + u * lpc, nv - 1);
+          const bool ok = valid[r] && base + lg + u * lpc < nv;
           const uint4 v = buf[r][u];
           if constexpr (PREC == PDET_BF16) {
             const float* q = qv + c * 8;
-            float df;
-            df = bf16_lo(v.x) - q[0]; accf[r] = fmaf(df, df, accf[r]);
-            df = bf16_hi(v.x) - q[1]; accf[r] = fmaf(df, df, accf[r]);
-            df = bf16_lo(v.y) - q[2]; accf[r] = fmaf(df, df, accf[r]);
-            df = bf16_hi(v.y) - q[3]; accf[r] = fmaf(df, df, accf[r]);
-            df = bf16_lo(v.z) - q[4]; accf[r] = fmaf(df, df, accf[r]);
-            df = bf16_hi(v.z) - q[5]; accf[r] = fmaf(df, df, accf[r]);
-            df = bf16_lo(v.w) - q[6]; accf[r] = fmaf(df, df, accf[r]);
-            df = bf16_hi(v.w) - q[7]; accf[r] = fmaf(df, df, accf[r]);
+            const float xs[8] = {bf16_lo(v.x), bf16_hi(v.x), bf16_lo(v.y), bf16_hi(v.y),
+                                 bf16_lo(v.z), bf16_hi(v.z), bf16_lo(v.w), bf16_hi(v.w)};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float df = ok ? xs[e] - q[e] : 0.0f;
+              accf[r] = fmaf(df, df, accf[r]);
+            }
           } else {
+            if (!ok) continue;
             const float* q = qv + c * 16;
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -644,6 +652,19 @@ __device__ inline bool is_new(const QArgs& a, bool dense, const uint8_t* rr, con
   for (int i2 = 0; i2 < a.L; ++i2) {
     if (i2 == i) continue;
     const int r2 = dense ? rr[(int64_t)i2 * a.nlpad + lr[i2]]
+                         : hash_round(hk, hr, ((uint32_t)i2 << TREE_SHIFT) | (uint32_t)lr[i2]);
+    if (i2 < i ? (r2 <= rho) : (r2 < rho)) return false;
+  }
+  return true;
+}
+
+// is_new for L = 4 trees, with the point's leaf row already in registers.
+__device__ inline bool is_new4(bool dense, int64_t nlpad, const uint8_t* rr, const uint32_t* hk,
+                               const uint8_t* hr, const int32_t (&lr)[4], int i, int rho) {
+#pragma unroll
+  for (int i2 = 0; i2 < 4; ++i2) {
+    if (i2 == i) continue;
+    const int r2 = dense ? rr[(int64_t)i2 * nlpad + lr[i2]]
                          : hash_round(hk, hr, ((uint32_t)i2 << TREE_SHIFT) | (uint32_t)lr[i2]);
     if (i2 < i ? (r2 <= rho) : (r2 < rho)) return false;
   }
@@ -765,24 +786,33 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
     cut_e = NO_CUT;
     if (tid == 0) s_ef = e_lo;
     __syncthreads();
+    // The window holds QM list entries from ef on (their prefixes up to w_pre[QM]) and is
+    // reloaded only when a chunk reaches past it: a window covers many chunks' points.
+    uint32_t ef = 0, wend = 0;
+    bool have = false;
     for (uint32_t base = P0; base < P1; base += QM) {
       visits += std::min<uint32_t>(QM, P1 - base);
-      const uint32_t ef = uni(s_ef);
-      {
+      const bool reload = !have || wend < std::min(base + (uint32_t)QM, P1);
+      if (reload) {
+        ef = uni(s_ef);   // the entry holding `base`
         const uint32_t e = ef + tid;
         w_pre[tid] = (e <= e_hi) ? pre2[e] : 0xffffffffu;
         if (e < e_hi) {
           w_tree[tid] = (uint8_t)(adm2[e] >> TREE_SHIFT);
           w_start[tid] = ast[e];
         }
-        wcnt[tid] = 0;
-        if (tid == 0) {
-          w_pre[QM] = (ef + QM <= e_hi) ? pre2[ef + QM] : 0xffffffffu;
-          s_nb = 0;
-          s_cute = NO_CUT;
-        }
+        if (tid == 0) w_pre[QM] = (ef + QM <= e_hi) ? pre2[ef + QM] : 0xffffffffu;
+      }
+      wcnt[tid] = 0;
+      if (tid == 0) {
+        s_nb = 0;
+        s_cute = NO_CUT;
       }
       __syncthreads();
+      if (reload) {
+        wend = uni(w_pre[QM]);
+        have = true;
+      }
       const uint32_t p = base + tid;
       bool nw = false;
       int32_t id = 0;
@@ -795,8 +825,16 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
         }
         const int tr = w_tree[lo];
         const int64_t pos = (int64_t)tr * a.n + w_start[lo] + (p - w_pre[lo]);
-        id = a.perm[pos];
-        nw = is_new(a, dense, rq, hkey, hrnd, a.leafrow + pos * a.L, tr, rho);
+        if (a.L == 4) {
+          // the point's leaf row and id loaded together, before either is used
+          const int4 r4 = *reinterpret_cast<const int4*>(a.leafrow + pos * 4);
+          id = a.perm[pos];
+          const int32_t lr[4] = {r4.x, r4.y, r4.z, r4.w};
+          nw = is_new4(dense, a.nlpad, rq, hkey, hrnd, lr, tr, rho);
+        } else {
+          id = a.perm[pos];
+          nw = is_new(a, dense, rq, hkey, hrnd, a.leafrow + pos * a.L, tr, rho);
+        }
       }
       if (mode == WALK_CUT && cut_e == NO_CUT) {
         // new points per window entry; the first entry whose inclusive count reaches R

@@ -89,10 +89,7 @@ __device__ inline uint32_t nonzero_bytes(uint32_t w) {
   return ((((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u) >> 7;
 }
 
-__device__ inline uint32_t lanes_below(uint64_t mask) {
-  const int lane = threadIdx.x & 63;
-  return __popcll(mask & ((1ull << lane) - 1ull));
-}
+__device__ inline uint32_t lanes_below(uint64_t mask) { return lanes_below_mask(mask); }
 
 __device__ void emit_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start, int count,
                           const uint8_t* depth, const uint8_t* prefix, int K) {
