@@ -5,8 +5,10 @@ One step = build the index over the resident data (sample projection, breakpoint
 projection + encoding of every point, the L DE-Trees) + answer the whole query batch
 (c^2-k-ANN with FP32 verification). Default workload: the 100M-point batching
 configuration (SIFT-like bytes, n = 100,000,000, d = 128, L = 4, K = 16, Nr = 256,
-10,000 queries, k = 10, c = 1.5; about 51 GB resident), followed by a secondary block on
-the 1M-point configuration (10,000 queries, k = 50).
+10,000 queries, k = 10, c = 1.5; about 51 GB resident), followed by secondary blocks on
+the 1M-point configuration (10,000 queries, k = 50; with the literal query form beside the
+optimised one) and the 10M-point serving configuration (d = 256, unit-norm rows, FP8 and
+FP32 verification under Poisson load).
 
 Per workload, before the timed steps (untimed): ground truth for recall@10 is FP64 brute
 force over every point for the first --recall-queries queries; the stop-rule parameter
@@ -41,6 +43,10 @@ GEN_THREADS_N = 4_000_000     # from this size: data drawn in parallel chunks (s
 MAX_CAL_CANDIDATES = 2e5      # largest beta * n tried by the recall calibration
 POOL = 16                     # host worker processes (the GPU machine's CPU share)
 LITERAL_MAX_N = 4_000_000     # largest index on which the literal query form is timed
+# parameter study on indexes up to this size: (encoding, L, K) per configuration
+STUDY_MAX_N = 4_000_000
+STUDY = (("dynamic", 4, 16), ("static", 4, 16), ("dynamic", 2, 16), ("dynamic", 8, 16),
+         ("dynamic", 4, 8), ("dynamic", 4, 12))
 # per workload: low-precision forms measured, and the form of the graph-launched batch
 FORMS = {"sift-like-100M-d128": (("bf16",), "bf16"), "sift-like-1M-d128": (("bf16", "fp8"), "fp32"),
          "normed-1M-d960": (("bf16",), "bf16"), "normed-10M-d256": (("fp8",), "fp8"),
@@ -101,6 +107,7 @@ def measure(w, args, primary, helper=None):
     """Everything measured on one workload; returns a dict (the primary one becomes the line)."""
     import torch
     from paper_2603_24920_amd import pdet
+    from paper_2603_24920_amd import workloads as wl
 
     lowp_forms, plan_prec = FORMS.get(w.name, (("bf16",), "fp32"))
     if args.no_lowp:
@@ -288,6 +295,34 @@ def measure(w, args, primary, helper=None):
                        mean_point_visits_optimised=float(ost[:, 7].mean()))
         log(f"[bench] {w.name} literal vs optimised: {literal}")
 
+    # parameter study (encoding, L, K), FP32 verification at the calibrated beta with the
+    # radius schedule autotuned per configuration: recall, QPS and build rate
+    study = None
+    if not args.no_study and w.n <= STUDY_MAX_N and exact_ids is not None:
+        study = []
+        for enc, L_s, K_s in STUDY:
+            A_s = A if (L_s, K_s) == (w.L, w.K) else wl.projection_matrix(w.d, L_s, K_s,
+                                                                          seed=2603 + 16 * L_s + K_s)
+            torch.cuda.synchronize()
+            tb0 = time.perf_counter()
+            ixs = pdet.Index(Xd, A_s, sid, K_s, L_s, w.Nr, w.max_leaf, encoding=enc)
+            torch.cuda.synchronize()
+            tbs = time.perf_counter() - tb0
+            t = ixs.autotune(Qp, k=w.k, c=w.c, beta=beta)
+            sids, _ = ixs.query(Qr, k=w.k, c=w.c, beta=beta, r_min=t["r_min"])
+            srec = recall_at(sids.cpu().numpy(), exact_ids)
+            ixs.reserve(nq)
+            sec_s = timed(lambda: ixs.query(Qd, k=w.k, c=w.c, beta=beta, r_min=t["r_min"]))
+            _, _, sst = ixs.query(Qd, k=w.k, c=w.c, beta=beta, r_min=t["r_min"], stats=True)
+            sst = sst.cpu().numpy()
+            study.append(dict(encoding=enc, L=L_s, K=K_s, beta=beta, r_min=t["r_min"],
+                              recall_at_10=srec, qps=nq / sec_s, build_ms=1e3 * tbs,
+                              mean_candidates=float(sst[:, 1].mean()),
+                              mean_rounds=float(sst[:, 0].mean())))
+            log(f"[bench] {w.name} study {study[-1]}")
+            ixs.close()
+            del ixs
+
     # batching form: one graph-launched batch with k in {1,10,100}, c in {1.2,1.5,2.0}
     batching = None
     if not args.no_plan:
@@ -365,6 +400,7 @@ def measure(w, args, primary, helper=None):
                                   "tflops_peak_fp32": 157.3},
         "lowp": lowp,
         "literal_vs_optimised": literal,
+        "parameter_study": study,
         "batching": batching,
         "serving": serving,
     }
@@ -543,7 +579,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sift-like-100M-d128")
-    ap.add_argument("--secondary", default="sift-like-1M-d128",
+    ap.add_argument("--secondary", default="sift-like-1M-d128,normed-10M-d256",
                     help="comma-separated workloads measured after the primary ('' for none)")
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--beta", type=float, default=None, help="skip the recall calibration")
@@ -554,6 +590,8 @@ def main():
     ap.add_argument("--rcap", type=int, default=4, help="rounds resolved (with --beta/--r-min)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-plan", action="store_true", help="skip the graph-launched batch")
+    ap.add_argument("--no-study", action="store_true",
+                    help="skip the (encoding, L, K) parameter study")
     ap.add_argument("--no-literal", action="store_true",
                     help="skip timing the literal query form beside the optimised one")
     ap.add_argument("--no-recall", action="store_true",

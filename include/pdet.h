@@ -58,13 +58,24 @@ typedef enum { PDET_FP32 = 0, PDET_BF16 = 1, PDET_FP8_E4M3 = 2 } pdet_precision;
  *               projections give the interior breakpoints. floor(n_sample/Nr) >= 1.
  *   lowp_copies bit mask: (1u<<PDET_BF16) and/or (1u<<PDET_FP8_E4M3) build the
  *               low-precision copies of the data used by those verification forms.
+ *   encoding    PDET_ENC_DYNAMIC (0): interior breakpoints are the order statistics of the
+ *               sampled projections (Algorithm 1, the method's encoding). PDET_ENC_STATIC
+ *               (1): the iSAX-style static breakpoints the encoding phase contrasts with
+ *               (Section 3.1): each column's sampled projections are normalised by their
+ *               mean mu and population standard deviation sigma (FP64 over the float32
+ *               values) and B(z) = mu + sigma * Phi^-1((z-1)/Nr) for z = 2..Nr, the
+ *               equal-mass quantiles of N(0,1). Both take B(1) and B(Nr+1) from the column
+ *               extremes over all points. Everything after the breakpoints is the same.
  */
+typedef enum { PDET_ENC_DYNAMIC = 0, PDET_ENC_STATIC = 1 } pdet_encoding;
+
 typedef struct {
   int32_t K, L, Nr, max_leaf;
   const float* proj;
   const int64_t* sample_ids;
   int64_t n_sample;
   uint32_t lowp_copies;
+  int32_t encoding;
 } pdet_build_params;
 
 /*
@@ -74,9 +85,11 @@ typedef struct {
  * (breakpoints, codes, trees, low-precision copies) is owned by the index.
  * Errors: EUNSUPPORTED for n >= 2^28, L*K*n_sample (rounded up to a power of two)
  * >= 2^32, or a tree with 2^24 leaves or more; EINVAL for
- * n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power of two in [2,256], max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range;
+ * n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power of two in [2,256],
+ * max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range, an unknown encoding;
  * ENOMEM/EDEVICE from the runtime. On error *out is NULL.
- * Synchronises `stream` once (to size the leaf tables).
+ * Synchronises `stream` once (to size the leaf tables), and once more with the static
+ * encoding (the column moments go to the host, which evaluates Phi^-1).
  */
 pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build_params* p,
                        void* stream, pdet_index** out);
@@ -401,6 +414,10 @@ pdet_status pdet_server_offer_poisson(pdet_server* sv, const float* queries, int
  * eps^2 = chi2_{alpha1}(K), alpha1 = exp(-1/L): the theoretical false-positive fraction that
  * queries use when beta < 0 (Section 5.2.1, Figure "betal"). NaN for K < 1, L < 1, c <= 1. */
 double pdet_theoretical_beta(int32_t K, int32_t L, double c);
+
+/* Phi^-1(p), the standard normal quantile, to double precision, as the static encoding
+ * (PDET_ENC_STATIC) evaluates it on the host; NaN outside (0, 1). */
+double pdet_normal_quantile(double p);
 
 /* eps = sqrt(chi2 upper exp(-1/L) quantile, K dof) from Eq. 2 / Lemma 3; NaN if invalid. */
 double pdet_epsilon(int32_t K, int32_t L);

@@ -294,6 +294,8 @@ extern "C" {
 
 const char* pdet_last_error(void) { return g_last_error.c_str(); }
 
+double pdet_normal_quantile(double p) { return pdet::normal_quantile(p); }
+
 double pdet_theoretical_beta(int32_t K, int32_t L, double c) {
   if (K < 1 || L < 1 || !(c > 1.0) || !std::isfinite(c)) return std::numeric_limits<double>::quiet_NaN();
   return pdet::theoretical_beta(K, L, c);
@@ -323,6 +325,8 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
                  "n_sample must be in [Nr, n]");
     PDET_REQUIRE((p->lowp_copies & ~((1u << PDET_BF16) | (1u << PDET_FP8_E4M3))) == 0,
                  PDET_EINVAL, "unknown lowp_copies bit");
+    PDET_REQUIRE(p->encoding == PDET_ENC_DYNAMIC || p->encoding == PDET_ENC_STATIC, PDET_EINVAL,
+                 "unknown encoding");
     for (int64_t i = 0; i < p->n_sample; ++i)
       PDET_REQUIRE(p->sample_ids[i] >= 0 && p->sample_ids[i] < n, PDET_EINVAL,
                    "sample id out of range");
@@ -363,8 +367,12 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     }
     {
       Span sp(s, &tm.build_sort_ms);
-      select_breakpoints(ps.as<float>(), LK, p->n_sample, p->n_sample, ix->Nr,
-                         ix->B.as<float>(), temps, s);
+      if (p->encoding == PDET_ENC_STATIC)
+        static_breakpoints(ps.as<float>(), LK, p->n_sample, p->n_sample, ix->Nr,
+                           ix->B.as<float>(), temps, s);
+      else
+        select_breakpoints(ps.as<float>(), LK, p->n_sample, p->n_sample, ix->Nr,
+                           ix->B.as<float>(), temps, s);
       sp.finish();
     }
 

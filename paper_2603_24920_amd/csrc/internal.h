@@ -177,6 +177,12 @@ void encode_points(const Index& ix, hipStream_t s);
 // Temporaries go to `keep`, which the caller holds until its stream has synchronised.
 void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,
                         std::vector<PooledBuf>& keep, hipStream_t s);
+// Static (iSAX-style) interior breakpoints mu + sigma * Phi^-1((u)/Nr), u = 1..Nr-1, from the
+// columns' sampled mean and population standard deviation (synchronises `s`).
+void static_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,
+                        std::vector<PooledBuf>& keep, hipStream_t s);
+// Phi^-1(p) for p in (0, 1): the standard normal quantile, to double precision.
+double normal_quantile(double p);
 void fill_f32(float* p, int64_t count, float v, hipStream_t s);
 void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, hipStream_t s);
 void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,

@@ -243,6 +243,44 @@ __global__ void fill_kernel(float* p, int64_t count, float v) {
   if (g < count) p[g] = v;
 }
 
+// ---- column moments of the sample (static encoding), in a fixed summation order
+constexpr int MOM_THREADS = 256;
+
+// part[col][b]: block b's sum over its share of column col of x (mean == nullptr) or of
+// (x - mean[col])^2, in FP64.
+__global__ __launch_bounds__(MOM_THREADS) void col_partial(const float* keys, int64_t ld,
+                                                           int64_t ns, int nblk,
+                                                           const double* mean, double* part) {
+  __shared__ double sh[MOM_THREADS / 64];
+  const int col = blockIdx.y, b = blockIdx.x;
+  const float* c = keys + (int64_t)col * ld;
+  const double mu = mean ? mean[col] : 0.0;
+  double s = 0.0;
+  for (int64_t i = (int64_t)b * MOM_THREADS + threadIdx.x; i < ns;
+       i += (int64_t)nblk * MOM_THREADS) {
+    const double x = (double)c[i] - mu;
+    s += mean ? x * x : x;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < MOM_THREADS / 64; ++w) t += sh[w];
+    part[(int64_t)col * nblk + b] = t;
+  }
+}
+
+// out[col] = (sum of part[col][0..nblk)) / ns, summed in block order.
+__global__ void col_finish(const double* part, int nblk, int ncols, int64_t ns, double* out) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncols) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += part[(int64_t)col * nblk + b];
+  out[col] = t / (double)ns;
+}
+
 __global__ void outer_kernel(float* B, const uint32_t* colmm, int ncols, int Nr) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ncols) return;
@@ -372,6 +410,66 @@ void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
   PDET_HIP(hipGetLastError());
   // the kernels above still use the temporaries: the caller keeps them until it synchronises
   for (PooledBuf* t : {&mm, &hist, &fill, &boff, &tb, &tr, &gbuf}) keep.push_back(std::move(*t));
+}
+
+double normal_quantile(double p) {
+  // Phi(x) = erfc(-x / sqrt 2) / 2. The lower half is solved directly (the upper half by
+  // symmetry, which keeps relative accuracy in both tails): bisection brackets the root,
+  // then Newton steps with Phi'(x) = exp(-x^2 / 2) / sqrt(2 pi) polish it.
+  if (!(p > 0.0 && p < 1.0)) return std::numeric_limits<double>::quiet_NaN();
+  if (p == 0.5) return 0.0;   // Phi(0) = 1/2 exactly
+  if (p > 0.5) return -normal_quantile(1.0 - p);
+  auto Phi = [](double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); };
+  double lo = -40.0, hi = 0.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (Phi(mid) < p) lo = mid; else hi = mid;
+  }
+  double x = 0.5 * (lo + hi);
+  const double inv_sqrt_2pi = 0.3989422804014327;   // 1 / sqrt(2 pi)
+  for (int it = 0; it < 8; ++it) {
+    const double pdf = inv_sqrt_2pi * std::exp(-0.5 * x * x);
+    if (pdf <= 0.0) break;
+    const double dx = (Phi(x) - p) / pdf;
+    x -= dx;
+    if (std::fabs(dx) <= 1e-16 * std::fabs(x)) break;
+  }
+  return x;
+}
+
+void static_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,
+                        std::vector<PooledBuf>& keep, hipStream_t s) {
+  const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(ns, MOM_THREADS * 16), 256));
+  keep.emplace_back((size_t)ncols * nblk * 8);
+  keep.emplace_back((size_t)2 * ncols * 8);
+  double* part = keep[keep.size() - 2].as<double>();
+  double* mom = keep.back().as<double>();   // [0, ncols): mean, [ncols, 2 ncols): variance
+  hipLaunchKernelGGL(col_partial, dim3(nblk, ncols), dim3(MOM_THREADS), 0, s, keys, ld, ns, nblk,
+                     nullptr, part);
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(col_finish, dim3(cdiv(ncols, 64)), dim3(64), 0, s, part, nblk, ncols, ns,
+                     mom);
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(col_partial, dim3(nblk, ncols), dim3(MOM_THREADS), 0, s, keys, ld, ns, nblk,
+                     mom, part);
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(col_finish, dim3(cdiv(ncols, 64)), dim3(64), 0, s, part, nblk, ncols, ns,
+                     mom + ncols);
+  PDET_HIP(hipGetLastError());
+  std::vector<double> hm((size_t)2 * ncols);
+  PDET_HIP(hipMemcpyAsync(hm.data(), mom, hm.size() * 8, hipMemcpyDeviceToHost, s));
+  PDET_HIP(hipStreamSynchronize(s));
+  std::vector<double> zq(Nr);
+  for (int u = 1; u < Nr; ++u) zq[u] = normal_quantile((double)u / Nr);
+  std::vector<float> hb((size_t)ncols * (Nr - 1));
+  for (int c = 0; c < ncols; ++c) {
+    const double mu = hm[c], sd = std::sqrt(std::max(0.0, hm[ncols + c]));
+    for (int u = 1; u < Nr; ++u) hb[(size_t)c * (Nr - 1) + u - 1] = (float)(mu + sd * zq[u]);
+  }
+  // interior entries 1 .. Nr-1 of each row of B (the outer ones come from the encode pass)
+  PDET_HIP(hipMemcpy2DAsync(B + 1, (size_t)(Nr + 1) * 4, hb.data(), (size_t)(Nr - 1) * 4,
+                            (size_t)(Nr - 1) * 4, ncols, hipMemcpyHostToDevice, s));
+  PDET_HIP(hipStreamSynchronize(s));
 }
 
 void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, hipStream_t s) {

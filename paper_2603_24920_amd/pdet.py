@@ -23,7 +23,7 @@ QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits
              band_leaf=8, band_stop_b=9)
 X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF = range(7)
 EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_literal", "pdet_rc_ann", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
-            "pdet_epsilon", "pdet_theoretical_beta", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
+            "pdet_epsilon", "pdet_theoretical_beta", "pdet_normal_quantile", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
             "pdet_server_get_stats", "pdet_server_free", "pdet_server_offer_poisson",
@@ -34,7 +34,10 @@ EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_literal", "pdet
 class BuildParams(ctypes.Structure):
     _fields_ = [("K", c_int32), ("L", c_int32), ("Nr", c_int32), ("max_leaf", c_int32),
                 ("proj", POINTER(c_float)), ("sample_ids", POINTER(c_int64)),
-                ("n_sample", c_int64), ("lowp_copies", c_uint32)]
+                ("n_sample", c_int64), ("lowp_copies", c_uint32), ("encoding", c_int32)]
+
+
+ENCODINGS = {"dynamic": 0, "static": 1}
 
 
 class QueryParams(ctypes.Structure):
@@ -119,6 +122,8 @@ def lib() -> ctypes.CDLL:
         L.pdet_epsilon.restype = c_double
         L.pdet_theoretical_beta.argtypes = [c_int32, c_int32, c_double]
         L.pdet_theoretical_beta.restype = c_double
+        L.pdet_normal_quantile.argtypes = [c_double]
+        L.pdet_normal_quantile.restype = c_double
         L.pdet_last_error.restype = ctypes.c_char_p
         L.pdet_set_timing.argtypes = [c_int32]
         L.pdet_set_timing.restype = None
@@ -162,6 +167,11 @@ def epsilon(K: int, L: int) -> float:
     return lib().pdet_epsilon(K, L)
 
 
+def normal_quantile(p: float) -> float:
+    """Phi^-1(p) as the library's static encoding computes it (host code)."""
+    return lib().pdet_normal_quantile(p)
+
+
 def theoretical_beta(K: int, L: int, c: float) -> float:
     """beta of Lemma 3 for (K, L, c), computed by the library's host code."""
     return lib().pdet_theoretical_beta(K, L, c)
@@ -193,7 +203,7 @@ class Index:
     """A DE-Tree index resident on the GPU. ``X`` (CUDA float32 [n][d]) is borrowed."""
 
     def __init__(self, X, proj, sample_ids, K=16, L=4, Nr=256, max_leaf=128, lowp=(),
-                 stream=None):
+                 stream=None, encoding="dynamic"):
         import torch
         if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
                 and X.dim() == 2 and X.is_contiguous()):
@@ -208,12 +218,14 @@ class Index:
         for name in lowp:
             mask |= 1 << PRECISIONS[name]
         p = BuildParams(K, L, Nr, max_leaf, self._proj.ctypes.data_as(POINTER(c_float)),
-                        self._sample.ctypes.data_as(POINTER(c_int64)), len(self._sample), mask)
+                        self._sample.ctypes.data_as(POINTER(c_int64)), len(self._sample), mask,
+                        ENCODINGS[encoding])
         h = c_void_p()
         _check(lib().pdet_build(c_void_p(X.data_ptr()), self.n, self.d, ctypes.byref(p),
                                 _stream(stream), ctypes.byref(h)))
         self._h, self._lib = h, lib()
         self.K, self.L, self.Nr, self.max_leaf = K, L, Nr, max_leaf
+        self.encoding = encoding
 
     def close(self):
         # the library handle is held on the object: module globals may already be gone when

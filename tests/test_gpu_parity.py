@@ -29,16 +29,17 @@ from parity import BAND, compare_batch, near_stop_b, near_threshold, proj_bound,
 
 
 class Case:
-    def __init__(self, X, A, sid, K, L, Nr, max_leaf, lowp=()):
+    def __init__(self, X, A, sid, K, L, Nr, max_leaf, lowp=(), encoding="dynamic"):
         self.X, self.A, self.sid = X, A, sid
         self.K, self.L, self.Nr, self.max_leaf = K, L, Nr, max_leaf
         self.Xd = torch.from_numpy(X).cuda()
-        print(f"\n[case] n={len(X)} d={X.shape[1]} K={K} L={L} Nr={Nr} max_leaf={max_leaf}",
-              flush=True)
-        self.idx = pdet.Index(self.Xd, A, sid, K, L, Nr, max_leaf, lowp=lowp)
+        print(f"\n[case] n={len(X)} d={X.shape[1]} K={K} L={L} Nr={Nr} max_leaf={max_leaf} "
+              f"encoding={encoding}", flush=True)
+        self.idx = pdet.Index(self.Xd, A, sid, K, L, Nr, max_leaf, lowp=lowp, encoding=encoding)
         torch.cuda.synchronize()
         self.H = oracle.project(X, A)
-        self.B_or = oracle.breakpoints(self.H[sid], Nr, self.H.min(axis=0), self.H.max(axis=0))
+        make = oracle.static_breakpoints if encoding == "static" else oracle.breakpoints
+        self.B_or = make(self.H[sid], Nr, self.H.min(axis=0), self.H.max(axis=0))
         self.B_gpu = self.idx.export(pdet.X_BREAKPOINTS).astype(np.float64)
         self.codes_gpu = np.ascontiguousarray(self.idx.export(pdet.X_CODES)[:, :, :K])
         # the oracle's own eps (Eq. 2 / Lemma 3), passed to both sides

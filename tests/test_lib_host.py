@@ -124,3 +124,25 @@ def test_theoretical_beta_matches_lemma3(L, c):
 def test_theoretical_beta_invalid():
     assert math.isnan(pdet.theoretical_beta(16, 4, 1.0))
     assert math.isnan(pdet.theoretical_beta(0, 4, 1.5))
+
+
+def test_normal_quantile_matches_scipy():
+    """The static encoding's Phi^-1 (bisection + Newton on erfc) against SciPy's ppf at the
+    quantiles it uses (u / Nr) and in the tails."""
+    from scipy.stats import norm
+    ps = [u / 256 for u in range(1, 256)] + [1e-12, 1e-6, 0.3, 0.7, 1 - 1e-6]
+    for p in ps:
+        want = norm.ppf(p)
+        got = pdet.normal_quantile(p)
+        assert abs(got - want) <= 1e-12 * max(1.0, abs(want)), (p, got, want)
+    assert pdet.normal_quantile(0.5) == 0.0
+    for bad in (0.0, 1.0, -0.5, 2.0, float("nan")):
+        assert math.isnan(pdet.normal_quantile(bad))
+
+
+def test_build_rejects_unknown_encoding():
+    p, keep = _params(encoding=2)
+    h = ctypes.c_void_p()
+    st = pdet.lib().pdet_build(ctypes.c_void_p(4096), 1000, 8, ctypes.byref(p), None,
+                               ctypes.byref(h))
+    assert st == pdet.PDET_EINVAL and b"encoding" in pdet.lib().pdet_last_error()
