@@ -120,103 +120,132 @@ __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, co
   }
 }
 
-// First-layer counting sort. A block takes FL_PTS consecutive points of one tree and counts
-// their keys in an LDS hash first, so a key shared by many points of the block (clustered
-// data) costs one global atomic instead of one per point; a key that finds no slot within
-// FL_PROBES probes goes straight to the global counters. Points of a first-layer node come
-// out in no particular order (a node's later splits do not depend on it).
-constexpr int FL_PTS = 4096;
-constexpr int FL_PER_THREAD = FL_PTS / 256;
-constexpr int FL_HASH = 2048;
-constexpr int FL_PROBES = 32;
-constexpr uint32_t FL_EMPTY = 0xffffffffu;
+// First layer: a stable LSD radix sort of each tree's 16-bit keys in two 8-bit passes
+// (one for K <= 8). A workgroup takes RK_TILE consecutive items of one tree in RK_ROUNDS
+// rounds of 256, in order; the lanes of a wave holding the same digit find each other with
+// eight ballots, so an item's place is its digit's running offset (the exclusive scan of the
+// [tree][digit][tile] counts, plus the tile's earlier rounds) plus the same-digit items of
+// the earlier waves and lanes of its round. The output keeps input order within a digit.
+constexpr int RK_THREADS = 256;
+constexpr int RK_ROUNDS = 16;
+constexpr int RK_TILE = RK_THREADS * RK_ROUNDS;
+constexpr int RK_WAVES = RK_THREADS / 64;
 
-// Slot of `key` in the block's hash (inserted if absent), or -1 if none within FL_PROBES.
-__device__ inline int fl_insert(uint32_t* hk, uint32_t key) {
-  uint32_t sl = mix32(key) & (FL_HASH - 1);
-  for (int pr = 0; pr < FL_PROBES; ++pr) {
-    const uint32_t prev = atomicCAS(&hk[sl], FL_EMPTY, key);
-    if (prev == FL_EMPTY || prev == key) return (int)sl;
-    sl = (sl + 1) & (FL_HASH - 1);
+// The lanes of the wave that hold the same 8-bit digit as this one (valid lanes only).
+__device__ inline uint64_t same_digit_lanes(uint32_t dgt, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool set = (dgt >> bit) & 1u;
+    const uint64_t bb = __ballot(valid && set);
+    m &= set ? bb : ~bb;
   }
-  return -1;
+  return m;
 }
 
-__global__ __launch_bounds__(256) void fl_hist(const uint16_t* flkey, int64_t n, int K,
-                                               uint32_t* hist) {
-  __shared__ uint32_t hk[FL_HASH], hc[FL_HASH];
-  const int tree = blockIdx.y;
-  const int64_t p0 = (int64_t)blockIdx.x * FL_PTS;
-  for (int i = threadIdx.x; i < FL_HASH; i += 256) { hk[i] = FL_EMPTY; hc[i] = 0; }
-  __syncthreads();
-  uint32_t* h = hist + ((int64_t)tree << K);
-  const uint16_t* kt = flkey + (int64_t)tree * n;
-  for (int u = 0; u < FL_PER_THREAD; ++u) {
-    const int64_t p = p0 + u * 256 + threadIdx.x;
-    if (p < n) {
-      const uint32_t key = kt[p];
-      const int sl = fl_insert(hk, key);
-      if (sl >= 0) atomicAdd(&hc[sl], 1u);
-      else atomicAdd(&h[key], 1u);
-    }
+// h[tree][digit][tile]: items of the tile whose key has `digit` at bits SHIFT..SHIFT+7.
+template <int SHIFT>
+__global__ __launch_bounds__(RK_THREADS) void rk_hist(const uint16_t* keys, int64_t n, int nblk,
+                                                      uint32_t* h) {
+  __shared__ uint32_t cnt[256];
+  const int tree = blockIdx.y, blk = blockIdx.x;
+  cnt[threadIdx.x] = 0;
+  const uint16_t* kt = keys + (int64_t)tree * n;
+  const int64_t p0 = (int64_t)blk * RK_TILE;
+  uint32_t kv[RK_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RK_ROUNDS; ++r) {
+    const int64_t p = p0 + r * RK_THREADS + threadIdx.x;
+    kv[r] = (p < n) ? kt[p] : 0u;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < FL_HASH; i += 256)
-    if (hk[i] != FL_EMPTY) atomicAdd(&h[hk[i]], hc[i]);
+#pragma unroll
+  for (int r = 0; r < RK_ROUNDS; ++r) {
+    const bool v = p0 + r * RK_THREADS + threadIdx.x < n;
+    const uint32_t d = (kv[r] >> SHIFT) & 255u;
+    const uint64_t m = same_digit_lanes(d, v);
+    if (v && lanes_below_mask(m) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
+  }
+  __syncthreads();
+  h[((int64_t)tree * 256 + threadIdx.x) * nblk + blk] = cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void fl_scatter(const uint16_t* flkey, const uint8_t* codes,
-                                                  int64_t n, int K, const uint32_t* off,
-                                                  uint32_t* cursor, Bufs b) {
-  __shared__ uint32_t hk[FL_HASH], hc[FL_HASH], hb[FL_HASH];
-  const int tree = blockIdx.y;
-  const int64_t p0 = (int64_t)blockIdx.x * FL_PTS;
-  for (int i = threadIdx.x; i < FL_HASH; i += 256) { hk[i] = FL_EMPTY; hc[i] = 0; }
-  __syncthreads();
-  const uint32_t* o = off + ((int64_t)tree << K);
-  uint32_t* cur = cursor + ((int64_t)tree << K);
+// One pass: items (key, code row, id) of each tree to their places. FIRST: the input is
+// the encoder's output in point order (ids are positions).
+template <int SHIFT, bool FIRST>
+__global__ __launch_bounds__(RK_THREADS) void rk_scatter(const uint16_t* kin, const uint4* rin,
+                                                         const int32_t* iin, int64_t n, int nblk,
+                                                         const uint32_t* off, uint16_t* kout,
+                                                         uint4* rout, int32_t* iout) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[RK_WAVES][256];
+  const int tree = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x, wave = tid >> 6;
   const int64_t tb = (int64_t)tree * n;
-  const uint16_t* kt = flkey + tb;
-  const uint4* ct = reinterpret_cast<const uint4*>(codes) + tb;
-  int32_t* pm = b.ids[0] + tb;
-  uint4* rw = b.rows[0] + tb;
-  uint32_t key[FL_PER_THREAD];
-  int slot[FL_PER_THREAD];
-  // count per slot (keys without a slot take their position from the global cursor now)
+  run[tid] = off[((int64_t)tree * 256 + tid) * nblk + blk];
 #pragma unroll
-  for (int u = 0; u < FL_PER_THREAD; ++u) {
-    const int64_t p = p0 + u * 256 + threadIdx.x;
-    slot[u] = -2;
+  for (int w = 0; w < RK_WAVES; ++w) wc[w][tid] = 0;
+  const int64_t p0 = (int64_t)blk * RK_TILE;
+  // the next round's item is loaded while the current one is placed
+  auto load = [&](int r, uint32_t& key, uint4& row, int32_t& id) {
+    const int64_t p = p0 + r * RK_THREADS + tid;
+    key = 0;
+    row = make_uint4(0, 0, 0, 0);
+    id = 0;
     if (p < n) {
-      key[u] = kt[p];
-      slot[u] = fl_insert(hk, key[u]);
-      if (slot[u] >= 0) {
-        atomicAdd(&hc[slot[u]], 1u);
-      } else {
-        const uint32_t pos = o[key[u]] + atomicAdd(&cur[key[u]], 1u);
-        pm[pos] = (int32_t)p;
-        rw[pos] = ct[p];
-      }
+      key = kin[tb + p];
+      row = rin[tb + p];
+      id = FIRST ? (int32_t)p : iin[tb + p];
     }
-  }
+  };
+  uint32_t key, nkey;
+  uint4 row, nrow;
+  int32_t id, nid;
+  load(0, key, row, id);
   __syncthreads();
-  // one reservation per key of the block
-  for (int i = threadIdx.x; i < FL_HASH; i += 256) {
-    if (hk[i] != FL_EMPTY) {
-      hb[i] = o[hk[i]] + atomicAdd(&cur[hk[i]], hc[i]);
-      hc[i] = 0;
+  for (int r = 0; r < RK_ROUNDS; ++r) {
+    if (r + 1 < RK_ROUNDS) load(r + 1, nkey, nrow, nid);
+    const bool v = p0 + r * RK_THREADS + tid < n;
+    const uint32_t d = (key >> SHIFT) & 255u;
+    const uint64_t m = same_digit_lanes(d, v);
+    const uint32_t rank = lanes_below_mask(m);
+    if (v && rank == 0) wc[wave][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (v) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wc[w][d];
+      kout[tb + pos] = (uint16_t)key;
+      rout[tb + pos] = row;
+      iout[tb + pos] = id;
     }
-  }
-  __syncthreads();
+    __syncthreads();
+    // thread t owns digit t: the round's counts move its running offset
+    uint32_t t = 0;
 #pragma unroll
-  for (int u = 0; u < FL_PER_THREAD; ++u) {
-    if (slot[u] >= 0) {
-      const int64_t p = p0 + u * 256 + threadIdx.x;
-      const uint32_t pos = hb[slot[u]] + atomicAdd(&hc[slot[u]], 1u);
-      pm[pos] = (int32_t)p;
-      rw[pos] = ct[p];
-    }
+    for (int w = 0; w < RK_WAVES; ++w) { t += wc[w][tid]; wc[w][tid] = 0; }
+    run[tid] += t;
+    __syncthreads();
+    key = nkey; row = nrow; id = nid;
   }
+}
+
+// First-layer nodes from the sorted keys: start[tree][key] and end[tree][key] at the
+// boundaries of each key's run (both zero for keys that do not occur).
+__global__ void rk_bounds(const uint16_t* keys, int64_t n, int K, uint32_t* start,
+                          uint32_t* end) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tree = blockIdx.y;
+  if (p >= n) return;
+  const uint16_t* kt = keys + (int64_t)tree * n;
+  const uint32_t key = kt[p];
+  const int64_t g = ((int64_t)tree << K) + key;
+  if (p == 0 || kt[p - 1] != key) start[g] = (uint32_t)p;
+  if (p == n - 1 || kt[p + 1] != key) end[g] = (uint32_t)(p + 1);
+}
+
+__global__ void rk_counts(const uint32_t* start, const uint32_t* end, int64_t total,
+                          uint32_t* hist) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < total) hist[g] = end[g] - start[g];
 }
 
 __global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, int K, int bits,
@@ -898,19 +927,56 @@ void build_trees(Index& ix, hipStream_t s) {
   DevBuf scan_tmp;
   PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
   PDET_HIP(hipMemsetAsync(cursor.ptr(), 0, cursor.bytes(), s));
-  const uint16_t* flkey = ix.flkey.as<uint16_t>();
   DevBuf rows0((size_t)L * n * KP);   // code rows in permutation order (buffer 0)
   Bufs bf{};
   bf.rows[0] = rows0.as<uint4>();
   bf.ids[0] = ix.perm.as<int32_t>();
 
-  hipLaunchKernelGGL(fl_hist, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, flkey, n, K,
-                     hist.as<uint32_t>());
-  PDET_HIP(hipGetLastError());
-  scan_rows(hist.as<uint32_t>(), off.as<uint32_t>(), nullptr, L, NK, scan_tmp, s);
-  hipLaunchKernelGGL(fl_scatter, dim3(cdiv(n, FL_PTS), L), dim3(256), 0, s, flkey,
-                     ix.codes.as<uint8_t>(), n, K, off.as<uint32_t>(), cursor.as<uint32_t>(), bf);
-  PDET_HIP(hipGetLastError());
+  // first layer: radix sort of the keys carrying code rows and ids, then the nodes' starts
+  // and sizes from the runs of equal keys. The pass buffers double as the split phase's
+  // second row / id buffers.
+  DevBuf rows1((size_t)L * n * KP);
+  PooledBuf ids1((size_t)L * n * 4), keys1((size_t)L * n * 2);
+  bf.rows[1] = rows1.as<uint4>();
+  bf.ids[1] = ids1.as<int32_t>();
+  const int nblk = (int)cdiv(n, RK_TILE);
+  // (temporaries live until the final synchronisation, like every one of this function)
+  PooledBuf h8((size_t)L * 256 * nblk * 4), o8((size_t)L * 256 * nblk * 4);
+  {
+    const dim3 grid((unsigned)nblk, (unsigned)L);
+    uint16_t* fk = ix.flkey.as<uint16_t>();
+    const uint4* codes = reinterpret_cast<const uint4*>(ix.codes.as<uint8_t>());
+    const bool two = K > 8;
+    // sorted keys: back in the key buffer after two passes, in keys1 after one (a pass
+    // never writes the buffer it reads)
+    uint16_t* kfin = two ? fk : keys1.as<uint16_t>();
+    hipLaunchKernelGGL(rk_hist<0>, grid, dim3(RK_THREADS), 0, s, fk, n, nblk, h8.as<uint32_t>());
+    PDET_HIP(hipGetLastError());
+    scan_rows(h8.as<uint32_t>(), o8.as<uint32_t>(), nullptr, L, (int64_t)256 * nblk, scan_tmp, s);
+    // one pass (K <= 8): straight to the final buffers; two: through buffer 1
+    hipLaunchKernelGGL((rk_scatter<0, true>), grid, dim3(RK_THREADS), 0, s, fk, codes, nullptr, n,
+                       nblk, o8.as<uint32_t>(), keys1.as<uint16_t>(),
+                       two ? bf.rows[1] : bf.rows[0], two ? bf.ids[1] : bf.ids[0]);
+    PDET_HIP(hipGetLastError());
+    if (two) {
+      hipLaunchKernelGGL(rk_hist<8>, grid, dim3(RK_THREADS), 0, s, keys1.as<uint16_t>(), n, nblk,
+                         h8.as<uint32_t>());
+      PDET_HIP(hipGetLastError());
+      scan_rows(h8.as<uint32_t>(), o8.as<uint32_t>(), nullptr, L, (int64_t)256 * nblk, scan_tmp,
+                s);
+      hipLaunchKernelGGL((rk_scatter<8, false>), grid, dim3(RK_THREADS), 0, s,
+                         keys1.as<uint16_t>(), bf.rows[1], bf.ids[1], n, nblk, o8.as<uint32_t>(),
+                         fk, bf.rows[0], bf.ids[0]);
+      PDET_HIP(hipGetLastError());
+    }
+    PDET_HIP(hipMemsetAsync(off.ptr(), 0, off.bytes(), s));
+    hipLaunchKernelGGL(rk_bounds, dim3(cdiv(n, 256), L), dim3(256), 0, s, kfin, n, K,
+                       off.as<uint32_t>(), cursor.as<uint32_t>());
+    PDET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(rk_counts, dim3(cdiv(L * NK, 256)), dim3(256), 0, s, off.as<uint32_t>(),
+                       cursor.as<uint32_t>(), L * NK, hist.as<uint32_t>());
+    PDET_HIP(hipGetLastError());
+  }
 
   // leaf records at start positions
   PooledBuf cnt_at((size_t)L * n * 4), hidx_at((size_t)L * n * KP * 2);
@@ -944,14 +1010,9 @@ void build_trees(Index& ix, hipStream_t s) {
   Seg* cur_big = bigA.as<Seg>();
   Seg* nxt_big = bigB.as<Seg>();
   int cur_slot = 0;   // counters of the current list at c[2*cur_slot]
-  DevBuf rows1;
-  PooledBuf ids1, cntbuf, split, c0, cur0, cur1, leafs, units;
+  PooledBuf cntbuf, split, c0, cur0, cur1, leafs, units;
   if (nbig) {
     units.alloc(((size_t)L * n / SEG_CHUNK + (size_t)big_cap) * sizeof(Unit));
-    rows1.alloc((size_t)L * n * KP);
-    ids1.alloc((size_t)L * n * 4);
-    bf.rows[1] = rows1.as<uint4>();
-    bf.ids[1] = ids1.as<int32_t>();
     cntbuf.alloc((size_t)big_cap * KP * 4);
     split.alloc((size_t)big_cap * 4); c0.alloc((size_t)big_cap * 4);
     cur0.alloc((size_t)big_cap * 4); cur1.alloc((size_t)big_cap * 4);
