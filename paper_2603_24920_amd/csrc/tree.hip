@@ -99,6 +99,20 @@ __device__ void emit_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start,
     h[j] = (j < K) ? (uint16_t)((1u << depth[j]) | prefix[j]) : (uint16_t)0;
 }
 
+// The leaf record of child `bit` of a node split on dimension j (depth and prefix of the
+// parent, read in place).
+__device__ void emit_child_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start, int count,
+                                const uint8_t* depth, const uint8_t* prefix, int j, int bit,
+                                int K) {
+  lo.cnt_at[(int64_t)tree * n + start] = (uint32_t)count;
+  uint16_t* h = lo.hidx_at + ((int64_t)tree * n + start) * KP;
+  for (int jj = 0; jj < KP; ++jj) {
+    const uint32_t d = depth[jj] + (jj == j ? 1u : 0u);
+    const uint32_t p = (jj == j) ? prefix[jj] * 2u + (uint32_t)bit : prefix[jj];
+    h[jj] = (jj < K) ? (uint16_t)((1u << d) | p) : (uint16_t)0;
+  }
+}
+
 __device__ inline bool fully_refined(const uint8_t* depth, int K, int bits) {
   bool f = true;
   for (int j = 0; j < K; ++j) f = f && (depth[j] >= bits);
@@ -394,9 +408,16 @@ __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, co
   a.count = (int32_t)c0[i];
   b.start = s.start + a.count;
   b.count = s.count - a.count;
-  a.depth[j] = b.depth[j] = s.depth[j] + 1;
-  a.prefix[j] = (uint8_t)(s.prefix[j] * 2);
-  b.prefix[j] = (uint8_t)(s.prefix[j] * 2 + 1);
+  // (every field written with a fixed index: a runtime index would put the copies in
+  // scratch memory)
+#pragma unroll
+  for (int jj = 0; jj < KP; ++jj) {
+    if (jj == j) {
+      a.depth[jj] = b.depth[jj] = (uint8_t)(s.depth[jj] + 1);
+      a.prefix[jj] = (uint8_t)(s.prefix[jj] * 2);
+      b.prefix[jj] = (uint8_t)(s.prefix[jj] * 2 + 1);
+    }
+  }
   route(a, K, bits, max_leaf, n, lo, li);
   route(b, K, bits, max_leaf, n, lo, li);
 }
@@ -615,37 +636,44 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
     for (int t = threadIdx.x; t < count; t += NT) ord[t] = tmp[t];
     // 4. children: leaves are emitted, open ones form the next level's list (in position
     //    order: children of a node are adjacent, bit 0 first)
+    //    The children are read and written field by field from the parent in LDS: a
+    //    private copy indexed by the runtime split dimension would live in scratch memory.
     uint32_t nopen = 0;
-    SegL ca, cb;
     bool oa = false, ob = false;
+    int za = 0, zb = 0, jc = 0;
     if ((int)threadIdx.x < nact) {
       const SegL& g = S[threadIdx.x];
-      const int j = jsel[threadIdx.x];
-      const int z = c0s[threadIdx.x];
-      ca = g;
-      cb = g;
-      ca.count = (int16_t)z;
-      cb.start = (int16_t)(g.start + z);
-      cb.count = (int16_t)(g.count - z);
-      ca.depth[j] = cb.depth[j] = (uint8_t)(g.depth[j] + 1);
-      ca.prefix[j] = (uint8_t)(g.prefix[j] * 2);
-      cb.prefix[j] = (uint8_t)(g.prefix[j] * 2 + 1);
-      const bool full = fully_refined(ca.depth, K, bits);
-      oa = ca.count > max_leaf && !full;
-      ob = cb.count > max_leaf && !full;
-      if (!oa && ca.count > 0)
-        emit_leaf(lo, n, s.tree, (int64_t)s.start + ca.start, ca.count, ca.depth, ca.prefix, K);
-      if (!ob && cb.count > 0)
-        emit_leaf(lo, n, s.tree, (int64_t)s.start + cb.start, cb.count, cb.depth, cb.prefix, K);
+      jc = jsel[threadIdx.x];
+      za = c0s[threadIdx.x];
+      zb = g.count - za;
+      bool full = true;   // every dimension fully refined after the split
+      for (int jj = 0; jj < K; ++jj) full = full && (g.depth[jj] + (jj == jc ? 1 : 0) >= bits);
+      oa = za > max_leaf && !full;
+      ob = zb > max_leaf && !full;
+      if (!oa && za > 0)
+        emit_child_leaf(lo, n, s.tree, (int64_t)s.start + g.start, za, g.depth, g.prefix, jc, 0,
+                        K);
+      if (!ob && zb > 0)
+        emit_child_leaf(lo, n, s.tree, (int64_t)s.start + g.start + za, zb, g.depth, g.prefix,
+                        jc, 1, K);
       nopen = (oa ? 1u : 0u) + (ob ? 1u : 0u);
     }
     uint32_t total;
     const uint32_t at = block_excl_scan<NT>(nopen, sh_scan, &total);
     if ((int)threadIdx.x < nact) {
+      const SegL& g = S[threadIdx.x];
       SegL* Nx = segs[cur ^ 1];
       uint32_t w = at;
-      if (oa) Nx[w++] = ca;
-      if (ob) Nx[w] = cb;
+      for (int bit = 0; bit < 2; ++bit) {
+        if (!(bit ? ob : oa)) continue;
+        SegL& c = Nx[w++];
+        c.start = (int16_t)(g.start + (bit ? za : 0));
+        c.count = (int16_t)(bit ? zb : za);
+        for (int jj = 0; jj < KP; ++jj) {
+          c.depth[jj] = (uint8_t)(g.depth[jj] + (jj == jc ? 1 : 0));
+          c.prefix[jj] = (uint8_t)(jj == jc ? g.prefix[jj] * 2 + bit : g.prefix[jj]);
+        }
+      }
     }
     if (threadIdx.x == 0) s_nact = total;
     __syncthreads();
@@ -819,23 +847,36 @@ struct LeafTables {
   int64_t nl[PDET_MAX_L];
 };
 
-__global__ void leaf_compact(const uint32_t* cnt_at, const uint16_t* hidx_at, const uint32_t* ord,
-                             int64_t n, int K, int bits, int Nr, const float* B, LeafTables t) {
+// Leaf tables in two steps: every recorded start position goes to its leaf's slot (one
+// sparse write per leaf), then one thread per leaf fills the rest (all lanes busy).
+__global__ void leaf_starts(const uint32_t* cnt_at, const uint32_t* ord, int64_t n,
+                            LeafTables t) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int tree = blockIdx.y;
   if (p >= n) return;
   const int64_t g = (int64_t)tree * n + p;
-  const uint32_t c = cnt_at[g];
-  if (!c) return;
-  const int64_t o = ord[g];
+  if (cnt_at[g]) t.start[tree][ord[g]] = (int32_t)p;
+}
+
+__global__ void leaf_fill(const uint32_t* cnt_at, const uint16_t* hidx_at, int64_t n, int K,
+                          int bits, int Nr, const float* B, LeafTables t) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tree = blockIdx.y;
   const int64_t nl = t.nl[tree];
-  t.start[tree][o] = (int32_t)p;
-  t.count[tree][o] = (int32_t)c;
+  if (o >= nl) return;
+  const int64_t g = (int64_t)tree * n + t.start[tree][o];
+  t.count[tree][o] = (int32_t)cnt_at[g];
+  const uint4* hs = reinterpret_cast<const uint4*>(hidx_at + g * KP);
+  const uint4 h0 = hs[0], h1 = hs[1];
+  uint4* hd = reinterpret_cast<uint4*>(t.hidx[tree] + o * KP);
+  hd[0] = h0;
+  hd[1] = h1;
+  const uint32_t hw[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
   for (int j = 0; j < KP; ++j) {
-    const uint16_t h = hidx_at[g * KP + j];
-    t.hidx[tree][o * KP + j] = h;
     if (j < K) {
-      const int dep = 31 - __clz((int)h);
+      const int h = (int)((hw[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+      const int dep = 31 - __clz(h);
       const int pre = h & ((1 << dep) - 1);
       const int lo_code = pre << (bits - dep);
       const int hi_code = ((pre + 1) << (bits - dep)) - 1;
@@ -868,6 +909,10 @@ __global__ void leafrow_kernel(const int32_t* perm, const int32_t* leaf_of, int6
   if (p >= n) return;
   const int32_t* src = leaf_of + (int64_t)perm[(int64_t)tree * n + p] * L;
   int32_t* dst = leafrow + ((int64_t)tree * n + p) * L;
+  if (L == 4) {   // one 16-byte row
+    *reinterpret_cast<int4*>(dst) = *reinterpret_cast<const int4*>(src);
+    return;
+  }
   for (int j = 0; j < L; ++j) dst[j] = src[j];
 }
 
@@ -1139,10 +1184,17 @@ void build_trees(Index& ix, hipStream_t s) {
     t.box[i] = ix.box[i].as<float>();
     t.nl[i] = nl[i];
   }
-  hipLaunchKernelGGL(leaf_compact, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
-                     hidx_at.as<uint16_t>(), flags.as<uint32_t>(), n, K, bits, ix.Nr,
-                     ix.B.as<float>(), t);
+  hipLaunchKernelGGL(leaf_starts, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
+                     flags.as<uint32_t>(), n, t);
   PDET_HIP(hipGetLastError());
+  int64_t nl_max = 0;
+  for (int i = 0; i < L; ++i) nl_max = std::max<int64_t>(nl_max, nl[i]);
+  if (nl_max) {
+    hipLaunchKernelGGL(leaf_fill, dim3(cdiv(nl_max, 256), L), dim3(256), 0, s,
+                       cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>(), n, K, bits, ix.Nr,
+                       ix.B.as<float>(), t);
+    PDET_HIP(hipGetLastError());
+  }
   GroupArgs ga{};
   int64_t nl_pad = 0;
   for (int i = 0; i < L; ++i) {
