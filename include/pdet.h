@@ -52,10 +52,16 @@ typedef enum { PDET_FP32 = 0, PDET_BF16 = 1, PDET_FP8_E4M3 = 2 } pdet_precision;
  *   K, L        projections per space and number of spaces (Eq. 1: K*L Gaussian vectors).
  *   Nr          regions per dimension, a power of two in [2, 256] (8-bit symbols).
  *   max_leaf    leaf capacity ("max_size" of Algorithm 2), >= 1.
- *   proj        host, float32 [d][L*K] row-major; column i*K+j is the hash vector a_ij.
- *               The caller draws it (entries i.i.d. N(0,1)); it is copied.
+ *   proj        host, float32 [d][L*K] row-major; column i*K+j is the hash vector a_ij
+ *               (entries i.i.d. N(0,1)); it is copied. NULL: the library draws it from
+ *               `seed` (pdet_draw_params).
  *   sample_ids  host, int64 [n_sample], distinct ids in [0,n): the points whose
  *               projections give the interior breakpoints. floor(n_sample/Nr) >= 1.
+ *               NULL: the library draws min(n, max(ceil(sample_frac * n), Nr^2)) distinct
+ *               ids uniformly from `seed` (n_sample is then ignored).
+ *   sample_frac fraction of n sampled when sample_ids is NULL, in (0, 1] (Section 3.1
+ *               uses 0.1); ignored otherwise.
+ *   seed        seed of the library's draws (used only where proj or sample_ids is NULL).
  *   lowp_copies bit mask: (1u<<PDET_BF16) and/or (1u<<PDET_FP8_E4M3) build the
  *               low-precision copies of the data used by those verification forms.
  *   encoding    PDET_ENC_DYNAMIC (0): interior breakpoints are the order statistics of the
@@ -76,14 +82,31 @@ typedef struct {
   int64_t n_sample;
   uint32_t lowp_copies;
   int32_t encoding;
+  double sample_frac;
+  uint64_t seed;
 } pdet_build_params;
+
+/*
+ * The library's seeded draws for pdet_build (host only, no device): proj (if not NULL)
+ * receives float32 [d][L*K] entries i.i.d. N(0,1) (mt19937_64 from `seed`, Box-Muller on
+ * 53-bit uniforms, row-major order); *n_sample receives min(n, max(ceil(sample_frac * n),
+ * Nr^2)); sample_ids (if not NULL) receives that many distinct ids in [0, n), ascending,
+ * uniformly drawn (Floyd's algorithm on a second stream of the same seed). A build with
+ * proj or sample_ids NULL uses exactly these draws, and exports them (PDET_X_PROJ,
+ * PDET_X_SAMPLE). EINVAL for n < 1, d < 1, L or K outside [1,16], Nr outside [2,256], or
+ * sample_frac outside (0, 1].
+ */
+pdet_status pdet_draw_params(int64_t n, int32_t d, int32_t L, int32_t K, int32_t Nr,
+                             double sample_frac, uint64_t seed, float* proj,
+                             int64_t* sample_ids, int64_t* n_sample);
 
 /*
  * Build an index over `data` (device, float32 [n][d] row-major, n < 2^28).
  * The data pointer is BORROWED: it must stay allocated and unchanged until
  * pdet_free(), because verification reads it. Everything derived from it
  * (breakpoints, codes, trees, low-precision copies) is owned by the index.
- * Errors: EUNSUPPORTED for n >= 2^28, L*K*n_sample (rounded up to a power of two)
+ * Errors: EINVAL if the data holds a non-finite value (found by the encoder; nothing is
+ * returned); EUNSUPPORTED for n >= 2^28, L*K*n_sample (rounded up to a power of two)
  * >= 2^32, or a tree with 2^24 leaves or more; EINVAL for
  * n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power of two in [2,256],
  * max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range, an unknown encoding;
@@ -288,11 +311,14 @@ pdet_status pdet_info(const pdet_index* idx, pdet_index_info* out);
  *   PDET_X_LEAF_HIDX   uint16 [leaves][16] for `tree`: (1 << t_j) | prefix_j, where the
  *                      leaf fixes the t_j leading bits prefix_j of dimension j's code.
  *   PDET_X_LEAF_OF     int32 [n] for `tree`: the leaf ordinal of every point id.
+ *   PDET_X_PROJ        float32 [d][L*K]: the projection the index uses (given or drawn).
+ *   PDET_X_SAMPLE      int64 [n_sample]: the sampled ids (given or drawn).
  * `bytes` must equal the exact size; otherwise EINVAL. Synchronises the device.
  */
 enum {
   PDET_X_BREAKPOINTS = 0, PDET_X_CODES = 1, PDET_X_PERM = 2,
-  PDET_X_LEAF_START = 3, PDET_X_LEAF_COUNT = 4, PDET_X_LEAF_HIDX = 5, PDET_X_LEAF_OF = 6
+  PDET_X_LEAF_START = 3, PDET_X_LEAF_COUNT = 4, PDET_X_LEAF_HIDX = 5, PDET_X_LEAF_OF = 6,
+  PDET_X_PROJ = 7, PDET_X_SAMPLE = 8
 };
 pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void* host,
                         size_t bytes);

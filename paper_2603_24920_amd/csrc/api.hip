@@ -5,6 +5,7 @@
 #include <exception>
 #include <limits>
 #include <new>
+#include <random>
 
 #include "internal.h"
 
@@ -306,6 +307,67 @@ double pdet_epsilon(int32_t K, int32_t L) {
   return pdet::epsilon(K, L);
 }
 
+namespace {
+// The seeded draws of pdet_draw_params: two mt19937_64 streams of one seed (projection and
+// sample), Box-Muller normals from 53-bit uniforms in (0, 1), Floyd's algorithm for the
+// sample (a bit per id marks the drawn ones; the ids come out ascending).
+uint64_t bounded(std::mt19937_64& g, uint64_t range) {   // uniform in [0, range)
+  const uint64_t lim = ~uint64_t(0) - (~uint64_t(0) % range);
+  uint64_t x;
+  do { x = g(); } while (x >= lim);
+  return x % range;
+}
+
+int64_t sample_count(int64_t n, int32_t Nr, double frac) {
+  const int64_t want = std::max<int64_t>((int64_t)std::ceil(frac * (double)n), (int64_t)Nr * Nr);
+  return std::min<int64_t>(n, want);
+}
+
+void draw(int64_t n, int32_t d, int32_t LK, int32_t Nr, double frac, uint64_t seed, float* proj,
+          int64_t* ids, int64_t* n_sample) {
+  if (proj) {
+    std::mt19937_64 g(seed);
+    const double two_pi = 6.283185307179586;
+    auto unit = [&]() { return ((double)(g() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
+    const int64_t total = (int64_t)d * LK;
+    for (int64_t e = 0; e < total; e += 2) {
+      const double rad = std::sqrt(-2.0 * std::log(unit())), ang = two_pi * unit();
+      proj[e] = (float)(rad * std::cos(ang));
+      if (e + 1 < total) proj[e + 1] = (float)(rad * std::sin(ang));
+    }
+  }
+  const int64_t m = sample_count(n, Nr, frac);
+  if (n_sample) *n_sample = m;
+  if (ids) {
+    std::mt19937_64 g(seed ^ 0x9e3779b97f4a7c15ull);
+    std::vector<uint64_t> bits((size_t)((n + 63) / 64), 0);
+    auto has = [&](int64_t v) { return (bits[v >> 6] >> (v & 63)) & 1u; };
+    auto put = [&](int64_t v) { bits[v >> 6] |= uint64_t(1) << (v & 63); };
+    for (int64_t j = n - m; j < n; ++j) {
+      const int64_t t = (int64_t)bounded(g, (uint64_t)j + 1);
+      put(has(t) ? j : t);
+    }
+    int64_t at = 0;
+    for (int64_t v = 0; v < n; ++v)
+      if (has(v)) ids[at++] = v;
+  }
+}
+}  // namespace
+
+pdet_status pdet_draw_params(int64_t n, int32_t d, int32_t L, int32_t K, int32_t Nr,
+                             double sample_frac, uint64_t seed, float* proj,
+                             int64_t* sample_ids, int64_t* n_sample) {
+  return guarded([&] {
+    PDET_REQUIRE(n >= 1 && d >= 1, PDET_EINVAL, "n and d must be >= 1");
+    PDET_REQUIRE(L >= 1 && L <= PDET_MAX_L && K >= 1 && K <= PDET_MAX_K, PDET_EINVAL,
+                 "L and K must be in [1, 16]");
+    PDET_REQUIRE(Nr >= 2 && Nr <= 256, PDET_EINVAL, "Nr must be in [2, 256]");
+    PDET_REQUIRE(sample_frac > 0.0 && sample_frac <= 1.0, PDET_EINVAL,
+                 "sample_frac must be in (0, 1]");
+    draw(n, d, L * K, Nr, sample_frac, seed, proj, sample_ids, n_sample);
+  });
+}
+
 pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build_params* p,
                        void* stream, pdet_index** out) {
   if (out) *out = nullptr;
@@ -320,23 +382,40 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     PDET_REQUIRE(p->Nr >= 2 && p->Nr <= 256 && (p->Nr & (p->Nr - 1)) == 0, PDET_EINVAL,
                  "Nr must be a power of two in [2, 256]");
     PDET_REQUIRE(p->max_leaf >= 1, PDET_EINVAL, "max_leaf must be >= 1");
-    PDET_REQUIRE(p->proj && p->sample_ids, PDET_EINVAL, "proj and sample_ids are required");
-    PDET_REQUIRE(p->n_sample >= p->Nr && p->n_sample <= n, PDET_EINVAL,
+    if (!p->sample_ids)
+      PDET_REQUIRE(p->sample_frac > 0.0 && p->sample_frac <= 1.0, PDET_EINVAL,
+                   "sample_frac must be in (0, 1] when sample_ids is NULL");
+    const int64_t n_sample =
+        p->sample_ids ? p->n_sample : sample_count(n, p->Nr, p->sample_frac);
+    PDET_REQUIRE(n_sample >= p->Nr && n_sample <= n, PDET_EINVAL,
                  "n_sample must be in [Nr, n]");
     PDET_REQUIRE((p->lowp_copies & ~((1u << PDET_BF16) | (1u << PDET_FP8_E4M3))) == 0,
                  PDET_EINVAL, "unknown lowp_copies bit");
     PDET_REQUIRE(p->encoding == PDET_ENC_DYNAMIC || p->encoding == PDET_ENC_STATIC, PDET_EINVAL,
                  "unknown encoding");
-    for (int64_t i = 0; i < p->n_sample; ++i)
-      PDET_REQUIRE(p->sample_ids[i] >= 0 && p->sample_ids[i] < n, PDET_EINVAL,
-                   "sample id out of range");
+    if (p->sample_ids)
+      for (int64_t i = 0; i < n_sample; ++i)
+        PDET_REQUIRE(p->sample_ids[i] >= 0 && p->sample_ids[i] < n, PDET_EINVAL,
+                     "sample id out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     ix = new pdet_index();
     ix->n = n; ix->d = d; ix->K = p->K; ix->L = p->L; ix->Nr = p->Nr;
     ix->bits = ilog2(p->Nr);
     ix->max_leaf = p->max_leaf;
-    ix->n_sample = p->n_sample;
+    ix->n_sample = n_sample;
+    // the projection and the sample, given or drawn, kept for export
+    ix->proj_host.resize((size_t)d * p->L * p->K);
+    if (p->proj)
+      std::copy(p->proj, p->proj + ix->proj_host.size(), ix->proj_host.begin());
+    else
+      draw(n, d, p->L * p->K, p->Nr, 1.0, p->seed, ix->proj_host.data(), nullptr, nullptr);
+    ix->sample_host.resize((size_t)n_sample);
+    if (p->sample_ids)
+      std::copy(p->sample_ids, p->sample_ids + n_sample, ix->sample_host.begin());
+    else
+      draw(n, d, p->L * p->K, p->Nr, p->sample_frac, p->seed, nullptr, ix->sample_host.data(),
+           nullptr);
     ix->lowp = p->lowp_copies;
     ix->X = data;
     ix->dpad = ((d + 15) / 16) * 16;
@@ -347,13 +426,14 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     const int LK = ix->L * ix->K;
 
     // projection matrix and sampled projections
-    const std::vector<float> Ap = pad_projection(p->proj, d, ix->L, ix->K);
+    const std::vector<float> Ap = pad_projection(ix->proj_host.data(), d, ix->L, ix->K);
     ix->A.alloc(Ap.size() * 4);
     PDET_HIP(hipMemcpyAsync(ix->A.p, Ap.data(), Ap.size() * 4, hipMemcpyHostToDevice, s));
     std::vector<PooledBuf> temps;   // build temporaries, held until the final synchronisation
-    PooledBuf sid((size_t)p->n_sample * 8);
-    PDET_HIP(hipMemcpyAsync(sid.ptr(), p->sample_ids, sid.bytes(), hipMemcpyHostToDevice, s));
-    PooledBuf ps((size_t)LK * p->n_sample * 4);   // sampled hash values, column-major
+    PooledBuf sid((size_t)n_sample * 8);
+    PDET_HIP(hipMemcpyAsync(sid.ptr(), ix->sample_host.data(), sid.bytes(), hipMemcpyHostToDevice,
+                            s));
+    PooledBuf ps((size_t)LK * n_sample * 4);   // sampled hash values, column-major
     pdet_timing& tm = timer().t;
     if (timer().on) {
       tm.build_sample_ms = tm.build_sort_ms = tm.build_encode_ms = 0.0;
@@ -362,22 +442,24 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     ix->B.alloc((size_t)LK * (ix->Nr + 1) * 4);
     {
       Span sp(s, &tm.build_sample_ms);
-      project_sample(*ix, sid.as<int64_t>(), p->n_sample, ps.as<float>(), p->n_sample, s);
+      project_sample(*ix, sid.as<int64_t>(), n_sample, ps.as<float>(), n_sample, s);
       sp.finish();
     }
     {
       Span sp(s, &tm.build_sort_ms);
       if (p->encoding == PDET_ENC_STATIC)
-        static_breakpoints(ps.as<float>(), LK, p->n_sample, p->n_sample, ix->Nr,
+        static_breakpoints(ps.as<float>(), LK, n_sample, n_sample, ix->Nr,
                            ix->B.as<float>(), temps, s);
       else
-        select_breakpoints(ps.as<float>(), LK, p->n_sample, p->n_sample, ix->Nr,
+        select_breakpoints(ps.as<float>(), LK, n_sample, n_sample, ix->Nr,
                            ix->B.as<float>(), temps, s);
       sp.finish();
     }
 
     // encode every point; column extremes give the outer breakpoints
     ix->colmm.alloc((size_t)2 * LK * 4);
+    ix->nonfinite.alloc(4);
+    PDET_HIP(hipMemsetAsync(ix->nonfinite.p, 0, 4, s));
     PDET_HIP(hipMemsetAsync(ix->colmm.p, 0xff, (size_t)LK * 4, s));
     PDET_HIP(hipMemsetAsync(ix->colmm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));
     ix->codes.alloc((size_t)ix->L * n * KP);
@@ -404,6 +486,9 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     }
     PDET_HIP(hipStreamSynchronize(s));
     flush_timing();
+    uint32_t nonfinite = 0;
+    PDET_HIP(hipMemcpy(&nonfinite, ix->nonfinite.p, 4, hipMemcpyDeviceToHost));
+    PDET_REQUIRE(nonfinite == 0, PDET_EINVAL, "the data holds non-finite values");
     *out = ix;
     ix = nullptr;
   });
@@ -503,7 +588,7 @@ pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void*
     PDET_REQUIRE(idx && host, PDET_EINVAL, "NULL argument");
     const void* src = nullptr;
     size_t want = 0;
-    const bool per_tree = what >= PDET_X_PERM;
+    const bool per_tree = what >= PDET_X_PERM && what <= PDET_X_LEAF_OF;
     if (per_tree) PDET_REQUIRE(tree >= 0 && tree < idx->L, PDET_EINVAL, "tree out of range");
     switch (what) {
       case PDET_X_BREAKPOINTS:
@@ -518,6 +603,16 @@ pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void*
         src = idx->leaf_count[tree].p; want = (size_t)idx->nl[tree] * 4; break;
       case PDET_X_LEAF_HIDX:
         src = idx->leaf_hidx[tree].p; want = (size_t)idx->nl[tree] * KP * 2; break;
+      case PDET_X_PROJ:
+      case PDET_X_SAMPLE: {   // host copies
+        const bool pj = what == PDET_X_PROJ;
+        want = pj ? idx->proj_host.size() * 4 : idx->sample_host.size() * 8;
+        PDET_REQUIRE(bytes == want, PDET_EINVAL,
+                     "export size mismatch: expected " + std::to_string(want) + " bytes");
+        if (pj) std::copy(idx->proj_host.begin(), idx->proj_host.end(), static_cast<float*>(host));
+        else std::copy(idx->sample_host.begin(), idx->sample_host.end(), static_cast<int64_t*>(host));
+        return;
+      }
       case PDET_X_LEAF_OF: {
         // from the first tree's permutation and leaf rows: the point at position p of
         // tree 0 is perm_0[p], and its leaf in `tree` is leafrow[0][p][tree]

@@ -49,10 +49,13 @@ struct pdet_index {
   int num_cus = 256;
   int device = 0;
   const float* X = nullptr;        // borrowed float32 [n][d]
+  std::vector<float> proj_host;    // the projection [d][L*K] (given or drawn)
+  std::vector<int64_t> sample_host;   // the sampled ids (given or drawn)
 
   pdet::DevBuf A;                  // float32 padded projection, see pad_projection()
   pdet::DevBuf B;                  // float32 [L*K][Nr+1] breakpoints
   pdet::DevBuf colmm;              // uint32 [2][L*K] ordered min / max of every column
+  pdet::DevBuf nonfinite;          // uint32: set by the encoder if a projection is not finite
   pdet::DevBuf codes;              // uint8 [L][n][KP]
   mutable pdet::DevBuf H;          // float32 [n][L*K] hash values (first literal query, kept)
   mutable std::mutex hash_mu;

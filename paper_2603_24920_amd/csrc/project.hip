@@ -44,6 +44,7 @@ struct ProjArgs {
   int64_t n;
   uint32_t* colmin;        // [L*K] ordered-uint min / max
   uint32_t* colmax;
+  uint32_t* nonfinite;     // set to 1 if some projection is NaN or infinite
 };
 
 template <int NT, bool VEC4, int MODE>
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
   float vmin[NT], vmax[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) { vmin[t] = INFINITY; vmax[t] = -INFINITY; }
+  bool nonfin = false;   // a projection of this lane's points was NaN or infinite
 
   const int64_t ntiles = (a.m + 15) / 16;
   const int64_t tiles_per_iter = (int64_t)gridDim.x * PROJ_WAVES;
@@ -194,7 +196,11 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
             int node = 1;
             for (int step = 0; step < a.bits; ++step) node = 2 * node + (tab[node] <= h ? 1 : 0);
             code = static_cast<uint8_t>(node - a.Nr);
-            if (pbase + i < a.m) { vmin[t] = fminf(vmin[t], h); vmax[t] = fmaxf(vmax[t], h); }
+            if (pbase + i < a.m) {
+              vmin[t] = fminf(vmin[t], h);
+              vmax[t] = fmaxf(vmax[t], h);
+              nonfin = nonfin || !isfinite(h);
+            }
           }
           st[(pl * NT + t) * KP + col16] = code;
         }
@@ -220,6 +226,7 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
   }
 
   if constexpr (MODE == MODE_ENCODE) {
+    if (__ballot(nonfin) && lane == 0) atomicOr(a.nonfinite, 1u);
     // column min / max over all points (outer breakpoints B(1), B(Nr+1))
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -295,6 +302,7 @@ void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* r
     a.flkey = ix.flkey.as<uint16_t>();
     a.colmin = ix.colmm.as<uint32_t>();
     a.colmax = ix.colmm.as<uint32_t>() + ix.L * ix.K;
+    a.nonfinite = ix.nonfinite.as<uint32_t>();
     // A is stored per launch group: [group][d][NC]
     a.A = ix.A.as<float>() + (int64_t)(t0 / TREES_PER_LAUNCH) * ix.d * (TREES_PER_LAUNCH * 16);
     const int NC = nt * 16;

@@ -8,7 +8,8 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+from ctypes import (POINTER, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_uint64,
+                    c_void_p)
 
 import numpy as np
 
@@ -21,8 +22,9 @@ MAX_K, MAX_L, MAX_TOPK, MAX_ROUNDS = 16, 16, 1024, 255
 QSTAT_WORDS = 10
 QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits=7,
              band_leaf=8, band_stop_b=9)
-X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF = range(7)
-EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_literal", "pdet_rc_ann", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
+(X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF,
+ X_PROJ, X_SAMPLE) = range(9)
+EXPORTED = ["pdet_draw_params", "pdet_build", "pdet_free", "pdet_query", "pdet_query_literal", "pdet_rc_ann", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
             "pdet_epsilon", "pdet_theoretical_beta", "pdet_normal_quantile", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -34,7 +36,8 @@ EXPORTED = ["pdet_build", "pdet_free", "pdet_query", "pdet_query_literal", "pdet
 class BuildParams(ctypes.Structure):
     _fields_ = [("K", c_int32), ("L", c_int32), ("Nr", c_int32), ("max_leaf", c_int32),
                 ("proj", POINTER(c_float)), ("sample_ids", POINTER(c_int64)),
-                ("n_sample", c_int64), ("lowp_copies", c_uint32), ("encoding", c_int32)]
+                ("n_sample", c_int64), ("lowp_copies", c_uint32), ("encoding", c_int32),
+                ("sample_frac", c_double), ("seed", c_uint64)]
 
 
 ENCODINGS = {"dynamic": 0, "static": 1}
@@ -96,6 +99,8 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         L.pdet_build.argtypes = [c_void_p, c_int64, c_int32, POINTER(BuildParams), c_void_p,
                                  POINTER(c_void_p)]
+        L.pdet_draw_params.argtypes = [c_int64, c_int32, c_int32, c_int32, c_int32, c_double,
+                                       c_uint64, c_void_p, c_void_p, POINTER(c_int64)]
         L.pdet_query.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams), c_void_p,
                                  c_void_p, c_void_p, c_void_p]
         L.pdet_query_candidates.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
@@ -147,7 +152,7 @@ def lib() -> ctypes.CDLL:
         L.pdet_server_offer_poisson.restype = c_int32
         L.pdet_server_free.argtypes = [c_void_p]
         L.pdet_server_free.restype = None
-        for f in ("pdet_build", "pdet_query", "pdet_query_candidates", "pdet_query_noalloc",
+        for f in ("pdet_draw_params", "pdet_build", "pdet_query", "pdet_query_candidates", "pdet_query_noalloc",
                   "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
                   "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
                   "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -160,6 +165,19 @@ def lib() -> ctypes.CDLL:
 def _check(status):
     if status != PDET_OK:
         raise PdetError(status, lib().pdet_last_error().decode())
+
+
+def draw_params(n: int, d: int, L: int, K: int, Nr: int = 256, sample_frac: float = 0.1,
+                seed: int = 0):
+    """The library's seeded projection (float32 [d][L*K]) and sample ids (int64, ascending):
+    the ones pdet_build draws when it is given neither (pdet_draw_params)."""
+    m = c_int64()
+    _check(lib().pdet_draw_params(n, d, L, K, Nr, sample_frac, seed, None, None, ctypes.byref(m)))
+    proj = np.empty((d, L * K), dtype=np.float32)
+    ids = np.empty((m.value,), dtype=np.int64)
+    _check(lib().pdet_draw_params(n, d, L, K, Nr, sample_frac, seed, proj.ctypes.data_as(c_void_p),
+                                  ids.ctypes.data_as(c_void_p), ctypes.byref(m)))
+    return proj, ids
 
 
 def epsilon(K: int, L: int) -> float:
@@ -202,24 +220,30 @@ def _stream(stream=None):
 class Index:
     """A DE-Tree index resident on the GPU. ``X`` (CUDA float32 [n][d]) is borrowed."""
 
-    def __init__(self, X, proj, sample_ids, K=16, L=4, Nr=256, max_leaf=128, lowp=(),
-                 stream=None, encoding="dynamic"):
+    def __init__(self, X, proj=None, sample_ids=None, K=16, L=4, Nr=256, max_leaf=128, lowp=(),
+                 stream=None, encoding="dynamic", sample_frac=0.1, seed=0):
+        """``proj`` (float32 [d][L*K]) and ``sample_ids`` (int64) may be None: the library
+        then draws them from ``seed`` (and ``sample_frac``), as draw_params does."""
         import torch
         if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
                 and X.dim() == 2 and X.is_contiguous()):
             raise ValueError("X must be a contiguous CUDA float32 [n][d] tensor")
         self.X = X
         self.n, self.d = X.shape
-        self._proj = np.ascontiguousarray(proj, dtype=np.float32)
-        self._sample = np.ascontiguousarray(sample_ids, dtype=np.int64)
-        if self._proj.shape != (self.d, L * K):
-            raise ValueError("proj must be [d][L*K]")
+        pp, sp, ns = None, None, 0
+        if proj is not None:
+            self._proj = np.ascontiguousarray(proj, dtype=np.float32)
+            if self._proj.shape != (self.d, L * K):
+                raise ValueError("proj must be [d][L*K]")
+            pp = self._proj.ctypes.data_as(POINTER(c_float))
+        if sample_ids is not None:
+            self._sample = np.ascontiguousarray(sample_ids, dtype=np.int64)
+            sp, ns = self._sample.ctypes.data_as(POINTER(c_int64)), len(self._sample)
         mask = 0
         for name in lowp:
             mask |= 1 << PRECISIONS[name]
-        p = BuildParams(K, L, Nr, max_leaf, self._proj.ctypes.data_as(POINTER(c_float)),
-                        self._sample.ctypes.data_as(POINTER(c_int64)), len(self._sample), mask,
-                        ENCODINGS[encoding])
+        p = BuildParams(K, L, Nr, max_leaf, pp, sp, ns, mask, ENCODINGS[encoding],
+                        float(sample_frac), int(seed))
         h = c_void_p()
         _check(lib().pdet_build(c_void_p(X.data_ptr()), self.n, self.d, ctypes.byref(p),
                                 _stream(stream), ctypes.byref(h)))
@@ -262,6 +286,8 @@ class Index:
             X_LEAF_COUNT: ((nl[tree],), np.int32),
             X_LEAF_HIDX: ((nl[tree], 16), np.uint16),
             X_LEAF_OF: ((self.n,), np.int32),
+            X_PROJ: ((self.d, self.L * self.K), np.float32),
+            X_SAMPLE: ((self.info()["n_sample"],), np.int64),
         }[what]
         out = np.empty(shape, dtype=dt)
         _check(lib().pdet_export(self._h, what, tree, out.ctypes.data_as(c_void_p), out.nbytes))

@@ -146,3 +146,64 @@ def test_build_rejects_unknown_encoding():
     st = pdet.lib().pdet_build(ctypes.c_void_p(4096), 1000, 8, ctypes.byref(p), None,
                                ctypes.byref(h))
     assert st == pdet.PDET_EINVAL and b"encoding" in pdet.lib().pdet_last_error()
+
+
+def test_draw_params_is_seeded_and_has_the_stated_shapes():
+    p1, s1 = pdet.draw_params(100000, 64, 4, 16, Nr=64, sample_frac=0.1, seed=7)
+    p2, s2 = pdet.draw_params(100000, 64, 4, 16, Nr=64, sample_frac=0.1, seed=7)
+    p3, s3 = pdet.draw_params(100000, 64, 4, 16, Nr=64, sample_frac=0.1, seed=8)
+    assert p1.shape == (64, 64) and p1.dtype == np.float32
+    assert np.array_equal(p1, p2) and np.array_equal(s1, s2)
+    assert not np.array_equal(p1, p3) and not np.array_equal(s1, s3)
+    # min(n, max(ceil(frac * n), Nr^2)) distinct ids, ascending, in range
+    assert len(s1) == 10000
+    assert np.all(np.diff(s1) > 0) and s1[0] >= 0 and s1[-1] < 100000
+    _, s = pdet.draw_params(100000, 8, 1, 1, Nr=256, sample_frac=0.01, seed=1)
+    assert len(s) == 256 * 256
+    _, s = pdet.draw_params(1000, 8, 1, 1, Nr=256, sample_frac=0.5, seed=1)
+    assert np.array_equal(s, np.arange(1000))
+    _, s = pdet.draw_params(5000, 8, 1, 1, Nr=2, sample_frac=1.0, seed=3)
+    assert np.array_equal(s, np.arange(5000))
+
+
+def test_drawn_projection_entries_are_standard_normal():
+    # Eq. 1 asks for i.i.d. N(0, 1) entries: Kolmogorov-Smirnov against the normal law
+    from scipy import stats
+    proj, _ = pdet.draw_params(1000, 512, 16, 16, seed=11)
+    v = proj.astype(np.float64).ravel()
+    assert stats.kstest(v, "norm").pvalue > 1e-3
+    assert abs(v.mean()) < 0.01 and abs(v.var() - 1.0) < 0.01
+    # neighbouring entries (the two outputs of one Box-Muller pair) are uncorrelated
+    assert abs(np.corrcoef(v[0::2], v[1::2])[0, 1]) < 0.01
+
+
+def test_drawn_sample_is_uniform_over_the_ids():
+    # every id is drawn with probability m / n; over 400 seeds the counts follow a binomial law
+    n, m, runs = 2000, 100, 400
+    hits = np.zeros(n)
+    for seed in range(runs):
+        _, s = pdet.draw_params(n, 4, 1, 1, Nr=8, sample_frac=m / n, seed=seed)
+        assert len(s) == m and len(np.unique(s)) == m
+        hits[s] += 1
+    from scipy import stats
+    expect = runs * m / n
+    chi2 = ((hits - expect) ** 2 / expect).sum()
+    assert stats.chi2.sf(chi2, n - 1) > 1e-3
+    # halves of the id range are drawn equally often (no bias toward the Floyd tail)
+    assert abs(hits[: n // 2].sum() - hits[n // 2:].sum()) < 4 * math.sqrt(runs * m)
+
+
+def test_draw_params_rejects_invalid_arguments():
+    L = pdet.lib()
+    m = ctypes.c_int64()
+    for args in [(0, 8, 1, 1, 256, 0.1), (1000, 0, 1, 1, 256, 0.1), (1000, 8, 17, 1, 256, 0.1),
+                 (1000, 8, 1, 0, 256, 0.1), (1000, 8, 1, 1, 1, 0.1), (1000, 8, 1, 1, 256, 0.0),
+                 (1000, 8, 1, 1, 256, 1.5), (1000, 8, 1, 1, 256, float("nan"))]:
+        assert L.pdet_draw_params(*args, 0, None, None, ctypes.byref(m)) == pdet.PDET_EINVAL, args
+
+
+def test_build_without_sample_ids_needs_a_sample_fraction():
+    p, keep = _params(sample_ids=None, n_sample=0, sample_frac=0.0)
+    h = ctypes.c_void_p(1234)
+    st = pdet.lib().pdet_build(ctypes.c_void_p(4096), 1000, 8, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == pdet.PDET_EINVAL
