@@ -109,7 +109,8 @@ pdet_status pdet_draw_params(int64_t n, int32_t d, int32_t L, int32_t K, int32_t
  * returned); EUNSUPPORTED for n >= 2^28, L*K*n_sample (rounded up to a power of two)
  * >= 2^32, or a tree with 2^24 leaves or more; EINVAL for
  * n < 1, d < 1, K outside [1,16], L outside [1,16], Nr not a power of two in [2,256],
- * max_leaf < 1, NULL proj/sample_ids, n_sample < Nr, ids out of range, an unknown encoding;
+ * max_leaf < 1, NULL sample_ids with sample_frac outside (0, 1], n_sample < Nr, ids out of
+ * range, an unknown encoding;
  * ENOMEM/EDEVICE from the runtime. On error *out is NULL.
  * Synchronises `stream` once (to size the leaf tables), and once more with the static
  * encoding (the column moments go to the host, which evaluates Phi^-1).
@@ -119,6 +120,28 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
 
 /* Release an index and all device memory it owns. NULL is a no-op. */
 void pdet_free(pdet_index* idx);
+
+/*
+ * Online insertion (Algorithm 2's insertion loop, Section 3.2): rows idx->n .. n_total-1 of
+ * `data` (device, float32 [n_total][d]; its first idx->n rows must be the indexed points,
+ * unchanged) are inserted into every tree, one point at a time in row order. A point goes
+ * to the leaf whose region holds its code (encoded with the index's interior breakpoints;
+ * the outer ones widen to the new column extremes); while that leaf holds max_leaf points
+ * or more and is not fully refined, it is split on the dimension the node-split rule picks
+ * over the points it holds, and the point follows its bit. The resident tree before the
+ * first insertion is the bulk tree with the empty children of its splits kept as empty
+ * leaves (and every first-layer node present); empty leaves never appear in the exported
+ * leaf tables. Afterwards the index borrows `data` (the old pointer is no longer read),
+ * n = n_total, and the codes, permutations, leaf tables and low-precision copies cover
+ * every point; the sample and the interior breakpoints stay as built.
+ * n_total == idx->n only replaces the data pointer.
+ * Must not overlap any other call on the index. EINVAL: NULL idx or data, n_total < n, a
+ * live plan or server on the index (free them first), or non-finite values in the new
+ * rows (then the index is unchanged); EUNSUPPORTED: n_total >= 2^28, a tree with 2^24
+ * leaves or more, or a batch whose work area exceeds 2^31 leaf records; ENOMEM / EDEVICE
+ * from the runtime (after such an error the index must be freed). Synchronises `stream`.
+ */
+pdet_status pdet_insert(pdet_index* idx, const float* data, int64_t n_total, void* stream);
 
 /*
  * Query parameters (c^2-k-ANN query, Algorithm 5, Section 3.3).

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpdet.so")
 SOURCES = ["api.hip", "project.hip", "sort.hip", "tree.hip", "query.hip", "lowp.hip", "serve.hip",
-           "noalloc.hip", "literal.hip"]
+           "noalloc.hip", "literal.hip", "insert.hip"]
 ARCH = os.environ.get("PDET_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

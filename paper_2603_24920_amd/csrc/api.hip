@@ -498,6 +498,20 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
 
 void pdet_free(pdet_index* idx) { delete idx; }
 
+pdet_status pdet_insert(pdet_index* idx, const float* data, int64_t n_total, void* stream) {
+  return guarded([&] {
+    PDET_REQUIRE(idx && data, PDET_EINVAL, "NULL argument");
+    PDET_REQUIRE(n_total >= idx->n, PDET_EINVAL, "n_total is below the indexed count");
+    PDET_REQUIRE(n_total < (int64_t(1) << 28), PDET_EUNSUPPORTED, "n must be below 2^28");
+    PDET_REQUIRE(idx->users.load() == 0, PDET_EINVAL,
+                 "the index has live plans or servers (free them before inserting)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n_total > idx->n) insert_points(*idx, data, n_total, s);
+    idx->X = data;
+    flush_timing();
+  });
+}
+
 pdet_status pdet_query(const pdet_index* idx, const float* queries, int64_t nq,
                        const pdet_query_params* p, int64_t* ids, float* dists, int32_t* qstats,
                        void* stream) {

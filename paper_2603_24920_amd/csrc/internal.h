@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <memory>
 #include <mutex>
@@ -82,6 +83,14 @@ struct pdet_index {
   pdet::DevBuf xfp8;               // fp8 e4m3 [n][dpad]
   pdet::DevBuf xscale;             // float32 [n]: fp8 row scale (power of two)
 
+  // online insertion (absent until the first pdet_insert): the empty leaves of every
+  // first-layer node an insertion has touched, in CSR order of (tree, first-layer key)
+  pdet::DevBuf empt;               // pdet::EmptyRec [n_empty]
+  pdet::DevBuf eoff;               // uint32 [L * 2^K + 1]
+  pdet::DevBuf emat;               // uint8 [L * 2^K]: 1 where the empty leaves are stored
+  int64_t n_empty = 0;
+  mutable std::atomic<int> users{0};   // live plans and servers (an insertion needs none)
+
   // query workspaces: one per concurrent pdet_query call
   mutable std::mutex ws_mu;
   mutable std::vector<std::unique_ptr<pdet::QueryWorkspace>> ws_free;
@@ -90,6 +99,16 @@ struct pdet_index {
 };
 
 namespace pdet {
+// An empty leaf of a first-layer node (48 bytes): a split child that holds no point.
+struct EmptyRec {
+  int32_t local;      // its position among the node's leaves, empty ones included, depth first
+  int32_t tree, key, pad;
+  uint16_t h[KP];     // node id per dimension: (1 << refined bits) | their value; 0 beyond K
+};
+// Inserts rows ix.n .. n_total-1 of `data` (which also holds the indexed rows, unchanged)
+// into every tree; the index then borrows `data`.
+void insert_points(pdet_index& ix, const float* data, int64_t n_total, hipStream_t s);
+
 // Takes a workspace from the index's pool for the duration of one call.
 class WorkspaceLease {
  public:
@@ -115,6 +134,18 @@ class WorkspaceLease {
 
 namespace pdet {
 using Index = pdet_index;
+
+// Counts a plan or a server as a user of its index for as long as it lives.
+struct IndexUse {
+  const pdet_index* ix = nullptr;
+  void hold(const pdet_index* i) {
+    ix = i;
+    ix->users.fetch_add(1);
+  }
+  ~IndexUse() {
+    if (ix) ix->users.fetch_sub(1);
+  }
+};
 
 // Build temporaries come from a process-wide pool (api.hip): they go back only after the
 // build has synchronised its stream (or are freed if an error unwinds the build), so a later
@@ -173,6 +204,11 @@ void project_points(const Index& ix, const float* X, int64_t m, float* out, hipS
 void project_sample(const Index& ix, const int64_t* rows, int64_t m, float* out, int64_t ld,
                     hipStream_t s);
 void encode_points(const Index& ix, hipStream_t s);
+// Encodes the m rows of X (points being inserted) with the index's breakpoints into
+// codes [L][m][KP] and first-layer keys [L][m], widening the column extremes (ix.colmm) and
+// raising ix.nonfinite for a non-finite projection.
+void encode_rows(const Index& ix, const float* X, int64_t m, uint8_t* codes, uint16_t* keys,
+                 hipStream_t s);
 
 // sort.hip
 // Interior breakpoints B[col][u] (u = 1..Nr-1) of the sampled hash values keys[col][0..ns)
@@ -193,9 +229,27 @@ void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, in
 
 // tree.hip
 void build_trees(Index& ix, hipStream_t s);
+// Stable sort of each tree's n first-layer keys (LSD radix over 8-bit digits) carrying the
+// points' 16-byte code rows and ids (the position of each point). Sorted rows and ids end in
+// rows0 / ids0; `keys` is overwritten; start[tree][key] / end[tree][key] bound each key's run
+// (both 0 for absent keys). h8 / o8 are temporaries that must outlive the stream's work.
+void first_layer_sort(int L, int K, int64_t n, uint16_t* keys, const uint4* codes, uint4* rows0,
+                      int32_t* ids0, uint4* rows1, int32_t* ids1, uint16_t* keys1,
+                      uint32_t* start, uint32_t* end, PooledBuf& h8, PooledBuf& o8,
+                      DevBuf& scan_tmp, hipStream_t s);
+// The per-tree leaf tables, per-point leaf ordinals, leaf rows and group boxes of an index
+// whose perm (ix.perm, [L][ix.n]) is final, from the leaf records at their start positions
+// (cnt_at [L][n]: the leaf's size at its first position, 0 elsewhere; hidx_at [L][n][KP]).
+// ix.leafrow must be allocated ([L][n][L]). Waits for the stream before returning.
+void finish_trees(Index& ix, const uint32_t* cnt_at, const uint16_t* hidx_at, DevBuf& scan_tmp,
+                  hipStream_t s);
 
 // lowp.hip
 void build_lowp_copies(Index& ix, hipStream_t s);
+// After an insertion (ix.n and ix.X already the new ones): the copies grow to ix.n rows,
+// the first n_old copied, the rest converted; the old buffers move into `keep` (they must
+// outlive the stream's work).
+void extend_lowp_copies(Index& ix, int64_t n_old, std::vector<DevBuf>& keep, hipStream_t s);
 
 // query.hip
 struct QueryConfig {

@@ -71,4 +71,28 @@ void build_lowp_copies(Index& ix, hipStream_t s) {
   PDET_HIP(hipGetLastError());
 }
 
+void extend_lowp_copies(Index& ix, int64_t n_old, std::vector<DevBuf>& keep, hipStream_t s) {
+  const bool bf = ix.lowp & (1u << PDET_BF16);
+  const bool f8 = ix.lowp & (1u << PDET_FP8_E4M3);
+  const int64_t m = ix.n - n_old;
+  if ((!bf && !f8) || m <= 0) return;
+  auto grow = [&](DevBuf& b, size_t row_bytes) {
+    DevBuf nb((size_t)ix.n * row_bytes);
+    PDET_HIP(hipMemcpyAsync(nb.p, b.p, (size_t)n_old * row_bytes, hipMemcpyDeviceToDevice, s));
+    keep.push_back(std::move(b));
+    b = std::move(nb);
+  };
+  if (bf) grow(ix.xbf16, (size_t)ix.dpad * 2);
+  if (f8) {
+    grow(ix.xfp8, (size_t)ix.dpad);
+    grow(ix.xscale, 4);
+  }
+  const unsigned grid = (unsigned)std::min<int64_t>(cdiv(m, 4), LOWP_MAX_BLOCKS);
+  hipLaunchKernelGGL(lowp_rows, dim3(grid), dim3(256), 0, s, ix.X + n_old * ix.d, m, ix.d,
+                     ix.dpad, bf ? ix.xbf16.as<uint16_t>() + n_old * ix.dpad : nullptr,
+                     f8 ? ix.xfp8.as<uint8_t>() + n_old * ix.dpad : nullptr,
+                     f8 ? ix.xscale.as<float>() + n_old : nullptr);
+  PDET_HIP(hipGetLastError());
+}
+
 }  // namespace pdet

@@ -287,19 +287,22 @@ constexpr int TREES_PER_LAUNCH = 4;
 
 static int group_nt(int trees) { return trees <= 1 ? 1 : (trees <= 2 ? 2 : 4); }
 
+// Encoded rows go to codes [L][stride][KP] and keys [L][stride] (the index's own arrays
+// unless given).
 void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* rows, int mode,
-                    float* out, int64_t ld, hipStream_t s) {
+                    float* out, int64_t ld, hipStream_t s, uint8_t* codes = nullptr,
+                    uint16_t* keys = nullptr, int64_t stride = 0) {
   for (int t0 = 0; t0 < ix.L; t0 += TREES_PER_LAUNCH) {
     const int trees = std::min(TREES_PER_LAUNCH, ix.L - t0);
     const int nt = group_nt(trees);
     ProjArgs a{};
     a.X = X; a.m = m; a.d = ix.d; a.rows = rows;
     a.tree0 = t0; a.ntrees = trees; a.L = ix.L; a.K = ix.K; a.Nr = ix.Nr; a.bits = ix.bits;
-    a.n = ix.n;
+    a.n = codes ? stride : ix.n;
     a.out = out; a.ld = ld;
     a.Btab = ix.B.as<float>();
-    a.codes = ix.codes.as<uint8_t>();
-    a.flkey = ix.flkey.as<uint16_t>();
+    a.codes = codes ? codes : ix.codes.as<uint8_t>();
+    a.flkey = codes ? keys : ix.flkey.as<uint16_t>();
     a.colmin = ix.colmm.as<uint32_t>();
     a.colmax = ix.colmm.as<uint32_t>() + ix.L * ix.K;
     a.nonfinite = ix.nonfinite.as<uint32_t>();
@@ -327,6 +330,10 @@ void project_sample(const Index& ix, const int64_t* rows, int64_t m, float* out,
 }
 void encode_points(const Index& ix, hipStream_t s) {
   run_projection(ix, ix.X, ix.n, nullptr, MODE_ENCODE, nullptr, 0, s);
+}
+void encode_rows(const Index& ix, const float* X, int64_t m, uint8_t* codes, uint16_t* keys,
+                 hipStream_t s) {
+  run_projection(ix, X, m, nullptr, MODE_ENCODE, nullptr, 0, s, codes, keys, m);
 }
 
 // Padded device layout of A: for each group of 4 trees, [d][64] with column

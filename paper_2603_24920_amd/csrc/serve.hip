@@ -21,6 +21,7 @@ using namespace pdet;
 
 struct pdet_plan {
   const pdet_index* ix = nullptr;
+  IndexUse use;
   QueryWorkspace ws;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -96,6 +97,7 @@ struct pdet_server {
   };
 
   const pdet_index* ix = nullptr;
+  IndexUse use;
   pdet_server_params prm{};
   double eps = 0.0, r_min = 0.0;
   int64_t cap = 0;                 // queries per batch admitted by the memory budget
@@ -311,6 +313,7 @@ pdet_status pdet_plan_create(const pdet_index* idx, const float* queries, int64_
     PDET_REQUIRE(nq >= 1, PDET_EINVAL, "a plan needs at least one query");
     plan = new pdet_plan();
     plan->ix = idx;
+    plan->use.hold(idx);
     plan->nq = nq;
     hipStream_t cs = nullptr;
     PDET_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -379,6 +382,7 @@ pdet_status pdet_server_create(const pdet_index* idx, const pdet_server_params* 
     PDET_REQUIRE(r_min > 0.0, PDET_EINVAL, "r_min <= 0 needs a tuned index");
     sv = new pdet_server();
     sv->ix = idx;
+    sv->use.hold(idx);
     sv->prm = *p;
     sv->r_min = r_min;
     sv->eps = p->eps > 0.0 ? p->eps : epsilon(idx->K, idx->L);

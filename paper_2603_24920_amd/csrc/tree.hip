@@ -961,6 +961,40 @@ uint32_t* readback_words() {
 
 }  // namespace
 
+void first_layer_sort(int L, int K, int64_t n, uint16_t* keys, const uint4* codes, uint4* rows0,
+                      int32_t* ids0, uint4* rows1, int32_t* ids1, uint16_t* keys1,
+                      uint32_t* start, uint32_t* end, PooledBuf& h8, PooledBuf& o8,
+                      DevBuf& scan_tmp, hipStream_t s) {
+  const int nblk = (int)cdiv(n, RK_TILE);
+  h8.alloc((size_t)L * 256 * nblk * 4);
+  o8.alloc((size_t)L * 256 * nblk * 4);
+  const dim3 grid((unsigned)nblk, (unsigned)L);
+  const bool two = K > 8;
+  // sorted keys: back in `keys` after two passes, in keys1 after one (a pass never writes
+  // the buffer it reads)
+  uint16_t* kfin = two ? keys : keys1;
+  hipLaunchKernelGGL(rk_hist<0>, grid, dim3(RK_THREADS), 0, s, keys, n, nblk, h8.as<uint32_t>());
+  PDET_HIP(hipGetLastError());
+  scan_rows(h8.as<uint32_t>(), o8.as<uint32_t>(), nullptr, L, (int64_t)256 * nblk, scan_tmp, s);
+  // one pass (K <= 8): straight to the final buffers; two: through buffer 1
+  hipLaunchKernelGGL((rk_scatter<0, true>), grid, dim3(RK_THREADS), 0, s, keys, codes, nullptr, n,
+                     nblk, o8.as<uint32_t>(), keys1, two ? rows1 : rows0, two ? ids1 : ids0);
+  PDET_HIP(hipGetLastError());
+  if (two) {
+    hipLaunchKernelGGL(rk_hist<8>, grid, dim3(RK_THREADS), 0, s, keys1, n, nblk,
+                       h8.as<uint32_t>());
+    PDET_HIP(hipGetLastError());
+    scan_rows(h8.as<uint32_t>(), o8.as<uint32_t>(), nullptr, L, (int64_t)256 * nblk, scan_tmp, s);
+    hipLaunchKernelGGL((rk_scatter<8, false>), grid, dim3(RK_THREADS), 0, s, keys1, rows1, ids1,
+                       n, nblk, o8.as<uint32_t>(), keys, rows0, ids0);
+    PDET_HIP(hipGetLastError());
+  }
+  PDET_HIP(hipMemsetAsync(start, 0, (size_t)L * ((size_t)1 << K) * 4, s));
+  PDET_HIP(hipMemsetAsync(end, 0, (size_t)L * ((size_t)1 << K) * 4, s));
+  hipLaunchKernelGGL(rk_bounds, dim3(cdiv(n, 256), L), dim3(256), 0, s, kfin, n, K, start, end);
+  PDET_HIP(hipGetLastError());
+}
+
 void build_trees(Index& ix, hipStream_t s) {
   const int64_t n = ix.n;
   const int L = ix.L, K = ix.K, bits = ix.bits;
@@ -970,8 +1004,6 @@ void build_trees(Index& ix, hipStream_t s) {
   ix.leafrow.alloc((size_t)L * n * L * 4);
   PooledBuf hist((size_t)L * NK * 4), off((size_t)L * NK * 4), cursor((size_t)L * NK * 4);
   DevBuf scan_tmp;
-  PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
-  PDET_HIP(hipMemsetAsync(cursor.ptr(), 0, cursor.bytes(), s));
   DevBuf rows0((size_t)L * n * KP);   // code rows in permutation order (buffer 0)
   Bufs bf{};
   bf.rows[0] = rows0.as<uint4>();
@@ -984,44 +1016,14 @@ void build_trees(Index& ix, hipStream_t s) {
   PooledBuf ids1((size_t)L * n * 4), keys1((size_t)L * n * 2);
   bf.rows[1] = rows1.as<uint4>();
   bf.ids[1] = ids1.as<int32_t>();
-  const int nblk = (int)cdiv(n, RK_TILE);
-  // (temporaries live until the final synchronisation, like every one of this function)
-  PooledBuf h8((size_t)L * 256 * nblk * 4), o8((size_t)L * 256 * nblk * 4);
-  {
-    const dim3 grid((unsigned)nblk, (unsigned)L);
-    uint16_t* fk = ix.flkey.as<uint16_t>();
-    const uint4* codes = reinterpret_cast<const uint4*>(ix.codes.as<uint8_t>());
-    const bool two = K > 8;
-    // sorted keys: back in the key buffer after two passes, in keys1 after one (a pass
-    // never writes the buffer it reads)
-    uint16_t* kfin = two ? fk : keys1.as<uint16_t>();
-    hipLaunchKernelGGL(rk_hist<0>, grid, dim3(RK_THREADS), 0, s, fk, n, nblk, h8.as<uint32_t>());
-    PDET_HIP(hipGetLastError());
-    scan_rows(h8.as<uint32_t>(), o8.as<uint32_t>(), nullptr, L, (int64_t)256 * nblk, scan_tmp, s);
-    // one pass (K <= 8): straight to the final buffers; two: through buffer 1
-    hipLaunchKernelGGL((rk_scatter<0, true>), grid, dim3(RK_THREADS), 0, s, fk, codes, nullptr, n,
-                       nblk, o8.as<uint32_t>(), keys1.as<uint16_t>(),
-                       two ? bf.rows[1] : bf.rows[0], two ? bf.ids[1] : bf.ids[0]);
-    PDET_HIP(hipGetLastError());
-    if (two) {
-      hipLaunchKernelGGL(rk_hist<8>, grid, dim3(RK_THREADS), 0, s, keys1.as<uint16_t>(), n, nblk,
-                         h8.as<uint32_t>());
-      PDET_HIP(hipGetLastError());
-      scan_rows(h8.as<uint32_t>(), o8.as<uint32_t>(), nullptr, L, (int64_t)256 * nblk, scan_tmp,
-                s);
-      hipLaunchKernelGGL((rk_scatter<8, false>), grid, dim3(RK_THREADS), 0, s,
-                         keys1.as<uint16_t>(), bf.rows[1], bf.ids[1], n, nblk, o8.as<uint32_t>(),
-                         fk, bf.rows[0], bf.ids[0]);
-      PDET_HIP(hipGetLastError());
-    }
-    PDET_HIP(hipMemsetAsync(off.ptr(), 0, off.bytes(), s));
-    hipLaunchKernelGGL(rk_bounds, dim3(cdiv(n, 256), L), dim3(256), 0, s, kfin, n, K,
-                       off.as<uint32_t>(), cursor.as<uint32_t>());
-    PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL(rk_counts, dim3(cdiv(L * NK, 256)), dim3(256), 0, s, off.as<uint32_t>(),
-                       cursor.as<uint32_t>(), L * NK, hist.as<uint32_t>());
-    PDET_HIP(hipGetLastError());
-  }
+  PooledBuf h8, o8;   // live until the final synchronisation, like every temporary here
+  first_layer_sort(L, K, n, ix.flkey.as<uint16_t>(),
+                   reinterpret_cast<const uint4*>(ix.codes.as<uint8_t>()), bf.rows[0], bf.ids[0],
+                   bf.rows[1], bf.ids[1], keys1.as<uint16_t>(), off.as<uint32_t>(),
+                   cursor.as<uint32_t>(), h8, o8, scan_tmp, s);
+  hipLaunchKernelGGL(rk_counts, dim3(cdiv(L * NK, 256)), dim3(256), 0, s, off.as<uint32_t>(),
+                     cursor.as<uint32_t>(), L * NK, hist.as<uint32_t>());
+  PDET_HIP(hipGetLastError());
 
   // leaf records at start positions
   PooledBuf cnt_at((size_t)L * n * 4), hidx_at((size_t)L * n * KP * 2);
@@ -1131,10 +1133,18 @@ void build_trees(Index& ix, hipStream_t s) {
     finish(std::integral_constant<int, LDS_SEG_CAP>{}, std::integral_constant<int, 512>{}, 3);
   }
 
+  finish_trees(ix, cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>(), scan_tmp, s);
+  ix.flkey.release();
+}
+
+void finish_trees(Index& ix, const uint32_t* cnt_at, const uint16_t* hidx_at, DevBuf& scan_tmp,
+                  hipStream_t s) {
+  const int64_t n = ix.n;
+  const int L = ix.L, K = ix.K, bits = ix.bits;
   // number the leaves in position (= depth-first) order
   PooledBuf flags((size_t)L * n * 4), totals((size_t)L * 4);
   hipLaunchKernelGGL(leaf_flags, dim3(cdiv((int64_t)L * n, 256)), dim3(256), 0, s,
-                     cnt_at.as<uint32_t>(), flags.as<uint32_t>(), (int64_t)L * n);
+                     cnt_at, flags.as<uint32_t>(), (int64_t)L * n);
   PDET_HIP(hipGetLastError());
   scan_rows(flags.as<uint32_t>(), flags.as<uint32_t>(), totals.as<uint32_t>(), L, n, scan_tmp, s);
   std::vector<uint32_t> nl(L);
@@ -1147,7 +1157,7 @@ void build_trees(Index& ix, hipStream_t s) {
   PDET_HIP(hipEventCreateWithFlags(&counts_ready, hipEventDisableTiming));
   PDET_HIP(hipEventRecord(counts_ready, s));
   PooledBuf leaf_of((size_t)n * L * 4);
-  hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
+  hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at,
                      flags.as<uint32_t>(), ix.perm.as<int32_t>(), n, L, leaf_of.as<int32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(leafrow_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s,
@@ -1184,14 +1194,14 @@ void build_trees(Index& ix, hipStream_t s) {
     t.box[i] = ix.box[i].as<float>();
     t.nl[i] = nl[i];
   }
-  hipLaunchKernelGGL(leaf_starts, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at.as<uint32_t>(),
+  hipLaunchKernelGGL(leaf_starts, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at,
                      flags.as<uint32_t>(), n, t);
   PDET_HIP(hipGetLastError());
   int64_t nl_max = 0;
   for (int i = 0; i < L; ++i) nl_max = std::max<int64_t>(nl_max, nl[i]);
   if (nl_max) {
     hipLaunchKernelGGL(leaf_fill, dim3(cdiv(nl_max, 256), L), dim3(256), 0, s,
-                       cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>(), n, K, bits, ix.Nr,
+                       cnt_at, hidx_at, n, K, bits, ix.Nr,
                        ix.B.as<float>(), t);
     PDET_HIP(hipGetLastError());
   }
@@ -1210,7 +1220,6 @@ void build_trees(Index& ix, hipStream_t s) {
     PDET_HIP(hipGetLastError());
   }
   PDET_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
-  ix.flkey.release();
 }
 
 }  // namespace pdet

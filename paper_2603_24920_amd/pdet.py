@@ -24,7 +24,7 @@ QSTAT = dict(rounds=0, ncand=1, stop=2, leaves=3, hsum=4, hmix=5, time=6, visits
              band_leaf=8, band_stop_b=9)
 (X_BREAKPOINTS, X_CODES, X_PERM, X_LEAF_START, X_LEAF_COUNT, X_LEAF_HIDX, X_LEAF_OF,
  X_PROJ, X_SAMPLE) = range(9)
-EXPORTED = ["pdet_draw_params", "pdet_build", "pdet_free", "pdet_query", "pdet_query_literal", "pdet_rc_ann", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
+EXPORTED = ["pdet_draw_params", "pdet_build", "pdet_insert", "pdet_free", "pdet_query", "pdet_query_literal", "pdet_rc_ann", "pdet_query_candidates", "pdet_query_noalloc", "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
             "pdet_epsilon", "pdet_theoretical_beta", "pdet_normal_quantile", "pdet_last_error", "pdet_set_timing", "pdet_get_timing",
             "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
             "pdet_plan_free", "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
                                  POINTER(c_void_p)]
         L.pdet_draw_params.argtypes = [c_int64, c_int32, c_int32, c_int32, c_int32, c_double,
                                        c_uint64, c_void_p, c_void_p, POINTER(c_int64)]
+        L.pdet_insert.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
         L.pdet_query.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams), c_void_p,
                                  c_void_p, c_void_p, c_void_p]
         L.pdet_query_candidates.argtypes = [c_void_p, c_void_p, c_int64, POINTER(QueryParams),
@@ -152,7 +153,7 @@ def lib() -> ctypes.CDLL:
         L.pdet_server_offer_poisson.restype = c_int32
         L.pdet_server_free.argtypes = [c_void_p]
         L.pdet_server_free.restype = None
-        for f in ("pdet_draw_params", "pdet_build", "pdet_query", "pdet_query_candidates", "pdet_query_noalloc",
+        for f in ("pdet_draw_params", "pdet_build", "pdet_insert", "pdet_query", "pdet_query_candidates", "pdet_query_noalloc",
                   "pdet_reserve", "pdet_info", "pdet_export", "pdet_project",
                   "pdet_autotune", "pdet_set_tuning", "pdet_plan_create", "pdet_plan_launch",
                   "pdet_server_create", "pdet_server_submit", "pdet_server_wait",
@@ -259,6 +260,17 @@ class Index:
             self._h = None
 
     __del__ = close
+
+    def insert(self, X, stream=None):
+        """Online insertion (pdet_insert): X (contiguous CUDA float32 [n_total][d]) holds the
+        indexed rows unchanged, then the new ones; the index borrows X from now on."""
+        import torch
+        if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
+                and X.dim() == 2 and X.is_contiguous() and X.shape[1] == self.d):
+            raise ValueError("X must be a contiguous CUDA float32 [n_total][d] tensor")
+        _check(lib().pdet_insert(self._h, c_void_p(X.data_ptr()), X.shape[0], _stream(stream)))
+        self.X = X
+        self.n = X.shape[0]
 
     def reserve(self, nq: int, stream=None):
         """Size the query workspace for batches of up to nq queries (pdet_reserve)."""

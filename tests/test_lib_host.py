@@ -207,3 +207,8 @@ def test_build_without_sample_ids_needs_a_sample_fraction():
     h = ctypes.c_void_p(1234)
     st = pdet.lib().pdet_build(ctypes.c_void_p(4096), 1000, 8, ctypes.byref(p), None, ctypes.byref(h))
     assert st == pdet.PDET_EINVAL
+
+
+def test_insert_rejects_null_arguments_before_touching_the_device():
+    L = pdet.lib()
+    assert L.pdet_insert(None, ctypes.c_void_p(4096), 10, None) == pdet.PDET_EINVAL
