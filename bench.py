@@ -7,7 +7,8 @@ projection + encoding of every point, the L DE-Trees) + answer the whole query b
 configuration (SIFT-like bytes, n = 100,000,000, d = 128, L = 4, K = 16, Nr = 256,
 10,000 queries, k = 10, c = 1.5; about 51 GB resident), followed by secondary blocks on
 the 1M-point configuration (10,000 queries, k = 50; with the literal query form beside the
-optimised one) and the 10M-point serving configuration (d = 256, unit-norm rows, FP8 and
+optimised one, the (encoding, L, K) study and online insertion of 1k / 10k / 100k points into
+an index of the remaining rows) and the 10M-point serving configuration (d = 256, unit-norm rows, FP8 and
 FP32 verification under Poisson load).
 
 Per workload, before the timed steps (untimed): ground truth for recall@10 is FP64 brute
@@ -45,6 +46,8 @@ POOL = 16                     # host worker processes (the GPU machine's CPU share)
 LITERAL_MAX_N = 4_000_000     # largest index on which the literal query form is timed
 # parameter study on indexes up to this size: (encoding, L, K) per configuration
 STUDY_MAX_N = 4_000_000
+INSERT_MAX_N = 4_000_000      # largest index grown by online insertion in the benchmark
+INSERT_BATCHES = (1_000, 10_000, 100_000)
 STUDY = (("dynamic", 4, 16), ("static", 4, 16), ("dynamic", 2, 16), ("dynamic", 8, 16),
          ("dynamic", 4, 8), ("dynamic", 4, 12))
 # per workload: low-precision forms measured, and the form of the graph-launched batch
@@ -323,6 +326,43 @@ def measure(w, args, primary, helper=None):
             ixs.close()
             del ixs
 
+    # online insertion (Algorithm 2's insertion loop into a resident index): an index of the
+    # first n - m rows grows by the last m rows in one call; each timed call starts from a
+    # fresh index (built untimed). The grown index is then queried at the calibrated beta.
+    insertion = None
+    if not args.no_insert and w.n <= INSERT_MAX_N:
+        insertion = []
+        for m in INSERT_BATCHES:
+            n0 = w.n - m
+            sid0 = sid[sid < n0]
+            secs = []
+            for it in range(args.warmup + args.steps):
+                ixg = pdet.Index(Xd[:n0], A, sid0, w.K, w.L, w.Nr, w.max_leaf)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                ixg.insert(Xd)
+                torch.cuda.synchronize()
+                if it >= args.warmup:
+                    secs.append(time.perf_counter() - t1)
+                if it < args.warmup + args.steps - 1:
+                    ixg.close()
+                    del ixg
+            sec = float(np.mean(secs))
+            rec = None
+            if exact_ids is not None:
+                gids, _ = ixg.query(Qr, k=w.k, c=w.c, beta=beta, r_min=r_min)
+                rec = recall_at(gids.cpu().numpy(), exact_ids)
+            # bytes the grown index's per-point arrays move: every tree's codes (16-byte rows)
+            # and permutation copied, and its leaf rows (4L bytes per point) written
+            ins_bytes = w.n * w.L * (32 + 8 + 4 * w.L) + m * w.d * 4
+            insertion.append(dict(m=m, n_resident=n0, ms_per_call=1e3 * sec,
+                                  inserted_pts_per_s=m / sec, recall_at_10_after=rec,
+                                  bytes_per_call=ins_bytes,
+                                  hbm_frac=ins_bytes / sec / 1e9 / HBM_PEAK_GBS))
+            log(f"[bench] {w.name} insertion {insertion[-1]}")
+            ixg.close()
+            del ixg
+
     # batching form: one graph-launched batch with k in {1,10,100}, c in {1.2,1.5,2.0}
     batching = None
     if not args.no_plan:
@@ -401,6 +441,7 @@ def measure(w, args, primary, helper=None):
         "lowp": lowp,
         "literal_vs_optimised": literal,
         "parameter_study": study,
+        "insertion": insertion,
         "batching": batching,
         "serving": serving,
     }
@@ -592,6 +633,8 @@ def main():
     ap.add_argument("--no-plan", action="store_true", help="skip the graph-launched batch")
     ap.add_argument("--no-study", action="store_true",
                     help="skip the (encoding, L, K) parameter study")
+    ap.add_argument("--no-insert", action="store_true",
+                    help="skip timing online insertion")
     ap.add_argument("--no-literal", action="store_true",
                     help="skip timing the literal query form beside the optimised one")
     ap.add_argument("--no-recall", action="store_true",

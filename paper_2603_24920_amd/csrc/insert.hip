@@ -63,6 +63,7 @@ struct InsArgs {
   const int32_t* leaf_start[PDET_MAX_L];
   const int32_t* leaf_count[PDET_MAX_L];
   const EmptyRec* empt;
+  uint32_t* worst;           // largest status over the nodes
   int64_t n_old, n_total, m;
   int K, bits, max_leaf;
 };
@@ -200,52 +201,72 @@ __global__ __launch_bounds__(64) void ins_subtree(InsArgs a) {
         ++len;
         continue;
       }
-      // an internal node: find its split
-      int msum = 0;
-      for (int l = na + lane; l < nb; l += 64) msum += LC[l];
-      msum = wave_sum_i(msum);
-      int best = -1, best_score = 0, best_n0 = 0;
-      int first = -1;
-      bool f_ok = false;
-      int f_bit = 0;
-      for (int j = 0; j < a.K; ++j) {
-        const uint32_t hj = h_at(h0, h1, j);
-        const int dep = depth_of(hj);
-        if (dep >= a.bits) continue;
-        bool notref = false, dec = false, any0 = false, any1 = false;
-        int c1 = 0, n0 = 0;
-        for (int l = na + lane; l < nb; l += 64) {
-          const uint32_t lh = LH[(int64_t)l * KP + j];
-          const int ld = depth_of(lh);
-          const bool ref = ld > dep;
-          const int bit = ref ? (int)((lh >> (ld - dep - 1)) & 1u) : 0;
-          notref = notref || !ref;
-          any0 = any0 || (ref && bit == 0);
-          any1 = any1 || (ref && bit == 1);
-          c1 += (ref && bit) ? LC[l] : 0;
-          n0 += (ref && bit == 0) ? 1 : 0;
-          if (l > na && ref && bit == 0) {
-            const uint32_t ph = LH[(int64_t)(l - 1) * KP + j];
-            const int pd = depth_of(ph);
-            if (pd > dep && ((ph >> (pd - dep - 1)) & 1u)) dec = true;
+      // an internal node: find its split. Per dimension (bit j of the masks): some leaf
+      // does not refine it further, some leaf has its next bit 0 / 1, a 1 precedes a 0;
+      // and the leaves' point counts (bit 1) and leaf counts (bit 0). Every leaf row is
+      // read once per node.
+      uint32_t unref_m = 0;
+#pragma unroll
+      for (int j = 0; j < KP; ++j)
+        if (j < a.K && depth_of(h_at(h0, h1, j)) < a.bits) unref_m |= 1u << j;
+      uint32_t notref_m = 0, any0_m = 0, any1_m = 0, dec_m = 0;
+      int c1[KP], n0[KP], msum = 0;
+#pragma unroll
+      for (int j = 0; j < KP; ++j) { c1[j] = 0; n0[j] = 0; }
+      for (int base = na; base < nb; base += 64) {
+        const int l = base + lane;
+        if (l < nb) {
+          uint4 r0, r1, p0 = make_uint4(0, 0, 0, 0), p1 = make_uint4(0, 0, 0, 0);
+          load_h(LH + (int64_t)l * KP, r0, r1);
+          if (l > na) load_h(LH + (int64_t)(l - 1) * KP, p0, p1);
+          const int cnt = LC[l];
+          msum += cnt;
+#pragma unroll
+          for (int j = 0; j < KP; ++j) {
+            if ((unref_m >> j) & 1u) {
+              const int dep = depth_of(h_at(h0, h1, j));
+              const uint32_t lh = h_at(r0, r1, j);
+              const int ld = depth_of(lh);
+              if (ld <= dep) {
+                notref_m |= 1u << j;
+              } else if ((lh >> (ld - dep - 1)) & 1u) {
+                any1_m |= 1u << j;
+                c1[j] += cnt;
+              } else {
+                any0_m |= 1u << j;
+                n0[j] += 1;
+                if (l > na) {
+                  const uint32_t ph = h_at(p0, p1, j);
+                  const int pd = depth_of(ph);
+                  if (pd > dep && ((ph >> (pd - dep - 1)) & 1u)) dec_m |= 1u << j;
+                }
+              }
+            }
           }
         }
-        notref = __ballot(notref) != 0;
-        dec = __ballot(dec) != 0;
-        any0 = __ballot(any0) != 0;
-        any1 = __ballot(any1) != 0;
-        c1 = wave_sum_i(c1);
-        n0 = wave_sum_i(n0);
-        if (first < 0) {
-          first = j;
-          f_ok = !notref && (any0 != any1);
-          f_bit = any1 ? 1 : 0;
-        }
-        if (!notref && !dec && any0 && any1) {
-          const int score = abs(2 * c1 - msum);
-          if (best < 0 || score < best_score) { best = j; best_score = score; best_n0 = n0; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        notref_m |= __shfl_xor(notref_m, o);
+        any0_m |= __shfl_xor(any0_m, o);
+        any1_m |= __shfl_xor(any1_m, o);
+        dec_m |= __shfl_xor(dec_m, o);
+      }
+      msum = wave_sum_i(msum);
+      const uint32_t cand = unref_m & ~notref_m & ~dec_m & any0_m & any1_m;
+      int best = -1, best_score = 0, best_n0 = 0;
+#pragma unroll
+      for (int j = 0; j < KP; ++j) {
+        if ((cand >> j) & 1u) {
+          const int cj = wave_sum_i(c1[j]), nj = wave_sum_i(n0[j]);
+          const int score = abs(2 * cj - msum);
+          if (best < 0 || score < best_score) { best = j; best_score = score; best_n0 = nj; }
         }
       }
+      const int first = unref_m ? __ffs((int)unref_m) - 1 : -1;
+      const bool f_ok = first >= 0 && !((notref_m >> first) & 1u) &&
+                        (((any0_m >> first) & 1u) != ((any1_m >> first) & 1u));
+      const int f_bit = first >= 0 ? (int)((any1_m >> first) & 1u) : 0;
       if (sp + 2 > STK || first < 0 || (best < 0 && !f_ok)) { status = 2; break; }
       const int j = best >= 0 ? best : first;
       // children: push bit 1 first so that bit 0 comes off the stack first
@@ -389,6 +410,7 @@ __global__ __launch_bounds__(64) void ins_subtree(InsArgs a) {
     tc.len = len;
     tc.nonempty = nonempty;
     tc.status = status;
+    if (status) atomicMax(a.worst, (uint32_t)status);
   }
 }
 
@@ -505,27 +527,41 @@ __global__ void ins_stats(LeafArgs la, int K, uint32_t* fsize, uint32_t* fleaves
 // Region capacity of a touched node: its known leaves and 4 slots per new point, times its
 // multiplier (2 at first; after an overflow, enough for K * (bits - 1) splits below every
 // leaf and every new point). A bulk node's empty leaves are not known before its replay,
-// so its leaves are scaled too. cap_total[0] (64-bit) sums the capacities.
-__global__ void ins_plan(const uint32_t* nstart, const uint32_t* nend, const uint32_t* fsize,
-                         const uint32_t* fleaves, const uint32_t* eoff, const uint8_t* emat,
-                         const uint32_t* multg, int64_t total, uint32_t* ncount,
-                         uint32_t* tflag, uint32_t* capg, uint32_t* lidg,
-                         unsigned long long* cap_total) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const uint32_t c = nend[g] - nstart[g];
-  ncount[g] = c;
-  tflag[g] = c ? 1u : 0u;
-  uint64_t cap = 0;
-  if (c) {
-    const uint64_t ec = eoff ? eoff[g + 1] - eoff[g] : 0u;
-    const bool mat = emat && emat[g];
-    const uint64_t base = fleaves[g] + ec, mult = multg[g];
-    cap = (mat ? base : base * mult) + 4u * (uint64_t)c * mult + 64u;
-    atomicAdd(cap_total, (unsigned long long)cap);
+// so its leaves are scaled too. cap_total[0] (64-bit) sums the capacities (a grid-stride
+// loop with one atomic per block).
+__global__ __launch_bounds__(256) void ins_plan(const uint32_t* nstart, const uint32_t* nend,
+                                                const uint32_t* fsize, const uint32_t* fleaves,
+                                                const uint32_t* eoff, const uint8_t* emat,
+                                                const uint32_t* multg, int64_t total,
+                                                uint32_t* ncount, uint32_t* tflag,
+                                                uint32_t* capg, uint32_t* lidg,
+                                                unsigned long long* cap_total) {
+  __shared__ unsigned long long part[4];
+  unsigned long long sum = 0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = nend[g] - nstart[g];
+    ncount[g] = c;
+    tflag[g] = c ? 1u : 0u;
+    uint64_t cap = 0;
+    if (c) {
+      const uint64_t ec = eoff ? eoff[g + 1] - eoff[g] : 0u;
+      const bool mat = emat && emat[g];
+      const uint64_t base = fleaves[g] + ec, mult = multg[g];
+      cap = (mat ? base : base * mult) + 4u * (uint64_t)c * mult + 64u;
+    }
+    capg[g] = (uint32_t)std::min<uint64_t>(cap, 0xffffffffu);
+    lidg[g] = c ? fsize[g] : 0u;
+    sum += cap;
   }
-  capg[g] = (uint32_t)std::min<uint64_t>(cap, 0xffffffffu);
-  lidg[g] = c ? fsize[g] : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long b = part[0] + part[1] + part[2] + part[3];
+    if (b) atomicAdd(cap_total, b);
+  }
 }
 
 __global__ void ins_widen(const Touch* touch, int64_t T, int K, uint32_t mult, uint32_t* multg) {
@@ -621,19 +657,9 @@ void insert_points(pdet_index& ix, const float* data, int64_t n_total, hipStream
   PDET_HIP(hipMemcpyAsync(mm_save.ptr(), ix.colmm.p, ix.colmm.bytes, hipMemcpyDeviceToDevice, s));
   PDET_HIP(hipMemsetAsync(ix.nonfinite.p, 0, 4, s));
   encode_rows(ix, data + n_old * ix.d, m, ncodes.as<uint8_t>(), nkeys.as<uint16_t>(), s);
-  uint32_t* hw = nullptr;
-  PDET_HIP(hipHostMalloc((void**)&hw, 16 * sizeof(uint32_t), hipHostMallocDefault));
-  struct HostWords {
-    uint32_t* p;
-    ~HostWords() { (void)hipHostFree(p); }
-  } hw_guard{hw};
-  PDET_HIP(hipMemcpyAsync(hw, ix.nonfinite.p, 4, hipMemcpyDeviceToHost, s));
-  PDET_HIP(hipStreamSynchronize(s));
-  if (hw[0]) {
-    PDET_HIP(hipMemcpyAsync(ix.colmm.p, mm_save.ptr(), ix.colmm.bytes, hipMemcpyDeviceToDevice, s));
-    PDET_HIP(hipStreamSynchronize(s));
-    throw Error{PDET_EINVAL, "the inserted rows hold non-finite values"};
-  }
+  // (checked at the first readback below: every step before the swap at the end writes
+  // temporaries only, and codes are in range whatever the projections)
+  uint32_t* hw = readback_words() + 48;
 
   // -- group the new points by (tree, first-layer node), in id order
   PooledBuf srows((size_t)L * m * KP), sids((size_t)L * m * 4), rows1((size_t)L * m * KP),
@@ -665,7 +691,7 @@ void insert_points(pdet_index& ix, const float* data, int64_t n_total, hipStream
   PooledBuf fsize((size_t)G * 4), fleaves((size_t)G * 4), ffirst((size_t)G * 4),
       fstart((size_t)G * 4), ncount((size_t)G * 4), nshift((size_t)G * 4), tflag((size_t)G * 4),
       tscan((size_t)G * 4), capg((size_t)G * 4), capscan((size_t)G * 4), lidg((size_t)G * 4),
-      lidscan((size_t)G * 4), totals(16 * 4);
+      lidscan((size_t)G * 4), totals(16 * 4), flags(8);
   PDET_HIP(hipMemsetAsync(fsize.ptr(), 0, fsize.bytes(), s));
   PDET_HIP(hipMemsetAsync(fleaves.ptr(), 0, fleaves.bytes(), s));
   PDET_HIP(hipMemsetAsync(ffirst.ptr(), 0xff, ffirst.bytes(), s));
@@ -680,12 +706,15 @@ void insert_points(pdet_index& ix, const float* data, int64_t n_total, hipStream
 
   // -- the touched nodes, their new lists, then the layout
   PooledBuf touch, recs, dfs, lidp, nlid((size_t)L * m * 4), multg((size_t)G * 4),
-      cap_total(8);
+      cap_total(8), ecnt((size_t)G * 4);
+  DevBuf eoff_new((size_t)(G + 1) * 4), emat_new((size_t)G);
   PDET_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(multg.ptr()), 2, (size_t)G, s));
   uint32_t T = 0;
+  int64_t n_empty = 0;
   for (int attempt = 0;; ++attempt) {
     PDET_HIP(hipMemsetAsync(cap_total.ptr(), 0, 8, s));
-    hipLaunchKernelGGL(ins_plan, dim3(cdiv(G, 256)), dim3(256), 0, s, nstart.as<uint32_t>(),
+    hipLaunchKernelGGL(ins_plan, dim3((unsigned)std::min<int64_t>(cdiv(G, 256), 128)), dim3(256),
+                       0, s, nstart.as<uint32_t>(),
                        nend.as<uint32_t>(), fsize.as<uint32_t>(), fleaves.as<uint32_t>(), eoff,
                        emat, multg.as<uint32_t>(), G, ncount.as<uint32_t>(),
                        tflag.as<uint32_t>(), capg.as<uint32_t>(), lidg.as<uint32_t>(),
@@ -698,7 +727,14 @@ void insert_points(pdet_index& ix, const float* data, int64_t n_total, hipStream
               scan_tmp, s);
     PDET_HIP(hipMemcpyAsync(hw, totals.ptr(), 3 * 4, hipMemcpyDeviceToHost, s));
     PDET_HIP(hipMemcpyAsync(hw + 4, cap_total.ptr(), 8, hipMemcpyDeviceToHost, s));
+    PDET_HIP(hipMemcpyAsync(hw + 6, ix.nonfinite.p, 4, hipMemcpyDeviceToHost, s));
     PDET_HIP(hipStreamSynchronize(s));
+    if (hw[6]) {
+      PDET_HIP(hipMemcpyAsync(ix.colmm.p, mm_save.ptr(), ix.colmm.bytes, hipMemcpyDeviceToDevice,
+                              s));
+      PDET_HIP(hipStreamSynchronize(s));
+      throw Error{PDET_EINVAL, "the inserted rows hold non-finite values"};
+    }
     T = hw[0];
     const uint32_t total_cap = hw[1], total_lid = hw[2];
     uint64_t cap64 = 0;
@@ -731,19 +767,26 @@ void insert_points(pdet_index& ix, const float* data, int64_t n_total, hipStream
       a.leaf_count[i] = la.count[i];
     }
     a.empt = ix.empt.p ? ix.empt.as<EmptyRec>() : nullptr;
+    a.worst = flags.as<uint32_t>();
     a.n_old = n_old; a.n_total = n_total; a.m = m;
     a.K = K; a.bits = ix.bits; a.max_leaf = ix.max_leaf;
+    PDET_HIP(hipMemsetAsync(flags.ptr(), 0, 4, s));
     if (T) {
       hipLaunchKernelGGL(ins_subtree, dim3(T), dim3(64), 0, s, a);
       PDET_HIP(hipGetLastError());
     }
-    // the worst status over the touched nodes
-    std::vector<Touch> ht(T);
-    if (T) PDET_HIP(hipMemcpyAsync(ht.data(), touch.ptr(), (size_t)T * sizeof(Touch),
-                                   hipMemcpyDeviceToHost, s));
+    // empty leaves per node (valid when every node succeeded), read back with the status
+    hipLaunchKernelGGL(ins_empty_counts, dim3(cdiv(G, 256)), dim3(256), 0, s,
+                       ncount.as<uint32_t>(), tscan.as<uint32_t>(), touch.as<Touch>(), eoff, emat,
+                       G, ecnt.as<uint32_t>(), emat_new.as<uint8_t>());
+    PDET_HIP(hipGetLastError());
+    scan_rows(ecnt.as<uint32_t>(), eoff_new.as<uint32_t>(), eoff_new.as<uint32_t>() + G, 1, G,
+              scan_tmp, s);
+    PDET_HIP(hipMemcpyAsync(hw, flags.ptr(), 4, hipMemcpyDeviceToHost, s));
+    PDET_HIP(hipMemcpyAsync(hw + 1, eoff_new.as<uint32_t>() + G, 4, hipMemcpyDeviceToHost, s));
     PDET_HIP(hipStreamSynchronize(s));
-    int worst = 0;
-    for (const Touch& tc : ht) worst = std::max(worst, tc.status);
+    const int worst = (int)hw[0];
+    n_empty = hw[1];
     PDET_REQUIRE(worst != 2, PDET_EDEVICE, "insertion: a tree's leaves are not consistent");
     if (worst == 0) break;
     PDET_REQUIRE(attempt == 0, PDET_EDEVICE, "insertion: node capacity exceeded");
@@ -762,18 +805,7 @@ void insert_points(pdet_index& ix, const float* data, int64_t n_total, hipStream
                      nshift.as<uint32_t>(), n_old, n_total, L, K, perm_new.as<int32_t>(),
                      cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>());
   PDET_HIP(hipGetLastError());
-  // empty leaves: counts, offsets, untouched nodes' records copied, touched ones written
-  PooledBuf ecnt((size_t)G * 4);
-  DevBuf eoff_new((size_t)(G + 1) * 4), emat_new((size_t)G);
-  hipLaunchKernelGGL(ins_empty_counts, dim3(cdiv(G, 256)), dim3(256), 0, s,
-                     ncount.as<uint32_t>(), tscan.as<uint32_t>(), touch.as<Touch>(), eoff, emat, G,
-                     ecnt.as<uint32_t>(), emat_new.as<uint8_t>());
-  PDET_HIP(hipGetLastError());
-  scan_rows(ecnt.as<uint32_t>(), eoff_new.as<uint32_t>(), eoff_new.as<uint32_t>() + G, 1, G,
-            scan_tmp, s);
-  PDET_HIP(hipMemcpyAsync(hw, eoff_new.as<uint32_t>() + G, 4, hipMemcpyDeviceToHost, s));
-  PDET_HIP(hipStreamSynchronize(s));
-  const int64_t n_empty = hw[0];
+  // empty leaves: untouched nodes' records copied, touched ones written by the layout
   DevBuf empt_new((size_t)std::max<int64_t>(n_empty, 1) * sizeof(EmptyRec));
   if (ix.n_empty) {
     hipLaunchKernelGGL(ins_copy_empties, dim3(cdiv(ix.n_empty, 256)), dim3(256), 0, s,

@@ -228,6 +228,9 @@ void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, in
                DevBuf& tmp, hipStream_t s);
 
 // tree.hip
+// 64 words of pinned host memory per thread for small readbacks (kept until the thread ends):
+// words 0..31 serve the tree build, 32..47 its leaf counts, 48..63 an insertion.
+uint32_t* readback_words();
 void build_trees(Index& ix, hipStream_t s);
 // Stable sort of each tree's n first-layer keys (LSD radix over 8-bit digits) carrying the
 // points' 16-byte code rows and ids (the position of each point). Sorted rows and ids end in

@@ -948,6 +948,8 @@ __global__ __launch_bounds__(256) void group_boxes(GroupArgs a) {
   }
 }
 
+}  // namespace
+
 // A small pinned host area per thread for counter readbacks (kept until the thread ends).
 uint32_t* readback_words() {
   struct Words {
@@ -958,8 +960,6 @@ uint32_t* readback_words() {
   if (!w.p) PDET_HIP(hipHostMalloc((void**)&w.p, 64 * sizeof(uint32_t), hipHostMallocDefault));
   return w.p;
 }
-
-}  // namespace
 
 void first_layer_sort(int L, int K, int64_t n, uint16_t* keys, const uint4* codes, uint4* rows0,
                       int32_t* ids0, uint4* rows1, int32_t* ids1, uint16_t* keys1,
