@@ -1,13 +1,18 @@
 // Projection (Eq. 1) and dynamic encoding (Algorithm 1) for gfx950.
 //
 // P = X . A is a thin contraction (m x d) . (d x 16L). Each wave computes a 16-point
-// tile against all 16-column tiles of A with v_mfma_f32_16x16x4_f32 (FP32 inputs,
-// FP32 accumulate), which runs at twice the rate of non-packed FP32 FMAs. The same
-// routine serves the sampled projection, the full encode pass and the query
-// projection, so a point gets bit-identical hash values in all three.
+// tile against all 16-column tiles of A on the bf16 matrix cores with FP32 accumulation:
+// every float32 operand is split exactly into three bf16 parts (hi + mid + lo: 3 x 8
+// significant bits), and the six products whose weight is at least 2^-16 of hi * hi are
+// accumulated (v_mfma_f32_16x16x32_bf16; each bf16 product is exact in FP32). The dropped
+// terms are below 2^-24 relative, so the result stays within the float32 dot-product error
+// bound, at a sixth of the matrix-core cycles of v_mfma_f32_16x16x4_f32. A tile whose rows
+// are exact in bf16 (e.g. byte-valued data: mid = lo = 0) needs only the three hi * (A part)
+// products. The same routine serves the sampled projection, the full encode pass and the
+// query projection, so a point gets bit-identical hash values in all three.
 //
-// MFMA 16x16x4 f32 lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// accumulator element i of lane l is D[4*(l/16)+i][l%16].
+// MFMA 16x16x32 bf16 lane layout: lane l supplies A[l%16][8*(l/16) .. +7] and
+// B[8*(l/16) .. +7][l%16]; accumulator element i of lane l is D[4*(l/16)+i][l%16].
 #include "internal.h"
 
 namespace pdet {
@@ -15,13 +20,22 @@ namespace pdet {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// x = hi + mid + lo, each part bf16 (round to nearest even; the differences are exact).
+__device__ inline void split3(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
+  hi = (__bf16)x;
+  const float r1 = x - (float)hi;
+  mid = (__bf16)r1;
+  lo = (__bf16)(r1 - (float)mid);
+}
 
 enum Mode { MODE_PROJECT = 0, MODE_SAMPLE = 1, MODE_ENCODE = 2 };
 
 constexpr int PROJ_THREADS = 1024;
 constexpr int PROJ_WAVES = PROJ_THREADS / 64;
 constexpr int DK_MAX = 128;              // rows of A staged per chunk (at most)
-constexpr int KB_MAX = DK_MAX / 16;      // 16-column steps per chunk
+constexpr int KB_MAX = DK_MAX / 32;      // 32-row MFMA steps per chunk
 
 struct ProjArgs {
   const float* X;          // [rows of X][d]
@@ -51,13 +65,13 @@ template <int NT, bool VEC4, int MODE>
 __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
   constexpr int NC = NT * 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // [dk][NC + 4]: with the padding, the rows that the two lane groups of a half-wave read
-  // per MFMA operand fall in disjoint LDS bank halves
-  constexpr int ASTR = NC + 4;
-  float* As = reinterpret_cast<float*>(smem_raw);
+  // A as bf16 parts, [part][32-row step][lane group][column] of 8 consecutive rows (16
+  // bytes): the 16 lanes of a group read 256 consecutive bytes per operand
+  uint4* As = reinterpret_cast<uint4*>(smem_raw);
+  const int kbc = (a.dk + 31) / 32;        // 32-row steps per chunk
   // [NT*K][Nr + 1]: interior breakpoints + inf, one padding word per column so that the
   // 16 columns a wave searches at once sit in different LDS banks
-  float* Bs = As + ((a.dk * ASTR + 3) & ~3);
+  float* Bs = reinterpret_cast<float*>(As + 3 * kbc * 4 * NC);
   const int bstride = a.Nr + 1;
   // the code staging area starts 16-byte aligned (rounded table size)
   uint8_t* stage = reinterpret_cast<uint8_t*>(
@@ -87,10 +101,21 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
 
   auto load_A = [&](int chunk) {
     const int k0 = chunk * a.dk;
-    const int tot = a.dk * NC;
+    const int tot = kbc * 4 * NC;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-      const int r = e / NC, c = e % NC;
-      As[r * ASTR + c] = (k0 + r < a.d) ? a.A[(int64_t)(k0 + r) * NC + c] : 0.0f;
+      const int c = e % NC, g = (e / NC) & 3, kb = e / (4 * NC);
+      bf16x8 hi, mid, lo;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int r = k0 + 32 * kb + 8 * g + j;
+        __bf16 h, m, l;
+        split3((r < a.d && 32 * kb + 8 * g + j < a.dk) ? a.A[(int64_t)r * NC + c] : 0.0f, h, m,
+               l);
+        hi[j] = h; mid[j] = m; lo[j] = l;
+      }
+      As[(0 * kbc * 4 + kb * 4 + g) * NC + c] = *reinterpret_cast<const uint4*>(&hi);
+      As[(1 * kbc * 4 + kb * 4 + g) * NC + c] = *reinterpret_cast<const uint4*>(&mid);
+      As[(2 * kbc * 4 + kb * 4 + g) * NC + c] = *reinterpret_cast<const uint4*>(&lo);
     }
   };
   // column min / max of this workgroup (ordered uints), reduced in LDS before one global
@@ -111,13 +136,37 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
   const int64_t ntiles = (a.m + 15) / 16;
   const int64_t tiles_per_iter = (int64_t)gridDim.x * PROJ_WAVES;
   const int64_t iters = (ntiles + tiles_per_iter - 1) / tiles_per_iter;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t tile = it * tiles_per_iter + (int64_t)blockIdx.x * PROJ_WAVES + wave;
+  // this lane's 8 consecutive values of its point per 32-row step of a chunk
+  float4 xb[2 * KB_MAX];
+  auto load_x = [&](int64_t tile, int k0) {
     const int64_t p_load = tile * 16 + col16;           // point whose X row this lane reads
     const bool load_ok = p_load < a.m;
     int64_t xrow = 0;
     if (load_ok) xrow = (MODE == MODE_SAMPLE) ? a.rows[p_load] : p_load;
     const float* xr = a.X + xrow * (int64_t)a.d;
+    const int kend = min(a.dk, a.d - k0);
+#pragma unroll
+    for (int u = 0; u < 2 * KB_MAX; ++u) {
+      const int kk = k0 + (u >> 1) * 32 + 8 * grp + 4 * (u & 1);   // first of 4 values
+      if ((u >> 1) * 32 < kend) {
+        if (VEC4 && load_ok && kk + 3 < a.d) {
+          xb[u] = *reinterpret_cast<const float4*>(xr + kk);
+        } else {
+          xb[u].x = (load_ok && kk + 0 < a.d) ? xr[kk + 0] : 0.0f;
+          xb[u].y = (load_ok && kk + 1 < a.d) ? xr[kk + 1] : 0.0f;
+          xb[u].z = (load_ok && kk + 2 < a.d) ? xr[kk + 2] : 0.0f;
+          xb[u].w = (load_ok && kk + 3 < a.d) ? xr[kk + 3] : 0.0f;
+        }
+      }
+    }
+  };
+  // with one chunk, the next tile's values are loaded while this tile's hash values are
+  // searched and written
+  const bool single = nchunks == 1;
+  const int64_t tile0 = (int64_t)blockIdx.x * PROJ_WAVES + wave;
+  if (single && iters > 0) load_x(tile0, 0);
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t tile = it * tiles_per_iter + tile0;
 
     floatx4 acc[NT];
 #pragma unroll
@@ -131,37 +180,45 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
       }
       const int k0 = chunk * a.dk;
       const int kend = min(a.dk, a.d - k0);
-      // this lane's values of the chunk (4 columns per 16-column step), all loads issued
-      // before the first MFMA
-      float4 xb[KB_MAX];
+      if (!single) load_x(tile, k0);
 #pragma unroll
-      for (int u = 0; u < KB_MAX; ++u) {
-        const int kk = k0 + u * 16 + 4 * grp;             // first of this lane's 4 columns
-        if (u * 16 < kend) {
-          if (VEC4 && load_ok && kk + 3 < a.d) {
-            xb[u] = *reinterpret_cast<const float4*>(xr + kk);
-          } else {
-            xb[u].x = (load_ok && kk + 0 < a.d) ? xr[kk + 0] : 0.0f;
-            xb[u].y = (load_ok && kk + 1 < a.d) ? xr[kk + 1] : 0.0f;
-            xb[u].z = (load_ok && kk + 2 < a.d) ? xr[kk + 2] : 0.0f;
-            xb[u].w = (load_ok && kk + 3 < a.d) ? xr[kk + 3] : 0.0f;
+      for (int kb = 0; kb < KB_MAX; ++kb) {
+        if (kb * 32 < kend) {
+          const float xv[8] = {xb[2 * kb].x, xb[2 * kb].y, xb[2 * kb].z, xb[2 * kb].w,
+                               xb[2 * kb + 1].x, xb[2 * kb + 1].y, xb[2 * kb + 1].z,
+                               xb[2 * kb + 1].w};
+          bf16x8 xh, xm, xl;
+          bool low = false;   // a mid or lo part is not zero
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            __bf16 h, m, l;
+            split3(xv[j], h, m, l);
+            xh[j] = h; xm[j] = m; xl[j] = l;
+            low = low || (float)m != 0.0f || (float)l != 0.0f;
           }
-        }
-      }
+          const bool full = __ballot(low) != 0;   // wave-uniform
+          const uint4* ab = As + (kb * 4 + grp) * NC + col16;
 #pragma unroll
-      for (int u = 0; u < KB_MAX; ++u) {
-        if (u * 16 < kend) {
-          const float xv[4] = {xb[u].x, xb[u].y, xb[u].z, xb[u].w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float* brow = As + (u * 16 + 4 * grp + e) * ASTR + col16;
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[e], brow[t * 16], acc[t], 0, 0, 0);
+          for (int t = 0; t < NT; ++t) {
+            const uint4 h4 = ab[t * 16], m4 = ab[kbc * 4 * NC + t * 16],
+                        l4 = ab[2 * kbc * 4 * NC + t * 16];
+            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&h4);
+            const bf16x8 am = *reinterpret_cast<const bf16x8*>(&m4);
+            const bf16x8 al = *reinterpret_cast<const bf16x8*>(&l4);
+            // smallest terms first
+            if (full) {
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, ah, acc[t], 0, 0, 0);
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, am, acc[t], 0, 0, 0);
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, al, acc[t], 0, 0, 0);
+            if (full) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, ah, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, am, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ah, acc[t], 0, 0, 0);
           }
         }
       }
     }
+    if (single && it + 1 < iters) load_x(tile + tiles_per_iter, 0);
 
     // acc[t][i] = P[tile*16 + 4*grp + i][t*16 + col16]
     const int64_t pbase = tile * 16 + 4 * grp;
@@ -309,8 +366,8 @@ void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* r
     // A is stored per launch group: [group][d][NC]
     a.A = ix.A.as<float>() + (int64_t)(t0 / TREES_PER_LAUNCH) * ix.d * (TREES_PER_LAUNCH * 16);
     const int NC = nt * 16;
-    a.dk = std::min(((ix.d + 15) / 16) * 16, DK_MAX);
-    size_t smem = (size_t)((a.dk * (NC + 4) + 3) & ~3) * 4;
+    a.dk = std::min(((ix.d + 31) / 32) * 32, DK_MAX);
+    size_t smem = (size_t)3 * ((a.dk + 31) / 32) * 4 * NC * 16;
     if (mode == MODE_ENCODE)
       smem += (size_t)((nt * ix.K * (ix.Nr + 1) + 3) & ~3) * 4 + (size_t)PROJ_WAVES * 16 * nt * KP;
     const bool vec4 = (ix.d % 4) == 0;
