@@ -6,6 +6,7 @@
 #include <limits>
 #include <new>
 #include <random>
+#include <thread>
 
 #include "internal.h"
 
@@ -281,7 +282,8 @@ void pool_give(DevBuf&& d) { scratch_pool().give(std::move(d)); }
 
 int64_t pdet_index::device_bytes() const {
   int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + H.bytes + perm.bytes + leafrow.bytes +
-              xbf16.bytes + xfp8.bytes + xscale.bytes + leaf_arena.bytes;
+              xbf16.bytes + xfp8.bytes + xscale.bytes + leaf_arena.bytes + sample_dev.bytes +
+              nonfinite.bytes + empt.bytes + eoff.bytes + emat.bytes;
   auto own = [](const pdet::DevBuf& x) { return x.owned ? (int64_t)x.bytes : 0; };
   for (int i = 0; i < PDET_MAX_L; ++i)
     b += own(leaf_start[i]) + own(leaf_count[i]) + own(leaf_hidx[i]) + own(box[i]) +
@@ -307,7 +309,33 @@ double pdet_epsilon(int32_t K, int32_t L) {
   return pdet::epsilon(K, L);
 }
 
+extern "C++" {
 namespace {
+// A pass over [0, count) split into contiguous parts on up to 16 host threads (one below
+// 2^20 items): f(begin, end, part) for each part.
+template <class F>
+void host_parallel(int64_t count, F&& f) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int parts = count < (int64_t(1) << 20) ? 1 : std::min(16, hw);
+  if (parts == 1) {
+    f(int64_t(0), count, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t per = (count + parts - 1) / parts;
+  for (int t = 0; t < parts; ++t)
+    th.emplace_back([&, t] { f(std::min(count, t * per), std::min(count, (t + 1) * per), t); });
+  for (auto& x : th) x.join();
+}
+
+// Pinned staging for the sample ids of a build (per thread, grown as needed, kept): the
+// upload is then one asynchronous DMA.
+PinnedBuf& sample_staging(size_t bytes) {
+  static thread_local PinnedBuf buf;
+  if (buf.bytes < bytes) buf.alloc(bytes);
+  return buf;
+}
+
 // The seeded draws of pdet_draw_params: two mt19937_64 streams of one seed (projection and
 // sample), Box-Muller normals from 53-bit uniforms in (0, 1), Floyd's algorithm for the
 // sample (a bit per id marks the drawn ones; the ids come out ascending).
@@ -353,6 +381,7 @@ void draw(int64_t n, int32_t d, int32_t LK, int32_t Nr, double frac, uint64_t se
   }
 }
 }  // namespace
+}  // extern "C++"
 
 pdet_status pdet_draw_params(int64_t n, int32_t d, int32_t L, int32_t K, int32_t Nr,
                              double sample_frac, uint64_t seed, float* proj,
@@ -393,10 +422,18 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
                  PDET_EINVAL, "unknown lowp_copies bit");
     PDET_REQUIRE(p->encoding == PDET_ENC_DYNAMIC || p->encoding == PDET_ENC_STATIC, PDET_EINVAL,
                  "unknown encoding");
-    if (p->sample_ids)
-      for (int64_t i = 0; i < n_sample; ++i)
-        PDET_REQUIRE(p->sample_ids[i] >= 0 && p->sample_ids[i] < n, PDET_EINVAL,
-                     "sample id out of range");
+    if (p->sample_ids) {
+      // branch-free passes on several threads: an id is out of range iff, as unsigned, >= n
+      uint64_t bad[16] = {};
+      host_parallel(n_sample, [&](int64_t b, int64_t e, int part) {
+        uint64_t x = 0;
+        for (int64_t i = b; i < e; ++i) x |= (uint64_t)((uint64_t)p->sample_ids[i] >= (uint64_t)n);
+        bad[part] = x;
+      });
+      uint64_t any = 0;
+      for (uint64_t x : bad) any |= x;
+      PDET_REQUIRE(any == 0, PDET_EINVAL, "sample id out of range");
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     ix = new pdet_index();
@@ -410,12 +447,12 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
       std::copy(p->proj, p->proj + ix->proj_host.size(), ix->proj_host.begin());
     else
       draw(n, d, p->L * p->K, p->Nr, 1.0, p->seed, ix->proj_host.data(), nullptr, nullptr);
-    ix->sample_host.resize((size_t)n_sample);
-    if (p->sample_ids)
-      std::copy(p->sample_ids, p->sample_ids + n_sample, ix->sample_host.begin());
-    else
-      draw(n, d, p->L * p->K, p->Nr, p->sample_frac, p->seed, nullptr, ix->sample_host.data(),
-           nullptr);
+    std::vector<int64_t> drawn;   // the drawn sample (a given one is uploaded directly)
+    if (!p->sample_ids) {
+      drawn.resize((size_t)n_sample);
+      draw(n, d, p->L * p->K, p->Nr, p->sample_frac, p->seed, nullptr, drawn.data(), nullptr);
+    }
+    const int64_t* sample_src = p->sample_ids ? p->sample_ids : drawn.data();
     ix->lowp = p->lowp_copies;
     ix->X = data;
     ix->dpad = ((d + 15) / 16) * 16;
@@ -430,9 +467,17 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     ix->A.alloc(Ap.size() * 4);
     PDET_HIP(hipMemcpyAsync(ix->A.p, Ap.data(), Ap.size() * 4, hipMemcpyHostToDevice, s));
     std::vector<PooledBuf> temps;   // build temporaries, held until the final synchronisation
-    PooledBuf sid((size_t)n_sample * 8);
-    PDET_HIP(hipMemcpyAsync(sid.ptr(), ix->sample_host.data(), sid.bytes(), hipMemcpyHostToDevice,
-                            s));
+    ix->sample_dev.alloc((size_t)n_sample * 8);   // kept for export
+    {
+      PinnedBuf& stg = sample_staging((size_t)n_sample * 8);
+      int64_t* dst = stg.as<int64_t>();
+      host_parallel(n_sample, [&](int64_t b, int64_t e, int) {
+        std::memcpy(dst + b, sample_src + b, (size_t)(e - b) * 8);
+      });
+      PDET_HIP(hipMemcpyAsync(ix->sample_dev.p, dst, ix->sample_dev.bytes, hipMemcpyHostToDevice,
+                              s));
+    }
+    const DevBuf& sid = ix->sample_dev;
     PooledBuf ps((size_t)LK * n_sample * 4);   // sampled hash values, column-major
     pdet_timing& tm = timer().t;
     if (timer().on) {
@@ -617,16 +662,15 @@ pdet_status pdet_export(const pdet_index* idx, int32_t what, int32_t tree, void*
         src = idx->leaf_count[tree].p; want = (size_t)idx->nl[tree] * 4; break;
       case PDET_X_LEAF_HIDX:
         src = idx->leaf_hidx[tree].p; want = (size_t)idx->nl[tree] * KP * 2; break;
-      case PDET_X_PROJ:
-      case PDET_X_SAMPLE: {   // host copies
-        const bool pj = what == PDET_X_PROJ;
-        want = pj ? idx->proj_host.size() * 4 : idx->sample_host.size() * 8;
+      case PDET_X_PROJ: {   // the host copy
+        want = idx->proj_host.size() * 4;
         PDET_REQUIRE(bytes == want, PDET_EINVAL,
                      "export size mismatch: expected " + std::to_string(want) + " bytes");
-        if (pj) std::copy(idx->proj_host.begin(), idx->proj_host.end(), static_cast<float*>(host));
-        else std::copy(idx->sample_host.begin(), idx->sample_host.end(), static_cast<int64_t*>(host));
+        std::copy(idx->proj_host.begin(), idx->proj_host.end(), static_cast<float*>(host));
         return;
       }
+      case PDET_X_SAMPLE:
+        src = idx->sample_dev.p; want = (size_t)idx->n_sample * 8; break;
       case PDET_X_LEAF_OF: {
         // from the first tree's permutation and leaf rows: the point at position p of
         // tree 0 is perm_0[p], and its leaf in `tree` is leafrow[0][p][tree]

@@ -51,7 +51,7 @@ struct pdet_index {
   int device = 0;
   const float* X = nullptr;        // borrowed float32 [n][d]
   std::vector<float> proj_host;    // the projection [d][L*K] (given or drawn)
-  std::vector<int64_t> sample_host;   // the sampled ids (given or drawn)
+  pdet::DevBuf sample_dev;         // int64 [n_sample]: the sampled ids (given or drawn)
 
   pdet::DevBuf A;                  // float32 padded projection, see pad_projection()
   pdet::DevBuf B;                  // float32 [L*K][Nr+1] breakpoints

@@ -62,6 +62,7 @@ struct Lists {
   Seg* big_next; uint32_t* n_big_next; uint32_t* pts_big_next;   // and their total size
   Seg* mid[NCLS]; uint32_t* n_mid;                              // n_mid[c]: class c
   Copy* copies; uint32_t* n_copies;   // leaves whose ids sit in buffer 1
+  uint32_t* cnt_next = nullptr;   // [big_next index][KP]: next-bit counts, if known
 };
 
 // A global pass over the nodes larger than LDS_SEG_CAP gives each workgroup one unit: at
@@ -120,7 +121,7 @@ __device__ inline bool fully_refined(const uint8_t* depth, int K, int bits) {
 }
 
 __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, const LeafOut& lo,
-                      const Lists& li) {
+                      const Lists& li, const uint32_t* counts = nullptr) {
   if (s.count <= 0) return;
   if (s.count <= max_leaf || fully_refined(s.depth, K, bits)) {
     emit_leaf(lo, n, s.tree, s.start, s.count, s.depth, s.prefix, K);
@@ -129,8 +130,11 @@ __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, co
     const int c = size_class(s.count);
     li.mid[c][atomicAdd(&li.n_mid[c], 1u)] = s;
   } else {
-    li.big_next[atomicAdd(li.n_big_next, 1u)] = s;
+    const uint32_t k = atomicAdd(li.n_big_next, 1u);
+    li.big_next[k] = s;
     atomicAdd(li.pts_big_next, (uint32_t)s.count);
+    if (counts && li.cnt_next)
+      for (int j = 0; j < KP; ++j) li.cnt_next[(int64_t)k * KP + j] = counts[j];
   }
 }
 
@@ -338,7 +342,9 @@ __global__ void seg_choose(const Seg* segs, int nseg, const uint32_t* cnt, int K
   }
   // a node routed here is never fully refined, so best >= 0
   split[i] = best;
-  const uint32_t z = (uint32_t)s.count - cnt[(int64_t)i * KP + best];
+  // (a count never exceeds the node's size; the bound keeps the cursors inside the node
+  // whatever the counts hold)
+  const uint32_t z = (uint32_t)s.count - min(cnt[(int64_t)i * KP + best], (uint32_t)s.count);
   c0[i] = z;
   cur0[i] = (uint32_t)s.start;
   cur1[i] = (uint32_t)s.start + z;
@@ -352,17 +358,34 @@ __global__ void seg_choose(const Seg* segs, int nseg, const uint32_t* cnt, int K
 }
 
 // Partition of each node's rows and ids into the other buffer, bit-0 child first. A
-// child that is a leaf needs no rows any more: only its ids are written.
+// child that is a leaf needs no rows any more: only its ids are written. A child that
+// stays above LDS_SEG_CAP points gets its next-bit counts here (cntn[node][bit][dim]), so
+// the next level needs no counting pass: a thread sums its rows' masked bits as byte
+// counters (16 rows per unit and thread), each wave adds them up as 16-bit fields.
 __global__ __launch_bounds__(256) void seg_split(const Seg* segs, const Unit* units,
                                                  const uint32_t* n_units, const int32_t* split,
-                                                 const uint8_t* leafs, Bufs b, int64_t n,
-                                                 int bits, uint32_t* cur0, uint32_t* cur1) {
+                                                 const uint8_t* leafs, const uint32_t* c0,
+                                                 Bufs b, int64_t n, int K, int bits,
+                                                 uint32_t* cur0, uint32_t* cur1,
+                                                 uint32_t* cntn) {
+  static_assert(SEG_CHUNK / 256 <= 255, "byte counters");
   if (blockIdx.x >= *n_units) return;
   const Unit u = units[blockIdx.x];
   const Seg s = segs[u.seg];
   const int j = split[u.seg];
   const int sh = bits - 1 - s.depth[j];
   const uint8_t lf = leafs[u.seg];
+  const uint32_t z = c0[u.seg];
+  const bool need0 = !(lf & 1) && z > (uint32_t)LDS_SEG_CAP;
+  const bool need1 = !(lf & 2) && (uint32_t)s.count - z > (uint32_t)LDS_SEG_CAP;
+  // the children's next unrefined bit of every dimension (dimension j one deeper)
+  uint32_t M[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int jj = 0; jj < KP; ++jj) {
+    const int cd = s.depth[jj] + (jj == j ? 1 : 0);
+    if (jj < K && cd < bits) M[jj >> 2] |= 1u << (8 * (jj & 3) + bits - 1 - cd);
+  }
+  uint32_t acc0[4] = {0u, 0u, 0u, 0u}, acc1[4] = {0u, 0u, 0u, 0u};
   const int64_t tb = (int64_t)s.tree * n;
   const uint4* rs = b.rows[s.buf] + tb + s.start;
   const int32_t* is = b.ids[s.buf] + tb + s.start;
@@ -393,12 +416,37 @@ __global__ __launch_bounds__(256) void seg_split(const Seg* segs, const Unit* un
       const uint32_t pos = bit ? bo + lanes_below(mo) : bz + lanes_below(mz);
       id_d[pos] = id;
       if (!((lf >> bit) & 1)) rd[pos] = row;
+      if (bit ? need1 : need0) {
+        uint32_t* acc = bit ? acc1 : acc0;
+        acc[0] += nonzero_bytes(row.x & M[0]);
+        acc[1] += nonzero_bytes(row.y & M[1]);
+        acc[2] += nonzero_bytes(row.z & M[2]);
+        acc[3] += nonzero_bytes(row.w & M[3]);
+      }
     }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (!(c ? need1 : need0)) continue;
+    const uint32_t* acc = c ? acc1 : acc0;
+    // bytes 0 and 2 (even dimensions), bytes 1 and 3 (odd) as 16-bit fields
+    uint32_t w[8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      w[2 * i] = wave_sum(acc[i] & 0x00ff00ffu);
+      w[2 * i + 1] = wave_sum((acc[i] >> 8) & 0x00ff00ffu);
+    }
+    if ((threadIdx.x & 63) == 0)
+      for (int jj = 0; jj < K; ++jj) {
+        const uint32_t v = (w[2 * (jj >> 2) + (jj & 1)] >> (16 * ((jj >> 1) & 1))) & 0xffffu;
+        if (v) atomicAdd(&cntn[((int64_t)u.seg * 2 + c) * KP + jj], v);
+      }
   }
 }
 
 __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, const uint32_t* c0,
-                             int K, int bits, int max_leaf, int64_t n, LeafOut lo, Lists li) {
+                             const uint32_t* cntn, int K, int bits, int max_leaf, int64_t n,
+                             LeafOut lo, Lists li) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nseg) return;
   const Seg s = segs[i];
@@ -418,8 +466,8 @@ __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, co
       b.prefix[jj] = (uint8_t)(s.prefix[jj] * 2 + 1);
     }
   }
-  route(a, K, bits, max_leaf, n, lo, li);
-  route(b, K, bits, max_leaf, n, lo, li);
+  route(a, K, bits, max_leaf, n, lo, li, cntn + (int64_t)i * 2 * KP);
+  route(b, K, bits, max_leaf, n, lo, li, cntn + ((int64_t)i * 2 + 1) * KP);
 }
 
 // Ids of leaves whose data sits in buffer 1 go to the permutation (buffer 0).
@@ -1057,16 +1105,23 @@ void build_trees(Index& ix, hipStream_t s) {
   Seg* cur_big = bigA.as<Seg>();
   Seg* nxt_big = bigB.as<Seg>();
   int cur_slot = 0;   // counters of the current list at c[2*cur_slot]
-  PooledBuf cntbuf, split, c0, cur0, cur1, leafs, units;
+  // next-bit counts of the current level's nodes (counted at the first level, carried from
+  // the split pass after it), of the next level's, and of every node's children
+  PooledBuf cntbuf, cntnext, cntn, split, c0, cur0, cur1, leafs, units;
   if (nbig) {
     units.alloc(((size_t)L * n / SEG_CHUNK + (size_t)big_cap) * sizeof(Unit));
     cntbuf.alloc((size_t)big_cap * KP * 4);
+    cntnext.alloc((size_t)big_cap * KP * 4);
+    cntn.alloc((size_t)big_cap * 2 * KP * 4);
     split.alloc((size_t)big_cap * 4); c0.alloc((size_t)big_cap * 4);
     cur0.alloc((size_t)big_cap * 4); cur1.alloc((size_t)big_cap * 4);
     leafs.alloc((size_t)big_cap);
   }
-  while (nbig > 0) {
-    PDET_HIP(hipMemsetAsync(cntbuf.ptr(), 0, (size_t)nbig * KP * 4, s));
+  uint32_t* cur_cnt = cntbuf.as<uint32_t>();
+  uint32_t* nxt_cnt = cntnext.as<uint32_t>();
+  for (int level = 0; nbig > 0; ++level) {
+    if (level == 0) PDET_HIP(hipMemsetAsync(cur_cnt, 0, (size_t)nbig * KP * 4, s));
+    PDET_HIP(hipMemsetAsync(cntn.ptr(), 0, (size_t)nbig * 2 * KP * 4, s));
     const int nxt_slot = 1 - cur_slot;
     PDET_HIP(hipMemsetAsync(c + 2 * nxt_slot, 0, 8, s));
     PDET_HIP(hipMemsetAsync(c + 8, 0, 8, s));   // copies, units
@@ -1075,24 +1130,28 @@ void build_trees(Index& ix, hipStream_t s) {
     hipLaunchKernelGGL(seg_units, dim3(cdiv(nbig, 256)), dim3(256), 0, s, cur_big, (int)nbig,
                        units.as<Unit>(), c + 9);
     PDET_HIP(hipGetLastError());
-    hipLaunchKernelGGL(seg_count, dim3(nu), dim3(256), 0, s, cur_big, units.as<Unit>(), c + 9, bf,
-                       n, K, bits, cntbuf.as<uint32_t>());
-    PDET_HIP(hipGetLastError());
+    if (level == 0) {
+      hipLaunchKernelGGL(seg_count, dim3(nu), dim3(256), 0, s, cur_big, units.as<Unit>(), c + 9,
+                         bf, n, K, bits, cur_cnt);
+      PDET_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(seg_choose, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
-                       cntbuf.as<uint32_t>(), K, bits, ix.max_leaf, split.as<int32_t>(),
+                       cur_cnt, K, bits, ix.max_leaf, split.as<int32_t>(),
                        c0.as<uint32_t>(), cur0.as<uint32_t>(), cur1.as<uint32_t>(),
                        leafs.as<uint8_t>());
     PDET_HIP(hipGetLastError());
     hipLaunchKernelGGL(seg_split, dim3(nu), dim3(256), 0, s, cur_big, units.as<Unit>(), c + 9,
-                       split.as<int32_t>(), leafs.as<uint8_t>(), bf, n, bits,
-                       cur0.as<uint32_t>(), cur1.as<uint32_t>());
+                       split.as<int32_t>(), leafs.as<uint8_t>(), c0.as<uint32_t>(), bf, n, K,
+                       bits, cur0.as<uint32_t>(), cur1.as<uint32_t>(), cntn.as<uint32_t>());
     PDET_HIP(hipGetLastError());
     Lists ln = li;
     ln.big_next = nxt_big;
     ln.n_big_next = c + 2 * nxt_slot;
     ln.pts_big_next = c + 2 * nxt_slot + 1;
+    ln.cnt_next = nxt_cnt;
     hipLaunchKernelGGL(seg_children, dim3(cdiv(nbig, 64)), dim3(64), 0, s, cur_big, (int)nbig,
-                       split.as<int32_t>(), c0.as<uint32_t>(), K, bits, ix.max_leaf, n, lo, ln);
+                       split.as<int32_t>(), c0.as<uint32_t>(), cntn.as<uint32_t>(), K, bits,
+                       ix.max_leaf, n, lo, ln);
     PDET_HIP(hipGetLastError());
     PDET_HIP(hipMemcpyAsync(hc, c, 16 * 4, hipMemcpyDeviceToHost, s));
     PDET_HIP(hipStreamSynchronize(s));
@@ -1103,6 +1162,7 @@ void build_trees(Index& ix, hipStream_t s) {
     nbig = hc[2 * nxt_slot];
     ptsbig = hc[2 * nxt_slot + 1];
     std::swap(cur_big, nxt_big);
+    std::swap(cur_cnt, nxt_cnt);
     cur_slot = nxt_slot;
   }
   {
