@@ -145,7 +145,7 @@ __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, co
 // [tree][digit][tile] counts, plus the tile's earlier rounds) plus the same-digit items of
 // the earlier waves and lanes of its round. The output keeps input order within a digit.
 constexpr int RK_THREADS = 256;
-constexpr int RK_ROUNDS = 16;
+constexpr int RK_ROUNDS = 8;
 constexpr int RK_TILE = RK_THREADS * RK_ROUNDS;
 constexpr int RK_WAVES = RK_THREADS / 64;
 
@@ -189,60 +189,102 @@ __global__ __launch_bounds__(RK_THREADS) void rk_hist(const uint16_t* keys, int6
 }
 
 // One pass: items (key, code row, id) of each tree to their places. FIRST: the input is
-// the encoder's output in point order (ids are positions).
+// the encoder's output in point order (ids are positions). The tile is first sorted by
+// digit in LDS (stable: rounds, then waves, then lanes, in input order), then written out
+// in tile order, so that the items of one digit leave as one contiguous run (whole cache
+// lines instead of one 16-byte row per digit and round).
 template <int SHIFT, bool FIRST>
 __global__ __launch_bounds__(RK_THREADS) void rk_scatter(const uint16_t* kin, const uint4* rin,
                                                          const int32_t* iin, int64_t n, int nblk,
                                                          const uint32_t* off, uint16_t* kout,
                                                          uint4* rout, int32_t* iout) {
-  __shared__ uint32_t run[256];
+  __shared__ uint4 srow[RK_TILE];
+  __shared__ int32_t sid[RK_TILE];
+  __shared__ uint16_t skey[RK_TILE];
+  __shared__ uint32_t lcur[256];    // running local position of each digit
+  __shared__ uint32_t lbase[256];   // first local position of each digit
+  __shared__ uint32_t gbase[256];   // first global position of each digit's run of this tile
   __shared__ uint32_t wc[RK_WAVES][256];
+  __shared__ uint32_t sh[RK_THREADS / 64 + 1];
   const int tree = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x, wave = tid >> 6;
   const int64_t tb = (int64_t)tree * n;
-  run[tid] = off[((int64_t)tree * 256 + tid) * nblk + blk];
-#pragma unroll
-  for (int w = 0; w < RK_WAVES; ++w) wc[w][tid] = 0;
   const int64_t p0 = (int64_t)blk * RK_TILE;
-  // the next round's item is loaded while the current one is placed
-  auto load = [&](int r, uint32_t& key, uint4& row, int32_t& id) {
-    const int64_t p = p0 + r * RK_THREADS + tid;
-    key = 0;
+  const int m = (int)min<int64_t>(RK_TILE, n - p0);   // items of this tile
+  // the tile's keys (rows and ids are loaded one round ahead of their placement)
+  uint32_t key[RK_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RK_ROUNDS; ++r) {
+    const int q = r * RK_THREADS + tid;
+    key[r] = q < m ? kin[tb + p0 + q] : 0u;
+  }
+  auto load = [&](int r, uint4& row, int32_t& id) {
+    const int q = r * RK_THREADS + tid;
     row = make_uint4(0, 0, 0, 0);
     id = 0;
-    if (p < n) {
-      key = kin[tb + p];
-      row = rin[tb + p];
-      id = FIRST ? (int32_t)p : iin[tb + p];
+    if (q < m) {
+      row = rin[tb + p0 + q];
+      id = FIRST ? (int32_t)(p0 + q) : iin[tb + p0 + q];
     }
   };
-  uint32_t key, nkey;
   uint4 row, nrow;
   int32_t id, nid;
-  load(0, key, row, id);
+  load(0, row, id);
+  // local digit counts -> local bases (an exclusive scan over the 256 digits)
+  {
+    const uint32_t gb = off[((int64_t)tree * 256 + tid) * nblk + blk];
+    gbase[tid] = gb;
+    lcur[tid] = 0;
+  }
+#pragma unroll
+  for (int w = 0; w < RK_WAVES; ++w) wc[w][tid] = 0;
   __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RK_ROUNDS; ++r)
+    if (r * RK_THREADS + tid < m) atomicAdd(&lcur[(key[r] >> SHIFT) & 255u], 1u);
+  __syncthreads();
+  {
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<RK_THREADS>(lcur[tid], sh, &tot);
+    __syncthreads();
+    lbase[tid] = ex;
+    lcur[tid] = ex;
+  }
+  __syncthreads();
+  // stable local placement, round by round
+#pragma unroll
   for (int r = 0; r < RK_ROUNDS; ++r) {
-    if (r + 1 < RK_ROUNDS) load(r + 1, nkey, nrow, nid);
-    const bool v = p0 + r * RK_THREADS + tid < n;
-    const uint32_t d = (key >> SHIFT) & 255u;
-    const uint64_t m = same_digit_lanes(d, v);
-    const uint32_t rank = lanes_below_mask(m);
-    if (v && rank == 0) wc[wave][d] = (uint32_t)__popcll(m);
+    if (r + 1 < RK_ROUNDS) load(r + 1, nrow, nid);
+    const bool v = r * RK_THREADS + tid < m;
+    const uint32_t d = (key[r] >> SHIFT) & 255u;
+    const uint64_t mk = same_digit_lanes(d, v);
+    const uint32_t rank = lanes_below_mask(mk);
+    if (v && rank == 0) wc[wave][d] = (uint32_t)__popcll(mk);
     __syncthreads();
     if (v) {
-      uint32_t pos = run[d] + rank;
+      uint32_t pos = lcur[d] + rank;
       for (int w = 0; w < wave; ++w) pos += wc[w][d];
-      kout[tb + pos] = (uint16_t)key;
-      rout[tb + pos] = row;
-      iout[tb + pos] = id;
+      srow[pos] = row;
+      sid[pos] = id;
+      skey[pos] = (uint16_t)key[r];
     }
     __syncthreads();
-    // thread t owns digit t: the round's counts move its running offset
     uint32_t t = 0;
 #pragma unroll
     for (int w = 0; w < RK_WAVES; ++w) { t += wc[w][tid]; wc[w][tid] = 0; }
-    run[tid] += t;
+    lcur[tid] += t;
     __syncthreads();
-    key = nkey; row = nrow; id = nid;
+    row = nrow;
+    id = nid;
+  }
+  // out in tile order: consecutive local positions of one digit go to consecutive places
+#pragma unroll 2
+  for (int q = tid; q < m; q += RK_THREADS) {
+    const uint32_t k = skey[q];
+    const uint32_t d = (k >> SHIFT) & 255u;
+    const uint32_t pos = gbase[d] + (uint32_t)q - lbase[d];
+    kout[tb + pos] = (uint16_t)k;
+    rout[tb + pos] = srow[q];
+    iout[tb + pos] = sid[q];
   }
 }
 
