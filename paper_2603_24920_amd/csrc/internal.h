@@ -226,6 +226,9 @@ void fill_f32(float* p, int64_t count, float v, hipStream_t s);
 void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, hipStream_t s);
 void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,
                DevBuf& tmp, hipStream_t s);
+// The same over the indicator (entry != 0) of each entry.
+void scan_rows_nonzero(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows,
+                       int64_t len, DevBuf& tmp, hipStream_t s);
 
 // tree.hip
 // 64 words of pinned host memory per thread for small readbacks (kept until the thread ends):

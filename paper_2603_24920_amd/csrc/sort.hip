@@ -316,6 +316,8 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* t
   return r;
 }
 
+// NZ: the scanned value of an entry is 1 if it is not zero, else 0
+template <bool NZ>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_sums(const uint32_t* in, int64_t len,
                                                           int64_t nblk, uint32_t* sums) {
   __shared__ uint32_t sh[SCAN_THREADS / 64 + 1];
@@ -324,7 +326,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_sums(const uint32_t* in, in
   uint32_t s = 0;
   for (int it = 0; it < SCAN_ITEMS; ++it) {
     const int64_t i = b * SCAN_BLOCK + it * SCAN_THREADS + threadIdx.x;
-    if (i < len) s += r[i];
+    if (i < len) s += NZ ? (r[i] != 0u ? 1u : 0u) : r[i];
   }
   uint32_t tot;
   block_excl_scan(s, sh, &tot);
@@ -347,6 +349,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_of_sums(uint32_t* sums, int
   if (threadIdx.x == 0 && totals) totals[blockIdx.x] = carry;
 }
 
+template <bool NZ>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_apply(const uint32_t* in, uint32_t* out,
                                                            int64_t len, int64_t nblk,
                                                            const uint32_t* sums) {
@@ -361,6 +364,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply(const uint32_t* in, u
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) {
     v[it] = (i0 + it < len) ? r[i0 + it] : 0;
+    if (NZ) v[it] = v[it] != 0u ? 1u : 0u;
     s += v[it];
   }
   uint32_t tot;
@@ -477,20 +481,31 @@ void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, h
   PDET_HIP(hipGetLastError());
 }
 
-void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,
-               DevBuf& tmp, hipStream_t s) {
+template <bool NZ>
+void scan_rows_t(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,
+                 DevBuf& tmp, hipStream_t s) {
   const int64_t nblk = (len + SCAN_BLOCK - 1) / SCAN_BLOCK;
   const size_t need = (size_t)rows * nblk * sizeof(uint32_t);
   if (tmp.bytes < need) tmp.alloc(need);
   uint32_t* sums = tmp.as<uint32_t>();
-  hipLaunchKernelGGL(scan_sums, dim3((unsigned)(rows * nblk)), dim3(SCAN_THREADS), 0, s, in, len,
+  hipLaunchKernelGGL(scan_sums<NZ>, dim3((unsigned)(rows * nblk)), dim3(SCAN_THREADS), 0, s, in, len,
                      nblk, sums);
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(scan_of_sums, dim3(rows), dim3(SCAN_THREADS), 0, s, sums, nblk, totals);
   PDET_HIP(hipGetLastError());
-  hipLaunchKernelGGL(scan_apply, dim3((unsigned)(rows * nblk)), dim3(SCAN_THREADS), 0, s, in, out,
+  hipLaunchKernelGGL(scan_apply<NZ>, dim3((unsigned)(rows * nblk)), dim3(SCAN_THREADS), 0, s, in, out,
                      len, nblk, sums);
   PDET_HIP(hipGetLastError());
+}
+
+void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,
+               DevBuf& tmp, hipStream_t s) {
+  scan_rows_t<false>(in, out, totals, rows, len, tmp, s);
+}
+
+void scan_rows_nonzero(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows,
+                       int64_t len, DevBuf& tmp, hipStream_t s) {
+  scan_rows_t<true>(in, out, totals, rows, len, tmp, s);
 }
 
 }  // namespace pdet

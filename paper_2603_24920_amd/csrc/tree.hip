@@ -924,11 +924,6 @@ __global__ __launch_bounds__(NT) void seg_lds_dfs(const Seg* mid, Bufs b, int64_
 }
 
 // ---- leaf tables
-__global__ void leaf_flags(const uint32_t* cnt_at, uint32_t* flags, int64_t total) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < total) flags[g] = cnt_at[g] ? 1u : 0u;
-}
-
 struct LeafTables {
   int32_t* start[PDET_MAX_L];
   int32_t* count[PDET_MAX_L];
@@ -1245,10 +1240,7 @@ void finish_trees(Index& ix, const uint32_t* cnt_at, const uint16_t* hidx_at, De
   const int L = ix.L, K = ix.K, bits = ix.bits;
   // number the leaves in position (= depth-first) order
   PooledBuf flags((size_t)L * n * 4), totals((size_t)L * 4);
-  hipLaunchKernelGGL(leaf_flags, dim3(cdiv((int64_t)L * n, 256)), dim3(256), 0, s,
-                     cnt_at, flags.as<uint32_t>(), (int64_t)L * n);
-  PDET_HIP(hipGetLastError());
-  scan_rows(flags.as<uint32_t>(), flags.as<uint32_t>(), totals.as<uint32_t>(), L, n, scan_tmp, s);
+  scan_rows_nonzero(cnt_at, flags.as<uint32_t>(), totals.as<uint32_t>(), L, n, scan_tmp, s);
   std::vector<uint32_t> nl(L);
   // per-point leaf ordinals and the leaf-row table need only the scan: they run while the
   // host reads the leaf counts back (into pinned memory, so the copy does not wait for
