@@ -422,17 +422,31 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
                  PDET_EINVAL, "unknown lowp_copies bit");
     PDET_REQUIRE(p->encoding == PDET_ENC_DYNAMIC || p->encoding == PDET_ENC_STATIC, PDET_EINVAL,
                  "unknown encoding");
+    // a given sample is checked on several host threads (branch-free: an id is out of range
+    // iff, as unsigned, >= n) while it is copied to the pinned staging of its upload; without
+    // staging (no device) it is only checked, so that the error is still reported first
+    PinnedBuf* staging = nullptr;
     if (p->sample_ids) {
-      // branch-free passes on several threads: an id is out of range iff, as unsigned, >= n
+      try {
+        staging = &sample_staging((size_t)n_sample * 8);
+      } catch (const Error&) {
+        staging = nullptr;
+      }
+      int64_t* dst = staging ? staging->as<int64_t>() : nullptr;
       uint64_t bad[16] = {};
       host_parallel(n_sample, [&](int64_t b, int64_t e, int part) {
         uint64_t x = 0;
-        for (int64_t i = b; i < e; ++i) x |= (uint64_t)((uint64_t)p->sample_ids[i] >= (uint64_t)n);
+        for (int64_t i = b; i < e; ++i) {
+          const int64_t v = p->sample_ids[i];
+          x |= (uint64_t)((uint64_t)v >= (uint64_t)n);
+          if (dst) dst[i] = v;
+        }
         bad[part] = x;
       });
       uint64_t any = 0;
       for (uint64_t x : bad) any |= x;
       PDET_REQUIRE(any == 0, PDET_EINVAL, "sample id out of range");
+      PDET_REQUIRE(staging, PDET_ENOMEM, "pinned staging for the sample ids failed");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
 
@@ -469,13 +483,12 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     std::vector<PooledBuf> temps;   // build temporaries, held until the final synchronisation
     ix->sample_dev.alloc((size_t)n_sample * 8);   // kept for export
     {
-      PinnedBuf& stg = sample_staging((size_t)n_sample * 8);
-      int64_t* dst = stg.as<int64_t>();
-      host_parallel(n_sample, [&](int64_t b, int64_t e, int) {
-        std::memcpy(dst + b, sample_src + b, (size_t)(e - b) * 8);
-      });
-      PDET_HIP(hipMemcpyAsync(ix->sample_dev.p, dst, ix->sample_dev.bytes, hipMemcpyHostToDevice,
-                              s));
+      if (!staging) {   // a drawn sample
+        staging = &sample_staging((size_t)n_sample * 8);
+        std::memcpy(staging->as<int64_t>(), sample_src, (size_t)n_sample * 8);
+      }
+      PDET_HIP(hipMemcpyAsync(ix->sample_dev.p, staging->p, ix->sample_dev.bytes,
+                              hipMemcpyHostToDevice, s));
     }
     const DevBuf& sid = ix->sample_dev;
     PooledBuf ps((size_t)LK * n_sample * 4);   // sampled hash values, column-major
