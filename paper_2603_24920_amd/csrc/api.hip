@@ -492,6 +492,7 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     }
     const DevBuf& sid = ix->sample_dev;
     PooledBuf ps((size_t)LK * n_sample * 4);   // sampled hash values, column-major
+    PooledBuf smm((size_t)2 * LK * 4);          // their column min / max
     pdet_timing& tm = timer().t;
     if (timer().on) {
       tm.build_sample_ms = tm.build_sort_ms = tm.build_encode_ms = 0.0;
@@ -500,7 +501,10 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     ix->B.alloc((size_t)LK * (ix->Nr + 1) * 4);
     {
       Span sp(s, &tm.build_sample_ms);
-      project_sample(*ix, sid.as<int64_t>(), n_sample, ps.as<float>(), n_sample, s);
+      PDET_HIP(hipMemsetAsync(smm.ptr(), 0xff, (size_t)LK * 4, s));
+      PDET_HIP(hipMemsetAsync(smm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));
+      project_sample(*ix, sid.as<int64_t>(), n_sample, ps.as<float>(), n_sample,
+                     smm.as<uint32_t>(), s);
       sp.finish();
     }
     {
@@ -510,7 +514,7 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
                            ix->B.as<float>(), temps, s);
       else
         select_breakpoints(ps.as<float>(), LK, n_sample, n_sample, ix->Nr,
-                           ix->B.as<float>(), temps, s);
+                           ix->B.as<float>(), smm.as<uint32_t>(), temps, s);
       sp.finish();
     }
 

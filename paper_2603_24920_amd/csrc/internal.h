@@ -201,8 +201,10 @@ class Span {
 // project.hip
 std::vector<float> pad_projection(const float* proj, int d, int L, int K);
 void project_points(const Index& ix, const float* X, int64_t m, float* out, hipStream_t s);
+// The sampled rows' hash values (column-major, ld) and their column min / max in mm
+// ([2][L*K] ordered uints, initialised by the caller to the empty range).
 void project_sample(const Index& ix, const int64_t* rows, int64_t m, float* out, int64_t ld,
-                    hipStream_t s);
+                    uint32_t* mm, hipStream_t s);
 void encode_points(const Index& ix, hipStream_t s);
 // Encodes the m rows of X (points being inserted) with the index's breakpoints into
 // codes [L][m][KP] and first-layer keys [L][m], widening the column extremes (ix.colmm) and
@@ -212,10 +214,11 @@ void encode_rows(const Index& ix, const float* X, int64_t m, uint8_t* codes, uin
 
 // sort.hip
 // Interior breakpoints B[col][u] (u = 1..Nr-1) of the sampled hash values keys[col][0..ns)
-// (column stride ld): the exact order statistics of 1-based rank floor(ns/Nr)*u.
+// (column stride ld): the exact order statistics of 1-based rank floor(ns/Nr)*u. mm holds
+// the columns' min / max ([2][ncols] ordered uints, from the sample projection).
 // Temporaries go to `keep`, which the caller holds until its stream has synchronised.
 void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,
-                        std::vector<PooledBuf>& keep, hipStream_t s);
+                        const uint32_t* mm, std::vector<PooledBuf>& keep, hipStream_t s);
 // Static (iSAX-style) interior breakpoints mu + sigma * Phi^-1((u)/Nr), u = 1..Nr-1, from the
 // columns' sampled mean and population standard deviation (synchronises `s`).
 void static_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
   // column min / max of this workgroup (ordered uints), reduced in LDS before one global
   // atomic per column: all workgroups update the same few cache lines
   __shared__ uint32_t wg_min[NT * 16], wg_max[NT * 16];
-  if (MODE == MODE_ENCODE && threadIdx.x < NT * 16) {
+  if ((MODE == MODE_ENCODE || MODE == MODE_SAMPLE) && threadIdx.x < NT * 16) {
     wg_min[threadIdx.x] = float_to_ordered(INFINITY);
     wg_max[threadIdx.x] = float_to_ordered(-INFINITY);
   }
@@ -232,8 +232,13 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
           for (int i = 0; i < 4; ++i) {
             const int64_t p = pbase + i;
             if (p < a.m) {
-              if (MODE == MODE_PROJECT) a.out[p * (int64_t)(a.L * a.K) + gcol] = acc[t][i];
-              else a.out[(int64_t)gcol * a.ld + p] = acc[t][i];
+              if (MODE == MODE_PROJECT) {
+                a.out[p * (int64_t)(a.L * a.K) + gcol] = acc[t][i];
+              } else {
+                a.out[(int64_t)gcol * a.ld + p] = acc[t][i];
+                vmin[t] = fminf(vmin[t], acc[t][i]);
+                vmax[t] = fmaxf(vmax[t], acc[t][i]);
+              }
             }
           }
         }
@@ -282,9 +287,10 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
     }
   }
 
-  if constexpr (MODE == MODE_ENCODE) {
-    if (__ballot(nonfin) && lane == 0) atomicOr(a.nonfinite, 1u);
-    // column min / max over all points (outer breakpoints B(1), B(Nr+1))
+  if constexpr (MODE == MODE_ENCODE || MODE == MODE_SAMPLE) {
+    if (MODE == MODE_ENCODE && __ballot(nonfin) && lane == 0) atomicOr(a.nonfinite, 1u);
+    // column min / max over all points (outer breakpoints B(1), B(Nr+1)), or over the
+    // sampled points (the range of the breakpoint selection's buckets)
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       float lo = vmin[t], hi = vmax[t];
@@ -346,9 +352,10 @@ static int group_nt(int trees) { return trees <= 1 ? 1 : (trees <= 2 ? 2 : 4); }
 
 // Encoded rows go to codes [L][stride][KP] and keys [L][stride] (the index's own arrays
 // unless given).
+// MODE_SAMPLE: the column min / max of the sampled hash values go to mm ([2][L*K] ordered).
 void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* rows, int mode,
                     float* out, int64_t ld, hipStream_t s, uint8_t* codes = nullptr,
-                    uint16_t* keys = nullptr, int64_t stride = 0) {
+                    uint16_t* keys = nullptr, int64_t stride = 0, uint32_t* mm = nullptr) {
   for (int t0 = 0; t0 < ix.L; t0 += TREES_PER_LAUNCH) {
     const int trees = std::min(TREES_PER_LAUNCH, ix.L - t0);
     const int nt = group_nt(trees);
@@ -360,8 +367,8 @@ void run_projection(const Index& ix, const float* X, int64_t m, const int64_t* r
     a.Btab = ix.B.as<float>();
     a.codes = codes ? codes : ix.codes.as<uint8_t>();
     a.flkey = codes ? keys : ix.flkey.as<uint16_t>();
-    a.colmin = ix.colmm.as<uint32_t>();
-    a.colmax = ix.colmm.as<uint32_t>() + ix.L * ix.K;
+    a.colmin = mode == MODE_SAMPLE ? mm : ix.colmm.as<uint32_t>();
+    a.colmax = (mode == MODE_SAMPLE ? mm : ix.colmm.as<uint32_t>()) + ix.L * ix.K;
     a.nonfinite = ix.nonfinite.as<uint32_t>();
     // A is stored per launch group: [group][d][NC]
     a.A = ix.A.as<float>() + (int64_t)(t0 / TREES_PER_LAUNCH) * ix.d * (TREES_PER_LAUNCH * 16);
@@ -382,8 +389,8 @@ void project_points(const Index& ix, const float* X, int64_t m, float* out, hipS
   run_projection(ix, X, m, nullptr, MODE_PROJECT, out, 0, s);
 }
 void project_sample(const Index& ix, const int64_t* rows, int64_t m, float* out, int64_t ld,
-                    hipStream_t s) {
-  run_projection(ix, ix.X, m, rows, MODE_SAMPLE, out, ld, s);
+                    uint32_t* mm, hipStream_t s) {
+  run_projection(ix, ix.X, m, rows, MODE_SAMPLE, out, ld, s, nullptr, nullptr, 0, mm);
 }
 void encode_points(const Index& ix, hipStream_t s) {
   run_projection(ix, ix.X, ix.n, nullptr, MODE_ENCODE, nullptr, 0, s);

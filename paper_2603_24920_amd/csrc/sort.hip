@@ -3,7 +3,7 @@
 // The paper selects the Nr-1 interior order statistics of each sampled column with rounds
 // of QuickSelect. Here each column's order statistics B(z) = C-up(m*(z-1)), m = floor(ns/Nr)
 // (1-based ranks) are selected without sorting the column:
-//  1. the column's sample min and max;
+//  1. the column's sample min and max (reduced by the sample projection);
 //  2. a histogram of NB equal-width value buckets between them (bucket index is a
 //     monotone function of the value, so bucket order is value order);
 //  3. per target rank, its bucket and its rank inside the bucket (a scan of the histogram);
@@ -24,33 +24,6 @@ constexpr int GATHER_KEYS = 4096;   // keys per gather / histogram block
 __device__ inline int bucket_of(float v, float lo, float scale) {
   const int b = (int)__fmul_rn(__fsub_rn(v, lo), scale);   // no contraction: one rounding each
   return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
-}
-
-// Column min / max of the sample (ordered uints; mm[col] = min, mm[ncols + col] = max): a
-// few blocks per column, reduced in the block, two atomics per block.
-__global__ __launch_bounds__(256) void col_minmax(const float* keys, int64_t ld, int64_t ns,
-                                                  int ncols, uint32_t* mm) {
-  __shared__ float wlo[4], whi[4];
-  const int col = blockIdx.y;
-  const float* c = keys + (int64_t)col * ld;
-  float lo = INFINITY, hi = -INFINITY;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ns; i += (int64_t)gridDim.x * 256) {
-    const float v = c[i];
-    lo = fminf(lo, v);
-    hi = fmaxf(hi, v);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fminf(lo, __shfl_xor(lo, o));
-    hi = fmaxf(hi, __shfl_xor(hi, o));
-  }
-  if ((threadIdx.x & 63) == 0) { wlo[threadIdx.x >> 6] = lo; whi[threadIdx.x >> 6] = hi; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 4; ++w) { lo = fminf(lo, wlo[w]); hi = fmaxf(hi, whi[w]); }
-    atomicMin(&mm[col], float_to_ordered(lo));
-    atomicMax(&mm[ncols + col], float_to_ordered(hi));
-  }
 }
 
 __device__ inline void col_range(const uint32_t* mm, int ncols, int col, float& lo, float& scale) {
@@ -385,27 +358,21 @@ void fill_f32(float* p, int64_t count, float v, hipStream_t s) {
 }
 
 void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, int Nr, float* B,
-                        std::vector<PooledBuf>& keep, hipStream_t s) {
+                        const uint32_t* mm, std::vector<PooledBuf>& keep, hipStream_t s) {
   const int64_t m = ns / Nr;
-  PooledBuf mm((size_t)2 * ncols * 4), hist((size_t)ncols * NB * 4), fill((size_t)ncols * NB * 4);
+  PooledBuf hist((size_t)ncols * NB * 4), fill((size_t)ncols * NB * 4);
   PooledBuf boff((size_t)ncols * NB * 4), tb((size_t)ncols * (Nr - 1) * 4);
   PooledBuf tr((size_t)ncols * (Nr - 1) * 4), gbuf((size_t)ncols * ns * 4);
-  PDET_HIP(hipMemsetAsync(mm.ptr(), 0xff, (size_t)ncols * 4, s));
-  PDET_HIP(hipMemsetAsync(mm.as<uint32_t>() + ncols, 0, (size_t)ncols * 4, s));
   PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
   PDET_HIP(hipMemsetAsync(fill.ptr(), 0, fill.bytes(), s));
-  const unsigned mmg = (unsigned)std::min<int64_t>(cdiv(ns, 256 * 32), 64);
-  hipLaunchKernelGGL(col_minmax, dim3(mmg, ncols), dim3(256), 0, s, keys, ld, ns, ncols,
-                     mm.as<uint32_t>());
-  PDET_HIP(hipGetLastError());
   const dim3 kg(cdiv(ns, GATHER_KEYS), ncols);
-  hipLaunchKernelGGL(col_hist, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm.as<uint32_t>(),
+  hipLaunchKernelGGL(col_hist, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm,
                      hist.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(col_targets, dim3(ncols), dim3(1024), 0, s, hist.as<uint32_t>(), Nr, m,
                      tb.as<int32_t>(), tr.as<uint32_t>(), boff.as<int32_t>());
   PDET_HIP(hipGetLastError());
-  hipLaunchKernelGGL(col_gather, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm.as<uint32_t>(),
+  hipLaunchKernelGGL(col_gather, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm,
                      boff.as<int32_t>(), fill.as<uint32_t>(), gbuf.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(col_select, dim3(Nr - 1, ncols), dim3(SEL_THREADS), 0, s,
@@ -413,7 +380,7 @@ void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
                      gbuf.as<uint32_t>(), ns, Nr, B);
   PDET_HIP(hipGetLastError());
   // the kernels above still use the temporaries: the caller keeps them until it synchronises
-  for (PooledBuf* t : {&mm, &hist, &fill, &boff, &tb, &tr, &gbuf}) keep.push_back(std::move(*t));
+  for (PooledBuf* t : {&hist, &fill, &boff, &tb, &tr, &gbuf}) keep.push_back(std::move(*t));
 }
 
 double normal_quantile(double p) {
