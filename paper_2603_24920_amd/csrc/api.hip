@@ -284,6 +284,7 @@ int64_t pdet_index::device_bytes() const {
   int64_t b = A.bytes + B.bytes + colmm.bytes + codes.bytes + H.bytes + perm.bytes + leafrow.bytes +
               xbf16.bytes + xfp8.bytes + xscale.bytes + leaf_arena.bytes + sample_dev.bytes +
               nonfinite.bytes + empt.bytes + eoff.bytes + emat.bytes;
+  b += small.bytes - A.bytes - B.bytes - colmm.bytes - nonfinite.bytes;   // (views of small)
   auto own = [](const pdet::DevBuf& x) { return x.owned ? (int64_t)x.bytes : 0; };
   for (int i = 0; i < PDET_MAX_L; ++i)
     b += own(leaf_start[i]) + own(leaf_count[i]) + own(leaf_hidx[i]) + own(box[i]) +
@@ -478,7 +479,20 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
 
     // projection matrix and sampled projections
     const std::vector<float> Ap = pad_projection(ix->proj_host.data(), d, ix->L, ix->K);
-    ix->A.alloc(Ap.size() * 4);
+    {
+      // the small per-index arrays share one block (a whole number of MiB, so that the
+      // block cache hands the same block to the next index of this shape)
+      auto part = [](size_t b) { return (b + 255) & ~size_t(255); };
+      const size_t a_b = Ap.size() * 4, b_b = (size_t)LK * (ix->Nr + 1) * 4,
+                   mm_b = (size_t)2 * LK * 4;
+      const size_t tot = part(a_b) + part(b_b) + part(mm_b) + part(4);
+      ix->small.alloc((tot + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1));
+      char* q = ix->small.as<char>();
+      ix->A.view(q, a_b); q += part(a_b);
+      ix->B.view(q, b_b); q += part(b_b);
+      ix->colmm.view(q, mm_b); q += part(mm_b);
+      ix->nonfinite.view(q, 4);
+    }
     PDET_HIP(hipMemcpyAsync(ix->A.p, Ap.data(), Ap.size() * 4, hipMemcpyHostToDevice, s));
     std::vector<PooledBuf> temps;   // build temporaries, held until the final synchronisation
     ix->sample_dev.alloc((size_t)n_sample * 8);   // kept for export
@@ -498,7 +512,6 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
       tm.build_sample_ms = tm.build_sort_ms = tm.build_encode_ms = 0.0;
       tm.build_tree_ms = tm.build_lowp_ms = 0.0;
     }
-    ix->B.alloc((size_t)LK * (ix->Nr + 1) * 4);
     {
       Span sp(s, &tm.build_sample_ms);
       PDET_HIP(hipMemsetAsync(smm.ptr(), 0xff, (size_t)LK * 4, s));
@@ -519,8 +532,6 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     }
 
     // encode every point; column extremes give the outer breakpoints
-    ix->colmm.alloc((size_t)2 * LK * 4);
-    ix->nonfinite.alloc(4);
     PDET_HIP(hipMemsetAsync(ix->nonfinite.p, 0, 4, s));
     PDET_HIP(hipMemsetAsync(ix->colmm.p, 0xff, (size_t)LK * 4, s));
     PDET_HIP(hipMemsetAsync(ix->colmm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));

@@ -41,11 +41,11 @@ void set_error(const std::string& msg);
 // Process-wide cache of large device blocks (api.hip). Freeing a block that kernels have
 // touched and allocating again costs the driver tens of milliseconds per GiB here, which a
 // process that rebuilds indexes or re-sizes query scratch pays on every cycle; blocks of at
-// least CACHE_MIN_BYTES are therefore kept on release and handed out again for a request of
+// least CACHE_MIN_BYTES (1 MiB) are therefore kept on release and handed out again for a request of
 // exactly their size on the same device. A cached block is taken only after its device was
 // idle (as hipFree waits), so no kernel still uses it. hipMalloc failures flush the cache and
 // retry; pdet_release_cache() returns every cached block to the driver.
-constexpr size_t CACHE_MIN_BYTES = size_t(32) << 20;
+constexpr size_t CACHE_MIN_BYTES = size_t(1) << 20;
 bool cache_take(size_t bytes, void** p);
 bool cache_give(void* p, size_t bytes, int device);
 void cache_flush();

@@ -53,6 +53,7 @@ struct pdet_index {
   std::vector<float> proj_host;    // the projection [d][L*K] (given or drawn)
   pdet::DevBuf sample_dev;         // int64 [n_sample]: the sampled ids (given or drawn)
 
+  pdet::DevBuf small;              // one block holding the views A, B, colmm and nonfinite
   pdet::DevBuf A;                  // float32 padded projection, see pad_projection()
   pdet::DevBuf B;                  // float32 [L*K][Nr+1] breakpoints
   pdet::DevBuf colmm;              // uint32 [2][L*K] ordered min / max of every column

@@ -1271,7 +1271,9 @@ void finish_trees(Index& ix, const uint32_t* cnt_at, const uint16_t* hidx_at, De
     arena += part((size_t)nl[i] * 4) * 2 + part((size_t)nl[i] * KP * 2) +
              part((size_t)nl[i] * 2 * K * 4) + part(ng * 2 * K * 4);
   }
-  ix.leaf_arena.alloc(arena);
+  // a whole number of MiB: the next index of this shape (whose leaf counts differ a little)
+  // then gets the same block from the block cache
+  ix.leaf_arena.alloc((arena + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1));
   char* cur = ix.leaf_arena.as<char>();
   auto take = [&](DevBuf& v, size_t b) { v.view(cur, b); cur += part(b); };
   for (int i = 0; i < L; ++i) {
