@@ -1046,6 +1046,33 @@ uint32_t* readback_words() {
   return w.p;
 }
 
+// Three streams (default priority) and their fork / join events per thread and device, kept
+// until the thread ends.
+struct SideStreams {
+  int dev = -1;
+  hipStream_t st[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+  void clear() {
+    for (auto& x : st) if (x) { (void)hipStreamDestroy(x); x = nullptr; }
+    for (auto& e : join) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    if (fork) { (void)hipEventDestroy(fork); fork = nullptr; }
+  }
+  ~SideStreams() { clear(); }
+};
+SideStreams& side_streams() {
+  static thread_local SideStreams ss;
+  int dev = 0;
+  PDET_HIP(hipGetDevice(&dev));
+  if (ss.dev != dev) {
+    ss.clear();
+    for (auto& x : ss.st) PDET_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    PDET_HIP(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+    for (auto& e : ss.join) PDET_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ss.dev = dev;
+  }
+  return ss;
+}
+
 void first_layer_sort(int L, int K, int64_t n, uint16_t* keys, const uint4* codes, uint4* rows0,
                       int32_t* ids0, uint4* rows1, int32_t* ids1, uint16_t* keys1,
                       uint32_t* start, uint32_t* end, PooledBuf& h8, PooledBuf& o8,
@@ -1081,6 +1108,7 @@ void first_layer_sort(int L, int K, int64_t n, uint16_t* keys, const uint4* code
 }
 
 void build_trees(Index& ix, hipStream_t s) {
+  const hipStream_t s_main = s;
   const int64_t n = ix.n;
   const int L = ix.L, K = ix.K, bits = ix.bits;
   const int64_t NK = 1ll << K;
@@ -1204,12 +1232,18 @@ void build_trees(Index& ix, hipStream_t s) {
   }
   {
     // one launch per size class, one node per block, in the frontier form when the class
-    // holds at most FR_MAXS open nodes
+    // holds at most FR_MAXS open nodes. The classes touch disjoint nodes: classes 0-2 run on
+    // side streams beside class 3 on the build's stream, so that one class's tail overlaps
+    // the others' work.
+    SideStreams& ss = side_streams();
+    PDET_HIP(hipEventRecord(ss.fork, s));
+    for (int k = 0; k < 3; ++k) PDET_HIP(hipStreamWaitEvent(ss.st[k], ss.fork, 0));
     auto finish = [&](auto cap_c, auto nt_c, int cl) {
       constexpr int CAP = decltype(cap_c)::value, NT = decltype(nt_c)::value;
       static_assert(CAP <= LDS_SEG_CAP, "class");
       const uint32_t nm = hc[4 + cl];
       if (!nm) return;
+      const hipStream_t s = cl < 3 ? ss.st[cl] : s_main;
       const Seg* list = mid.as<Seg>() + mid_off[cl];
       const int below = CLS_BELOW[cl];
       const int open_max = CAP / (ix.max_leaf + 1);
@@ -1224,10 +1258,14 @@ void build_trees(Index& ix, hipStream_t s) {
                            bits, ix.max_leaf, below, lo);
       PDET_HIP(hipGetLastError());
     };
-    finish(std::integral_constant<int, 256>{}, std::integral_constant<int, 64>{}, 0);
-    finish(std::integral_constant<int, 512>{}, std::integral_constant<int, 128>{}, 1);
-    finish(std::integral_constant<int, 1024>{}, std::integral_constant<int, 256>{}, 2);
     finish(std::integral_constant<int, LDS_SEG_CAP>{}, std::integral_constant<int, 512>{}, 3);
+    finish(std::integral_constant<int, 1024>{}, std::integral_constant<int, 256>{}, 2);
+    finish(std::integral_constant<int, 512>{}, std::integral_constant<int, 128>{}, 1);
+    finish(std::integral_constant<int, 256>{}, std::integral_constant<int, 64>{}, 0);
+    for (int k = 0; k < 3; ++k) {
+      PDET_HIP(hipEventRecord(ss.join[k], ss.st[k]));
+      PDET_HIP(hipStreamWaitEvent(s, ss.join[k], 0));
+    }
   }
 
   finish_trees(ix, cnt_at.as<uint32_t>(), hidx_at.as<uint16_t>(), scan_tmp, s);
