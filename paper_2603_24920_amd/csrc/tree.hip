@@ -120,19 +120,43 @@ __device__ inline bool fully_refined(const uint8_t* depth, int K, int bits) {
   return f;
 }
 
+// A slot of an appendable list for every lane that wants one; the lanes of a wave that
+// append to the same list share one atomic. Every lane of the wave must call it.
+__device__ inline uint32_t append_slot(uint32_t* ctr, bool want) {
+  const uint64_t m = __ballot(want);
+  if (!m) return 0u;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0u;
+  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  return base + lanes_below_mask(m);
+}
+
+// A node to its place: a leaf (records at its start; ids copied later if they sit in buffer
+// 1), an LDS size class, or the next global level (with its bit counts, if known). Called by
+// every lane of the wave; lanes with active == false take no place.
 __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, const LeafOut& lo,
-                      const Lists& li, const uint32_t* counts = nullptr) {
-  if (s.count <= 0) return;
-  if (s.count <= max_leaf || fully_refined(s.depth, K, bits)) {
-    emit_leaf(lo, n, s.tree, s.start, s.count, s.depth, s.prefix, K);
-    if (s.buf == 1) li.copies[atomicAdd(li.n_copies, 1u)] = Copy{s.tree, s.start, s.count};
-  } else if (s.count <= LDS_SEG_CAP) {
-    const int c = size_class(s.count);
-    li.mid[c][atomicAdd(&li.n_mid[c], 1u)] = s;
-  } else {
-    const uint32_t k = atomicAdd(li.n_big_next, 1u);
+                      const Lists& li, bool active, const uint32_t* counts = nullptr) {
+  active = active && s.count > 0;
+  const bool leaf = active && (s.count <= max_leaf || fully_refined(s.depth, K, bits));
+  const bool mid = active && !leaf && s.count <= LDS_SEG_CAP;
+  const bool big = active && !leaf && !mid;
+  const int c = mid ? size_class(s.count) : -1;
+  if (leaf) emit_leaf(lo, n, s.tree, s.start, s.count, s.depth, s.prefix, K);
+  const uint32_t cp = append_slot(li.n_copies, leaf && s.buf == 1);
+  if (leaf && s.buf == 1) li.copies[cp] = Copy{s.tree, s.start, s.count};
+#pragma unroll
+  for (int cl = 0; cl < NCLS; ++cl) {
+    const uint32_t k = append_slot(&li.n_mid[cl], c == cl);
+    if (c == cl) li.mid[cl][k] = s;
+  }
+  const uint32_t k = append_slot(li.n_big_next, big);
+  uint32_t pts = big ? (uint32_t)s.count : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pts += __shfl_xor(pts, o);
+  if ((threadIdx.x & 63) == 0 && pts) atomicAdd(li.pts_big_next, pts);
+  if (big) {
     li.big_next[k] = s;
-    atomicAdd(li.pts_big_next, (uint32_t)s.count);
     if (counts && li.cnt_next)
       for (int j = 0; j < KP; ++j) li.cnt_next[(int64_t)k * KP + j] = counts[j];
   }
@@ -311,13 +335,12 @@ __global__ void rk_counts(const uint32_t* start, const uint32_t* end, int64_t to
 __global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, int K, int bits,
                             int max_leaf, int64_t n, LeafOut lo, Lists li) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ((int64_t)L << K)) return;
-  const uint32_t c = hist[g];
-  if (c == 0) return;
+  const bool in = g < ((int64_t)L << K);   // (every lane routes: the appends are per wave)
+  const uint32_t c = in ? hist[g] : 0u;
   const uint32_t key = (uint32_t)(g & ((1ll << K) - 1));
   Seg s;
   s.tree = (int32_t)(g >> K);
-  s.start = (int32_t)off[g];
+  s.start = in ? (int32_t)off[g] : 0;
   s.count = (int32_t)c;
   s.buf = 0;
   s.pad[0] = s.pad[1] = s.pad[2] = 0;
@@ -325,7 +348,7 @@ __global__ void fl_segments(const uint32_t* hist, const uint32_t* off, int L, in
     s.depth[j] = (j < K) ? 1 : (uint8_t)bits;
     s.prefix[j] = (j < K) ? (uint8_t)((key >> (K - 1 - j)) & 1) : 0;
   }
-  route(s, K, bits, max_leaf, n, lo, li);
+  route(s, K, bits, max_leaf, n, lo, li, in && c > 0);
 }
 
 // ---- global passes over nodes larger than LDS_SEG_CAP (contiguous rows, no gathers)
@@ -489,8 +512,9 @@ __global__ __launch_bounds__(256) void seg_split(const Seg* segs, const Unit* un
 __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, const uint32_t* c0,
                              const uint32_t* cntn, int K, int bits, int max_leaf, int64_t n,
                              LeafOut lo, Lists li) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nseg) return;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i0 < nseg;   // (every lane routes: the appends are per wave)
+  const int i = in ? i0 : 0;
   const Seg s = segs[i];
   const int j = split[i];
   Seg a = s, b = s;
@@ -508,8 +532,8 @@ __global__ void seg_children(const Seg* segs, int nseg, const int32_t* split, co
       b.prefix[jj] = (uint8_t)(s.prefix[jj] * 2 + 1);
     }
   }
-  route(a, K, bits, max_leaf, n, lo, li, cntn + (int64_t)i * 2 * KP);
-  route(b, K, bits, max_leaf, n, lo, li, cntn + ((int64_t)i * 2 + 1) * KP);
+  route(a, K, bits, max_leaf, n, lo, li, in, cntn + (int64_t)i * 2 * KP);
+  route(b, K, bits, max_leaf, n, lo, li, in, cntn + ((int64_t)i * 2 + 1) * KP);
 }
 
 // Ids of leaves whose data sits in buffer 1 go to the permutation (buffer 0).
