@@ -999,14 +999,35 @@ __global__ void leaf_fill(const uint32_t* cnt_at, const uint16_t* hidx_at, int64
 // Leaf ordinal of every point: position p lies in the leaf that starts at the last
 // recorded start <= p, whose ordinal is the exclusive start count at p, plus one if p
 // itself starts a leaf, minus one.
+// Per-point leaf ordinals, tree-major: leaf_soa[tree][id]. One launch covers the points whose
+// id lies in window `win` of 2^LEAF_WIN ids, so its writes stay within 4 * 2^LEAF_WIN bytes of
+// each tree's array (small enough for the last-level cache to gather the 4-byte writes into
+// whole lines); every window's launch reads the permutation in full, the rest only for its ids.
+constexpr int LEAF_WIN = 25;
+
 __global__ void leaf_of_kernel(const uint32_t* cnt_at, const uint32_t* ord, const int32_t* perm,
-                               int64_t n, int L, int32_t* leaf_of) {
+                               int64_t n, int win, int32_t* leaf_soa) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int tree = blockIdx.y;
   if (p >= n) return;
   const int64_t g = (int64_t)tree * n + p;
-  const int32_t leaf = (int32_t)ord[g] + (cnt_at[g] ? 1 : 0) - 1;
-  leaf_of[(int64_t)perm[g] * L + tree] = leaf;
+  const int32_t id = perm[g];
+  if ((id >> LEAF_WIN) != win) return;
+  leaf_soa[(int64_t)tree * n + id] = (int32_t)ord[g] + (cnt_at[g] ? 1 : 0) - 1;
+}
+
+// leaf_of[id][tree] from the tree-major form: coalesced reads of every tree's array, one
+// row of L ordinals written per point.
+__global__ void leaf_rows_by_id(const int32_t* leaf_soa, int64_t n, int L, int32_t* leaf_of) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (L == 4) {
+    const int4 v = make_int4(leaf_soa[i], leaf_soa[n + i], leaf_soa[2 * n + i],
+                             leaf_soa[3 * n + i]);
+    *reinterpret_cast<int4*>(leaf_of + i * 4) = v;
+    return;
+  }
+  for (int t = 0; t < L; ++t) leaf_of[i * L + t] = leaf_soa[(int64_t)t * n + i];
 }
 
 // leafrow[i][p] = leaf_of[perm_i[p]]: the leaf ordinals of a point in every tree, stored in
@@ -1312,9 +1333,14 @@ void finish_trees(Index& ix, const uint32_t* cnt_at, const uint16_t* hidx_at, De
   hipEvent_t counts_ready;
   PDET_HIP(hipEventCreateWithFlags(&counts_ready, hipEventDisableTiming));
   PDET_HIP(hipEventRecord(counts_ready, s));
-  PooledBuf leaf_of((size_t)n * L * 4);
-  hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at,
-                     flags.as<uint32_t>(), ix.perm.as<int32_t>(), n, L, leaf_of.as<int32_t>());
+  PooledBuf leaf_of((size_t)n * L * 4), leaf_soa((size_t)n * L * 4);
+  const int nwin = (int)((n + (int64_t(1) << LEAF_WIN) - 1) >> LEAF_WIN);
+  for (int w = 0; w < nwin; ++w)
+    hipLaunchKernelGGL(leaf_of_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at,
+                       flags.as<uint32_t>(), ix.perm.as<int32_t>(), n, w, leaf_soa.as<int32_t>());
+  PDET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(leaf_rows_by_id, dim3(cdiv(n, 256)), dim3(256), 0, s, leaf_soa.as<int32_t>(),
+                     n, L, leaf_of.as<int32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(leafrow_kernel, dim3(cdiv(n, 256), L), dim3(256), 0, s,
                      ix.perm.as<int32_t>(), leaf_of.as<int32_t>(), n, L, ix.leafrow.as<int32_t>());
