@@ -245,6 +245,29 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
       }
     } else {
       uint8_t* st = stage + wave * (16 * NT * KP);          // [16 points][NT][KP]
+      // descend the implicit search trees of the lane's NT x 4 hash values together, one
+      // level per step: the 4*NT table reads of a step are issued before any compare (one
+      // search after another would wait for every read). After bits steps,
+      // node - Nr = #{B(z) <= h}. Lanes past the K columns search column K-1 and discard it.
+      int node[NT][4];
+      const int ccol = min(col16, a.K - 1);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) node[t][i] = 1;
+      for (int step = 0; step < a.bits; ++step) {
+        float b[NT][4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float* tab = Bs + (t * a.K + ccol) * bstride;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b[t][i] = tab[node[t][i]];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) node[t][i] = 2 * node[t][i] + (b[t][i] <= acc[t][i] ? 1 : 0);
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -253,11 +276,7 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
           uint8_t code = 0;
           if (col16 < a.K && t < a.ntrees) {
             const float h = acc[t][i];
-            const float* tab = Bs + (t * a.K + col16) * bstride;
-            // descend the implicit tree: after bits steps, node - Nr = #{B(z) <= h}
-            int node = 1;
-            for (int step = 0; step < a.bits; ++step) node = 2 * node + (tab[node] <= h ? 1 : 0);
-            code = static_cast<uint8_t>(node - a.Nr);
+            code = static_cast<uint8_t>(node[t][i] - a.Nr);
             if (pbase + i < a.m) {
               vmin[t] = fminf(vmin[t], h);
               vmax[t] = fmaxf(vmax[t], h);
