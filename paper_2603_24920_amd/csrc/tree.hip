@@ -85,6 +85,51 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
+// Sum over a whole wave (every lane active): row sums by DPP moves (quad swaps, half-row and
+// row mirrors), then the four row totals read into scalar registers; the result is uniform.
+__device__ inline uint32_t wave_total(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
+// Inclusive scan over a whole wave (every lane active): scans of the 16-lane rows by
+// row_shr:1,2,4,8 (a lane without a source adds 0), then the row totals carried on by
+// row_bcast:15 (into rows 1 and 3) and row_bcast:31 (into rows 2 and 3).
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+  return x;
+}
+
+// Exclusive scan of one uint32 per thread over a workgroup of NT threads (every thread
+// calls it; sh holds NT/64 words): wave scans by DPP, the wave totals through LDS, each
+// wave adding those before it. Two barriers.
+template <int NT>
+__device__ inline uint32_t block_excl_scan_dpp(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  if ((threadIdx.x & 63) == 63) sh[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint32_t t = sh[w];
+    before += (w < wave) ? t : 0u;
+    tot += t;
+  }
+  *total = uni(tot);
+  __syncthreads();   // sh is free for the next scan
+  return uni(before) + incl - v;
+}
+
 // 1 in every byte of w that is not zero, 0 in the others.
 __device__ inline uint32_t nonzero_bytes(uint32_t w) {
   return ((((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u) >> 7;
@@ -560,6 +605,12 @@ struct SegL {
 // Instantiated per size class (count in (below, CAP], NT threads): LDS and threads scale
 // with the node, so small nodes run many workgroups per CU. Blocks whose node is outside
 // the class return at once.
+//
+// A level: each thread finds the open node of each of its PER consecutive positions and
+// reads their rows once (kept in registers through the level); 1. next-bit counts per open
+// node and dimension; 2. split dimension per node; 3. stable partition of every node by its
+// split bit (a workgroup scan of the bit-0 flags); 4. children, open ones listed for the next
+// level. The position order lives in one of two LDS arrays, the partition writing the other.
 template <int CAP, int NT, int MAXS>
 __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, int64_t n, int K,
                                                        int bits, int max_leaf, int below,
@@ -567,14 +618,14 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
   constexpr int PER = CAP / NT;           // consecutive positions per thread in the scan
   static_assert(PER * NT == CAP && PER <= 32 && MAXS <= NT, "class shape");
   __shared__ uint4 rows[CAP];
-  __shared__ uint16_t ord[CAP];
-  __shared__ uint16_t tmp[CAP];
+  __shared__ uint16_t ordb[2][CAP];
   __shared__ SegL segs[2][MAXS];
   __shared__ uint4 smask[MAXS];
   __shared__ uint32_t cnt[MAXS][KP];
   __shared__ uint32_t zstart[MAXS];
   __shared__ uint16_t c0s[MAXS];
   __shared__ uint8_t jsel[MAXS];
+  __shared__ uint4 bmask[MAXS];   // the split bit of a node's code rows (one bit set)
   __shared__ uint32_t sh_scan[NT / 64 + 1];
   __shared__ uint32_t s_nact;
 
@@ -586,7 +637,7 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
   const int32_t* isrc = b.ids[s.buf] + tb + s.start;
   for (int t = threadIdx.x; t < count; t += NT) {
     rows[t] = rsrc[t];
-    ord[t] = (uint16_t)t;
+    ordb[0][t] = (uint16_t)t;
   }
   if (threadIdx.x == 0) {
     SegL r;
@@ -598,35 +649,12 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  int cur = 0;
+  const int p0 = threadIdx.x * PER;
+  int cur = 0, co = 0;   // node list and position order of this level
   for (;;) {
     const int nact = (int)uni(s_nact);
     if (nact == 0) break;
     const SegL* S = segs[cur];
-    // open node holding position p (binary search over the sorted starts), or -1
-    auto find = [&](int p) -> int {
-      int lo = 0, hi = nact;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (S[mid].start <= p) lo = mid; else hi = mid;
-      }
-      return (S[lo].start <= p && p < S[lo].start + S[lo].count) ? lo : -1;
-    };
-    // open node holding position p0 and the first open node starting after p0
-    auto locate = [&](int p0, int& sg, int& snext) {
-      sg = (p0 < count) ? find(p0) : -1;
-      int lo2 = 0, hi2 = nact;
-      while (lo2 < hi2) {
-        const int md = (lo2 + hi2) >> 1;
-        if (S[md].start <= p0) lo2 = md + 1; else hi2 = md;
-      }
-      snext = lo2;
-    };
-    // 1. next-bit counts per open node and dimension. Byte j of a code row is dimension
-    //    j's code; a node's mask keeps the next unrefined bit of each of its dimensions, so
-    //    a masked row has at most one bit per byte. A thread sums its PER consecutive
-    //    positions as byte counters, one per dimension; each wave then adds up the counters
-    //    of its lanes in one node (as 16-bit fields) and adds them to the node's counts.
     if ((int)threadIdx.x < nact) {
       const SegL& g = S[threadIdx.x];
       uint32_t m[4] = {0u, 0u, 0u, 0u};
@@ -636,58 +664,92 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
 #pragma unroll
       for (int j = 0; j < KP; ++j) cnt[threadIdx.x][j] = 0;
     }
-    __syncthreads();
+    // the open node of each of the thread's positions (-1: none): the node holding p0 by
+    // binary search over the sorted starts, then the boundaries met in order
+    int se[PER];
     {
-      int sg, snext;
-      locate(threadIdx.x * PER, sg, snext);
+      int lo2 = 0, hi2 = nact;   // first node starting after p0
+      while (lo2 < hi2) {
+        const int md = (lo2 + hi2) >> 1;
+        if (S[md].start <= p0) lo2 = md + 1; else hi2 = md;
+      }
+      int snext = lo2, sg = lo2 - 1;   // sg: last node starting at or before p0
+      int send = (sg >= 0) ? S[sg].start + S[sg].count : 0;
+      int nstart = (snext < nact) ? S[snext].start : CAP;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int p = p0 + e;
+        if (p == nstart) {
+          sg = snext++;
+          send = S[sg].start + S[sg].count;
+          nstart = (snext < nact) ? S[snext].start : CAP;
+        }
+        se[e] = (sg >= 0 && p < send && p < count) ? sg : -1;
+      }
+    }
+    // the thread's rows, all read before any is used, and their current order entries
+    int oi[PER];
+    uint4 rv[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      oi[e] = ordb[co][p0 + e];
+      rv[e] = rows[se[e] >= 0 ? oi[e] : 0];
+    }
+    __syncthreads();   // masks and zeroed counts visible
+    // 1. next-bit counts per open node and dimension. Byte j of a code row is dimension
+    //    j's code; a node's mask keeps the next unrefined bit of each of its dimensions, so
+    //    a masked row has at most one bit per byte. A thread sums its positions as byte
+    //    counters, one per dimension; each wave then adds up the counters of its lanes in
+    //    one node (as 16-bit fields) and adds them to the node's counts.
+    {
       uint32_t acc[4] = {0u, 0u, 0u, 0u};
+      uint4 M = make_uint4(0u, 0u, 0u, 0u);
       int run = -1;   // node whose counts acc holds
 #pragma unroll
       for (int e = 0; e < PER; ++e) {
-        const int p = threadIdx.x * PER + e;
-        if (p < count) {
-          if (snext < nact && S[snext].start == p) { sg = snext; ++snext; }
-          if (sg >= 0 && p >= S[sg].start + S[sg].count) sg = -1;
-          if (sg != run) {
-            // a node boundary inside the thread's positions: the finished run's counts go
-            // to its node directly
-            if (run >= 0)
-              for (int j = 0; j < K; ++j) {
-                const uint32_t c = (acc[j >> 2] >> (8 * (j & 3))) & 255u;
-                if (c) atomicAdd(&cnt[run][j], c);
-              }
-            acc[0] = acc[1] = acc[2] = acc[3] = 0u;
-            run = sg;
+        const int g = se[e];
+        if (g != run) {
+          // a node boundary inside the thread's positions: the finished run's counts go
+          // to its node directly
+          if (run >= 0) {
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+              const uint32_t c = (acc[j >> 2] >> (8 * (j & 3))) & 255u;
+              if (j < K && c) atomicAdd(&cnt[run][j], c);
+            }
           }
-          if (sg >= 0) {
-            const uint4 v = rows[ord[p]];
-            const uint4 M = smask[sg];
-            acc[0] += nonzero_bytes(v.x & M.x);
-            acc[1] += nonzero_bytes(v.y & M.y);
-            acc[2] += nonzero_bytes(v.z & M.z);
-            acc[3] += nonzero_bytes(v.w & M.w);
-          }
+          acc[0] = acc[1] = acc[2] = acc[3] = 0u;
+          run = g;
+          if (g >= 0) M = smask[g];
+        }
+        if (g >= 0) {
+          acc[0] += nonzero_bytes(rv[e].x & M.x);
+          acc[1] += nonzero_bytes(rv[e].y & M.y);
+          acc[2] += nonzero_bytes(rv[e].z & M.z);
+          acc[3] += nonzero_bytes(rv[e].w & M.w);
         }
       }
       uint64_t pending = __ballot(run >= 0);
       while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int s0 = __shfl(run, leader);
+        const int s0 = __builtin_amdgcn_readlane(run, leader);
         const bool mine = run == s0;
-        // bytes 0 and 2 (even dimensions), bytes 1 and 3 (odd) as 16-bit fields
+        // bytes 0 and 2 (even dimensions), bytes 1 and 3 (odd) as 16-bit fields, summed
+        // over the wave (uniform results)
         uint32_t w[8];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          w[2 * i] = mine ? (acc[i] & 0x00ff00ffu) : 0u;
-          w[2 * i + 1] = mine ? ((acc[i] >> 8) & 0x00ff00ffu) : 0u;
+          w[2 * i] = wave_total(mine ? (acc[i] & 0x00ff00ffu) : 0u);
+          w[2 * i + 1] = wave_total(mine ? ((acc[i] >> 8) & 0x00ff00ffu) : 0u);
         }
+        if (lane < K) {
+          const int wi = 2 * (lane >> 2) + (lane & 1);
+          uint32_t ww = w[0];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) w[i] = wave_sum(w[i]);
-        if (lane == leader)
-          for (int j = 0; j < K; ++j) {
-            const uint32_t c = (w[2 * (j >> 2) + (j & 1)] >> (16 * ((j >> 1) & 1))) & 0xffffu;
-            if (c) atomicAdd(&cnt[s0][j], c);
-          }
+          for (int i = 1; i < 8; ++i) ww = (wi == i) ? w[i] : ww;
+          const uint32_t c = (ww >> (16 * ((lane >> 1) & 1))) & 0xffffu;
+          if (c) atomicAdd(&cnt[s0][lane], c);
+        }
         pending &= ~__ballot(mine);
       }
     }
@@ -695,59 +757,63 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
     // 2. split dimension of every open node: the most balanced one, ties to the smallest
     if ((int)threadIdx.x < nact) {
       const SegL& g = S[threadIdx.x];
-      int best = -1, best_score = 0;
-      for (int j = 0; j < K; ++j) {
-        if (g.depth[j] >= bits) continue;
-        const int sc = abs(2 * (int)cnt[threadIdx.x][j] - g.count);
-        if (best < 0 || sc < best_score) { best = j; best_score = sc; }
+      int best = -1, best_score = 0, best_cnt = 0;
+#pragma unroll
+      for (int j = 0; j < KP; ++j) {
+        const int dj = g.depth[j];
+        const int cj = (int)cnt[threadIdx.x][j];
+        const int sc = abs(2 * cj - g.count);
+        if (j < K && dj < bits && (best < 0 || sc < best_score)) {
+          best = j; best_score = sc; best_cnt = cj;
+        }
       }
       jsel[threadIdx.x] = (uint8_t)best;
-      c0s[threadIdx.x] = (uint16_t)(g.count - (int)cnt[threadIdx.x][best]);
+      const int bj = max(best, 0);
+      const uint32_t bit = 1u << (8 * (bj & 3) + bits - 1 - g.depth[bj]);
+      bmask[threadIdx.x] = make_uint4((bj >> 2) == 0 ? bit : 0u, (bj >> 2) == 1 ? bit : 0u,
+                                      (bj >> 2) == 2 ? bit : 0u, (bj >> 2) == 3 ? bit : 0u);
+      c0s[threadIdx.x] = (uint16_t)(g.count - best_cnt);
     }
     __syncthreads();
     // 3. stable partition of every open node: a workgroup-wide scan of the bit-0 flags
     //    over consecutive position runs gives each point its rank among its node's zeros
-    const int p0 = threadIdx.x * PER;
     uint32_t zmask = 0;
-    int sg, snext;
-    locate(p0, sg, snext);
-    int segof[PER];
+    {
+      int jg = -1;
+      uint4 B = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int p = p0 + e;
-      segof[e] = -1;
-      if (p >= count) continue;
-      if (snext < nact && S[snext].start == p) { sg = snext; ++snext; }
-      if (sg >= 0 && p >= S[sg].start + S[sg].count) sg = -1;
-      if (sg < 0) continue;
-      segof[e] = sg;
-      const int j = jsel[sg];
-      const uint32_t bit = (code_byte(rows[ord[p]], j) >> (bits - 1 - S[sg].depth[j])) & 1u;
-      if (!bit) zmask |= 1u << e;
+      for (int e = 0; e < PER; ++e) {
+        const int g = se[e];
+        if (g >= 0 && g != jg) { jg = g; B = bmask[g]; }
+        const bool one = ((rv[e].x & B.x) | (rv[e].y & B.y) | (rv[e].z & B.z) | (rv[e].w & B.w)) != 0u;
+        if (g >= 0 && !one) zmask |= 1u << e;
+      }
     }
     uint32_t ztot;
-    const uint32_t zbase = block_excl_scan<NT>((uint32_t)__popc(zmask), sh_scan, &ztot);
+    const uint32_t zbase = block_excl_scan_dpp<NT>((uint32_t)__popc(zmask), sh_scan, &ztot);
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      const int g = segof[e];
+      const int g = se[e];
       if (g >= 0 && p0 + e == S[g].start)
         zstart[g] = zbase + (uint32_t)__popc(zmask & ((1u << e) - 1u));
     }
     __syncthreads();
+    {
+      int gs = -1, gstart = 0, gc0 = 0;
+      uint32_t gz = 0;
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int p = p0 + e;
-      if (p >= count) continue;
-      const int g = segof[e];
-      if (g < 0) { tmp[p] = ord[p]; continue; }
-      const uint32_t zb = zbase + (uint32_t)__popc(zmask & ((1u << e) - 1u)) - zstart[g];
-      const int off = p - S[g].start;
-      const int np = ((zmask >> e) & 1u) ? S[g].start + (int)zb
-                                         : S[g].start + (int)c0s[g] + (off - (int)zb);
-      tmp[np] = ord[p];
+      for (int e = 0; e < PER; ++e) {
+        const int p = p0 + e;
+        if (p >= count) continue;
+        const int g = se[e];
+        if (g < 0) { ordb[co ^ 1][p] = (uint16_t)oi[e]; continue; }
+        if (g != gs) { gs = g; gstart = S[g].start; gc0 = c0s[g]; gz = zstart[g]; }
+        const uint32_t zb = zbase + (uint32_t)__popc(zmask & ((1u << e) - 1u)) - gz;
+        const int off = p - gstart;
+        const int np = ((zmask >> e) & 1u) ? gstart + (int)zb : gstart + gc0 + (off - (int)zb);
+        ordb[co ^ 1][np] = (uint16_t)oi[e];
+      }
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < count; t += NT) ord[t] = tmp[t];
     // 4. children: leaves are emitted, open ones form the next level's list (in position
     //    order: children of a node are adjacent, bit 0 first)
     //    The children are read and written field by field from the parent in LDS: a
@@ -773,7 +839,7 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
       nopen = (oa ? 1u : 0u) + (ob ? 1u : 0u);
     }
     uint32_t total;
-    const uint32_t at = block_excl_scan<NT>(nopen, sh_scan, &total);
+    const uint32_t at = block_excl_scan_dpp<NT>(nopen, sh_scan, &total);
     if ((int)threadIdx.x < nact) {
       const SegL& g = S[threadIdx.x];
       SegL* Nx = segs[cur ^ 1];
@@ -792,14 +858,16 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
     if (threadIdx.x == 0) s_nact = total;
     __syncthreads();
     cur ^= 1;
+    co ^= 1;
   }
   // the ids in leaf order: every read (the node's ids may sit in the output array) before
-  // any write
+  // any write; an order entry is below count (clamped all the same, so that the reads stay
+  // inside the node)
   int32_t outv[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int t = threadIdx.x + e * NT;
-    outv[e] = (t < count) ? isrc[ord[t]] : 0;
+    outv[e] = (t < count) ? isrc[min((int)ordb[co][t], count - 1)] : 0;
   }
   __syncthreads();
   int32_t* out = b.ids[0] + tb + s.start;
