@@ -137,12 +137,24 @@ __device__ inline uint32_t nonzero_bytes(uint32_t w) {
 
 __device__ inline uint32_t lanes_below(uint64_t mask) { return lanes_below_mask(mask); }
 
+// A leaf record: the leaf's size at its first position and its 16 index words
+// ((1 << depth) | prefix per dimension, 0 past K) in two 16-byte stores.
+__device__ inline void store_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start, int count,
+                                  const uint32_t (&hv)[KP]) {
+  lo.cnt_at[(int64_t)tree * n + start] = (uint32_t)count;
+  uint4* h = reinterpret_cast<uint4*>(lo.hidx_at + ((int64_t)tree * n + start) * KP);
+  h[0] = make_uint4(hv[0] | (hv[1] << 16), hv[2] | (hv[3] << 16), hv[4] | (hv[5] << 16),
+                    hv[6] | (hv[7] << 16));
+  h[1] = make_uint4(hv[8] | (hv[9] << 16), hv[10] | (hv[11] << 16), hv[12] | (hv[13] << 16),
+                    hv[14] | (hv[15] << 16));
+}
+
 __device__ void emit_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start, int count,
                           const uint8_t* depth, const uint8_t* prefix, int K) {
-  lo.cnt_at[(int64_t)tree * n + start] = (uint32_t)count;
-  uint16_t* h = lo.hidx_at + ((int64_t)tree * n + start) * KP;
-  for (int j = 0; j < KP; ++j)
-    h[j] = (j < K) ? (uint16_t)((1u << depth[j]) | prefix[j]) : (uint16_t)0;
+  uint32_t hv[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) hv[j] = (j < K) ? ((1u << depth[j]) | prefix[j]) & 0xffffu : 0u;
+  store_leaf(lo, n, tree, start, count, hv);
 }
 
 // The leaf record of child `bit` of a node split on dimension j (depth and prefix of the
@@ -150,13 +162,14 @@ __device__ void emit_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start,
 __device__ void emit_child_leaf(const LeafOut& lo, int64_t n, int tree, int64_t start, int count,
                                 const uint8_t* depth, const uint8_t* prefix, int j, int bit,
                                 int K) {
-  lo.cnt_at[(int64_t)tree * n + start] = (uint32_t)count;
-  uint16_t* h = lo.hidx_at + ((int64_t)tree * n + start) * KP;
+  uint32_t hv[KP];
+#pragma unroll
   for (int jj = 0; jj < KP; ++jj) {
     const uint32_t d = depth[jj] + (jj == j ? 1u : 0u);
     const uint32_t p = (jj == j) ? prefix[jj] * 2u + (uint32_t)bit : prefix[jj];
-    h[jj] = (jj < K) ? (uint16_t)((1u << d) | p) : (uint16_t)0;
+    hv[jj] = (jj < K) ? ((1u << d) | p) & 0xffffu : 0u;
   }
+  store_leaf(lo, n, tree, start, count, hv);
 }
 
 __device__ inline bool fully_refined(const uint8_t* depth, int K, int bits) {
@@ -611,15 +624,21 @@ struct SegL {
 // node and dimension; 2. split dimension per node; 3. stable partition of every node by its
 // split bit (a workgroup scan of the bit-0 flags); 4. children, open ones listed for the next
 // level. The position order lives in one of two LDS arrays, the partition writing the other.
+// Six waves per SIMD for the classes whose LDS allows them (three workgroups of the largest
+// class share a CU); the others are limited by LDS first.
+constexpr int frontier_waves(int cap, int maxs) {
+  return (cap >= 512 && (maxs == 16 || cap == 2048)) ? 6 : 1;
+}
+
 template <int CAP, int NT, int MAXS>
-__global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, int64_t n, int K,
-                                                       int bits, int max_leaf, int below,
-                                                       LeafOut lo) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(frontier_waves(CAP, MAXS))))
+void seg_lds_frontier(
+    const Seg* mid, Bufs b, int64_t n, int K, int bits, int max_leaf, int below, LeafOut lo) {
   constexpr int PER = CAP / NT;           // consecutive positions per thread in the scan
   static_assert(PER * NT == CAP && PER <= 32 && MAXS <= NT, "class shape");
   __shared__ uint4 rows[CAP];
   __shared__ uint16_t ordb[2][CAP];
-  __shared__ SegL segs[2][MAXS];
+  __shared__ __align__(16) SegL segs[2][MAXS];   // (depth bytes read as words)
   __shared__ uint4 smask[MAXS];
   __shared__ uint32_t cnt[MAXS][KP];
   __shared__ uint32_t zstart[MAXS];
@@ -655,11 +674,17 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
     const int nact = (int)uni(s_nact);
     if (nact == 0) break;
     const SegL* S = segs[cur];
+    // thread i < nact handles open node i: its depth bytes stay in registers for the level
+    uint32_t dw[4] = {0u, 0u, 0u, 0u};
+    auto dep = [&](int j) { return (dw[j >> 2] >> (8 * (j & 3))) & 255u; };   // j constant
     if ((int)threadIdx.x < nact) {
-      const SegL& g = S[threadIdx.x];
+      const uint32_t* gd = reinterpret_cast<const uint32_t*>(S[threadIdx.x].depth);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dw[q] = gd[q];
       uint32_t m[4] = {0u, 0u, 0u, 0u};
-      for (int j = 0; j < K; ++j)
-        if (g.depth[j] < bits) m[j >> 2] |= 1u << (8 * (j & 3) + bits - 1 - g.depth[j]);
+#pragma unroll
+      for (int j = 0; j < KP; ++j)
+        if (j < K && dep(j) < (uint32_t)bits) m[j >> 2] |= 1u << (8 * (j & 3) + bits - 1 - dep(j));
       smask[threadIdx.x] = make_uint4(m[0], m[1], m[2], m[3]);
 #pragma unroll
       for (int j = 0; j < KP; ++j) cnt[threadIdx.x][j] = 0;
@@ -760,7 +785,7 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
       int best = -1, best_score = 0, best_cnt = 0;
 #pragma unroll
       for (int j = 0; j < KP; ++j) {
-        const int dj = g.depth[j];
+        const int dj = (int)dep(j);
         const int cj = (int)cnt[threadIdx.x][j];
         const int sc = abs(2 * cj - g.count);
         if (j < K && dj < bits && (best < 0 || sc < best_score)) {
@@ -769,7 +794,8 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
       }
       jsel[threadIdx.x] = (uint8_t)best;
       const int bj = max(best, 0);
-      const uint32_t bit = 1u << (8 * (bj & 3) + bits - 1 - g.depth[bj]);
+      const uint32_t wsel = (bj >> 2) == 0 ? dw[0] : (bj >> 2) == 1 ? dw[1] : (bj >> 2) == 2 ? dw[2] : dw[3];
+      const uint32_t bit = 1u << (8 * (bj & 3) + bits - 1 - ((wsel >> (8 * (bj & 3))) & 255u));
       bmask[threadIdx.x] = make_uint4((bj >> 2) == 0 ? bit : 0u, (bj >> 2) == 1 ? bit : 0u,
                                       (bj >> 2) == 2 ? bit : 0u, (bj >> 2) == 3 ? bit : 0u);
       c0s[threadIdx.x] = (uint16_t)(g.count - best_cnt);
@@ -827,7 +853,9 @@ __global__ __launch_bounds__(NT) void seg_lds_frontier(const Seg* mid, Bufs b, i
       za = c0s[threadIdx.x];
       zb = g.count - za;
       bool full = true;   // every dimension fully refined after the split
-      for (int jj = 0; jj < K; ++jj) full = full && (g.depth[jj] + (jj == jc ? 1 : 0) >= bits);
+#pragma unroll
+      for (int jj = 0; jj < KP; ++jj)
+        full = full && (jj >= K || (int)dep(jj) + (jj == jc ? 1 : 0) >= bits);
       oa = za > max_leaf && !full;
       ob = zb > max_leaf && !full;
       if (!oa && za > 0)
