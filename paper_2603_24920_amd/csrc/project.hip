@@ -187,16 +187,24 @@ __global__ __launch_bounds__(PROJ_THREADS) void project_kernel(ProjArgs a) {
           const float xv[8] = {xb[2 * kb].x, xb[2 * kb].y, xb[2 * kb].z, xb[2 * kb].w,
                                xb[2 * kb + 1].x, xb[2 * kb + 1].y, xb[2 * kb + 1].z,
                                xb[2 * kb + 1].w};
-          bf16x8 xh, xm, xl;
-          bool low = false;   // a mid or lo part is not zero
+          // hi parts first; mid and lo (split3's remaining steps) only when some value of
+          // the wave is not exact in bf16 (otherwise both are zero and their products drop)
+          bf16x8 xh, xm = {}, xl = {};
+          bool inexact = false;
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            __bf16 h, m, l;
-            split3(xv[j], h, m, l);
-            xh[j] = h; xm[j] = m; xl[j] = l;
-            low = low || (float)m != 0.0f || (float)l != 0.0f;
+            xh[j] = (__bf16)xv[j];
+            inexact = inexact || (float)xh[j] != xv[j];
           }
-          const bool full = __ballot(low) != 0;   // wave-uniform
+          const bool full = __ballot(inexact) != 0;   // wave-uniform
+          if (full) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const float r1 = xv[j] - (float)xh[j];
+              xm[j] = (__bf16)r1;
+              xl[j] = (__bf16)(r1 - (float)xm[j]);
+            }
+          }
           const uint4* ab = As + (kb * 4 + grp) * NC + col16;
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
