@@ -508,6 +508,10 @@ __global__ __launch_bounds__(256) void seg_split(const Seg* segs, const Unit* un
     const int cd = s.depth[jj] + (jj == j ? 1 : 0);
     if (jj < K && cd < bits) M[jj >> 2] |= 1u << (8 * (jj & 3) + bits - 1 - cd);
   }
+  // the split bit of a code row (one bit set)
+  const uint32_t sbit = 1u << (8 * (j & 3) + sh);
+  const uint4 SB = make_uint4((j >> 2) == 0 ? sbit : 0u, (j >> 2) == 1 ? sbit : 0u,
+                              (j >> 2) == 2 ? sbit : 0u, (j >> 2) == 3 ? sbit : 0u);
   uint32_t acc0[4] = {0u, 0u, 0u, 0u}, acc1[4] = {0u, 0u, 0u, 0u};
   const int64_t tb = (int64_t)s.tree * n;
   const uint4* rs = b.rows[s.buf] + tb + s.start;
@@ -515,37 +519,54 @@ __global__ __launch_bounds__(256) void seg_split(const Seg* segs, const Unit* un
   uint4* rd = b.rows[1 - s.buf] + tb;
   int32_t* id_d = b.ids[1 - s.buf] + tb;
   const int end = min(s.count, (int)u.first + SEG_CHUNK);
-  for (int b0 = (int)u.first; b0 < end; b0 += 256) {
-    const int p = b0 + threadIdx.x;
-    const bool valid = p < end;
-    int32_t id = 0;
-    uint4 row = make_uint4(0, 0, 0, 0);
-    int bit = 0;
-    if (valid) {
-      row = rs[p];
-      id = is[p];
-      bit = (code_byte(row, j) >> sh) & 1;
+  // SPLIT_G steps of 256 points at a time: their loads are all in flight together, and a
+  // wave reserves its places in each child once per group
+  constexpr int SPLIT_G = 4;
+  for (int b0 = (int)u.first; b0 < end; b0 += 256 * SPLIT_G) {
+    uint4 row[SPLIT_G];
+    int32_t id[SPLIT_G];
+    bool valid[SPLIT_G], bit[SPLIT_G];
+#pragma unroll
+    for (int i = 0; i < SPLIT_G; ++i) {
+      const int p = b0 + i * 256 + (int)threadIdx.x;
+      valid[i] = p < end;
+      row[i] = valid[i] ? rs[p] : make_uint4(0, 0, 0, 0);
+      id[i] = valid[i] ? is[p] : 0;
     }
-    const uint64_t mz = __ballot(valid && bit == 0);
-    const uint64_t mo = __ballot(valid && bit == 1);
+    uint64_t mz[SPLIT_G], mo[SPLIT_G];
+    uint32_t nz = 0, no = 0;
+#pragma unroll
+    for (int i = 0; i < SPLIT_G; ++i) {
+      bit[i] = ((row[i].x & SB.x) | (row[i].y & SB.y) | (row[i].z & SB.z) | (row[i].w & SB.w)) != 0u;
+      mz[i] = __ballot(valid[i] && !bit[i]);
+      mo[i] = __ballot(valid[i] && bit[i]);
+      nz += (uint32_t)__popcll(mz[i]);
+      no += (uint32_t)__popcll(mo[i]);
+    }
     uint32_t bz = 0, bo = 0;
     if ((threadIdx.x & 63) == 0) {
-      if (mz) bz = atomicAdd(&cur0[u.seg], (uint32_t)__popcll(mz));
-      if (mo) bo = atomicAdd(&cur1[u.seg], (uint32_t)__popcll(mo));
+      if (nz) bz = atomicAdd(&cur0[u.seg], nz);
+      if (no) bo = atomicAdd(&cur1[u.seg], no);
     }
-    bz = __shfl(bz, 0);
-    bo = __shfl(bo, 0);
-    if (valid) {
-      const uint32_t pos = bit ? bo + lanes_below(mo) : bz + lanes_below(mz);
-      id_d[pos] = id;
-      if (!((lf >> bit) & 1)) rd[pos] = row;
-      if (bit ? need1 : need0) {
-        uint32_t* acc = bit ? acc1 : acc0;
-        acc[0] += nonzero_bytes(row.x & M[0]);
-        acc[1] += nonzero_bytes(row.y & M[1]);
-        acc[2] += nonzero_bytes(row.z & M[2]);
-        acc[3] += nonzero_bytes(row.w & M[3]);
+    bz = uni(bz);   // lane 0 holds them
+    bo = uni(bo);
+#pragma unroll
+    for (int i = 0; i < SPLIT_G; ++i) {
+      if (valid[i]) {
+        const int bt = bit[i] ? 1 : 0;
+        const uint32_t pos = bt ? bo + lanes_below(mo[i]) : bz + lanes_below(mz[i]);
+        id_d[pos] = id[i];
+        if (!((lf >> bt) & 1)) rd[pos] = row[i];
+        if (bt ? need1 : need0) {
+          uint32_t* acc = bt ? acc1 : acc0;
+          acc[0] += nonzero_bytes(row[i].x & M[0]);
+          acc[1] += nonzero_bytes(row[i].y & M[1]);
+          acc[2] += nonzero_bytes(row[i].z & M[2]);
+          acc[3] += nonzero_bytes(row[i].w & M[3]);
+        }
       }
+      bz += (uint32_t)__popcll(mz[i]);
+      bo += (uint32_t)__popcll(mo[i]);
     }
   }
 #pragma unroll
