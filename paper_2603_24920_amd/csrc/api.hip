@@ -514,8 +514,15 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     }
     {
       Span sp(s, &tm.build_sample_ms);
-      PDET_HIP(hipMemsetAsync(smm.ptr(), 0xff, (size_t)LK * 4, s));
-      PDET_HIP(hipMemsetAsync(smm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));
+      // the sample's and the encode's column extremes (ordered-uint min / max) and the
+      // non-finite flag start in one launch
+      FillList fz;
+      fz.add(smm.ptr(), 0xffffffffu, (size_t)LK * 4);
+      fz.add(smm.as<uint32_t>() + LK, 0u, (size_t)LK * 4);
+      fz.add(ix->nonfinite.p, 0u, 4);
+      fz.add(ix->colmm.p, 0xffffffffu, (size_t)LK * 4);
+      fz.add(ix->colmm.as<uint32_t>() + LK, 0u, (size_t)LK * 4);
+      fill_words(fz, s);
       project_sample(*ix, sid.as<int64_t>(), n_sample, ps.as<float>(), n_sample,
                      smm.as<uint32_t>(), s);
       sp.finish();
@@ -532,9 +539,6 @@ pdet_status pdet_build(const float* data, int64_t n, int32_t d, const pdet_build
     }
 
     // encode every point; column extremes give the outer breakpoints
-    PDET_HIP(hipMemsetAsync(ix->nonfinite.p, 0, 4, s));
-    PDET_HIP(hipMemsetAsync(ix->colmm.p, 0xff, (size_t)LK * 4, s));
-    PDET_HIP(hipMemsetAsync(ix->colmm.as<uint32_t>() + LK, 0, (size_t)LK * 4, s));
     ix->codes.alloc((size_t)ix->L * n * KP);
     ix->flkey.alloc((size_t)ix->L * n * 2);
     ix->perm.alloc((size_t)ix->L * n * 4);

@@ -7,6 +7,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <stdexcept>
 #include <vector>
 
 #include "common.h"
@@ -227,6 +228,24 @@ void static_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
 // Phi^-1(p) for p in (0, 1): the standard normal quantile, to double precision.
 double normal_quantile(double p);
 void fill_f32(float* p, int64_t count, float v, hipStream_t s);
+
+// Up to FILL_MAX ranges of 32-bit words, each set to its own value by one launch (in place of
+// a memset per small buffer: counters, extremes, flags).
+constexpr int FILL_MAX = 8;
+struct FillList {
+  uint32_t* p[FILL_MAX];
+  uint32_t value[FILL_MAX];
+  uint32_t nwords[FILL_MAX];
+  int n = 0;
+  void add(void* ptr, uint32_t v, size_t bytes) {
+    if (n >= FILL_MAX) throw std::logic_error("fill list full");
+    p[n] = static_cast<uint32_t*>(ptr);
+    value[n] = v;
+    nwords[n] = (uint32_t)(bytes / 4);
+    ++n;
+  }
+};
+void fill_words(const FillList& f, hipStream_t s);
 void set_outer_breakpoints(float* B, const uint32_t* colmm, int ncols, int Nr, hipStream_t s);
 void scan_rows(const uint32_t* in, uint32_t* out, uint32_t* totals, int rows, int64_t len,
                DevBuf& tmp, hipStream_t s);

@@ -216,6 +216,15 @@ __global__ void fill_kernel(float* p, int64_t count, float v) {
   if (g < count) p[g] = v;
 }
 
+// range blockIdx.y of the list, grid-stride
+__global__ void fill_words_kernel(FillList f) {
+  const int r = blockIdx.y;
+  uint32_t* p = f.p[r];
+  const uint32_t v = f.value[r], nw = f.nwords[r];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 // ---- column moments of the sample (static encoding), in a fixed summation order
 constexpr int MOM_THREADS = 256;
 
@@ -351,6 +360,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply(const uint32_t* in, u
 
 }  // namespace
 
+void fill_words(const FillList& f, hipStream_t s) {
+  if (f.n == 0) return;
+  uint32_t most = 0;
+  for (int r = 0; r < f.n; ++r) most = std::max(most, f.nwords[r]);
+  const unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>(cdiv(most, 256), 1), 1024);
+  hipLaunchKernelGGL(fill_words_kernel, dim3(gx, f.n), dim3(256), 0, s, f);
+  PDET_HIP(hipGetLastError());
+}
+
 void fill_f32(float* p, int64_t count, float v, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(cdiv(count, 256)), dim3(256), 0, s, p, count, v);
@@ -363,8 +381,10 @@ void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
   PooledBuf hist((size_t)ncols * NB * 4), fill((size_t)ncols * NB * 4);
   PooledBuf boff((size_t)ncols * NB * 4), tb((size_t)ncols * (Nr - 1) * 4);
   PooledBuf tr((size_t)ncols * (Nr - 1) * 4), gbuf((size_t)ncols * ns * 4);
-  PDET_HIP(hipMemsetAsync(hist.ptr(), 0, hist.bytes(), s));
-  PDET_HIP(hipMemsetAsync(fill.ptr(), 0, fill.bytes(), s));
+  FillList fz;
+  fz.add(hist.ptr(), 0u, hist.bytes());
+  fz.add(fill.ptr(), 0u, fill.bytes());
+  fill_words(fz, s);
   const dim3 kg(cdiv(ns, GATHER_KEYS), ncols);
   hipLaunchKernelGGL(col_hist, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm,
                      hist.as<uint32_t>());

@@ -521,7 +521,7 @@ __global__ __launch_bounds__(256) void seg_split(const Seg* segs, const Unit* un
   const int end = min(s.count, (int)u.first + SEG_CHUNK);
   // SPLIT_G steps of 256 points at a time: their loads are all in flight together, and a
   // wave reserves its places in each child once per group
-  constexpr int SPLIT_G = 4;
+  constexpr int SPLIT_G = 8;
   for (int b0 = (int)u.first; b0 < end; b0 += 256 * SPLIT_G) {
     uint4 row[SPLIT_G];
     int32_t id[SPLIT_G];
@@ -1263,8 +1263,10 @@ void first_layer_sort(int L, int K, int64_t n, uint16_t* keys, const uint4* code
                        n, nblk, o8.as<uint32_t>(), keys, rows0, ids0);
     PDET_HIP(hipGetLastError());
   }
-  PDET_HIP(hipMemsetAsync(start, 0, (size_t)L * ((size_t)1 << K) * 4, s));
-  PDET_HIP(hipMemsetAsync(end, 0, (size_t)L * ((size_t)1 << K) * 4, s));
+  FillList fz;
+  fz.add(start, 0u, (size_t)L * ((size_t)1 << K) * 4);
+  fz.add(end, 0u, (size_t)L * ((size_t)1 << K) * 4);
+  fill_words(fz, s);
   hipLaunchKernelGGL(rk_bounds, dim3(cdiv(n, 256), L), dim3(256), 0, s, kfin, n, K, start, end);
   PDET_HIP(hipGetLastError());
 }
@@ -1317,7 +1319,11 @@ void build_trees(Index& ix, hipStream_t s) {
   PooledBuf bigA((size_t)big_cap * sizeof(Seg)), bigB((size_t)big_cap * sizeof(Seg));
   PooledBuf copies((size_t)2 * big_cap * sizeof(Copy));
   PooledBuf ctr(16 * 4);
-  PDET_HIP(hipMemsetAsync(ctr.ptr(), 0, ctr.bytes(), s));
+  {
+    FillList fz;
+    fz.add(ctr.ptr(), 0u, ctr.bytes());
+    fill_words(fz, s);
+  }
   uint32_t* c = ctr.as<uint32_t>();
   Lists li{bigA.as<Seg>(), c + 0, c + 1, {}, c + 4, copies.as<Copy>(), c + 8};
   for (int cl = 0; cl < NCLS; ++cl) li.mid[cl] = mid.as<Seg>() + mid_off[cl];
@@ -1347,11 +1353,15 @@ void build_trees(Index& ix, hipStream_t s) {
   uint32_t* cur_cnt = cntbuf.as<uint32_t>();
   uint32_t* nxt_cnt = cntnext.as<uint32_t>();
   for (int level = 0; nbig > 0; ++level) {
-    if (level == 0) PDET_HIP(hipMemsetAsync(cur_cnt, 0, (size_t)nbig * KP * 4, s));
-    PDET_HIP(hipMemsetAsync(cntn.ptr(), 0, (size_t)nbig * 2 * KP * 4, s));
     const int nxt_slot = 1 - cur_slot;
-    PDET_HIP(hipMemsetAsync(c + 2 * nxt_slot, 0, 8, s));
-    PDET_HIP(hipMemsetAsync(c + 8, 0, 8, s));   // copies, units
+    {
+      FillList fz;
+      if (level == 0) fz.add(cur_cnt, 0u, (size_t)nbig * KP * 4);
+      fz.add(cntn.ptr(), 0u, (size_t)nbig * 2 * KP * 4);
+      fz.add(c + 2 * nxt_slot, 0u, 8);
+      fz.add(c + 8, 0u, 8);   // copies, units
+      fill_words(fz, s);
+    }
     // every node gives at most count / SEG_CHUNK + 1 units
     const unsigned nu = (unsigned)(ptsbig / SEG_CHUNK + nbig);
     hipLaunchKernelGGL(seg_units, dim3(cdiv(nbig, 256)), dim3(256), 0, s, cur_big, (int)nbig,
