@@ -17,33 +17,40 @@ __device__ inline uint64_t uni(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Exclusive scan of one uint32 per thread over a workgroup of NT threads.
-// sh must hold NT/64 + 1 words. Contains barriers: call from every thread.
+// Inclusive scan over a whole wave (every lane active): scans of the 16-lane rows by
+// row_shr:1,2,4,8 (a lane without a source adds 0), then the row totals carried on by
+// row_bcast:15 (into rows 1 and 3) and row_bcast:31 (into rows 2 and 3).
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+  return x;
+}
+
+// Exclusive scan of one uint32 per thread over a workgroup of NT threads (NT a multiple of
+// 64; every thread calls it, with all lanes of its wave active). sh must hold NT/64 + 1
+// words. Wave scans by DPP, the wave totals through LDS, each wave adding those before it;
+// two barriers.
 template <int NT>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
+  static_assert(NT % 64 == 0, "whole waves");
+  const int wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  if ((threadIdx.x & 63) == 63) sh[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint32_t t = sh[w];
+    before += (w < wave) ? t : 0u;
+    tot += t;
   }
-  if (lane == 63) sh[wave] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int w = 0; w < NT / 64; ++w) {
-      const uint32_t t = sh[w];
-      sh[w] = acc;
-      acc += t;
-    }
-    sh[NT / 64] = acc;
-  }
-  __syncthreads();
-  const uint32_t r = sh[wave] + x - v;
-  *total = uni(sh[NT / 64]);
-  __syncthreads();
-  return r;
+  *total = uni(tot);
+  __syncthreads();   // sh is free for the next scan
+  return uni(before) + incl - v;
 }
 
 // A double moved across lanes with a DPP control (both 32-bit halves; every lane of the

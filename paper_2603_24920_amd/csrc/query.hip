@@ -870,15 +870,10 @@ __device__ __forceinline__ void q_main_body(const QArgs& a) {
       __syncthreads();
       const uint32_t nb = uni(s_nb);
       newc += nb;
-      if (tid == 0) {
-        // first window entry of the next chunk: last e with pre <= base + QM
-        const uint32_t nbase = base + QM;
-        int l2 = 0, h2 = QM + 1;
-        while (h2 - l2 > 1) {
-          const int mid = (l2 + h2) >> 1;
-          if (w_pre[mid] <= nbase) l2 = mid; else h2 = mid;
-        }
-        s_ef = ef + l2;
+      if (tid == QM - 1 && p < P1) {
+        // first window entry of the next chunk (the one holding base + QM): this thread's
+        // entry or, when that ends here, the next (every entry holds at least one point)
+        s_ef = ef + lo + (w_pre[lo + 1] <= base + QM ? 1 : 0);
       }
       if (mode != WALK_COUNT) {
         constexpr int NRV = (PREC == PDET_FP32) ? NR32 : 1;

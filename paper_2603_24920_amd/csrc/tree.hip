@@ -96,40 +96,6 @@ __device__ inline uint32_t wave_total(uint32_t v) {
          __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
-// Inclusive scan over a whole wave (every lane active): scans of the 16-lane rows by
-// row_shr:1,2,4,8 (a lane without a source adds 0), then the row totals carried on by
-// row_bcast:15 (into rows 1 and 3) and row_bcast:31 (into rows 2 and 3).
-__device__ inline uint32_t wave_incl_scan(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
-  return x;
-}
-
-// Exclusive scan of one uint32 per thread over a workgroup of NT threads (every thread
-// calls it; sh holds NT/64 words): wave scans by DPP, the wave totals through LDS, each
-// wave adding those before it. Two barriers.
-template <int NT>
-__device__ inline uint32_t block_excl_scan_dpp(uint32_t v, uint32_t* sh, uint32_t* total) {
-  const int wave = threadIdx.x >> 6;
-  const uint32_t incl = wave_incl_scan(v);
-  if ((threadIdx.x & 63) == 63) sh[wave] = incl;
-  __syncthreads();
-  uint32_t before = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) {
-    const uint32_t t = sh[w];
-    before += (w < wave) ? t : 0u;
-    tot += t;
-  }
-  *total = uni(tot);
-  __syncthreads();   // sh is free for the next scan
-  return uni(before) + incl - v;
-}
-
 // 1 in every byte of w that is not zero, 0 in the others.
 __device__ inline uint32_t nonzero_bytes(uint32_t w) {
   return ((((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u) >> 7;
@@ -837,7 +803,7 @@ void seg_lds_frontier(
       }
     }
     uint32_t ztot;
-    const uint32_t zbase = block_excl_scan_dpp<NT>((uint32_t)__popc(zmask), sh_scan, &ztot);
+    const uint32_t zbase = block_excl_scan<NT>((uint32_t)__popc(zmask), sh_scan, &ztot);
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int g = se[e];
@@ -888,7 +854,7 @@ void seg_lds_frontier(
       nopen = (oa ? 1u : 0u) + (ob ? 1u : 0u);
     }
     uint32_t total;
-    const uint32_t at = block_excl_scan_dpp<NT>(nopen, sh_scan, &total);
+    const uint32_t at = block_excl_scan<NT>(nopen, sh_scan, &total);
     if ((int)threadIdx.x < nact) {
       const SegL& g = S[threadIdx.x];
       SegL* Nx = segs[cur ^ 1];
