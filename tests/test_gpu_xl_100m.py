@@ -12,6 +12,9 @@ one by one, and properties that hold at any size:
   codes          the sampled rows' codes equal the oracle's encoding on the GPU's
                  breakpoints, except within 1e-5 of the column range of a breakpoint;
   trees          each tree's perm is a permutation of the n ids and its leaf counts tile it;
+  leaf ordinals  every point's leaf in every tree (scattered over three id windows at this
+                 size, read back through tree 0's leaf rows) is the leaf holding it in that
+                 tree's permutation;
   queries        the FP32 batch runs on capped leaf lists (2,048 slots); 64 of its queries
                  run again on full-capacity slots and give identical ids, distances and
                  statistics; returned distances equal the FP64 distances of the returned ids;
@@ -53,6 +56,18 @@ def xl():
     del Xd
     torch.cuda.empty_cache()
     pdet.release_cache()
+
+
+def test_100m_leaf_ordinals_match_every_tree(xl):
+    w, X, A, sid, Xd, idx, Q, Qd, t = xl
+    for j in range(w.L):
+        perm = idx.export(pdet.X_PERM, j)
+        cnt = idx.export(pdet.X_LEAF_COUNT, j)
+        want = np.empty(w.n, dtype=np.int32)
+        want[perm] = np.repeat(np.arange(len(cnt), dtype=np.int32), cnt)
+        got = idx.export(pdet.X_LEAF_OF, j)
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, f"tree {j}: {bad.size} ids, first {bad[:5]} (windows of 2^25 ids)"
 
 
 def test_100m_sampled_projection_codes_and_breakpoints(xl):
