@@ -171,6 +171,46 @@ __device__ inline void load_box(const float* box, int64_t nb, uint32_t b, int K,
   }
 }
 
+// Union of the 16 group boxes of a 256-leaf block (lanes 16i..16i+15 of each wave hold group
+// i of the wave's four), into bbox: within waves by lane shuffles, across them through red.
+// Every thread calls it; a barrier must follow before bbox is read. The union's bound to any
+// query is never above a group's (each term of box_lb2 only shrinks, and FP32 fma and
+// subtraction are monotone), so a query the block's box does not admit opens none of its
+// groups.
+__device__ inline void block_box(const float (&lo)[PDET_MAX_K], const float (&hi)[PDET_MAX_K],
+                                 float (*red)[2][PDET_MAX_K], float (*bbox)[PDET_MAX_K]) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < PDET_MAX_K; ++j) {
+    float l = lo[j], h = hi[j];
+    l = fminf(l, __shfl_xor(l, 16));
+    l = fminf(l, __shfl_xor(l, 32));
+    h = fmaxf(h, __shfl_xor(h, 16));
+    h = fmaxf(h, __shfl_xor(h, 32));
+    if ((threadIdx.x & 63) == 0) { red[w][0][j] = l; red[w][1][j] = h; }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * PDET_MAX_K) {
+    const int side = threadIdx.x / PDET_MAX_K, j = threadIdx.x % PDET_MAX_K;
+    float v = red[0][side][j];
+    for (int u = 1; u < (int)(blockDim.x >> 6); ++u)
+      v = side ? fmaxf(v, red[u][side][j]) : fminf(v, red[u][side][j]);
+    bbox[side][j] = v;
+  }
+}
+
+// box_lb2 (below) of a box held in LDS, in a loop that keeps few values in registers: the
+// same fma sequence in dimension order, so the same value.
+__device__ inline float box_lb2_lds(const float* blo, const float* bhi, const float* q, int K) {
+  float acc = 0.0f;
+#pragma unroll 2
+  for (int j = 0; j < K; ++j) {
+    const float g = fmaxf(0.0f, fmaxf(blo[j] - q[j], q[j] - bhi[j]));
+    acc = __fmaf_rn(g, g, acc);
+  }
+  return acc;
+}
+
 // Squared lower-bound distance from q' to a box; explicit fma in dimension order keeps it
 // identical wherever it is evaluated.
 __device__ inline float box_lb2(const float (&lo)[PDET_MAX_K], const float (&hi)[PDET_MAX_K],
@@ -221,6 +261,8 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_tile(QArgs a) {
   // one padding word per query row: the 16 queries a wave tests at once read 16 banks
   __shared__ float sq[QT][PDET_MAX_K + 1];
   __shared__ float st[QT][RCAP_MAX + 1];
+  __shared__ float bred[QR_THREADS / 64][2][PDET_MAX_K];
+  __shared__ float bbox[2][PDET_MAX_K];
   // Grid (NXCD * query tiles, lb_per_die, L): the row length is a multiple of NXCD, so
   // blockIdx.x % NXCD is the die a workgroup runs on. Each die takes a fixed share of every
   // tree's leaf blocks and runs through the query tiles of one leaf block after another,
@@ -277,13 +319,21 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_tile(QArgs a) {
     const int e = threadIdx.x + u * QR_THREADS;
     sq[e / PDET_MAX_K][e % PDET_MAX_K] = sqv[u];
   }
+  block_box(lo, hi, bred, bbox);
   __syncthreads();
-  // lane sl of the 16 lanes sharing group g tests that group against query 16*sub + sl
+  // the block's box first (lane l: query l of the tile, in every wave); then lane sl of the
+  // 16 lanes sharing group g tests that group against query 16*sub + sl, for the queries the
+  // block's box admits
+  const int ql = threadIdx.x & 63;
+  const bool bopen = slot0 + ql < a.nslots &&
+                     box_lb2_lds(bbox[0], bbox[1], sq[ql], K) <= st[ql][rcap] * (1.0f + BAND_REL);
+  const uint64_t bmask = __ballot(bopen);
   uint64_t open_mask = 0;
   for (int sub = 0; sub < QT / 16; ++sub) {
+    if (!((bmask >> (16 * sub)) & 0xffffull)) continue;
     const int qi = sub * 16 + sl;
     bool open = false;
-    if (g < ng && slot0 + qi < a.nslots)
+    if (g < ng && ((bmask >> qi) & 1ull))
       open = box_lb2(lo, hi, sq[qi], K) <= st[qi][rcap] * (1.0f + BAND_REL);
     const uint64_t mask = __ballot(open);
     open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
@@ -332,6 +382,8 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_runs(QArgs a) {
   __shared__ uint64_t gmask[QR_TILES_MAX][NGB];   // pass 1: open queries per tile and group
   __shared__ uint8_t open_tiles[QR_TILES_MAX];    // tiles where some group is open, in order
   __shared__ uint32_t n_open;
+  __shared__ float bred[QR_THREADS / 64][2][PDET_MAX_K];
+  __shared__ float bbox[2][PDET_MAX_K];
   // Grid (NXCD * lb_per_die, L, runs of a.qr_tiles tiles): blockIdx.x % NXCD is the die a
   // workgroup runs on. Each die takes a fixed share of every tree's leaf blocks, which keeps
   // its share of the box tables in its own L2.
@@ -386,6 +438,7 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_runs(QArgs a) {
   float lo[PDET_MAX_K], hi[PDET_MAX_K];
   load_box(a.gbox[tree], ng, (uint32_t)std::min(g, ng - 1), K, lo, hi);   // tested if g < ng
   fetch(t0 * QT);
+  block_box(lo, hi, bred, bbox);   // read after the first tile's barrier
   // pass 1: group tests (double buffered: past a tile's barrier, a thread has finished
   // reading the other buffer)
   for (int tile = 0; tile < ntiles; ++tile) {
@@ -393,13 +446,21 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_runs(QArgs a) {
     stage(b);
     __syncthreads();
     if (tile + 1 < ntiles) fetch(slot0 + QT);
-    // lane sl of the 16 lanes sharing group gl tests that group against query 16*sub + sl
+    // the block's box first (lane l: query l of the tile, in every wave); then lane sl of
+    // the 16 lanes sharing group gl tests that group against query 16*sub + sl, for the
+    // queries the block's box admits
+    const int ql = threadIdx.x & 63;
+    const bool bopen = slot0 + ql < a.nslots &&
+                       box_lb2_lds(bbox[0], bbox[1], sq[b][ql], K) <=
+                           st[b][ql][rcap] * (1.0f + BAND_REL);
+    const uint64_t bmask = __ballot(bopen);
     uint64_t open_mask = 0;
 #pragma unroll
     for (int sub = 0; sub < QT / 16; ++sub) {
+      if (!((bmask >> (16 * sub)) & 0xffffull)) continue;
       const int qi = sub * 16 + sl;
       bool open = false;
-      if (g < ng && slot0 + qi < a.nslots)
+      if (g < ng && ((bmask >> qi) & 1ull))
         open = box_lb2(lo, hi, sq[b][qi], K) <= st[b][qi][rcap] * (1.0f + BAND_REL);
       const uint64_t mask = __ballot(open);
       open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
