@@ -261,8 +261,6 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_tile(QArgs a) {
   // one padding word per query row: the 16 queries a wave tests at once read 16 banks
   __shared__ float sq[QT][PDET_MAX_K + 1];
   __shared__ float st[QT][RCAP_MAX + 1];
-  __shared__ float bred[QR_THREADS / 64][2][PDET_MAX_K];
-  __shared__ float bbox[2][PDET_MAX_K];
   // Grid (NXCD * query tiles, lb_per_die, L): the row length is a multiple of NXCD, so
   // blockIdx.x % NXCD is the die a workgroup runs on. Each die takes a fixed share of every
   // tree's leaf blocks and runs through the query tiles of one leaf block after another,
@@ -319,21 +317,15 @@ __global__ __launch_bounds__(QR_THREADS) void q_rho_tile(QArgs a) {
     const int e = threadIdx.x + u * QR_THREADS;
     sq[e / PDET_MAX_K][e % PDET_MAX_K] = sqv[u];
   }
-  block_box(lo, hi, bred, bbox);
   __syncthreads();
-  // the block's box first (lane l: query l of the tile, in every wave); then lane sl of the
-  // 16 lanes sharing group g tests that group against query 16*sub + sl, for the queries the
-  // block's box admits
-  const int ql = threadIdx.x & 63;
-  const bool bopen = slot0 + ql < a.nslots &&
-                     box_lb2_lds(bbox[0], bbox[1], sq[ql], K) <= st[ql][rcap] * (1.0f + BAND_REL);
-  const uint64_t bmask = __ballot(bopen);
+  // lane sl of the 16 lanes sharing group g tests that group against query 16*sub + sl (one
+  // tile per workgroup: a block-box test first, as in q_rho_runs, would cost more here than
+  // it saves)
   uint64_t open_mask = 0;
   for (int sub = 0; sub < QT / 16; ++sub) {
-    if (!((bmask >> (16 * sub)) & 0xffffull)) continue;
     const int qi = sub * 16 + sl;
     bool open = false;
-    if (g < ng && ((bmask >> qi) & 1ull))
+    if (g < ng && slot0 + qi < a.nslots)
       open = box_lb2(lo, hi, sq[qi], K) <= st[qi][rcap] * (1.0f + BAND_REL);
     const uint64_t mask = __ballot(open);
     open_mask |= (uint64_t)((uint32_t)(mask >> (threadIdx.x & 48)) & 0xffffu) << (16 * sub);
