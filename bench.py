@@ -306,6 +306,10 @@ def measure(w, args, primary, helper=None):
         for enc, L_s, K_s in STUDY:
             A_s = A if (L_s, K_s) == (w.L, w.K) else wl.projection_matrix(w.d, L_s, K_s,
                                                                           seed=2603 + 16 * L_s + K_s)
+            # one untimed build of this shape first: the timed one reuses its device blocks,
+            # as the step's builds do (a first build of a new shape allocates, and may first
+            # have to release cached blocks of other shapes)
+            pdet.Index(Xd, A_s, sid, K_s, L_s, w.Nr, w.max_leaf, encoding=enc).close()
             torch.cuda.synchronize()
             tb0 = time.perf_counter()
             ixs = pdet.Index(Xd, A_s, sid, K_s, L_s, w.Nr, w.max_leaf, encoding=enc)
