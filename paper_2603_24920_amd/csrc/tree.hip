@@ -144,18 +144,6 @@ __device__ inline bool fully_refined(const uint8_t* depth, int K, int bits) {
   return f;
 }
 
-// A slot of an appendable list for every lane that wants one; the lanes of a wave that
-// append to the same list share one atomic. Every lane of the wave must call it.
-__device__ inline uint32_t append_slot(uint32_t* ctr, bool want) {
-  const uint64_t m = __ballot(want);
-  if (!m) return 0u;
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  uint32_t base = 0u;
-  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
-  base = __shfl(base, leader);
-  return base + lanes_below_mask(m);
-}
-
 // A node to its place: a leaf (records at its start; ids copied later if they sit in buffer
 // 1), an LDS size class, or the next global level (with its bit counts, if known). Called by
 // every lane of the wave; lanes with active == false take no place.
@@ -166,20 +154,42 @@ __device__ void route(const Seg& s, int K, int bits, int max_leaf, int64_t n, co
   const bool mid = active && !leaf && s.count <= LDS_SEG_CAP;
   const bool big = active && !leaf && !mid;
   const int c = mid ? size_class(s.count) : -1;
+  const bool copy = leaf && s.buf == 1;
   if (leaf) emit_leaf(lo, n, s.tree, s.start, s.count, s.depth, s.prefix, K);
-  const uint32_t cp = append_slot(li.n_copies, leaf && s.buf == 1);
-  if (leaf && s.buf == 1) li.copies[cp] = Copy{s.tree, s.start, s.count};
+  // the wave's places in every list it appends to: lane 0 reserves the copies, lane 1 + cl
+  // size class cl, lane 5 the next level, lane 6 adds its points; the reservations are all
+  // in flight together (one after another, each would wait for the one before)
+  const uint64_t m_copy = __ballot(copy);
+  uint64_t m_mid[NCLS];
 #pragma unroll
-  for (int cl = 0; cl < NCLS; ++cl) {
-    const uint32_t k = append_slot(&li.n_mid[cl], c == cl);
-    if (c == cl) li.mid[cl][k] = s;
-  }
-  const uint32_t k = append_slot(li.n_big_next, big);
+  for (int cl = 0; cl < NCLS; ++cl) m_mid[cl] = __ballot(c == cl);
+  const uint64_t m_big = __ballot(big);
   uint32_t pts = big ? (uint32_t)s.count : 0u;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) pts += __shfl_xor(pts, o);
-  if ((threadIdx.x & 63) == 0 && pts) atomicAdd(li.pts_big_next, pts);
+  const int lane = threadIdx.x & 63;
+  uint32_t* ctr = nullptr;
+  uint32_t add = 0;
+  if (lane == 0) { ctr = li.n_copies; add = (uint32_t)__popcll(m_copy); }
+#pragma unroll
+  for (int cl = 0; cl < NCLS; ++cl)
+    if (lane == 1 + cl) { ctr = &li.n_mid[cl]; add = (uint32_t)__popcll(m_mid[cl]); }
+  if (lane == 1 + NCLS) { ctr = li.n_big_next; add = (uint32_t)__popcll(m_big); }
+  if (lane == 2 + NCLS) { ctr = li.pts_big_next; add = pts; }
+  uint32_t got = 0;
+  if (add) got = atomicAdd(ctr, add);
+  if (copy) {
+    const uint32_t cp = (uint32_t)__builtin_amdgcn_readlane((int)got, 0) + lanes_below_mask(m_copy);
+    li.copies[cp] = Copy{s.tree, s.start, s.count};
+  }
+#pragma unroll
+  for (int cl = 0; cl < NCLS; ++cl) {
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)got, 1 + cl);
+    if (c == cl) li.mid[cl][b + lanes_below_mask(m_mid[cl])] = s;
+  }
   if (big) {
+    const uint32_t k =
+        (uint32_t)__builtin_amdgcn_readlane((int)got, 1 + NCLS) + lanes_below_mask(m_big);
     li.big_next[k] = s;
     if (counts && li.cnt_next)
       for (int j = 0; j < KP; ++j) li.cnt_next[(int64_t)k * KP + j] = counts[j];
