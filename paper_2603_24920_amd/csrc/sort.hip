@@ -13,6 +13,7 @@
 // The result is the exact order statistic whatever the distribution (a bucket may hold
 // any number of keys; large ones only take longer).
 #include "internal.h"
+#include "devutil.h"
 
 namespace pdet {
 namespace {
@@ -275,29 +276,6 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_BLOCK = SCAN_THREADS * SCAN_ITEMS;
 
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  // sh: [SCAN_THREADS/64 + 1]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wave] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int w = 0; w < SCAN_THREADS / 64; ++w) { const uint32_t t = sh[w]; sh[w] = acc; acc += t; }
-    sh[SCAN_THREADS / 64] = acc;
-  }
-  __syncthreads();
-  const uint32_t r = sh[wave] + x - v;
-  *total = sh[SCAN_THREADS / 64];
-  __syncthreads();
-  return r;
-}
-
 // NZ: the scanned value of an entry is 1 if it is not zero, else 0
 template <bool NZ>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_sums(const uint32_t* in, int64_t len,
@@ -306,12 +284,23 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_sums(const uint32_t* in, in
   const int64_t row = blockIdx.x / nblk, b = blockIdx.x % nblk;
   const uint32_t* r = in + row * len;
   uint32_t s = 0;
-  for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const int64_t i = b * SCAN_BLOCK + it * SCAN_THREADS + threadIdx.x;
-    if (i < len) s += NZ ? (r[i] != 0u ? 1u : 0u) : r[i];
+  auto val = [](uint32_t x) { return NZ ? (x != 0u ? 1u : 0u) : x; };
+  if ((len & 3) == 0 && (b + 1) * SCAN_BLOCK <= len) {
+    // a whole block of a row of length divisible by 4: 16-byte loads, consecutive per lane
+    const uint4* r4 = reinterpret_cast<const uint4*>(r + b * SCAN_BLOCK);
+#pragma unroll
+    for (int u = 0; u < SCAN_ITEMS / 4; ++u) {
+      const uint4 w = r4[u * SCAN_THREADS + threadIdx.x];
+      s += val(w.x) + val(w.y) + val(w.z) + val(w.w);
+    }
+  } else {
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+      const int64_t i = b * SCAN_BLOCK + it * SCAN_THREADS + threadIdx.x;
+      if (i < len) s += val(r[i]);
+    }
   }
   uint32_t tot;
-  block_excl_scan(s, sh, &tot);
+  block_excl_scan<SCAN_THREADS>(s, sh, &tot);
   if (threadIdx.x == 0) sums[row * nblk + b] = tot;
 }
 
@@ -324,7 +313,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_of_sums(uint32_t* sums, int
     const int64_t i = b0 + threadIdx.x;
     const uint32_t v = i < nblk ? r[i] : 0;
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(v, sh, &tot);
+    const uint32_t ex = block_excl_scan<SCAN_THREADS>(v, sh, &tot);
     if (i < nblk) r[i] = carry + ex;
     carry += tot;
   }
@@ -339,22 +328,44 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply(const uint32_t* in, u
   const int64_t row = blockIdx.x / nblk, b = blockIdx.x % nblk;
   const uint32_t* r = in + row * len;
   uint32_t* o = out + row * len;
-  // each thread owns SCAN_ITEMS consecutive entries
+  // each thread owns SCAN_ITEMS consecutive entries, read and written as 16-byte vectors
+  // when the row is (rows of a length divisible by 4 start 16-byte aligned)
   const int64_t i0 = b * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const bool vec = (len & 3) == 0 && i0 + SCAN_ITEMS <= len;
   uint32_t v[SCAN_ITEMS];
+  if (vec) {
+#pragma unroll
+    for (int u = 0; u < SCAN_ITEMS / 4; ++u) {
+      const uint4 w = reinterpret_cast<const uint4*>(r + i0)[u];
+      v[4 * u] = w.x; v[4 * u + 1] = w.y; v[4 * u + 2] = w.z; v[4 * u + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) v[it] = (i0 + it < len) ? r[i0 + it] : 0;
+  }
   uint32_t s = 0;
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    v[it] = (i0 + it < len) ? r[i0 + it] : 0;
     if (NZ) v[it] = v[it] != 0u ? 1u : 0u;
     s += v[it];
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan(s, sh, &tot) + sums[row * nblk + b];
+  uint32_t run = block_excl_scan<SCAN_THREADS>(s, sh, &tot) + sums[row * nblk + b];
+  uint32_t ov[SCAN_ITEMS];
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    if (i0 + it < len) o[i0 + it] = run;
+    ov[it] = run;
     run += v[it];
+  }
+  if (vec) {
+#pragma unroll
+    for (int u = 0; u < SCAN_ITEMS / 4; ++u)
+      reinterpret_cast<uint4*>(o + i0)[u] =
+          make_uint4(ov[4 * u], ov[4 * u + 1], ov[4 * u + 2], ov[4 * u + 3]);
+  } else {
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it)
+      if (i0 + it < len) o[i0 + it] = ov[it];
   }
 }
 
