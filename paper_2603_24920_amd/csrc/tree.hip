@@ -348,16 +348,36 @@ __global__ __launch_bounds__(RK_THREADS) void rk_scatter(const uint16_t* kin, co
 
 // First-layer nodes from the sorted keys: start[tree][key] and end[tree][key] at the
 // boundaries of each key's run (both zero for keys that do not occur).
+// 8 consecutive keys per thread (one 16-byte load when the row allows) and their neighbours;
+// a run of equal keys starts where the key before differs and ends where the key after does
+// (0xffffffff stands for the missing neighbours of the row's ends).
 __global__ void rk_bounds(const uint16_t* keys, int64_t n, int K, uint32_t* start,
                           uint32_t* end) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
   const int tree = blockIdx.y;
-  if (p >= n) return;
+  if (p0 >= n) return;
   const uint16_t* kt = keys + (int64_t)tree * n;
-  const uint32_t key = kt[p];
-  const int64_t g = ((int64_t)tree << K) + key;
-  if (p == 0 || kt[p - 1] != key) start[g] = (uint32_t)p;
-  if (p == n - 1 || kt[p + 1] != key) end[g] = (uint32_t)(p + 1);
+  uint32_t k[10];
+  k[0] = p0 > 0 ? kt[p0 - 1] : 0xffffffffu;
+  if ((n & 7) == 0) {   // rows start 16-byte aligned and hold whole groups of 8
+    const uint4 w = *reinterpret_cast<const uint4*>(kt + p0);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { k[1 + 2 * e] = ws[e] & 0xffffu; k[2 + 2 * e] = ws[e] >> 16; }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) k[1 + e] = p0 + e < n ? kt[p0 + e] : 0xffffffffu;
+  }
+  k[9] = p0 + 8 < n ? kt[p0 + 8] : 0xffffffffu;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t p = p0 + e;
+    if (p >= n) break;
+    const uint32_t key = k[1 + e];
+    const int64_t g = ((int64_t)tree << K) + key;
+    if (k[e] != key) start[g] = (uint32_t)p;
+    if (k[e + 2] != key) end[g] = (uint32_t)(p + 1);
+  }
 }
 
 __global__ void rk_counts(const uint32_t* start, const uint32_t* end, int64_t total,
@@ -1051,13 +1071,29 @@ struct LeafTables {
 
 // Leaf tables in two steps: every recorded start position goes to its leaf's slot (one
 // sparse write per leaf), then one thread per leaf fills the rest (all lanes busy).
+// 4 consecutive positions per thread (16-byte loads when the row allows).
 __global__ void leaf_starts(const uint32_t* cnt_at, const uint32_t* ord, int64_t n,
                             LeafTables t) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   const int tree = blockIdx.y;
-  if (p >= n) return;
-  const int64_t g = (int64_t)tree * n + p;
-  if (cnt_at[g]) t.start[tree][ord[g]] = (int32_t)p;
+  if (p0 >= n) return;
+  const int64_t g0 = (int64_t)tree * n + p0;
+  uint32_t c[4], o[4];
+  if ((n & 3) == 0) {   // rows start 16-byte aligned and hold whole groups of 4
+    const uint4 cw = *reinterpret_cast<const uint4*>(cnt_at + g0);
+    const uint4 ow = *reinterpret_cast<const uint4*>(ord + g0);
+    c[0] = cw.x; c[1] = cw.y; c[2] = cw.z; c[3] = cw.w;
+    o[0] = ow.x; o[1] = ow.y; o[2] = ow.z; o[3] = ow.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      c[e] = p0 + e < n ? cnt_at[g0 + e] : 0u;
+      o[e] = p0 + e < n ? ord[g0 + e] : 0u;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (c[e]) t.start[tree][o[e]] = (int32_t)(p0 + e);
 }
 
 __global__ void leaf_fill(const uint32_t* cnt_at, const uint16_t* hidx_at, int64_t n, int K,
@@ -1243,7 +1279,8 @@ void first_layer_sort(int L, int K, int64_t n, uint16_t* keys, const uint4* code
   fz.add(start, 0u, (size_t)L * ((size_t)1 << K) * 4);
   fz.add(end, 0u, (size_t)L * ((size_t)1 << K) * 4);
   fill_words(fz, s);
-  hipLaunchKernelGGL(rk_bounds, dim3(cdiv(n, 256), L), dim3(256), 0, s, kfin, n, K, start, end);
+  hipLaunchKernelGGL(rk_bounds, dim3(cdiv(n, 256 * 8), L), dim3(256), 0, s, kfin, n, K, start,
+                     end);
   PDET_HIP(hipGetLastError());
 }
 
@@ -1481,7 +1518,7 @@ void finish_trees(Index& ix, const uint32_t* cnt_at, const uint16_t* hidx_at, De
     t.box[i] = ix.box[i].as<float>();
     t.nl[i] = nl[i];
   }
-  hipLaunchKernelGGL(leaf_starts, dim3(cdiv(n, 256), L), dim3(256), 0, s, cnt_at,
+  hipLaunchKernelGGL(leaf_starts, dim3(cdiv(n, 256 * 4), L), dim3(256), 0, s, cnt_at,
                      flags.as<uint32_t>(), n, t);
   PDET_HIP(hipGetLastError());
   int64_t nl_max = 0;
