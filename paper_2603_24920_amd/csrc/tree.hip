@@ -228,20 +228,30 @@ __global__ __launch_bounds__(RK_THREADS) void rk_hist(const uint16_t* keys, int6
   cnt[threadIdx.x] = 0;
   const uint16_t* kt = keys + (int64_t)tree * n;
   const int64_t p0 = (int64_t)blk * RK_TILE;
-  uint32_t kv[RK_ROUNDS];
+  // the tile's keys, 8 per thread (one 16-byte load for a whole tile of a row whose length
+  // is a multiple of 8); only the counts matter here, so any key may go to any thread
+  static_assert(RK_TILE == 8 * RK_THREADS, "8 keys per thread");
+  uint32_t kv[8];
+  bool ok[8];
+  if ((n & 7) == 0 && p0 + RK_TILE <= n) {
+    const uint4 w = reinterpret_cast<const uint4*>(kt + p0)[threadIdx.x];
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-  for (int r = 0; r < RK_ROUNDS; ++r) {
-    const int64_t p = p0 + r * RK_THREADS + threadIdx.x;
-    kv[r] = (p < n) ? kt[p] : 0u;
+    for (int e = 0; e < 4; ++e) { kv[2 * e] = ws[e] & 0xffffu; kv[2 * e + 1] = ws[e] >> 16; }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ok[e] = true;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int64_t p = p0 + r * RK_THREADS + threadIdx.x;
+      ok[r] = p < n;
+      kv[r] = ok[r] ? kt[p] : 0u;
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < RK_ROUNDS; ++r) {
-    const bool v = p0 + r * RK_THREADS + threadIdx.x < n;
-    const uint32_t d = (kv[r] >> SHIFT) & 255u;
-    const uint64_t m = same_digit_lanes(d, v);
-    if (v && lanes_below_mask(m) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
-  }
+  for (int e = 0; e < 8; ++e)
+    if (ok[e]) atomicAdd(&cnt[(kv[e] >> SHIFT) & 255u], 1u);
   __syncthreads();
   h[((int64_t)tree * 256 + threadIdx.x) * nblk + blk] = cnt[threadIdx.x];
 }
