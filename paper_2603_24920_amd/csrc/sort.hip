@@ -20,7 +20,11 @@ namespace {
 
 constexpr int NB = 4096;            // value buckets per column
 constexpr int SEL_THREADS = 256;
-constexpr int GATHER_KEYS = 4096;   // keys per gather / histogram block
+constexpr int GATHER_KEYS = 4096;   // keys per gather block
+constexpr int HIST_KEYS_MAX = 32768;   // keys per histogram block at most: several per
+                                       // bucket before the block adds its counts to the
+                                       // column's (one atomic per bucket it saw), while a
+                                       // column still spans at least 64 blocks
 
 __device__ inline int bucket_of(float v, float lo, float scale) {
   const int b = (int)__fmul_rn(__fsub_rn(v, lo), scale);   // no contraction: one rounding each
@@ -35,7 +39,8 @@ __device__ inline void col_range(const uint32_t* mm, int ncols, int col, float& 
 
 // Bucket histogram of every column, counted in LDS per block.
 __global__ __launch_bounds__(256) void col_hist(const float* keys, int64_t ld, int64_t ns,
-                                                int ncols, const uint32_t* mm, uint32_t* hist) {
+                                                int ncols, const uint32_t* mm, int kpb,
+                                                uint32_t* hist) {
   __shared__ uint32_t h[NB];
   const int col = blockIdx.y;
   for (int i = threadIdx.x; i < NB; i += 256) h[i] = 0;
@@ -43,8 +48,8 @@ __global__ __launch_bounds__(256) void col_hist(const float* keys, int64_t ld, i
   float lo, scale;
   col_range(mm, ncols, col, lo, scale);
   const float* c = keys + (int64_t)col * ld;
-  const int64_t k0 = (int64_t)blockIdx.x * GATHER_KEYS;
-  for (int u = threadIdx.x; u < GATHER_KEYS; u += 256) {
+  const int64_t k0 = (int64_t)blockIdx.x * kpb;
+  for (int u = threadIdx.x; u < kpb; u += 256) {
     const int64_t i = k0 + u;
     if (i < ns) atomicAdd(&h[bucket_of(c[i], lo, scale)], 1u);
   }
@@ -397,8 +402,11 @@ void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
   fz.add(fill.ptr(), 0u, fill.bytes());
   fill_words(fz, s);
   const dim3 kg(cdiv(ns, GATHER_KEYS), ncols);
-  hipLaunchKernelGGL(col_hist, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm,
-                     hist.as<uint32_t>());
+  const int kpb = (int)std::min<int64_t>(
+      HIST_KEYS_MAX, std::max<int64_t>(GATHER_KEYS, (ns / 64 + GATHER_KEYS - 1) / GATHER_KEYS *
+                                                         GATHER_KEYS));
+  hipLaunchKernelGGL(col_hist, dim3(cdiv(ns, kpb), ncols), dim3(256), 0, s, keys, ld, ns, ncols,
+                     mm, kpb, hist.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(col_targets, dim3(ncols), dim3(1024), 0, s, hist.as<uint32_t>(), Nr, m,
                      tb.as<int32_t>(), tr.as<uint32_t>(), boff.as<int32_t>());
