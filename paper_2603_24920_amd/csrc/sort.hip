@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void col_hist(const float* keys, int64_t ld, i
 // gather offset of every bucket that holds a target (-1 for the others).
 __global__ __launch_bounds__(1024) void col_targets(const uint32_t* hist, int Nr, int64_t m,
                                                     int32_t* tbucket, uint32_t* trank,
-                                                    int32_t* boff) {
+                                                    int32_t* boff, uint32_t* needbits) {
   __shared__ uint32_t cum[NB];      // inclusive prefix of the histogram
   __shared__ uint32_t need[NB];
   __shared__ uint32_t wsum[1024 / 64 + 1];
@@ -119,20 +119,29 @@ __global__ __launch_bounds__(1024) void col_targets(const uint32_t* hist, int Nr
   int32_t* bo = boff + (int64_t)col * NB;
   for (int i = threadIdx.x; i < NB; i += 1024)
     bo[i] = need[i] ? (int32_t)(cum[i] - need[i]) : -1;
+  // the same choice as a bit mask (bit b of word b / 32: bucket b is gathered)
+  if (threadIdx.x < NB / 32) {
+    uint32_t w = 0;
+    for (int j = 0; j < 32; ++j) w |= (need[threadIdx.x * 32 + j] ? 1u : 0u) << j;
+    needbits[(int64_t)col * (NB / 32) + threadIdx.x] = w;
+  }
 }
 
 // Keys of the needed buckets, gathered per column bucket by bucket (order inside a bucket
 // unspecified) as order-preserving uints: a block counts its keys per bucket in LDS, takes
-// one global reservation per bucket, then writes.
+// one global reservation per bucket, then writes. Whether a key's bucket is needed comes
+// from the column's bit mask, held in LDS.
 __global__ __launch_bounds__(256) void col_gather(const float* keys, int64_t ld, int64_t ns,
                                                   int ncols, const uint32_t* mm,
-                                                  const int32_t* boff, uint32_t* fill,
-                                                  uint32_t* gbuf) {
+                                                  const int32_t* boff, const uint32_t* needbits,
+                                                  uint32_t* fill, uint32_t* gbuf) {
   __shared__ uint32_t cntl[NB];
   __shared__ uint32_t basel[NB];
+  __shared__ uint32_t needl[NB / 32];
   constexpr int PER = GATHER_KEYS / 256;
   const int col = blockIdx.y;
   for (int i = threadIdx.x; i < NB; i += 256) cntl[i] = 0;
+  if (threadIdx.x < NB / 32) needl[threadIdx.x] = needbits[(int64_t)col * (NB / 32) + threadIdx.x];
   __syncthreads();
   float lo, scale;
   col_range(mm, ncols, col, lo, scale);
@@ -149,7 +158,7 @@ __global__ __launch_bounds__(256) void col_gather(const float* keys, int64_t ld,
     if (i < ns) {
       kv[e] = c[i];
       const int b = bucket_of(kv[e], lo, scale);
-      if (bo[b] >= 0) {
+      if ((needl[b >> 5] >> (b & 31)) & 1u) {
         bk[e] = b;
         rk[e] = atomicAdd(&cntl[b], 1u);
       }
@@ -396,6 +405,7 @@ void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
   const int64_t m = ns / Nr;
   PooledBuf hist((size_t)ncols * NB * 4), fill((size_t)ncols * NB * 4);
   PooledBuf boff((size_t)ncols * NB * 4), tb((size_t)ncols * (Nr - 1) * 4);
+  PooledBuf needbits((size_t)ncols * (NB / 32) * 4);
   PooledBuf tr((size_t)ncols * (Nr - 1) * 4), gbuf((size_t)ncols * ns * 4);
   FillList fz;
   fz.add(hist.ptr(), 0u, hist.bytes());
@@ -409,17 +419,20 @@ void select_breakpoints(const float* keys, int ncols, int64_t ld, int64_t ns, in
                      mm, kpb, hist.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(col_targets, dim3(ncols), dim3(1024), 0, s, hist.as<uint32_t>(), Nr, m,
-                     tb.as<int32_t>(), tr.as<uint32_t>(), boff.as<int32_t>());
+                     tb.as<int32_t>(), tr.as<uint32_t>(), boff.as<int32_t>(),
+                     needbits.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(col_gather, kg, dim3(256), 0, s, keys, ld, ns, ncols, mm,
-                     boff.as<int32_t>(), fill.as<uint32_t>(), gbuf.as<uint32_t>());
+                     boff.as<int32_t>(), needbits.as<uint32_t>(), fill.as<uint32_t>(),
+                     gbuf.as<uint32_t>());
   PDET_HIP(hipGetLastError());
   hipLaunchKernelGGL(col_select, dim3(Nr - 1, ncols), dim3(SEL_THREADS), 0, s,
                      hist.as<uint32_t>(), tb.as<int32_t>(), tr.as<uint32_t>(), boff.as<int32_t>(),
                      gbuf.as<uint32_t>(), ns, Nr, B);
   PDET_HIP(hipGetLastError());
   // the kernels above still use the temporaries: the caller keeps them until it synchronises
-  for (PooledBuf* t : {&hist, &fill, &boff, &tb, &tr, &gbuf}) keep.push_back(std::move(*t));
+  for (PooledBuf* t : {&hist, &fill, &boff, &needbits, &tb, &tr, &gbuf})
+    keep.push_back(std::move(*t));
 }
 
 double normal_quantile(double p) {
