@@ -203,9 +203,12 @@ def measure(w, args, primary, helper=None):
         torch.cuda.synchronize()
         tbt = pdet.get_timing()
         ix.set_tuning(r_min, rcap)
-        # query scratch sized once for the batch, as a serving process does before traffic
+        # query scratch sized once for the batch, as a serving process does before traffic;
+        # its initialisation (the round table's fill) is queued on the stream, so wait for it
+        # here, or it is charged to the query
         tr = time.perf_counter()
         ix.reserve(nq)
+        torch.cuda.synchronize()
         tq = time.perf_counter()
         ids, dists, st = ix.query(Qd, k=w.k, c=w.c, beta=beta, r_min=r_min, stats=True)
         torch.cuda.synchronize()
